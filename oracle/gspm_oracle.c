@@ -1,0 +1,1034 @@
+/*
+ * GSPM oracle -- plain CPU FP64 reference.  TEST INFRASTRUCTURE ONLY: only the
+ * test-suite, the smoke check and the CPU-baseline leg of the benchmark call
+ * it; the HIP product library shares no code with it.
+ *
+ * What it computes, and where the paper defines it:
+ *   - periodic node identification by wrapping max-face nodes onto their
+ *     min-face partners (Sec. 2.5);
+ *   - P1 tetrahedral geometry; the global sparse matrices of Eq. (LHS):
+ *     Laplacian K, mass M (= F^GS of Eq. (RHS_F)) and the elastic K^mech,
+ *     assembled once, as the paper does (Sec. 2.3);
+ *   - the right-hand sides of Eq. (RHS_b) by element integration;
+ *   - volume averages (Sec. 2.4), the ellipsoid-theorem split and the
+ *     far-field demagnetising field -N_d mbar (Sec. 2.1);
+ *   - unpreconditioned CG with d pinned DOFs (Sec. 2.5) and the relative
+ *     residual criterion of Sec. 3.1;
+ *   - one step of the Gauss-Seidel projection method, Algorithm B.1 (App. B),
+ *     with the effective field of App. B and the energy of Eq.
+ *     (MicromagneticsEnergy), spontaneous strain from App. A.
+ * Where the paper is silent the readings are listed in the design notes; the
+ * ones this file depends on are named at the point of use.
+ */
+#include "gspm_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+struct or_sim {
+    int n0, n, ne;
+    int *map;            /* n0: caller node -> unique node */
+    double *x;           /* n x 3 coordinates of the unique nodes */
+    int *tet;            /* ne x 4 unique ids */
+    uint8_t *tag;        /* ne */
+    int periodic;
+    double lo[3], L[3];
+    double *vol;         /* ne */
+    double *grad;        /* ne x 4 x 3: gradients of the barycentric coordinates */
+    double vc;           /* volume of the computational cell */
+    double *w;           /* n: sum over magnetic elements of V_e / 4 */
+    uint8_t *mag;        /* n: node touched by a magnetic element */
+    int *n2e_ptr, *n2e;  /* node -> element incidence */
+    int *adj_ptr, *adj;  /* node adjacency (sparsity of the scalar matrices), sorted, with self */
+    double *Kmag, *Mmag, *Kall, *Kmech; /* Kmech: 3x3 block per adjacency entry */
+    int have_params, have_m;
+    or_params p;
+    double C[3][3][3][3];
+    int p0;
+    double *m, *u;       /* n x 3 */
+    char err[256];
+};
+
+/* ------------------------------------------------------------------ utils */
+
+static void seterr(or_sim *s, const char *msg) {
+    if (s) snprintf(s->err, sizeof s->err, "%s", msg);
+}
+
+static double dot(const double *a, const double *b, int n) {
+    double acc = 0.0;
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+    for (int i = 0; i < n; ++i) acc += a[i] * b[i];
+    return acc;
+}
+
+/* Symmetric 3x3 tensor <-> 6 components, order xx yy zz yz xz xy. */
+static void sym_from6(const double v[6], double T[3][3]) {
+    T[0][0] = v[0]; T[1][1] = v[1]; T[2][2] = v[2];
+    T[1][2] = T[2][1] = v[3];
+    T[0][2] = T[2][0] = v[4];
+    T[0][1] = T[1][0] = v[5];
+}
+static void sym_to6(double T[3][3], double v[6]) {
+    v[0] = T[0][0]; v[1] = T[1][1]; v[2] = T[2][2];
+    v[3] = T[1][2]; v[4] = T[0][2]; v[5] = T[0][1];
+}
+
+/* Gaussian elimination with partial pivoting on an n x n system (n <= 9),
+ * k right-hand sides stored as columns of B (n x k, row-major).  Returns the
+ * determinant of A. */
+static double gauss_solve(int n, double *A, int k, double *B) {
+    double det = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[r * n + c]) > fabs(A[piv * n + c])) piv = r;
+        if (A[piv * n + c] == 0.0) return 0.0;
+        if (piv != c) {
+            det = -det;
+            for (int j = 0; j < n; ++j) { double t = A[c * n + j]; A[c * n + j] = A[piv * n + j]; A[piv * n + j] = t; }
+            for (int j = 0; j < k; ++j) { double t = B[c * k + j]; B[c * k + j] = B[piv * k + j]; B[piv * k + j] = t; }
+        }
+        det *= A[c * n + c];
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[r * n + c] / A[c * n + c];
+            for (int j = c; j < n; ++j) A[r * n + j] -= f * A[c * n + j];
+            for (int j = 0; j < k; ++j) B[r * k + j] -= f * B[c * k + j];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c)
+        for (int j = 0; j < k; ++j) {
+            double v = B[c * k + j];
+            for (int q = c + 1; q < n; ++q) v -= A[c * n + q] * B[q * k + j];
+            B[c * k + j] = v / A[c * n + c];
+        }
+    return det;
+}
+
+/* ------------------------------------------------------------- material */
+
+/* Cubic stiffness as a full fourth-order tensor:
+ * C_ijkl = c12 d_ij d_kl + c44 (d_ik d_jl + d_il d_jk) + (c11 - c12 - 2 c44) sum_p d_ip d_jp d_kp d_lp. */
+static void cubic_tensor(const or_params *p, double C[3][3][3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) {
+                    double v = p->c12 * (i == j) * (k == l) + p->c44 * ((i == k) * (j == l) + (i == l) * (j == k));
+                    if (i == j && j == k && k == l) v += p->c11 - p->c12 - 2.0 * p->c44;
+                    C[i][j][k][l] = v;
+                }
+}
+
+static void contract(double C[3][3][3][3], double E[3][3], double S[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) v += C[i][j][k][l] * E[k][l];
+            S[i][j] = v;
+        }
+}
+
+/* Spontaneous strain of a cubic crystal, App. A. */
+static void spont_strain(const or_params *p, const double m[3], double E0[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            E0[i][j] = (i == j) ? 1.5 * p->lambda100 * (m[i] * m[i] - 1.0 / 3.0)
+                                : 1.5 * p->lambda111 * m[i] * m[j];
+}
+
+/* d E0_ij / d m_k. */
+static void spont_strain_deriv(const or_params *p, const double m[3], int k, double D[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            if (i == j) D[i][j] = (i == k) ? 3.0 * p->lambda100 * m[i] : 0.0;
+            else D[i][j] = 1.5 * p->lambda111 * ((i == k) * m[j] + (j == k) * m[i]);
+        }
+}
+
+/* Solve C : X = S for symmetric X in the six independent components. */
+static void cubic_compliance_apply(double C[3][3][3][3], const double S6[6], double X6[6]) {
+    static const int ij[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+    double A[36], B[6];
+    for (int r = 0; r < 6; ++r) {
+        for (int c = 0; c < 6; ++c) {
+            int k = ij[c][0], l = ij[c][1];
+            A[r * 6 + c] = (k == l) ? C[ij[r][0]][ij[r][1]][k][l] : 2.0 * C[ij[r][0]][ij[r][1]][k][l];
+        }
+        B[r] = S6[r];
+    }
+    gauss_solve(6, A, 1, B);
+    for (int r = 0; r < 6; ++r) X6[r] = B[r];
+}
+
+/* The local part of the effective field h(m) of App. B (everything except the
+ * exchange term): cubic anisotropy, Zeeman, far-field demagnetisation -N mbar
+ * (Sec. 2.1) and magnetoelastic, h = -(1/(mu0 Ms^2)) d psi / d m with psi from
+ * Eq. (MicromagneticsEnergy); E is the total strain at the point. */
+void or_h_local(const or_params *p, const double m[3], const double E6[6], const double mbar[3], double h[3]) {
+    double C[3][3][3][3], E[3][3], E0[3][3], D[3][3], R[3][3], S[3][3];
+    cubic_tensor(p, C);
+    sym_from6(E6, E);
+    spont_strain(p, m, E0);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R[i][j] = E[i][j] - E0[i][j];
+    contract(C, R, S);
+    double scale = 1.0 / (p->mu0 * p->Ms * p->Ms);
+    for (int k = 0; k < 3; ++k) {
+        double others = 0.0;
+        for (int l = 0; l < 3; ++l)
+            if (l != k) others += m[l] * m[l];
+        double h_anis = -2.0 * p->K1 * scale * m[k] * others;
+        double h_zee = p->hext[k] / p->Ms;
+        double h_dem = 0.0;
+        for (int l = 0; l < 3; ++l) h_dem -= p->Nd[k * 3 + l] * mbar[l];
+        spont_strain_deriv(p, m, k, D);
+        double me = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) me += S[i][j] * D[i][j];
+        h[k] = h_anis + h_zee + h_dem + scale * me;
+    }
+}
+
+/* Local energy density without exchange and demagnetisation: anisotropy,
+ * magnetoelastic and Zeeman terms of Eq. (MicromagneticsEnergy). */
+double or_energy_density_local(const or_params *p, const double m[3], const double E6[6]) {
+    double C[3][3][3][3], E[3][3], E0[3][3], R[3][3], S[3][3];
+    cubic_tensor(p, C);
+    sym_from6(E6, E);
+    spont_strain(p, m, E0);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R[i][j] = E[i][j] - E0[i][j];
+    contract(C, R, S);
+    double el = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) el += 0.5 * R[i][j] * S[i][j];
+    double an = p->K1 * (m[0] * m[0] * m[1] * m[1] + m[1] * m[1] * m[2] * m[2] + m[2] * m[2] * m[0] * m[0]);
+    double ze = -p->mu0 * p->Ms * (p->hext[0] * m[0] + p->hext[1] * m[1] + p->hext[2] * m[2]);
+    return an + el + ze;
+}
+
+/* ----------------------------------------------------------------- mesh */
+
+typedef struct { long long q[3]; int node; } keyed;
+
+static int cmp_keyed(const void *a, const void *b) {
+    const keyed *x = (const keyed *)a, *y = (const keyed *)b;
+    for (int k = 0; k < 3; ++k) {
+        if (x->q[k] < y->q[k]) return -1;
+        if (x->q[k] > y->q[k]) return 1;
+    }
+    return (x->node > y->node) - (x->node < y->node);
+}
+
+static int cmp_int(const void *a, const void *b) {
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* Periodic identification, Sec. 2.5: a node on the max face in some axis is
+ * wrapped onto the min face; nodes with equal wrapped coordinates (quantised
+ * to 1e-9 of the box edge) become one unique node. */
+static int wrap_nodes(or_sim *s, const double *xyz, const double lo[3], const double hi[3]) {
+    int n0 = s->n0;
+    keyed *k = (keyed *)malloc(sizeof(keyed) * (size_t)n0);
+    unsigned char *onmax = (unsigned char *)calloc((size_t)n0, 1);
+    for (int i = 0; i < n0; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            double L = hi[a] - lo[a], tol = 1e-9 * L, v = xyz[i * 3 + a];
+            if (v < lo[a] - tol || v > hi[a] + tol) {
+                free(k); free(onmax);
+                seterr(s, "node outside the periodic box");
+                return OR_E_MESH;
+            }
+            if (fabs(v - hi[a]) <= tol) { v = lo[a]; onmax[i] = 1; }
+            k[i].q[a] = llround((v - lo[a]) / tol);
+        }
+        k[i].node = i;
+    }
+    qsort(k, (size_t)n0, sizeof(keyed), cmp_keyed);
+    int *rep_of = (int *)malloc(sizeof(int) * (size_t)n0);
+    int *reps = (int *)malloc(sizeof(int) * (size_t)n0);
+    int ng = 0, g0 = 0;
+    while (g0 < n0) {
+        int g1 = g0 + 1;
+        while (g1 < n0 && k[g1].q[0] == k[g0].q[0] && k[g1].q[1] == k[g0].q[1] && k[g1].q[2] == k[g0].q[2]) ++g1;
+        int rep = -1, count = 0;
+        for (int t = g0; t < g1; ++t)
+            if (!onmax[k[t].node]) { if (rep < 0) rep = k[t].node; ++count; }
+        if (rep < 0 || count > 1) {
+            free(k); free(onmax); free(rep_of); free(reps);
+            seterr(s, rep < 0 ? "unmatched periodic node" : "duplicate node");
+            return OR_E_MESH;
+        }
+        for (int t = g0; t < g1; ++t) rep_of[k[t].node] = rep;
+        reps[ng++] = rep;
+        g0 = g1;
+    }
+    /* Unique ids follow the caller's order of the representatives. */
+    qsort(reps, (size_t)ng, sizeof(int), cmp_int);
+    int *uid = (int *)malloc(sizeof(int) * (size_t)n0);
+    for (int i = 0; i < n0; ++i) uid[i] = -1;
+    for (int g = 0; g < ng; ++g) uid[reps[g]] = g;
+    s->n = ng;
+    s->map = (int *)malloc(sizeof(int) * (size_t)n0);
+    s->x = (double *)malloc(sizeof(double) * 3 * (size_t)ng);
+    for (int i = 0; i < n0; ++i) s->map[i] = uid[rep_of[i]];
+    for (int g = 0; g < ng; ++g)
+        for (int a = 0; a < 3; ++a) s->x[g * 3 + a] = xyz[reps[g] * 3 + a];
+    free(k); free(onmax); free(rep_of); free(reps); free(uid);
+    return OR_OK;
+}
+
+/* P1 geometry of one element: gradients g_i of the barycentric coordinates
+ * from g_i . (x_k - x_0) = delta_ik (k = 1..3), g_0 = -(g_1 + g_2 + g_3), and the
+ * volume |det[x1-x0, x2-x0, x3-x0]| / 6.  Edges use the nearest periodic image. */
+static int tet_geometry(const or_sim *s, int e, double *vol, double g[4][3]) {
+    double X[4][3];
+    for (int v = 0; v < 4; ++v)
+        for (int a = 0; a < 3; ++a) X[v][a] = s->x[s->tet[e * 4 + v] * 3 + a];
+    double A[9], B[9];
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a) {
+            double d = X[k + 1][a] - X[0][a];
+            if (s->periodic) d -= s->L[a] * round(d / s->L[a]);
+            A[k * 3 + a] = d;          /* row k: edge vector k */
+        }
+    for (int r = 0; r < 9; ++r) B[r] = (r % 4 == 0) ? 1.0 : 0.0;   /* identity: columns are the three RHS */
+    double edge = 0.0;
+    for (int r = 0; r < 9; ++r) edge += A[r] * A[r];
+    edge = sqrt(edge / 3.0);
+    double det = gauss_solve(3, A, 3, B);
+    *vol = fabs(det) / 6.0;
+    if (!(*vol > 1e-9 * edge * edge * edge)) return OR_E_MESH;
+    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 3; ++a) g[i + 1][a] = B[a * 3 + i];
+    for (int a = 0; a < 3; ++a) g[0][a] = -(g[1][a] + g[2][a] + g[3][a]);
+    return OR_OK;
+}
+
+static int find_col(const or_sim *s, int row, int col) {
+    int lo = s->adj_ptr[row], hi = s->adj_ptr[row + 1] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) / 2;
+        if (s->adj[mid] == col) return mid;
+        if (s->adj[mid] < col) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+int or_create(or_sim **out, int32_t n0, const double *xyz, int32_t ne, const int32_t *tets, const uint8_t *tags,
+              const double lo[3], const double hi[3], int32_t periodic, char *err, int32_t errlen) {
+    *out = NULL;
+    or_sim *s = (or_sim *)calloc(1, sizeof(or_sim));
+    s->n0 = n0; s->ne = ne; s->periodic = periodic ? 1 : 0;
+    for (int a = 0; a < 3; ++a) { s->lo[a] = lo[a]; s->L[a] = hi[a] - lo[a]; }
+    int rc = OR_OK;
+    if (n0 < 4 || ne < 1) { seterr(s, "empty mesh"); rc = OR_E_ARG; goto fail; }
+    for (int a = 0; a < 3; ++a)
+        if (!(s->L[a] > 0)) { seterr(s, "bad box"); rc = OR_E_ARG; goto fail; }
+    if (s->periodic) {
+        rc = wrap_nodes(s, xyz, lo, hi);
+        if (rc) goto fail;
+    } else {
+        s->n = n0;
+        s->map = (int *)malloc(sizeof(int) * (size_t)n0);
+        s->x = (double *)malloc(sizeof(double) * 3 * (size_t)n0);
+        for (int i = 0; i < n0; ++i) s->map[i] = i;
+        memcpy(s->x, xyz, sizeof(double) * 3 * (size_t)n0);
+    }
+    int n = s->n;
+    s->tet = (int *)malloc(sizeof(int) * 4 * (size_t)ne);
+    s->tag = (uint8_t *)malloc((size_t)ne);
+    for (int e = 0; e < ne; ++e) {
+        for (int v = 0; v < 4; ++v) {
+            int t = tets[e * 4 + v];
+            if (t < 0 || t >= n0) { seterr(s, "node index out of range"); rc = OR_E_MESH; goto fail; }
+            s->tet[e * 4 + v] = s->map[t];
+        }
+        for (int v = 0; v < 4; ++v)
+            for (int w = v + 1; w < 4; ++w)
+                if (s->tet[e * 4 + v] == s->tet[e * 4 + w]) { seterr(s, "element with repeated node"); rc = OR_E_MESH; goto fail; }
+        s->tag[e] = tags[e];
+    }
+    s->vol = (double *)malloc(sizeof(double) * (size_t)ne);
+    s->grad = (double *)malloc(sizeof(double) * 12 * (size_t)ne);
+    s->w = (double *)calloc((size_t)n, sizeof(double));
+    s->mag = (uint8_t *)calloc((size_t)n, 1);
+    s->vc = 0.0;
+    for (int e = 0; e < ne; ++e) {
+        double g[4][3];
+        if (tet_geometry(s, e, &s->vol[e], g)) { seterr(s, "degenerate element"); rc = OR_E_MESH; goto fail; }
+        for (int v = 0; v < 4; ++v)
+            for (int a = 0; a < 3; ++a) s->grad[e * 12 + v * 3 + a] = g[v][a];
+        s->vc += s->vol[e];
+        if (s->tag[e])
+            for (int v = 0; v < 4; ++v) { s->w[s->tet[e * 4 + v]] += s->vol[e] / 4.0; s->mag[s->tet[e * 4 + v]] = 1; }
+    }
+    /* node -> element incidence */
+    s->n2e_ptr = (int *)calloc((size_t)n + 1, sizeof(int));
+    for (int e = 0; e < ne; ++e)
+        for (int v = 0; v < 4; ++v) s->n2e_ptr[s->tet[e * 4 + v] + 1]++;
+    for (int i = 0; i < n; ++i) s->n2e_ptr[i + 1] += s->n2e_ptr[i];
+    s->n2e = (int *)malloc(sizeof(int) * 4 * (size_t)ne);
+    {
+        int *fill = (int *)malloc(sizeof(int) * (size_t)n);
+        memcpy(fill, s->n2e_ptr, sizeof(int) * (size_t)n);
+        for (int e = 0; e < ne; ++e)
+            for (int v = 0; v < 4; ++v) s->n2e[fill[s->tet[e * 4 + v]]++] = e;
+        free(fill);
+    }
+    /* adjacency: all nodes sharing an element with node i (self included), sorted */
+    s->adj_ptr = (int *)calloc((size_t)n + 1, sizeof(int));
+    {
+        int *cnt = (int *)calloc((size_t)n, sizeof(int));
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int i = 0; i < n; ++i) {
+            int deg = s->n2e_ptr[i + 1] - s->n2e_ptr[i];
+            int *buf = (int *)malloc(sizeof(int) * 4 * (size_t)deg);
+            int c = 0;
+            for (int t = s->n2e_ptr[i]; t < s->n2e_ptr[i + 1]; ++t)
+                for (int v = 0; v < 4; ++v) buf[c++] = s->tet[s->n2e[t] * 4 + v];
+            qsort(buf, (size_t)c, sizeof(int), cmp_int);
+            int u = 0;
+            for (int t = 0; t < c; ++t)
+                if (t == 0 || buf[t] != buf[t - 1]) ++u;
+            cnt[i] = u;
+            free(buf);
+        }
+        for (int i = 0; i < n; ++i) s->adj_ptr[i + 1] = s->adj_ptr[i] + cnt[i];
+        free(cnt);
+    }
+    s->adj = (int *)malloc(sizeof(int) * (size_t)s->adj_ptr[n]);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int i = 0; i < n; ++i) {
+        int deg = s->n2e_ptr[i + 1] - s->n2e_ptr[i];
+        int *buf = (int *)malloc(sizeof(int) * 4 * (size_t)deg);
+        int c = 0;
+        for (int t = s->n2e_ptr[i]; t < s->n2e_ptr[i + 1]; ++t)
+            for (int v = 0; v < 4; ++v) buf[c++] = s->tet[s->n2e[t] * 4 + v];
+        qsort(buf, (size_t)c, sizeof(int), cmp_int);
+        int o = s->adj_ptr[i];
+        for (int t = 0; t < c; ++t)
+            if (t == 0 || buf[t] != buf[t - 1]) s->adj[o++] = buf[t];
+        free(buf);
+    }
+    /* Scalar matrices of Eq. (LHS) and the mass matrix F^GS of Eq. (RHS_F),
+     * assembled row by row from the elements incident to the row's node. */
+    {
+        size_t nnz = (size_t)s->adj_ptr[n];
+        s->Kmag = (double *)calloc(nnz, sizeof(double));
+        s->Mmag = (double *)calloc(nnz, sizeof(double));
+        s->Kall = (double *)calloc(nnz, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int i = 0; i < n; ++i)
+            for (int t = s->n2e_ptr[i]; t < s->n2e_ptr[i + 1]; ++t) {
+                int e = s->n2e[t], li = -1;
+                for (int v = 0; v < 4; ++v)
+                    if (s->tet[e * 4 + v] == i) li = v;
+                const double *gi = &s->grad[e * 12 + li * 3];
+                double V = s->vol[e];
+                for (int lj = 0; lj < 4; ++lj) {
+                    const double *gj = &s->grad[e * 12 + lj * 3];
+                    int pos = find_col(s, i, s->tet[e * 4 + lj]);
+                    double kij = V * (gi[0] * gj[0] + gi[1] * gj[1] + gi[2] * gj[2]);
+                    double mij = V * (li == lj ? 2.0 : 1.0) / 20.0;   /* int phi_i phi_j over a tet */
+                    s->Kall[pos] += kij;
+                    if (s->tag[e]) { s->Kmag[pos] += kij; s->Mmag[pos] += mij; }
+                }
+            }
+    }
+    s->p0 = s->map[0];   /* pinned node for the elastic solve: the caller's node 0 */
+    *out = s;
+    return OR_OK;
+fail:
+    if (err && errlen > 0) snprintf(err, (size_t)errlen, "%s", s->err);
+    or_destroy(s);
+    return rc;
+}
+
+void or_destroy(or_sim *s) {
+    if (!s) return;
+    free(s->map); free(s->x); free(s->tet); free(s->tag); free(s->vol); free(s->grad); free(s->w); free(s->mag);
+    free(s->n2e_ptr); free(s->n2e); free(s->adj_ptr); free(s->adj);
+    free(s->Kmag); free(s->Mmag); free(s->Kall); free(s->Kmech); free(s->m); free(s->u);
+    free(s);
+}
+
+int32_t or_n_unique(const or_sim *s) { return s->n; }
+void or_node_map(const or_sim *s, int32_t *map) { memcpy(map, s->map, sizeof(int) * (size_t)s->n0); }
+void or_geometry(const or_sim *s, double *vol, double *grad) {
+    memcpy(vol, s->vol, sizeof(double) * (size_t)s->ne);
+    memcpy(grad, s->grad, sizeof(double) * 12 * (size_t)s->ne);
+}
+double or_total_volume(const or_sim *s) { return s->vc; }
+void or_lumped_weights(const or_sim *s, double *w) { memcpy(w, s->w, sizeof(double) * (size_t)s->n); }
+int32_t or_pinned_node(const or_sim *s) { return s->p0; }
+const char *or_last_error(const or_sim *s) { return s ? s->err : "null oracle"; }
+
+/* Elastic stiffness of Eq. (LHS): block (i,j)_ab = int E(phi_j e_b) : C E(phi_i e_a)
+ * = V_e sum_qs C_aqbs d_q phi_i d_s phi_j on each element. */
+static void assemble_elastic(or_sim *s) {
+    int n = s->n;
+    size_t nnz = (size_t)s->adj_ptr[n];
+    free(s->Kmech);
+    s->Kmech = (double *)calloc(nnz * 9, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int i = 0; i < n; ++i)
+        for (int t = s->n2e_ptr[i]; t < s->n2e_ptr[i + 1]; ++t) {
+            int e = s->n2e[t], li = -1;
+            for (int v = 0; v < 4; ++v)
+                if (s->tet[e * 4 + v] == i) li = v;
+            const double *gi = &s->grad[e * 12 + li * 3];
+            double V = s->vol[e];
+            for (int lj = 0; lj < 4; ++lj) {
+                const double *gj = &s->grad[e * 12 + lj * 3];
+                int pos = find_col(s, i, s->tet[e * 4 + lj]);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        double v = 0.0;
+                        for (int q = 0; q < 3; ++q)
+                            for (int r = 0; r < 3; ++r) v += s->C[a][q][b][r] * gi[q] * gj[r];
+                        s->Kmech[pos * 9 + a * 3 + b] += V * v;
+                    }
+            }
+        }
+}
+
+int or_set_params(or_sim *s, const or_params *p) {
+    if (!(p->Ms > 0 && p->A >= 0 && p->mu0 > 0 && p->gamma0 > 0 && p->alpha >= 0 && p->cg_tol > 0 && p->cg_maxit > 0)) {
+        seterr(s, "invalid parameters");
+        return OR_E_ARG;
+    }
+    s->p = *p;
+    cubic_tensor(p, s->C);
+    assemble_elastic(s);
+    s->have_params = 1;
+    if (!s->u) s->u = (double *)calloc((size_t)s->n * 3, sizeof(double));
+    return OR_OK;
+}
+
+static int set_nodal(or_sim *s, const double *v, double *dst) {
+    /* periodic copies must carry the same value */
+    unsigned char *seen = (unsigned char *)calloc((size_t)s->n, 1);
+    for (int i = 0; i < s->n0; ++i) {
+        int g = s->map[i];
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(v[i * 3 + a])) { free(seen); seterr(s, "non-finite field value"); return OR_E_ARG; }
+        if (seen[g]) {
+            for (int a = 0; a < 3; ++a)
+                if (fabs(dst[g * 3 + a] - v[i * 3 + a]) > 1e-12 * (1.0 + fabs(dst[g * 3 + a]))) {
+                    free(seen); seterr(s, "periodic copies disagree"); return OR_E_ARG;
+                }
+        } else {
+            for (int a = 0; a < 3; ++a) dst[g * 3 + a] = v[i * 3 + a];
+            seen[g] = 1;
+        }
+    }
+    free(seen);
+    return OR_OK;
+}
+
+/* m is normalised on magnetic nodes and zero on nodes of the inclusions only. */
+int or_set_m(or_sim *s, const double *m) {
+    if (!s->m) s->m = (double *)calloc((size_t)s->n * 3, sizeof(double));
+    int rc = set_nodal(s, m, s->m);
+    if (rc) return rc;
+    for (int g = 0; g < s->n; ++g) {
+        double *v = &s->m[g * 3];
+        if (!s->mag[g]) { v[0] = v[1] = v[2] = 0.0; continue; }
+        double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (!(r > 0)) { seterr(s, "zero magnetisation on a magnetic node"); return OR_E_ARG; }
+        for (int a = 0; a < 3; ++a) v[a] /= r;
+    }
+    s->have_m = 1;
+    return OR_OK;
+}
+
+int or_set_u(or_sim *s, const double *u) {
+    if (!s->u) s->u = (double *)calloc((size_t)s->n * 3, sizeof(double));
+    return set_nodal(s, u, s->u);
+}
+
+void or_get_m(const or_sim *s, double *m) {
+    for (int i = 0; i < s->n0; ++i)
+        for (int a = 0; a < 3; ++a) m[i * 3 + a] = s->m ? s->m[s->map[i] * 3 + a] : 0.0;
+}
+void or_get_u(const or_sim *s, double *u) {
+    for (int i = 0; i < s->n0; ++i)
+        for (int a = 0; a < 3; ++a) u[i * 3 + a] = s->u ? s->u[s->map[i] * 3 + a] : 0.0;
+}
+
+/* ------------------------------------------------------------ operators */
+
+static void spmv_scalar(const or_sim *s, const double *A, const double *x, double *y, int stride, int comp) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < s->n; ++i) {
+        double v = 0.0;
+        for (int t = s->adj_ptr[i]; t < s->adj_ptr[i + 1]; ++t) v += A[t] * x[s->adj[t] * stride + comp];
+        y[i * stride + comp] = v;
+    }
+}
+
+static void spmv_elastic(const or_sim *s, const double *x, double *y) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < s->n; ++i) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int t = s->adj_ptr[i]; t < s->adj_ptr[i + 1]; ++t) {
+            const double *B = &s->Kmech[(size_t)t * 9];
+            const double *xj = &x[s->adj[t] * 3];
+            for (int a = 0; a < 3; ++a) v[a] += B[a * 3 + 0] * xj[0] + B[a * 3 + 1] * xj[1] + B[a * 3 + 2] * xj[2];
+        }
+        for (int a = 0; a < 3; ++a) y[i * 3 + a] = (i == s->p0) ? 0.0 : v[a];
+    }
+}
+
+/* eps K + M on one scalar component (contiguous length-n vectors). */
+static void apply_gs_scalar(const or_sim *s, double eps, const double *x, double *y) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < s->n; ++i) {
+        double v = 0.0;
+        for (int t = s->adj_ptr[i]; t < s->adj_ptr[i + 1]; ++t) v += (eps * s->Kmag[t] + s->Mmag[t]) * x[s->adj[t]];
+        y[i] = v;
+    }
+}
+
+int or_apply(const or_sim *s, int32_t which, double eps, const double *x, double *y) {
+    if (which == 3) {
+        if (!s->have_params) return OR_E_STATE;
+        spmv_elastic(s, x, y);
+        return OR_OK;
+    }
+    for (int c = 0; c < 3; ++c) {
+        if (which == 0) spmv_scalar(s, s->Kmag, x, y, 3, c);
+        else if (which == 1) spmv_scalar(s, s->Mmag, x, y, 3, c);
+        else if (which == 4) spmv_scalar(s, s->Kall, x, y, 3, c);
+        else if (which == 2) {
+#pragma omp parallel for schedule(static)
+            for (int i = 0; i < s->n; ++i) {
+                double v = 0.0;
+                for (int t = s->adj_ptr[i]; t < s->adj_ptr[i + 1]; ++t)
+                    v += (eps * s->Kmag[t] + s->Mmag[t]) * x[s->adj[t] * 3 + c];
+                y[i * 3 + c] = v;
+            }
+        } else return OR_E_ARG;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------- CG */
+
+typedef void (*apply_fn)(const or_sim *s, const void *ctx, const double *x, double *y);
+
+/* Unpreconditioned conjugate gradients on the DOFs not marked fixed (those
+ * rows are the identity with zero right-hand side, Sec. 2.5).  Stops when the
+ * recurrence residual satisfies ||r|| <= tol ||b||; b = 0 gives x = 0. */
+static int cg(const or_sim *s, apply_fn A, const void *ctx, int len, const uint8_t *fixed, const double *b_in,
+              double *x, double tol, int maxit, int *iters) {
+    double *b = (double *)malloc(sizeof(double) * (size_t)len);
+    double *r = (double *)malloc(sizeof(double) * (size_t)len);
+    double *p = (double *)malloc(sizeof(double) * (size_t)len);
+    double *q = (double *)malloc(sizeof(double) * (size_t)len);
+    for (int i = 0; i < len; ++i) {
+        b[i] = fixed[i] ? 0.0 : b_in[i];
+        if (fixed[i]) x[i] = 0.0;
+    }
+    int rc = OR_OK, k = 0;
+    double bb = dot(b, b, len);
+    if (bb == 0.0) {
+        for (int i = 0; i < len; ++i) x[i] = 0.0;
+        goto done;
+    }
+    A(s, ctx, x, q);
+    for (int i = 0; i < len; ++i) {
+        r[i] = fixed[i] ? 0.0 : b[i] - q[i];
+        p[i] = r[i];
+    }
+    double rr = dot(r, r, len), thr = tol * tol * bb;
+    while (rr > thr) {
+        if (k >= maxit) { rc = OR_E_NOCONV; break; }
+        A(s, ctx, p, q);
+        for (int i = 0; i < len; ++i)
+            if (fixed[i]) q[i] = 0.0;
+        double pq = dot(p, q, len);
+        double alpha = rr / pq;
+        for (int i = 0; i < len; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+        double rr_new = dot(r, r, len);
+        ++k;
+        if (!isfinite(rr_new)) { rc = OR_E_NONFINITE; break; }
+        if (rr_new <= thr) { rr = rr_new; break; }
+        double beta = rr_new / rr;
+        for (int i = 0; i < len; ++i) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+    }
+done:
+    *iters = k;
+    free(b); free(r); free(p); free(q);
+    return rc;
+}
+
+static void cg_apply_elastic(const or_sim *s, const void *ctx, const double *x, double *y) {
+    (void)ctx;
+    spmv_elastic(s, x, y);
+}
+static void cg_apply_gs(const or_sim *s, const void *ctx, const double *x, double *y) {
+    apply_gs_scalar(s, *(const double *)ctx, x, y);
+}
+
+static int solve_elastic(const or_sim *s, const double *b, double *u, double tol, int maxit, int *iters) {
+    int len = 3 * s->n;
+    uint8_t *fixed = (uint8_t *)calloc((size_t)len, 1);
+    for (int a = 0; a < 3; ++a) fixed[s->p0 * 3 + a] = 1;
+    int rc = cg(s, cg_apply_elastic, NULL, len, fixed, b, u, tol, maxit, iters);
+    free(fixed);
+    return rc;
+}
+
+/* One scalar GS solve (eps K + M) x = b on the magnetic nodes (Eq. weak_GS). */
+static int solve_gs(const or_sim *s, double eps, const double *b, double *x, double tol, int maxit, int *iters) {
+    uint8_t *fixed = (uint8_t *)malloc((size_t)s->n);
+    for (int i = 0; i < s->n; ++i) fixed[i] = !s->mag[i];
+    int rc = cg(s, cg_apply_gs, &eps, s->n, fixed, b, x, tol, maxit, iters);
+    free(fixed);
+    return rc;
+}
+
+int or_solve(const or_sim *s, int32_t which, double eps, const double *b, double *x, double tol, int32_t maxit,
+             int32_t *iters) {
+    if (which == 3) {
+        if (!s->have_params) return OR_E_STATE;
+        int it = 0, rc = solve_elastic(s, b, x, tol, maxit, &it);
+        *iters = it;
+        return rc;
+    }
+    if (which != 2) return OR_E_ARG;
+    int n = s->n, total = 0, rc = OR_OK;
+    double *bc = (double *)malloc(sizeof(double) * (size_t)n), *xc = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int c = 0; c < 3 && rc == OR_OK; ++c) {
+        for (int i = 0; i < n; ++i) { bc[i] = b[i * 3 + c]; xc[i] = x[i * 3 + c]; }
+        int it = 0;
+        rc = solve_gs(s, eps, bc, xc, tol, maxit, &it);
+        total += it;
+        for (int i = 0; i < n; ++i) x[i * 3 + c] = xc[i];
+    }
+    free(bc); free(xc);
+    *iters = total;
+    return rc;
+}
+
+/* --------------------------------------------------- averages and RHS */
+
+/* Volume averages over the computational cell (Sec. 2.4).  For a P1 field the
+ * element integral is V_e times the vertex mean, so any quadrature rule of
+ * degree >= 1 gives sum_j w_j g_j / V_c with w_j the magnetic lumped weights;
+ * m and E0(m) vanish in the inclusions.  Ebar = <E0(m)> + C^-1 sigma_ext
+ * minimises Eq. (MicromagneticsEnergy) over the homogeneous strain when the
+ * heterogeneous strain has zero mean. */
+static void averages_at(const or_sim *s, const double *m, double mbar[3], double ebar[6]) {
+    double sm[3] = {0, 0, 0}, se[3][3] = {{0}};
+    for (int i = 0; i < s->n; ++i) {
+        if (!s->mag[i]) continue;
+        double E0[3][3];
+        spont_strain(&s->p, &m[i * 3], E0);
+        for (int a = 0; a < 3; ++a) {
+            sm[a] += s->w[i] * m[i * 3 + a];
+            for (int b = 0; b < 3; ++b) se[a][b] += s->w[i] * E0[a][b];
+        }
+    }
+    double e6[6], c6[6], C[3][3][3][3];
+    for (int a = 0; a < 3; ++a) {
+        mbar[a] = sm[a] / s->vc;
+        for (int b = 0; b < 3; ++b) se[a][b] /= s->vc;
+    }
+    sym_to6(se, e6);
+    memcpy(C, s->C, sizeof C);
+    cubic_compliance_apply(C, s->p.sigma_ext, c6);
+    for (int k = 0; k < 6; ++k) ebar[k] = e6[k] + c6[k];
+}
+
+/* Elastic right-hand side of Eq. (RHS_b): b_(i,a) = int E(phi_i e_a) : C E0_h with
+ * E0_h the P1 interpolant of E0(m) on magnetic elements and zero in the
+ * inclusions; the pinned node's rows are zero. */
+static void elastic_rhs_at(const or_sim *s, const double *m, double *b) {
+    memset(b, 0, sizeof(double) * 3 * (size_t)s->n);
+    for (int e = 0; e < s->ne; ++e) {
+        if (!s->tag[e]) continue;
+        double E0m[3][3] = {{0}}, S[3][3], C[3][3][3][3];
+        for (int v = 0; v < 4; ++v) {
+            double E0[3][3];
+            spont_strain(&s->p, &m[s->tet[e * 4 + v] * 3], E0);
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) E0m[a][c] += 0.25 * E0[a][c];
+        }
+        memcpy(C, s->C, sizeof C);
+        contract(C, E0m, S);
+        for (int v = 0; v < 4; ++v) {
+            const double *g = &s->grad[e * 12 + v * 3];
+            int node = s->tet[e * 4 + v];
+            for (int a = 0; a < 3; ++a)
+                b[node * 3 + a] += s->vol[e] * (S[a][0] * g[0] + S[a][1] * g[1] + S[a][2] * g[2]);
+        }
+    }
+    for (int a = 0; a < 3; ++a) b[s->p0 * 3 + a] = 0.0;
+}
+
+/* Right-hand side of Eq. (RHS_b) for the GS equation (Eq. weak_GS) with
+ * f = y + c h: b = M y + ch, ch = sum_e M^e (c h^e) over magnetic elements.
+ * h^e at vertex j uses m_j and the element's total strain Ebar + sym grad u
+ * (constant on a P1 element). */
+static void field_rhs_at(const or_sim *s, const double *m, const double *y, const double *u, const double ebar[6],
+                         const double mbar[3], double c, double *b, double *ch) {
+    memset(ch, 0, sizeof(double) * 3 * (size_t)s->n);
+    for (int e = 0; e < s->ne; ++e) {
+        if (!s->tag[e]) continue;
+        double H[3][3] = {{0}}, E[3][3], E6[6], Eb[3][3];
+        for (int v = 0; v < 4; ++v) {
+            const double *g = &s->grad[e * 12 + v * 3];
+            const double *uv = &u[s->tet[e * 4 + v] * 3];
+            for (int a = 0; a < 3; ++a)
+                for (int d = 0; d < 3; ++d) H[a][d] += uv[a] * g[d];
+        }
+        sym_from6(ebar, Eb);
+        for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) E[a][d] = Eb[a][d] + 0.5 * (H[a][d] + H[d][a]);
+        sym_to6(E, E6);
+        double f[4][3];
+        for (int v = 0; v < 4; ++v) {
+            double h[3];
+            or_h_local(&s->p, &m[s->tet[e * 4 + v] * 3], E6, mbar, h);
+            for (int a = 0; a < 3; ++a) f[v][a] = c * h[a];
+        }
+        for (int i = 0; i < 4; ++i) {
+            int node = s->tet[e * 4 + i];
+            for (int j = 0; j < 4; ++j) {
+                double mij = s->vol[e] * (i == j ? 2.0 : 1.0) / 20.0;
+                for (int a = 0; a < 3; ++a) ch[node * 3 + a] += mij * f[j][a];
+            }
+        }
+    }
+    for (int comp = 0; comp < 3; ++comp) spmv_scalar(s, s->Mmag, y, b, 3, comp);
+    for (int i = 0; i < 3 * s->n; ++i) b[i] += ch[i];
+}
+
+int or_elastic_rhs(or_sim *s, double *b) {
+    if (!s->have_params || !s->have_m) return OR_E_STATE;
+    elastic_rhs_at(s, s->m, b);
+    return OR_OK;
+}
+
+int or_field_rhs(or_sim *s, double c, double *b, double *ch) {
+    if (!s->have_params || !s->have_m) return OR_E_STATE;
+    double mbar[3], ebar[6];
+    averages_at(s, s->m, mbar, ebar);
+    field_rhs_at(s, s->m, s->m, s->u, ebar, mbar, c, b, ch);
+    return OR_OK;
+}
+
+int or_averages(or_sim *s, double mbar[3], double ebar[6]) {
+    if (!s->have_params || !s->have_m) return OR_E_STATE;
+    averages_at(s, s->m, mbar, ebar);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------ the step */
+
+/* GS initial guess: the lumped estimate y + ch / w of f (the solution is close
+ * to f when eps is small, Sec. 2.1); zero off the magnetic nodes. */
+static void gs_guess(const or_sim *s, const double *y, const double *ch, int comp, double *x) {
+    for (int i = 0; i < s->n; ++i) x[i] = s->mag[i] ? y[i * 3 + comp] + ch[i * 3 + comp] / s->w[i] : 0.0;
+}
+
+static int gs_component(const or_sim *s, double eps, const double *b, const double *y, const double *ch, int comp,
+                        double *out, int *iters) {
+    int n = s->n;
+    double *bc = (double *)malloc(sizeof(double) * (size_t)n), *xc = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int i = 0; i < n; ++i) bc[i] = b[i * 3 + comp];
+    gs_guess(s, y, ch, comp, xc);
+    int rc = solve_gs(s, eps, bc, xc, s->p.cg_tol, s->p.cg_maxit, iters);
+    for (int i = 0; i < n; ++i) out[i * 3 + comp] = xc[i];
+    free(bc); free(xc);
+    return rc;
+}
+
+/* Algorithm B.1 (App. B) in the finite-element form of Eq. (weak_GS):
+ * (1 - eps lap)^-1 [y + c h] is the solution g of (eps K + M) g = M y + c M h,
+ * with eps = A* dtau = l_ex^2 dtau (SI lengths), dtau = gamma0 Ms dt.
+ * The updates of Step 2 use the values printed in the algorithm: rows 1 and 2
+ * take m^n and g^n, row 3 takes m* and g*; g* uses h[m^n].  Elasticity is
+ * solved once per step at m^n and its displacement is held for h[m*]. */
+int or_step(or_sim *s, double dt, int32_t nsteps, or_stats *st) {
+    if (!s->have_params || !s->have_m) { seterr(s, "step before params and m"); return OR_E_STATE; }
+    if (!(dt > 0) || nsteps < 0) { seterr(s, "bad dt or step count"); return OR_E_ARG; }
+    const or_params *p = &s->p;
+    int n = s->n;
+    size_t sz = sizeof(double) * 3 * (size_t)n;
+    double *b = (double *)malloc(sz), *ch = (double *)malloc(sz), *g = (double *)malloc(sz);
+    double *ms = (double *)malloc(sz), *gs = (double *)malloc(sz), *mss = (double *)malloc(sz);
+    double *u = (double *)malloc(sz), *bm = (double *)malloc(sz);
+    double dtau = p->gamma0 * p->Ms * dt;
+    double lex2 = 2.0 * p->A / (p->mu0 * p->Ms * p->Ms);
+    double eps1 = lex2 * dtau, eps3 = p->alpha * eps1;
+    int rc = OR_OK;
+    if (st) memset(st, 0, sizeof *st);
+    for (int step = 0; step < nsteps; ++step) {
+        const double *m = s->m;
+        double mbar[3], ebar[6];
+        int it;
+        /* averages at m^n feed the far field and the homogeneous strain */
+        averages_at(s, m, mbar, ebar);
+        /* mechanical equilibrium, Eq. (weak_elasticity), warm start u^{n-1} */
+        elastic_rhs_at(s, m, bm);
+        memcpy(u, s->u, sz);
+        rc = solve_elastic(s, bm, u, p->cg_tol, p->cg_maxit, &it);
+        if (st) st->mech_iters += it;
+        if (rc) break;
+        if (p->precession) {
+            /* Step 1: g^n for all three components */
+            field_rhs_at(s, m, m, u, ebar, mbar, dtau, b, ch);
+            for (int c = 0; c < 3 && !rc; ++c) {
+                rc = gs_component(s, eps1, b, m, ch, c, g, &it);
+                if (st) st->gs_iters[c] += it;
+            }
+            if (rc) break;
+            /* Step 2, rows 1 and 2 */
+            for (int i = 0; i < n; ++i) {
+                const double *mi = &m[i * 3], *gi = &g[i * 3];
+                ms[i * 3 + 0] = mi[0] + (gi[1] * mi[2] - gi[2] * mi[1]);
+                ms[i * 3 + 1] = mi[1] + (gi[2] * mi[0] - gi[0] * mi[2]);
+                ms[i * 3 + 2] = mi[2];
+            }
+            /* Step 1, g* for components 1 and 2 with h[m^n] */
+            for (int c = 0; c < 2; ++c) spmv_scalar(s, s->Mmag, ms, b, 3, c);
+            for (int i = 0; i < n; ++i)
+                for (int c = 0; c < 2; ++c) b[i * 3 + c] += ch[i * 3 + c];
+            for (int c = 0; c < 2 && !rc; ++c) {
+                rc = gs_component(s, eps1, b, ms, ch, c, gs, &it);
+                if (st) st->gs_iters[3 + c] += it;
+            }
+            if (rc) break;
+            /* Step 2, row 3 */
+            for (int i = 0; i < n; ++i)
+                ms[i * 3 + 2] = m[i * 3 + 2] + (gs[i * 3 + 0] * ms[i * 3 + 1] - gs[i * 3 + 1] * ms[i * 3 + 0]);
+        } else {
+            memcpy(ms, m, sz);
+        }
+        /* Step 3: damped solve with h[m*] (averages re-evaluated at m*) */
+        {
+            double mbar2[3], ebar2[6];
+            averages_at(s, ms, mbar2, ebar2);
+            field_rhs_at(s, ms, ms, u, ebar2, mbar2, p->alpha * dtau, b, ch);
+            for (int c = 0; c < 3 && !rc; ++c) {
+                rc = gs_component(s, eps3, b, ms, ch, c, mss, &it);
+                if (st) st->gs_iters[5 + c] += it;
+            }
+            if (rc) break;
+        }
+        /* Step 4: unit length on the magnetic nodes */
+        double dsum = 0.0;
+        int nmag = 0, bad = 0;
+        for (int i = 0; i < n; ++i) {
+            double *v = &mss[i * 3];
+            if (!s->mag[i]) { v[0] = v[1] = v[2] = 0.0; continue; }
+            double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (!(r > 0) || !isfinite(r)) { bad = 1; break; }
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                v[a] /= r;
+                d2 += (v[a] - m[i * 3 + a]) * (v[a] - m[i * 3 + a]);
+            }
+            dsum += sqrt(d2);
+            ++nmag;
+        }
+        if (bad) { rc = OR_E_NONFINITE; seterr(s, "non-finite magnetisation"); break; }
+        memcpy(s->m, mss, sz);
+        memcpy(s->u, u, sz);
+        if (st) { st->steps_done = step + 1; st->dm_avg = nmag ? dsum / nmag : 0.0; }
+    }
+    if (rc == OR_E_NOCONV) seterr(s, "CG did not converge");
+    free(b); free(ch); free(g); free(ms); free(gs); free(mss); free(u); free(bm);
+    return rc;
+}
+
+/* --------------------------------------------------------------- energy */
+
+/* Energy densities of Eq. (MicromagneticsEnergy) averaged over the cell:
+ * exchange A |grad m|^2 exact for P1; anisotropy, Zeeman and magnetoelastic
+ * by the vertex rule (V_e / 4 per vertex); stress work -sigma_ext : Ebar (the
+ * heterogeneous strain has zero mean); far-field demagnetisation
+ * (mu0 Ms^2 / 2) mbar . N mbar. */
+int or_energies(or_sim *s, double out[7]) {
+    if (!s->have_params || !s->have_m) return OR_E_STATE;
+    const or_params *p = &s->p;
+    double mbar[3], ebar[6], Eb[3][3], C[3][3][3][3];
+    averages_at(s, s->m, mbar, ebar);
+    sym_from6(ebar, Eb);
+    memcpy(C, s->C, sizeof C);
+    double ex = 0, an = 0, ze = 0, me = 0;
+    for (int e = 0; e < s->ne; ++e) {
+        double V = s->vol[e], H[3][3] = {{0}}, Gm[3][3] = {{0}};
+        for (int v = 0; v < 4; ++v) {
+            const double *g = &s->grad[e * 12 + v * 3];
+            const double *uv = &s->u[s->tet[e * 4 + v] * 3], *mv = &s->m[s->tet[e * 4 + v] * 3];
+            for (int a = 0; a < 3; ++a)
+                for (int d = 0; d < 3; ++d) { H[a][d] += uv[a] * g[d]; Gm[a][d] += mv[a] * g[d]; }
+        }
+        double E[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) E[a][d] = Eb[a][d] + 0.5 * (H[a][d] + H[d][a]);
+        if (s->tag[e])
+            for (int a = 0; a < 3; ++a)
+                for (int d = 0; d < 3; ++d) ex += p->A * V * Gm[a][d] * Gm[a][d];
+        for (int v = 0; v < 4; ++v) {
+            const double *mv = &s->m[s->tet[e * 4 + v] * 3];
+            double E0[3][3] = {{0}}, R[3][3], S[3][3];
+            if (s->tag[e]) {
+                spont_strain(p, mv, E0);
+                an += 0.25 * V * p->K1 * (mv[0] * mv[0] * mv[1] * mv[1] + mv[1] * mv[1] * mv[2] * mv[2] + mv[2] * mv[2] * mv[0] * mv[0]);
+                ze += -0.25 * V * p->mu0 * p->Ms * (p->hext[0] * mv[0] + p->hext[1] * mv[1] + p->hext[2] * mv[2]);
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int d = 0; d < 3; ++d) R[a][d] = E[a][d] - E0[a][d];
+            contract(C, R, S);
+            for (int a = 0; a < 3; ++a)
+                for (int d = 0; d < 3; ++d) me += 0.25 * V * 0.5 * R[a][d] * S[a][d];
+        }
+    }
+    double sg[3][3], work = 0.0;
+    sym_from6(p->sigma_ext, sg);
+    for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 3; ++d) work -= sg[a][d] * Eb[a][d];
+    double dem = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 3; ++d) dem += mbar[a] * p->Nd[a * 3 + d] * mbar[d];
+    dem *= 0.5 * p->mu0 * p->Ms * p->Ms;
+    out[0] = ex / s->vc; out[1] = an / s->vc; out[2] = ze / s->vc; out[3] = me / s->vc;
+    out[4] = work; out[5] = dem;
+    out[6] = out[0] + out[1] + out[2] + out[3] + out[4] + out[5];
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------- demag */
+
+/* Demagnetisation factors of an ellipsoid with semi-axes a, b, c:
+ * N_a = (abc/2) int_0^inf ds / ((a^2+s) sqrt((a^2+s)(b^2+s)(c^2+s))),
+ * evaluated by composite Simpson quadrature in t = ln s. */
+void or_demag_factors(double a, double b, double c, double N[3]) {
+    double ax[3] = {a, b, c};
+    double smin = fmin(a, fmin(b, c)), smax = fmax(a, fmax(b, c));
+    double t0 = log(smin * smin) - 45.0, t1 = log(smax * smax) + 80.0;
+    int steps = 200000;
+    double h = (t1 - t0) / steps;
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i <= steps; ++i) {
+            double t = t0 + h * i, s = exp(t);
+            double f = s / ((ax[k] * ax[k] + s) * sqrt((a * a + s) * (b * b + s) * (c * c + s)));
+            double wgt = (i == 0 || i == steps) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+            acc += wgt * f;
+        }
+        N[k] = 0.5 * a * b * c * acc * h / 3.0;
+    }
+}

@@ -1,0 +1,98 @@
+/*
+ * GSPM oracle: a plain, slow CPU FP64 reference of one time step of the
+ * Gauss-Seidel projection method for finite-element micromagnetics with
+ * magnetostriction and ellipsoid-theorem far-field demagnetisation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark are the only callers.  The HIP library never
+ * includes this header or links this code, and this code knows nothing of it.
+ *
+ * Units are SI.  Node-indexed arrays passed in or out are in the caller's
+ * node order, three values per node (row-major n0 x 3), unless stated.
+ */
+#ifndef GSPM_ORACLE_H
+#define GSPM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_OK = 0, OR_E_ARG = -1, OR_E_MESH = -2, OR_E_STATE = -3, OR_E_NOCONV = -5, OR_E_NONFINITE = -6 };
+
+typedef struct {
+    double Ms, A, K1, lambda100, lambda111, c11, c12, c44, alpha, mu0, gamma0;
+    double Nd[9];          /* body demagnetisation tensor, row-major */
+    double hext[3];        /* applied field [A/m] */
+    double sigma_ext[6];   /* applied stress [Pa], order xx yy zz yz xz xy */
+    double cg_tol;         /* relative residual ||r|| <= tol ||b|| */
+    int32_t cg_maxit;
+    int32_t precession;    /* 1: full Algorithm B.1; 0: damping stage only (m* = m^n) */
+} or_params;
+
+typedef struct {
+    int32_t steps_done;
+    int32_t mech_iters;    /* elastic CG iterations summed over the steps */
+    int32_t gs_iters[8];   /* per scalar GS solve, summed: g1 g2 g3, g*1 g*2, m**1 m**2 m**3 */
+    double dm_avg;         /* mean |m^{n+1} - m^n| over magnetic nodes, last step */
+} or_stats;
+
+typedef struct or_sim or_sim;
+
+/* Mesh: xyz n0x3, tets ne x 4 (0-based), tags ne (0 = nonmagnetic).  With
+ * periodic != 0 nodes on the max face of the box [lo, hi] are identified with
+ * their min-face partners.  Returns OR_E_MESH with a message in err on failure. */
+int or_create(or_sim **out, int32_t n0, const double *xyz, int32_t ne, const int32_t *tets,
+              const uint8_t *tags, const double lo[3], const double hi[3], int32_t periodic,
+              char *err, int32_t errlen);
+void or_destroy(or_sim *s);
+
+int32_t or_n_unique(const or_sim *s);
+void or_node_map(const or_sim *s, int32_t *map);          /* n0: caller node -> unique node */
+void or_geometry(const or_sim *s, double *vol, double *grad); /* ne and ne x 4 x 3 */
+double or_total_volume(const or_sim *s);
+void or_lumped_weights(const or_sim *s, double *w);       /* unique-node order, n */
+int32_t or_pinned_node(const or_sim *s);
+
+int or_set_params(or_sim *s, const or_params *p);
+int or_set_m(or_sim *s, const double *m);                 /* n0 x 3 */
+int or_set_u(or_sim *s, const double *u);                 /* n0 x 3 */
+void or_get_m(const or_sim *s, double *m);
+void or_get_u(const or_sim *s, double *u);
+
+/* Operators in unique-node order, x and y are n x 3.
+ * which: 0 Laplacian K over magnetic elements (per component)
+ *        1 mass M over magnetic elements (per component)
+ *        2 eps K + M (per component)
+ *        3 elastic K^mech over all elements, pinned node rows zeroed
+ *        4 Laplacian over all elements (per component) */
+int or_apply(const or_sim *s, int32_t which, double eps, const double *x, double *y);
+
+/* CG on operator `which` (2 or 3 above), unique-node order; x holds x0 on
+ * entry.  Components of the GS operator are solved independently. */
+int or_solve(const or_sim *s, int32_t which, double eps, const double *b, double *x, double tol,
+             int32_t maxit, int32_t *iters);
+
+int or_step(or_sim *s, double dt, int32_t n, or_stats *st);
+
+/* Energy densities averaged over the computational cell [J/m^3]:
+ * out = {exchange, anisotropy, zeeman, magnetoelastic, stress work, far-field demag, total}. */
+int or_energies(or_sim *s, double out[7]);
+/* mbar[3]; ebar[6] = mean strain, order xx yy zz yz xz xy. */
+int or_averages(or_sim *s, double mbar[3], double ebar[6]);
+
+/* Pieces exposed for the pins. */
+int or_elastic_rhs(or_sim *s, double *b);                 /* unique order n x 3, at current m */
+int or_field_rhs(or_sim *s, double c, double *b, double *ch); /* at current m and u, n x 3 each */
+void or_demag_factors(double a, double b, double c, double N[3]);
+void or_h_local(const or_params *p, const double m[3], const double E[6], const double mbar[3],
+                double h[3]);
+double or_energy_density_local(const or_params *p, const double m[3], const double E[6]);
+
+const char *or_last_error(const or_sim *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
