@@ -1,0 +1,186 @@
+/*
+ * gspm.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of one time step of the Gauss-Seidel projection method (GSPM) for
+ * finite-element micromagnetics with magnetostriction (Guan & Renuka
+ * Balakrishna, "CuPyMag", arXiv 2510.09812).
+ *
+ * The problem (Sec. 2.1): a cuboid computational cell Omega_c inside an
+ * ellipsoidal body, split into a ferromagnetic host Omega_m and nonmagnetic
+ * inclusions; unknowns are the unit magnetisation m = M/Ms and the periodic
+ * displacement u.  One call of gspm_step advances Algorithm B.1 (App. B) by
+ * n steps: volume averages (Sec. 2.4) feed the far-field demagnetising field
+ * -Ms N_d mbar (Sec. 2.1, ellipsoid theorem) and the homogeneous strain;
+ * mechanical equilibrium (Eq. elasticity, weak form Eq. weak_elasticity) is
+ * solved by unpreconditioned CG with one pinned node (Sec. 2.5); the three
+ * stages of (1 - eps lap) g = f (Eq. GS, weak form Eq. weak_GS) are solved by
+ * unpreconditioned CG; the cross-product update and the unit-length
+ * projection close the step.
+ *
+ * Conventions shared by every entry point
+ *   - Units are SI (metres, A/m, Pa, J/m^3, seconds).
+ *   - Node-indexed arrays are host arrays in the caller's node order, three
+ *     doubles per node, row-major (n_nodes x 3).  The library identifies the
+ *     max-face copies of periodic nodes with their min-face partners (Sec. 2.5)
+ *     and renumbers nodes internally; neither is visible to the caller.  On
+ *     input, the copies of one periodic node must carry the same values (to
+ *     1e-12 relative) or the call fails with GSPM_E_ARG; on output all copies
+ *     receive the value of their node.
+ *   - Ownership: the caller owns every host array; the library reads or writes
+ *     it only during the call and keeps no pointer.  The context owns all device
+ *     memory and releases it in gspm_destroy.
+ *   - Errors: every call returns a gspm_status; on failure gspm_last_error()
+ *     gives a message.  No call throws or aborts.  A failed call leaves the
+ *     state as it was, except gspm_step (see there).
+ *   - Call order: create -> upload_mesh -> set_params -> set_field(M) -> step.
+ *     Calls out of order return GSPM_E_STATE.
+ *   - Threads: one context is used by one host thread at a time.  All device
+ *     work runs on the context's stream.
+ */
+#ifndef GSPM_H
+#define GSPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gspm_ctx gspm_ctx;
+
+typedef enum {
+    GSPM_OK = 0,
+    GSPM_E_ARG = -1,        /* invalid argument (null pointer, size, value) */
+    GSPM_E_MESH = -2,       /* degenerate element, unmatched periodic node, bad index */
+    GSPM_E_STATE = -3,      /* call out of order */
+    GSPM_E_DEVICE = -4,     /* HIP runtime error or no usable gfx950 device */
+    GSPM_E_NOCONV = -5,     /* CG reached cg_maxit */
+    GSPM_E_NONFINITE = -6,  /* NaN or Inf in the state */
+    GSPM_E_OOM = -7         /* device allocation failed */
+} gspm_status;
+
+typedef enum { GSPM_FP64 = 0, GSPM_MIXED = 1 } gspm_precision;
+
+typedef enum { GSPM_FIELD_M = 0, GSPM_FIELD_U = 1 } gspm_field;
+
+/* Operators of Eq. (LHS) and Eq. (RHS_F), Sec. 2.3, for gspm_apply/gspm_solve. */
+typedef enum {
+    GSPM_OP_LAPLACE = 0,    /* K_ij = int grad phi_i . grad phi_j over magnetic elements, per component */
+    GSPM_OP_MASS = 1,       /* M_ij = int phi_i phi_j over magnetic elements (F^GS), per component */
+    GSPM_OP_GS = 2,         /* eps K + M: the GSPM operator of Eq. (weak_GS), per component */
+    GSPM_OP_ELASTIC = 3     /* K^mech over all elements; rows of the pinned node are zero */
+} gspm_op;
+
+#define GSPM_PERIODIC 1u
+
+typedef struct {
+    int32_t device;         /* HIP device ordinal */
+    int32_t precision;      /* GSPM_FP64, or GSPM_MIXED: FP32 element work and matvecs,
+                               FP64 state, dot products, norms and averages */
+    int32_t block_nodes;    /* nodes per owner block (power of two, 64..1024), 0 = automatic */
+    int32_t profile;        /* nonzero: time every elastic matvec launch with HIP events */
+    void *stream;           /* hipStream_t to run on, or NULL for a stream owned by the context */
+} gspm_create_opts;
+
+/* Material and run parameters (App. A notation; SI units). */
+typedef struct {
+    double Ms;              /* saturation magnetisation m_s [A/m] */
+    double A;               /* exchange coefficient [J/m] */
+    double K1;              /* cubic anisotropy kappa_1 [J/m^3] */
+    double lambda100, lambda111;   /* magnetostriction constants */
+    double c11, c12, c44;   /* cubic elastic constants [Pa] */
+    double alpha;           /* damping constant */
+    double mu0;             /* vacuum permeability [T m/A] */
+    double gamma0;          /* gyromagnetic ratio of tau = gamma0 Ms t [m/(A s)] */
+    double Nd[9];           /* demagnetisation tensor of the body, row-major */
+    double hext[3];         /* applied field H_ext [A/m] */
+    double sigma_ext[6];    /* applied stress [Pa], order xx yy zz yz xz xy */
+    double cg_tol;          /* CG stops at ||r||_2 <= cg_tol ||b||_2 (Sec. 3.1 criterion) */
+    int32_t cg_maxit;       /* CG iteration cap per scalar or vector solve; exceeding it is GSPM_E_NOCONV */
+    int32_t precession;     /* 1: full Algorithm B.1; 0: damping stage only (m* = m^n) */
+} gspm_params;
+
+typedef struct {
+    int32_t steps_done;     /* steps completed by this call */
+    int32_t failed_step;    /* index (within the call) of the step that failed, or -1 */
+    int64_t mech_iters;     /* elastic CG iterations, summed over the steps */
+    int64_t gs_iters;       /* GS CG iterations, summed over all scalar solves and steps */
+    int64_t gs_iters_stage[8]; /* per scalar solve: g1 g2 g3, g*1 g*2, m**1 m**2 m**3 */
+    double dm_avg;          /* mean |m^{n+1} - m^n| over magnetic nodes, last step (Sec. 3.2) */
+    double elapsed_ms;      /* wall time of the call on the device stream */
+    double matvec_ms;       /* profile mode: summed duration of the elastic matvec launches */
+    int64_t matvec_launches;/* profile mode: number of elastic matvec launches timed */
+} gspm_step_stats;
+
+/* Create a context on opts->device (NULL opts: device 0, FP64, own stream).
+ * Fails with GSPM_E_DEVICE when no HIP device is usable. */
+gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts);
+void gspm_destroy(gspm_ctx *ctx);
+
+/* Mesh upload (Sec. 2.1 domain, Sec. 2.5 periodic identification).
+ * xyz: n_nodes x 3 coordinates; tets: n_tets x 4 node indices (0-based, either
+ * orientation); tags: n_tets bytes, 0 = nonmagnetic inclusion (Omega_d), any
+ * other value = magnetic host (Omega_m); lo/hi: the periodic box.  flags must
+ * contain GSPM_PERIODIC.  Validates the mesh (GSPM_E_MESH on a degenerate or
+ * repeated-node element, a node outside the box, or an unmatched periodic
+ * node), renumbers nodes along a Morton curve, builds the element blocks and
+ * copies everything to the device once.  Resets all fields to zero. */
+gspm_status gspm_upload_mesh(gspm_ctx *ctx, int64_t n_nodes, const double *xyz, int64_t n_tets,
+                             const int32_t *tets, const uint8_t *tags, const double lo[3], const double hi[3],
+                             uint32_t flags);
+
+/* Set material and run parameters; may be called again between steps (for
+ * example to change hext along a hysteresis sweep). */
+gspm_status gspm_set_params(gspm_ctx *ctx, const gspm_params *params);
+
+/* Set or read a nodal field (n_nodes x 3, caller's order).  Setting M
+ * normalises m on magnetic nodes and zeroes it on nodes that lie in
+ * inclusions only; a zero or non-finite vector on a magnetic node is
+ * GSPM_E_ARG.  U is the periodic displacement [m]. */
+gspm_status gspm_set_field(gspm_ctx *ctx, gspm_field which, const double *values, int64_t n_nodes);
+gspm_status gspm_get_field(gspm_ctx *ctx, gspm_field which, double *out, int64_t n_nodes);
+
+/* Advance Algorithm B.1 by n_steps steps of dt seconds.  stats may be NULL.
+ * On GSPM_E_NOCONV or GSPM_E_NONFINITE the state is that after the last
+ * completed step and stats->failed_step names the step that failed. */
+gspm_status gspm_step(gspm_ctx *ctx, double dt, int32_t n_steps, gspm_step_stats *stats);
+
+/* Energy densities of Eq. (MicromagneticsEnergy) averaged over the cell
+ * [J/m^3] at the current state: out = {exchange, anisotropy, zeeman,
+ * magnetoelastic, stress work, far-field demagnetisation, total}. */
+gspm_status gspm_energies(gspm_ctx *ctx, double out[7]);
+
+/* Volume averages over the cell (Sec. 2.4): mbar[3] and the homogeneous
+ * strain ebar[6] (order xx yy zz yz xz xy). */
+gspm_status gspm_averages(gspm_ctx *ctx, double mbar[3], double ebar[6]);
+
+/* Apply one operator of Sec. 2.3 to x (n_nodes x 3, caller's order), writing
+ * y = A x (the assembled residual at each node, reported at all its copies).
+ * eps is used by GSPM_OP_GS only.  GSPM_OP_ELASTIC needs gspm_set_params. */
+gspm_status gspm_apply(gspm_ctx *ctx, gspm_op op, double eps, const double *x, double *y, int64_t n_nodes);
+
+/* Solve A x = b by the library's CG (GSPM_OP_GS per component on the magnetic
+ * nodes, or GSPM_OP_ELASTIC with the pinned node).  x holds the initial guess
+ * on entry and the solution on return; iters (nullable) receives the
+ * iteration count (summed over components for GSPM_OP_GS). */
+gspm_status gspm_solve(gspm_ctx *ctx, gspm_op op, double eps, const double *b, double *x, int64_t n_nodes,
+                       double tol, int32_t maxit, int32_t *iters);
+
+/* Mesh facts after upload: unique nodes, tetrahedra, owner blocks, element
+ * copies processed per element pass, cell volume [m^3]. Pointers may be NULL. */
+gspm_status gspm_mesh_info(gspm_ctx *ctx, int64_t *n_unique, int64_t *n_tets, int64_t *n_blocks,
+                           int64_t *n_elem_copies, double *volume);
+
+/* Demagnetisation factors (N_a, N_b, N_c) of an ellipsoid with semi-axes a, b,
+ * c along its own axes (the body factor N_d of Sec. 2.1; for a body aligned
+ * with the crystal axes pass diag(N) as gspm_params.Nd).  Host only: needs no
+ * device and no context.  GSPM_E_ARG unless a, b, c are positive and finite. */
+gspm_status gspm_demag_factors(double a, double b, double c, double N[3]);
+
+/* Message of the last failure on this context (or of the last failed
+ * gspm_create when ctx is NULL).  Never NULL. */
+const char *gspm_last_error(const gspm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

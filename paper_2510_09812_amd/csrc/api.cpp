@@ -1,0 +1,511 @@
+// C ABI of the GSPM library: argument checking, state machine, host<->device
+// marshalling in the caller's node order.  Every numerical step runs in the
+// HIP kernels; this file only moves data and sequences calls.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "context.h"
+
+using namespace gspm;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+constexpr int kRing = 520;        // CG dot-product slots: >= largest iteration batch + 2
+
+gspm_status fail(gspm_ctx *c, gspm_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+template <class T>
+int dev_alloc(gspm_ctx *c, T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_check(c, e, "hipMalloc");
+    }
+    return GSPM_OK;
+}
+
+template <class T>
+void dev_free(T *&p) {
+    if (p) hipFree(p);
+    p = nullptr;
+}
+
+bool all_finite(const double *v, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// Caller-order n0 x 3 -> internal component-major 3 x n.  The copies of a
+// periodic node must agree to 1e-12 relative.
+int gather_user(gspm_ctx *c, const double *v, std::vector<double> &out) {
+    const int n = c->n;
+    out.assign(3 * static_cast<size_t>(n), 0.0);
+    std::vector<uint8_t> seen(static_cast<size_t>(n), 0);
+    for (int64_t i = 0; i < c->n0; ++i) {
+        const int32_t k = c->user2int[i];
+        for (int a = 0; a < 3; ++a) {
+            const double x = v[i * 3 + a];
+            if (!std::isfinite(x)) {
+                c->err = "non-finite value in a nodal field";
+                return GSPM_E_ARG;
+            }
+            double &dst = out[static_cast<size_t>(a) * n + k];
+            if (!seen[k]) dst = x;
+            else if (std::fabs(dst - x) > 1e-12 * std::max(std::fabs(dst), std::fabs(x))) {
+                c->err = "periodic copies of a node carry different values";
+                return GSPM_E_ARG;
+            }
+        }
+        seen[k] = 1;
+    }
+    return GSPM_OK;
+}
+
+void scatter_user(const gspm_ctx *c, const std::vector<double> &in, double *out) {
+    const int n = c->n;
+    for (int64_t i = 0; i < c->n0; ++i) {
+        const int32_t k = c->user2int[i];
+        for (int a = 0; a < 3; ++a) out[i * 3 + a] = in[static_cast<size_t>(a) * n + k];
+    }
+}
+
+int upload(gspm_ctx *c, double *dst, const std::vector<double> &h) {
+    int rc = hip_check(c, hipMemcpyAsync(dst, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream),
+                       "copy to device");
+    if (rc) return rc;
+    return hip_check(c, hipStreamSynchronize(c->stream), "copy to device");
+}
+
+int download(gspm_ctx *c, const double *src, std::vector<double> &h) {
+    int rc = hip_check(c, hipMemcpyAsync(h.data(), src, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream),
+                       "copy to host");
+    if (rc) return rc;
+    return hip_check(c, hipStreamSynchronize(c->stream), "copy to host");
+}
+
+// Homogeneous strain of an applied stress for cubic C:
+// normal part eps = (sigma - c12 tr(sigma) / (c11 + 2 c12)) / (c11 - c12),
+// shear eps_ij = sigma_ij / (2 c44).
+void cubic_compliance(const gspm_params &p, const double s[6], double e[6]) {
+    const double tr = s[0] + s[1] + s[2];
+    for (int k = 0; k < 3; ++k) e[k] = (s[k] - p.c12 * tr / (p.c11 + 2.0 * p.c12)) / (p.c11 - p.c12);
+    for (int k = 3; k < 6; ++k) e[k] = s[k] / (2.0 * p.c44);
+}
+
+}  // namespace
+
+gspm_ctx::~gspm_ctx() {
+    release_mesh();
+    for (hipEvent_t e : prof_ev) hipEventDestroy(e);
+    for (hipEvent_t e : ev)
+        if (e) hipEventDestroy(e);
+    if (t0) hipEventDestroy(t0);
+    if (t1) hipEventDestroy(t1);
+    if (h_flags) hipHostFree(h_flags);
+    if (own_stream && stream) hipStreamDestroy(stream);
+}
+
+void gspm_ctx::release_mesh() {
+    if (stream) hipStreamSynchronize(stream);
+    auto &b = d;
+    dev_free(b.x); dev_free(b.conn); dev_free(b.blk_ptr); dev_free(b.blk_nmag); dev_free(b.w);
+    dev_free(b.m); dev_free(b.mnext); dev_free(b.u); dev_free(b.unext);
+    dev_free(b.ms); dev_free(b.g); dev_free(b.gs); dev_free(b.b); dev_free(b.ch2);
+    dev_free(b.r); dev_free(b.p); dev_free(b.q);
+    dev_free(b.sums); dev_free(b.esums); dev_free(b.dm); dev_free(b.der); dev_free(b.bad);
+    dev_free(b.cg_rr); dev_free(b.cg_pq); dev_free(b.cg_bb); dev_free(b.cg_flags);
+    have_mesh = have_m = false;
+}
+
+extern "C" {
+
+gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts) {
+    if (!out) {
+        g_create_error = "gspm_create: null output pointer";
+        return GSPM_E_ARG;
+    }
+    *out = nullptr;
+    gspm_create_opts o{};
+    if (opts) o = *opts;
+    if (o.precision != GSPM_FP64 && o.precision != GSPM_MIXED) {
+        g_create_error = "gspm_create: unknown precision";
+        return GSPM_E_ARG;
+    }
+    if (o.precision == GSPM_MIXED) {
+        g_create_error = "gspm_create: GSPM_MIXED is not available in this build";
+        return GSPM_E_ARG;
+    }
+    if (o.block_nodes != 0 && (o.block_nodes < 64 || o.block_nodes > 1024 || (o.block_nodes & (o.block_nodes - 1)))) {
+        g_create_error = "gspm_create: block_nodes must be 0 or a power of two in [64, 1024]";
+        return GSPM_E_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        g_create_error = "gspm_create: no HIP device available";
+        return GSPM_E_DEVICE;
+    }
+    if (o.device < 0 || o.device >= ndev) {
+        g_create_error = "gspm_create: device ordinal out of range";
+        return GSPM_E_ARG;
+    }
+    hipDeviceProp_t prop;
+    if (hipSetDevice(o.device) != hipSuccess || hipGetDeviceProperties(&prop, o.device) != hipSuccess) {
+        g_create_error = "gspm_create: cannot use the device";
+        return GSPM_E_DEVICE;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_create_error = std::string("gspm_create: the library is built for gfx950, device is ") + prop.gcnArchName;
+        return GSPM_E_DEVICE;
+    }
+    auto *c = new gspm_ctx();
+    c->device = o.device;
+    c->precision = o.precision;
+    c->block_nodes = o.block_nodes;
+    c->profile = o.profile != 0;
+    if (o.stream) {
+        c->stream = static_cast<hipStream_t>(o.stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            g_create_error = "gspm_create: cannot create a stream";
+            return GSPM_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    bool ok = hipHostMalloc(reinterpret_cast<void **>(&c->h_flags), sizeof(int32_t) * 4 * kMaxComp) == hipSuccess;
+    for (auto &e : c->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreate(&c->t0) == hipSuccess && hipEventCreate(&c->t1) == hipSuccess;
+    if (!ok) {
+        delete c;
+        g_create_error = "gspm_create: cannot allocate host resources";
+        return GSPM_E_DEVICE;
+    }
+    c->err = "no error";
+    *out = c;
+    return GSPM_OK;
+}
+
+void gspm_destroy(gspm_ctx *ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    delete ctx;
+}
+
+gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, int64_t n_tets, const int32_t *tets,
+                             const uint8_t *tags, const double lo[3], const double hi[3], uint32_t flags) {
+    if (!c) return GSPM_E_ARG;
+    if (!xyz || !tets || !tags || !lo || !hi) return fail(c, GSPM_E_ARG, "upload_mesh: null array");
+    if (!(flags & GSPM_PERIODIC)) return fail(c, GSPM_E_ARG, "upload_mesh: only periodic cells are supported");
+    hipSetDevice(c->device);
+    HostMesh hm;
+    std::string err;
+    int rc = prepare_mesh(n_nodes, xyz, n_tets, tets, tags, lo, hi, nodes_per_block(c->block_nodes, n_nodes), hm, err);
+    if (rc) return fail(c, static_cast<gspm_status>(rc), "upload_mesh: " + err);
+    c->release_mesh();
+    const size_t n = static_cast<size_t>(hm.n), n3 = 3 * n;
+    auto &d = c->d;
+    rc = 0;
+    rc = rc ? rc : dev_alloc(c, &d.x, n3);
+    rc = rc ? rc : dev_alloc(c, &d.conn, static_cast<size_t>(hm.ncopies));
+    rc = rc ? rc : dev_alloc(c, &d.blk_ptr, hm.blk_ptr.size());
+    rc = rc ? rc : dev_alloc(c, &d.blk_nmag, hm.blk_nmag.size());
+    rc = rc ? rc : dev_alloc(c, &d.w, n);
+    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.q})
+        rc = rc ? rc : dev_alloc(c, p, n3);
+    rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
+    rc = rc ? rc : dev_alloc(c, &d.sums, 9 * kShards);
+    rc = rc ? rc : dev_alloc(c, &d.esums, 4 * kShards);
+    rc = rc ? rc : dev_alloc(c, &d.dm, kShards);
+    rc = rc ? rc : dev_alloc(c, &d.der, 2);
+    rc = rc ? rc : dev_alloc(c, &d.bad, 1);
+    rc = rc ? rc : dev_alloc(c, &d.cg_rr, static_cast<size_t>(kMaxComp) * kRing * kShards);
+    rc = rc ? rc : dev_alloc(c, &d.cg_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
+    rc = rc ? rc : dev_alloc(c, &d.cg_bb, static_cast<size_t>(kMaxComp) * kShards);
+    rc = rc ? rc : dev_alloc(c, &d.cg_flags, 2 * kMaxComp);
+    if (rc) {
+        c->release_mesh();
+        return static_cast<gspm_status>(rc);
+    }
+    hipStream_t s = c->stream;
+    hipMemcpyAsync(d.x, hm.xs.data(), sizeof(double) * n3, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.conn, hm.conn.data(), sizeof(int32_t) * hm.conn.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.blk_ptr, hm.blk_ptr.data(), sizeof(int32_t) * hm.blk_ptr.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.blk_nmag, hm.blk_nmag.data(), sizeof(int32_t) * hm.blk_nmag.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.w, hm.w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
+    for (double *p : {d.m, d.mnext, d.u, d.unext, d.ms, d.g, d.gs, d.b, d.r, d.p, d.q}) launch_fill(p, n3, 0.0, s);
+    launch_fill(d.ch2, 2 * n, 0.0, s);
+    rc = hip_check(c, hipStreamSynchronize(s), "upload_mesh");
+    if (rc) {
+        c->release_mesh();
+        return static_cast<gspm_status>(rc);
+    }
+    c->n0 = hm.n0;
+    c->ne = hm.ne;
+    c->ncopies = hm.ncopies;
+    c->n = hm.n;
+    c->nblk = hm.nblk;
+    c->p0 = hm.p0;
+    c->vc = hm.vc;
+    c->user2int = std::move(hm.user2int);
+    c->w_host = hm.w;
+    c->nmag = 0;
+    for (double wv : c->w_host) c->nmag += wv > 0.0;
+    auto &mv = c->mv;
+    mv.x = d.x;
+    mv.y = d.x + n;
+    mv.z = d.x + 2 * n;
+    mv.conn = d.conn;
+    mv.blk_ptr = d.blk_ptr;
+    mv.blk_nmag = d.blk_nmag;
+    mv.w = d.w;
+    mv.n = hm.n;
+    mv.nb = hm.nb;
+    mv.nblk = hm.nblk;
+    mv.p0 = hm.p0;
+    mv.Lx = hm.L[0]; mv.Ly = hm.L[1]; mv.Lz = hm.L[2];
+    mv.iLx = 1.0 / hm.L[0]; mv.iLy = 1.0 / hm.L[1]; mv.iLz = 1.0 / hm.L[2];
+    c->cg.rr = d.cg_rr;
+    c->cg.pq = d.cg_pq;
+    c->cg.bb = d.cg_bb;
+    c->cg.done = d.cg_flags;
+    c->cg.iters = d.cg_flags + kMaxComp;
+    c->cg.ring = kRing;
+    c->dargs.vc = hm.vc;
+    c->have_mesh = true;
+    c->have_m = false;
+    return GSPM_OK;
+}
+
+gspm_status gspm_set_params(gspm_ctx *c, const gspm_params *p) {
+    if (!c) return GSPM_E_ARG;
+    if (!p) return fail(c, GSPM_E_ARG, "set_params: null params");
+    if (!c->have_mesh) return fail(c, GSPM_E_STATE, "set_params before upload_mesh");
+    const double *raw = &p->Ms;
+    if (!all_finite(raw, 11) || !all_finite(p->Nd, 9) || !all_finite(p->hext, 3) || !all_finite(p->sigma_ext, 6) ||
+        !std::isfinite(p->cg_tol))
+        return fail(c, GSPM_E_ARG, "set_params: non-finite value");
+    if (!(p->Ms > 0 && p->A >= 0 && p->mu0 > 0 && p->gamma0 > 0 && p->alpha >= 0 && p->cg_tol > 0 && p->cg_maxit > 0))
+        return fail(c, GSPM_E_ARG, "set_params: Ms, mu0, gamma0, cg_tol, cg_maxit must be positive; A, alpha >= 0");
+    if (!(p->c44 > 0 && p->c11 - p->c12 > 0 && p->c11 + 2 * p->c12 > 0))
+        return fail(c, GSPM_E_ARG, "set_params: elastic constants are not positive definite");
+    c->p = *p;
+    auto &m = c->mat;
+    m.c11 = p->c11; m.c12 = p->c12; m.c44 = p->c44;
+    m.l100 = p->lambda100; m.l111 = p->lambda111;
+    m.kan = 2.0 * p->K1 / (p->mu0 * p->Ms * p->Ms);
+    m.kme = 1.0 / (p->mu0 * p->Ms * p->Ms);
+    m.A = p->A; m.K1 = p->K1; m.mu0Ms = p->mu0 * p->Ms;
+    for (int k = 0; k < 9; ++k) c->dargs.Nd[k] = p->Nd[k];
+    for (int k = 0; k < 3; ++k) c->dargs.hz[k] = p->hext[k] / p->Ms;
+    cubic_compliance(*p, p->sigma_ext, c->dargs.csig);
+    c->have_params = true;
+    return GSPM_OK;
+}
+
+gspm_status gspm_set_field(gspm_ctx *c, gspm_field which, const double *v, int64_t n_nodes) {
+    if (!c) return GSPM_E_ARG;
+    if (!v) return fail(c, GSPM_E_ARG, "set_field: null array");
+    if (!c->have_mesh) return fail(c, GSPM_E_STATE, "set_field before upload_mesh");
+    if (n_nodes != c->n0) return fail(c, GSPM_E_ARG, "set_field: node count differs from the mesh");
+    if (which != GSPM_FIELD_M && which != GSPM_FIELD_U) return fail(c, GSPM_E_ARG, "set_field: unknown field");
+    hipSetDevice(c->device);
+    std::vector<double> h;
+    int rc = gather_user(c, v, h);
+    if (rc) return static_cast<gspm_status>(rc);
+    const int n = c->n;
+    if (which == GSPM_FIELD_M) {
+        for (int k = 0; k < n; ++k) {
+            double *a = &h[k], *b = &h[static_cast<size_t>(n) + k], *cc = &h[2 * static_cast<size_t>(n) + k];
+            if (!(c->w_host[k] > 0.0)) {
+                *a = *b = *cc = 0.0;
+                continue;
+            }
+            const double r = std::sqrt(*a * *a + *b * *b + *cc * *cc);
+            if (!(r > 0.0)) return fail(c, GSPM_E_ARG, "set_field: zero magnetisation on a magnetic node");
+            *a /= r; *b /= r; *cc /= r;
+        }
+        rc = upload(c, c->d.m, h);
+        if (rc) return static_cast<gspm_status>(rc);
+        c->have_m = true;
+    } else {
+        rc = upload(c, c->d.u, h);
+        if (rc) return static_cast<gspm_status>(rc);
+    }
+    return GSPM_OK;
+}
+
+gspm_status gspm_get_field(gspm_ctx *c, gspm_field which, double *out, int64_t n_nodes) {
+    if (!c) return GSPM_E_ARG;
+    if (!out) return fail(c, GSPM_E_ARG, "get_field: null array");
+    if (!c->have_mesh) return fail(c, GSPM_E_STATE, "get_field before upload_mesh");
+    if (n_nodes != c->n0) return fail(c, GSPM_E_ARG, "get_field: node count differs from the mesh");
+    if (which != GSPM_FIELD_M && which != GSPM_FIELD_U) return fail(c, GSPM_E_ARG, "get_field: unknown field");
+    hipSetDevice(c->device);
+    std::vector<double> h(3 * static_cast<size_t>(c->n));
+    int rc = download(c, which == GSPM_FIELD_M ? c->d.m : c->d.u, h);
+    if (rc) return static_cast<gspm_status>(rc);
+    scatter_user(c, h, out);
+    return GSPM_OK;
+}
+
+gspm_status gspm_step(gspm_ctx *c, double dt, int32_t n_steps, gspm_step_stats *stats) {
+    if (!c) return GSPM_E_ARG;
+    if (!c->have_mesh || !c->have_params || !c->have_m)
+        return fail(c, GSPM_E_STATE, "step needs upload_mesh, set_params and set_field(M) first");
+    if (!(dt > 0) || !std::isfinite(dt) || n_steps < 0) return fail(c, GSPM_E_ARG, "step: dt must be positive, n >= 0");
+    hipSetDevice(c->device);
+    gspm_step_stats local;
+    gspm_step_stats *st = stats ? stats : &local;
+    return static_cast<gspm_status>(run_steps(c, dt, n_steps, st));
+}
+
+gspm_status gspm_energies(gspm_ctx *c, double out[7]) {
+    if (!c) return GSPM_E_ARG;
+    if (!out) return fail(c, GSPM_E_ARG, "energies: null output");
+    if (!c->have_mesh || !c->have_params || !c->have_m) return fail(c, GSPM_E_STATE, "energies need mesh, params and m");
+    hipSetDevice(c->device);
+    auto &d = c->d;
+    hipStream_t s = c->stream;
+    launch_avg_sums(c->n, d.w, d.m, c->mat.l100, c->mat.l111, d.sums, s);
+    launch_derive(d.sums, c->dargs, &d.der[0], s);
+    launch_fill(d.esums, 4 * kShards, 0.0, s);
+    launch_energy_elem(c->mv, c->mat, d.m, d.u, &d.der[0], d.esums, s);
+    launch_energy_nodes(c->n, d.w, d.m, c->mat, c->p.hext, d.esums + 2 * kShards, s);
+    double es[4 * kShards];
+    Derived der;
+    hipMemcpyAsync(es, d.esums, sizeof es, hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(&der, &d.der[0], sizeof der, hipMemcpyDeviceToHost, s);
+    int rc = hip_check(c, hipStreamSynchronize(s), "energies");
+    if (rc) return static_cast<gspm_status>(rc);
+    double tot[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k)
+        for (int q = 0; q < kShards; ++q) tot[k] += es[k * kShards + q];
+    const gspm_params &p = c->p;
+    out[0] = tot[0] / c->vc;
+    out[1] = tot[2] / c->vc;
+    out[2] = tot[3] / c->vc;
+    out[3] = tot[1] / c->vc;
+    const double *sg = p.sigma_ext, *eb = der.ebar;
+    out[4] = -(sg[0] * eb[0] + sg[1] * eb[1] + sg[2] * eb[2] + 2.0 * (sg[3] * eb[3] + sg[4] * eb[4] + sg[5] * eb[5]));
+    double dem = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) dem += der.mbar[a] * p.Nd[a * 3 + b] * der.mbar[b];
+    out[5] = 0.5 * p.mu0 * p.Ms * p.Ms * dem;
+    out[6] = out[0] + out[1] + out[2] + out[3] + out[4] + out[5];
+    return GSPM_OK;
+}
+
+gspm_status gspm_averages(gspm_ctx *c, double mbar[3], double ebar[6]) {
+    if (!c) return GSPM_E_ARG;
+    if (!mbar || !ebar) return fail(c, GSPM_E_ARG, "averages: null output");
+    if (!c->have_mesh || !c->have_params || !c->have_m) return fail(c, GSPM_E_STATE, "averages need mesh, params and m");
+    hipSetDevice(c->device);
+    launch_avg_sums(c->n, c->d.w, c->d.m, c->mat.l100, c->mat.l111, c->d.sums, c->stream);
+    launch_derive(c->d.sums, c->dargs, &c->d.der[0], c->stream);
+    Derived der;
+    hipMemcpyAsync(&der, &c->d.der[0], sizeof der, hipMemcpyDeviceToHost, c->stream);
+    int rc = hip_check(c, hipStreamSynchronize(c->stream), "averages");
+    if (rc) return static_cast<gspm_status>(rc);
+    for (int k = 0; k < 3; ++k) mbar[k] = der.mbar[k];
+    for (int k = 0; k < 6; ++k) ebar[k] = der.ebar[k];
+    return GSPM_OK;
+}
+
+gspm_status gspm_apply(gspm_ctx *c, gspm_op op, double eps, const double *x, double *y, int64_t n_nodes) {
+    if (!c) return GSPM_E_ARG;
+    if (!x || !y) return fail(c, GSPM_E_ARG, "apply: null array");
+    if (!c->have_mesh) return fail(c, GSPM_E_STATE, "apply before upload_mesh");
+    if (n_nodes != c->n0) return fail(c, GSPM_E_ARG, "apply: node count differs from the mesh");
+    if (op < GSPM_OP_LAPLACE || op > GSPM_OP_ELASTIC) return fail(c, GSPM_E_ARG, "apply: unknown operator");
+    if (op == GSPM_OP_ELASTIC && !c->have_params) return fail(c, GSPM_E_STATE, "apply(ELASTIC) needs set_params");
+    if (!std::isfinite(eps)) return fail(c, GSPM_E_ARG, "apply: non-finite eps");
+    hipSetDevice(c->device);
+    std::vector<double> h;
+    int rc = gather_user(c, x, h);
+    if (rc) return static_cast<gspm_status>(rc);
+    rc = upload(c, c->d.ms, h);
+    if (rc) return static_cast<gspm_status>(rc);
+    if (op == GSPM_OP_ELASTIC) {
+        launch_elastic_matvec(c->mv, c->mat, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, c->stream);
+    } else {
+        const double e = op == GSPM_OP_LAPLACE ? 1.0 : (op == GSPM_OP_MASS ? 0.0 : eps);
+        const double mass = op == GSPM_OP_LAPLACE ? 0.0 : 1.0;
+        launch_gs_matvec(c->mv, 3, e, mass, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, c->stream);
+    }
+    rc = download(c, c->d.q, h);
+    if (rc) return static_cast<gspm_status>(rc);
+    scatter_user(c, h, y);
+    return GSPM_OK;
+}
+
+gspm_status gspm_solve(gspm_ctx *c, gspm_op op, double eps, const double *b, double *x, int64_t n_nodes, double tol,
+                       int32_t maxit, int32_t *iters) {
+    if (!c) return GSPM_E_ARG;
+    if (!b || !x) return fail(c, GSPM_E_ARG, "solve: null array");
+    if (!c->have_mesh) return fail(c, GSPM_E_STATE, "solve before upload_mesh");
+    if (n_nodes != c->n0) return fail(c, GSPM_E_ARG, "solve: node count differs from the mesh");
+    if (op != GSPM_OP_GS && op != GSPM_OP_ELASTIC) return fail(c, GSPM_E_ARG, "solve: operator must be GS or ELASTIC");
+    if (op == GSPM_OP_ELASTIC && !c->have_params) return fail(c, GSPM_E_STATE, "solve(ELASTIC) needs set_params");
+    if (!(tol > 0) || maxit <= 0 || !std::isfinite(eps)) return fail(c, GSPM_E_ARG, "solve: tol and maxit must be positive");
+    hipSetDevice(c->device);
+    std::vector<double> hb, hx;
+    int rc = gather_user(c, b, hb);
+    if (!rc) rc = gather_user(c, x, hx);
+    if (rc) return static_cast<gspm_status>(rc);
+    const int n = c->n;
+    const bool el = op == GSPM_OP_ELASTIC;
+    const int ns = el ? 1 : 3;
+    for (int k = 0; k < n; ++k) {
+        const bool fixed = el ? (k == c->p0) : !(c->w_host[k] > 0.0);
+        if (!fixed) continue;
+        for (int a = 0; a < 3; ++a) hb[static_cast<size_t>(a) * n + k] = hx[static_cast<size_t>(a) * n + k] = 0.0;
+    }
+    std::vector<double> bbh(static_cast<size_t>(kMaxComp) * kShards, 0.0);
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < n; ++k) bbh[static_cast<size_t>(el ? 0 : a) * kShards] += hb[static_cast<size_t>(a) * n + k] * hb[static_cast<size_t>(a) * n + k];
+    cg_prepare(c, ns);
+    hipMemcpyAsync(c->d.cg_bb, bbh.data(), sizeof(double) * bbh.size(), hipMemcpyHostToDevice, c->stream);
+    rc = upload(c, c->d.b, hb);
+    if (!rc) rc = upload(c, c->d.mnext, hx);
+    if (rc) return static_cast<gspm_status>(rc);
+    CgResult r = el ? cg_elastic(c, c->d.mnext, c->d.b, tol, maxit, SK_OTHER)
+                    : cg_gs(c, 3, eps, c->d.mnext, c->d.b, tol, maxit, SK_OTHER);
+    if (iters) *iters = r.iters[0] + r.iters[1] + r.iters[2];
+    rc = download(c, c->d.mnext, hx);
+    if (rc) return static_cast<gspm_status>(rc);
+    scatter_user(c, hx, x);
+    return static_cast<gspm_status>(r.status);
+}
+
+gspm_status gspm_mesh_info(gspm_ctx *c, int64_t *n_unique, int64_t *n_tets, int64_t *n_blocks, int64_t *n_copies,
+                           double *volume) {
+    if (!c) return GSPM_E_ARG;
+    if (!c->have_mesh) return fail(c, GSPM_E_STATE, "mesh_info before upload_mesh");
+    if (n_unique) *n_unique = c->n;
+    if (n_tets) *n_tets = c->ne;
+    if (n_blocks) *n_blocks = c->nblk;
+    if (n_copies) *n_copies = c->ncopies;
+    if (volume) *volume = c->vc;
+    return GSPM_OK;
+}
+
+gspm_status gspm_demag_factors(double a, double b, double c, double N[3]) {
+    if (!N || !(a > 0) || !(b > 0) || !(c > 0) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c))
+        return GSPM_E_ARG;
+    demag_factors(a, b, c, N);
+    return GSPM_OK;
+}
+
+const char *gspm_last_error(const gspm_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Internal declarations of the GSPM library (device data views, launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gspm.h"
+
+namespace gspm {
+
+constexpr int kThreads = 256;     // threads per workgroup of every kernel
+constexpr int kMaxComp = 3;
+
+// ---------------------------------------------------------------- host mesh
+
+// Result of the one-time host preprocessing of an uploaded mesh.
+struct HostMesh {
+    int64_t n0 = 0;               // caller's nodes
+    int32_t n = 0;                // unique nodes after periodic identification
+    int64_t ne = 0;               // tetrahedra
+    int32_t nb = 0;               // owned nodes per block
+    int32_t nblk = 0;             // blocks
+    int32_t p0 = -1;              // internal id of the pinned node (caller's node 0)
+    int64_t ncopies = 0;          // element copies over all block lists
+    double lo[3] = {0, 0, 0}, L[3] = {0, 0, 0};
+    double vc = 0.0;              // cell volume
+    std::vector<int32_t> user2int;        // n0
+    std::vector<double> xs;               // 3 x n coordinates, component-major
+    std::vector<int32_t> conn;            // 4 x ncopies (element copies, block order)
+    std::vector<int32_t> blk_ptr;         // nblk + 1
+    std::vector<int32_t> blk_nmag;        // nblk: magnetic copies come first in each list
+    std::vector<double> w;                // n: lumped magnetic weights sum_e chi_e V_e / 4
+};
+
+int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets, const uint8_t *tags,
+                 const double lo[3], const double hi[3], int32_t nb, HostMesh &out, std::string &err);
+
+// ------------------------------------------------------------- device views
+
+// Mesh as the element kernels see it.  Coordinates have the working type T.
+template <class T>
+struct MeshView {
+    const T *x, *y, *z;           // n each
+    const int4 *conn;             // element copies
+    const int32_t *blk_ptr, *blk_nmag;
+    const double *w;              // n
+    int32_t n, nb, nblk, p0;
+    T Lx, Ly, Lz, iLx, iLy, iLz;  // box edges and their inverses (nearest periodic image)
+};
+
+// Material constants in the form the kernels use.
+struct Material {
+    double c11, c12, c44;         // cubic stiffness
+    double l100, l111;            // magnetostriction
+    double kan;                   // 2 K1 / (mu0 Ms^2)
+    double kme;                   // 1 / (mu0 Ms^2)
+    double A;                     // exchange coefficient (energies)
+    double K1;                    // anisotropy (energies)
+    double mu0Ms;                 // mu0 Ms (energies)
+};
+
+// Per-stage quantities derived from the volume averages (device resident).
+struct Derived {
+    double mbar[3];
+    double ebar[6];               // homogeneous strain, xx yy zz yz xz xy
+    double hc[3];                 // h_zeeman + h_demag_far (uniform part of h)
+};
+
+// Reduction scalars are sharded: each is kShards doubles that producer
+// workgroups add into (workgroup w into shard w % kShards) and consumers sum.
+constexpr int kShards = 32;
+
+// Scalars of up to kMaxComp simultaneous CG solves (device resident).  The
+// per-iteration dot products live in a ring of `ring` slots: slot k % ring.
+struct CGScalars {
+    double *rr;                   // [comp][ring][kShards]: r_k . r_k
+    double *pq;                   // [comp][ring][kShards]: p_k . A p_k
+    double *bb;                   // [comp][kShards]: b . b
+    int32_t *done;                // [comp]: 0 running, 1 converged, 2 broke down (non-finite)
+    int32_t *iters;               // [comp]: iterations at convergence
+    int32_t ring;
+
+    __host__ __device__ double *rr_at(int c, int k) const {
+        return rr + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
+    }
+    __host__ __device__ double *pq_at(int c, int k) const {
+        return pq + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
+    }
+    __host__ __device__ double *bb_at(int c) const { return bb + static_cast<size_t>(c) * kShards; }
+    __host__ __device__ int comp_stride() const { return ring * kShards; }
+};
+
+enum MatvecMode { MV_APPLY = 0, MV_ITER = 1, MV_RESID = 2 };
+
+// ---------------------------------------------------------------- launchers
+
+void launch_fill(double *p, int64_t n, double v, hipStream_t s);
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+
+// Volume-average sums (sharded, 9 x kShards): sum w m (3), sum w E0(m) (6).
+void launch_avg_sums(int n, const double *w, const double *m, double l100, double l111, double *sums,
+                     hipStream_t s);
+struct DeriveArgs {
+    double vc;
+    double Nd[9];
+    double hz[3];                 // H_ext / Ms
+    double csig[6];               // C^-1 sigma_ext
+};
+void launch_derive(const double *sums, const DeriveArgs &a, Derived *out, hipStream_t s);
+
+// Element passes (one workgroup per owner block).
+void launch_elastic_rhs(const MeshView<double> &mv, const Material &mat, const double *m, double *b, double *x,
+                        double *bb, hipStream_t s);
+void launch_field_rhs(const MeshView<double> &mv, const Material &mat, const double *m, const double *u,
+                      const Derived *d, double c, double *b, double *x0, double *ch2, double *bb, int bbstride,
+                      hipStream_t s);
+void launch_mass_rhs(const MeshView<double> &mv, const double *y, const double *ch2, double *b, double *x0,
+                     double *bb, int bbstride, hipStream_t s);
+void launch_elastic_matvec(const MeshView<double> &mv, const Material &mat, MatvecMode mode, const double *in,
+                           double *out, const double *b, double *r, double *p, const CGScalars &cg, int k,
+                           hipStream_t s);
+void launch_gs_matvec(const MeshView<double> &mv, int nc, double eps, double mass, MatvecMode mode,
+                      const double *in, double *out, const double *b, double *r, double *p,
+                      const CGScalars &cg, int k, hipStream_t s);
+void launch_energy_elem(const MeshView<double> &mv, const Material &mat, const double *m, const double *u,
+                        const Derived *d, double *out2, hipStream_t s);
+void launch_energy_nodes(int n, const double *w, const double *m, const Material &mat, const double hext[3],
+                         double *out2, hipStream_t s);
+
+// CG vector kernels on [nc][n] component-major vectors; joint: one set of
+// scalars for all components (the elastic solve), else one per component.
+void launch_cg_start(int n, int nc, bool joint, double *x, const CGScalars &cg, double tol, hipStream_t s);
+void launch_cg_update(int n, int nc, bool joint, double *x, double *r, const double *p, const double *q,
+                      const CGScalars &cg, int k, hipStream_t s);
+void launch_cg_direction(int n, int nc, bool joint, const double *r, double *p, const CGScalars &cg, int k,
+                         double tol, hipStream_t s);
+
+// GSPM node updates (Algorithm B.1, Step 2 and Step 4).
+void launch_update_m12(int n, const double *m, const double *g, double *ms, hipStream_t s);
+void launch_update_m3(int n, const double *m, const double *gs, double *ms, hipStream_t s);
+void launch_normalize(int n, const double *w, const double *mss, const double *mold, double *mnew, double *dm_sum,
+                      int32_t *bad, hipStream_t s);
+void launch_zero_ring(const CGScalars &cg, int ns, int rr_from, int rr_to, int pq_from, int pq_to, hipStream_t s);
+
+// --------------------------------------------------------------- utilities
+
+int nodes_per_block(int32_t requested, int64_t n);
+double carlson_rd(double x, double y, double z);
+void demag_factors(double a, double b, double c, double N[3]);
+
+}  // namespace gspm

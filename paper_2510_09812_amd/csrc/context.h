@@ -1,0 +1,83 @@
+// The library context behind the opaque gspm_ctx handle.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace gspm {
+
+// Which solve a CG call belongs to, for the iteration-count predictor that
+// sizes the first batch of iterations launched before polling.
+enum SolveKind { SK_MECH = 0, SK_GS1 = 1, SK_GS2 = 2, SK_GS3 = 3, SK_OTHER = 4, SK_COUNT = 5 };
+
+struct DeviceBuffers {
+    double *x = nullptr;          // 3n coordinates
+    int4 *conn = nullptr;
+    int32_t *blk_ptr = nullptr, *blk_nmag = nullptr;
+    double *w = nullptr;
+    double *m = nullptr, *mnext = nullptr, *u = nullptr, *unext = nullptr;   // 3n each
+    double *ms = nullptr, *g = nullptr, *gs = nullptr, *b = nullptr, *ch2 = nullptr;
+    double *r = nullptr, *p = nullptr, *q = nullptr;
+    double *sums = nullptr;       // 9 x kShards
+    double *esums = nullptr;      // 4 x kShards
+    double *dm = nullptr;         // kShards
+    Derived *der = nullptr;       // [2]: stage at m^n, stage at m*
+    int32_t *bad = nullptr;
+    double *cg_rr = nullptr, *cg_pq = nullptr, *cg_bb = nullptr;
+    int32_t *cg_flags = nullptr;  // done[3], iters[3]
+};
+
+}  // namespace gspm
+
+struct gspm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int precision = GSPM_FP64;
+    int block_nodes = 0;
+    bool profile = false;
+    std::string err;
+
+    bool have_mesh = false, have_params = false, have_m = false;
+    int64_t n0 = 0, ne = 0, ncopies = 0;
+    int32_t n = 0, nblk = 0, nmag = 0, p0 = -1;
+    double vc = 0.0;
+    std::vector<int32_t> user2int;
+    std::vector<double> w_host;   // lumped weights (internal order)
+
+    gspm::DeviceBuffers d;
+    gspm::MeshView<double> mv{};
+    gspm::CGScalars cg{};
+    int32_t *h_flags = nullptr;   // pinned host mirror: 2 slots x (done[3], iters[3])
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_iter;   // CG iteration of each timed pair, -1 = dropped
+    size_t prof_used = 0;
+
+    gspm_params p{};
+    gspm::Material mat{};
+    gspm::DeriveArgs dargs{};
+    int predict[gspm::SK_COUNT] = {32, 8, 8, 8, 16};
+
+    ~gspm_ctx();
+    void release_mesh();
+};
+
+namespace gspm {
+
+// CG on a prepared right-hand side; see solver.cpp.
+struct CgResult {
+    int status = GSPM_OK;
+    int iters[kMaxComp] = {0, 0, 0};
+};
+
+void cg_prepare(gspm_ctx *c, int ns);
+CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int maxit, SolveKind kind);
+CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit, SolveKind kind);
+int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st);
+int hip_check(gspm_ctx *c, hipError_t e, const char *what);
+
+}  // namespace gspm

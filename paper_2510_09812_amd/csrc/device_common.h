@@ -1,0 +1,122 @@
+// Device-side helpers shared by the library's kernels.
+#pragma once
+
+#include "common.h"
+
+namespace gspm {
+
+// Workgroups are dispatched round-robin over the eight XCDs (workgroup w goes
+// to XCD w % 8).  Give each XCD a contiguous range of owner blocks, so that the
+// halo nodes a block gathers were mostly touched by the same XCD's L2.
+__device__ __forceinline__ int xcd_block(int wg, int nwg) {
+    const int q = nwg >> 3, r = nwg & 7, x = wg & 7, slot = wg >> 3;
+    return x * q + (x < r ? x : r) + slot;
+}
+
+__device__ __forceinline__ double round_even(double v) { return rint(v); }
+__device__ __forceinline__ float round_even(float v) { return rintf(v); }
+
+template <class T>
+__device__ __forceinline__ T near_image(T d, T L, T iL) {
+    return d - L * round_even(d * iL);
+}
+
+// P1 geometry of a tetrahedron from the coordinates of its vertices: the
+// gradients of the barycentric coordinates, g_k = (e_{k+1} x e_{k+2}) / det for
+// the edge vectors e_k = x_k - x_0 (nearest periodic image), g_0 = -sum g_k,
+// and the volume |det| / 6.
+template <class T>
+struct Geo {
+    T g[4][3];
+    T vol;
+};
+
+template <class T>
+__device__ __forceinline__ void tet_geometry(const MeshView<T> &mv, const int4 c, Geo<T> &G) {
+    const T x0 = mv.x[c.x], y0 = mv.y[c.x], z0 = mv.z[c.x];
+    const int vv[3] = {c.y, c.z, c.w};
+    T e[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e[k][0] = near_image(mv.x[vv[k]] - x0, mv.Lx, mv.iLx);
+        e[k][1] = near_image(mv.y[vv[k]] - y0, mv.Ly, mv.iLy);
+        e[k][2] = near_image(mv.z[vv[k]] - z0, mv.Lz, mv.iLz);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T *a = e[(k + 1) % 3], *b = e[(k + 2) % 3];
+        G.g[k + 1][0] = a[1] * b[2] - a[2] * b[1];
+        G.g[k + 1][1] = a[2] * b[0] - a[0] * b[2];
+        G.g[k + 1][2] = a[0] * b[1] - a[1] * b[0];
+    }
+    const T det = e[0][0] * G.g[1][0] + e[0][1] * G.g[1][1] + e[0][2] * G.g[1][2];
+    const T inv = T(1) / det;
+#pragma unroll
+    for (int k = 1; k < 4; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) G.g[k][a] *= inv;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) G.g[0][a] = -(G.g[1][a] + G.g[2][a] + G.g[3][a]);
+    G.vol = fabs(det) * T(1.0 / 6.0);
+}
+
+// Sum NR per-thread values over the workgroup (wave shuffles, then LDS) and add
+// the totals with one FP64 atomic each to shard (blockIdx.x % kShards) of the
+// sharded scalars dst + k * stride.  Spreading the atomics of thousands of
+// workgroups over kShards addresses keeps them from serialising on one.  All
+// threads of the workgroup call it.
+template <int NR>
+__device__ __forceinline__ void block_atomic_add(const double (&v)[NR], double *dst, int stride) {
+    __shared__ double red[kThreads / 64][NR];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        double s = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NR && dst != nullptr) {
+        double s = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < kThreads / 64; ++w2) s += red[w2][threadIdx.x];
+        unsafeAtomicAdd(dst + threadIdx.x * stride + (blockIdx.x % kShards), s);
+    }
+}
+
+__device__ __forceinline__ void block_atomic_add1(double v, double *dst) {
+    const double a[1] = {v};
+    block_atomic_add<1>(a, dst, 0);
+}
+
+// Totals of NR sharded scalars (each kShards consecutive doubles at src[k]),
+// summed in a fixed order by the first wave and broadcast through LDS.  All
+// threads of the workgroup call it.
+template <int NR>
+__device__ __forceinline__ void shard_totals(const double *const (&src)[NR], double (&out)[NR]) {
+    __shared__ double tot[NR];
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            double s = (lane < kShards && src[k] != nullptr) ? src[k][lane] : 0.0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+            if (lane == 0) tot[k] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NR; ++k) out[k] = tot[k];
+    __syncthreads();
+}
+
+__device__ __forceinline__ double shard_total(const double *src) {
+    const double *const a[1] = {src};
+    double o[1];
+    shard_totals<1>(a, o);
+    return o[0];
+}
+
+}  // namespace gspm

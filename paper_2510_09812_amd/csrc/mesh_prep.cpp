@@ -1,0 +1,216 @@
+// One-time host preprocessing of an uploaded mesh.
+//
+//  1. Periodic identification (Sec. 2.5): every node on a max face of the box
+//     is wrapped onto the min face; nodes whose wrapped coordinates agree (to
+//     1e-9 of the box edge) are one unique node.  A hash table keyed by the
+//     quantised coordinates of the min-face representatives does the matching.
+//  2. Validation and geometry in FP64: repeated vertices, degenerate elements,
+//     lumped magnetic weights w_j = sum_e chi_e V_e / 4 (the volume-average
+//     weights of Sec. 2.4) and the cell volume.
+//  3. Renumbering of the unique nodes along a Morton (Z-order) curve, so that
+//     a contiguous range of node ids is a compact patch of the mesh.
+//  4. Owner blocks: block b owns the node range [b*nb, (b+1)*nb) and lists
+//     every element with a vertex in that range (magnetic elements first).
+//     An element pass runs one workgroup per block, accumulates the
+//     contributions to owned nodes in LDS, and writes each owned node once.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <unordered_map>
+
+#include "common.h"
+
+namespace gspm {
+
+namespace {
+
+struct KeyHash {
+    size_t operator()(const std::array<int64_t, 3> &k) const noexcept {
+        uint64_t h = 1469598103934665603ull;
+        for (int a = 0; a < 3; ++a) {
+            h ^= static_cast<uint64_t>(k[a]) + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+        }
+        return static_cast<size_t>(h);
+    }
+};
+
+uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit of 63
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+}  // namespace
+
+int nodes_per_block(int32_t requested, int64_t n) {
+    if (requested > 0) return requested;
+    (void)n;
+    return 256;
+}
+
+int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets, const uint8_t *tags,
+                 const double lo[3], const double hi[3], int32_t nb, HostMesh &M, std::string &err) {
+    M = HostMesh();
+    if (n0 < 4 || ne < 1 || n0 > INT32_MAX || ne > INT32_MAX) { err = "mesh needs 4..2^31-1 nodes and >= 1 tetrahedron"; return GSPM_E_ARG; }
+    if (nb < 64 || nb > 1024 || (nb & (nb - 1))) { err = "block_nodes must be a power of two in [64, 1024]"; return GSPM_E_ARG; }
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(hi[a] > lo[a])) { err = "invalid periodic box"; return GSPM_E_ARG; }
+        M.lo[a] = lo[a];
+        M.L[a] = hi[a] - lo[a];
+    }
+    M.n0 = n0;
+    M.ne = ne;
+
+    // ---- 1. periodic identification
+    std::vector<std::array<int64_t, 3>> key(static_cast<size_t>(n0));
+    std::vector<uint8_t> onmax(static_cast<size_t>(n0), 0);
+    for (int64_t i = 0; i < n0; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            double v = xyz[i * 3 + a], q = 1e-9 * M.L[a];
+            if (!std::isfinite(v) || v < lo[a] - q || v > hi[a] + q) { err = "node outside the periodic box"; return GSPM_E_MESH; }
+            if (std::fabs(v - hi[a]) <= q) { v = lo[a]; onmax[i] = 1; }
+            key[i][a] = std::llround((v - lo[a]) / q);
+        }
+    }
+    std::unordered_map<std::array<int64_t, 3>, int32_t, KeyHash> site;
+    site.reserve(static_cast<size_t>(n0));
+    std::vector<int32_t> uid(static_cast<size_t>(n0), -1);
+    std::vector<int64_t> rep;                                  // unique -> caller's representative node
+    for (int64_t i = 0; i < n0; ++i) {
+        if (onmax[i]) continue;
+        auto ins = site.emplace(key[i], static_cast<int32_t>(rep.size()));
+        if (!ins.second) { err = "two nodes share one position"; return GSPM_E_MESH; }
+        uid[i] = ins.first->second;
+        rep.push_back(i);
+    }
+    for (int64_t i = 0; i < n0; ++i) {
+        if (!onmax[i]) continue;
+        auto it = site.find(key[i]);
+        if (it == site.end()) { err = "unmatched periodic node on a max face"; return GSPM_E_MESH; }
+        uid[i] = it->second;
+    }
+    const int32_t n = static_cast<int32_t>(rep.size());
+    M.n = n;
+
+    // ---- 2. validation, geometry, lumped weights (unique-id indexing)
+    std::vector<double> wu(static_cast<size_t>(n), 0.0);
+    double vc = 0.0;
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t v[4];
+        for (int j = 0; j < 4; ++j) {
+            int32_t t = tets[e * 4 + j];
+            if (t < 0 || t >= n0) { err = "tetrahedron refers to a node that does not exist"; return GSPM_E_MESH; }
+            v[j] = uid[t];
+        }
+        for (int j = 0; j < 4; ++j)
+            for (int k = j + 1; k < 4; ++k)
+                if (v[j] == v[k]) { err = "tetrahedron with a repeated (periodic) vertex"; return GSPM_E_MESH; }
+        double d[3][3], len2 = 0.0;
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 3; ++a) {
+                double dv = xyz[rep[v[k + 1]] * 3 + a] - xyz[rep[v[0]] * 3 + a];
+                dv -= M.L[a] * std::nearbyint(dv / M.L[a]);
+                d[k][a] = dv;
+                len2 += dv * dv;
+            }
+        double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) - d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                     d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+        double vol = std::fabs(det) / 6.0, h = std::sqrt(len2 / 3.0);
+        if (!(vol > 1e-9 * h * h * h)) { err = "degenerate tetrahedron"; return GSPM_E_MESH; }
+        vc += vol;
+        if (tags[e])
+            for (int j = 0; j < 4; ++j) wu[v[j]] += 0.25 * vol;
+    }
+    M.vc = vc;
+
+    // ---- 3. Morton renumbering of the unique nodes
+    std::vector<uint64_t> code(static_cast<size_t>(n));
+    for (int32_t g = 0; g < n; ++g) {
+        uint64_t c = 0;
+        for (int a = 0; a < 3; ++a) {
+            double t = (xyz[rep[g] * 3 + a] - lo[a]) / M.L[a];
+            t = std::min(std::max(t, 0.0), 1.0 - 1e-12);
+            c |= spread3(static_cast<uint64_t>(t * 2097152.0)) << a;
+        }
+        code[g] = c;
+    }
+    std::vector<int32_t> order(static_cast<size_t>(n));
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+    std::vector<int32_t> newid(static_cast<size_t>(n));
+    for (int32_t k = 0; k < n; ++k) newid[order[k]] = k;
+
+    M.user2int.resize(static_cast<size_t>(n0));
+    for (int64_t i = 0; i < n0; ++i) M.user2int[i] = newid[uid[i]];
+    M.xs.resize(3 * static_cast<size_t>(n));
+    M.w.resize(static_cast<size_t>(n));
+    for (int32_t g = 0; g < n; ++g) {
+        int32_t k = newid[g];
+        for (int a = 0; a < 3; ++a) M.xs[static_cast<size_t>(a) * n + k] = xyz[rep[g] * 3 + a];
+        M.w[k] = wu[g];
+    }
+    M.p0 = M.user2int[0];
+
+    // ---- 4. owner blocks and their element lists
+    M.nb = nb;
+    M.nblk = (n + nb - 1) / nb;
+    std::vector<int64_t> cnt(static_cast<size_t>(M.nblk) + 1, 0);
+    auto blocks_of = [&](int64_t e, int32_t *blk) {
+        int nbk = 0;
+        for (int j = 0; j < 4; ++j) {
+            int32_t b = M.user2int[tets[e * 4 + j]] / nb;
+            bool seen = false;
+            for (int k = 0; k < nbk; ++k) seen |= (blk[k] == b);
+            if (!seen) blk[nbk++] = b;
+        }
+        return nbk;
+    };
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t blk[4];
+        int nbk = blocks_of(e, blk);
+        for (int k = 0; k < nbk; ++k) cnt[blk[k] + 1]++;
+    }
+    for (int32_t b = 0; b < M.nblk; ++b) cnt[b + 1] += cnt[b];
+    M.ncopies = cnt[M.nblk];
+    if (M.ncopies > INT32_MAX) { err = "mesh too large for 32-bit element lists"; return GSPM_E_ARG; }
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    std::vector<int64_t> copy_elem(static_cast<size_t>(M.ncopies));
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t blk[4];
+        int nbk = blocks_of(e, blk);
+        for (int k = 0; k < nbk; ++k) copy_elem[fill[blk[k]]++] = e;
+    }
+    M.blk_ptr.resize(static_cast<size_t>(M.nblk) + 1);
+    M.blk_nmag.resize(static_cast<size_t>(M.nblk));
+    M.conn.resize(4 * static_cast<size_t>(M.ncopies));
+    for (int32_t b = 0; b < M.nblk; ++b) {
+        M.blk_ptr[b] = static_cast<int32_t>(cnt[b]);
+        auto first = copy_elem.begin() + cnt[b], last = copy_elem.begin() + cnt[b + 1];
+        auto minv = [&](int64_t e) {
+            int32_t m = INT32_MAX;
+            for (int j = 0; j < 4; ++j) m = std::min(m, M.user2int[tets[e * 4 + j]]);
+            return m;
+        };
+        std::sort(first, last, [&](int64_t a, int64_t c) {
+            bool ma = tags[a] != 0, mc = tags[c] != 0;
+            if (ma != mc) return ma;
+            int32_t va = minv(a), vb = minv(c);
+            return va != vb ? va < vb : a < c;
+        });
+        int32_t nmag = 0;
+        for (auto it = first; it != last; ++it) nmag += tags[*it] != 0;
+        M.blk_nmag[b] = nmag;
+        for (int64_t c = cnt[b]; c < cnt[b + 1]; ++c)
+            for (int j = 0; j < 4; ++j) M.conn[4 * c + j] = M.user2int[tets[copy_elem[c] * 4 + j]];
+    }
+    M.blk_ptr[M.nblk] = static_cast<int32_t>(M.ncopies);
+    return GSPM_OK;
+}
+
+}  // namespace gspm

@@ -1,0 +1,332 @@
+// Node-parallel kernels of the GSPM step: fills, volume averages, the
+// quantities derived from them, the CG vector updates and the GSPM node
+// updates.  Vectors are component-major [c][n]; one thread per node per
+// grid-stride step, so every access is coalesced.
+#include "device_common.h"
+
+namespace gspm {
+
+namespace {
+
+inline int node_grid(int64_t n) {
+    const int64_t g = (n + kThreads - 1) / kThreads;
+    return static_cast<int>(g < 2048 ? (g > 0 ? g : 1) : 2048);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- fills
+
+__global__ void __launch_bounds__(kThreads) k_fill(double *p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        p[i] = v;
+}
+
+__global__ void __launch_bounds__(kThreads) k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        p[i] = v;
+}
+
+void launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(node_grid(n)), dim3(kThreads), 0, s, p, n, v);
+}
+
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(node_grid(n)), dim3(kThreads), 0, s, p, n, v);
+}
+
+// ---------------------------------------------------------------- averages
+
+// Volume averages of Sec. 2.4 for P1 fields: int_Omega g = sum_j w_j g_j with
+// the magnetic lumped weights w_j (m and E0(m) vanish in the inclusions).
+__global__ void __launch_bounds__(kThreads) k_avg_sums(int n, const double *w, const double *m, double l100,
+                                                       double l111, double *sums) {
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const double a = 1.5 * l100, b = 1.5 * l111, third = 1.0 / 3.0;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        const double wi = w[i];
+        const double m0 = m[i], m1 = m[n + i], m2 = m[2 * static_cast<size_t>(n) + i];
+        acc[0] += wi * m0;
+        acc[1] += wi * m1;
+        acc[2] += wi * m2;
+        acc[3] += wi * a * (m0 * m0 - third);
+        acc[4] += wi * a * (m1 * m1 - third);
+        acc[5] += wi * a * (m2 * m2 - third);
+        acc[6] += wi * b * m1 * m2;
+        acc[7] += wi * b * m0 * m2;
+        acc[8] += wi * b * m0 * m1;
+    }
+    block_atomic_add<9>(acc, sums, kShards);
+}
+
+void launch_avg_sums(int n, const double *w, const double *m, double l100, double l111, double *sums,
+                     hipStream_t s) {
+    launch_fill(sums, 9 * kShards, 0.0, s);
+    hipLaunchKernelGGL(k_avg_sums, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, m, l100, l111, sums);
+}
+
+// mbar = sum w m / V_c; Ebar = <E0(m)> + C^-1 sigma_ext (the homogeneous strain
+// that minimises the energy when the heterogeneous strain has zero mean);
+// hc = H_ext / Ms - N_d mbar (Zeeman plus far-field demagnetisation, Sec. 2.1).
+__global__ void __launch_bounds__(kThreads) k_derive(const double *sums, DeriveArgs a, Derived *out) {
+    const double *const src[9] = {sums, sums + kShards, sums + 2 * kShards, sums + 3 * kShards, sums + 4 * kShards,
+                                  sums + 5 * kShards, sums + 6 * kShards, sums + 7 * kShards, sums + 8 * kShards};
+    double t[9];
+    shard_totals<9>(src, t);
+    if (threadIdx.x == 0) {
+        double mb[3];
+        for (int k = 0; k < 3; ++k) mb[k] = t[k] / a.vc;
+        for (int k = 0; k < 3; ++k) out->mbar[k] = mb[k];
+        for (int k = 0; k < 6; ++k) out->ebar[k] = t[3 + k] / a.vc + a.csig[k];
+        for (int k = 0; k < 3; ++k)
+            out->hc[k] = a.hz[k] - (a.Nd[3 * k] * mb[0] + a.Nd[3 * k + 1] * mb[1] + a.Nd[3 * k + 2] * mb[2]);
+    }
+}
+
+void launch_derive(const double *sums, const DeriveArgs &a, Derived *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_derive, dim3(1), dim3(kThreads), 0, s, sums, a, out);
+}
+
+// Anisotropy and Zeeman energies by the vertex rule: sum_j w_j psi(m_j).
+__global__ void __launch_bounds__(kThreads) k_energy_nodes(int n, const double *w, const double *m, double K1,
+                                                           double mu0Ms, double h0, double h1, double h2,
+                                                           double *out) {
+    double acc[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        const double m0 = m[i], m1 = m[n + i], m2 = m[2 * static_cast<size_t>(n) + i];
+        acc[0] += w[i] * K1 * (m0 * m0 * m1 * m1 + m1 * m1 * m2 * m2 + m2 * m2 * m0 * m0);
+        acc[1] -= w[i] * mu0Ms * (h0 * m0 + h1 * m1 + h2 * m2);
+    }
+    block_atomic_add<2>(acc, out, kShards);
+}
+
+void launch_energy_nodes(int n, const double *w, const double *m, const Material &mat, const double hext[3],
+                         double *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_nodes, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, m, mat.K1, mat.mu0Ms,
+                       hext[0], hext[1], hext[2], out2);
+}
+
+// ---------------------------------------------------------------------- CG
+
+namespace {
+
+// Scalar set of component c (all components share set 0 when joint).
+__device__ __forceinline__ int set_of(int c, int joint) { return joint ? 0 : c; }
+
+// Which of the ns solves are still running.  One thread reads the flags and
+// broadcasts them, so every wave of the workgroup takes the same decision
+// even while workgroup 0 of the direction kernel is writing them.
+__device__ __forceinline__ bool read_live(const int32_t *done, int ns, bool (&live)[3]) {
+    __shared__ int32_t f[3];
+    if (threadIdx.x == 0)
+        for (int s = 0; s < 3; ++s) f[s] = s < ns ? done[s] : 1;
+    __syncthreads();
+    bool any = false;
+    for (int s = 0; s < 3; ++s) {
+        live[s] = f[s] == 0;
+        any |= live[s];
+    }
+    __syncthreads();
+    return any;
+}
+
+}  // namespace
+
+// After the residual matvec: b = 0 gives x = 0 with no iterations; a
+// residual already below tol ||b|| converges with no iterations.
+__global__ void __launch_bounds__(kThreads) k_cg_start(int n, int nc, int joint, double *x, CGScalars cg,
+                                                       double tol2) {
+    const int ns = joint ? 1 : nc;
+    const double *const src[6] = {cg.bb_at(0), ns > 1 ? cg.bb_at(1) : nullptr, ns > 2 ? cg.bb_at(2) : nullptr,
+                                  cg.rr_at(0, 0), ns > 1 ? cg.rr_at(1, 0) : nullptr, ns > 2 ? cg.rr_at(2, 0) : nullptr};
+    double t[6];
+    shard_totals<6>(src, t);
+    bool zero[3], conv[3];
+    for (int s = 0; s < 3; ++s) {
+        zero[s] = s < ns && t[s] == 0.0;
+        conv[s] = s < ns && (zero[s] || t[3 + s] <= tol2 * t[s]);
+    }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+        for (int c = 0; c < nc; ++c)
+            if (zero[set_of(c, joint)]) x[static_cast<size_t>(c) * n + i] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int s = 0; s < ns; ++s)
+            if (conv[s]) {
+                cg.done[s] = 1;
+                cg.iters[s] = 0;
+            }
+}
+
+// Iteration k, after q = A p and pq[k]: alpha = rr[k] / pq[k];
+// x += alpha p; r -= alpha q; rr[k+1] += r.r.
+__global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint, double *x, double *r,
+                                                        const double *p, const double *q, CGScalars cg, int k) {
+    const int ns = joint ? 1 : nc;
+    bool live[3];
+    if (!read_live(cg.done, ns, live)) return;
+    const double *const src[6] = {cg.rr_at(0, k), ns > 1 ? cg.rr_at(1, k) : nullptr, ns > 2 ? cg.rr_at(2, k) : nullptr,
+                                  cg.pq_at(0, k), ns > 1 ? cg.pq_at(1, k) : nullptr, ns > 2 ? cg.pq_at(2, k) : nullptr};
+    double t[6];
+    shard_totals<6>(src, t);
+    double alpha[3];
+    for (int s = 0; s < 3; ++s) alpha[s] = live[s] ? t[s] / t[3 + s] : 0.0;
+    double part[3] = {0.0, 0.0, 0.0};
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+        for (int c = 0; c < nc; ++c) {
+            const int s = set_of(c, joint);
+            if (!live[s]) continue;
+            const size_t o = static_cast<size_t>(c) * n + i;
+            x[o] += alpha[s] * p[o];
+            const double rv = r[o] - alpha[s] * q[o];
+            r[o] = rv;
+            part[s] += rv * rv;
+        }
+    block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride());
+}
+
+// Iteration k, after rr[k+1]: stop a component at ||r|| <= tol ||b||
+// (recording k+1 iterations) or on a non-finite residual; otherwise
+// beta = rr[k+1] / rr[k] and p = r + beta p.
+__global__ void __launch_bounds__(kThreads) k_cg_direction(int n, int nc, int joint, const double *r, double *p,
+                                                           CGScalars cg, int k, double tol2) {
+    const int ns = joint ? 1 : nc;
+    bool live[3];
+    if (!read_live(cg.done, ns, live)) return;
+    const double *const src[9] = {cg.rr_at(0, k + 1), ns > 1 ? cg.rr_at(1, k + 1) : nullptr,
+                                  ns > 2 ? cg.rr_at(2, k + 1) : nullptr, cg.rr_at(0, k),
+                                  ns > 1 ? cg.rr_at(1, k) : nullptr, ns > 2 ? cg.rr_at(2, k) : nullptr,
+                                  cg.bb_at(0), ns > 1 ? cg.bb_at(1) : nullptr, ns > 2 ? cg.bb_at(2) : nullptr};
+    double t[9];
+    shard_totals<9>(src, t);
+    double beta[3];
+    int stop[3];
+    for (int s = 0; s < 3; ++s) {
+        beta[s] = 0.0;
+        stop[s] = 0;
+        if (!live[s]) continue;
+        const double rrn = t[s];
+        if (!isfinite(rrn)) stop[s] = 2;
+        else if (rrn <= tol2 * t[6 + s]) stop[s] = 1;
+        else beta[s] = rrn / t[3 + s];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int s = 0; s < ns; ++s)
+            if (stop[s]) {
+                cg.done[s] = stop[s];
+                cg.iters[s] = k + 1;
+            }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+        for (int c = 0; c < nc; ++c) {
+            const int s = set_of(c, joint);
+            if (!live[s] || stop[s]) continue;
+            const size_t o = static_cast<size_t>(c) * n + i;
+            p[o] = r[o] + beta[s] * p[o];
+        }
+}
+
+void launch_cg_start(int n, int nc, bool joint, double *x, const CGScalars &cg, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_start, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, x, cg, tol * tol);
+}
+
+void launch_cg_update(int n, int nc, bool joint, double *x, double *r, const double *p, const double *q,
+                      const CGScalars &cg, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, x, r, p, q, cg, k);
+}
+
+void launch_cg_direction(int n, int nc, bool joint, const double *r, double *p, const CGScalars &cg, int k,
+                         double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_direction, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, r, p, cg, k,
+                       tol * tol);
+}
+
+// ------------------------------------------------------ GSPM node updates
+
+// Algorithm B.1, Step 2, rows 1 and 2 (time-n values as printed):
+// m1* = m1 + g2 m3 - g3 m2, m2* = m2 + g3 m1 - g1 m3; m3* starts as m3.
+__global__ void __launch_bounds__(kThreads) k_update_m12(int n, const double *m, const double *g, double *ms) {
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        const size_t n1 = n, n2 = 2 * static_cast<size_t>(n);
+        const double m0 = m[i], m1 = m[n1 + i], m2 = m[n2 + i];
+        const double g0 = g[i], g1 = g[n1 + i], g2 = g[n2 + i];
+        ms[i] = m0 + (g1 * m2 - g2 * m1);
+        ms[n1 + i] = m1 + (g2 * m0 - g0 * m2);
+        ms[n2 + i] = m2;
+    }
+}
+
+// Step 2, row 3: m3* = m3 + g*1 m2* - g*2 m1*.
+__global__ void __launch_bounds__(kThreads) k_update_m3(int n, const double *m, const double *gs, double *ms) {
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        const size_t n1 = n, n2 = 2 * static_cast<size_t>(n);
+        ms[n2 + i] = m[n2 + i] + (gs[i] * ms[n1 + i] - gs[n1 + i] * ms[i]);
+    }
+}
+
+// Step 4: m^{n+1} = m** / |m**| on magnetic nodes (zero elsewhere), written to
+// mnew; sums |m^{n+1} - m^n| for the convergence measure of Sec. 3.2; flags a
+// zero or non-finite m**.
+__global__ void __launch_bounds__(kThreads) k_normalize(int n, const double *w, const double *mss, const double *mold,
+                                                        double *mnew, double *dm_sum, int32_t *bad) {
+    double dsum = 0.0;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        const size_t n1 = n, n2 = 2 * static_cast<size_t>(n);
+        if (!(w[i] > 0.0)) {
+            mnew[i] = 0.0;
+            mnew[n1 + i] = 0.0;
+            mnew[n2 + i] = 0.0;
+            continue;
+        }
+        const double a = mss[i], b = mss[n1 + i], c = mss[n2 + i];
+        const double rr = sqrt(a * a + b * b + c * c);
+        if (!(rr > 0.0) || !isfinite(rr)) {
+            *bad = 1;
+            continue;
+        }
+        const double inv = 1.0 / rr;
+        const double na = a * inv, nb = b * inv, nc = c * inv;
+        const double da = na - mold[i], db = nb - mold[n1 + i], dc = nc - mold[n2 + i];
+        dsum += sqrt(da * da + db * db + dc * dc);
+        mnew[i] = na;
+        mnew[n1 + i] = nb;
+        mnew[n2 + i] = nc;
+    }
+    block_atomic_add1(dsum, dm_sum);
+}
+
+// Zero the ring slots that iterations [rr_from, rr_to) of r.r and
+// [pq_from, pq_to) of p.Ap will accumulate into.
+__global__ void __launch_bounds__(kThreads) k_zero_ring(CGScalars cg, int ns, int rr_from, int rr_to, int pq_from,
+                                                        int pq_to) {
+    const int nrr = rr_to - rr_from, npq = pq_to - pq_from;
+    const int total = ns * (nrr + npq) * kShards;
+    for (int t = blockIdx.x * kThreads + threadIdx.x; t < total; t += gridDim.x * kThreads) {
+        const int sh = t % kShards, rest = t / kShards;
+        const int c = rest % ns, slot = rest / ns;
+        double *base = slot < nrr ? cg.rr_at(c, rr_from + slot) : cg.pq_at(c, pq_from + slot - nrr);
+        base[sh] = 0.0;
+    }
+}
+
+void launch_zero_ring(const CGScalars &cg, int ns, int rr_from, int rr_to, int pq_from, int pq_to, hipStream_t s) {
+    const int total = ns * ((rr_to - rr_from) + (pq_to - pq_from)) * kShards;
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_zero_ring, dim3(node_grid(total)), dim3(kThreads), 0, s, cg, ns, rr_from, rr_to, pq_from,
+                       pq_to);
+}
+
+void launch_update_m12(int n, const double *m, const double *g, double *ms, hipStream_t s) {
+    hipLaunchKernelGGL(k_update_m12, dim3(node_grid(n)), dim3(kThreads), 0, s, n, m, g, ms);
+}
+
+void launch_update_m3(int n, const double *m, const double *gs, double *ms, hipStream_t s) {
+    hipLaunchKernelGGL(k_update_m3, dim3(node_grid(n)), dim3(kThreads), 0, s, n, m, gs, ms);
+}
+
+void launch_normalize(int n, const double *w, const double *mss, const double *mold, double *mnew, double *dm_sum,
+                      int32_t *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_normalize, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, mss, mold, mnew, dm_sum, bad);
+}
+
+}  // namespace gspm

@@ -1,0 +1,287 @@
+"""Python binding of the C ABI in include/gspm.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own; all numerical work runs in libgspm.so's HIP kernels.
+The library must be built (paper_2510_09812_amd.build) -- a missing library
+is an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgspm.so")
+
+GSPM_OK, GSPM_E_ARG, GSPM_E_MESH, GSPM_E_STATE, GSPM_E_DEVICE, GSPM_E_NOCONV, GSPM_E_NONFINITE, GSPM_E_OOM = \
+    0, -1, -2, -3, -4, -5, -6, -7
+GSPM_FP64, GSPM_MIXED = 0, 1
+GSPM_FIELD_M, GSPM_FIELD_U = 0, 1
+GSPM_OP_LAPLACE, GSPM_OP_MASS, GSPM_OP_GS, GSPM_OP_ELASTIC = 0, 1, 2, 3
+GSPM_PERIODIC = 1
+
+STATUS_NAMES = {0: "GSPM_OK", -1: "GSPM_E_ARG", -2: "GSPM_E_MESH", -3: "GSPM_E_STATE", -4: "GSPM_E_DEVICE",
+                -5: "GSPM_E_NOCONV", -6: "GSPM_E_NONFINITE", -7: "GSPM_E_OOM"}
+
+EXPORTS = ("gspm_create", "gspm_destroy", "gspm_upload_mesh", "gspm_set_params", "gspm_set_field",
+           "gspm_get_field", "gspm_step", "gspm_energies", "gspm_averages", "gspm_apply", "gspm_solve",
+           "gspm_mesh_info", "gspm_demag_factors", "gspm_last_error")
+
+
+class GspmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class gspm_create_opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("block_nodes", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class gspm_params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0")] + [
+        ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
+        ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32)]
+
+
+class gspm_step_stats(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int32), ("failed_step", ctypes.c_int32), ("mech_iters", ctypes.c_int64),
+                ("gs_iters", ctypes.c_int64), ("gs_iters_stage", ctypes.c_int64 * 8), ("dm_avg", ctypes.c_double),
+                ("elapsed_ms", ctypes.c_double), ("matvec_ms", ctypes.c_double),
+                ("matvec_launches", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libgspm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} is missing: run paper_2510_09812_amd.build.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
+    S = ctypes.c_int
+    lib.gspm_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(gspm_create_opts)]; lib.gspm_create.restype = S
+    lib.gspm_destroy.argtypes = [P]; lib.gspm_destroy.restype = None
+    lib.gspm_upload_mesh.argtypes = [P, i64, dp, i64, P, P, dp, dp, ctypes.c_uint32]; lib.gspm_upload_mesh.restype = S
+    lib.gspm_set_params.argtypes = [P, ctypes.POINTER(gspm_params)]; lib.gspm_set_params.restype = S
+    lib.gspm_set_field.argtypes = [P, ctypes.c_int, dp, i64]; lib.gspm_set_field.restype = S
+    lib.gspm_get_field.argtypes = [P, ctypes.c_int, dp, i64]; lib.gspm_get_field.restype = S
+    lib.gspm_step.argtypes = [P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(gspm_step_stats)]
+    lib.gspm_step.restype = S
+    lib.gspm_energies.argtypes = [P, dp]; lib.gspm_energies.restype = S
+    lib.gspm_averages.argtypes = [P, dp, dp]; lib.gspm_averages.restype = S
+    lib.gspm_apply.argtypes = [P, ctypes.c_int, ctypes.c_double, dp, dp, i64]; lib.gspm_apply.restype = S
+    lib.gspm_solve.argtypes = [P, ctypes.c_int, ctypes.c_double, dp, dp, i64, ctypes.c_double, ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32)]
+    lib.gspm_solve.restype = S
+    lib.gspm_mesh_info.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                   ctypes.POINTER(i64), dp]
+    lib.gspm_mesh_info.restype = S
+    lib.gspm_demag_factors.argtypes = [ctypes.c_double] * 3 + [dp]; lib.gspm_demag_factors.restype = S
+    lib.gspm_last_error.argtypes = [P]; lib.gspm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a.reshape(shape) if shape is not None else a
+
+
+def _check(ctx, status: int):
+    if status != GSPM_OK:
+        raise GspmError(status, gspm_last_error(ctx))
+
+
+def gspm_last_error(ctx) -> str:
+    return load().gspm_last_error(ctx).decode()
+
+
+def gspm_create(device: int = 0, precision: int = GSPM_FP64, block_nodes: int = 0, profile: bool = False,
+                stream=None):
+    """Returns an opaque context handle.  `stream` may be a torch.cuda.Stream
+    (the library then runs on it) or a raw hipStream_t integer."""
+    opts = gspm_create_opts(device, precision, block_nodes, 1 if profile else 0, None)
+    if stream is not None:
+        opts.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    h = ctypes.c_void_p()
+    _check(None, load().gspm_create(ctypes.byref(h), ctypes.byref(opts)))
+    return h
+
+
+def gspm_destroy(ctx) -> None:
+    if ctx is not None and ctx.value:
+        load().gspm_destroy(ctx)
+
+
+def gspm_upload_mesh(ctx, xyz, tets, tags, lo, hi, flags: int = GSPM_PERIODIC) -> None:
+    xyz = _f64(xyz, (-1, 3))
+    tets = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
+    tags = np.ascontiguousarray(tags, dtype=np.uint8).reshape(-1)
+    if tags.shape[0] != tets.shape[0]:
+        raise ValueError("one tag per tetrahedron")
+    _check(ctx, load().gspm_upload_mesh(ctx, xyz.shape[0], _dp(xyz), tets.shape[0], tets.ctypes.data,
+                                        tags.ctypes.data, _dp(_f64(lo)), _dp(_f64(hi)), flags))
+
+
+def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession: bool = True,
+                cg_maxit: int = 10000) -> gspm_params:
+    p = gspm_params()
+    for k in ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0"):
+        setattr(p, k, float(params[k]))
+    nd = np.asarray(params.get("Nd", np.eye(3) / 3.0), dtype=np.float64).reshape(9)
+    for i in range(9):
+        p.Nd[i] = nd[i]
+    for i in range(3):
+        p.hext[i] = float(hext[i])
+    for i in range(6):
+        p.sigma_ext[i] = float(sigma_ext[i])
+    p.cg_tol = float(params.get("cg_tol", 1e-8))
+    p.cg_maxit = int(params.get("cg_maxit", cg_maxit))
+    p.precession = 1 if precession else 0
+    return p
+
+
+def gspm_set_params(ctx, params) -> None:
+    if isinstance(params, dict):
+        params = make_params(params)
+    _check(ctx, load().gspm_set_params(ctx, ctypes.byref(params)))
+
+
+def gspm_set_field(ctx, which: int, values) -> None:
+    v = _f64(values, (-1, 3))
+    _check(ctx, load().gspm_set_field(ctx, which, _dp(v), v.shape[0]))
+
+
+def gspm_get_field(ctx, which: int, n_nodes: int) -> np.ndarray:
+    out = np.zeros((n_nodes, 3))
+    _check(ctx, load().gspm_get_field(ctx, which, _dp(out), n_nodes))
+    return out
+
+
+def stats_dict(st: gspm_step_stats) -> dict:
+    return dict(steps_done=st.steps_done, failed_step=st.failed_step, mech_iters=st.mech_iters,
+                gs_iters=st.gs_iters, gs_iters_stage=list(st.gs_iters_stage), dm_avg=st.dm_avg,
+                elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches)
+
+
+def gspm_step(ctx, dt: float, n_steps: int = 1) -> dict:
+    """Runs n steps; returns the stats as a dict.  On failure the GspmError
+    carries the stats in its `stats` attribute."""
+    st = gspm_step_stats()
+    status = load().gspm_step(ctx, dt, n_steps, ctypes.byref(st))
+    if status != GSPM_OK:
+        err = GspmError(status, gspm_last_error(ctx))
+        err.stats = stats_dict(st)
+        raise err
+    return stats_dict(st)
+
+
+ENERGY_KEYS = ("exchange", "anisotropy", "zeeman", "magnetoelastic", "stress", "demag_far", "total")
+
+
+def gspm_energies(ctx) -> dict:
+    out = np.zeros(7)
+    _check(ctx, load().gspm_energies(ctx, _dp(out)))
+    return dict(zip(ENERGY_KEYS, out.tolist()))
+
+
+def gspm_averages(ctx):
+    mbar = np.zeros(3); ebar = np.zeros(6)
+    _check(ctx, load().gspm_averages(ctx, _dp(mbar), _dp(ebar)))
+    return mbar, ebar
+
+
+def gspm_apply(ctx, op: int, x, eps: float = 0.0) -> np.ndarray:
+    x = _f64(x, (-1, 3)); y = np.zeros_like(x)
+    _check(ctx, load().gspm_apply(ctx, op, eps, _dp(x), _dp(y), x.shape[0]))
+    return y
+
+
+def gspm_solve(ctx, op: int, b, x0=None, eps: float = 0.0, tol: float = 1e-8, maxit: int = 100000):
+    b = _f64(b, (-1, 3))
+    x = np.zeros_like(b) if x0 is None else _f64(x0, (-1, 3)).copy()
+    it = ctypes.c_int32(0)
+    _check(ctx, load().gspm_solve(ctx, op, eps, _dp(b), _dp(x), b.shape[0], tol, maxit, ctypes.byref(it)))
+    return x, int(it.value)
+
+
+def gspm_mesh_info(ctx) -> dict:
+    a, b, c, d = (ctypes.c_int64() for _ in range(4))
+    v = np.zeros(1)
+    _check(ctx, load().gspm_mesh_info(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                                      _dp(v)))
+    return dict(n_unique=a.value, n_tets=b.value, n_blocks=c.value, n_elem_copies=d.value, volume=float(v[0]))
+
+
+def gspm_demag_factors(a: float, b: float, c: float) -> np.ndarray:
+    out = np.zeros(3)
+    _check(None, load().gspm_demag_factors(a, b, c, _dp(out)))
+    return out
+
+
+class Simulation:
+    """Owns one context; thin convenience over the functions above."""
+
+    def __init__(self, mesh, params: dict | None = None, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6,
+                 precession: bool = True, **create_kw):
+        self.ctx = gspm_create(**create_kw)
+        self.n0 = int(np.asarray(mesh.xyz).shape[0])
+        gspm_upload_mesh(self.ctx, mesh.xyz, mesh.tets, mesh.tags, mesh.lo, mesh.hi)
+        if params is not None:
+            self.set_params(params, hext, sigma_ext, precession)
+
+    def set_params(self, params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession: bool = True):
+        gspm_set_params(self.ctx, make_params(params, hext, sigma_ext, precession))
+
+    def set_m(self, m):
+        gspm_set_field(self.ctx, GSPM_FIELD_M, m)
+
+    def set_u(self, u):
+        gspm_set_field(self.ctx, GSPM_FIELD_U, u)
+
+    def get_m(self) -> np.ndarray:
+        return gspm_get_field(self.ctx, GSPM_FIELD_M, self.n0)
+
+    def get_u(self) -> np.ndarray:
+        return gspm_get_field(self.ctx, GSPM_FIELD_U, self.n0)
+
+    def step(self, dt: float, n: int = 1) -> dict:
+        return gspm_step(self.ctx, dt, n)
+
+    def energies(self) -> dict:
+        return gspm_energies(self.ctx)
+
+    def averages(self):
+        return gspm_averages(self.ctx)
+
+    def apply(self, op: int, x, eps: float = 0.0) -> np.ndarray:
+        return gspm_apply(self.ctx, op, x, eps)
+
+    def solve(self, op: int, b, x0=None, eps: float = 0.0, tol: float = 1e-8, maxit: int = 100000):
+        return gspm_solve(self.ctx, op, b, x0, eps, tol, maxit)
+
+    def mesh_info(self) -> dict:
+        return gspm_mesh_info(self.ctx)
+
+    def close(self):
+        gspm_destroy(getattr(self, "ctx", None))
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,65 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every entry point include/gspm.h declares, reports a missing device cleanly,
+and its host-only demagnetisation factors meet the closed forms."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2510_09812_amd import gspm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "gspm.h")).read()
+    return sorted(set(re.findall(r"\b(gspm_[a-z_]+)\s*\(", text)) - {"gspm_ctx"})
+
+
+def test_header_and_binding_agree():
+    assert sorted(gspm.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gspm.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", gspm.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (gspm_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_no_device_or_bad_options_fail_cleanly():
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    with pytest.raises(gspm.GspmError) as e:
+        gspm.gspm_create(precision=7)
+    assert e.value.status == gspm.GSPM_E_ARG
+    with pytest.raises(gspm.GspmError) as e:
+        gspm.gspm_create(block_nodes=100)
+    assert e.value.status == gspm.GSPM_E_ARG
+    if not has_gpu:
+        with pytest.raises(gspm.GspmError) as e:
+            gspm.gspm_create()
+        assert e.value.status == gspm.GSPM_E_DEVICE
+        assert "device" in gspm.gspm_last_error(None)
+
+
+def test_demag_factors_closed_forms():
+    assert np.allclose(gspm.gspm_demag_factors(2.0, 2.0, 2.0), 1.0 / 3.0, atol=1e-14)
+    for mm in (1.5, 3.0, 10.0):
+        Na = (mm / np.sqrt(mm * mm - 1) * np.log(mm + np.sqrt(mm * mm - 1)) - 1.0) / (mm * mm - 1)
+        N = gspm.gspm_demag_factors(mm, 1.0, 1.0)
+        assert abs(N[0] - Na) < 1e-13 and abs(N[1] - (1 - Na) / 2) < 1e-13
+        Nc = mm * mm / (mm * mm - 1) * (1.0 - np.arcsin(np.sqrt(mm * mm - 1) / mm) / np.sqrt(mm * mm - 1))
+        N = gspm.gspm_demag_factors(mm, mm, 1.0)
+        assert abs(N[2] - Nc) < 1e-13
+    N = gspm.gspm_demag_factors(3.0, 1.3, 0.6)
+    assert abs(N.sum() - 1.0) < 1e-13
+    with pytest.raises(gspm.GspmError):
+        gspm.gspm_demag_factors(-1.0, 1.0, 1.0)
