@@ -1,0 +1,174 @@
+"""Throughput of the GSPM time step on one MI355X.
+
+One step is one pass of the whole hot path: volume averages, the elastic
+right-hand side and its CG solve, the three GSPM stages (field right-hand
+sides, 3 + 2 + 3 scalar CG solves, cross-product updates) and the unit-length
+projection.  The workload is the 1M-node cube (100^3 nodes, 5.8M
+tetrahedra, three random ellipsoidal inclusions, dt = 10 ps, CG tolerance
+1e-8); the metric is node-steps/s = unique nodes x steps / wall time, with
+the mesh and state already resident in HBM when the timed region starts.
+
+Prints one JSON line (see the design doc for every field), including the
+roofline of the dominant kernel (the elastic matvec, timed with HIP events
+around each of its launches inside the timed region) and the CPU oracle's
+throughput on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GSPM node-steps/s at 1M nodes, mixed vs FP64 at 1e-6 rel err; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_elastic_matvec_cube100.json")
+KERNEL_SOURCES = ["paper_2510_09812_amd/csrc/elem_kernels.hip", "paper_2510_09812_amd/csrc/device_common.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def matvec_bytes(n_nodes: int, n_tets: int, real_bytes: int = 8) -> int:
+    """Algorithmic bytes of one elastic matvec: connectivity (4 x int32 per
+    tetrahedron), coordinates, the input vector and the output vector (3
+    values per node each), each read or written once."""
+    return 16 * n_tets + 3 * real_bytes * 3 * n_nodes
+
+
+def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float) -> float:
+    """Algorithmic bytes of one step (FP64): per elastic CG iteration the
+    matvec plus 7 vector passes (x, r, p read and written, Ap read); per
+    scalar GS CG iteration the connectivity and coordinates plus 8 scalar
+    vector passes; three element right-hand-side passes (connectivity,
+    coordinates, m, u, b) and the node passes (averages, updates,
+    projection)."""
+    conn = 16 * n_tets
+    mech = conn + 24 * n_nodes * (3 + 7)
+    gs = conn + 24 * n_nodes + 8 * n_nodes * 9
+    rhs = 3 * (conn + 24 * n_nodes * 4)
+    nodes = 24 * n_nodes * 12
+    return mech_iters * mech + gs_iters * gs + rhs + nodes
+
+
+def traffic_from_profile(launch_bytes: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(case, sample_steps: int = 1) -> dict:
+    """The CPU oracle as it stands, on the same workload: assembly is excluded
+    (the paper times setup separately); `sample_steps` steps from the initial
+    state are timed."""
+    import oracle
+    orc = oracle.Oracle.from_mesh(case.mesh)
+    orc.set_params(case.params, hext=case.hext)
+    orc.set_m(case.m0)
+    t0 = time.perf_counter()
+    st = orc.step(case.dt, sample_steps)
+    dt = time.perf_counter() - t0
+    return {"value": orc.n * sample_steps / dt, "unit": "node-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{sample_steps} step(s) of {case.name} from the initial state (elastic CG from u = 0, "
+                      f"{st['mech_iters']} elastic iterations), global matrix assembly excluded, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube100_ellipsoids")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-launch matvec events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
+                                   "and not implemented", "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+
+    import workloads as w
+    from paper_2510_09812_amd import gspm
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 1
+    torch.cuda.set_device(0)
+    print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
+    case = w.CASES[args.workload]()
+    t_up = time.perf_counter()
+    sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, device=0, profile=not args.no_profile)
+    sim.set_m(case.m0)
+    info = sim.mesh_info()
+    t_up = time.perf_counter() - t_up
+    print(f"[bench] uploaded {info['n_unique']} nodes, {info['n_tets']} tets in {t_up:.1f} s; warmup {args.warmup}",
+          file=sys.stderr, flush=True)
+    if args.warmup:
+        sim.step(case.dt, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sim.step(case.dt, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n, ne = info["n_unique"], info["n_tets"]
+    value = n * args.steps / wall
+    print(f"[bench] {args.steps} steps in {wall:.3f} s, mech iters {st['mech_iters']}, gs iters {st['gs_iters']}",
+          file=sys.stderr, flush=True)
+
+    roofline = None
+    if st["matvec_launches"] > 0:
+        avg_s = st["matvec_ms"] / st["matvec_launches"] * 1e-3
+        mb = matvec_bytes(n, ne)
+        achieved = mb / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(mb),
+                    "kernel": "k_elem<double,3,ElasticMatvecOp>", "bytes_per_launch": mb,
+                    "avg_launch_us": avg_s * 1e6, "launches": st["matvec_launches"]}
+    mech_per_step = st["mech_iters"] / args.steps
+    gs_per_step = st["gs_iters"] / args.steps
+    b_step = step_bytes(n, ne, mech_per_step, gs_per_step)
+    out = {
+        "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": case.name, "nodes": n, "tets": ne, "dt_s": case.dt, "cg_tol": case.cg_tol,
+                   "precision": "fp64", "mech_iters_per_step": mech_per_step, "gs_iters_per_step": gs_per_step},
+        "roofline": roofline,
+        "step_roofline": {"bytes_per_node_step": b_step / n, "roofline_node_steps_per_s": HBM_PEAK_GBS * 1e9 / b_step * n,
+                          "frac": value / (HBM_PEAK_GBS * 1e9 / b_step * n)},
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

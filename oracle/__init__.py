@@ -81,6 +81,7 @@ def _load():
     lib.or_energy_density_local.argtypes = [ctypes.POINTER(_Params), dp, dp]
     lib.or_energy_density_local.restype = ctypes.c_double
     lib.or_last_error.argtypes = [P]; lib.or_last_error.restype = ctypes.c_char_p
+    lib.or_num_threads.argtypes = []; lib.or_num_threads.restype = ctypes.c_int32
     _lib = lib
     return lib
 
@@ -118,6 +119,10 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
     p.cg_maxit = int(params.get("cg_maxit", cg_maxit))
     p.precession = 1 if precession else 0
     return p
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
 
 
 def demag_factors(a: float, b: float, c: float) -> np.ndarray:

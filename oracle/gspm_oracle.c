@@ -23,6 +23,9 @@
 #include "gspm_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -469,6 +472,14 @@ void or_lumped_weights(const or_sim *s, double *w) { memcpy(w, s->w, sizeof(doub
 int32_t or_pinned_node(const or_sim *s) { return s->p0; }
 const char *or_last_error(const or_sim *s) { return s ? s->err : "null oracle"; }
 
+int32_t or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* Elastic stiffness of Eq. (LHS): block (i,j)_ab = int E(phi_j e_b) : C E(phi_i e_a)
  * = V_e sum_qs C_aqbs d_q phi_i d_s phi_j on each element. */
 static void assemble_elastic(or_sim *s) {
@@ -844,7 +855,7 @@ static void gs_guess(const or_sim *s, const double *y, const double *ch, int com
 static int gs_component(const or_sim *s, double eps, const double *b, const double *y, const double *ch, int comp,
                         double *out, int *iters) {
     int n = s->n;
-    double *bc = (double *)malloc(sizeof(double) * (size_t)n), *xc = (double *)malloc(sizeof(double) * (size_t)n);
+    double *bc = (double *)calloc((size_t)n, sizeof(double)), *xc = (double *)calloc((size_t)n, sizeof(double));
     for (int i = 0; i < n; ++i) bc[i] = b[i * 3 + comp];
     gs_guess(s, y, ch, comp, xc);
     int rc = solve_gs(s, eps, bc, xc, s->p.cg_tol, s->p.cg_maxit, iters);

@@ -91,6 +91,7 @@ void or_h_local(const or_params *p, const double m[3], const double E[6], const 
 double or_energy_density_local(const or_params *p, const double m[3], const double E[6]);
 
 const char *or_last_error(const or_sim *s);
+int32_t or_num_threads(void);   /* OpenMP threads the oracle's loops use */
 
 #ifdef __cplusplus
 }
