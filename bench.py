@@ -102,6 +102,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-profile", action="store_true", help="skip the per-launch matvec events")
+    ap.add_argument("--block-nodes", type=int, default=0, help="nodes per owner block (0 = library default)")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="first run one device-to-device copy of this many MB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
@@ -117,10 +120,18 @@ def main() -> int:
         print(json.dumps({"error": "no GPU visible"}))
         return 1
     torch.cuda.set_device(0)
+    if args.copy_calib_mb > 0:
+        src = torch.ones(args.copy_calib_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.copy_calib_mb} MiB done", file=sys.stderr, flush=True)
+        del src, dst
     print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
     case = w.CASES[args.workload]()
     t_up = time.perf_counter()
-    sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, device=0, profile=not args.no_profile)
+    sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, device=0, profile=not args.no_profile,
+                          block_nodes=args.block_nodes)
     sim.set_m(case.m0)
     info = sim.mesh_info()
     t_up = time.perf_counter() - t_up
@@ -155,6 +166,7 @@ def main() -> int:
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": case.name, "nodes": n, "tets": ne, "dt_s": case.dt, "cg_tol": case.cg_tol,
+                   "block_nodes": info["n_unique"] // max(info["n_blocks"] - 1, 1) if args.block_nodes == 0 else args.block_nodes,
                    "precision": "fp64", "mech_iters_per_step": mech_per_step, "gs_iters_per_step": gs_per_step},
         "roofline": roofline,
         "step_roofline": {"bytes_per_node_step": b_step / n, "roofline_node_steps_per_s": HBM_PEAK_GBS * 1e9 / b_step * n,

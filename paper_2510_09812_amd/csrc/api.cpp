@@ -118,10 +118,11 @@ gspm_ctx::~gspm_ctx() {
 void gspm_ctx::release_mesh() {
     if (stream) hipStreamSynchronize(stream);
     auto &b = d;
-    dev_free(b.x); dev_free(b.conn); dev_free(b.blk_ptr); dev_free(b.blk_nmag); dev_free(b.w);
+    dev_free(b.x); dev_free(b.lconn); dev_free(b.blk_ptr); dev_free(b.blk_nmag); dev_free(b.w);
+    dev_free(b.halo_ptr); dev_free(b.halo_ids); dev_free(b.halo_lo); dev_free(b.img);
     dev_free(b.m); dev_free(b.mnext); dev_free(b.u); dev_free(b.unext);
     dev_free(b.ms); dev_free(b.g); dev_free(b.gs); dev_free(b.b); dev_free(b.ch2);
-    dev_free(b.r); dev_free(b.p); dev_free(b.q);
+    dev_free(b.r); dev_free(b.p); dev_free(b.p2); dev_free(b.q);
     dev_free(b.sums); dev_free(b.esums); dev_free(b.dm); dev_free(b.der); dev_free(b.bad);
     dev_free(b.cg_rr); dev_free(b.cg_pq); dev_free(b.cg_bb); dev_free(b.cg_flags);
     have_mesh = have_m = false;
@@ -216,11 +217,15 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     auto &d = c->d;
     rc = 0;
     rc = rc ? rc : dev_alloc(c, &d.x, n3);
-    rc = rc ? rc : dev_alloc(c, &d.conn, static_cast<size_t>(hm.ncopies));
+    rc = rc ? rc : dev_alloc(c, &d.lconn, static_cast<size_t>(hm.ncopies));
     rc = rc ? rc : dev_alloc(c, &d.blk_ptr, hm.blk_ptr.size());
     rc = rc ? rc : dev_alloc(c, &d.blk_nmag, hm.blk_nmag.size());
+    rc = rc ? rc : dev_alloc(c, &d.halo_ptr, hm.halo_ptr.size());
+    rc = rc ? rc : dev_alloc(c, &d.halo_ids, hm.halo_ids.size());
+    rc = rc ? rc : dev_alloc(c, &d.halo_lo, hm.halo_lo.size());
+    rc = rc ? rc : dev_alloc(c, &d.img, hm.img.size());
     rc = rc ? rc : dev_alloc(c, &d.w, n);
-    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.q})
+    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q})
         rc = rc ? rc : dev_alloc(c, p, n3);
     rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
     rc = rc ? rc : dev_alloc(c, &d.sums, 9 * kShards);
@@ -238,11 +243,16 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     }
     hipStream_t s = c->stream;
     hipMemcpyAsync(d.x, hm.xs.data(), sizeof(double) * n3, hipMemcpyHostToDevice, s);
-    hipMemcpyAsync(d.conn, hm.conn.data(), sizeof(int32_t) * hm.conn.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.lconn, hm.lconn.data(), sizeof(uint16_t) * hm.lconn.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.halo_ptr, hm.halo_ptr.data(), sizeof(int32_t) * hm.halo_ptr.size(), hipMemcpyHostToDevice, s);
+    if (!hm.halo_ids.empty())
+        hipMemcpyAsync(d.halo_ids, hm.halo_ids.data(), sizeof(int32_t) * hm.halo_ids.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.halo_lo, hm.halo_lo.data(), sizeof(int32_t) * hm.halo_lo.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.img, hm.img.data(), hm.img.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.blk_ptr, hm.blk_ptr.data(), sizeof(int32_t) * hm.blk_ptr.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.blk_nmag, hm.blk_nmag.data(), sizeof(int32_t) * hm.blk_nmag.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.w, hm.w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
-    for (double *p : {d.m, d.mnext, d.u, d.unext, d.ms, d.g, d.gs, d.b, d.r, d.p, d.q}) launch_fill(p, n3, 0.0, s);
+    for (double *p : {d.m, d.mnext, d.u, d.unext, d.ms, d.g, d.gs, d.b, d.r, d.p, d.p2, d.q}) launch_fill(p, n3, 0.0, s);
     launch_fill(d.ch2, 2 * n, 0.0, s);
     rc = hip_check(c, hipStreamSynchronize(s), "upload_mesh");
     if (rc) {
@@ -264,9 +274,14 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     mv.x = d.x;
     mv.y = d.x + n;
     mv.z = d.x + 2 * n;
-    mv.conn = d.conn;
+    mv.lconn = d.lconn;
     mv.blk_ptr = d.blk_ptr;
     mv.blk_nmag = d.blk_nmag;
+    mv.halo_ptr = d.halo_ptr;
+    mv.halo_ids = d.halo_ids;
+    mv.halo_lo = d.halo_lo;
+    mv.img = d.img;
+    mv.nloc_max = hm.nloc_max;
     mv.w = d.w;
     mv.n = hm.n;
     mv.nb = hm.nb;
@@ -436,11 +451,13 @@ gspm_status gspm_apply(gspm_ctx *c, gspm_op op, double eps, const double *x, dou
     rc = upload(c, c->d.ms, h);
     if (rc) return static_cast<gspm_status>(rc);
     if (op == GSPM_OP_ELASTIC) {
-        launch_elastic_matvec(c->mv, c->mat, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, c->stream);
+        launch_elastic_matvec(c->mv, c->mat, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, 0.0,
+                              c->stream);
     } else {
         const double e = op == GSPM_OP_LAPLACE ? 1.0 : (op == GSPM_OP_MASS ? 0.0 : eps);
         const double mass = op == GSPM_OP_LAPLACE ? 0.0 : 1.0;
-        launch_gs_matvec(c->mv, 3, e, mass, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, c->stream);
+        launch_gs_matvec(c->mv, 3, e, mass, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, 0.0,
+                         c->stream);
     }
     rc = download(c, c->d.q, h);
     if (rc) return static_cast<gspm_status>(rc);

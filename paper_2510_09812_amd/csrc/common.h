@@ -11,7 +11,10 @@
 
 namespace gspm {
 
-constexpr int kThreads = 256;     // threads per workgroup of every kernel
+#ifndef GSPM_THREADS
+#define GSPM_THREADS 256
+#endif
+constexpr int kThreads = GSPM_THREADS;   // threads per workgroup of every kernel
 constexpr int kMaxComp = 3;
 
 // ---------------------------------------------------------------- host mesh
@@ -25,13 +28,19 @@ struct HostMesh {
     int32_t nblk = 0;             // blocks
     int32_t p0 = -1;              // internal id of the pinned node (caller's node 0)
     int64_t ncopies = 0;          // element copies over all block lists
+    int32_t nloc_max = 0;         // largest owned + halo node count of a block
+    int64_t nhalo = 0;            // halo entries over all blocks
     double lo[3] = {0, 0, 0}, L[3] = {0, 0, 0};
     double vc = 0.0;              // cell volume
     std::vector<int32_t> user2int;        // n0
     std::vector<double> xs;               // 3 x n coordinates, component-major
-    std::vector<int32_t> conn;            // 4 x ncopies (element copies, block order)
-    std::vector<int32_t> blk_ptr;         // nblk + 1
+    std::vector<uint16_t> lconn;          // 4 x ncopies local vertex indices (owned: id - n0; halo: nb + slot)
+    std::vector<int32_t> blk_ptr;         // nblk + 1 element-copy ranges
     std::vector<int32_t> blk_nmag;        // nblk: magnetic copies come first in each list
+    std::vector<int32_t> halo_ptr;        // nblk + 1
+    std::vector<int32_t> halo_ids;        // halo node ids, sorted within a block
+    std::vector<int32_t> halo_lo;         // nblk: halo ids below the block's range
+    std::vector<uint8_t> img;             // nblk: edges need the nearest periodic image
     std::vector<double> w;                // n: lumped magnetic weights sum_e chi_e V_e / 4
 };
 
@@ -40,15 +49,17 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
 
 // ------------------------------------------------------------- device views
 
-// Mesh as the element kernels see it.  Coordinates have the working type T.
-template <class T>
+// Mesh as the element kernels see it: node coordinates (FP64), and per owner
+// block its element copies as local vertex indices into the block's staged
+// node set [owned range | halo list].
 struct MeshView {
-    const T *x, *y, *z;           // n each
-    const int4 *conn;             // element copies
-    const int32_t *blk_ptr, *blk_nmag;
+    const double *x, *y, *z;      // n each
+    const ushort4 *lconn;         // element copies, local indices
+    const int32_t *blk_ptr, *blk_nmag, *halo_ptr, *halo_ids, *halo_lo;
+    const uint8_t *img;
     const double *w;              // n
-    int32_t n, nb, nblk, p0;
-    T Lx, Ly, Lz, iLx, iLy, iLz;  // box edges and their inverses (nearest periodic image)
+    int32_t n, nb, nblk, p0, nloc_max;
+    double Lx, Ly, Lz, iLx, iLy, iLz;   // box edges and their inverses (nearest periodic image)
 };
 
 // Material constants in the form the kernels use.
@@ -112,20 +123,24 @@ struct DeriveArgs {
 void launch_derive(const double *sums, const DeriveArgs &a, Derived *out, hipStream_t s);
 
 // Element passes (one workgroup per owner block).
-void launch_elastic_rhs(const MeshView<double> &mv, const Material &mat, const double *m, double *b, double *x,
+void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x,
                         double *bb, hipStream_t s);
-void launch_field_rhs(const MeshView<double> &mv, const Material &mat, const double *m, const double *u,
+void launch_field_rhs(const MeshView &mv, const Material &mat, const double *m, const double *u,
                       const Derived *d, double c, double *b, double *x0, double *ch2, double *bb, int bbstride,
                       hipStream_t s);
-void launch_mass_rhs(const MeshView<double> &mv, const double *y, const double *ch2, double *b, double *x0,
+void launch_mass_rhs(const MeshView &mv, const double *y, const double *ch2, double *b, double *x0,
                      double *bb, int bbstride, hipStream_t s);
-void launch_elastic_matvec(const MeshView<double> &mv, const Material &mat, MatvecMode mode, const double *in,
-                           double *out, const double *b, double *r, double *p, const CGScalars &cg, int k,
-                           hipStream_t s);
-void launch_gs_matvec(const MeshView<double> &mv, int nc, double eps, double mass, MatvecMode mode,
-                      const double *in, double *out, const double *b, double *r, double *p,
-                      const CGScalars &cg, int k, hipStream_t s);
-void launch_energy_elem(const MeshView<double> &mv, const Material &mat, const double *m, const double *u,
+// Matrix-free operators.  APPLY: out = A in.  RESID: r = b - A x (x = in),
+// rr[0] += r.r.  ITER (CG iteration k): p_new = r + beta_k p_old (p_new = r at
+// k = 0, with beta_k = rr[k] / rr[k-1] and the convergence test of rr[k] done
+// first), q = A p_new, pq[k] += p_new.q; p_old = in, p_new = pout.
+void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode mode, const double *in,
+                           double *out, const double *b, const double *r, double *pout, const CGScalars &cg, int k,
+                           double tol, hipStream_t s);
+void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const double *in,
+                      double *out, const double *b, const double *r, double *pout, const CGScalars &cg, int k,
+                      double tol, hipStream_t s);
+void launch_energy_elem(const MeshView &mv, const Material &mat, const double *m, const double *u,
                         const Derived *d, double *out2, hipStream_t s);
 void launch_energy_nodes(int n, const double *w, const double *m, const Material &mat, const double hext[3],
                          double *out2, hipStream_t s);
@@ -135,8 +150,7 @@ void launch_energy_nodes(int n, const double *w, const double *m, const Material
 void launch_cg_start(int n, int nc, bool joint, double *x, const CGScalars &cg, double tol, hipStream_t s);
 void launch_cg_update(int n, int nc, bool joint, double *x, double *r, const double *p, const double *q,
                       const CGScalars &cg, int k, hipStream_t s);
-void launch_cg_direction(int n, int nc, bool joint, const double *r, double *p, const CGScalars &cg, int k,
-                         double tol, hipStream_t s);
+void launch_cg_check(int nc, bool joint, const CGScalars &cg, int k, double tol, hipStream_t s);
 
 // GSPM node updates (Algorithm B.1, Step 2 and Step 4).
 void launch_update_m12(int n, const double *m, const double *g, double *ms, hipStream_t s);

@@ -14,12 +14,13 @@ enum SolveKind { SK_MECH = 0, SK_GS1 = 1, SK_GS2 = 2, SK_GS3 = 3, SK_OTHER = 4, 
 
 struct DeviceBuffers {
     double *x = nullptr;          // 3n coordinates
-    int4 *conn = nullptr;
-    int32_t *blk_ptr = nullptr, *blk_nmag = nullptr;
+    ushort4 *lconn = nullptr;
+    int32_t *blk_ptr = nullptr, *blk_nmag = nullptr, *halo_ptr = nullptr, *halo_ids = nullptr, *halo_lo = nullptr;
+    uint8_t *img = nullptr;
     double *w = nullptr;
     double *m = nullptr, *mnext = nullptr, *u = nullptr, *unext = nullptr;   // 3n each
     double *ms = nullptr, *g = nullptr, *gs = nullptr, *b = nullptr, *ch2 = nullptr;
-    double *r = nullptr, *p = nullptr, *q = nullptr;
+    double *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
     double *sums = nullptr;       // 9 x kShards
     double *esums = nullptr;      // 4 x kShards
     double *dm = nullptr;         // kShards
@@ -48,7 +49,7 @@ struct gspm_ctx {
     std::vector<double> w_host;   // lumped weights (internal order)
 
     gspm::DeviceBuffers d;
-    gspm::MeshView<double> mv{};
+    gspm::MeshView mv{};
     gspm::CGScalars cg{};
     int32_t *h_flags = nullptr;   // pinned host mirror: 2 slots x (done[3], iters[3])
     hipEvent_t ev[2] = {nullptr, nullptr};

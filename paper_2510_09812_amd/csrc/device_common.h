@@ -21,27 +21,16 @@ __device__ __forceinline__ T near_image(T d, T L, T iL) {
     return d - L * round_even(d * iL);
 }
 
-// P1 geometry of a tetrahedron from the coordinates of its vertices: the
-// gradients of the barycentric coordinates, g_k = (e_{k+1} x e_{k+2}) / det for
-// the edge vectors e_k = x_k - x_0 (nearest periodic image), g_0 = -sum g_k,
-// and the volume |det| / 6.
+// P1 geometry of a tetrahedron from its edge vectors e_k = x_k - x_0: the
+// gradients of the barycentric coordinates, g_k = (e_{k+1} x e_{k+2}) / det,
+// g_0 = -sum g_k, and the volume |det| / 6.
 template <class T>
 struct Geo {
     T g[4][3];
     T vol;
 };
-
 template <class T>
-__device__ __forceinline__ void tet_geometry(const MeshView<T> &mv, const int4 c, Geo<T> &G) {
-    const T x0 = mv.x[c.x], y0 = mv.y[c.x], z0 = mv.z[c.x];
-    const int vv[3] = {c.y, c.z, c.w};
-    T e[3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        e[k][0] = near_image(mv.x[vv[k]] - x0, mv.Lx, mv.iLx);
-        e[k][1] = near_image(mv.y[vv[k]] - y0, mv.Ly, mv.iLy);
-        e[k][2] = near_image(mv.z[vv[k]] - z0, mv.Lz, mv.iLz);
-    }
+__device__ __forceinline__ void tet_geometry_from_edges(const T (&e)[3][3], Geo<T> &G) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const T *a = e[(k + 1) % 3], *b = e[(k + 2) % 3];

@@ -1,72 +1,124 @@
 // Element passes of the GSPM step on gfx950.
 //
-// Every pass runs one 256-thread workgroup per owner block.  The block's
-// threads stride over the block's element list (elements with at least one
-// vertex in the block's node range), gather the vertex data from the SoA node
-// arrays, recompute the P1 geometry from the coordinates, and add the
-// contributions to owned vertices into LDS with ds_add_f64; halo vertices are
-// dropped (their owner block computes the same element).  After one barrier
-// each owned node is written once, coalesced, together with the fused
-// epilogue of the pass (CG dot products, residuals, initial guesses).  No
-// global atomics touch node data.
+// One 256-thread workgroup per owner block (a Morton range of nb nodes).
+//   1. Staging: the block's node set -- its owned range followed by its halo
+//      list (the other vertices of its elements) -- is copied into LDS once:
+//      coordinates, shifted to the nearest periodic image of the block's first
+//      node, and the field values the pass reads.  Owned nodes are a
+//      contiguous, coalesced range; each halo node is fetched once per block
+//      instead of once per element vertex.
+//   2. Element loop: threads stride over the block's element copies (16-bit
+//      local vertex indices), recompute the P1 geometry from the staged
+//      coordinates, and add the contributions to owned vertices into LDS
+//      accumulators with ds_add_f64 / ds_add_f32.  Contributions to halo
+//      vertices are dropped: the halo node's owner block computes the same
+//      element.
+//   3. Epilogue: each owned node is written once, coalesced, with the pass's
+//      fused work (CG dot products, residuals, initial guesses).
+// No global atomics touch node data.
 //
 // Element arithmetic (Sec. 2.3, Eqs. LHS, RHS_F, RHS_b):
-//   Laplacian  K^e_ij  = V g_i . g_j
-//   mass       M^e_ij  = V (1 + delta_ij) / 20
-//   elastic    (K^e u)_i = V sigma(u) g_i,  sigma = C sym(grad u), C cubic
-//   elastic RHS b_i    = V (C <E0>_e) g_i,  <E0>_e the vertex mean of E0(m)
-//   field RHS  b_i     = sum_j M^e_ij (y_j + c h^e_j)
-// with h^e_j the local field of App. B at vertex j (anisotropy, Zeeman,
-// far field, magnetoelastic with the element's total strain).
+//   Laplacian   K^e_ij  = V g_i . g_j
+//   mass        M^e_ij  = V (1 + delta_ij) / 20
+//   elastic     (K^e u)_i = V sigma(u) g_i,  sigma = C sym(grad u), C cubic
+//   elastic RHS b_i     = V (C <E0>_e) g_i,  <E0>_e the vertex mean of E0(m)
+//   field RHS   b_i     = sum_j M^e_ij (y_j + c h^e_j)
+// with h^e_j the local field of App. B at vertex j (anisotropy, Zeeman, far
+// field, magnetoelastic with the element's total strain).
 #include "device_common.h"
 
 namespace gspm {
 
 // ------------------------------------------------------------ the skeleton
 
+// LDS layout of an element pass: acc[NC][nb] | sx, sy, sz [nloc_max] | fields [NF][nloc_max]
+template <class T, int NC, int NF>
+struct Staged {
+    T *acc, *sx, *sy, *sz, *f;
+    int nloc_max;
+    __device__ __forceinline__ T &fld(int k, int l) const { return f[k * nloc_max + l]; }
+};
+
+template <class T>
+__device__ __forceinline__ void stage_geometry(const T *sx, const T *sy, const T *sz, const ushort4 c, bool img,
+                                               const MeshView &mv, Geo<T> &G) {
+    const int v[4] = {c.x, c.y, c.z, c.w};
+    T e[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e[k][0] = sx[v[k + 1]] - sx[v[0]];
+        e[k][1] = sy[v[k + 1]] - sy[v[0]];
+        e[k][2] = sz[v[k + 1]] - sz[v[0]];
+    }
+    if (img) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            e[k][0] = near_image(e[k][0], static_cast<T>(mv.Lx), static_cast<T>(mv.iLx));
+            e[k][1] = near_image(e[k][1], static_cast<T>(mv.Ly), static_cast<T>(mv.iLy));
+            e[k][2] = near_image(e[k][2], static_cast<T>(mv.Lz), static_cast<T>(mv.iLz));
+        }
+    }
+    tet_geometry_from_edges(e, G);
+}
+
 template <class T, int NC>
-__device__ __forceinline__ void scatter_owned(T *acc, int nb, int n0, const int4 c, const T (&y)[4][NC]) {
+__device__ __forceinline__ void scatter_owned(T *acc, int nb, const ushort4 c, const T (&y)[4][NC]) {
     const int v[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const unsigned loc = static_cast<unsigned>(v[j] - n0);
-        if (loc < static_cast<unsigned>(nb)) {
+        if (v[j] < nb) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) atomicAdd(&acc[k * nb + loc], y[j][k]);
+            for (int k = 0; k < NC; ++k) atomicAdd(&acc[k * nb + v[j]], y[j][k]);
         }
     }
 }
 
-template <class T, int NC, class Op>
-__global__ void __launch_bounds__(kThreads) k_elem(const MeshView<T> mv, const Op op_in) {
+template <class T, int NC, int NF, class Op>
+__global__ void __launch_bounds__(kThreads) k_elem(const MeshView mv, const Op op_in) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *acc = reinterpret_cast<T *>(smem_raw);
     Op op = op_in;
     if (!op.prepare()) return;                 // uniform: e.g. every CG component converged
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int nb = mv.nb, n0 = b * nb;
-    for (int i = threadIdx.x; i < NC * nb; i += kThreads) acc[i] = T(0);
+    const int nb = mv.nb, n0 = b * nb, cnt = min(nb, mv.n - n0);
+    const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg);
+    Staged<T, NC, NF> st;
+    st.nloc_max = mv.nloc_max;
+    st.acc = reinterpret_cast<T *>(smem_raw);
+    st.sx = st.acc + NC * nb;
+    st.sy = st.sx + mv.nloc_max;
+    st.sz = st.sy + mv.nloc_max;
+    st.f = st.sz + mv.nloc_max;
+    for (int i = threadIdx.x; i < NC * nb; i += kThreads) st.acc[i] = T(0);
+    const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0];
+    for (int l = threadIdx.x; l < nloc; l += kThreads) {
+        if (l >= cnt && l < nb) continue;      // owned slots past the last node
+        const int g = l < nb ? n0 + l : mv.halo_ids[hbeg + l - nb];
+        st.sx[l] = static_cast<T>(near_image(mv.x[g] - xr, mv.Lx, mv.iLx));
+        st.sy[l] = static_cast<T>(near_image(mv.y[g] - yr, mv.Ly, mv.iLy));
+        st.sz[l] = static_cast<T>(near_image(mv.z[g] - zr, mv.Lz, mv.iLz));
+        op.stage(st, l, g);
+    }
     __syncthreads();
+    const bool img = mv.img[b] != 0;
     const int e_beg = mv.blk_ptr[b];
     const int e_mag = e_beg + mv.blk_nmag[b];
     const int e_end = Op::kMagneticOnly ? e_mag : mv.blk_ptr[b + 1];
     for (int e = e_beg + static_cast<int>(threadIdx.x); e < e_end; e += kThreads) {
-        const int4 c = mv.conn[e];
+        const ushort4 c = mv.lconn[e];
         Geo<T> G;
-        tet_geometry(mv, c, G);
+        stage_geometry(st.sx, st.sy, st.sz, c, img, mv, G);
         T y[4][NC];
-        op.element(c, G, e < e_mag, y);
-        scatter_owned<T, NC>(acc, nb, n0, c, y);
+        op.element(st, c, G, e < e_mag, y);
+        scatter_owned<T, NC>(st.acc, nb, c, y);
     }
     __syncthreads();
-    const int cnt = min(nb, mv.n - n0);
-    op.finish(mv, n0, cnt, acc);
+    op.finish(mv, st, n0, cnt);
 }
 
-template <class T, int NC, class Op>
-static void run_elem(const MeshView<T> &mv, const Op &op, hipStream_t s) {
-    const size_t lds = sizeof(T) * NC * static_cast<size_t>(mv.nb);
-    hipLaunchKernelGGL((k_elem<T, NC, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
+template <class T, int NC, int NF, class Op>
+static void run_elem(const MeshView &mv, const Op &op, hipStream_t s) {
+    const size_t lds = sizeof(T) * (NC * static_cast<size_t>(mv.nb) + (3 + NF) * static_cast<size_t>(mv.nloc_max));
+    hipLaunchKernelGGL((k_elem<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
 }
 
 // --------------------------------------------------------- cubic material
@@ -128,36 +180,106 @@ __device__ __forceinline__ void sym_grad(const T (&v)[4][3], const Geo<T> &G, T 
     e[5] = T(0.5) * (H[0][1] + H[1][0]);
 }
 
-template <class T>
-__device__ __forceinline__ void gather3(const T *base, int n, const int4 c, T (&v)[4][3]) {
+// The staged 3-vectors (fields k0..k0+2) at the four vertices.
+template <class T, int NC, int NF>
+__device__ __forceinline__ void vertex3(const Staged<T, NC, NF> &st, int k0, const ushort4 c, T (&v)[4][3]) {
     const int id[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) v[j][a] = base[static_cast<size_t>(a) * n + id[j]];
+        for (int a = 0; a < 3; ++a) v[j][a] = st.fld(k0 + a, id[j]);
+}
+
+// Totals of the CG scalars an iteration's matvec needs: rr[k], rr[k-1], bb
+// per scalar set; decides convergence of rr[k] (recorded by workgroup 0) and
+// the direction coefficient beta_k = rr[k] / rr[k-1].
+template <int NS>
+__device__ __forceinline__ bool cg_direction_scalars(const CGScalars &cg, int k, double tol2, int (&live)[NS],
+                                                     double (&beta)[NS]) {
+    __shared__ int32_t flags[NS];
+    if (threadIdx.x == 0)
+        for (int s = 0; s < NS; ++s) flags[s] = cg.done[s];
+    __syncthreads();
+    for (int s = 0; s < NS; ++s) {
+        live[s] = flags[s] == 0;
+        beta[s] = 0.0;
+    }
+    __syncthreads();
+    if (k == 0) {
+        bool any = false;
+        for (int s = 0; s < NS; ++s) any |= live[s] != 0;
+        return any;
+    }
+    const double *src[3 * NS];
+    for (int s = 0; s < NS; ++s) {
+        src[s] = cg.rr_at(s, k);
+        src[NS + s] = cg.rr_at(s, k - 1);
+        src[2 * NS + s] = cg.bb_at(s);
+    }
+    double t[3 * NS];
+    shard_totals<3 * NS>(src, t);
+    bool any = false;
+    int stop[NS];
+    for (int s = 0; s < NS; ++s) {
+        stop[s] = 0;
+        if (!live[s]) continue;
+        const double rrk = t[s];
+        if (!isfinite(rrk)) stop[s] = 2;
+        else if (rrk <= tol2 * t[2 * NS + s]) stop[s] = 1;
+        else beta[s] = rrk / t[NS + s];
+        if (stop[s]) live[s] = 0;
+        any |= live[s] != 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int s = 0; s < NS; ++s)
+            if (stop[s]) {
+                cg.done[s] = stop[s];
+                cg.iters[s] = k;
+            }
+    return any;
 }
 
 // ------------------------------------------------------------- elasticity
 
-// Matrix-free K^mech (Eq. LHS): y_i = V sigma(u) g_i over all elements.
-// APPLY: out = K in.  ITER: out = q = K p, pq[k] += p.q.  RESID: r = p = b - K x,
-// rr[0] += r.r.  Rows of the pinned node are zero.
+// Matrix-free K^mech (Eq. LHS): y_i = V sigma(u) g_i over all elements; rows of
+// the pinned node are zero.  See launch_elastic_matvec for the modes.
 template <class T>
 struct ElasticMatvecOp {
     static constexpr bool kMagneticOnly = false;
-    const T *in;
-    T *out;
-    const T *b;
-    T *r, *p;
+    const T *in;                  // APPLY/RESID: the vector; ITER: p_old
+    T *out;                       // APPLY: A in; ITER: q
+    const T *b;                   // RESID
+    const T *r;                   // RESID: r (out); ITER: r (in)
+    T *pout;                      // ITER: p_new
     CGScalars cg;
     int k, mode, n;
+    double tol2;
     Cubic<T> C;
+    int live[1];
+    double beta[1];
 
-    __device__ bool prepare() { return mode == MV_APPLY || cg.done[0] == 0; }
+    __device__ bool prepare() {
+        if (mode != MV_ITER) return mode == MV_APPLY || cg.done[0] == 0;
+        return cg_direction_scalars<1>(cg, k, tol2, live, beta);
+    }
 
-    __device__ __forceinline__ void element(const int4 c, const Geo<T> &G, bool, T (&y)[4][3]) const {
+    template <int NF>
+    __device__ __forceinline__ void stage(const Staged<T, 3, NF> &st, int l, int g) const {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const size_t o = static_cast<size_t>(a) * n + g;
+            T v;
+            if (mode == MV_ITER) v = (k == 0) ? r[o] : r[o] + static_cast<T>(beta[0]) * in[o];
+            else v = in[o];
+            st.fld(a, l) = v;
+        }
+    }
+
+    template <int NF>
+    __device__ __forceinline__ void element(const Staged<T, 3, NF> &st, const ushort4 c, const Geo<T> &G, bool,
+                                            T (&y)[4][3]) const {
         T v[4][3], e[6], s[6];
-        gather3(in, n, c, v);
+        vertex3(st, 0, c, v);
         sym_grad(v, G, e);
         C.stress(e, s);
 #pragma unroll
@@ -165,7 +287,8 @@ struct ElasticMatvecOp {
         sym_times_grads(s, G, y);
     }
 
-    __device__ void finish(const MeshView<T> &mv, int n0, int cnt, const T *acc) const {
+    template <int NF>
+    __device__ void finish(const MeshView &mv, const Staged<T, 3, NF> &st, int n0, int cnt) const {
         double part = 0.0;
         for (int i = threadIdx.x; i < cnt; i += kThreads) {
             const int node = n0 + i;
@@ -173,15 +296,18 @@ struct ElasticMatvecOp {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const size_t o = static_cast<size_t>(a) * n + node;
-                const T q = pinned ? T(0) : acc[a * mv.nb + i];
+                const T q = pinned ? T(0) : st.acc[a * mv.nb + i];
                 if (mode == MV_RESID) {
                     const T rv = pinned ? T(0) : b[o] - q;
-                    r[o] = rv;
-                    p[o] = rv;
+                    const_cast<T *>(r)[o] = rv;
                     part += static_cast<double>(rv) * rv;
+                } else if (mode == MV_ITER) {
+                    const T pv = st.fld(a, i);
+                    pout[o] = pv;
+                    out[o] = q;
+                    part += static_cast<double>(pv) * q;
                 } else {
                     out[o] = q;
-                    if (mode == MV_ITER) part += static_cast<double>(in[o]) * q;
                 }
             }
         }
@@ -205,9 +331,17 @@ struct ElasticRhsOp {
 
     __device__ bool prepare() { return true; }
 
-    __device__ __forceinline__ void element(const int4 c, const Geo<T> &G, bool, T (&y)[4][3]) const {
+    template <int NF>
+    __device__ __forceinline__ void stage(const Staged<T, 3, NF> &st, int l, int g) const {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) st.fld(a, l) = m[static_cast<size_t>(a) * n + g];
+    }
+
+    template <int NF>
+    __device__ __forceinline__ void element(const Staged<T, 3, NF> &st, const ushort4 c, const Geo<T> &G, bool,
+                                            T (&y)[4][3]) const {
         T v[4][3], e0[6] = {0, 0, 0, 0, 0, 0};
-        gather3(m, n, c, v);
+        vertex3(st, 0, c, v);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             T ej[6];
@@ -225,7 +359,8 @@ struct ElasticRhsOp {
         sym_times_grads(s, G, y);
     }
 
-    __device__ void finish(const MeshView<T> &mv, int n0, int cnt, const T *acc) const {
+    template <int NF>
+    __device__ void finish(const MeshView &mv, const Staged<T, 3, NF> &st, int n0, int cnt) const {
         double part = 0.0;
         for (int i = threadIdx.x; i < cnt; i += kThreads) {
             const int node = n0 + i;
@@ -233,7 +368,7 @@ struct ElasticRhsOp {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const size_t o = static_cast<size_t>(a) * n + node;
-                const T v = pinned ? T(0) : acc[a * mv.nb + i];
+                const T v = pinned ? T(0) : st.acc[a * mv.nb + i];
                 b[o] = v;
                 if (pinned) x[o] = T(0);
                 part += static_cast<double>(v) * v;
@@ -246,30 +381,51 @@ struct ElasticRhsOp {
 // ------------------------------------------------------------ GS operator
 
 // (eps K + mass M) on NC scalar components stored [c][n], magnetic elements
-// only (Eq. weak_GS).  Per-component CG: a converged component is skipped.
+// only (Eq. weak_GS), with one CG scalar set per component; a converged
+// component is skipped.
 template <class T, int NC>
 struct GsMatvecOp {
     static constexpr bool kMagneticOnly = true;
     const T *in;
     T *out;
     const T *b;
-    T *r, *p;
+    const T *r;
+    T *pout;
     CGScalars cg;
     int k, mode, n;
+    double tol2;
     T eps, mass;
     int live[NC];
+    double beta[NC];
 
     __device__ bool prepare() {
+        if (mode == MV_ITER) return cg_direction_scalars<NC>(cg, k, tol2, live, beta);
         bool any = false;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             live[c] = (mode == MV_APPLY) ? 1 : (cg.done[c] == 0);
+            beta[c] = 0.0;
             any |= live[c] != 0;
         }
         return any;
     }
 
-    __device__ __forceinline__ void element(const int4 c, const Geo<T> &G, bool, T (&y)[4][NC]) const {
+    template <int NF>
+    __device__ __forceinline__ void stage(const Staged<T, NC, NF> &st, int l, int g) const {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            if (!live[q]) continue;
+            const size_t o = static_cast<size_t>(q) * n + g;
+            T v;
+            if (mode == MV_ITER) v = (k == 0) ? r[o] : r[o] + static_cast<T>(beta[q]) * in[o];
+            else v = in[o];
+            st.fld(q, l) = v;
+        }
+    }
+
+    template <int NF>
+    __device__ __forceinline__ void element(const Staged<T, NC, NF> &st, const ushort4 c, const Geo<T> &G, bool,
+                                            T (&y)[4][NC]) const {
         const int id[4] = {c.x, c.y, c.z, c.w};
         const T ev = eps * G.vol, mv20 = mass * G.vol * T(0.05);
 #pragma unroll
@@ -279,10 +435,9 @@ struct GsMatvecOp {
                 for (int j = 0; j < 4; ++j) y[j][q] = T(0);
                 continue;
             }
-            const T *src = in + static_cast<size_t>(q) * n;
             T v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = src[id[j]];
+            for (int j = 0; j < 4; ++j) v[j] = st.fld(q, id[j]);
             const T d1 = v[1] - v[0], d2 = v[2] - v[0], d3 = v[3] - v[0];
             T gp[3];
 #pragma unroll
@@ -294,7 +449,8 @@ struct GsMatvecOp {
         }
     }
 
-    __device__ void finish(const MeshView<T> &mv, int n0, int cnt, const T *acc) const {
+    template <int NF>
+    __device__ void finish(const MeshView &mv, const Staged<T, NC, NF> &st, int n0, int cnt) const {
         double part[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) part[q] = 0.0;
@@ -304,15 +460,18 @@ struct GsMatvecOp {
             for (int q = 0; q < NC; ++q) {
                 if (!live[q]) continue;
                 const size_t o = static_cast<size_t>(q) * n + node;
-                const T av = acc[q * mv.nb + i];
+                const T av = st.acc[q * mv.nb + i];
                 if (mode == MV_RESID) {
                     const T rv = b[o] - av;
-                    r[o] = rv;
-                    p[o] = rv;
+                    const_cast<T *>(r)[o] = rv;
                     part[q] += static_cast<double>(rv) * rv;
+                } else if (mode == MV_ITER) {
+                    const T pv = st.fld(q, i);
+                    pout[o] = pv;
+                    out[o] = av;
+                    part[q] += static_cast<double>(pv) * av;
                 } else {
                     out[o] = av;
-                    if (mode == MV_ITER) part[q] += static_cast<double>(in[o]) * av;
                 }
             }
         }
@@ -364,10 +523,21 @@ struct FieldRhsOp {
         return true;
     }
 
-    __device__ __forceinline__ void element(const int4 cn, const Geo<T> &G, bool, T (&y)[4][6]) const {
+    template <int NF>
+    __device__ __forceinline__ void stage(const Staged<T, 6, NF> &st, int l, int g) const {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            st.fld(a, l) = m[static_cast<size_t>(a) * n + g];
+            st.fld(3 + a, l) = u[static_cast<size_t>(a) * n + g];
+        }
+    }
+
+    template <int NF>
+    __device__ __forceinline__ void element(const Staged<T, 6, NF> &st, const ushort4 cn, const Geo<T> &G, bool,
+                                            T (&y)[4][6]) const {
         T mv[4][3], uv[4][3], E[6];
-        gather3(m, n, cn, mv);
-        gather3(u, n, cn, uv);
+        vertex3(st, 0, cn, mv);
+        vertex3(st, 3, cn, uv);
         sym_grad(uv, G, E);
 #pragma unroll
         for (int t = 0; t < 6; ++t) E[t] += E0bar[t];
@@ -394,7 +564,8 @@ struct FieldRhsOp {
             }
     }
 
-    __device__ void finish(const MeshView<T> &mv, int n0, int cnt, const T *acc) const {
+    template <int NF>
+    __device__ void finish(const MeshView &mv, const Staged<T, 6, NF> &st, int n0, int cnt) const {
         double part[3] = {0.0, 0.0, 0.0};
         for (int i = threadIdx.x; i < cnt; i += kThreads) {
             const int node = n0 + i;
@@ -402,10 +573,10 @@ struct FieldRhsOp {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const size_t o = static_cast<size_t>(a) * n + node;
-                const T my = acc[a * mv.nb + i], chv = acc[(3 + a) * mv.nb + i];
+                const T my = st.acc[a * mv.nb + i], chv = st.acc[(3 + a) * mv.nb + i];
                 const T bv = my + chv;
                 b[o] = bv;
-                x0[o] = w > 0.0 ? m[o] + chv / static_cast<T>(w) : T(0);
+                x0[o] = w > 0.0 ? st.fld(a, i) + chv / static_cast<T>(w) : T(0);
                 if (ch2 != nullptr && a < 2) ch2[o] = chv;
                 part[a] += static_cast<double>(bv) * bv;
             }
@@ -426,21 +597,30 @@ struct MassRhsOp {
 
     __device__ bool prepare() { return true; }
 
-    __device__ __forceinline__ void element(const int4 cn, const Geo<T> &G, bool, T (&out)[4][2]) const {
+    template <int NF>
+    __device__ __forceinline__ void stage(const Staged<T, 2, NF> &st, int l, int g) const {
+        st.fld(0, l) = y[g];
+        st.fld(1, l) = y[static_cast<size_t>(n) + g];
+    }
+
+    template <int NF>
+    __device__ __forceinline__ void element(const Staged<T, 2, NF> &st, const ushort4 cn, const Geo<T> &G, bool,
+                                            T (&out)[4][2]) const {
         const int id[4] = {cn.x, cn.y, cn.z, cn.w};
         const T w20 = G.vol * T(0.05);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             T v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = y[static_cast<size_t>(q) * n + id[j]];
+            for (int j = 0; j < 4; ++j) v[j] = st.fld(q, id[j]);
             const T s = v[0] + v[1] + v[2] + v[3];
 #pragma unroll
             for (int j = 0; j < 4; ++j) out[j][q] = w20 * (v[j] + s);
         }
     }
 
-    __device__ void finish(const MeshView<T> &mv, int n0, int cnt, const T *acc) const {
+    template <int NF>
+    __device__ void finish(const MeshView &mv, const Staged<T, 2, NF> &st, int n0, int cnt) const {
         double part[2] = {0.0, 0.0};
         for (int i = threadIdx.x; i < cnt; i += kThreads) {
             const int node = n0 + i;
@@ -449,9 +629,9 @@ struct MassRhsOp {
             for (int q = 0; q < 2; ++q) {
                 const size_t o = static_cast<size_t>(q) * n + node;
                 const T chv = ch2[o];
-                const T bv = acc[q * mv.nb + i] + chv;
+                const T bv = st.acc[q * mv.nb + i] + chv;
                 b[o] = bv;
-                x0[o] = w > 0.0 ? y[o] + chv / static_cast<T>(w) : T(0);
+                x0[o] = w > 0.0 ? st.fld(q, i) + chv / static_cast<T>(w) : T(0);
                 part[q] += static_cast<double>(bv) * bv;
             }
         }
@@ -463,29 +643,57 @@ struct MassRhsOp {
 
 // Element sums of the exchange energy A V |grad m|^2 (magnetic elements) and
 // of the magnetoelastic energy V/4 sum_j 1/2 (E - chi E0(m_j)) : C (E - chi E0(m_j))
-// (all elements).  Each element is counted by the block owning its smallest
-// vertex id only.
+// (all elements), E = Ebar + sym grad u.  Each element is counted only by the
+// block owning its smallest vertex id: a copy is skipped when one of its
+// vertices is a halo node below the block's range (halo slots [nb, nb + halo_lo)).
 template <class T>
-__global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView<T> mv, Material mat, const T *m,
-                                                          const T *u, const Derived *d, double *out) {
+__global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Material mat, const T *m, const T *u,
+                                                          const Derived *d, double *out) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    const int n0 = b * mv.nb, n1 = n0 + mv.nb;
+    const int nb = mv.nb, n0 = b * nb, cnt = min(nb, mv.n - n0);
+    const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg), below = mv.halo_lo[b];
+    Staged<T, 1, 6> st;
+    st.nloc_max = mv.nloc_max;
+    st.acc = reinterpret_cast<T *>(smem_raw);
+    st.sx = st.acc + nb;
+    st.sy = st.sx + mv.nloc_max;
+    st.sz = st.sy + mv.nloc_max;
+    st.f = st.sz + mv.nloc_max;
+    const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0];
+    for (int l = threadIdx.x; l < nloc; l += kThreads) {
+        if (l >= cnt && l < nb) continue;
+        const int g = l < nb ? n0 + l : mv.halo_ids[hbeg + l - nb];
+        st.sx[l] = static_cast<T>(near_image(mv.x[g] - xr, mv.Lx, mv.iLx));
+        st.sy[l] = static_cast<T>(near_image(mv.y[g] - yr, mv.Ly, mv.iLy));
+        st.sz[l] = static_cast<T>(near_image(mv.z[g] - zr, mv.Lz, mv.iLz));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            st.fld(a, l) = m[static_cast<size_t>(a) * mv.n + g];
+            st.fld(3 + a, l) = u[static_cast<size_t>(a) * mv.n + g];
+        }
+    }
+    __syncthreads();
     const Cubic<T> C{static_cast<T>(mat.c11), static_cast<T>(mat.c12), static_cast<T>(mat.c44)};
     T Eb[6];
 #pragma unroll
     for (int t = 0; t < 6; ++t) Eb[t] = static_cast<T>(d->ebar[t]);
+    const bool img = mv.img[b] != 0;
     double ex = 0.0, me = 0.0;
     const int e_beg = mv.blk_ptr[b], e_mag = e_beg + mv.blk_nmag[b], e_end = mv.blk_ptr[b + 1];
     for (int e = e_beg + static_cast<int>(threadIdx.x); e < e_end; e += kThreads) {
-        const int4 c = mv.conn[e];
-        const int vmin = min(min(c.x, c.y), min(c.z, c.w));
-        if (vmin < n0 || vmin >= n1) continue;
+        const ushort4 c = mv.lconn[e];
+        const int v[4] = {c.x, c.y, c.z, c.w};
+        bool skip = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) skip |= v[j] >= nb && v[j] < nb + below;
+        if (skip) continue;
         const bool mag = e < e_mag;
         Geo<T> G;
-        tet_geometry(mv, c, G);
+        stage_geometry(st.sx, st.sy, st.sz, c, img, mv, G);
         T mv4[4][3], uv[4][3], E[6];
-        gather3(m, mv.n, c, mv4);
-        gather3(u, mv.n, c, uv);
+        vertex3(st, 0, c, mv4);
+        vertex3(st, 3, c, uv);
         sym_grad(uv, G, E);
 #pragma unroll
         for (int t = 0; t < 6; ++t) E[t] += Eb[t];
@@ -534,46 +742,49 @@ Cubic<T> cubic_of(const Material &m) {
 }
 }  // namespace
 
-void launch_elastic_matvec(const MeshView<double> &mv, const Material &mat, MatvecMode mode, const double *in,
-                           double *out, const double *b, double *r, double *p, const CGScalars &cg, int k,
+void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode mode, const double *in, double *out,
+                           const double *b, const double *r, double *pout, const CGScalars &cg, int k, double tol,
                            hipStream_t s) {
-    ElasticMatvecOp<double> op{in, out, b, r, p, cg, k, static_cast<int>(mode), mv.n, cubic_of<double>(mat)};
-    run_elem<double, 3>(mv, op, s);
+    ElasticMatvecOp<double> op{in, out, b, r, pout, cg, k, static_cast<int>(mode), mv.n, tol * tol,
+                               cubic_of<double>(mat), {0}, {0.0}};
+    run_elem<double, 3, 3>(mv, op, s);
 }
 
-void launch_elastic_rhs(const MeshView<double> &mv, const Material &mat, const double *m, double *b, double *x,
-                        double *bb, hipStream_t s) {
+void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x, double *bb,
+                        hipStream_t s) {
     ElasticRhsOp<double> op{m, b, x, bb, mv.n, cubic_of<double>(mat), mat.l100, mat.l111};
-    run_elem<double, 3>(mv, op, s);
+    run_elem<double, 3, 3>(mv, op, s);
 }
 
-void launch_gs_matvec(const MeshView<double> &mv, int nc, double eps, double mass, MatvecMode mode,
-                      const double *in, double *out, const double *b, double *r, double *p, const CGScalars &cg,
-                      int k, hipStream_t s) {
+void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const double *in,
+                      double *out, const double *b, const double *r, double *pout, const CGScalars &cg, int k,
+                      double tol, hipStream_t s) {
+    const int md = static_cast<int>(mode);
+    const double t2 = tol * tol;
     switch (nc) {
-        case 1: run_elem<double, 1>(mv, GsMatvecOp<double, 1>{in, out, b, r, p, cg, k, static_cast<int>(mode), mv.n, eps, mass, {0}}, s); break;
-        case 2: run_elem<double, 2>(mv, GsMatvecOp<double, 2>{in, out, b, r, p, cg, k, static_cast<int>(mode), mv.n, eps, mass, {0, 0}}, s); break;
-        default: run_elem<double, 3>(mv, GsMatvecOp<double, 3>{in, out, b, r, p, cg, k, static_cast<int>(mode), mv.n, eps, mass, {0, 0, 0}}, s); break;
+        case 1: run_elem<double, 1, 1>(mv, GsMatvecOp<double, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, eps, mass, {0}, {0.0}}, s); break;
+        case 2: run_elem<double, 2, 2>(mv, GsMatvecOp<double, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, eps, mass, {0, 0}, {0.0, 0.0}}, s); break;
+        default: run_elem<double, 3, 3>(mv, GsMatvecOp<double, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, eps, mass, {0, 0, 0}, {0.0, 0.0, 0.0}}, s); break;
     }
 }
 
-void launch_field_rhs(const MeshView<double> &mv, const Material &mat, const double *m, const double *u,
-                      const Derived *d, double c, double *b, double *x0, double *ch2, double *bb, int bbstride,
-                      hipStream_t s) {
+void launch_field_rhs(const MeshView &mv, const Material &mat, const double *m, const double *u, const Derived *d,
+                      double c, double *b, double *x0, double *ch2, double *bb, int bbstride, hipStream_t s) {
     FieldRhsOp<double> op{m, u, d, b, x0, ch2, bb, mv.n, bbstride, c, cubic_of<double>(mat), mat.l100, mat.l111,
                           mat.kan, mat.kme, {0, 0, 0, 0, 0, 0}, {0, 0, 0}};
-    run_elem<double, 6>(mv, op, s);
+    run_elem<double, 6, 6>(mv, op, s);
 }
 
-void launch_mass_rhs(const MeshView<double> &mv, const double *y, const double *ch2, double *b, double *x0,
-                     double *bb, int bbstride, hipStream_t s) {
+void launch_mass_rhs(const MeshView &mv, const double *y, const double *ch2, double *b, double *x0, double *bb,
+                     int bbstride, hipStream_t s) {
     MassRhsOp<double> op{y, ch2, b, x0, bb, mv.n, bbstride};
-    run_elem<double, 2>(mv, op, s);
+    run_elem<double, 2, 2>(mv, op, s);
 }
 
-void launch_energy_elem(const MeshView<double> &mv, const Material &mat, const double *m, const double *u,
-                        const Derived *d, double *out2, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy_elem<double>, dim3(mv.nblk), dim3(kThreads), 0, s, mv, mat, m, u, d, out2);
+void launch_energy_elem(const MeshView &mv, const Material &mat, const double *m, const double *u, const Derived *d,
+                        double *out2, hipStream_t s) {
+    const size_t lds = sizeof(double) * (static_cast<size_t>(mv.nb) + 9 * static_cast<size_t>(mv.nloc_max));
+    hipLaunchKernelGGL(k_energy_elem<double>, dim3(mv.nblk), dim3(kThreads), lds, s, mv, mat, m, u, d, out2);
 }
 
 }  // namespace gspm

@@ -188,8 +188,15 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
     }
     M.blk_ptr.resize(static_cast<size_t>(M.nblk) + 1);
     M.blk_nmag.resize(static_cast<size_t>(M.nblk));
-    M.conn.resize(4 * static_cast<size_t>(M.ncopies));
+    M.halo_ptr.assign(static_cast<size_t>(M.nblk) + 1, 0);
+    M.halo_lo.resize(static_cast<size_t>(M.nblk));
+    M.img.resize(static_cast<size_t>(M.nblk));
+    M.lconn.resize(4 * static_cast<size_t>(M.ncopies));
+    M.halo_ids.clear();
+    M.nloc_max = 0;
+    std::vector<int32_t> halo;
     for (int32_t b = 0; b < M.nblk; ++b) {
+        const int32_t n0b = b * nb, n1b = std::min(n0b + nb, n);
         M.blk_ptr[b] = static_cast<int32_t>(cnt[b]);
         auto first = copy_elem.begin() + cnt[b], last = copy_elem.begin() + cnt[b + 1];
         auto minv = [&](int64_t e) {
@@ -206,10 +213,45 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
         int32_t nmag = 0;
         for (auto it = first; it != last; ++it) nmag += tags[*it] != 0;
         M.blk_nmag[b] = nmag;
+        // halo: vertices of the block's elements outside its owned range
+        halo.clear();
+        for (auto it = first; it != last; ++it)
+            for (int j = 0; j < 4; ++j) {
+                const int32_t v = M.user2int[tets[*it * 4 + j]];
+                if (v < n0b || v >= n1b) halo.push_back(v);
+            }
+        std::sort(halo.begin(), halo.end());
+        halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+        const int32_t nloc = nb + static_cast<int32_t>(halo.size());
+        if (nloc > 65535) { err = "element block too large for 16-bit local indices"; return GSPM_E_ARG; }
+        M.nloc_max = std::max(M.nloc_max, nloc);
+        M.halo_lo[b] = static_cast<int32_t>(std::lower_bound(halo.begin(), halo.end(), n0b) - halo.begin());
+        M.halo_ptr[b + 1] = M.halo_ptr[b] + static_cast<int32_t>(halo.size());
         for (int64_t c = cnt[b]; c < cnt[b + 1]; ++c)
-            for (int j = 0; j < 4; ++j) M.conn[4 * c + j] = M.user2int[tets[copy_elem[c] * 4 + j]];
+            for (int j = 0; j < 4; ++j) {
+                const int32_t v = M.user2int[tets[copy_elem[c] * 4 + j]];
+                int32_t l = (v >= n0b && v < n1b) ? v - n0b
+                                                  : nb + static_cast<int32_t>(std::lower_bound(halo.begin(), halo.end(), v) - halo.begin());
+                M.lconn[4 * c + j] = static_cast<uint16_t>(l);
+            }
+        // Staged coordinates are shifted to the nearest image of the block's
+        // first node; if every staged node lies within a quarter box of it,
+        // element edges are plain differences of staged coordinates.
+        bool far = false;
+        auto check = [&](int32_t v) {
+            for (int a = 0; a < 3; ++a) {
+                double d = M.xs[static_cast<size_t>(a) * n + v] - M.xs[static_cast<size_t>(a) * n + n0b];
+                d -= M.L[a] * std::nearbyint(d / M.L[a]);
+                far |= std::fabs(d) >= 0.25 * M.L[a];
+            }
+        };
+        for (int32_t v = n0b; v < n1b; ++v) check(v);
+        for (int32_t v : halo) check(v);
+        M.img[b] = far ? 1 : 0;
+        M.halo_ids.insert(M.halo_ids.end(), halo.begin(), halo.end());
     }
     M.blk_ptr[M.nblk] = static_cast<int32_t>(M.ncopies);
+    M.nhalo = static_cast<int64_t>(M.halo_ids.size());
     return GSPM_OK;
 }
 

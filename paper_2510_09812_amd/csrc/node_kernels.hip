@@ -159,8 +159,10 @@ __global__ void __launch_bounds__(kThreads) k_cg_start(int n, int nc, int joint,
             }
 }
 
-// Iteration k, after q = A p and pq[k]: alpha = rr[k] / pq[k];
-// x += alpha p; r -= alpha q; rr[k+1] += r.r.
+// Iteration k, after the matvec wrote p_k, q = A p_k and pq[k]:
+// alpha = rr[k] / pq[k]; x += alpha p; r -= alpha q; rr[k+1] += r.r.  The
+// convergence test of rr[k+1] and the next direction happen in the next
+// iteration's matvec.
 __global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint, double *x, double *r,
                                                         const double *p, const double *q, CGScalars cg, int k) {
     const int ns = joint ? 1 : nc;
@@ -186,43 +188,27 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint
     block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride());
 }
 
-// Iteration k, after rr[k+1]: stop a component at ||r|| <= tol ||b||
-// (recording k+1 iterations) or on a non-finite residual; otherwise
-// beta = rr[k+1] / rr[k] and p = r + beta p.
-__global__ void __launch_bounds__(kThreads) k_cg_direction(int n, int nc, int joint, const double *r, double *p,
-                                                           CGScalars cg, int k, double tol2) {
+// Convergence test of rr[k] alone (after the last permitted iteration, when no
+// further matvec will test it): ||r|| <= tol ||b|| converges with k
+// iterations, a non-finite residual breaks down.  One workgroup.
+__global__ void __launch_bounds__(kThreads) k_cg_check(int nc, int joint, CGScalars cg, int k, double tol2) {
     const int ns = joint ? 1 : nc;
     bool live[3];
     if (!read_live(cg.done, ns, live)) return;
-    const double *const src[9] = {cg.rr_at(0, k + 1), ns > 1 ? cg.rr_at(1, k + 1) : nullptr,
-                                  ns > 2 ? cg.rr_at(2, k + 1) : nullptr, cg.rr_at(0, k),
-                                  ns > 1 ? cg.rr_at(1, k) : nullptr, ns > 2 ? cg.rr_at(2, k) : nullptr,
+    const double *const src[6] = {cg.rr_at(0, k), ns > 1 ? cg.rr_at(1, k) : nullptr, ns > 2 ? cg.rr_at(2, k) : nullptr,
                                   cg.bb_at(0), ns > 1 ? cg.bb_at(1) : nullptr, ns > 2 ? cg.bb_at(2) : nullptr};
-    double t[9];
-    shard_totals<9>(src, t);
-    double beta[3];
-    int stop[3];
-    for (int s = 0; s < 3; ++s) {
-        beta[s] = 0.0;
-        stop[s] = 0;
-        if (!live[s]) continue;
-        const double rrn = t[s];
-        if (!isfinite(rrn)) stop[s] = 2;
-        else if (rrn <= tol2 * t[6 + s]) stop[s] = 1;
-        else beta[s] = rrn / t[3 + s];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int s = 0; s < ns; ++s)
-            if (stop[s]) {
-                cg.done[s] = stop[s];
-                cg.iters[s] = k + 1;
+    double t[6];
+    shard_totals<6>(src, t);
+    if (threadIdx.x == 0)
+        for (int s = 0; s < ns; ++s) {
+            if (!live[s]) continue;
+            if (!isfinite(t[s])) {
+                cg.done[s] = 2;
+                cg.iters[s] = k;
+            } else if (t[s] <= tol2 * t[3 + s]) {
+                cg.done[s] = 1;
+                cg.iters[s] = k;
             }
-    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
-        for (int c = 0; c < nc; ++c) {
-            const int s = set_of(c, joint);
-            if (!live[s] || stop[s]) continue;
-            const size_t o = static_cast<size_t>(c) * n + i;
-            p[o] = r[o] + beta[s] * p[o];
         }
 }
 
@@ -235,10 +221,8 @@ void launch_cg_update(int n, int nc, bool joint, double *x, double *r, const dou
     hipLaunchKernelGGL(k_cg_update, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, x, r, p, q, cg, k);
 }
 
-void launch_cg_direction(int n, int nc, bool joint, const double *r, double *p, const CGScalars &cg, int k,
-                         double tol, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_direction, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, r, p, cg, k,
-                       tol * tol);
+void launch_cg_check(int nc, bool joint, const CGScalars &cg, int k, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(kThreads), 0, s, nc, joint ? 1 : 0, cg, k, tol * tol);
 }
 
 // ------------------------------------------------------ GSPM node updates

@@ -1,10 +1,13 @@
 // CG driver and the GSPM step sequence (host side; all arithmetic runs in
 // the kernels).
 //
-// CG runs without a host round trip per iteration: each iteration is three
-// launches (matvec with fused p.Ap, x/r update with fused r.r, convergence
-// test and new direction), convergence is decided on the device, and a
-// converged solve turns the remaining launches into immediate exits.  The host
+// CG runs without a host round trip per iteration.  Each iteration is two
+// launches: the matvec, whose staging forms the new direction
+// p_k = r_k + beta_k p_{k-1} after testing ||r_k|| on the device, with p.Ap
+// fused into its epilogue; and the x/r update with r.r fused.  Directions are
+// double-buffered (a block reads the previous direction at its halo nodes
+// while other blocks write the new one).  Convergence is decided on the device
+// and a converged solve turns the remaining launches into immediate exits.  The host
 // enqueues iterations in batches and reads the convergence flags of the
 // previous batch while the next one runs, so the device never waits for it.
 #include <algorithm>
@@ -34,21 +37,23 @@ CgResult cg_run(gspm_ctx *c, int nc, bool joint, double *x, const double *b, dou
     hipStream_t s = c->stream;
     const int ns = joint ? 1 : nc, n = c->n;
     CgResult res;
-    apply(MV_RESID, x, nullptr, b, c->d.r, c->d.p, 0);
+    apply(MV_RESID, x, nullptr, b, c->d.r, nullptr, 0);
     launch_cg_start(n, nc, joint, x, c->cg, tol, s);
+    double *P[2] = {c->d.p, c->d.p2};
 
     const int cap = c->cg.ring - 2;
-    const int first = std::min(std::max(c->predict[kind] + 2, 2), cap);
-    const int later = std::min(std::max(c->predict[kind] / 8, 4), cap);
+    const int first = std::min(std::max(c->predict[kind] + 1, 2), cap);
+    const int later = std::min(std::max(c->predict[kind] / 32, 4), std::min(cap, 32));
     int k = 0;
     auto enqueue = [&](int cnt) {
         const int k1 = std::min(k + cnt, maxit);
         launch_zero_ring(c->cg, ns, k + 1, k1 + 1, k, k1, s);
         for (int it = k; it < k1; ++it) {
-            apply(MV_ITER, c->d.p, c->d.q, nullptr, nullptr, nullptr, it);
-            launch_cg_update(n, nc, joint, x, c->d.r, c->d.p, c->d.q, c->cg, it, s);
-            launch_cg_direction(n, nc, joint, c->d.r, c->d.p, c->cg, it, tol, s);
+            double *pold = P[it & 1], *pnew = P[(it + 1) & 1];
+            apply(MV_ITER, pold, c->d.q, nullptr, c->d.r, pnew, it);
+            launch_cg_update(n, nc, joint, x, c->d.r, pnew, c->d.q, c->cg, it, s);
         }
+        if (k1 == maxit) launch_cg_check(nc, joint, c->cg, maxit, tol, s);
         k = k1;
     };
     auto post = [&](int slot) {
@@ -131,7 +136,7 @@ CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int max
                             int k) {
                             const bool timed = mode == MV_ITER;
                             if (timed) prof_begin(c, k);
-                            launch_elastic_matvec(c->mv, c->mat, mode, in, out, bb, rr, p, c->cg, k, c->stream);
+                            launch_elastic_matvec(c->mv, c->mat, mode, in, out, bb, rr, p, c->cg, k, tol, c->stream);
                             if (timed) prof_end(c);
                         });
     if (c->profile)
@@ -143,7 +148,7 @@ CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int max
 CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit, SolveKind kind) {
     return cg_run(c, nc, false, x, b, tol, maxit, kind,
                   [&](MatvecMode mode, const double *in, double *out, const double *bb, double *r, double *p, int k) {
-                      launch_gs_matvec(c->mv, nc, eps, 1.0, mode, in, out, bb, r, p, c->cg, k, c->stream);
+                      launch_gs_matvec(c->mv, nc, eps, 1.0, mode, in, out, bb, r, p, c->cg, k, tol, c->stream);
                   });
 }
 

@@ -3,12 +3,14 @@
 Tolerances (FP64 on both sides, different summation orders):
   - operators:  max |y_gpu - y_ref| <= 1e-12 max |y_ref|
   - CG solves at tol 1e-12: relative 2-norm error <= 1e-9
-  - steps at the workload's CG tolerance (1e-8): relative 2-norm error of m and
-    of the mean-removed u <= 1e-9; energies <= 1e-9 relative.
-Both sides run the same CG recurrence with the same initial guess and stopping
-rule, so they take the same number of iterations up to a residual that lands
-on the threshold within rounding; iteration totals must agree to within 1 per
-solve.
+  - steps at CG tolerance 1e-12: relative 2-norm error of m and of the
+    mean-removed u <= 1e-9; energies <= 1e-9 relative.
+  - steps at the workloads' CG tolerance 1e-8: m and u <= 1e-6 (the stated
+    accuracy target), energies <= 1e-9.  Both sides stop CG at the first
+    iterate with ||r|| <= tol ||b|| (Sec. 3.1); when a residual lands on that
+    threshold within rounding one side takes one more iteration, and the two
+    accepted iterates differ by one CG correction (observed: 2e-9 relative in
+    u).  Iteration totals must agree to within 1 per solve.
 """
 import numpy as np
 import pytest
@@ -103,13 +105,14 @@ def _run_both(case, steps, hext=None, sigma=(0.0,) * 6, precession=True, tol=Non
 
 
 def _compare_states(sim, orc, st, ost, tol=1e-9):
+    """tol bounds m and u; energies are held to 1e-9 at any CG tolerance."""
     em = _rel(sim.get_m(), orc.get_m())
     eu = _rel(_demean(sim.get_u()), _demean(orc.get_u()))
     eg, er = sim.energies(), orc.energies()
     ee = max(abs(eg[k] - er[k]) / max(abs(er["total"]), 1e-300) for k in er)
     print(f"m {em:.2e} u {eu:.2e} energies {ee:.2e} | mech iters gpu {st['mech_iters']} oracle {ost['mech_iters']}"
           f" | gs gpu {st['gs_iters_stage']} oracle {ost['gs_iters']}", flush=True)
-    assert em < tol and eu < tol and ee < tol
+    assert em < tol and eu < tol and ee < 1e-9
     nsolve = st["steps_done"]
     assert abs(st["mech_iters"] - ost["mech_iters"]) <= nsolve
     assert all(abs(a - b) <= nsolve for a, b in zip(st["gs_iters_stage"], ost["gs_iters"]))
@@ -120,17 +123,18 @@ def test_step_cube10_twenty_steps():
     case = w.cube10_random()
     sim, orc, st, ost = _run_both(case, case.steps)
     assert st["steps_done"] == 20 and st["failed_step"] == -1
-    _compare_states(sim, orc, st, ost)
+    _compare_states(sim, orc, st, ost, 1e-6)
     sim.close()
 
 
 @pytest.mark.parametrize("precession", [True, False])
-def test_step_with_inclusion_field_and_stress(precession):
+@pytest.mark.parametrize("cg_tol,tol", [(1e-8, 1e-6), (1e-12, 1e-9)])
+def test_step_with_inclusion_field_and_stress(precession, cg_tol, tol):
     case = w.small_cube(9, seed=103, L=8e-8, jitter=0.15, sphere=0.3, shuffle=True)
     sigma = np.array([4e6, -2e6, 1e6, 0.5e6, -0.3e6, 1e6])
     sim, orc, st, ost = _run_both(case, 6, hext=(-0.2 * case.material["Ms"], 0.05 * case.material["Ms"], 0.0),
-                                  sigma=sigma, precession=precession)
-    _compare_states(sim, orc, st, ost)
+                                  sigma=sigma, precession=precession, tol=cg_tol)
+    _compare_states(sim, orc, st, ost, tol)
     mg, eg = sim.averages()
     mr, er = orc.averages()
     assert np.abs(mg - mr).max() < 1e-12 and np.abs(eg - er).max() < 1e-12 * np.abs(er).max()
@@ -218,5 +222,5 @@ def test_checkpoint_resume_matches_continuous_run():
 def test_cube47_sphere_steps_match_oracle():
     case = w.cube47_sphere()
     sim, orc, st, ost = _run_both(case, 3)
-    _compare_states(sim, orc, st, ost)
+    _compare_states(sim, orc, st, ost, 1e-6)
     sim.close()
