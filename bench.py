@@ -44,7 +44,8 @@ def kernel_hash() -> str:
 def matvec_bytes(n_nodes: int, n_tets: int, real_bytes: int = 8) -> int:
     """Algorithmic bytes of one elastic matvec: connectivity (4 x int32 per
     tetrahedron), coordinates, the input vector and the output vector (3
-    values per node each), each read or written once."""
+    values per node each, in the working precision), each read or written
+    once."""
     return 16 * n_tets + 3 * real_bytes * 3 * n_nodes
 
 
@@ -63,9 +64,9 @@ def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float) ->
     return mech_iters * mech + gs_iters * gs + rhs + nodes
 
 
-def traffic_from_profile(launch_bytes: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources."""
+def traffic_from_profile(path: str):
+    """HBM bytes per launch of the path's elastic matvec from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel sources."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -73,7 +74,7 @@ def traffic_from_profile(launch_bytes: int):
         return None
     if t.get("kernel_hash") != kernel_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t.get(path, {}).get("bytes_per_launch")
 
 
 def cpu_baseline(case, sample_steps: int = 1) -> dict:
@@ -103,6 +104,8 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-profile", action="store_true", help="skip the per-launch matvec events")
     ap.add_argument("--block-nodes", type=int, default=0, help="nodes per owner block (0 = library default)")
+    ap.add_argument("--precision", choices=("fp64", "mixed", "both"), default="both",
+                    help="paths to run; with both, `value` is the mixed path and the FP64 path is reported beside it")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MB (HBM counter calibration)")
     args = ap.parse_args()
@@ -129,50 +132,76 @@ def main() -> int:
         del src, dst
     print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
     case = w.CASES[args.workload]()
-    t_up = time.perf_counter()
-    sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, device=0, profile=not args.no_profile,
-                          block_nodes=args.block_nodes)
-    sim.set_m(case.m0)
-    info = sim.mesh_info()
-    t_up = time.perf_counter() - t_up
-    print(f"[bench] uploaded {info['n_unique']} nodes, {info['n_tets']} tets in {t_up:.1f} s; warmup {args.warmup}",
-          file=sys.stderr, flush=True)
-    if args.warmup:
-        sim.step(case.dt, args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = sim.step(case.dt, args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+
+    def run_path(precision: int) -> dict:
+        t_up = time.perf_counter()
+        sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, device=0, profile=not args.no_profile,
+                              block_nodes=args.block_nodes, precision=precision)
+        sim.set_m(case.m0)
+        info = sim.mesh_info()
+        t_up = time.perf_counter() - t_up
+        print(f"[bench] precision {precision}: uploaded {info['n_unique']} nodes, {info['n_tets']} tets in "
+              f"{t_up:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
+        if args.warmup:
+            sim.step(case.dt, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sim.step(case.dt, args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print(f"[bench] precision {precision}: {args.steps} steps in {wall:.3f} s, mech iters {st['mech_iters']}, "
+              f"gs iters {st['gs_iters']}, refinements {st['refinements']}", file=sys.stderr, flush=True)
+        out = dict(info=info, st=st, wall=wall, value=info["n_unique"] * args.steps / wall, m=sim.get_m(),
+                   u=sim.get_u())
+        sim.close()
+        return out
+
+    paths = {}
+    if args.precision in ("fp64", "both"):
+        paths["fp64"] = run_path(gspm.GSPM_FP64)
+    if args.precision in ("mixed", "both"):
+        paths["mixed"] = run_path(gspm.GSPM_MIXED)
+    head = paths["mixed"] if "mixed" in paths else paths["fp64"]
+    head_name = "mixed" if "mixed" in paths else "fp64"
+    info, st, wall, value = head["info"], head["st"], head["wall"], head["value"]
     n, ne = info["n_unique"], info["n_tets"]
-    value = n * args.steps / wall
-    print(f"[bench] {args.steps} steps in {wall:.3f} s, mech iters {st['mech_iters']}, gs iters {st['gs_iters']}",
-          file=sys.stderr, flush=True)
 
     roofline = None
     if st["matvec_launches"] > 0:
         avg_s = st["matvec_ms"] / st["matvec_launches"] * 1e-3
-        mb = matvec_bytes(n, ne)
+        mb = matvec_bytes(n, ne, 4 if head_name == "mixed" else 8)
         achieved = mb / avg_s / 1e9
+        kname = "k_elem<float,3,3,ElasticMatvecOp>" if head_name == "mixed" else "k_elem<double,3,3,ElasticMatvecOp>"
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(mb),
-                    "kernel": "k_elem<double,3,ElasticMatvecOp>", "bytes_per_launch": mb,
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(head_name),
+                    "kernel": kname, "bytes_per_launch": mb,
                     "avg_launch_us": avg_s * 1e6, "launches": st["matvec_launches"]}
     mech_per_step = st["mech_iters"] / args.steps
     gs_per_step = st["gs_iters"] / args.steps
     b_step = step_bytes(n, ne, mech_per_step, gs_per_step)
+    compare = None
+    if "fp64" in paths and "mixed" in paths:
+        f, x = paths["fp64"], paths["mixed"]
+        um = lambda u: u - u.mean(axis=0)
+        compare = {"fp64_value": f["value"], "fp64_ms_per_step": f["wall"] / args.steps * 1e3,
+                   "speedup_vs_fp64": x["value"] / f["value"],
+                   "rel_err_m_vs_fp64": float(np.linalg.norm(x["m"] - f["m"]) / np.linalg.norm(f["m"])),
+                   "rel_err_u_vs_fp64": float(np.linalg.norm(um(x["u"]) - um(f["u"])) / np.linalg.norm(um(f["u"]))),
+                   "fp64_mech_iters_per_step": f["st"]["mech_iters"] / args.steps,
+                   "mixed_refinements_per_step": x["st"]["refinements"] / args.steps}
     out = {
         "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if head_name == "mixed" else "f64",
+        "data": "synthetic",
         "config": {"workload": case.name, "nodes": n, "tets": ne, "dt_s": case.dt, "cg_tol": case.cg_tol,
-                   "block_nodes": info["n_unique"] // max(info["n_blocks"] - 1, 1) if args.block_nodes == 0 else args.block_nodes,
-                   "precision": "fp64", "mech_iters_per_step": mech_per_step, "gs_iters_per_step": gs_per_step},
+                   "path": head_name, "block_nodes": args.block_nodes or 256,
+                   "mech_iters_per_step": mech_per_step, "gs_iters_per_step": gs_per_step},
         "roofline": roofline,
         "step_roofline": {"bytes_per_node_step": b_step / n, "roofline_node_steps_per_s": HBM_PEAK_GBS * 1e9 / b_step * n,
                           "frac": value / (HBM_PEAK_GBS * 1e9 / b_step * n)},
+        "mixed_vs_fp64": compare,
     }
-    sim.close()
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

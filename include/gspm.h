@@ -74,8 +74,11 @@ typedef enum {
 
 typedef struct {
     int32_t device;         /* HIP device ordinal */
-    int32_t precision;      /* GSPM_FP64, or GSPM_MIXED: FP32 element work and matvecs,
-                               FP64 state, dot products, norms and averages */
+    int32_t precision;      /* GSPM_FP64, or GSPM_MIXED: every CG solve is FP64 iterative
+                               refinement (true FP64 residual, same stopping rule)
+                               around an inner CG with FP32 vectors and FP32 element
+                               arithmetic; state, right-hand sides, dot products,
+                               norms and averages stay FP64 */
     int32_t block_nodes;    /* nodes per owner block (power of two, 64..1024), 0 = automatic */
     int32_t profile;        /* nonzero: time every elastic matvec launch with HIP events */
     void *stream;           /* hipStream_t to run on, or NULL for a stream owned by the context */
@@ -102,13 +105,14 @@ typedef struct {
 typedef struct {
     int32_t steps_done;     /* steps completed by this call */
     int32_t failed_step;    /* index (within the call) of the step that failed, or -1 */
-    int64_t mech_iters;     /* elastic CG iterations, summed over the steps */
+    int64_t mech_iters;     /* elastic CG iterations (GSPM_MIXED: inner FP32 iterations), summed over the steps */
     int64_t gs_iters;       /* GS CG iterations, summed over all scalar solves and steps */
     int64_t gs_iters_stage[8]; /* per scalar solve: g1 g2 g3, g*1 g*2, m**1 m**2 m**3 */
     double dm_avg;          /* mean |m^{n+1} - m^n| over magnetic nodes, last step (Sec. 3.2) */
     double elapsed_ms;      /* wall time of the call on the device stream */
     double matvec_ms;       /* profile mode: summed duration of the elastic matvec launches */
     int64_t matvec_launches;/* profile mode: number of elastic matvec launches timed */
+    int64_t refinements;    /* GSPM_MIXED: outer FP64 residual evaluations that started an FP32 inner solve */
 } gspm_step_stats;
 
 /* Create a context on opts->device (NULL opts: device 0, FP64, own stream).
@@ -164,6 +168,13 @@ gspm_status gspm_apply(gspm_ctx *ctx, gspm_op op, double eps, const double *x, d
  * iteration count (summed over components for GSPM_OP_GS). */
 gspm_status gspm_solve(gspm_ctx *ctx, gspm_op op, double eps, const double *b, double *x, int64_t n_nodes,
                        double tol, int32_t maxit, int32_t *iters);
+
+/* Time one operator of Sec. 2.3 on device-resident data: reps launches of the
+ * matvec y = A x on internal work vectors (their contents are whatever the
+ * last call left; timing does not depend on them), bracketed by HIP events on
+ * the context's stream.  *avg_ms receives the mean duration of one launch.
+ * GSPM_OP_ELASTIC needs gspm_set_params.  Changes no field. */
+gspm_status gspm_time_operator(gspm_ctx *ctx, gspm_op op, double eps, int32_t reps, double *avg_ms);
 
 /* Mesh facts after upload: unique nodes, tetrahedra, owner blocks, element
  * copies processed per element pass, cell volume [m^3]. Pointers may be NULL. */

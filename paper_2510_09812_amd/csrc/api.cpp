@@ -112,6 +112,7 @@ gspm_ctx::~gspm_ctx() {
     if (t0) hipEventDestroy(t0);
     if (t1) hipEventDestroy(t1);
     if (h_flags) hipHostFree(h_flags);
+    if (h_mixed) hipHostFree(h_mixed);
     if (own_stream && stream) hipStreamDestroy(stream);
 }
 
@@ -125,6 +126,8 @@ void gspm_ctx::release_mesh() {
     dev_free(b.r); dev_free(b.p); dev_free(b.p2); dev_free(b.q);
     dev_free(b.sums); dev_free(b.esums); dev_free(b.dm); dev_free(b.der); dev_free(b.bad);
     dev_free(b.cg_rr); dev_free(b.cg_pq); dev_free(b.cg_bb); dev_free(b.cg_flags);
+    dev_free(b.r32); dev_free(b.p32); dev_free(b.p32b); dev_free(b.q32); dev_free(b.x32);
+    dev_free(b.cgi_rr); dev_free(b.cgi_pq); dev_free(b.cgi_bb); dev_free(b.cgi_flags);
     have_mesh = have_m = false;
 }
 
@@ -140,10 +143,6 @@ gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts) {
     if (opts) o = *opts;
     if (o.precision != GSPM_FP64 && o.precision != GSPM_MIXED) {
         g_create_error = "gspm_create: unknown precision";
-        return GSPM_E_ARG;
-    }
-    if (o.precision == GSPM_MIXED) {
-        g_create_error = "gspm_create: GSPM_MIXED is not available in this build";
         return GSPM_E_ARG;
     }
     if (o.block_nodes != 0 && (o.block_nodes < 64 || o.block_nodes > 1024 || (o.block_nodes & (o.block_nodes - 1)))) {
@@ -184,6 +183,7 @@ gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts) {
         c->own_stream = true;
     }
     bool ok = hipHostMalloc(reinterpret_cast<void **>(&c->h_flags), sizeof(int32_t) * 4 * kMaxComp) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void **>(&c->h_mixed), sizeof(double) * 16 * kShards) == hipSuccess;
     for (auto &e : c->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreate(&c->t0) == hipSuccess && hipEventCreate(&c->t1) == hipSuccess;
     if (!ok) {
@@ -237,6 +237,13 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     rc = rc ? rc : dev_alloc(c, &d.cg_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
     rc = rc ? rc : dev_alloc(c, &d.cg_bb, static_cast<size_t>(kMaxComp) * kShards);
     rc = rc ? rc : dev_alloc(c, &d.cg_flags, 2 * kMaxComp);
+    if (c->precision == GSPM_MIXED) {
+        for (float **p : {&d.r32, &d.p32, &d.p32b, &d.q32, &d.x32}) rc = rc ? rc : dev_alloc(c, p, n3);
+        rc = rc ? rc : dev_alloc(c, &d.cgi_rr, static_cast<size_t>(kMaxComp) * kRing * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cgi_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cgi_bb, static_cast<size_t>(kMaxComp) * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cgi_flags, 2 * kMaxComp);
+    }
     if (rc) {
         c->release_mesh();
         return static_cast<gspm_status>(rc);
@@ -253,6 +260,8 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     hipMemcpyAsync(d.blk_nmag, hm.blk_nmag.data(), sizeof(int32_t) * hm.blk_nmag.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.w, hm.w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
     for (double *p : {d.m, d.mnext, d.u, d.unext, d.ms, d.g, d.gs, d.b, d.r, d.p, d.p2, d.q}) launch_fill(p, n3, 0.0, s);
+    if (c->precision == GSPM_MIXED)
+        for (float *p : {d.r32, d.p32, d.p32b, d.q32, d.x32}) launch_fill_f32(p, n3, s);
     launch_fill(d.ch2, 2 * n, 0.0, s);
     rc = hip_check(c, hipStreamSynchronize(s), "upload_mesh");
     if (rc) {
@@ -289,12 +298,19 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     mv.p0 = hm.p0;
     mv.Lx = hm.L[0]; mv.Ly = hm.L[1]; mv.Lz = hm.L[2];
     mv.iLx = 1.0 / hm.L[0]; mv.iLy = 1.0 / hm.L[1]; mv.iLz = 1.0 / hm.L[2];
+    mv.len_scale = std::cbrt(hm.vc / static_cast<double>(hm.ne));
     c->cg.rr = d.cg_rr;
     c->cg.pq = d.cg_pq;
     c->cg.bb = d.cg_bb;
     c->cg.done = d.cg_flags;
     c->cg.iters = d.cg_flags + kMaxComp;
     c->cg.ring = kRing;
+    c->cg_in.rr = d.cgi_rr;
+    c->cg_in.pq = d.cgi_pq;
+    c->cg_in.bb = d.cgi_bb;
+    c->cg_in.done = d.cgi_flags;
+    c->cg_in.iters = d.cgi_flags ? d.cgi_flags + kMaxComp : nullptr;
+    c->cg_in.ring = kRing;
     c->dargs.vc = hm.vc;
     c->have_mesh = true;
     c->have_m = false;
@@ -451,13 +467,13 @@ gspm_status gspm_apply(gspm_ctx *c, gspm_op op, double eps, const double *x, dou
     rc = upload(c, c->d.ms, h);
     if (rc) return static_cast<gspm_status>(rc);
     if (op == GSPM_OP_ELASTIC) {
-        launch_elastic_matvec(c->mv, c->mat, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, 0.0,
-                              c->stream);
+        launch_elastic_matvec<double>(c->mv, c->mat, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0,
+                                      0.0, c->stream);
     } else {
         const double e = op == GSPM_OP_LAPLACE ? 1.0 : (op == GSPM_OP_MASS ? 0.0 : eps);
         const double mass = op == GSPM_OP_LAPLACE ? 0.0 : 1.0;
-        launch_gs_matvec(c->mv, 3, e, mass, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, 0.0,
-                         c->stream);
+        launch_gs_matvec<double>(c->mv, 3, e, mass, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0,
+                                 0.0, c->stream);
     }
     rc = download(c, c->d.q, h);
     if (rc) return static_cast<gspm_status>(rc);
@@ -502,6 +518,43 @@ gspm_status gspm_solve(gspm_ctx *c, gspm_op op, double eps, const double *b, dou
     if (rc) return static_cast<gspm_status>(rc);
     scatter_user(c, hx, x);
     return static_cast<gspm_status>(r.status);
+}
+
+gspm_status gspm_time_operator(gspm_ctx *c, gspm_op op, double eps, int32_t reps, double *avg_ms) {
+    if (!c) return GSPM_E_ARG;
+    if (!avg_ms || reps <= 0 || !std::isfinite(eps)) return fail(c, GSPM_E_ARG, "time_operator: bad arguments");
+    if (!c->have_mesh) return fail(c, GSPM_E_STATE, "time_operator before upload_mesh");
+    if (op < GSPM_OP_LAPLACE || op > GSPM_OP_ELASTIC) return fail(c, GSPM_E_ARG, "time_operator: unknown operator");
+    if (op == GSPM_OP_ELASTIC && !c->have_params) return fail(c, GSPM_E_STATE, "time_operator(ELASTIC) needs set_params");
+    hipSetDevice(c->device);
+    const double e = op == GSPM_OP_LAPLACE ? 1.0 : (op == GSPM_OP_MASS ? 0.0 : eps);
+    const double mass = op == GSPM_OP_LAPLACE ? 0.0 : 1.0;
+    hipEventRecord(c->t0, c->stream);
+    const bool f32 = c->precision == GSPM_MIXED;   // time the operator the inner solves use
+    for (int i = 0; i < reps; ++i) {
+        if (op == GSPM_OP_ELASTIC) {
+            if (f32)
+                launch_elastic_matvec<float>(c->mv, c->mat, MV_APPLY, c->d.r32, c->d.q32, nullptr, nullptr, nullptr,
+                                             c->cg, 0, 0.0, c->stream);
+            else
+                launch_elastic_matvec<double>(c->mv, c->mat, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr,
+                                              c->cg, 0, 0.0, c->stream);
+        } else {
+            if (f32)
+                launch_gs_matvec<float>(c->mv, 3, e, mass, MV_APPLY, c->d.r32, c->d.q32, nullptr, nullptr, nullptr,
+                                        c->cg, 0, 0.0, c->stream);
+            else
+                launch_gs_matvec<double>(c->mv, 3, e, mass, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr,
+                                         c->cg, 0, 0.0, c->stream);
+        }
+    }
+    hipEventRecord(c->t1, c->stream);
+    int rc = hip_check(c, hipEventSynchronize(c->t1), "time_operator");
+    if (rc) return static_cast<gspm_status>(rc);
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, c->t0, c->t1);
+    *avg_ms = ms / reps;
+    return GSPM_OK;
 }
 
 gspm_status gspm_mesh_info(gspm_ctx *c, int64_t *n_unique, int64_t *n_tets, int64_t *n_blocks, int64_t *n_copies,

@@ -60,6 +60,7 @@ struct MeshView {
     const double *w;              // n
     int32_t n, nb, nblk, p0, nloc_max;
     double Lx, Ly, Lz, iLx, iLy, iLz;   // box edges and their inverses (nearest periodic image)
+    double len_scale;                   // cube root of the mean element volume (FP32 non-dimensionalisation)
 };
 
 // Material constants in the form the kernels use.
@@ -134,12 +135,12 @@ void launch_mass_rhs(const MeshView &mv, const double *y, const double *ch2, dou
 // rr[0] += r.r.  ITER (CG iteration k): p_new = r + beta_k p_old (p_new = r at
 // k = 0, with beta_k = rr[k] / rr[k-1] and the convergence test of rr[k] done
 // first), q = A p_new, pq[k] += p_new.q; p_old = in, p_new = pout.
-void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode mode, const double *in,
-                           double *out, const double *b, const double *r, double *pout, const CGScalars &cg, int k,
-                           double tol, hipStream_t s);
-void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const double *in,
-                      double *out, const double *b, const double *r, double *pout, const CGScalars &cg, int k,
-                      double tol, hipStream_t s);
+template <class T>
+void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode mode, const T *in, T *out, const T *b,
+                           const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);
+template <class T>
+void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
+                      const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);
 void launch_energy_elem(const MeshView &mv, const Material &mat, const double *m, const double *u,
                         const Derived *d, double *out2, hipStream_t s);
 void launch_energy_nodes(int n, const double *w, const double *m, const Material &mat, const double hext[3],
@@ -147,10 +148,19 @@ void launch_energy_nodes(int n, const double *w, const double *m, const Material
 
 // CG vector kernels on [nc][n] component-major vectors; joint: one set of
 // scalars for all components (the elastic solve), else one per component.
-void launch_cg_start(int n, int nc, bool joint, double *x, const CGScalars &cg, double tol, hipStream_t s);
-void launch_cg_update(int n, int nc, bool joint, double *x, double *r, const double *p, const double *q,
-                      const CGScalars &cg, int k, hipStream_t s);
+template <class T>
+void launch_cg_start(int n, int nc, bool joint, T *x, const CGScalars &cg, double tol, hipStream_t s);
+template <class T>
+void launch_cg_update(int n, int nc, bool joint, T *x, T *r, const T *p, const T *q, const CGScalars &cg, int k,
+                      hipStream_t s);
 void launch_cg_check(int nc, bool joint, const CGScalars &cg, int k, double tol, hipStream_t s);
+
+// Precision conversions of the mixed form: dst = (float) src; x += (double) d.
+void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s);
+void launch_to_f32_norms(int n, int nc, bool joint, const double *src, double scale, float *dst, const CGScalars &cg,
+                         hipStream_t s);
+void launch_add_f32(int64_t n, double *x, const float *d, hipStream_t s);
+void launch_fill_f32(float *p, int64_t n, hipStream_t s);
 
 // GSPM node updates (Algorithm B.1, Step 2 and Step 4).
 void launch_update_m12(int n, const double *m, const double *g, double *ms, hipStream_t s);

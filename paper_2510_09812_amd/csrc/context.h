@@ -28,6 +28,10 @@ struct DeviceBuffers {
     int32_t *bad = nullptr;
     double *cg_rr = nullptr, *cg_pq = nullptr, *cg_bb = nullptr;
     int32_t *cg_flags = nullptr;  // done[3], iters[3]
+    // mixed form: FP32 inner-solve vectors and scalars
+    float *r32 = nullptr, *p32 = nullptr, *p32b = nullptr, *q32 = nullptr, *x32 = nullptr;
+    double *cgi_rr = nullptr, *cgi_pq = nullptr, *cgi_bb = nullptr;
+    int32_t *cgi_flags = nullptr;
 };
 
 }  // namespace gspm
@@ -51,7 +55,10 @@ struct gspm_ctx {
     gspm::DeviceBuffers d;
     gspm::MeshView mv{};
     gspm::CGScalars cg{};
+    gspm::CGScalars cg_in{};      // inner FP32 solves of the mixed form
     int32_t *h_flags = nullptr;   // pinned host mirror: 2 slots x (done[3], iters[3])
+    double *h_mixed = nullptr;    // pinned staging of the mixed form's outer loop
+    int64_t refinements = 0;      // outer FP64 residual evaluations that launched an inner solve
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
     std::vector<hipEvent_t> prof_ev;

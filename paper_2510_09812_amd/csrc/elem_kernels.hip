@@ -39,9 +39,11 @@ struct Staged {
     __device__ __forceinline__ T &fld(int k, int l) const { return f[k * nloc_max + l]; }
 };
 
+// Edge vectors from staged coordinates (scaled by sc), with the nearest
+// periodic image when the block spans more than a quarter box.
 template <class T>
 __device__ __forceinline__ void stage_geometry(const T *sx, const T *sy, const T *sz, const ushort4 c, bool img,
-                                               const MeshView &mv, Geo<T> &G) {
+                                               const MeshView &mv, double sc, Geo<T> &G) {
     const int v[4] = {c.x, c.y, c.z, c.w};
     T e[3][3];
 #pragma unroll
@@ -53,9 +55,9 @@ __device__ __forceinline__ void stage_geometry(const T *sx, const T *sy, const T
     if (img) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            e[k][0] = near_image(e[k][0], static_cast<T>(mv.Lx), static_cast<T>(mv.iLx));
-            e[k][1] = near_image(e[k][1], static_cast<T>(mv.Ly), static_cast<T>(mv.iLy));
-            e[k][2] = near_image(e[k][2], static_cast<T>(mv.Lz), static_cast<T>(mv.iLz));
+            e[k][0] = near_image(e[k][0], static_cast<T>(mv.Lx * sc), static_cast<T>(mv.iLx / sc));
+            e[k][1] = near_image(e[k][1], static_cast<T>(mv.Ly * sc), static_cast<T>(mv.iLy / sc));
+            e[k][2] = near_image(e[k][2], static_cast<T>(mv.Lz * sc), static_cast<T>(mv.iLz / sc));
         }
     }
     tet_geometry_from_edges(e, G);
@@ -89,13 +91,13 @@ __global__ void __launch_bounds__(kThreads) k_elem(const MeshView mv, const Op o
     st.sz = st.sy + mv.nloc_max;
     st.f = st.sz + mv.nloc_max;
     for (int i = threadIdx.x; i < NC * nb; i += kThreads) st.acc[i] = T(0);
-    const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0];
+    const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0], sc = op.coord_scale;
     for (int l = threadIdx.x; l < nloc; l += kThreads) {
         if (l >= cnt && l < nb) continue;      // owned slots past the last node
         const int g = l < nb ? n0 + l : mv.halo_ids[hbeg + l - nb];
-        st.sx[l] = static_cast<T>(near_image(mv.x[g] - xr, mv.Lx, mv.iLx));
-        st.sy[l] = static_cast<T>(near_image(mv.y[g] - yr, mv.Ly, mv.iLy));
-        st.sz[l] = static_cast<T>(near_image(mv.z[g] - zr, mv.Lz, mv.iLz));
+        st.sx[l] = static_cast<T>(sc * near_image(mv.x[g] - xr, mv.Lx, mv.iLx));
+        st.sy[l] = static_cast<T>(sc * near_image(mv.y[g] - yr, mv.Ly, mv.iLy));
+        st.sz[l] = static_cast<T>(sc * near_image(mv.z[g] - zr, mv.Lz, mv.iLz));
         op.stage(st, l, g);
     }
     __syncthreads();
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__(kThreads) k_elem(const MeshView mv, const Op o
     for (int e = e_beg + static_cast<int>(threadIdx.x); e < e_end; e += kThreads) {
         const ushort4 c = mv.lconn[e];
         Geo<T> G;
-        stage_geometry(st.sx, st.sy, st.sz, c, img, mv, G);
+        stage_geometry(st.sx, st.sy, st.sz, c, img, mv, sc, G);
         T y[4][NC];
         op.element(st, c, G, e < e_mag, y);
         scatter_owned<T, NC>(st.acc, nb, c, y);
@@ -257,6 +259,7 @@ struct ElasticMatvecOp {
     Cubic<T> C;
     int live[1];
     double beta[1];
+    double coord_scale;           // staged coordinates in units of 1/coord_scale metres
 
     __device__ bool prepare() {
         if (mode != MV_ITER) return mode == MV_APPLY || cg.done[0] == 0;
@@ -328,6 +331,7 @@ struct ElasticRhsOp {
     int n;
     Cubic<T> C;
     T l100, l111;
+    double coord_scale = 1.0;
 
     __device__ bool prepare() { return true; }
 
@@ -397,6 +401,7 @@ struct GsMatvecOp {
     T eps, mass;
     int live[NC];
     double beta[NC];
+    double coord_scale;
 
     __device__ bool prepare() {
         if (mode == MV_ITER) return cg_direction_scalars<NC>(cg, k, tol2, live, beta);
@@ -514,6 +519,7 @@ struct FieldRhsOp {
     Cubic<T> C;
     T l100, l111, kan, kme;
     T E0bar[6], hc[3];
+    double coord_scale = 1.0;
 
     __device__ bool prepare() {
 #pragma unroll
@@ -594,6 +600,7 @@ struct MassRhsOp {
     T *b, *x0;
     double *bb;
     int n, bbstride;
+    double coord_scale = 1.0;
 
     __device__ bool prepare() { return true; }
 
@@ -690,7 +697,7 @@ __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Mat
         if (skip) continue;
         const bool mag = e < e_mag;
         Geo<T> G;
-        stage_geometry(st.sx, st.sy, st.sz, c, img, mv, G);
+        stage_geometry(st.sx, st.sy, st.sz, c, img, mv, 1.0, G);
         T mv4[4][3], uv[4][3], E[6];
         vertex3(st, 0, c, mv4);
         vertex3(st, 3, c, uv);
@@ -742,13 +749,30 @@ Cubic<T> cubic_of(const Material &m) {
 }
 }  // namespace
 
-void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode mode, const double *in, double *out,
-                           const double *b, const double *r, double *pout, const CGScalars &cg, int k, double tol,
-                           hipStream_t s) {
-    ElasticMatvecOp<double> op{in, out, b, r, pout, cg, k, static_cast<int>(mode), mv.n, tol * tol,
-                               cubic_of<double>(mat), {0}, {0.0}};
-    run_elem<double, 3, 3>(mv, op, s);
+// FP64 works in SI units.  FP32 works on the non-dimensional operator
+// A' = A / (len_scale * c11): coordinates divided by the mesh length scale and
+// stiffness divided by c11, which keeps every product inside FP32's normal range.
+template <class T>
+void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode mode, const T *in, T *out, const T *b,
+                           const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s) {
+    const bool nd = sizeof(T) == sizeof(float);
+    Material m2 = mat;
+    if (nd) {
+        m2.c12 = mat.c12 / mat.c11;
+        m2.c44 = mat.c44 / mat.c11;
+        m2.c11 = 1.0;
+    }
+    ElasticMatvecOp<T> op{in, out, b, r, pout, cg, k, static_cast<int>(mode), mv.n, tol * tol, cubic_of<T>(m2), {0},
+                          {0.0}, nd ? 1.0 / mv.len_scale : 1.0};
+    run_elem<T, 3, 3>(mv, op, s);
 }
+
+template void launch_elastic_matvec<double>(const MeshView &, const Material &, MatvecMode, const double *, double *,
+                                            const double *, const double *, double *, const CGScalars &, int, double,
+                                            hipStream_t);
+template void launch_elastic_matvec<float>(const MeshView &, const Material &, MatvecMode, const float *, float *,
+                                           const float *, const float *, float *, const CGScalars &, int, double,
+                                           hipStream_t);
 
 void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x, double *bb,
                         hipStream_t s) {
@@ -756,17 +780,29 @@ void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m
     run_elem<double, 3, 3>(mv, op, s);
 }
 
-void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const double *in,
-                      double *out, const double *b, const double *r, double *pout, const CGScalars &cg, int k,
-                      double tol, hipStream_t s) {
+// FP32: the non-dimensional operator A' = A / len_scale^3, i.e. eps' = eps / len_scale^2
+// on coordinates divided by len_scale.
+template <class T>
+void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
+                      const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s) {
+    const bool nd = sizeof(T) == sizeof(float);
+    const double sc = nd ? 1.0 / mv.len_scale : 1.0;
     const int md = static_cast<int>(mode);
     const double t2 = tol * tol;
+    const T e = static_cast<T>(eps * sc * sc), ms = static_cast<T>(mass);
     switch (nc) {
-        case 1: run_elem<double, 1, 1>(mv, GsMatvecOp<double, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, eps, mass, {0}, {0.0}}, s); break;
-        case 2: run_elem<double, 2, 2>(mv, GsMatvecOp<double, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, eps, mass, {0, 0}, {0.0, 0.0}}, s); break;
-        default: run_elem<double, 3, 3>(mv, GsMatvecOp<double, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, eps, mass, {0, 0, 0}, {0.0, 0.0, 0.0}}, s); break;
+        case 1: run_elem<T, 1, 1>(mv, GsMatvecOp<T, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc}, s); break;
+        case 2: run_elem<T, 2, 2>(mv, GsMatvecOp<T, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0}, {0.0, 0.0}, sc}, s); break;
+        default: run_elem<T, 3, 3>(mv, GsMatvecOp<T, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0}, {0.0, 0.0, 0.0}, sc}, s); break;
     }
 }
+
+template void launch_gs_matvec<double>(const MeshView &, int, double, double, MatvecMode, const double *, double *,
+                                       const double *, const double *, double *, const CGScalars &, int, double,
+                                       hipStream_t);
+template void launch_gs_matvec<float>(const MeshView &, int, double, double, MatvecMode, const float *, float *,
+                                      const float *, const float *, float *, const CGScalars &, int, double,
+                                      hipStream_t);
 
 void launch_field_rhs(const MeshView &mv, const Material &mat, const double *m, const double *u, const Derived *d,
                       double c, double *b, double *x0, double *ch2, double *bb, int bbstride, hipStream_t s) {

@@ -136,8 +136,8 @@ __device__ __forceinline__ bool read_live(const int32_t *done, int ns, bool (&li
 
 // After the residual matvec: b = 0 gives x = 0 with no iterations; a
 // residual already below tol ||b|| converges with no iterations.
-__global__ void __launch_bounds__(kThreads) k_cg_start(int n, int nc, int joint, double *x, CGScalars cg,
-                                                       double tol2) {
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_cg_start(int n, int nc, int joint, T *x, CGScalars cg, double tol2) {
     const int ns = joint ? 1 : nc;
     const double *const src[6] = {cg.bb_at(0), ns > 1 ? cg.bb_at(1) : nullptr, ns > 2 ? cg.bb_at(2) : nullptr,
                                   cg.rr_at(0, 0), ns > 1 ? cg.rr_at(1, 0) : nullptr, ns > 2 ? cg.rr_at(2, 0) : nullptr};
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_start(int n, int nc, int joint,
     }
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
         for (int c = 0; c < nc; ++c)
-            if (zero[set_of(c, joint)]) x[static_cast<size_t>(c) * n + i] = 0.0;
+            if (zero[set_of(c, joint)]) x[static_cast<size_t>(c) * n + i] = T(0);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         for (int s = 0; s < ns; ++s)
             if (conv[s]) {
@@ -163,8 +163,9 @@ __global__ void __launch_bounds__(kThreads) k_cg_start(int n, int nc, int joint,
 // alpha = rr[k] / pq[k]; x += alpha p; r -= alpha q; rr[k+1] += r.r.  The
 // convergence test of rr[k+1] and the next direction happen in the next
 // iteration's matvec.
-__global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint, double *x, double *r,
-                                                        const double *p, const double *q, CGScalars cg, int k) {
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint, T *x, T *r, const T *p, const T *q,
+                                                        CGScalars cg, int k) {
     const int ns = joint ? 1 : nc;
     bool live[3];
     if (!read_live(cg.done, ns, live)) return;
@@ -180,10 +181,11 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint
             const int s = set_of(c, joint);
             if (!live[s]) continue;
             const size_t o = static_cast<size_t>(c) * n + i;
-            x[o] += alpha[s] * p[o];
-            const double rv = r[o] - alpha[s] * q[o];
+            const T a = static_cast<T>(alpha[s]);
+            x[o] += a * p[o];
+            const T rv = r[o] - a * q[o];
             r[o] = rv;
-            part[s] += rv * rv;
+            part[s] += static_cast<double>(rv) * rv;
         }
     block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride());
 }
@@ -212,13 +214,76 @@ __global__ void __launch_bounds__(kThreads) k_cg_check(int nc, int joint, CGScal
         }
 }
 
-void launch_cg_start(int n, int nc, bool joint, double *x, const CGScalars &cg, double tol, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_start, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, x, cg, tol * tol);
+template <class T>
+void launch_cg_start(int n, int nc, bool joint, T *x, const CGScalars &cg, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_start<T>, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, x, cg, tol * tol);
 }
 
-void launch_cg_update(int n, int nc, bool joint, double *x, double *r, const double *p, const double *q,
-                      const CGScalars &cg, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, x, r, p, q, cg, k);
+template <class T>
+void launch_cg_update(int n, int nc, bool joint, T *x, T *r, const T *p, const T *q, const CGScalars &cg, int k,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, x, r, p, q, cg, k);
+}
+
+template void launch_cg_start<double>(int, int, bool, double *, const CGScalars &, double, hipStream_t);
+template void launch_cg_start<float>(int, int, bool, float *, const CGScalars &, double, hipStream_t);
+template void launch_cg_update<double>(int, int, bool, double *, double *, const double *, const double *,
+                                       const CGScalars &, int, hipStream_t);
+template void launch_cg_update<float>(int, int, bool, float *, float *, const float *, const float *,
+                                      const CGScalars &, int, hipStream_t);
+
+// ------------------------------------------------------ precision conversions
+
+__global__ void __launch_bounds__(kThreads) k_to_f32(int64_t n, const double *src, float *dst) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        dst[i] = static_cast<float>(src[i]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_add_f32(int64_t n, double *x, const float *d) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        x[i] += static_cast<double>(d[i]);
+}
+
+__global__ void __launch_bounds__(kThreads) k_fill_f32(float *p, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        p[i] = 0.0f;
+}
+
+// r32 = (float) (scale * r64) on nc components, and ||r32||^2 per scalar set
+// into slot 0 of the inner solve's r.r ring (the starting residual of the
+// inner CG).
+__global__ void __launch_bounds__(kThreads) k_to_f32_norms(int n, int nc, int joint, const double *src, double scale,
+                                                           float *dst, CGScalars cg) {
+    double part[3] = {0.0, 0.0, 0.0};
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+        for (int c = 0; c < nc; ++c) {
+            const size_t o = static_cast<size_t>(c) * n + i;
+            const float v = static_cast<float>(scale * src[o]);
+            dst[o] = v;
+            part[joint ? 0 : c] += static_cast<double>(v) * v;
+        }
+    block_atomic_add<3>(part, cg.rr_at(0, 0), cg.comp_stride());
+}
+
+void launch_to_f32_norms(int n, int nc, bool joint, const double *src, double scale, float *dst, const CGScalars &cg,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_to_f32_norms, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, src, scale, dst,
+                       cg);
+}
+
+void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3(node_grid(n)), dim3(kThreads), 0, s, n, src, dst);
+}
+
+void launch_add_f32(int64_t n, double *x, const float *d, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_add_f32, dim3(node_grid(n)), dim3(kThreads), 0, s, n, x, d);
+}
+
+void launch_fill_f32(float *p, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_f32, dim3(node_grid(n)), dim3(kThreads), 0, s, p, n);
 }
 
 void launch_cg_check(int nc, bool joint, const CGScalars &cg, int k, double tol, hipStream_t s) {

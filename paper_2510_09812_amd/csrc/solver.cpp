@@ -11,6 +11,7 @@
 // enqueues iterations in batches and reads the convergence flags of the
 // previous batch while the next one runs, so the device never waits for it.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "context.h"
@@ -31,33 +32,29 @@ void cg_prepare(gspm_ctx *c, int ns) {
 
 namespace {
 
-template <class Apply>
-CgResult cg_run(gspm_ctx *c, int nc, bool joint, double *x, const double *b, double tol, int maxit, SolveKind kind,
-                Apply apply) {
+// Batched CG iterations with device-side convergence.  iter(k) enqueues
+// iteration k (matvec with fused direction, then the x/r update) on the
+// scalar set `cg`.  Returns when every component of `cg` has converged (or
+// broken down), or after maxit iterations.
+template <class Iter>
+CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int maxit, double tol, SolveKind kind,
+                    Iter iter) {
     hipStream_t s = c->stream;
-    const int ns = joint ? 1 : nc, n = c->n;
+    const int ns = joint ? 1 : nc;
     CgResult res;
-    apply(MV_RESID, x, nullptr, b, c->d.r, nullptr, 0);
-    launch_cg_start(n, nc, joint, x, c->cg, tol, s);
-    double *P[2] = {c->d.p, c->d.p2};
-
-    const int cap = c->cg.ring - 2;
+    const int cap = cg.ring - 2;
     const int first = std::min(std::max(c->predict[kind] + 1, 2), cap);
     const int later = std::min(std::max(c->predict[kind] / 32, 4), std::min(cap, 32));
     int k = 0;
     auto enqueue = [&](int cnt) {
         const int k1 = std::min(k + cnt, maxit);
-        launch_zero_ring(c->cg, ns, k + 1, k1 + 1, k, k1, s);
-        for (int it = k; it < k1; ++it) {
-            double *pold = P[it & 1], *pnew = P[(it + 1) & 1];
-            apply(MV_ITER, pold, c->d.q, nullptr, c->d.r, pnew, it);
-            launch_cg_update(n, nc, joint, x, c->d.r, pnew, c->d.q, c->cg, it, s);
-        }
-        if (k1 == maxit) launch_cg_check(nc, joint, c->cg, maxit, tol, s);
+        launch_zero_ring(cg, ns, k + 1, k1 + 1, k, k1, s);
+        for (int it = k; it < k1; ++it) iter(it);
+        if (k1 == maxit) launch_cg_check(nc, joint, cg, maxit, tol, s);
         k = k1;
     };
     auto post = [&](int slot) {
-        hipMemcpyAsync(c->h_flags + 2 * kMaxComp * slot, c->d.cg_flags, sizeof(int32_t) * 2 * kMaxComp,
+        hipMemcpyAsync(c->h_flags + 2 * kMaxComp * slot, cg.done, sizeof(int32_t) * 2 * kMaxComp,
                        hipMemcpyDeviceToHost, s);
         hipEventRecord(c->ev[slot], s);
     };
@@ -127,29 +124,168 @@ void prof_end(gspm_ctx *c) {
     c->prof_used += 2;
 }
 
+void prof_drop_after(gspm_ctx *c, size_t first_pair, int iters) {
+    if (!c->profile) return;
+    for (size_t i = first_pair; i < c->prof_used / 2; ++i)
+        if (c->prof_iter[i] >= iters) c->prof_iter[i] = -1;
+}
+
+// Plain FP64 CG from the initial guess x (Sec. 2.5): residual, start test,
+// iterations.  resid() writes r = b - A x and rr[0]; iter(k) one iteration.
+template <class Resid, class Iter>
+CgResult cg_fp64(gspm_ctx *c, int nc, bool joint, double *x, double tol, int maxit, SolveKind kind, Resid resid,
+                 Iter iter) {
+    resid();
+    launch_cg_start<double>(c->n, nc, joint, x, c->cg, tol, c->stream);
+    return cg_iterate(c, c->cg, nc, joint, maxit, tol, kind, iter);
+}
+
+// Mixed form: FP64 iterative refinement around FP32 CG.  Each outer step
+// computes the true residual r = b - A x with the FP64 operator and stops
+// when ||r|| <= tol ||b|| for every component (the same criterion as the
+// plain path, on the true residual); otherwise an inner CG in FP32 vectors
+// and FP32 element arithmetic (FP64 dot products) reduces the residual of
+// A d = r by eta = max(tol ||b|| / (2 ||r||), kInnerFloor), and x += d.
+// `scale` maps the FP64 residual to the right-hand side of the FP32 inner
+// operator A' = scale A (the non-dimensional form the FP32 kernels use).
+template <class Resid, class Iter32>
+CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int maxit, SolveKind kind, double scale,
+                  Resid resid, Iter32 iter32) {
+    constexpr double kInnerFloor = 1e-5;
+    hipStream_t s = c->stream;
+    const int ns = joint ? 1 : nc, n = c->n;
+    const size_t n3 = 3 * static_cast<size_t>(n);
+    CgResult res;
+    int total[kMaxComp] = {0, 0, 0};
+    double *hs = c->h_mixed;   // pinned: rr[3][kShards] | bb[3][kShards] staging
+    for (int outer = 0;; ++outer) {
+        launch_zero_ring(c->cg, ns, 0, 1, 0, 0, s);
+        resid();
+        for (int q = 0; q < ns; ++q) {
+            hipMemcpyAsync(hs + q * kShards, c->cg.rr_at(q, 0), sizeof(double) * kShards, hipMemcpyDeviceToHost, s);
+            hipMemcpyAsync(hs + (3 + q) * kShards, c->cg.bb_at(q), sizeof(double) * kShards, hipMemcpyDeviceToHost, s);
+        }
+        int rc = hip_check(c, hipStreamSynchronize(s), "CG");
+        if (rc) {
+            res.status = rc;
+            return res;
+        }
+        double rr[kMaxComp] = {0, 0, 0}, bb[kMaxComp] = {0, 0, 0};
+        bool conv[kMaxComp] = {true, true, true}, all = true;
+        for (int q = 0; q < ns; ++q) {
+            for (int k = 0; k < kShards; ++k) {
+                rr[q] += hs[q * kShards + k];
+                bb[q] += hs[(3 + q) * kShards + k];
+            }
+            if (!std::isfinite(rr[q])) {
+                res.status = GSPM_E_NONFINITE;
+                c->err = "non-finite residual";
+                return res;
+            }
+            if (bb[q] == 0.0) {
+                for (int cc = 0; cc < nc; ++cc)
+                    if ((joint ? 0 : cc) == q) launch_fill(x + static_cast<size_t>(cc) * n, n, 0.0, s);
+            }
+            conv[q] = bb[q] == 0.0 || rr[q] <= tol * tol * bb[q];
+            all &= conv[q];
+        }
+        if (all) break;
+        int used = 0;
+        for (int q = 0; q < ns; ++q) used = std::max(used, total[q]);
+        if (used >= maxit) {
+            res.status = GSPM_E_NOCONV;
+            c->err = "CG did not converge within cg_maxit iterations";
+            break;
+        }
+        // inner FP32 solve: per-component stopping folded into bb_in = eta^2 rr
+        double *h_in = hs + 6 * kShards;   // bb_in[3][kShards] | rr0[3][kShards]
+        int32_t *h_fl = reinterpret_cast<int32_t *>(hs + 12 * kShards);
+        std::memset(h_in, 0, sizeof(double) * 6 * kShards);
+        for (int q = 0; q < kMaxComp; ++q) {
+            h_fl[q] = (q < ns && !conv[q]) ? 0 : 1;
+            h_fl[kMaxComp + q] = 0;
+        }
+        for (int q = 0; q < ns; ++q) {
+            if (conv[q]) continue;
+            const double eta = std::max(0.5 * tol * std::sqrt(bb[q] / rr[q]), kInnerFloor);
+            h_in[q * kShards] = eta * eta * rr[q] * scale * scale;
+        }
+        const CGScalars &ci = c->cg_in;
+        hipMemcpyAsync(ci.bb, h_in, sizeof(double) * kMaxComp * kShards, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(ci.done, h_fl, sizeof(int32_t) * 2 * kMaxComp, hipMemcpyHostToDevice, s);
+        launch_zero_ring(ci, ns, 0, 1, 0, 0, s);
+        launch_to_f32_norms(n, nc, joint, c->d.r, scale, c->d.r32, ci, s);
+        launch_fill_f32(c->d.x32, n3, s);
+        const int budget = maxit - used;
+        const size_t first_pair = c->prof_used / 2;
+        CgResult in = cg_iterate(c, ci, nc, joint, budget, 1.0, kind, iter32);
+        prof_drop_after(c, first_pair, std::max(in.iters[0], std::max(in.iters[1], in.iters[2])));
+        if (in.status == GSPM_E_NONFINITE || in.status == GSPM_E_DEVICE || in.status == GSPM_E_OOM) {
+            res.status = in.status;
+            return res;
+        }
+        for (int q = 0; q < ns; ++q)
+            if (!conv[q]) total[q] += in.iters[q];
+        launch_add_f32(static_cast<int64_t>(nc) * n, x, c->d.x32, s);
+        ++c->refinements;
+    }
+    for (int q = 0; q < ns; ++q) res.iters[q] = total[q];
+    return res;
+}
+
 }  // namespace
 
 CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int maxit, SolveKind kind) {
     const size_t first_pair = c->prof_used / 2;
-    CgResult r = cg_run(c, 3, true, x, b, tol, maxit, kind,
-                        [&](MatvecMode mode, const double *in, double *out, const double *bb, double *rr, double *p,
-                            int k) {
-                            const bool timed = mode == MV_ITER;
-                            if (timed) prof_begin(c, k);
-                            launch_elastic_matvec(c->mv, c->mat, mode, in, out, bb, rr, p, c->cg, k, tol, c->stream);
-                            if (timed) prof_end(c);
-                        });
-    if (c->profile)
-        for (size_t i = first_pair; i < c->prof_used / 2; ++i)
-            if (c->prof_iter[i] >= r.iters[0]) c->prof_iter[i] = -1;
+    hipStream_t s = c->stream;
+    auto resid = [&]() {
+        launch_elastic_matvec<double>(c->mv, c->mat, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
+    };
+    CgResult r;
+    if (c->precision == GSPM_MIXED) {
+        float *P[2] = {c->d.p32, c->d.p32b};
+        const double scale = 1.0 / (c->mv.len_scale * c->mat.c11);
+        r = cg_mixed(c, 3, true, x, tol, maxit, kind, scale, resid, [&](int k) {
+            prof_begin(c, k);
+            launch_elastic_matvec<float>(c->mv, c->mat, MV_ITER, P[k & 1], c->d.q32, nullptr, c->d.r32,
+                                         P[(k + 1) & 1], c->cg_in, k, 1.0, s);
+            prof_end(c);
+            launch_cg_update<float>(c->n, 3, true, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, c->cg_in, k, s);
+        });
+    } else {
+        double *P[2] = {c->d.p, c->d.p2};
+        r = cg_fp64(c, 3, true, x, tol, maxit, kind, resid, [&](int k) {
+            prof_begin(c, k);
+            launch_elastic_matvec<double>(c->mv, c->mat, MV_ITER, P[k & 1], c->d.q, nullptr, c->d.r, P[(k + 1) & 1],
+                                          c->cg, k, tol, s);
+            prof_end(c);
+            launch_cg_update<double>(c->n, 3, true, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
+        });
+        prof_drop_after(c, first_pair, r.iters[0]);
+    }
     return r;
 }
 
 CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit, SolveKind kind) {
-    return cg_run(c, nc, false, x, b, tol, maxit, kind,
-                  [&](MatvecMode mode, const double *in, double *out, const double *bb, double *r, double *p, int k) {
-                      launch_gs_matvec(c->mv, nc, eps, 1.0, mode, in, out, bb, r, p, c->cg, k, tol, c->stream);
-                  });
+    hipStream_t s = c->stream;
+    auto resid = [&]() {
+        launch_gs_matvec<double>(c->mv, nc, eps, 1.0, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
+    };
+    if (c->precision == GSPM_MIXED) {
+        float *P[2] = {c->d.p32, c->d.p32b};
+        const double ls = c->mv.len_scale, scale = 1.0 / (ls * ls * ls);
+        return cg_mixed(c, nc, false, x, tol, maxit, kind, scale, resid, [&](int k) {
+            launch_gs_matvec<float>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q32, nullptr, c->d.r32, P[(k + 1) & 1],
+                                    c->cg_in, k, 1.0, s);
+            launch_cg_update<float>(c->n, nc, false, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, c->cg_in, k, s);
+        });
+    }
+    double *P[2] = {c->d.p, c->d.p2};
+    return cg_fp64(c, nc, false, x, tol, maxit, kind, resid, [&](int k) {
+        launch_gs_matvec<double>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q, nullptr, c->d.r, P[(k + 1) & 1], c->cg,
+                                 k, tol, s);
+        launch_cg_update<double>(c->n, nc, false, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
+    });
 }
 
 namespace {
@@ -242,6 +378,7 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     const double lex2 = 2.0 * c->p.A / (c->p.mu0 * c->p.Ms * c->p.Ms);
     const double eps1 = lex2 * dtau, eps3 = c->p.alpha * eps1;
     c->prof_used = 0;
+    const int64_t ref0 = c->refinements;
     hipEventRecord(c->t0, c->stream);
     int rc = GSPM_OK;
     for (int step = 0; step < nsteps; ++step) {
@@ -259,6 +396,7 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     hipEventElapsedTime(&ms, c->t0, c->t1);
     st->elapsed_ms = ms;
     for (int q = 0; q < 8; ++q) st->gs_iters += st->gs_iters_stage[q];
+    st->refinements = c->refinements - ref0;
     if (c->profile) {
         double tot = 0.0;
         int64_t cnt = 0;

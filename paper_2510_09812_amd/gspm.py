@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "GSPM_OK", -1: "GSPM_E_ARG", -2: "GSPM_E_MESH", -3: "GSPM_E_S
 
 EXPORTS = ("gspm_create", "gspm_destroy", "gspm_upload_mesh", "gspm_set_params", "gspm_set_field",
            "gspm_get_field", "gspm_step", "gspm_energies", "gspm_averages", "gspm_apply", "gspm_solve",
-           "gspm_mesh_info", "gspm_demag_factors", "gspm_last_error")
+           "gspm_mesh_info", "gspm_demag_factors", "gspm_time_operator", "gspm_last_error")
 
 
 class GspmError(RuntimeError):
@@ -52,7 +52,7 @@ class gspm_step_stats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int32), ("failed_step", ctypes.c_int32), ("mech_iters", ctypes.c_int64),
                 ("gs_iters", ctypes.c_int64), ("gs_iters_stage", ctypes.c_int64 * 8), ("dm_avg", ctypes.c_double),
                 ("elapsed_ms", ctypes.c_double), ("matvec_ms", ctypes.c_double),
-                ("matvec_launches", ctypes.c_int64)]
+                ("matvec_launches", ctypes.c_int64), ("refinements", ctypes.c_int64)]
 
 
 _lib = None
@@ -86,6 +86,8 @@ def load() -> ctypes.CDLL:
                                    ctypes.POINTER(i64), dp]
     lib.gspm_mesh_info.restype = S
     lib.gspm_demag_factors.argtypes = [ctypes.c_double] * 3 + [dp]; lib.gspm_demag_factors.restype = S
+    lib.gspm_time_operator.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_int32, dp]
+    lib.gspm_time_operator.restype = S
     lib.gspm_last_error.argtypes = [P]; lib.gspm_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
@@ -174,7 +176,8 @@ def gspm_get_field(ctx, which: int, n_nodes: int) -> np.ndarray:
 def stats_dict(st: gspm_step_stats) -> dict:
     return dict(steps_done=st.steps_done, failed_step=st.failed_step, mech_iters=st.mech_iters,
                 gs_iters=st.gs_iters, gs_iters_stage=list(st.gs_iters_stage), dm_avg=st.dm_avg,
-                elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches)
+                elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches,
+                refinements=st.refinements)
 
 
 def gspm_step(ctx, dt: float, n_steps: int = 1) -> dict:
@@ -226,6 +229,13 @@ def gspm_mesh_info(ctx) -> dict:
     return dict(n_unique=a.value, n_tets=b.value, n_blocks=c.value, n_elem_copies=d.value, volume=float(v[0]))
 
 
+def gspm_time_operator(ctx, op: int, eps: float = 0.0, reps: int = 20) -> float:
+    """Mean duration [ms] of one device-resident launch of operator `op`."""
+    out = np.zeros(1)
+    _check(ctx, load().gspm_time_operator(ctx, op, eps, reps, _dp(out)))
+    return float(out[0])
+
+
 def gspm_demag_factors(a: float, b: float, c: float) -> np.ndarray:
     out = np.zeros(3)
     _check(None, load().gspm_demag_factors(a, b, c, _dp(out)))
@@ -272,6 +282,9 @@ class Simulation:
 
     def solve(self, op: int, b, x0=None, eps: float = 0.0, tol: float = 1e-8, maxit: int = 100000):
         return gspm_solve(self.ctx, op, b, x0, eps, tol, maxit)
+
+    def time_operator(self, op: int, eps: float = 0.0, reps: int = 20) -> float:
+        return gspm_time_operator(self.ctx, op, eps, reps)
 
     def mesh_info(self) -> dict:
         return gspm_mesh_info(self.ctx)
