@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GSPM node-steps/s at 1M nodes, mixed vs FP64 at 1e-6 rel err; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_elastic_matvec_cube100.json")
+WEIGHTS_FILE = os.path.join(ROOT, "paper_2510_09812_amd", "weights", "warm_start.f32")
 KERNEL_SOURCES = ["paper_2510_09812_amd/csrc/elem_kernels.hip", "paper_2510_09812_amd/csrc/device_common.h"]
 
 
@@ -105,7 +106,9 @@ def main() -> int:
     ap.add_argument("--no-profile", action="store_true", help="skip the per-launch matvec events")
     ap.add_argument("--block-nodes", type=int, default=0, help="nodes per owner block (0 = library default)")
     ap.add_argument("--precision", choices=("fp64", "mixed", "both"), default="both",
-                    help="paths to run; with both, `value` is the mixed path and the FP64 path is reported beside it")
+                    help="paths to run; with both, `value` is the mixed path (with the learned warm start when "
+                         "trained weights exist) and the other paths are reported beside it")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start path")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MB (HBM counter calibration)")
     args = ap.parse_args()
@@ -133,14 +136,24 @@ def main() -> int:
     print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
     case = w.CASES[args.workload]()
 
-    def run_path(precision: int) -> dict:
+    weights = None
+    if not args.no_learned and os.path.exists(WEIGHTS_FILE):
+        weights = np.fromfile(WEIGHTS_FILE, dtype=np.float32)
+        if weights.size != gspm.GSPM_MPNN_PARAMS:
+            weights = None
+
+    def run_path(precision: int, learned: bool = False) -> dict:
         t_up = time.perf_counter()
         sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, device=0, profile=not args.no_profile,
                               block_nodes=args.block_nodes, precision=precision)
         sim.set_m(case.m0)
+        if learned:
+            sim.mpnn_set_params(weights)
+            sim.set_warm_start(gspm.GSPM_WARM_LEARNED)
         info = sim.mesh_info()
         t_up = time.perf_counter() - t_up
-        print(f"[bench] precision {precision}: uploaded {info['n_unique']} nodes, {info['n_tets']} tets in "
+        tag = f"{'mixed' if precision else 'fp64'}{'+learned' if learned else ''}"
+        print(f"[bench] {tag}: uploaded {info['n_unique']} nodes, {info['n_tets']} tets in "
               f"{t_up:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
         if args.warmup:
             sim.step(case.dt, args.warmup)
@@ -149,10 +162,11 @@ def main() -> int:
         st = sim.step(case.dt, args.steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        print(f"[bench] precision {precision}: {args.steps} steps in {wall:.3f} s, mech iters {st['mech_iters']}, "
-              f"gs iters {st['gs_iters']}, refinements {st['refinements']}", file=sys.stderr, flush=True)
+        print(f"[bench] {tag}: {args.steps} steps in {wall:.3f} s, mech iters {st['mech_iters']}, "
+              f"gs iters {st['gs_iters']}, refinements {st['refinements']}, learned starts {st['learned_starts']}",
+              file=sys.stderr, flush=True)
         out = dict(info=info, st=st, wall=wall, value=info["n_unique"] * args.steps / wall, m=sim.get_m(),
-                   u=sim.get_u())
+                   u=sim.get_u(), tag=tag)
         sim.close()
         return out
 
@@ -161,38 +175,45 @@ def main() -> int:
         paths["fp64"] = run_path(gspm.GSPM_FP64)
     if args.precision in ("mixed", "both"):
         paths["mixed"] = run_path(gspm.GSPM_MIXED)
-    head = paths["mixed"] if "mixed" in paths else paths["fp64"]
-    head_name = "mixed" if "mixed" in paths else "fp64"
+        if weights is not None:
+            paths["mixed+learned"] = run_path(gspm.GSPM_MIXED, learned=True)
+    head_name = next(k for k in ("mixed+learned", "mixed", "fp64") if k in paths)
+    head = paths[head_name]
+    mixed = head_name.startswith("mixed")
     info, st, wall, value = head["info"], head["st"], head["wall"], head["value"]
     n, ne = info["n_unique"], info["n_tets"]
 
     roofline = None
     if st["matvec_launches"] > 0:
         avg_s = st["matvec_ms"] / st["matvec_launches"] * 1e-3
-        mb = matvec_bytes(n, ne, 4 if head_name == "mixed" else 8)
+        mb = matvec_bytes(n, ne, 4 if mixed else 8)
         achieved = mb / avg_s / 1e9
-        kname = "k_elem<float,3,3,ElasticMatvecOp>" if head_name == "mixed" else "k_elem<double,3,3,ElasticMatvecOp>"
+        kname = "k_elem<float,3,3,ElasticMatvecOp>" if mixed else "k_elem<double,3,3,ElasticMatvecOp>"
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(head_name),
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("mixed" if mixed else "fp64"),
                     "kernel": kname, "bytes_per_launch": mb,
                     "avg_launch_us": avg_s * 1e6, "launches": st["matvec_launches"]}
     mech_per_step = st["mech_iters"] / args.steps
     gs_per_step = st["gs_iters"] / args.steps
     b_step = step_bytes(n, ne, mech_per_step, gs_per_step)
-    compare = None
-    if "fp64" in paths and "mixed" in paths:
-        f, x = paths["fp64"], paths["mixed"]
-        um = lambda u: u - u.mean(axis=0)
-        compare = {"fp64_value": f["value"], "fp64_ms_per_step": f["wall"] / args.steps * 1e3,
-                   "speedup_vs_fp64": x["value"] / f["value"],
-                   "rel_err_m_vs_fp64": float(np.linalg.norm(x["m"] - f["m"]) / np.linalg.norm(f["m"])),
-                   "rel_err_u_vs_fp64": float(np.linalg.norm(um(x["u"]) - um(f["u"])) / np.linalg.norm(um(f["u"]))),
-                   "fp64_mech_iters_per_step": f["st"]["mech_iters"] / args.steps,
-                   "mixed_refinements_per_step": x["st"]["refinements"] / args.steps}
+    um = lambda u: u - u.mean(axis=0)
+    per_path = {}
+    for k, p in paths.items():
+        row = {"value": p["value"], "ms_per_step": p["wall"] / args.steps * 1e3,
+               "mech_iters_per_step": p["st"]["mech_iters"] / args.steps,
+               "gs_iters_per_step": p["st"]["gs_iters"] / args.steps,
+               "refinements_per_step": p["st"]["refinements"] / args.steps,
+               "learned_starts": p["st"]["learned_starts"]}
+        if "fp64" in paths and k != "fp64":
+            f = paths["fp64"]
+            row["speedup_vs_fp64"] = p["value"] / f["value"]
+            row["rel_err_m_vs_fp64"] = float(np.linalg.norm(p["m"] - f["m"]) / np.linalg.norm(f["m"]))
+            row["rel_err_u_vs_fp64"] = float(np.linalg.norm(um(p["u"]) - um(f["u"])) / np.linalg.norm(um(f["u"])))
+        per_path[k] = row
     out = {
         "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if head_name == "mixed" else "f64",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": case.name, "nodes": n, "tets": ne, "dt_s": case.dt, "cg_tol": case.cg_tol,
                    "path": head_name, "block_nodes": args.block_nodes or 256,
@@ -200,7 +221,7 @@ def main() -> int:
         "roofline": roofline,
         "step_roofline": {"bytes_per_node_step": b_step / n, "roofline_node_steps_per_s": HBM_PEAK_GBS * 1e9 / b_step * n,
                           "frac": value / (HBM_PEAK_GBS * 1e9 / b_step * n)},
-        "mixed_vs_fp64": compare,
+        "paths": per_path,
     }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

@@ -113,6 +113,8 @@ typedef struct {
     double matvec_ms;       /* profile mode: summed duration of the elastic matvec launches */
     int64_t matvec_launches;/* profile mode: number of elastic matvec launches timed */
     int64_t refinements;    /* GSPM_MIXED: outer FP64 residual evaluations that started an FP32 inner solve */
+    int64_t learned_starts; /* steps whose elastic solve started from the learned warm start */
+    double warm_scale;      /* Galerkin step length s of the last learned start (0 if none) */
 } gspm_step_stats;
 
 /* Create a context on opts->device (NULL opts: device 0, FP64, own stream).
@@ -186,6 +188,67 @@ gspm_status gspm_mesh_info(gspm_ctx *ctx, int64_t *n_unique, int64_t *n_tets, in
  * with the crystal axes pass diag(N) as gspm_params.Nd).  Host only: needs no
  * device and no context.  GSPM_E_ARG unless a, b, c are positive and finite. */
 gspm_status gspm_demag_factors(double a, double b, double c, double N[3]);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start of the elastic solve.
+ *
+ * The paper starts each elastic CG (Sec. 2.5, stopping rule of Sec. 3.1) from
+ * the previous step's displacement and names the elastic solve as the cost to
+ * reduce (Sec. 5.2); it describes no learned start.  These entry points add
+ * one: a message-passing network predicts the displacement increment d from
+ * the magnetisation increment m^n - m^{n-1}, and the solve starts from
+ * u^{n-1} + s d with the Galerkin step s = d.r0 / d.K d (r0 = b - K u^{n-1}),
+ * which never increases the K-norm error of the start.  CG then runs to the
+ * same tolerance, so the solution is that of the plain path within the CG
+ * tolerance.
+ *
+ * Network (hidden width 64, weights and stored activations BF16, FP32
+ * arithmetic, MFMA node GEMMs), on the directed edges (i, j) of the mesh
+ * (nodes sharing a tetrahedron):
+ *   x_i = [dm_i / s_m, m_i, tag_i], s_m = sqrt(sum w |dm|^2 / sum w),
+ *         tag_i = 1 on magnetic nodes (w = lumped magnetic volume)
+ *   h_i = SiLU(W0 x_i + b0)
+ *   3 layers: z_ij = Wa h_i + Wb h_j + We e_ij + c, e_ij = nearest-image
+ *         (x_j - x_i) / hbar, hbar = (6 V_cell / n_tets)^(1/3);
+ *         a_i = mean_j SiLU(z_ij); h_i <- h_i + Wu [h_i ; a_i] + bu
+ *   y_i = Wd h_i + bd;  d = lambda100 hbar s_m (y - y_pinned)
+ * Parameters: GSPM_MPNN_PARAMS floats, in this order, matrices row-major
+ * (out x in): W0[64][7] b0[64], 3 x (Wa[64][64] Wb[64][64] We[64][3] c[64]
+ * Wu[64][128] bu[64]), Wd[3][64] bd[3].
+ * ------------------------------------------------------------------------- */
+#define GSPM_MPNN_PARAMS 50819
+
+typedef enum { GSPM_WARM_PREVIOUS = 0, GSPM_WARM_LEARNED = 1 } gspm_warm_start;
+
+/* Choose the elastic start of gspm_step.  GSPM_WARM_LEARNED needs
+ * gspm_mpnn_set_params and takes effect from the second step after the last
+ * gspm_set_field(M) (it needs m^{n-1}). */
+gspm_status gspm_set_warm_start(gspm_ctx *ctx, int32_t mode);
+
+/* Load (or replace) the network parameters (count == GSPM_MPNN_PARAMS, all
+ * finite) and reset the optimiser moments.  The first call after a mesh
+ * upload builds the edge graph and allocates the network's device buffers. */
+gspm_status gspm_mpnn_set_params(gspm_ctx *ctx, const float *params, int64_t count);
+gspm_status gspm_mpnn_get_params(gspm_ctx *ctx, float *params, int64_t count);
+
+/* Network output y (n_nodes x 3, caller's order) for the inputs (m_prev, m)
+ * (n_nodes x 3 each); s_m (nullable) receives the increment scale. */
+gspm_status gspm_mpnn_forward(gspm_ctx *ctx, const double *m_prev, const double *m, int64_t n_nodes, double *y,
+                              double *s_m);
+
+/* One training step on one sample: forward, loss = mean over nodes and
+ * components of ((y - mean y) - (t - mean t))^2 with t = du / (lambda100 hbar
+ * s_m), backward, and (update != 0) one Adam step (beta1 0.9, beta2 0.999,
+ * eps 1e-8, learning rate lr).  du is the displacement increment
+ * u^n - u^{n-1} (n_nodes x 3).  loss and grad (GSPM_MPNN_PARAMS floats, the
+ * gradient before the update) are nullable.  Needs gspm_set_params. */
+gspm_status gspm_mpnn_train_step(gspm_ctx *ctx, const double *m_prev, const double *m, const double *du,
+                                 int64_t n_nodes, float lr, int32_t update, double *loss, float *grad);
+
+/* The learned start for the current state (M and U as set): forms the
+ * elastic right-hand side at m, evaluates the network at (m_prev, m) and
+ * writes u0 = u + s d (n_nodes x 3) and s (nullable).  Changes no field. */
+gspm_status gspm_mpnn_warm_start(gspm_ctx *ctx, const double *m_prev, int64_t n_nodes, double *u0, double *scale);
 
 /* Message of the last failure on this context (or of the last failed
  * gspm_create when ctx is NULL).  Never NULL. */

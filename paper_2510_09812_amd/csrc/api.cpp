@@ -45,6 +45,33 @@ bool all_finite(const double *v, size_t n) {
     return true;
 }
 
+int upload(gspm_ctx *c, double *dst, const std::vector<double> &h) {
+    int rc = hip_check(c, hipMemcpyAsync(dst, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream),
+                       "copy to device");
+    if (rc) return rc;
+    return hip_check(c, hipStreamSynchronize(c->stream), "copy to device");
+}
+
+int download(gspm_ctx *c, const double *src, std::vector<double> &h) {
+    int rc = hip_check(c, hipMemcpyAsync(h.data(), src, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream),
+                       "copy to host");
+    if (rc) return rc;
+    return hip_check(c, hipStreamSynchronize(c->stream), "copy to host");
+}
+
+// Homogeneous strain of an applied stress for cubic C:
+// normal part eps = (sigma - c12 tr(sigma) / (c11 + 2 c12)) / (c11 - c12),
+// shear eps_ij = sigma_ij / (2 c44).
+void cubic_compliance(const gspm_params &p, const double s[6], double e[6]) {
+    const double tr = s[0] + s[1] + s[2];
+    for (int k = 0; k < 3; ++k) e[k] = (s[k] - p.c12 * tr / (p.c11 + 2.0 * p.c12)) / (p.c11 - p.c12);
+    for (int k = 3; k < 6; ++k) e[k] = s[k] / (2.0 * p.c44);
+}
+
+}  // namespace
+
+namespace gspm {
+
 // Caller-order n0 x 3 -> internal component-major 3 x n.  The copies of a
 // periodic node must agree to 1e-12 relative.
 int gather_user(gspm_ctx *c, const double *v, std::vector<double> &out) {
@@ -79,32 +106,10 @@ void scatter_user(const gspm_ctx *c, const std::vector<double> &in, double *out)
     }
 }
 
-int upload(gspm_ctx *c, double *dst, const std::vector<double> &h) {
-    int rc = hip_check(c, hipMemcpyAsync(dst, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, c->stream),
-                       "copy to device");
-    if (rc) return rc;
-    return hip_check(c, hipStreamSynchronize(c->stream), "copy to device");
-}
-
-int download(gspm_ctx *c, const double *src, std::vector<double> &h) {
-    int rc = hip_check(c, hipMemcpyAsync(h.data(), src, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream),
-                       "copy to host");
-    if (rc) return rc;
-    return hip_check(c, hipStreamSynchronize(c->stream), "copy to host");
-}
-
-// Homogeneous strain of an applied stress for cubic C:
-// normal part eps = (sigma - c12 tr(sigma) / (c11 + 2 c12)) / (c11 - c12),
-// shear eps_ij = sigma_ij / (2 c44).
-void cubic_compliance(const gspm_params &p, const double s[6], double e[6]) {
-    const double tr = s[0] + s[1] + s[2];
-    for (int k = 0; k < 3; ++k) e[k] = (s[k] - p.c12 * tr / (p.c11 + 2.0 * p.c12)) / (p.c11 - p.c12);
-    for (int k = 3; k < 6; ++k) e[k] = s[k] / (2.0 * p.c44);
-}
-
-}  // namespace
+}  // namespace gspm
 
 gspm_ctx::~gspm_ctx() {
+    release_nn();
     release_mesh();
     for (hipEvent_t e : prof_ev) hipEventDestroy(e);
     for (hipEvent_t e : ev)
@@ -121,6 +126,7 @@ void gspm_ctx::release_mesh() {
     auto &b = d;
     dev_free(b.x); dev_free(b.lconn); dev_free(b.blk_ptr); dev_free(b.blk_nmag); dev_free(b.w);
     dev_free(b.halo_ptr); dev_free(b.halo_ids); dev_free(b.halo_lo); dev_free(b.img);
+    dev_free(b.seg_ent); dev_free(b.seg_mask); dev_free(b.seg_ptr); dev_free(b.seg_nmag);
     dev_free(b.m); dev_free(b.mnext); dev_free(b.u); dev_free(b.unext);
     dev_free(b.ms); dev_free(b.g); dev_free(b.gs); dev_free(b.b); dev_free(b.ch2);
     dev_free(b.r); dev_free(b.p); dev_free(b.p2); dev_free(b.q);
@@ -128,7 +134,21 @@ void gspm_ctx::release_mesh() {
     dev_free(b.cg_rr); dev_free(b.cg_pq); dev_free(b.cg_bb); dev_free(b.cg_flags);
     dev_free(b.r32); dev_free(b.p32); dev_free(b.p32b); dev_free(b.q32); dev_free(b.x32);
     dev_free(b.cgi_rr); dev_free(b.cgi_pq); dev_free(b.cgi_bb); dev_free(b.cgi_flags);
-    have_mesh = have_m = false;
+    dev_free(b.mprev);
+    have_mesh = have_m = have_prev = false;
+    tets_int.clear();
+    release_nn();
+}
+
+void gspm_ctx::release_nn() {
+    if (stream) hipStreamSynchronize(stream);
+    auto &q = nn;
+    dev_free(q.gptr); dev_free(q.gnbr); dev_free(q.master); dev_free(q.wr); dev_free(q.m1); dev_free(q.m2);
+    dev_free(q.grad); dev_free(q.mats); dev_free(q.acts); dev_free(q.y); dev_free(q.red); dev_free(q.dvec);
+    dev_free(q.du); dev_free(q.mp_in); dev_free(q.m_in); dev_free(q.s_dev);
+    dev_free(q.gh); dev_free(q.gha); dev_free(q.gab); dev_free(q.gy); dev_free(q.part);
+    q = gspm::MpnnState{};
+    warm_mode = GSPM_WARM_PREVIOUS;
 }
 
 extern "C" {
@@ -225,7 +245,12 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     rc = rc ? rc : dev_alloc(c, &d.halo_lo, hm.halo_lo.size());
     rc = rc ? rc : dev_alloc(c, &d.img, hm.img.size());
     rc = rc ? rc : dev_alloc(c, &d.w, n);
-    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q})
+    const size_t nseg = hm.seg_mask.size();
+    rc = rc ? rc : dev_alloc(c, &d.seg_ent, 2 * nseg);
+    rc = rc ? rc : dev_alloc(c, &d.seg_mask, nseg);
+    rc = rc ? rc : dev_alloc(c, &d.seg_ptr, hm.seg_ptr.size());
+    rc = rc ? rc : dev_alloc(c, &d.seg_nmag, hm.seg_nmag.size());
+    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.mprev})
         rc = rc ? rc : dev_alloc(c, p, n3);
     rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
     rc = rc ? rc : dev_alloc(c, &d.sums, 9 * kShards);
@@ -259,7 +284,14 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     hipMemcpyAsync(d.blk_ptr, hm.blk_ptr.data(), sizeof(int32_t) * hm.blk_ptr.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.blk_nmag, hm.blk_nmag.data(), sizeof(int32_t) * hm.blk_nmag.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.w, hm.w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
-    for (double *p : {d.m, d.mnext, d.u, d.unext, d.ms, d.g, d.gs, d.b, d.r, d.p, d.p2, d.q}) launch_fill(p, n3, 0.0, s);
+    if (nseg) {
+        hipMemcpyAsync(d.seg_ent, hm.seg_ent.data(), sizeof(uint16_t) * hm.seg_ent.size(), hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(d.seg_mask, hm.seg_mask.data(), sizeof(uint16_t) * nseg, hipMemcpyHostToDevice, s);
+    }
+    hipMemcpyAsync(d.seg_ptr, hm.seg_ptr.data(), sizeof(int32_t) * hm.seg_ptr.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.seg_nmag, hm.seg_nmag.data(), sizeof(int32_t) * hm.seg_nmag.size(), hipMemcpyHostToDevice, s);
+    for (double *p : {d.m, d.mnext, d.u, d.unext, d.ms, d.g, d.gs, d.b, d.r, d.p, d.p2, d.q, d.mprev})
+        launch_fill(p, n3, 0.0, s);
     if (c->precision == GSPM_MIXED)
         for (float *p : {d.r32, d.p32, d.p32b, d.q32, d.x32}) launch_fill_f32(p, n3, s);
     launch_fill(d.ch2, 2 * n, 0.0, s);
@@ -275,6 +307,8 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->nblk = hm.nblk;
     c->p0 = hm.p0;
     c->vc = hm.vc;
+    c->tets_int.resize(4 * static_cast<size_t>(n_tets));
+    for (size_t q = 0; q < c->tets_int.size(); ++q) c->tets_int[q] = hm.user2int[tets[q]];
     c->user2int = std::move(hm.user2int);
     c->w_host = hm.w;
     c->nmag = 0;
@@ -290,6 +324,10 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     mv.halo_ids = d.halo_ids;
     mv.halo_lo = d.halo_lo;
     mv.img = d.img;
+    mv.seg_ent = d.seg_ent;
+    mv.seg_mask = d.seg_mask;
+    mv.seg_ptr = d.seg_ptr;
+    mv.seg_nmag = d.seg_nmag;
     mv.nloc_max = hm.nloc_max;
     mv.w = d.w;
     mv.n = hm.n;
@@ -368,6 +406,7 @@ gspm_status gspm_set_field(gspm_ctx *c, gspm_field which, const double *v, int64
         rc = upload(c, c->d.m, h);
         if (rc) return static_cast<gspm_status>(rc);
         c->have_m = true;
+        c->have_prev = false;     // a new state has no history for the learned warm start
     } else {
         rc = upload(c, c->d.u, h);
         if (rc) return static_cast<gspm_status>(rc);

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "common.h"
+#include "mpnn.h"
 
 namespace gspm {
 
@@ -18,6 +19,9 @@ struct DeviceBuffers {
     int32_t *blk_ptr = nullptr, *blk_nmag = nullptr, *halo_ptr = nullptr, *halo_ids = nullptr, *halo_lo = nullptr;
     uint8_t *img = nullptr;
     double *w = nullptr;
+    uint4 *seg_ent = nullptr;
+    uint16_t *seg_mask = nullptr;
+    int32_t *seg_ptr = nullptr, *seg_nmag = nullptr;
     double *m = nullptr, *mnext = nullptr, *u = nullptr, *unext = nullptr;   // 3n each
     double *ms = nullptr, *g = nullptr, *gs = nullptr, *b = nullptr, *ch2 = nullptr;
     double *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr;
@@ -32,6 +36,25 @@ struct DeviceBuffers {
     float *r32 = nullptr, *p32 = nullptr, *p32b = nullptr, *q32 = nullptr, *x32 = nullptr;
     double *cgi_rr = nullptr, *cgi_pq = nullptr, *cgi_bb = nullptr;
     int32_t *cgi_flags = nullptr;
+    double *mprev = nullptr;      // 3n: m^{n-1} (previous committed state), for the learned warm start
+};
+
+// Device state of the learned warm start (allocated on first use).
+struct MpnnState {
+    bool ready = false, have_params = false;
+    int32_t *gptr = nullptr, *gnbr = nullptr;
+    int64_t nedges = 0;
+    float *master = nullptr, *wr = nullptr, *m1 = nullptr, *m2 = nullptr, *grad = nullptr;
+    uint16_t *mats = nullptr, *acts = nullptr;
+    float *y = nullptr;
+    double *red = nullptr, *dvec = nullptr, *du = nullptr, *mp_in = nullptr, *m_in = nullptr, *s_dev = nullptr;
+    float *gh = nullptr, *gha = nullptr, *gab = nullptr, *gy = nullptr, *part = nullptr;
+    int part_wgs = 0;
+    int64_t adam_t = 0;
+    mpnn::Graph graph{};
+    mpnn::Net net{};
+    mpnn::Acts A{};
+    mpnn::Grads G{};
 };
 
 }  // namespace gspm
@@ -70,8 +93,15 @@ struct gspm_ctx {
     gspm::DeriveArgs dargs{};
     int predict[gspm::SK_COUNT] = {32, 8, 8, 8, 16};
 
+    // learned warm start
+    gspm::MpnnState nn;
+    int warm_mode = GSPM_WARM_PREVIOUS;
+    bool have_prev = false;               // d.mprev holds the state before the last committed step
+    std::vector<int32_t> tets_int;        // 4 x ne internal node ids (graph construction)
+
     ~gspm_ctx();
     void release_mesh();
+    void release_nn();
 };
 
 namespace gspm {
@@ -87,5 +117,9 @@ CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int max
 CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit, SolveKind kind);
 int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st);
 int hip_check(gspm_ctx *c, hipError_t e, const char *what);
+int learned_start(gspm_ctx *c, const double *m, const double *mprev, double *x, const double *b);
+// Caller-order n0 x 3 <-> internal component-major 3 x n (api.cpp).
+int gather_user(gspm_ctx *c, const double *v, std::vector<double> &out);
+void scatter_user(const gspm_ctx *c, const std::vector<double> &in, double *out);
 
 }  // namespace gspm

@@ -123,6 +123,147 @@ static void run_elem(const MeshView &mv, const Op &op, hipStream_t s) {
     hipLaunchKernelGGL((k_elem<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
 }
 
+// The matrix-free operators walk tet strips instead of element lists.  Each
+// thread takes one strip segment and keeps a window of four vertices in
+// registers (coordinates, fields, and the contributions accumulated for
+// them); an entry loads one staged vertex into a slot, and when an element is
+// complete after an entry the window holds exactly its four vertices.  A
+// vertex's accumulated contribution goes to LDS once, when it leaves the
+// window, and only for owned vertices.  Along a strip each element loads one
+// vertex instead of four, which cuts the LDS reads and atomics that bound the
+// element-list form.  Staging and the per-node epilogue are the same.
+template <class T, int NC, int NF, class Op>
+__global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op op_in) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Op op = op_in;
+    if (!op.prepare()) return;                 // uniform: e.g. every CG component converged
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int nb = mv.nb, n0 = b * nb, cnt = min(nb, mv.n - n0);
+    const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg);
+    Staged<T, NC, NF> st;
+    st.nloc_max = mv.nloc_max;
+    st.acc = reinterpret_cast<T *>(smem_raw);
+    st.sx = st.acc + NC * nb;
+    st.sy = st.sx + mv.nloc_max;
+    st.sz = st.sy + mv.nloc_max;
+    st.f = st.sz + mv.nloc_max;
+    for (int i = threadIdx.x; i < NC * nb; i += kThreads) st.acc[i] = T(0);
+    const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0], sc = op.coord_scale;
+    for (int l = threadIdx.x; l < nloc; l += kThreads) {
+        if (l >= cnt && l < nb) continue;      // owned slots past the last node
+        const int g = l < nb ? n0 + l : mv.halo_ids[hbeg + l - nb];
+        st.sx[l] = static_cast<T>(sc * near_image(mv.x[g] - xr, mv.Lx, mv.iLx));
+        st.sy[l] = static_cast<T>(sc * near_image(mv.y[g] - yr, mv.Ly, mv.iLy));
+        st.sz[l] = static_cast<T>(sc * near_image(mv.z[g] - zr, mv.Lz, mv.iLz));
+        op.stage(st, l, g);
+    }
+    __syncthreads();
+    const bool img = mv.img[b] != 0;
+    const T Lx = static_cast<T>(mv.Lx * sc), Ly = static_cast<T>(mv.Ly * sc), Lz = static_cast<T>(mv.Lz * sc);
+    const T iLx = static_cast<T>(mv.iLx / sc), iLy = static_cast<T>(mv.iLy / sc), iLz = static_cast<T>(mv.iLz / sc);
+    const int s_beg = mv.seg_ptr[b];
+    const int s_end = Op::kMagneticOnly ? s_beg + mv.seg_nmag[b] : mv.seg_ptr[b + 1];
+    for (int sg = s_beg + static_cast<int>(threadIdx.x); sg < s_end; sg += kThreads) {
+        uint4 qa = mv.seg_ent[2 * sg], qb = mv.seg_ent[2 * sg + 1];
+        uint32_t msk = mv.seg_mask[sg];
+        int ids[4] = {-1, -1, -1, -1};
+        T x[4][3], f[4][NF], acc[4][NC];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) x[j][a] = T(0);
+#pragma unroll
+            for (int q = 0; q < NF; ++q) f[j][q] = T(0);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) acc[j][q] = T(0);
+        }
+        for (int k = 0; k < kSegEntries; ++k) {
+            const uint32_t e = qa.x & 0xFFFFu;
+            qa.x = (qa.x >> 16) | (qa.y << 16);
+            qa.y = (qa.y >> 16) | (qa.z << 16);
+            qa.z = (qa.z >> 16) | (qa.w << 16);
+            qa.w = (qa.w >> 16) | (qb.x << 16);
+            qb.x = (qb.x >> 16) | (qb.y << 16);
+            qb.y = (qb.y >> 16) | (qb.z << 16);
+            qb.z = (qb.z >> 16) | (qb.w << 16);
+            qb.w = (qb.w >> 16) | 0xFFFF0000u;
+            if (e == kSegEnd) break;
+            const int id = static_cast<int>(e & 0x3FFFu), sl = static_cast<int>(e >> 14);
+            // retire the vertex in slot sl
+            int oid = ids[0];
+            T oacc[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) oacc[q] = acc[0][q];
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                const bool hit = sl == j;
+                oid = hit ? ids[j] : oid;
+#pragma unroll
+                for (int q = 0; q < NC; ++q) oacc[q] = hit ? acc[j][q] : oacc[q];
+            }
+            if (oid >= 0 && oid < nb) {
+#pragma unroll
+                for (int q = 0; q < NC; ++q) atomicAdd(&st.acc[q * nb + oid], oacc[q]);
+            }
+            // load the new vertex into slot sl
+            const T nx = st.sx[id], ny = st.sy[id], nz = st.sz[id];
+            T nf[NF];
+#pragma unroll
+            for (int q = 0; q < NF; ++q) nf[q] = st.fld(q, id);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool hit = sl == j;
+                ids[j] = hit ? id : ids[j];
+                x[j][0] = hit ? nx : x[j][0];
+                x[j][1] = hit ? ny : x[j][1];
+                x[j][2] = hit ? nz : x[j][2];
+#pragma unroll
+                for (int q = 0; q < NF; ++q) f[j][q] = hit ? nf[q] : f[j][q];
+#pragma unroll
+                for (int q = 0; q < NC; ++q) acc[j][q] = hit ? T(0) : acc[j][q];
+            }
+            if (msk & 1u) {
+                T ed[3][3];
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) ed[kk][a] = x[kk + 1][a] - x[0][a];
+                if (img) {
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk) {
+                        ed[kk][0] = near_image(ed[kk][0], Lx, iLx);
+                        ed[kk][1] = near_image(ed[kk][1], Ly, iLy);
+                        ed[kk][2] = near_image(ed[kk][2], Lz, iLz);
+                    }
+                }
+                Geo<T> G;
+                tet_geometry_from_edges(ed, G);
+                T y[4][NC];
+                op.element_w(f, G, y);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) acc[j][q] += y[j][q];
+            }
+            msk >>= 1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (ids[j] >= 0 && ids[j] < nb) {
+#pragma unroll
+                for (int q = 0; q < NC; ++q) atomicAdd(&st.acc[q * nb + ids[j]], acc[j][q]);
+            }
+    }
+    __syncthreads();
+    op.finish(mv, st, n0, cnt);
+}
+
+template <class T, int NC, int NF, class Op>
+static void run_strip(const MeshView &mv, const Op &op, hipStream_t s) {
+    const size_t lds = sizeof(T) * (NC * static_cast<size_t>(mv.nb) + (3 + NF) * static_cast<size_t>(mv.nloc_max));
+    hipLaunchKernelGGL((k_strip<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
+}
+
 // --------------------------------------------------------- cubic material
 
 template <class T>
@@ -281,8 +422,14 @@ struct ElasticMatvecOp {
     template <int NF>
     __device__ __forceinline__ void element(const Staged<T, 3, NF> &st, const ushort4 c, const Geo<T> &G, bool,
                                             T (&y)[4][3]) const {
-        T v[4][3], e[6], s[6];
+        T v[4][3];
         vertex3(st, 0, c, v);
+        element_w(v, G, y);
+    }
+
+    // the element with its vertex values given (strip form)
+    __device__ __forceinline__ void element_w(const T (&v)[4][3], const Geo<T> &G, T (&y)[4][3]) const {
+        T e[6], s[6];
         sym_grad(v, G, e);
         C.stress(e, s);
 #pragma unroll
@@ -432,6 +579,16 @@ struct GsMatvecOp {
     __device__ __forceinline__ void element(const Staged<T, NC, NF> &st, const ushort4 c, const Geo<T> &G, bool,
                                             T (&y)[4][NC]) const {
         const int id[4] = {c.x, c.y, c.z, c.w};
+        T f[4][NC];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < NC; ++q) f[j][q] = live[q] ? st.fld(q, id[j]) : T(0);
+        element_w(f, G, y);
+    }
+
+    // the element with its vertex values given (strip form)
+    __device__ __forceinline__ void element_w(const T (&f)[4][NC], const Geo<T> &G, T (&y)[4][NC]) const {
         const T ev = eps * G.vol, mv20 = mass * G.vol * T(0.05);
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
@@ -442,7 +599,7 @@ struct GsMatvecOp {
             }
             T v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = st.fld(q, id[j]);
+            for (int j = 0; j < 4; ++j) v[j] = f[j][q];
             const T d1 = v[1] - v[0], d2 = v[2] - v[0], d3 = v[3] - v[0];
             T gp[3];
 #pragma unroll
@@ -764,7 +921,7 @@ void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode m
     }
     ElasticMatvecOp<T> op{in, out, b, r, pout, cg, k, static_cast<int>(mode), mv.n, tol * tol, cubic_of<T>(m2), {0},
                           {0.0}, nd ? 1.0 / mv.len_scale : 1.0};
-    run_elem<T, 3, 3>(mv, op, s);
+    run_strip<T, 3, 3>(mv, op, s);
 }
 
 template void launch_elastic_matvec<double>(const MeshView &, const Material &, MatvecMode, const double *, double *,
@@ -791,9 +948,9 @@ void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, Matve
     const double t2 = tol * tol;
     const T e = static_cast<T>(eps * sc * sc), ms = static_cast<T>(mass);
     switch (nc) {
-        case 1: run_elem<T, 1, 1>(mv, GsMatvecOp<T, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc}, s); break;
-        case 2: run_elem<T, 2, 2>(mv, GsMatvecOp<T, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0}, {0.0, 0.0}, sc}, s); break;
-        default: run_elem<T, 3, 3>(mv, GsMatvecOp<T, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0}, {0.0, 0.0, 0.0}, sc}, s); break;
+        case 1: run_strip<T, 1, 1>(mv, GsMatvecOp<T, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc}, s); break;
+        case 2: run_strip<T, 2, 2>(mv, GsMatvecOp<T, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0}, {0.0, 0.0}, sc}, s); break;
+        default: run_strip<T, 3, 3>(mv, GsMatvecOp<T, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0}, {0.0, 0.0, 0.0}, sc}, s); break;
     }
 }
 

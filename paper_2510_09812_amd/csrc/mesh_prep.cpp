@@ -54,6 +54,104 @@ int nodes_per_block(int32_t requested, int64_t n) {
     return 256;
 }
 
+// Orders one group of a block's elements (4 local vertex ids each) into
+// strips of face-adjacent tetrahedra (greedy walk that prefers the neighbour
+// with the fewest unvisited neighbours) and packs them into segments of
+// kSegEntries window updates.  Each element after the first of a strip
+// shares a face with its predecessor, so it costs one vertex load; at a strip
+// break the missing vertices are loaded before the element.  A new vertex
+// replaces a slot whose vertex the element does not use (empty first, else
+// the least recently used), so the four slots always hold exactly the
+// element's vertices when it is computed.
+static void build_strips(const uint16_t *lc, int32_t m, std::vector<uint16_t> &ent, std::vector<uint16_t> &mask) {
+    if (m <= 0) return;
+    std::vector<std::pair<uint64_t, int32_t>> faces;
+    faces.reserve(4 * static_cast<size_t>(m));
+    for (int32_t e = 0; e < m; ++e) {
+        uint16_t v[4] = {lc[4 * e], lc[4 * e + 1], lc[4 * e + 2], lc[4 * e + 3]};
+        std::sort(v, v + 4);
+        for (int skip = 0; skip < 4; ++skip) {
+            uint64_t key = 0;
+            for (int j = 0; j < 4; ++j)
+                if (j != skip) key = (key << 16) | v[j];
+            faces.emplace_back(key, e);
+        }
+    }
+    std::sort(faces.begin(), faces.end());
+    std::vector<int32_t> adj(4 * static_cast<size_t>(m), -1);
+    std::vector<int8_t> nadj(static_cast<size_t>(m), 0);
+    for (size_t i = 0; i + 1 < faces.size(); ++i)
+        if (faces[i].first == faces[i + 1].first) {
+            const int32_t a = faces[i].second, c = faces[i + 1].second;
+            if (nadj[a] < 4 && nadj[c] < 4) {
+                adj[4 * a + nadj[a]++] = c;
+                adj[4 * c + nadj[c]++] = a;
+            }
+        }
+    std::vector<uint8_t> vis(static_cast<size_t>(m), 0);
+    auto free_nbrs = [&](int32_t e) {
+        int k = 0;
+        for (int j = 0; j < nadj[e]; ++j) k += !vis[adj[4 * e + j]];
+        return k;
+    };
+    std::vector<int32_t> order;
+    order.reserve(static_cast<size_t>(m));
+    for (int32_t s0 = 0; s0 < m; ++s0) {
+        if (vis[s0]) continue;
+        int32_t cur = s0;
+        vis[cur] = 1;
+        order.push_back(cur);
+        for (;;) {
+            int32_t best = -1, bestk = 5;
+            for (int j = 0; j < nadj[cur]; ++j) {
+                const int32_t c = adj[4 * cur + j];
+                if (vis[c]) continue;
+                const int k = free_nbrs(c);
+                if (k < bestk) { bestk = k; best = c; }
+            }
+            if (best < 0) break;
+            cur = best;
+            vis[cur] = 1;
+            order.push_back(cur);
+        }
+    }
+    int32_t win[4] = {-1, -1, -1, -1};
+    int64_t lru[4] = {0, 0, 0, 0}, clock = 0;
+    int used = 0;
+    uint16_t seg[kSegEntries], msk = 0;
+    auto close = [&]() {
+        for (int k = used; k < kSegEntries; ++k) seg[k] = kSegEnd;
+        ent.insert(ent.end(), seg, seg + kSegEntries);
+        mask.push_back(msk);
+        for (int k = 0; k < 4; ++k) win[k] = -1;
+        used = 0;
+        msk = 0;
+    };
+    for (int32_t e : order) {
+        const int32_t v[4] = {lc[4 * e], lc[4 * e + 1], lc[4 * e + 2], lc[4 * e + 3]};
+        auto in_win = [&](int32_t x) { return x == win[0] || x == win[1] || x == win[2] || x == win[3]; };
+        auto in_elem = [&](int32_t x) { return x == v[0] || x == v[1] || x == v[2] || x == v[3]; };
+        int nnew = 0;
+        for (int j = 0; j < 4; ++j) nnew += !in_win(v[j]);
+        if (used + nnew > kSegEntries) close();
+        for (int j = 0; j < 4; ++j) {
+            if (in_win(v[j])) continue;
+            int slot = -1;
+            for (int k = 0; k < 4; ++k) {
+                if (in_elem(win[k])) continue;          // the element still needs this vertex
+                if (win[k] < 0) { slot = k; break; }    // an empty slot first
+                if (slot < 0 || lru[k] < lru[slot]) slot = k;
+            }
+            win[slot] = v[j];
+            seg[used++] = static_cast<uint16_t>(v[j] | (slot << 14));
+        }
+        msk |= static_cast<uint16_t>(1u << (used - 1));
+        for (int k = 0; k < 4; ++k)
+            if (in_elem(win[k])) lru[k] = ++clock;
+    }
+    if (used > 0) close();
+}
+
 int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets, const uint8_t *tags,
                  const double lo[3], const double hi[3], int32_t nb, HostMesh &M, std::string &err) {
     M = HostMesh();
@@ -192,6 +290,10 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
     M.halo_lo.resize(static_cast<size_t>(M.nblk));
     M.img.resize(static_cast<size_t>(M.nblk));
     M.lconn.resize(4 * static_cast<size_t>(M.ncopies));
+    M.seg_ptr.assign(static_cast<size_t>(M.nblk) + 1, 0);
+    M.seg_nmag.assign(static_cast<size_t>(M.nblk), 0);
+    M.seg_ent.clear();
+    M.seg_mask.clear();
     M.halo_ids.clear();
     M.nloc_max = 0;
     std::vector<int32_t> halo;
@@ -223,7 +325,7 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
         std::sort(halo.begin(), halo.end());
         halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
         const int32_t nloc = nb + static_cast<int32_t>(halo.size());
-        if (nloc > 65535) { err = "element block too large for 16-bit local indices"; return GSPM_E_ARG; }
+        if (nloc > 16383) { err = "element block too large for 14-bit local indices"; return GSPM_E_ARG; }
         M.nloc_max = std::max(M.nloc_max, nloc);
         M.halo_lo[b] = static_cast<int32_t>(std::lower_bound(halo.begin(), halo.end(), n0b) - halo.begin());
         M.halo_ptr[b + 1] = M.halo_ptr[b] + static_cast<int32_t>(halo.size());
@@ -249,8 +351,16 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
         for (int32_t v : halo) check(v);
         M.img[b] = far ? 1 : 0;
         M.halo_ids.insert(M.halo_ids.end(), halo.begin(), halo.end());
+        // strips: magnetic elements, then the rest
+        const uint16_t *lc = M.lconn.data() + 4 * cnt[b];
+        const int32_t nall = static_cast<int32_t>(cnt[b + 1] - cnt[b]);
+        M.seg_ptr[b] = static_cast<int32_t>(M.seg_mask.size());
+        build_strips(lc, nmag, M.seg_ent, M.seg_mask);
+        M.seg_nmag[b] = static_cast<int32_t>(M.seg_mask.size()) - M.seg_ptr[b];
+        build_strips(lc + 4 * static_cast<size_t>(nmag), nall - nmag, M.seg_ent, M.seg_mask);
     }
     M.blk_ptr[M.nblk] = static_cast<int32_t>(M.ncopies);
+    M.seg_ptr[M.nblk] = static_cast<int32_t>(M.seg_mask.size());
     M.nhalo = static_cast<int64_t>(M.halo_ids.size());
     return GSPM_OK;
 }

@@ -312,6 +312,10 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     hipMemcpyAsync(d.unext, d.u, bytes3, hipMemcpyDeviceToDevice, s);
     cg_prepare(c, 1);
     launch_elastic_rhs(c->mv, c->mat, d.m, d.b, d.unext, c->cg.bb, s);
+    if (c->warm_mode == GSPM_WARM_LEARNED && c->have_prev) {
+        learned_start(c, d.m, d.mprev, d.unext, d.b);
+        ++st->learned_starts;
+    }
     CgResult r = cg_elastic(c, d.unext, d.b, tol, maxit, SK_MECH);
     st->mech_iters += r.iters[0];
     if (r.status) return r.status;
@@ -364,8 +368,11 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     double dsum = 0.0;
     for (int k = 0; k < kShards; ++k) dsum += dmh[k];
     st->dm_avg = c->nmag > 0 ? dsum / c->nmag : 0.0;
+    // m^{n-1} <- m^n <- m^{n+1}: the old m buffer keeps the previous state
+    std::swap(d.mprev, d.m);
     std::swap(d.m, d.mnext);
     std::swap(d.u, d.unext);
+    c->have_prev = true;
     return GSPM_OK;
 }
 
@@ -397,6 +404,7 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     st->elapsed_ms = ms;
     for (int q = 0; q < 8; ++q) st->gs_iters += st->gs_iters_stage[q];
     st->refinements = c->refinements - ref0;
+    if (st->learned_starts > 0) hipMemcpy(&st->warm_scale, c->nn.s_dev, sizeof(double), hipMemcpyDeviceToHost);
     if (c->profile) {
         double tot = 0.0;
         int64_t cnt = 0;

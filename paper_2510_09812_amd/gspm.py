@@ -21,13 +21,17 @@ GSPM_FP64, GSPM_MIXED = 0, 1
 GSPM_FIELD_M, GSPM_FIELD_U = 0, 1
 GSPM_OP_LAPLACE, GSPM_OP_MASS, GSPM_OP_GS, GSPM_OP_ELASTIC = 0, 1, 2, 3
 GSPM_PERIODIC = 1
+GSPM_WARM_PREVIOUS, GSPM_WARM_LEARNED = 0, 1
+GSPM_MPNN_PARAMS = 50819
 
 STATUS_NAMES = {0: "GSPM_OK", -1: "GSPM_E_ARG", -2: "GSPM_E_MESH", -3: "GSPM_E_STATE", -4: "GSPM_E_DEVICE",
                 -5: "GSPM_E_NOCONV", -6: "GSPM_E_NONFINITE", -7: "GSPM_E_OOM"}
 
 EXPORTS = ("gspm_create", "gspm_destroy", "gspm_upload_mesh", "gspm_set_params", "gspm_set_field",
            "gspm_get_field", "gspm_step", "gspm_energies", "gspm_averages", "gspm_apply", "gspm_solve",
-           "gspm_mesh_info", "gspm_demag_factors", "gspm_time_operator", "gspm_last_error")
+           "gspm_mesh_info", "gspm_demag_factors", "gspm_time_operator", "gspm_last_error",
+           "gspm_set_warm_start", "gspm_mpnn_set_params", "gspm_mpnn_get_params", "gspm_mpnn_forward",
+           "gspm_mpnn_train_step", "gspm_mpnn_warm_start")
 
 
 class GspmError(RuntimeError):
@@ -52,7 +56,8 @@ class gspm_step_stats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int32), ("failed_step", ctypes.c_int32), ("mech_iters", ctypes.c_int64),
                 ("gs_iters", ctypes.c_int64), ("gs_iters_stage", ctypes.c_int64 * 8), ("dm_avg", ctypes.c_double),
                 ("elapsed_ms", ctypes.c_double), ("matvec_ms", ctypes.c_double),
-                ("matvec_launches", ctypes.c_int64), ("refinements", ctypes.c_int64)]
+                ("matvec_launches", ctypes.c_int64), ("refinements", ctypes.c_int64),
+                ("learned_starts", ctypes.c_int64), ("warm_scale", ctypes.c_double)]
 
 
 _lib = None
@@ -89,6 +94,14 @@ def load() -> ctypes.CDLL:
     lib.gspm_time_operator.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_int32, dp]
     lib.gspm_time_operator.restype = S
     lib.gspm_last_error.argtypes = [P]; lib.gspm_last_error.restype = ctypes.c_char_p
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.gspm_set_warm_start.argtypes = [P, ctypes.c_int32]; lib.gspm_set_warm_start.restype = S
+    lib.gspm_mpnn_set_params.argtypes = [P, fp, i64]; lib.gspm_mpnn_set_params.restype = S
+    lib.gspm_mpnn_get_params.argtypes = [P, fp, i64]; lib.gspm_mpnn_get_params.restype = S
+    lib.gspm_mpnn_forward.argtypes = [P, dp, dp, i64, dp, dp]; lib.gspm_mpnn_forward.restype = S
+    lib.gspm_mpnn_train_step.argtypes = [P, dp, dp, dp, i64, ctypes.c_float, ctypes.c_int32, dp, fp]
+    lib.gspm_mpnn_train_step.restype = S
+    lib.gspm_mpnn_warm_start.argtypes = [P, dp, i64, dp, dp]; lib.gspm_mpnn_warm_start.restype = S
     _lib = lib
     return lib
 
@@ -177,7 +190,7 @@ def stats_dict(st: gspm_step_stats) -> dict:
     return dict(steps_done=st.steps_done, failed_step=st.failed_step, mech_iters=st.mech_iters,
                 gs_iters=st.gs_iters, gs_iters_stage=list(st.gs_iters_stage), dm_avg=st.dm_avg,
                 elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches,
-                refinements=st.refinements)
+                refinements=st.refinements, learned_starts=st.learned_starts, warm_scale=st.warm_scale)
 
 
 def gspm_step(ctx, dt: float, n_steps: int = 1) -> dict:
@@ -242,6 +255,63 @@ def gspm_demag_factors(a: float, b: float, c: float) -> np.ndarray:
     return out
 
 
+def _fp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _f32(a, n) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.shape != (n,):
+        raise ValueError(f"expected {n} parameters, got shape {a.shape}")
+    return a
+
+
+def gspm_set_warm_start(ctx, mode: int) -> None:
+    _check(ctx, load().gspm_set_warm_start(ctx, mode))
+
+
+def gspm_mpnn_set_params(ctx, params) -> None:
+    p = _f32(params, GSPM_MPNN_PARAMS)
+    _check(ctx, load().gspm_mpnn_set_params(ctx, _fp(p), p.size))
+
+
+def gspm_mpnn_get_params(ctx) -> np.ndarray:
+    out = np.zeros(GSPM_MPNN_PARAMS, dtype=np.float32)
+    _check(ctx, load().gspm_mpnn_get_params(ctx, _fp(out), out.size))
+    return out
+
+
+def gspm_mpnn_forward(ctx, m_prev, m):
+    """Network output (n_nodes x 3) and the increment scale s_m."""
+    mp, mm = _f64(m_prev), _f64(m)
+    n = mm.shape[0]
+    y = np.zeros((n, 3))
+    sm = np.zeros(1)
+    _check(ctx, load().gspm_mpnn_forward(ctx, _dp(mp), _dp(mm), n, _dp(y), _dp(sm)))
+    return y, float(sm[0])
+
+
+def gspm_mpnn_train_step(ctx, m_prev, m, du, lr: float = 1e-3, update: bool = True, want_grad: bool = False):
+    """One training step; returns (loss, gradient or None)."""
+    mp, mm, dd = _f64(m_prev), _f64(m), _f64(du)
+    n = mm.shape[0]
+    loss = np.zeros(1)
+    g = np.zeros(GSPM_MPNN_PARAMS, dtype=np.float32) if want_grad else None
+    _check(ctx, load().gspm_mpnn_train_step(ctx, _dp(mp), _dp(mm), _dp(dd), n, lr, 1 if update else 0, _dp(loss),
+                                            _fp(g) if g is not None else None))
+    return float(loss[0]), g
+
+
+def gspm_mpnn_warm_start(ctx, m_prev):
+    """The learned elastic start for the current state: (u0, s)."""
+    mp = _f64(m_prev)
+    n = mp.shape[0]
+    u0 = np.zeros((n, 3))
+    sc = np.zeros(1)
+    _check(ctx, load().gspm_mpnn_warm_start(ctx, _dp(mp), n, _dp(u0), _dp(sc)))
+    return u0, float(sc[0])
+
+
 class Simulation:
     """Owns one context; thin convenience over the functions above."""
 
@@ -288,6 +358,24 @@ class Simulation:
 
     def mesh_info(self) -> dict:
         return gspm_mesh_info(self.ctx)
+
+    def set_warm_start(self, mode: int):
+        gspm_set_warm_start(self.ctx, mode)
+
+    def mpnn_set_params(self, params):
+        gspm_mpnn_set_params(self.ctx, params)
+
+    def mpnn_get_params(self) -> np.ndarray:
+        return gspm_mpnn_get_params(self.ctx)
+
+    def mpnn_forward(self, m_prev, m):
+        return gspm_mpnn_forward(self.ctx, m_prev, m)
+
+    def mpnn_train_step(self, m_prev, m, du, lr: float = 1e-3, update: bool = True, want_grad: bool = False):
+        return gspm_mpnn_train_step(self.ctx, m_prev, m, du, lr, update, want_grad)
+
+    def mpnn_warm_start(self, m_prev):
+        return gspm_mpnn_warm_start(self.ctx, m_prev)
 
     def close(self):
         gspm_destroy(getattr(self, "ctx", None))

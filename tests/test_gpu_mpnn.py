@@ -1,0 +1,199 @@
+"""Learned warm start on the GPU against the FP64 oracle network.
+
+Tolerances.  The GPU network stores weights and activations in BF16 (unit
+roundoff u = 2^-9 ~ 2e-3) and computes in FP32; the oracle runs the same
+network in FP64 with BF16 rounding emulated at the same storage points, so
+the two differ only where an FP32-vs-FP64 difference flips a BF16 rounding
+(one BF16 ulp, relative 2^-8).  Through 3 residual layers that bounds the
+output difference to a few ulps: relative 2-norm <= 1e-2 on y.  Gradients on
+the GPU also round the backward GEMM operands (gradients and activations) to
+BF16 once per product, the oracle's backward is exact: relative 2-norm <= 5e-2
+per parameter block and cosine >= 0.998 over the whole vector.  The Galerkin
+step s and the start u0 follow from d: 3e-2.  The step with the learned start
+solves to the same CG tolerance as the plain step, so the states agree like
+two FP64 runs with different starts: 1e-6 relative at CG tolerance 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as w
+from oracle import mpnn_oracle as N
+from paper_2510_09812_amd import gspm
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _init_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shp in N.param_shapes():
+        fan_in = shp[1] if len(shp) == 2 else 16
+        p[name] = rng.standard_normal(shp) * scale / np.sqrt(fan_in)
+    return N.pack(p).astype(np.float32)
+
+
+def _setup(n=9, seed=401, shuffle=True):
+    case = w.small_cube(n, seed=seed, L=8e-8, jitter=0.15, sphere=0.3, shuffle=shuffle)
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(case.params)
+    g = N.Graph.from_oracle(orc, case.mesh)
+    rng = np.random.default_rng(seed + 1)
+    m = case.m0
+    mp = case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)) * 0.05) + m
+    mp /= np.linalg.norm(mp, axis=1, keepdims=True)
+    return case, orc, g, m, mp
+
+
+def _unique(orc, v_user):
+    out = np.zeros((orc.n, 3))
+    out[orc.node_map()] = v_user
+    return out
+
+
+def _oracle_inputs(orc, m, mp):
+    wts = orc.lumped_weights()
+    mu, mpu = _unique(orc, m), _unique(orc, mp)
+    mu[wts <= 0] = 0.0
+    mpu[wts <= 0] = 0.0
+    return mu, mpu, wts
+
+
+def test_forward_matches_oracle():
+    case, orc, g, m, mp = _setup()
+    params = _init_params(11)
+    sim = gspm.Simulation(case.mesh, case.params)
+    sim.set_m(m)
+    sim.mpnn_set_params(params)
+    mu, mpu, wts = _oracle_inputs(orc, m, mp)
+    y_gpu, sm_gpu = sim.mpnn_forward(mpu[orc.node_map()], mu[orc.node_map()])
+    x, sm = N.features(mu, mpu, wts)
+    y_ref, _ = N.forward(N.unpack(params), x, g, bf16=True)
+    err = _rel(y_gpu, y_ref[orc.node_map()])
+    print(f"forward: rel err {err:.2e}, s_m gpu {sm_gpu:.6e} oracle {sm:.6e}", flush=True)
+    assert abs(sm_gpu - sm) <= 1e-12 * sm
+    assert err < 1e-2
+    assert np.array_equal(sim.mpnn_get_params(), params)
+    sim.close()
+
+
+def test_gradient_matches_oracle():
+    case, orc, g, m, mp = _setup(n=8, seed=402)
+    params = _init_params(12, scale=0.8)
+    sim = gspm.Simulation(case.mesh, case.params)
+    sim.mpnn_set_params(params)
+    mu, mpu, wts = _oracle_inputs(orc, m, mp)
+    rng = np.random.default_rng(5)
+    du = case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)) * 1e-12)
+    loss_gpu, grad_gpu = sim.mpnn_train_step(mpu[orc.node_map()], mu[orc.node_map()], du, update=False,
+                                             want_grad=True)
+    x, sm = N.features(mu, mpu, wts)
+    P = N.unpack(params)
+    y, cache = N.forward(P, x, g, bf16=True)
+    t = _unique(orc, du) / (case.params["lambda100"] * g.hbar * sm)
+    loss, gy = N.loss_and_grad_y(y, t)
+    G = N.pack(N.backward(P, cache, gy, g))
+    print(f"loss gpu {loss_gpu:.6e} oracle {loss:.6e}", flush=True)
+    assert abs(loss_gpu - loss) <= 2e-2 * loss
+    o = 0
+    for name, shp in N.param_shapes():
+        k = int(np.prod(shp))
+        eb = _rel(grad_gpu[o:o + k], G[o:o + k])
+        print(f"  {name:4s} rel err {eb:.2e}", flush=True)
+        assert eb < 5e-2, name
+        o += k
+    cos = grad_gpu @ G / (np.linalg.norm(grad_gpu) * np.linalg.norm(G))
+    assert cos > 0.998
+    sim.close()
+
+
+def test_adam_training_lowers_the_loss():
+    case, orc, g, m, mp = _setup(n=8, seed=403)
+    sim = gspm.Simulation(case.mesh, case.params)
+    sim.mpnn_set_params(_init_params(13, scale=0.5))
+    rng = np.random.default_rng(6)
+    du = case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)) * 1e-12)
+    losses = [sim.mpnn_train_step(mp, m, du, lr=3e-3)[0] for _ in range(40)]
+    print(f"loss {losses[0]:.4e} -> {losses[-1]:.4e}", flush=True)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.7 * losses[0]
+    # the update changed the master weights and the next forward uses them
+    p2 = sim.mpnn_get_params()
+    assert not np.array_equal(p2, _init_params(13, scale=0.5))
+    sim.close()
+
+
+def test_adam_first_step_matches_closed_form():
+    case, orc, g, m, mp = _setup(n=6, seed=404, shuffle=False)
+    params = _init_params(14)
+    sim = gspm.Simulation(case.mesh, case.params)
+    sim.mpnn_set_params(params)
+    rng = np.random.default_rng(7)
+    du = case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)) * 1e-12)
+    _, grad = sim.mpnn_train_step(mp, m, du, lr=1e-3, update=True, want_grad=True)
+    ref, _, _ = N.adam(params.astype(np.float64), grad.astype(np.float64), np.zeros(params.size),
+                       np.zeros(params.size), 1, 1e-3)
+    got = sim.mpnn_get_params()
+    assert np.allclose(got, ref, rtol=0, atol=2e-7 + 1e-6 * np.abs(ref))
+    sim.close()
+
+
+def test_learned_start_matches_oracle_galerkin_step():
+    case, orc, g, m, mp = _setup(n=9, seed=405)
+    params = _init_params(15, scale=0.6)
+    sim = gspm.Simulation(case.mesh, case.params)
+    sim.mpnn_set_params(params)
+    rng = np.random.default_rng(8)
+    u = case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)) * 1e-10)
+    sim.set_m(m)
+    sim.set_u(u)
+    u0, s = sim.mpnn_warm_start(mp)
+    # oracle: d from the emulated network, r0 = b - K u, s = d.r0 / d.K d
+    mu, mpu, wts = _oracle_inputs(orc, m, mp)
+    orc.set_m(m)
+    x, sm = N.features(mu, mpu, wts)
+    y, _ = N.forward(N.unpack(params), x, g, bf16=True)
+    p0 = orc.pinned_node()
+    d = N.increment(y, sm, case.params["lambda100"], g.hbar, p0)
+    uu = _unique(orc, u)
+    uu[p0] = 0.0
+    b = orc.elastic_rhs()
+    r0 = b - orc.apply(O.OP_ELASTIC, uu)
+    r0[p0] = 0.0
+    kd = orc.apply(O.OP_ELASTIC, d)
+    s_ref = N.galerkin_scale(d, r0, kd)
+    step_gpu = _unique(orc, u0) - uu
+    print(f"s gpu {s:.6e} oracle {s_ref:.6e}; step rel err {_rel(step_gpu, s_ref * d):.2e}", flush=True)
+    assert abs(s - s_ref) <= 3e-2 * abs(s_ref)
+    assert _rel(step_gpu, s_ref * d) < 3e-2
+    # the K-norm error of the learned start is not larger than the previous start's
+    xs, _ = orc.solve(O.OP_ELASTIC, b, uu, tol=1e-13)
+    en = lambda v: float(np.sum((xs - v) * orc.apply(O.OP_ELASTIC, xs - v)))
+    assert en(_unique(orc, u0)) <= en(uu) * (1 + 1e-9)
+    sim.close()
+
+
+def test_steps_with_learned_start_match_plain_steps():
+    case = w.small_cube(10, seed=406, L=9e-8, jitter=0.15, sphere=0.3)
+    params = dict(case.params)
+    params["cg_tol"] = 1e-10
+    out = {}
+    for mode in (gspm.GSPM_WARM_PREVIOUS, gspm.GSPM_WARM_LEARNED):
+        sim = gspm.Simulation(case.mesh, params, hext=(-0.3 * case.material["Ms"], 0.0, 0.0))
+        sim.mpnn_set_params(_init_params(16, scale=0.5))
+        sim.set_warm_start(mode)
+        sim.set_m(case.m0)
+        st = sim.step(2e-12, 5)
+        out[mode] = (sim.get_m(), sim.get_u(), st)
+        sim.close()
+    (m0, u0, s0), (m1, u1, s1) = out[gspm.GSPM_WARM_PREVIOUS], out[gspm.GSPM_WARM_LEARNED]
+    dm = lambda u: u - u.mean(axis=0)
+    print(f"plain mech {s0['mech_iters']} learned mech {s1['mech_iters']} starts {s1['learned_starts']} "
+          f"s {s1['warm_scale']:.3e} | m {_rel(m1, m0):.2e} u {_rel(dm(u1), dm(u0)):.2e}", flush=True)
+    assert s1["learned_starts"] == 4 and s0["learned_starts"] == 0
+    assert np.isfinite(s1["warm_scale"])
+    assert _rel(m1, m0) < 1e-6 and _rel(dm(u1), dm(u0)) < 1e-6

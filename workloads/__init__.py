@@ -7,8 +7,8 @@ inputs from it without sharing any of the method.
 """
 from .mesh import Mesh, kuhn_cube, random_rotation, tag_inclusions, Inclusion
 from .cases import (Case, MATERIAL_FEGA, cube10_random, cube47_sphere,
-                    cube100_ellipsoids, cube144_ellipsoids, small_cube, CASES)
+                    cube100_ellipsoids, cube144_ellipsoids, small_cube, warm_start_training, CASES)
 
 __all__ = ["Mesh", "kuhn_cube", "random_rotation", "tag_inclusions", "Inclusion",
            "Case", "MATERIAL_FEGA", "cube10_random", "cube47_sphere",
-           "cube100_ellipsoids", "cube144_ellipsoids", "small_cube", "CASES"]
+           "cube100_ellipsoids", "cube144_ellipsoids", "small_cube", "warm_start_training", "CASES"]

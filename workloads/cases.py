@@ -152,6 +152,19 @@ def small_cube(n: int, seed: int, L: float = 40e-9, jitter: float = 0.15, sphere
     return Case(f"small_cube{n}", mesh, dict(MATERIAL_FEGA), m0, np.asarray(hext, float), dt, steps)
 
 
+def warm_start_training(seed: int, n: int = 47, inclusions: int = 3) -> Case:
+    """Training family of the learned elastic warm start: n^3 nodes at the
+    1M-node cube's spacing (47^3 ~ 100k nodes), jittered, `inclusions` random
+    ellipsoids; m = [100] + 1% noise; H = -0.5 Ms [100]; dt = 10 ps."""
+    s_mesh, s_inc, s_m = np.random.SeedSequence(seed).spawn(3)
+    L = (n - 1) * H_C2
+    mesh = kuhn_cube(n, L, jitter=0.15, rng=np.random.default_rng(s_mesh))
+    tag_inclusions(mesh, _random_ellipsoids(np.random.default_rng(s_inc), inclusions, L))
+    m0 = _m_noisy_x(mesh, np.random.default_rng(s_m))
+    hext = np.array([-0.5 * MATERIAL_FEGA["Ms"], 0.0, 0.0])
+    return Case(f"warm_start_training{n}_s{seed}", mesh, dict(MATERIAL_FEGA), m0, hext, 10e-12, 60)
+
+
 CASES = {
     "cube10_random": cube10_random,
     "cube47_sphere": cube47_sphere,
