@@ -205,8 +205,8 @@ gspm_status gspm_demag_factors(double a, double b, double c, double N[3]);
  * Network (hidden width 64, weights and stored activations BF16, FP32
  * arithmetic, MFMA node GEMMs), on the directed edges (i, j) of the mesh
  * (nodes sharing a tetrahedron):
- *   x_i = [dm_i / s_m, m_i, tag_i], s_m = sqrt(sum w |dm|^2 / sum w),
- *         tag_i = 1 on magnetic nodes (w = lumped magnetic volume)
+ *   x_i = tag_i [dm_i / s_m, m_i, 1], s_m = sqrt(sum w |dm|^2 / sum w),
+ *         tag_i = 1 on magnetic nodes (w = lumped magnetic volume), else 0
  *   h_i = SiLU(W0 x_i + b0)
  *   3 layers: z_ij = Wa h_i + Wb h_j + We e_ij + c, e_ij = nearest-image
  *         (x_j - x_i) / hbar, hbar = (6 V_cell / n_tets)^(1/3);

@@ -10,9 +10,11 @@ The paper does not describe a learned warm start; the network is the reading
 this project takes for it (a message-passing net that predicts the elastic
 displacement increment from the magnetisation increment):
 
-  node input   x_i = [dm_i / s_m, m_i, tag_i]                     (7 values)
+  node input   x_i = tag_i [dm_i / s_m, m_i, 1]                  (7 values)
                s_m = sqrt(sum_i w_i |dm_i|^2 / sum_i w_i), dm = m^n - m^{n-1},
-               tag_i = 1 on magnetic nodes (w_i > 0), else 0
+               tag_i = 1 on magnetic nodes (w_i > 0), else 0 (m is zero on
+               the other nodes, so the mask only fixes what arbitrary inputs
+               give there)
   encoder      h_i = SiLU(W0 x_i + b0)                              (64)
   3 layers     z_ij = Wa h_i + Wb h_j + We e_ij + c   over directed mesh edges,
                e_ij = nearest-image (x_j - x_i) / hbar,  hbar = (6 mean V_e)^(1/3)
@@ -145,11 +147,12 @@ def features(m, m_prev, w):
     dm = np.asarray(m, np.float64) - np.asarray(m_prev, np.float64)
     w = np.asarray(w, np.float64)
     sm = np.sqrt(np.sum(w[:, None] * dm * dm) / np.sum(w))
+    tag = (w > 0).astype(np.float64)
     x = np.zeros((m.shape[0], F_IN))
     if sm > 0:
-        x[:, 0:3] = dm / sm
-    x[:, 3:6] = m
-    x[:, 6] = (w > 0).astype(np.float64)
+        x[:, 0:3] = tag[:, None] * dm / sm
+    x[:, 3:6] = tag[:, None] * np.asarray(m, np.float64)
+    x[:, 6] = tag
     return x, sm
 
 

@@ -31,10 +31,14 @@ namespace gspm {
 
 // ------------------------------------------------------------ the skeleton
 
-// LDS layout of an element pass: acc[NC][nb] | sx, sy, sz [nloc_max] | fields [NF][nloc_max]
+// LDS layout of an element pass: acc[NC][nb] (FP64) | sx, sy, sz [nloc_max] | fields [NF][nloc_max]
+// The owned-node accumulators are FP64 in both precisions: on gfx950 the
+// FP64 LDS add (ds_add_f64) is far cheaper than the FP32 one, and FP32
+// contributions lose nothing by being summed in FP64.
 template <class T, int NC, int NF>
 struct Staged {
-    T *acc, *sx, *sy, *sz, *f;
+    double *acc;
+    T *sx, *sy, *sz, *f;
     int nloc_max;
     __device__ __forceinline__ T &fld(int k, int l) const { return f[k * nloc_max + l]; }
 };
@@ -64,13 +68,13 @@ __device__ __forceinline__ void stage_geometry(const T *sx, const T *sy, const T
 }
 
 template <class T, int NC>
-__device__ __forceinline__ void scatter_owned(T *acc, int nb, const ushort4 c, const T (&y)[4][NC]) {
+__device__ __forceinline__ void scatter_owned(double *acc, int nb, const ushort4 c, const T (&y)[4][NC]) {
     const int v[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (v[j] < nb) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) atomicAdd(&acc[k * nb + v[j]], y[j][k]);
+            for (int k = 0; k < NC; ++k) atomicAdd(&acc[k * nb + v[j]], static_cast<double>(y[j][k]));
         }
     }
 }
@@ -85,12 +89,12 @@ __global__ void __launch_bounds__(kThreads) k_elem(const MeshView mv, const Op o
     const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg);
     Staged<T, NC, NF> st;
     st.nloc_max = mv.nloc_max;
-    st.acc = reinterpret_cast<T *>(smem_raw);
-    st.sx = st.acc + NC * nb;
+    st.acc = reinterpret_cast<double *>(smem_raw);
+    st.sx = reinterpret_cast<T *>(st.acc + NC * nb);
     st.sy = st.sx + mv.nloc_max;
     st.sz = st.sy + mv.nloc_max;
     st.f = st.sz + mv.nloc_max;
-    for (int i = threadIdx.x; i < NC * nb; i += kThreads) st.acc[i] = T(0);
+    for (int i = threadIdx.x; i < NC * nb; i += kThreads) st.acc[i] = 0.0;
     const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0], sc = op.coord_scale;
     for (int l = threadIdx.x; l < nloc; l += kThreads) {
         if (l >= cnt && l < nb) continue;      // owned slots past the last node
@@ -119,7 +123,7 @@ __global__ void __launch_bounds__(kThreads) k_elem(const MeshView mv, const Op o
 
 template <class T, int NC, int NF, class Op>
 static void run_elem(const MeshView &mv, const Op &op, hipStream_t s) {
-    const size_t lds = sizeof(T) * (NC * static_cast<size_t>(mv.nb) + (3 + NF) * static_cast<size_t>(mv.nloc_max));
+    const size_t lds = sizeof(double) * NC * static_cast<size_t>(mv.nb) + sizeof(T) * (3 + NF) * static_cast<size_t>(mv.nloc_max);
     hipLaunchKernelGGL((k_elem<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
 }
 
@@ -142,12 +146,12 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
     const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg);
     Staged<T, NC, NF> st;
     st.nloc_max = mv.nloc_max;
-    st.acc = reinterpret_cast<T *>(smem_raw);
-    st.sx = st.acc + NC * nb;
+    st.acc = reinterpret_cast<double *>(smem_raw);
+    st.sx = reinterpret_cast<T *>(st.acc + NC * nb);
     st.sy = st.sx + mv.nloc_max;
     st.sz = st.sy + mv.nloc_max;
     st.f = st.sz + mv.nloc_max;
-    for (int i = threadIdx.x; i < NC * nb; i += kThreads) st.acc[i] = T(0);
+    for (int i = threadIdx.x; i < NC * nb; i += kThreads) st.acc[i] = 0.0;
     const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0], sc = op.coord_scale;
     for (int l = threadIdx.x; l < nloc; l += kThreads) {
         if (l >= cnt && l < nb) continue;      // owned slots past the last node
@@ -203,7 +207,7 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
             }
             if (oid >= 0 && oid < nb) {
 #pragma unroll
-                for (int q = 0; q < NC; ++q) atomicAdd(&st.acc[q * nb + oid], oacc[q]);
+                for (int q = 0; q < NC; ++q) atomicAdd(&st.acc[q * nb + oid], static_cast<double>(oacc[q]));
             }
             // load the new vertex into slot sl
             const T nx = st.sx[id], ny = st.sy[id], nz = st.sz[id];
@@ -251,7 +255,7 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
         for (int j = 0; j < 4; ++j)
             if (ids[j] >= 0 && ids[j] < nb) {
 #pragma unroll
-                for (int q = 0; q < NC; ++q) atomicAdd(&st.acc[q * nb + ids[j]], acc[j][q]);
+                for (int q = 0; q < NC; ++q) atomicAdd(&st.acc[q * nb + ids[j]], static_cast<double>(acc[j][q]));
             }
     }
     __syncthreads();
@@ -260,7 +264,7 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
 
 template <class T, int NC, int NF, class Op>
 static void run_strip(const MeshView &mv, const Op &op, hipStream_t s) {
-    const size_t lds = sizeof(T) * (NC * static_cast<size_t>(mv.nb) + (3 + NF) * static_cast<size_t>(mv.nloc_max));
+    const size_t lds = sizeof(double) * NC * static_cast<size_t>(mv.nb) + sizeof(T) * (3 + NF) * static_cast<size_t>(mv.nloc_max);
     hipLaunchKernelGGL((k_strip<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
 }
 
@@ -819,8 +823,8 @@ __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Mat
     const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg), below = mv.halo_lo[b];
     Staged<T, 1, 6> st;
     st.nloc_max = mv.nloc_max;
-    st.acc = reinterpret_cast<T *>(smem_raw);
-    st.sx = st.acc + nb;
+    st.acc = reinterpret_cast<double *>(smem_raw);
+    st.sx = reinterpret_cast<T *>(st.acc + nb);
     st.sy = st.sx + mv.nloc_max;
     st.sz = st.sy + mv.nloc_max;
     st.f = st.sz + mv.nloc_max;

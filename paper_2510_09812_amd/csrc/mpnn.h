@@ -2,7 +2,7 @@
 // launchers of its kernels (mpnn.hip).
 //
 // Network (per node i of the periodic mesh graph, hidden width 64):
-//   x_i  = [dm_i / s_m, m_i, tag_i]                 dm = m^n - m^{n-1}
+//   x_i  = tag_i [dm_i / s_m, m_i, 1]               dm = m^n - m^{n-1}, tag = magnetic node
 //   h_i  = SiLU(W0 x_i + b0)
 //   3 x: z_ij = Wa h_i + Wb h_j + We e_ij + c,  a_i = mean_j SiLU(z_ij),
 //        h_i <- h_i + Wu [h_i ; a_i] + bu

@@ -249,16 +249,18 @@ __device__ __forceinline__ double dm_scale(const double *red) {
     return t[1] > 0.0 ? sqrt(t[0] / t[1]) : 0.0;
 }
 
-// The 7 node inputs, rounded to BF16 as the network stores them.
+// The 7 node inputs tag [dm / s_m, m, 1] (zero off the magnetic nodes),
+// rounded to BF16 as the network stores them.
 __device__ __forceinline__ void node_features(int n, int i, const double *w, const double *m, const double *mp,
                                               double ism, float (&x)[kIn]) {
+    const bool mag = w[i] > 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double mc = m[static_cast<size_t>(c) * n + i];
-        x[c] = round_bf(static_cast<float>((mc - mp[static_cast<size_t>(c) * n + i]) * ism));
-        x[3 + c] = round_bf(static_cast<float>(mc));
+        x[c] = mag ? round_bf(static_cast<float>((mc - mp[static_cast<size_t>(c) * n + i]) * ism)) : 0.0f;
+        x[3 + c] = mag ? round_bf(static_cast<float>(mc)) : 0.0f;
     }
-    x[6] = w[i] > 0.0 ? 1.0f : 0.0f;
+    x[6] = mag ? 1.0f : 0.0f;
 }
 
 // h0 = SiLU(W0 x + b0); one wave per node, lane = channel.

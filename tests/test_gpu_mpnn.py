@@ -100,9 +100,14 @@ def test_gradient_matches_oracle():
     print(f"loss gpu {loss_gpu:.6e} oracle {loss:.6e}", flush=True)
     assert abs(loss_gpu - loss) <= 2e-2 * loss
     o = 0
+    gscale = np.linalg.norm(G) / np.sqrt(G.size)
     for name, shp in N.param_shapes():
         k = int(np.prod(shp))
-        eb = _rel(grad_gpu[o:o + k], G[o:o + k])
+        # blocks whose exact gradient vanishes (the last biases: the loss
+        # gradient is mean-removed, so its node sum is zero) are held to the
+        # rms gradient entry instead of their own norm
+        den = max(np.linalg.norm(G[o:o + k]), 1e-2 * gscale * np.sqrt(k))
+        eb = np.linalg.norm(grad_gpu[o:o + k] - G[o:o + k]) / den
         print(f"  {name:4s} rel err {eb:.2e}", flush=True)
         assert eb < 5e-2, name
         o += k
@@ -115,12 +120,15 @@ def test_adam_training_lowers_the_loss():
     case, orc, g, m, mp = _setup(n=8, seed=403)
     sim = gspm.Simulation(case.mesh, case.params)
     sim.mpnn_set_params(_init_params(13, scale=0.5))
-    rng = np.random.default_rng(6)
-    du = case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)) * 1e-12)
-    losses = [sim.mpnn_train_step(mp, m, du, lr=3e-3)[0] for _ in range(40)]
+    # a learnable target: the normalised increment equals the dm input
+    mu, mpu, wts = _oracle_inputs(orc, m, mp)
+    x, sm = N.features(mu, mpu, wts)
+    du = (case.params["lambda100"] * g.hbar * sm * x[:, 0:3])[orc.node_map()]
+    mp_u, m_u = mpu[orc.node_map()], mu[orc.node_map()]
+    losses = [sim.mpnn_train_step(mp_u, m_u, du, lr=3e-3)[0] for _ in range(60)]
     print(f"loss {losses[0]:.4e} -> {losses[-1]:.4e}", flush=True)
     assert np.all(np.isfinite(losses))
-    assert losses[-1] < 0.7 * losses[0]
+    assert losses[-1] < 0.3 * losses[0]
     # the update changed the master weights and the next forward uses them
     p2 = sim.mpnn_get_params()
     assert not np.array_equal(p2, _init_params(13, scale=0.5))

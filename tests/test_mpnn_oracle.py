@@ -64,9 +64,11 @@ def test_features_scale_and_tag():
     m = np.zeros((g.n, 3)); m[:, 0] = 1.0
     v = np.array([0.003, -0.004, 0.0])
     x, sm = N.features(m, m - v, wts)
+    mag = wts > 0
     assert np.isclose(sm, 0.005)
-    assert np.allclose(x[:, 0:3], v / 0.005)
-    assert np.array_equal(x[:, 6], (wts > 0).astype(float))
+    assert np.allclose(x[mag, 0:3], v / 0.005) and np.allclose(x[mag, 3:6], m[mag])
+    assert np.array_equal(x[:, 6], mag.astype(float))
+    assert (~mag).any() and np.all(x[~mag] == 0.0)          # inputs vanish off the magnetic nodes
     x0, sm0 = N.features(m, m, wts)
     assert sm0 == 0 and np.all(x0[:, 0:3] == 0)
 
