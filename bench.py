@@ -142,17 +142,17 @@ def main() -> int:
         if weights.size != gspm.GSPM_MPNN_PARAMS:
             weights = None
 
-    def run_path(precision: int, learned: bool = False) -> dict:
+    def run_path(precision: int, warm: int = 0) -> dict:
         t_up = time.perf_counter()
         sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, device=0, profile=not args.no_profile,
                               block_nodes=args.block_nodes, precision=precision)
         sim.set_m(case.m0)
-        if learned:
+        if warm == gspm.GSPM_WARM_LEARNED:
             sim.mpnn_set_params(weights)
-            sim.set_warm_start(gspm.GSPM_WARM_LEARNED)
+        sim.set_warm_start(warm)
         info = sim.mesh_info()
         t_up = time.perf_counter() - t_up
-        tag = f"{'mixed' if precision else 'fp64'}{'+learned' if learned else ''}"
+        tag = f"{'mixed' if precision else 'fp64'}" + {0: "", 1: "+learned", 2: "+extrapolated"}[warm]
         print(f"[bench] {tag}: uploaded {info['n_unique']} nodes, {info['n_tets']} tets in "
               f"{t_up:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
         if args.warmup:
@@ -163,7 +163,8 @@ def main() -> int:
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         print(f"[bench] {tag}: {args.steps} steps in {wall:.3f} s, mech iters {st['mech_iters']}, "
-              f"gs iters {st['gs_iters']}, refinements {st['refinements']}, learned starts {st['learned_starts']}",
+              f"gs iters {st['gs_iters']}, refinements {st['refinements']}, learned starts {st['learned_starts']}, "
+              f"Galerkin starts {st['galerkin_starts']}, last coefficients {st['warm_coef']}",
               file=sys.stderr, flush=True)
         out = dict(info=info, st=st, wall=wall, value=info["n_unique"] * args.steps / wall, m=sim.get_m(),
                    u=sim.get_u(), tag=tag)
@@ -175,8 +176,10 @@ def main() -> int:
         paths["fp64"] = run_path(gspm.GSPM_FP64)
     if args.precision in ("mixed", "both"):
         paths["mixed"] = run_path(gspm.GSPM_MIXED)
+        if not args.no_learned:
+            paths["mixed+extrapolated"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_EXTRAPOLATE)
         if weights is not None:
-            paths["mixed+learned"] = run_path(gspm.GSPM_MIXED, learned=True)
+            paths["mixed+learned"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_LEARNED)
     head_name = next(k for k in ("mixed+learned", "mixed", "fp64") if k in paths)
     head = paths[head_name]
     mixed = head_name.startswith("mixed")
@@ -188,7 +191,7 @@ def main() -> int:
         avg_s = st["matvec_ms"] / st["matvec_launches"] * 1e-3
         mb = matvec_bytes(n, ne, 4 if mixed else 8)
         achieved = mb / avg_s / 1e9
-        kname = "k_elem<float,3,3,ElasticMatvecOp>" if mixed else "k_elem<double,3,3,ElasticMatvecOp>"
+        kname = "k_strip<float,3,3,ElasticMatvecOp>" if mixed else "k_strip<double,3,3,ElasticMatvecOp>"
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("mixed" if mixed else "fp64"),
                     "kernel": kname, "bytes_per_launch": mb,
@@ -203,7 +206,7 @@ def main() -> int:
                "mech_iters_per_step": p["st"]["mech_iters"] / args.steps,
                "gs_iters_per_step": p["st"]["gs_iters"] / args.steps,
                "refinements_per_step": p["st"]["refinements"] / args.steps,
-               "learned_starts": p["st"]["learned_starts"]}
+               "learned_starts": p["st"]["learned_starts"], "galerkin_starts": p["st"]["galerkin_starts"]}
         if "fp64" in paths and k != "fp64":
             f = paths["fp64"]
             row["speedup_vs_fp64"] = p["value"] / f["value"]

@@ -113,8 +113,10 @@ typedef struct {
     double matvec_ms;       /* profile mode: summed duration of the elastic matvec launches */
     int64_t matvec_launches;/* profile mode: number of elastic matvec launches timed */
     int64_t refinements;    /* GSPM_MIXED: outer FP64 residual evaluations that started an FP32 inner solve */
-    int64_t learned_starts; /* steps whose elastic solve started from the learned warm start */
-    double warm_scale;      /* Galerkin step length s of the last learned start (0 if none) */
+    int64_t learned_starts; /* steps whose elastic start used the network's increment */
+    int64_t galerkin_starts;/* steps whose elastic start was a Galerkin step (learned or extrapolated) */
+    double warm_coef[2];    /* last Galerkin start: coefficients of the network increment and of the
+                               previous displacement increment (0 if unused) */
 } gspm_step_stats;
 
 /* Create a context on opts->device (NULL opts: device 0, FP64, own stream).
@@ -196,11 +198,14 @@ gspm_status gspm_demag_factors(double a, double b, double c, double N[3]);
  * the previous step's displacement and names the elastic solve as the cost to
  * reduce (Sec. 5.2); it describes no learned start.  These entry points add
  * one: a message-passing network predicts the displacement increment d from
- * the magnetisation increment m^n - m^{n-1}, and the solve starts from
- * u^{n-1} + s d with the Galerkin step s = d.r0 / d.K d (r0 = b - K u^{n-1}),
- * which never increases the K-norm error of the start.  CG then runs to the
- * same tolerance, so the solution is that of the plain path within the CG
- * tolerance.
+ * the magnetisation increment m^n - m^{n-1}.  With e = u^{n-1} - u^{n-2} the
+ * previous displacement increment (the long-wavelength response a local
+ * network cannot see), the solve starts from u^{n-1} + a d + c e with (a, c)
+ * the Galerkin coefficients on span{d, e}:
+ *   [[d.Kd, d.Ke], [e.Kd, e.Ke]] (a, c) = (d.r0, e.r0),  r0 = b - K u^{n-1},
+ * which never increases the K-norm error of the start (nearly parallel d, e:
+ * the better single-direction step).  CG then runs to the same tolerance, so
+ * the solution is that of the plain path within the CG tolerance.
  *
  * Network (hidden width 64, weights and stored activations BF16, FP32
  * arithmetic, MFMA node GEMMs), on the directed edges (i, j) of the mesh
@@ -218,11 +223,17 @@ gspm_status gspm_demag_factors(double a, double b, double c, double N[3]);
  * ------------------------------------------------------------------------- */
 #define GSPM_MPNN_PARAMS 50819
 
-typedef enum { GSPM_WARM_PREVIOUS = 0, GSPM_WARM_LEARNED = 1 } gspm_warm_start;
+typedef enum {
+    GSPM_WARM_PREVIOUS = 0,     /* u^{n-1} (the paper's start) */
+    GSPM_WARM_LEARNED = 1,      /* u^{n-1} + a d + c e: network increment and previous increment */
+    GSPM_WARM_EXTRAPOLATE = 2   /* u^{n-1} + c e: previous increment only (no network) */
+} gspm_warm_start;
 
 /* Choose the elastic start of gspm_step.  GSPM_WARM_LEARNED needs
- * gspm_mpnn_set_params and takes effect from the second step after the last
- * gspm_set_field(M) (it needs m^{n-1}). */
+ * gspm_mpnn_set_params.  The network term needs m^{n-1} (from the second
+ * step after gspm_set_field(M)); the increment term needs u^{n-2} (from the
+ * third step after the last gspm_set_field); before that the missing term is
+ * left out. */
 gspm_status gspm_set_warm_start(gspm_ctx *ctx, int32_t mode);
 
 /* Load (or replace) the network parameters (count == GSPM_MPNN_PARAMS, all
@@ -247,8 +258,10 @@ gspm_status gspm_mpnn_train_step(gspm_ctx *ctx, const double *m_prev, const doub
 
 /* The learned start for the current state (M and U as set): forms the
  * elastic right-hand side at m, evaluates the network at (m_prev, m) and
- * writes u0 = u + s d (n_nodes x 3) and s (nullable).  Changes no field. */
-gspm_status gspm_mpnn_warm_start(gspm_ctx *ctx, const double *m_prev, int64_t n_nodes, double *u0, double *scale);
+ * writes u0 = u + a d + c e (n_nodes x 3) with e = u - u_prev when u_prev is
+ * given (else c = 0), and coef = (a, c) (nullable).  Changes no field. */
+gspm_status gspm_mpnn_warm_start(gspm_ctx *ctx, const double *m_prev, const double *u_prev, int64_t n_nodes,
+                                 double *u0, double coef[2]);
 
 /* Message of the last failure on this context (or of the last failed
  * gspm_create when ctx is NULL).  Never NULL. */

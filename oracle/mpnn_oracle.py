@@ -24,7 +24,9 @@ displacement increment from the magnetisation increment):
   increment    d = (lambda100 hbar s_m) (y - y_p0)   (zero at the pinned node)
   start        u0 = u_prev + s d,  s = d.r0 / d.K d,  r0 = b - K u_prev
                (the Galerkin step along d: the K-norm error of u0 is never
-               larger than that of u_prev)
+               larger than that of u_prev); with the previous increment
+               e = u_prev - u_prev2 also available, u0 = u_prev + a d + c e
+               with (a, c) the Galerkin solution on span{d, e}
 
 Training minimises the mean squared difference between the mean-removed
 network output and the mean-removed normalised target
@@ -234,6 +236,24 @@ def galerkin_scale(d, r0, Kd):
     """Step length along d minimising the K-norm error: s = d.r0 / d.Kd."""
     den = float(np.sum(d * Kd))
     return float(np.sum(d * r0)) / den if den > 0 else 0.0
+
+
+def galerkin2(d, e, r0, Kd, Ke):
+    """Coefficients (a, c) minimising the K-norm error of u_prev + a d + c e:
+    the 2 x 2 Galerkin system [[d.Kd, d.Ke], [e.Kd, e.Ke]] (a, c) = (d.r0, e.r0).
+    When d and e are nearly parallel (determinant below 1e-10 of the diagonal
+    product) the one of the two single-direction steps that lowers the error
+    more is taken."""
+    dd, de, ee = float(np.sum(d * Kd)), float(np.sum(d * Ke)), float(np.sum(e * Ke))
+    dr, er = float(np.sum(d * r0)), float(np.sum(e * r0))
+    det = dd * ee - de * de
+    if dd > 0 and ee > 0 and det > 1e-10 * dd * ee:
+        return (dr * ee - er * de) / det, (er * dd - dr * de) / det
+    gain_d = dr * dr / dd if dd > 0 else 0.0
+    gain_e = er * er / ee if ee > 0 else 0.0
+    if gain_d >= gain_e:
+        return (dr / dd if dd > 0 else 0.0), 0.0
+    return 0.0, er / ee
 
 
 def adam(vec, grad, m1, m2, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):

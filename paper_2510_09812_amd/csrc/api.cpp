@@ -134,8 +134,9 @@ void gspm_ctx::release_mesh() {
     dev_free(b.cg_rr); dev_free(b.cg_pq); dev_free(b.cg_bb); dev_free(b.cg_flags);
     dev_free(b.r32); dev_free(b.p32); dev_free(b.p32b); dev_free(b.q32); dev_free(b.x32);
     dev_free(b.cgi_rr); dev_free(b.cgi_pq); dev_free(b.cgi_bb); dev_free(b.cgi_flags);
-    dev_free(b.mprev);
+    dev_free(b.mprev); dev_free(b.uprev); dev_free(b.du_prev); dev_free(b.kdu); dev_free(b.wred); dev_free(b.wcoef);
     have_mesh = have_m = have_prev = false;
+    commits = 0;
     tets_int.clear();
     release_nn();
 }
@@ -145,7 +146,7 @@ void gspm_ctx::release_nn() {
     auto &q = nn;
     dev_free(q.gptr); dev_free(q.gnbr); dev_free(q.master); dev_free(q.wr); dev_free(q.m1); dev_free(q.m2);
     dev_free(q.grad); dev_free(q.mats); dev_free(q.acts); dev_free(q.y); dev_free(q.red); dev_free(q.dvec);
-    dev_free(q.du); dev_free(q.mp_in); dev_free(q.m_in); dev_free(q.s_dev);
+    dev_free(q.du); dev_free(q.mp_in); dev_free(q.m_in);
     dev_free(q.gh); dev_free(q.gha); dev_free(q.gab); dev_free(q.gy); dev_free(q.part);
     q = gspm::MpnnState{};
     warm_mode = GSPM_WARM_PREVIOUS;
@@ -250,8 +251,11 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     rc = rc ? rc : dev_alloc(c, &d.seg_mask, nseg);
     rc = rc ? rc : dev_alloc(c, &d.seg_ptr, hm.seg_ptr.size());
     rc = rc ? rc : dev_alloc(c, &d.seg_nmag, hm.seg_nmag.size());
-    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.mprev})
+    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.mprev,
+                        &d.uprev, &d.du_prev, &d.kdu})
         rc = rc ? rc : dev_alloc(c, p, n3);
+    rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kGalSums) * kShards);
+    rc = rc ? rc : dev_alloc(c, &d.wcoef, 2);
     rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
     rc = rc ? rc : dev_alloc(c, &d.sums, 9 * kShards);
     rc = rc ? rc : dev_alloc(c, &d.esums, 4 * kShards);
@@ -290,8 +294,10 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     }
     hipMemcpyAsync(d.seg_ptr, hm.seg_ptr.data(), sizeof(int32_t) * hm.seg_ptr.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.seg_nmag, hm.seg_nmag.data(), sizeof(int32_t) * hm.seg_nmag.size(), hipMemcpyHostToDevice, s);
-    for (double *p : {d.m, d.mnext, d.u, d.unext, d.ms, d.g, d.gs, d.b, d.r, d.p, d.p2, d.q, d.mprev})
+    for (double *p : {d.m, d.mnext, d.u, d.unext, d.ms, d.g, d.gs, d.b, d.r, d.p, d.p2, d.q, d.mprev, d.uprev, d.du_prev,
+                      d.kdu})
         launch_fill(p, n3, 0.0, s);
+    launch_fill(d.wcoef, 2, 0.0, s);
     if (c->precision == GSPM_MIXED)
         for (float *p : {d.r32, d.p32, d.p32b, d.q32, d.x32}) launch_fill_f32(p, n3, s);
     launch_fill(d.ch2, 2 * n, 0.0, s);
@@ -406,10 +412,12 @@ gspm_status gspm_set_field(gspm_ctx *c, gspm_field which, const double *v, int64
         rc = upload(c, c->d.m, h);
         if (rc) return static_cast<gspm_status>(rc);
         c->have_m = true;
-        c->have_prev = false;     // a new state has no history for the learned warm start
+        c->have_prev = false;     // a new state has no history for the warm starts
+        c->commits = 0;
     } else {
         rc = upload(c, c->d.u, h);
         if (rc) return static_cast<gspm_status>(rc);
+        c->commits = 0;           // u^{n-2} no longer precedes u
     }
     return GSPM_OK;
 }

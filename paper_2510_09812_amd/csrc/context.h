@@ -37,6 +37,11 @@ struct DeviceBuffers {
     double *cgi_rr = nullptr, *cgi_pq = nullptr, *cgi_bb = nullptr;
     int32_t *cgi_flags = nullptr;
     double *mprev = nullptr;      // 3n: m^{n-1} (previous committed state), for the learned warm start
+    double *uprev = nullptr;      // 3n: u^{n-2}, for the previous displacement increment
+    double *du_prev = nullptr;    // 3n: u^{n-1} - u^{n-2} (warm start scratch)
+    double *kdu = nullptr;        // 3n: K (u^{n-1} - u^{n-2}) (warm start scratch)
+    double *wred = nullptr;       // kGalSums x kShards: Galerkin sums
+    double *wcoef = nullptr;      // 2: coefficients of the last Galerkin start
 };
 
 // Device state of the learned warm start (allocated on first use).
@@ -47,7 +52,7 @@ struct MpnnState {
     float *master = nullptr, *wr = nullptr, *m1 = nullptr, *m2 = nullptr, *grad = nullptr;
     uint16_t *mats = nullptr, *acts = nullptr;
     float *y = nullptr;
-    double *red = nullptr, *dvec = nullptr, *du = nullptr, *mp_in = nullptr, *m_in = nullptr, *s_dev = nullptr;
+    double *red = nullptr, *dvec = nullptr, *du = nullptr, *mp_in = nullptr, *m_in = nullptr;
     float *gh = nullptr, *gha = nullptr, *gab = nullptr, *gy = nullptr, *part = nullptr;
     int part_wgs = 0;
     int64_t adam_t = 0;
@@ -97,6 +102,7 @@ struct gspm_ctx {
     gspm::MpnnState nn;
     int warm_mode = GSPM_WARM_PREVIOUS;
     bool have_prev = false;               // d.mprev holds the state before the last committed step
+    int commits = 0;                      // steps committed since the last set_field (u^{n-2} valid from 2)
     std::vector<int32_t> tets_int;        // 4 x ne internal node ids (graph construction)
 
     ~gspm_ctx();
@@ -117,7 +123,12 @@ CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int max
 CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit, SolveKind kind);
 int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st);
 int hip_check(gspm_ctx *c, hipError_t e, const char *what);
-int learned_start(gspm_ctx *c, const double *m, const double *mprev, double *x, const double *b);
+// Warm start of the elastic solve on the right-hand side b: x (holding u^{n-1})
+// becomes u^{n-1} + a d + c e, d the network's increment at (m, mprev) (when
+// mprev != nullptr), e = u^{n-1} - uprev (when uprev != nullptr), (a, c) the
+// Galerkin coefficients (stored at d.wcoef).  Leaves the CG scalars as
+// cg_prepare set them.
+int galerkin_start(gspm_ctx *c, const double *m, const double *mprev, const double *uprev, double *x, const double *b);
 // Caller-order n0 x 3 <-> internal component-major 3 x n (api.cpp).
 int gather_user(gspm_ctx *c, const double *v, std::vector<double> &out);
 void scatter_user(const gspm_ctx *c, const std::vector<double> &in, double *out);

@@ -86,7 +86,6 @@ int nn_setup(gspm_ctx *c) {
     rc = rc ? rc : nn_alloc(c, &nn.du, 3 * n);
     rc = rc ? rc : nn_alloc(c, &nn.mp_in, 3 * n);
     rc = rc ? rc : nn_alloc(c, &nn.m_in, 3 * n);
-    rc = rc ? rc : nn_alloc(c, &nn.s_dev, 1);
     rc = rc ? rc : nn_alloc(c, &nn.gh, n * kHid);
     rc = rc ? rc : nn_alloc(c, &nn.gha, n * 128);
     rc = rc ? rc : nn_alloc(c, &nn.gab, n * 128);
@@ -122,17 +121,25 @@ int nn_setup(gspm_ctx *c) {
 
 }  // namespace
 
-// The learned start of the elastic solve: x <- x + s d with d the network's
-// increment at (m, mprev) and s the Galerkin step along d for K x = b.
-// Leaves the CG scalars as cg_prepare set them.
-int learned_start(gspm_ctx *c, const double *m, const double *mprev, double *x, const double *b) {
+int galerkin_start(gspm_ctx *c, const double *m, const double *mprev, const double *uprev, double *x, const double *b) {
     auto &nn = c->nn;
+    auto &d = c->d;
     hipStream_t s = c->stream;
-    mpnn::launch_forward(nn.graph, c->mv, nn.net, m, mprev, nn.red, nn.A, c->mat.l100, nn.dvec, s);
-    launch_elastic_matvec<double>(c->mv, c->mat, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, 0.0, s);
-    launch_elastic_matvec<double>(c->mv, c->mat, MV_APPLY, nn.dvec, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, 0.0,
-                                  s);
-    mpnn::launch_galerkin(c->n, nn.dvec, c->d.r, c->d.q, x, nn.red, nn.s_dev, s);
+    const double *dv = nullptr, *ev = nullptr;
+    if (mprev) {
+        mpnn::launch_forward(nn.graph, c->mv, nn.net, m, mprev, nn.red, nn.A, c->mat.l100, nn.dvec, s);
+        launch_elastic_matvec<double>(c->mv, c->mat, MV_APPLY, nn.dvec, d.q, nullptr, nullptr, nullptr, c->cg, 0, 0.0,
+                                      s);
+        dv = nn.dvec;
+    }
+    if (uprev) {
+        mpnn::launch_sub(3 * static_cast<int64_t>(c->n), x, uprev, d.du_prev, s);
+        launch_elastic_matvec<double>(c->mv, c->mat, MV_APPLY, d.du_prev, d.kdu, nullptr, nullptr, nullptr, c->cg, 0,
+                                      0.0, s);
+        ev = d.du_prev;
+    }
+    launch_elastic_matvec<double>(c->mv, c->mat, MV_RESID, x, nullptr, b, d.r, nullptr, c->cg, 0, 0.0, s);
+    mpnn::launch_galerkin(c->n, dv, d.q, ev, d.kdu, d.r, x, d.wred, d.wcoef, s);
     launch_zero_ring(c->cg, 1, 0, 1, 0, 0, s);
     return GSPM_OK;
 }
@@ -165,7 +172,8 @@ extern "C" {
 
 gspm_status gspm_set_warm_start(gspm_ctx *c, int32_t mode) {
     if (!c) return GSPM_E_ARG;
-    if (mode != GSPM_WARM_PREVIOUS && mode != GSPM_WARM_LEARNED) return nfail(c, GSPM_E_ARG, "unknown warm start");
+    if (mode != GSPM_WARM_PREVIOUS && mode != GSPM_WARM_LEARNED && mode != GSPM_WARM_EXTRAPOLATE)
+        return nfail(c, GSPM_E_ARG, "unknown warm start");
     if (mode == GSPM_WARM_LEARNED && !c->nn.have_params)
         return nfail(c, GSPM_E_STATE, "learned warm start needs gspm_mpnn_set_params");
     c->warm_mode = mode;
@@ -276,7 +284,8 @@ gspm_status gspm_mpnn_train_step(gspm_ctx *c, const double *m_prev, const double
     return GSPM_OK;
 }
 
-gspm_status gspm_mpnn_warm_start(gspm_ctx *c, const double *m_prev, int64_t n_nodes, double *u0, double *scale) {
+gspm_status gspm_mpnn_warm_start(gspm_ctx *c, const double *m_prev, const double *u_prev, int64_t n_nodes, double *u0,
+                                 double coef[2]) {
     if (!c) return GSPM_E_ARG;
     if (!m_prev || !u0) return nfail(c, GSPM_E_ARG, "mpnn_warm_start: null array");
     gspm_status st = nn_ready(c);
@@ -287,6 +296,7 @@ gspm_status gspm_mpnn_warm_start(gspm_ctx *c, const double *m_prev, int64_t n_no
     auto &nn = c->nn;
     auto &d = c->d;
     int rc = upload_user(c, m_prev, nn.mp_in);
+    if (!rc && u_prev) rc = upload_user(c, u_prev, nn.du);
     if (rc) return static_cast<gspm_status>(rc);
     hipStream_t s = c->stream;
     const size_t bytes3 = sizeof(double) * 3 * static_cast<size_t>(c->n);
@@ -296,15 +306,25 @@ gspm_status gspm_mpnn_warm_start(gspm_ctx *c, const double *m_prev, int64_t n_no
     hipMemcpyAsync(d.unext, d.u, bytes3, hipMemcpyDeviceToDevice, s);
     cg_prepare(c, 1);
     launch_elastic_rhs(c->mv, c->mat, d.m, d.b, d.unext, c->cg.bb, s);
-    learned_start(c, d.m, nn.mp_in, d.unext, d.b);
+    if (u_prev) {
+        // the pinned node's displacement is zero in the start; so in u_prev
+        std::vector<double> z(3, 0.0);
+        for (int a = 0; a < 3; ++a)
+            hipMemcpyAsync(nn.du + static_cast<size_t>(a) * c->n + c->p0, z.data(), sizeof(double),
+                           hipMemcpyHostToDevice, s);
+    }
+    galerkin_start(c, d.m, nn.mp_in, u_prev ? nn.du : nullptr, d.unext, d.b);
     std::vector<double> h(3 * static_cast<size_t>(c->n));
-    double sh = 0.0;
+    double ch[2] = {0.0, 0.0};
     hipMemcpyAsync(h.data(), d.unext, bytes3, hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(&sh, nn.s_dev, sizeof sh, hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(ch, d.wcoef, sizeof ch, hipMemcpyDeviceToHost, s);
     rc = hip_check(c, hipStreamSynchronize(s), "mpnn_warm_start");
     if (rc) return static_cast<gspm_status>(rc);
     scatter_user(c, h, u0);
-    if (scale) *scale = sh;
+    if (coef) {
+        coef[0] = ch[0];
+        coef[1] = ch[1];
+    }
     return GSPM_OK;
 }
 

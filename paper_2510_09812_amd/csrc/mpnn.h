@@ -26,7 +26,9 @@ constexpr int kMat = 128 * 64;              // elements of each BF16 weight-matr
 constexpr int kPartStride = 8192;           // floats of one workgroup's gradient partial
 
 // Reduction slots (each kShards doubles) of the network's scalar buffer.
-enum RedSlot { R_DM2 = 0, R_W = 1, R_Y = 2, R_T = 5, R_LOSS = 8, R_DR = 9, R_DKD = 10, R_COUNT = 11 };
+enum RedSlot { R_DM2 = 0, R_W = 1, R_Y = 2, R_T = 5, R_LOSS = 8, R_COUNT = 9 };
+// Sharded sums of the Galerkin start (their own buffer of kGalSums x kShards).
+enum GalSlot { G_DKD = 0, G_DKE = 1, G_EKE = 2, G_DR = 3, G_ER = 4, kGalSums = 5 };
 
 struct Graph {
     const int32_t *ptr, *nbr;                // CSR over unique nodes, neighbours sorted
@@ -69,10 +71,15 @@ void launch_loss_backward(const Graph &g, const MeshView &mv, const Net &net, co
                           float *grad, hipStream_t s);
 void launch_adam(float *master, const float *grad, float *m1, float *m2, float lr, int64_t t, hipStream_t s);
 void launch_prepare_weights(const float *master, float *wr, uint16_t *mats, hipStream_t s);
-// Galerkin step along d: x += s d with s = d.r0 / d.Kd (0 if d.Kd <= 0 or
-// the ratio is not finite); s is also written to *s_out when s_out != nullptr.
-void launch_galerkin(int n, const double *d, const double *r0, const double *kd, double *x, double *red,
-                     double *s_out, hipStream_t s);
+// Galerkin start on span{d, e} (either may be null): x += a d + c e with (a, c)
+// solving [[d.Kd, d.Ke], [e.Kd, e.Ke]] (a, c) = (d.r0, e.r0); when d and e are
+// nearly parallel (determinant below 1e-10 of the diagonal product) the better
+// single-direction step; a non-finite or non-positive system gives 0.  red
+// holds 5 sharded sums; coef (device, 2 doubles) receives (a, c).
+void launch_galerkin(int n, const double *d, const double *kd, const double *e, const double *ke, const double *r0,
+                     double *x, double *red, double *coef, hipStream_t s);
+// out = a - b over n3 values.
+void launch_sub(int64_t n3, const double *a, const double *b, double *out, hipStream_t s);
 
 // Host: directed edge graph of the mesh on unique nodes (every pair of
 // distinct nodes sharing a tetrahedron, both directions), CSR with sorted

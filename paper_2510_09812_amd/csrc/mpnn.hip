@@ -20,6 +20,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = kThreads / 64;
+constexpr int kBatch = 8;       // neighbour rows loaded before they are used (edge passes)
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
@@ -301,11 +302,23 @@ __global__ void __launch_bounds__(kThreads) k_edge_fwd(Graph g, MeshView mv, con
                 jl = g.nbr[base + lane];
                 edge_vec(mv, g.ihbar, xi, yi, zi, jl, ex, ey, ez);
             }
-            for (int t = 0; t < cnt; ++t) {
-                const int j = rdlane(jl, t);
-                const float z = ai + bf2f(AB[static_cast<size_t>(j) * 128 + 64 + lane]) + we0 * rdlane(ex, t) +
-                                we1 * rdlane(ey, t) + we2 * rdlane(ez, t);
-                acc += silu(z);
+            // eight neighbour rows in flight at a time: the loads are issued
+            // back to back (indices clamped to the last neighbour), then used
+            for (int t0 = 0; t0 < cnt; t0 += kBatch) {
+                float bv[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int j = rdlane(jl, min(t0 + u, cnt - 1));
+                    bv[u] = bf2f(AB[static_cast<size_t>(j) * 128 + 64 + lane]);
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int t = t0 + u;
+                    if (t < cnt) {
+                        const float z = ai + bv[u] + we0 * rdlane(ex, t) + we1 * rdlane(ey, t) + we2 * rdlane(ez, t);
+                        acc += silu(z);
+                    }
+                }
             }
         }
         const int deg = end - beg;
@@ -473,21 +486,32 @@ __global__ void __launch_bounds__(kThreads) k_edge_bwd(Graph g, MeshView mv, con
                 const int du = g.ptr[ul + 1] - g.ptr[ul];
                 idu = du > 0 ? 1.0f / static_cast<float>(du) : 0.0f;
             }
-            for (int t = 0; t < cnt; ++t) {
-                const int u = rdlane(ul, t);
-                const float e0 = rdlane(ex, t), e1 = rdlane(ey, t), e2 = rdlane(ez, t);
-                const float wde = we0 * e0 + we1 * e1 + we2 * e2;
-                const size_t ru = static_cast<size_t>(u) * 128;
-                // edge v -> u (message into v)
-                const float g1 = gav * dsilu(av + bf2f(AB[ru + 64 + lane]) + wde);
-                gA += g1;
-                s[0] += g1 * e0;
-                s[1] += g1 * e1;
-                s[2] += g1 * e2;
-                s[3] += g1;
-                // edge u -> v (message into u), edge vector -e
-                const float g2 = gha[ru + 64 + lane] * rdlane(idu, t) * dsilu(bf2f(AB[ru + lane]) + bv - wde);
-                gB += g2;
+            for (int t0 = 0; t0 < cnt; t0 += kBatch) {
+                float au[kBatch], bu[kBatch], gu[kBatch];
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    const size_t ru = static_cast<size_t>(rdlane(ul, min(t0 + q, cnt - 1))) * 128;
+                    au[q] = bf2f(AB[ru + lane]);
+                    bu[q] = bf2f(AB[ru + 64 + lane]);
+                    gu[q] = gha[ru + 64 + lane];
+                }
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    const int t = t0 + q;
+                    if (t >= cnt) continue;
+                    const float e0 = rdlane(ex, t), e1 = rdlane(ey, t), e2 = rdlane(ez, t);
+                    const float wde = we0 * e0 + we1 * e1 + we2 * e2;
+                    // edge v -> u (message into v)
+                    const float g1 = gav * dsilu(av + bu[q] + wde);
+                    gA += g1;
+                    s[0] += g1 * e0;
+                    s[1] += g1 * e1;
+                    s[2] += g1 * e2;
+                    s[3] += g1;
+                    // edge u -> v (message into u), edge vector -e
+                    const float g2 = gu[q] * rdlane(idu, t) * dsilu(au[q] + bv - wde);
+                    gB += g2;
+                }
             }
         }
         gab[static_cast<size_t>(v) * 128 + lane] = gA;
@@ -561,24 +585,57 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const float *p, float *wr,
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_dot2(int n3, const double *d, const double *r0, const double *kd,
-                                                   double *red) {
-    double a[2] = {0.0, 0.0};
+// Sums of the Galerkin system on span{d, e}; a null direction contributes 0.
+__global__ void __launch_bounds__(kThreads) k_galerkin_sums(int n3, const double *d, const double *kd, const double *e,
+                                                            const double *ke, const double *r0, double *red) {
+    double a[kGalSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n3; i += gridDim.x * kThreads) {
-        a[0] += d[i] * r0[i];
-        a[1] += d[i] * kd[i];
+        const double di = d ? d[i] : 0.0, ei = e ? e[i] : 0.0, r = r0[i];
+        const double kdi = d ? kd[i] : 0.0, kei = e ? ke[i] : 0.0;
+        a[G_DKD] += di * kdi;
+        a[G_DKE] += di * kei;
+        a[G_EKE] += ei * kei;
+        a[G_DR] += di * r;
+        a[G_ER] += ei * r;
     }
-    block_atomic_add<2>(a, red + R_DR * kShards, kShards);
+    block_atomic_add<kGalSums>(a, red, kShards);
 }
 
-__global__ void __launch_bounds__(kThreads) k_galerkin_axpy(int n3, const double *d, double *x, const double *red,
-                                                            double *s_out) {
-    const double *const src[2] = {red + R_DR * kShards, red + R_DKD * kShards};
-    double t[2];
-    shard_totals<2>(src, t);
-    const double sc = (t[1] > 0.0 && __builtin_isfinite(t[0] / t[1])) ? t[0] / t[1] : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && s_out) *s_out = sc;
-    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n3; i += gridDim.x * kThreads) x[i] += sc * d[i];
+__device__ __forceinline__ void galerkin_coef(const double (&t)[kGalSums], double &ca, double &cc) {
+    const double dd = t[G_DKD], de = t[G_DKE], ee = t[G_EKE], dr = t[G_DR], er = t[G_ER];
+    const double det = dd * ee - de * de;
+    ca = cc = 0.0;
+    if (dd > 0.0 && ee > 0.0 && det > 1e-10 * dd * ee) {
+        ca = (dr * ee - er * de) / det;
+        cc = (er * dd - dr * de) / det;
+    } else {
+        const double gd = dd > 0.0 ? dr * dr / dd : 0.0, ge = ee > 0.0 ? er * er / ee : 0.0;
+        if (gd >= ge) ca = dd > 0.0 ? dr / dd : 0.0;
+        else cc = er / ee;
+    }
+    if (!__builtin_isfinite(ca) || !__builtin_isfinite(cc)) ca = cc = 0.0;
+}
+
+__global__ void __launch_bounds__(kThreads) k_galerkin_apply(int n3, const double *d, const double *e, double *x,
+                                                             const double *red, double *coef) {
+    const double *const src[kGalSums] = {red, red + kShards, red + 2 * kShards, red + 3 * kShards,
+                                         red + 4 * kShards};
+    double t[kGalSums];
+    shard_totals<kGalSums>(src, t);
+    double ca, cc;
+    galerkin_coef(t, ca, cc);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && coef) {
+        coef[0] = ca;
+        coef[1] = cc;
+    }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n3; i += gridDim.x * kThreads)
+        x[i] += (d ? ca * d[i] : 0.0) + (e ? cc * e[i] : 0.0);
+}
+
+__global__ void __launch_bounds__(kThreads) k_sub(int64_t n3, const double *a, const double *b, double *out) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n3;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        out[i] = a[i] - b[i];
 }
 
 }  // namespace
@@ -677,12 +734,16 @@ void launch_prepare_weights(const float *master, float *wr, uint16_t *mats, hipS
     hipLaunchKernelGGL(k_prepare, dim3(grid_for(kNParam, kThreads)), dim3(kThreads), 0, s, master, wr, mats);
 }
 
-void launch_galerkin(int n, const double *d, const double *r0, const double *kd, double *x, double *red,
-                     double *s_out, hipStream_t s) {
+void launch_galerkin(int n, const double *d, const double *kd, const double *e, const double *ke, const double *r0,
+                     double *x, double *red, double *coef, hipStream_t s) {
     const int n3 = 3 * n;
-    launch_fill(red + R_DR * kShards, 2 * kShards, 0.0, s);
-    hipLaunchKernelGGL(k_dot2, dim3(grid_for(n3, kThreads)), dim3(kThreads), 0, s, n3, d, r0, kd, red);
-    hipLaunchKernelGGL(k_galerkin_axpy, dim3(grid_for(n3, kThreads)), dim3(kThreads), 0, s, n3, d, x, red, s_out);
+    launch_fill(red, kGalSums * kShards, 0.0, s);
+    hipLaunchKernelGGL(k_galerkin_sums, dim3(grid_for(n3, kThreads)), dim3(kThreads), 0, s, n3, d, kd, e, ke, r0, red);
+    hipLaunchKernelGGL(k_galerkin_apply, dim3(grid_for(n3, kThreads)), dim3(kThreads), 0, s, n3, d, e, x, red, coef);
+}
+
+void launch_sub(int64_t n3, const double *a, const double *b, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub, dim3(grid_for(n3, kThreads)), dim3(kThreads), 0, s, n3, a, b, out);
 }
 
 }  // namespace mpnn

@@ -312,9 +312,14 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     hipMemcpyAsync(d.unext, d.u, bytes3, hipMemcpyDeviceToDevice, s);
     cg_prepare(c, 1);
     launch_elastic_rhs(c->mv, c->mat, d.m, d.b, d.unext, c->cg.bb, s);
-    if (c->warm_mode == GSPM_WARM_LEARNED && c->have_prev) {
-        learned_start(c, d.m, d.mprev, d.unext, d.b);
-        ++st->learned_starts;
+    {
+        const bool net = c->warm_mode == GSPM_WARM_LEARNED && c->have_prev;
+        const bool extrap = c->warm_mode != GSPM_WARM_PREVIOUS && c->commits >= 2;
+        if (net || extrap) {
+            galerkin_start(c, d.m, net ? d.mprev : nullptr, extrap ? d.uprev : nullptr, d.unext, d.b);
+            st->learned_starts += net;
+            ++st->galerkin_starts;
+        }
     }
     CgResult r = cg_elastic(c, d.unext, d.b, tol, maxit, SK_MECH);
     st->mech_iters += r.iters[0];
@@ -368,11 +373,14 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     double dsum = 0.0;
     for (int k = 0; k < kShards; ++k) dsum += dmh[k];
     st->dm_avg = c->nmag > 0 ? dsum / c->nmag : 0.0;
-    // m^{n-1} <- m^n <- m^{n+1}: the old m buffer keeps the previous state
+    // m^{n-1} <- m^n <- m^{n+1} and u^{n-2} <- u^{n-1} <- u^n: the old
+    // buffers keep the previous states
     std::swap(d.mprev, d.m);
     std::swap(d.m, d.mnext);
+    std::swap(d.uprev, d.u);
     std::swap(d.u, d.unext);
     c->have_prev = true;
+    ++c->commits;
     return GSPM_OK;
 }
 
@@ -404,7 +412,7 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     st->elapsed_ms = ms;
     for (int q = 0; q < 8; ++q) st->gs_iters += st->gs_iters_stage[q];
     st->refinements = c->refinements - ref0;
-    if (st->learned_starts > 0) hipMemcpy(&st->warm_scale, c->nn.s_dev, sizeof(double), hipMemcpyDeviceToHost);
+    if (st->galerkin_starts > 0) hipMemcpy(st->warm_coef, c->d.wcoef, 2 * sizeof(double), hipMemcpyDeviceToHost);
     if (c->profile) {
         double tot = 0.0;
         int64_t cnt = 0;

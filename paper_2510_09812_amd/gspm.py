@@ -21,7 +21,7 @@ GSPM_FP64, GSPM_MIXED = 0, 1
 GSPM_FIELD_M, GSPM_FIELD_U = 0, 1
 GSPM_OP_LAPLACE, GSPM_OP_MASS, GSPM_OP_GS, GSPM_OP_ELASTIC = 0, 1, 2, 3
 GSPM_PERIODIC = 1
-GSPM_WARM_PREVIOUS, GSPM_WARM_LEARNED = 0, 1
+GSPM_WARM_PREVIOUS, GSPM_WARM_LEARNED, GSPM_WARM_EXTRAPOLATE = 0, 1, 2
 GSPM_MPNN_PARAMS = 50819
 
 STATUS_NAMES = {0: "GSPM_OK", -1: "GSPM_E_ARG", -2: "GSPM_E_MESH", -3: "GSPM_E_STATE", -4: "GSPM_E_DEVICE",
@@ -57,7 +57,8 @@ class gspm_step_stats(ctypes.Structure):
                 ("gs_iters", ctypes.c_int64), ("gs_iters_stage", ctypes.c_int64 * 8), ("dm_avg", ctypes.c_double),
                 ("elapsed_ms", ctypes.c_double), ("matvec_ms", ctypes.c_double),
                 ("matvec_launches", ctypes.c_int64), ("refinements", ctypes.c_int64),
-                ("learned_starts", ctypes.c_int64), ("warm_scale", ctypes.c_double)]
+                ("learned_starts", ctypes.c_int64), ("galerkin_starts", ctypes.c_int64),
+                ("warm_coef", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -101,7 +102,7 @@ def load() -> ctypes.CDLL:
     lib.gspm_mpnn_forward.argtypes = [P, dp, dp, i64, dp, dp]; lib.gspm_mpnn_forward.restype = S
     lib.gspm_mpnn_train_step.argtypes = [P, dp, dp, dp, i64, ctypes.c_float, ctypes.c_int32, dp, fp]
     lib.gspm_mpnn_train_step.restype = S
-    lib.gspm_mpnn_warm_start.argtypes = [P, dp, i64, dp, dp]; lib.gspm_mpnn_warm_start.restype = S
+    lib.gspm_mpnn_warm_start.argtypes = [P, dp, dp, i64, dp, dp]; lib.gspm_mpnn_warm_start.restype = S
     _lib = lib
     return lib
 
@@ -190,7 +191,8 @@ def stats_dict(st: gspm_step_stats) -> dict:
     return dict(steps_done=st.steps_done, failed_step=st.failed_step, mech_iters=st.mech_iters,
                 gs_iters=st.gs_iters, gs_iters_stage=list(st.gs_iters_stage), dm_avg=st.dm_avg,
                 elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches,
-                refinements=st.refinements, learned_starts=st.learned_starts, warm_scale=st.warm_scale)
+                refinements=st.refinements, learned_starts=st.learned_starts, galerkin_starts=st.galerkin_starts,
+                warm_coef=list(st.warm_coef))
 
 
 def gspm_step(ctx, dt: float, n_steps: int = 1) -> dict:
@@ -302,14 +304,16 @@ def gspm_mpnn_train_step(ctx, m_prev, m, du, lr: float = 1e-3, update: bool = Tr
     return float(loss[0]), g
 
 
-def gspm_mpnn_warm_start(ctx, m_prev):
-    """The learned elastic start for the current state: (u0, s)."""
+def gspm_mpnn_warm_start(ctx, m_prev, u_prev=None):
+    """The learned elastic start for the current state: (u0, (a, c))."""
     mp = _f64(m_prev)
     n = mp.shape[0]
+    up = _f64(u_prev) if u_prev is not None else None
     u0 = np.zeros((n, 3))
-    sc = np.zeros(1)
-    _check(ctx, load().gspm_mpnn_warm_start(ctx, _dp(mp), n, _dp(u0), _dp(sc)))
-    return u0, float(sc[0])
+    coef = np.zeros(2)
+    _check(ctx, load().gspm_mpnn_warm_start(ctx, _dp(mp), _dp(up) if up is not None else None, n, _dp(u0),
+                                            _dp(coef)))
+    return u0, (float(coef[0]), float(coef[1]))
 
 
 class Simulation:
@@ -374,8 +378,8 @@ class Simulation:
     def mpnn_train_step(self, m_prev, m, du, lr: float = 1e-3, update: bool = True, want_grad: bool = False):
         return gspm_mpnn_train_step(self.ctx, m_prev, m, du, lr, update, want_grad)
 
-    def mpnn_warm_start(self, m_prev):
-        return gspm_mpnn_warm_start(self.ctx, m_prev)
+    def mpnn_warm_start(self, m_prev, u_prev=None):
+        return gspm_mpnn_warm_start(self.ctx, m_prev, u_prev)
 
     def close(self):
         gspm_destroy(getattr(self, "ctx", None))

@@ -159,7 +159,8 @@ def test_learned_start_matches_oracle_galerkin_step():
     u = case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)) * 1e-10)
     sim.set_m(m)
     sim.set_u(u)
-    u0, s = sim.mpnn_warm_start(mp)
+    u0, (s, c0) = sim.mpnn_warm_start(mp)
+    assert c0 == 0.0
     # oracle: d from the emulated network, r0 = b - K u, s = d.r0 / d.K d
     mu, mpu, wts = _oracle_inputs(orc, m, mp)
     orc.set_m(m)
@@ -201,7 +202,66 @@ def test_steps_with_learned_start_match_plain_steps():
     (m0, u0, s0), (m1, u1, s1) = out[gspm.GSPM_WARM_PREVIOUS], out[gspm.GSPM_WARM_LEARNED]
     dm = lambda u: u - u.mean(axis=0)
     print(f"plain mech {s0['mech_iters']} learned mech {s1['mech_iters']} starts {s1['learned_starts']} "
-          f"s {s1['warm_scale']:.3e} | m {_rel(m1, m0):.2e} u {_rel(dm(u1), dm(u0)):.2e}", flush=True)
+          f"coef {s1['warm_coef']} | m {_rel(m1, m0):.2e} u {_rel(dm(u1), dm(u0)):.2e}", flush=True)
     assert s1["learned_starts"] == 4 and s0["learned_starts"] == 0
-    assert np.isfinite(s1["warm_scale"])
+    assert s1["galerkin_starts"] == 4 and np.all(np.isfinite(s1["warm_coef"]))
+    assert _rel(m1, m0) < 1e-6 and _rel(dm(u1), dm(u0)) < 1e-6
+
+
+def test_two_direction_start_matches_oracle():
+    """Network increment and previous displacement increment together: the
+    GPU start against the oracle's Galerkin solution on span{d, e}."""
+    case, orc, g, m, mp = _setup(n=9, seed=407)
+    params = _init_params(17, scale=0.6)
+    sim = gspm.Simulation(case.mesh, case.params)
+    sim.mpnn_set_params(params)
+    rng = np.random.default_rng(9)
+    u = case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)) * 1e-10)
+    up = u - case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)) * 2e-11)
+    sim.set_m(m)
+    sim.set_u(u)
+    u0, (a, c) = sim.mpnn_warm_start(mp, up)
+    mu, mpu, wts = _oracle_inputs(orc, m, mp)
+    orc.set_m(m)
+    x, sm = N.features(mu, mpu, wts)
+    y, _ = N.forward(N.unpack(params), x, g, bf16=True)
+    p0 = orc.pinned_node()
+    d = N.increment(y, sm, case.params["lambda100"], g.hbar, p0)
+    uu, uup = _unique(orc, u), _unique(orc, up)
+    uu[p0] = 0.0
+    uup[p0] = 0.0
+    e = uu - uup
+    b = orc.elastic_rhs()
+    r0 = b - orc.apply(O.OP_ELASTIC, uu)
+    r0[p0] = 0.0
+    a_ref, c_ref = N.galerkin2(d, e, r0, orc.apply(O.OP_ELASTIC, d), orc.apply(O.OP_ELASTIC, e))
+    step_gpu = _unique(orc, u0) - uu
+    step_ref = a_ref * d + c_ref * e
+    print(f"a gpu {a:.6e} oracle {a_ref:.6e}; c gpu {c:.6e} oracle {c_ref:.6e}; "
+          f"step rel err {_rel(step_gpu, step_ref):.2e}", flush=True)
+    assert _rel(step_gpu, step_ref) < 3e-2
+    assert abs(c - c_ref) <= 3e-2 * abs(c_ref) + 3e-2 * abs(a_ref) * np.linalg.norm(d) / np.linalg.norm(e)
+    xs, _ = orc.solve(O.OP_ELASTIC, b, uu, tol=1e-13)
+    en = lambda v: float(np.sum((xs - v) * orc.apply(O.OP_ELASTIC, xs - v)))
+    assert en(_unique(orc, u0)) <= en(uu) * (1 + 1e-9)
+    sim.close()
+
+
+def test_extrapolated_start_steps_match_plain_steps():
+    case = w.small_cube(10, seed=408, L=9e-8, jitter=0.15, sphere=0.3)
+    params = dict(case.params)
+    params["cg_tol"] = 1e-10
+    out = {}
+    for mode in (gspm.GSPM_WARM_PREVIOUS, gspm.GSPM_WARM_EXTRAPOLATE):
+        sim = gspm.Simulation(case.mesh, params, hext=(-0.3 * case.material["Ms"], 0.0, 0.0))
+        sim.set_warm_start(mode)
+        sim.set_m(case.m0)
+        st = sim.step(2e-12, 6)
+        out[mode] = (sim.get_m(), sim.get_u(), st)
+        sim.close()
+    (m0, u0, s0), (m1, u1, s1) = out[gspm.GSPM_WARM_PREVIOUS], out[gspm.GSPM_WARM_EXTRAPOLATE]
+    dm = lambda u: u - u.mean(axis=0)
+    print(f"plain mech {s0['mech_iters']} extrapolated mech {s1['mech_iters']} "
+          f"Galerkin starts {s1['galerkin_starts']} coef {s1['warm_coef']}", flush=True)
+    assert s1["galerkin_starts"] == 4 and s1["learned_starts"] == 0
     assert _rel(m1, m0) < 1e-6 and _rel(dm(u1), dm(u0)) < 1e-6

@@ -164,6 +164,27 @@ def test_galerkin_step_minimises_energy_error():
     assert N.galerkin_scale(np.zeros(40), b, np.zeros(40)) == 0.0
 
 
+def test_two_direction_galerkin_step_is_the_energy_projection():
+    rng = np.random.default_rng(14)
+    Q = rng.standard_normal((50, 50))
+    K = Q @ Q.T + 50 * np.eye(50)
+    b = rng.standard_normal(50)
+    xs = np.linalg.solve(K, b)
+    u = xs + 0.3 * rng.standard_normal(50)
+    d = (xs - u) + 0.3 * rng.standard_normal(50)
+    e = 0.5 * (xs - u) + 0.3 * rng.standard_normal(50)
+    a, c = N.galerkin2(d, e, b - K @ u, K @ d, K @ e)
+    # the K-orthogonal projection of the error onto span{d, e}, by a dense solve
+    V = np.stack([d, e], axis=1)
+    coef = np.linalg.solve(V.T @ K @ V, V.T @ K @ (xs - u))
+    assert np.allclose([a, c], coef, rtol=1e-10)
+    err = lambda v: (xs - v) @ K @ (xs - v)
+    assert err(u + a * d + c * e) <= min(err(u), err(u + N.galerkin_scale(d, b - K @ u, K @ d) * d)) + 1e-12
+    # parallel directions fall back to one step
+    a2, c2 = N.galerkin2(d, 2 * d, b - K @ u, K @ d, 2 * (K @ d))
+    assert np.isclose(a2 + 2 * c2, N.galerkin_scale(d, b - K @ u, K @ d))
+
+
 def test_increment_zero_at_pinned_node():
     rng = np.random.default_rng(11)
     y = rng.standard_normal((30, 3))
