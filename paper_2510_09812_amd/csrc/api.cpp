@@ -126,7 +126,7 @@ void gspm_ctx::release_mesh() {
     auto &b = d;
     dev_free(b.x); dev_free(b.lconn); dev_free(b.blk_ptr); dev_free(b.blk_nmag); dev_free(b.w);
     dev_free(b.halo_ptr); dev_free(b.halo_ids); dev_free(b.halo_lo); dev_free(b.img);
-    dev_free(b.seg_ent); dev_free(b.seg_mask); dev_free(b.seg_ptr); dev_free(b.seg_nmag);
+    dev_free(b.seg_ent); dev_free(b.seg_off); dev_free(b.seg_nel); dev_free(b.seg_ptr); dev_free(b.seg_nmag);
     dev_free(b.m); dev_free(b.mnext); dev_free(b.u); dev_free(b.unext);
     dev_free(b.ms); dev_free(b.g); dev_free(b.gs); dev_free(b.b); dev_free(b.ch2);
     dev_free(b.r); dev_free(b.p); dev_free(b.p2); dev_free(b.q);
@@ -246,9 +246,10 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     rc = rc ? rc : dev_alloc(c, &d.halo_lo, hm.halo_lo.size());
     rc = rc ? rc : dev_alloc(c, &d.img, hm.img.size());
     rc = rc ? rc : dev_alloc(c, &d.w, n);
-    const size_t nseg = hm.seg_mask.size();
-    rc = rc ? rc : dev_alloc(c, &d.seg_ent, 2 * nseg);
-    rc = rc ? rc : dev_alloc(c, &d.seg_mask, nseg);
+    const size_t nseg = hm.seg_nel.size();
+    rc = rc ? rc : dev_alloc(c, &d.seg_ent, hm.seg_ent.size() / 8);
+    rc = rc ? rc : dev_alloc(c, &d.seg_off, nseg);
+    rc = rc ? rc : dev_alloc(c, &d.seg_nel, nseg);
     rc = rc ? rc : dev_alloc(c, &d.seg_ptr, hm.seg_ptr.size());
     rc = rc ? rc : dev_alloc(c, &d.seg_nmag, hm.seg_nmag.size());
     for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.mprev,
@@ -290,7 +291,8 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     hipMemcpyAsync(d.w, hm.w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
     if (nseg) {
         hipMemcpyAsync(d.seg_ent, hm.seg_ent.data(), sizeof(uint16_t) * hm.seg_ent.size(), hipMemcpyHostToDevice, s);
-        hipMemcpyAsync(d.seg_mask, hm.seg_mask.data(), sizeof(uint16_t) * nseg, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(d.seg_off, hm.seg_off.data(), sizeof(uint32_t) * nseg, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(d.seg_nel, hm.seg_nel.data(), sizeof(uint16_t) * nseg, hipMemcpyHostToDevice, s);
     }
     hipMemcpyAsync(d.seg_ptr, hm.seg_ptr.data(), sizeof(int32_t) * hm.seg_ptr.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.seg_nmag, hm.seg_nmag.data(), sizeof(int32_t) * hm.seg_nmag.size(), hipMemcpyHostToDevice, s);
@@ -331,7 +333,8 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     mv.halo_lo = d.halo_lo;
     mv.img = d.img;
     mv.seg_ent = d.seg_ent;
-    mv.seg_mask = d.seg_mask;
+    mv.seg_off = d.seg_off;
+    mv.seg_nel = d.seg_nel;
     mv.seg_ptr = d.seg_ptr;
     mv.seg_nmag = d.seg_nmag;
     mv.nloc_max = hm.nloc_max;

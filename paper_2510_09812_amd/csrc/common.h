@@ -42,19 +42,23 @@ struct HostMesh {
     std::vector<int32_t> halo_lo;         // nblk: halo ids below the block's range
     std::vector<uint8_t> img;             // nblk: edges need the nearest periodic image
     std::vector<double> w;                // n: lumped magnetic weights sum_e chi_e V_e / 4
-    // Tet strips of the matrix-free operators: per block, segments of
-    // kSegEntries window updates (see build_strips), magnetic segments first.
-    std::vector<uint16_t> seg_ent;        // kSegEntries per segment
-    std::vector<uint16_t> seg_mask;       // per segment: bit k = an element is complete after entry k
+    // Tet strips of the matrix-free operators (see pack_strips): per block at
+    // most kThreads segments of about equal length, magnetic segments first.
+    std::vector<uint16_t> seg_ent;        // window updates; each segment padded to a multiple of 8, 16 zeros at the end
+    std::vector<uint32_t> seg_off;        // per segment: first entry / 8
+    std::vector<uint16_t> seg_nel;        // per segment: window updates (entries)
     std::vector<int32_t> seg_ptr;         // nblk + 1
     std::vector<int32_t> seg_nmag;        // nblk
 };
 
-// A strip segment is a sequence of window updates: entry = local vertex id
-// (14 bits) | slot (2 bits) << 14 loads that vertex into one of four window
-// slots, replacing the vertex held there; 0xFFFF ends the segment early.
-constexpr int kSegEntries = 16;
-constexpr uint16_t kSegEnd = 0xFFFF;
+// A strip segment is a sequence of window updates.  Entry = local vertex id
+// (13 bits) | element-complete flag (bit 13) | slot (2 bits) << 14: load that
+// staged vertex into one of four window slots (replacing the vertex held
+// there); when the flag is set, the window now holds exactly the four
+// vertices of the segment's next element.
+constexpr uint32_t kEntIdMask = 0x1FFFu;
+constexpr uint32_t kEntElem = 1u << 13;
+constexpr int kMaxLocal = 8191;           // staged nodes per block the entries can address
 
 int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets, const uint8_t *tags,
                  const double lo[3], const double hi[3], int32_t nb, HostMesh &out, std::string &err);
@@ -70,8 +74,9 @@ struct MeshView {
     const int32_t *blk_ptr, *blk_nmag, *halo_ptr, *halo_ids, *halo_lo;
     const uint8_t *img;
     const double *w;              // n
-    const uint4 *seg_ent;         // 2 x uint4 (kSegEntries entries) per strip segment
-    const uint16_t *seg_mask;
+    const uint4 *seg_ent;         // strip entries, 8 per uint4
+    const uint32_t *seg_off;      // per segment: first uint4 of its entries
+    const uint16_t *seg_nel;      // per segment: entries
     const int32_t *seg_ptr, *seg_nmag;
     int32_t n, nb, nblk, p0, nloc_max;
     double Lx, Ly, Lz, iLx, iLy, iLz;   // box edges and their inverses (nearest periodic image)

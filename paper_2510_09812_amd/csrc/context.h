@@ -20,7 +20,8 @@ struct DeviceBuffers {
     uint8_t *img = nullptr;
     double *w = nullptr;
     uint4 *seg_ent = nullptr;
-    uint16_t *seg_mask = nullptr;
+    uint32_t *seg_off = nullptr;
+    uint16_t *seg_nel = nullptr;
     int32_t *seg_ptr = nullptr, *seg_nmag = nullptr;
     double *m = nullptr, *mnext = nullptr, *u = nullptr, *unext = nullptr;   // 3n each
     double *ms = nullptr, *g = nullptr, *gs = nullptr, *b = nullptr, *ch2 = nullptr;

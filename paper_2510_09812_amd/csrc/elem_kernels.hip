@@ -128,10 +128,14 @@ static void run_elem(const MeshView &mv, const Op &op, hipStream_t s) {
 }
 
 // The matrix-free operators walk tet strips instead of element lists.  Each
-// thread takes one strip segment and keeps a window of four vertices in
-// registers (coordinates, fields, and the contributions accumulated for
-// them); an entry loads one staged vertex into a slot, and when an element is
-// complete after an entry the window holds exactly its four vertices.  A
+// thread takes one strip segment (at most one per thread; a block's segments
+// have about the same number of window updates) and keeps a window of four
+// vertices in registers (coordinates, fields, and the contributions
+// accumulated for them).  Each update loads one staged vertex into one slot;
+// after an update flagged as completing an element the window holds exactly
+// that element's four vertices.  Lanes step through updates in lockstep, so
+// a strip break in one lane (several loads before its next element) costs
+// the other lanes nothing.  A
 // vertex's accumulated contribution goes to LDS once, when it leaves the
 // window, and only for owned vertices.  Along a strip each element loads one
 // vertex instead of four, which cuts the LDS reads and atomics that bound the
@@ -168,8 +172,14 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
     const int s_beg = mv.seg_ptr[b];
     const int s_end = Op::kMagneticOnly ? s_beg + mv.seg_nmag[b] : mv.seg_ptr[b + 1];
     for (int sg = s_beg + static_cast<int>(threadIdx.x); sg < s_end; sg += kThreads) {
-        uint4 qa = mv.seg_ent[2 * sg], qb = mv.seg_ent[2 * sg + 1];
-        uint32_t msk = mv.seg_mask[sg];
+        const int nel = mv.seg_nel[sg];
+        // entries are consumed from the low half-word of q; the next eight are
+        // already in flight in qn (the entry array carries 16 entries of tail
+        // padding, so the lookahead stays in bounds)
+        const uint4 *src = mv.seg_ent + mv.seg_off[sg];
+        uint4 q = src[0], qn = src[1];
+        src += 2;
+        int avail = 8;
         int ids[4] = {-1, -1, -1, -1};
         T x[4][3], f[4][NF], acc[4][NC];
 #pragma unroll
@@ -177,43 +187,44 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
 #pragma unroll
             for (int a = 0; a < 3; ++a) x[j][a] = T(0);
 #pragma unroll
-            for (int q = 0; q < NF; ++q) f[j][q] = T(0);
+            for (int c = 0; c < NF; ++c) f[j][c] = T(0);
 #pragma unroll
-            for (int q = 0; q < NC; ++q) acc[j][q] = T(0);
+            for (int c = 0; c < NC; ++c) acc[j][c] = T(0);
         }
-        for (int k = 0; k < kSegEntries; ++k) {
-            const uint32_t e = qa.x & 0xFFFFu;
-            qa.x = (qa.x >> 16) | (qa.y << 16);
-            qa.y = (qa.y >> 16) | (qa.z << 16);
-            qa.z = (qa.z >> 16) | (qa.w << 16);
-            qa.w = (qa.w >> 16) | (qb.x << 16);
-            qb.x = (qb.x >> 16) | (qb.y << 16);
-            qb.y = (qb.y >> 16) | (qb.z << 16);
-            qb.z = (qb.z >> 16) | (qb.w << 16);
-            qb.w = (qb.w >> 16) | 0xFFFF0000u;
-            if (e == kSegEnd) break;
-            const int id = static_cast<int>(e & 0x3FFFu), sl = static_cast<int>(e >> 14);
+        for (int k = 0; k < nel; ++k) {
+            if (avail == 0) {
+                q = qn;
+                qn = *src++;
+                avail = 8;
+            }
+            const uint32_t e = q.x & 0xFFFFu;
+            q.x = (q.x >> 16) | (q.y << 16);
+            q.y = (q.y >> 16) | (q.z << 16);
+            q.z = (q.z >> 16) | (q.w << 16);
+            q.w >>= 16;
+            --avail;
+            const int id = static_cast<int>(e & kEntIdMask), sl = static_cast<int>(e >> 14);
             // retire the vertex in slot sl
             int oid = ids[0];
             T oacc[NC];
 #pragma unroll
-            for (int q = 0; q < NC; ++q) oacc[q] = acc[0][q];
+            for (int c = 0; c < NC; ++c) oacc[c] = acc[0][c];
 #pragma unroll
             for (int j = 1; j < 4; ++j) {
                 const bool hit = sl == j;
                 oid = hit ? ids[j] : oid;
 #pragma unroll
-                for (int q = 0; q < NC; ++q) oacc[q] = hit ? acc[j][q] : oacc[q];
+                for (int c = 0; c < NC; ++c) oacc[c] = hit ? acc[j][c] : oacc[c];
             }
             if (oid >= 0 && oid < nb) {
 #pragma unroll
-                for (int q = 0; q < NC; ++q) atomicAdd(&st.acc[q * nb + oid], static_cast<double>(oacc[q]));
+                for (int c = 0; c < NC; ++c) atomicAdd(&st.acc[c * nb + oid], static_cast<double>(oacc[c]));
             }
             // load the new vertex into slot sl
             const T nx = st.sx[id], ny = st.sy[id], nz = st.sz[id];
             T nf[NF];
 #pragma unroll
-            for (int q = 0; q < NF; ++q) nf[q] = st.fld(q, id);
+            for (int c = 0; c < NF; ++c) nf[c] = st.fld(c, id);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const bool hit = sl == j;
@@ -222,11 +233,11 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
                 x[j][1] = hit ? ny : x[j][1];
                 x[j][2] = hit ? nz : x[j][2];
 #pragma unroll
-                for (int q = 0; q < NF; ++q) f[j][q] = hit ? nf[q] : f[j][q];
+                for (int c = 0; c < NF; ++c) f[j][c] = hit ? nf[c] : f[j][c];
 #pragma unroll
-                for (int q = 0; q < NC; ++q) acc[j][q] = hit ? T(0) : acc[j][q];
+                for (int c = 0; c < NC; ++c) acc[j][c] = hit ? T(0) : acc[j][c];
             }
-            if (msk & 1u) {
+            if (e & kEntElem) {
                 T ed[3][3];
 #pragma unroll
                 for (int kk = 0; kk < 3; ++kk)
@@ -247,15 +258,14 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int q = 0; q < NC; ++q) acc[j][q] += y[j][q];
+                    for (int c = 0; c < NC; ++c) acc[j][c] += y[j][c];
             }
-            msk >>= 1;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (ids[j] >= 0 && ids[j] < nb) {
 #pragma unroll
-                for (int q = 0; q < NC; ++q) atomicAdd(&st.acc[q * nb + ids[j]], static_cast<double>(acc[j][q]));
+                for (int c = 0; c < NC; ++c) atomicAdd(&st.acc[c * nb + ids[j]], static_cast<double>(acc[j][c]));
             }
     }
     __syncthreads();

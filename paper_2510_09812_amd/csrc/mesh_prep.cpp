@@ -55,15 +55,10 @@ int nodes_per_block(int32_t requested, int64_t n) {
 }
 
 // Orders one group of a block's elements (4 local vertex ids each) into
-// strips of face-adjacent tetrahedra (greedy walk that prefers the neighbour
-// with the fewest unvisited neighbours) and packs them into segments of
-// kSegEntries window updates.  Each element after the first of a strip
-// shares a face with its predecessor, so it costs one vertex load; at a strip
-// break the missing vertices are loaded before the element.  A new vertex
-// replaces a slot whose vertex the element does not use (empty first, else
-// the least recently used), so the four slots always hold exactly the
-// element's vertices when it is computed.
-static void build_strips(const uint16_t *lc, int32_t m, std::vector<uint16_t> &ent, std::vector<uint16_t> &mask) {
+// strips of face-adjacent tetrahedra: a greedy walk that prefers the
+// neighbour with the fewest unvisited neighbours.
+static void strip_order(const uint16_t *lc, int32_t m, std::vector<int32_t> &order) {
+    order.clear();
     if (m <= 0) return;
     std::vector<std::pair<uint64_t, int32_t>> faces;
     faces.reserve(4 * static_cast<size_t>(m));
@@ -94,7 +89,6 @@ static void build_strips(const uint16_t *lc, int32_t m, std::vector<uint16_t> &e
         for (int j = 0; j < nadj[e]; ++j) k += !vis[adj[4 * e + j]];
         return k;
     };
-    std::vector<int32_t> order;
     order.reserve(static_cast<size_t>(m));
     for (int32_t s0 = 0; s0 < m; ++s0) {
         if (vis[s0]) continue;
@@ -115,17 +109,28 @@ static void build_strips(const uint16_t *lc, int32_t m, std::vector<uint16_t> &e
             order.push_back(cur);
         }
     }
+}
+
+// Packs a strip order into segments of at most `budget` window updates (an
+// element's updates never straddle two segments).  Along a strip an element
+// costs one vertex load; at a strip break or a segment start the missing
+// vertices are loaded first.  A new vertex replaces a slot whose vertex the
+// element does not use (empty first, else the least recently used), so the
+// four slots hold exactly the element's vertices at its flagged entry.
+// With `emit` false only the number of segments is returned.
+static int32_t pack_strips(const uint16_t *lc, const std::vector<int32_t> &order, int budget, bool emit,
+                           std::vector<uint16_t> &ent, std::vector<uint32_t> &off, std::vector<uint16_t> &nent) {
     int32_t win[4] = {-1, -1, -1, -1};
     int64_t lru[4] = {0, 0, 0, 0}, clock = 0;
     int used = 0;
-    uint16_t seg[kSegEntries], msk = 0;
+    int32_t segs = 0;
     auto close = [&]() {
-        for (int k = used; k < kSegEntries; ++k) seg[k] = kSegEnd;
-        ent.insert(ent.end(), seg, seg + kSegEntries);
-        mask.push_back(msk);
+        if (emit) {
+            nent.push_back(static_cast<uint16_t>(used));
+            while (ent.size() % 8) ent.push_back(0);
+        }
         for (int k = 0; k < 4; ++k) win[k] = -1;
         used = 0;
-        msk = 0;
     };
     for (int32_t e : order) {
         const int32_t v[4] = {lc[4 * e], lc[4 * e + 1], lc[4 * e + 2], lc[4 * e + 3]};
@@ -133,7 +138,14 @@ static void build_strips(const uint16_t *lc, int32_t m, std::vector<uint16_t> &e
         auto in_elem = [&](int32_t x) { return x == v[0] || x == v[1] || x == v[2] || x == v[3]; };
         int nnew = 0;
         for (int j = 0; j < 4; ++j) nnew += !in_win(v[j]);
-        if (used + nnew > kSegEntries) close();
+        if (used > 0 && used + nnew > budget) {
+            close();
+            nnew = 4;
+        }
+        if (used == 0) {
+            ++segs;
+            if (emit) off.push_back(static_cast<uint32_t>(ent.size() / 8));
+        }
         for (int j = 0; j < 4; ++j) {
             if (in_win(v[j])) continue;
             int slot = -1;
@@ -143,13 +155,15 @@ static void build_strips(const uint16_t *lc, int32_t m, std::vector<uint16_t> &e
                 if (slot < 0 || lru[k] < lru[slot]) slot = k;
             }
             win[slot] = v[j];
-            seg[used++] = static_cast<uint16_t>(v[j] | (slot << 14));
+            ++used;
+            if (emit) ent.push_back(static_cast<uint16_t>(v[j] | (slot << 14)));
         }
-        msk |= static_cast<uint16_t>(1u << (used - 1));
+        if (emit) ent.back() = static_cast<uint16_t>(ent.back() | kEntElem);
         for (int k = 0; k < 4; ++k)
             if (in_elem(win[k])) lru[k] = ++clock;
     }
     if (used > 0) close();
+    return segs;
 }
 
 int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets, const uint8_t *tags,
@@ -293,10 +307,11 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
     M.seg_ptr.assign(static_cast<size_t>(M.nblk) + 1, 0);
     M.seg_nmag.assign(static_cast<size_t>(M.nblk), 0);
     M.seg_ent.clear();
-    M.seg_mask.clear();
+    M.seg_off.clear();
+    M.seg_nel.clear();
     M.halo_ids.clear();
     M.nloc_max = 0;
-    std::vector<int32_t> halo;
+    std::vector<int32_t> halo, ord_mag, ord_rest;
     for (int32_t b = 0; b < M.nblk; ++b) {
         const int32_t n0b = b * nb, n1b = std::min(n0b + nb, n);
         M.blk_ptr[b] = static_cast<int32_t>(cnt[b]);
@@ -325,7 +340,7 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
         std::sort(halo.begin(), halo.end());
         halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
         const int32_t nloc = nb + static_cast<int32_t>(halo.size());
-        if (nloc > 16383) { err = "element block too large for 14-bit local indices"; return GSPM_E_ARG; }
+        if (nloc > kMaxLocal) { err = "element block too large for 13-bit local indices"; return GSPM_E_ARG; }
         M.nloc_max = std::max(M.nloc_max, nloc);
         M.halo_lo[b] = static_cast<int32_t>(std::lower_bound(halo.begin(), halo.end(), n0b) - halo.begin());
         M.halo_ptr[b + 1] = M.halo_ptr[b] + static_cast<int32_t>(halo.size());
@@ -351,16 +366,36 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
         for (int32_t v : halo) check(v);
         M.img[b] = far ? 1 : 0;
         M.halo_ids.insert(M.halo_ids.end(), halo.begin(), halo.end());
-        // strips: magnetic elements, then the rest
+        // strips: magnetic elements, then the rest; the smallest update budget
+        // per segment that fits the block into kThreads segments (one per
+        // thread of the operator kernels, all of about the same length)
         const uint16_t *lc = M.lconn.data() + 4 * cnt[b];
+        const uint16_t *lc_rest = lc + 4 * static_cast<size_t>(nmag);
         const int32_t nall = static_cast<int32_t>(cnt[b + 1] - cnt[b]);
-        M.seg_ptr[b] = static_cast<int32_t>(M.seg_mask.size());
-        build_strips(lc, nmag, M.seg_ent, M.seg_mask);
-        M.seg_nmag[b] = static_cast<int32_t>(M.seg_mask.size()) - M.seg_ptr[b];
-        build_strips(lc + 4 * static_cast<size_t>(nmag), nall - nmag, M.seg_ent, M.seg_mask);
+        strip_order(lc, nmag, ord_mag);
+        strip_order(lc_rest, nall - nmag, ord_rest);
+        auto nsegs = [&](int budget) {
+            return pack_strips(lc, ord_mag, budget, false, M.seg_ent, M.seg_off, M.seg_nel) +
+                   pack_strips(lc_rest, ord_rest, budget, false, M.seg_ent, M.seg_off, M.seg_nel);
+        };
+        int hi_b = 16;
+        while (nsegs(hi_b) > kThreads) hi_b *= 2;   // one element always fits: the loop ends
+        int lo_b = std::max(4, hi_b / 2 + 1);
+        if (hi_b == 16) lo_b = 4;
+        while (lo_b < hi_b) {
+            const int mid = (lo_b + hi_b) / 2;
+            if (nsegs(mid) <= kThreads) hi_b = mid;
+            else lo_b = mid + 1;
+        }
+        lo_b = hi_b;
+        M.seg_ptr[b] = static_cast<int32_t>(M.seg_nel.size());
+        pack_strips(lc, ord_mag, lo_b, true, M.seg_ent, M.seg_off, M.seg_nel);
+        M.seg_nmag[b] = static_cast<int32_t>(M.seg_nel.size()) - M.seg_ptr[b];
+        pack_strips(lc_rest, ord_rest, lo_b, true, M.seg_ent, M.seg_off, M.seg_nel);
     }
     M.blk_ptr[M.nblk] = static_cast<int32_t>(M.ncopies);
-    M.seg_ptr[M.nblk] = static_cast<int32_t>(M.seg_mask.size());
+    M.seg_ptr[M.nblk] = static_cast<int32_t>(M.seg_nel.size());
+    M.seg_ent.resize(M.seg_ent.size() + 16, 0);   // lookahead of the operator kernels stays in bounds
     M.nhalo = static_cast<int64_t>(M.halo_ids.size());
     return GSPM_OK;
 }
