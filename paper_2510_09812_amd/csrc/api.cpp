@@ -231,8 +231,22 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     hipSetDevice(c->device);
     HostMesh hm;
     std::string err;
-    int rc = prepare_mesh(n_nodes, xyz, n_tets, tets, tags, lo, hi, nodes_per_block(c->block_nodes, n_nodes), hm, err);
-    if (rc) return fail(c, static_cast<gspm_status>(rc), "upload_mesh: " + err);
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+        return fail(c, GSPM_E_DEVICE, "upload_mesh: cannot query the LDS size");
+    int32_t nb = nodes_per_block(c->block_nodes, n_nodes);
+    int rc;
+    for (;;) {
+        rc = prepare_mesh(n_nodes, xyz, n_tets, tets, tags, lo, hi, nb, hm, err);
+        if (rc) return fail(c, static_cast<gspm_status>(rc), "upload_mesh: " + err);
+        const size_t need = elem_lds_bytes(hm.nb, hm.nloc_max);
+        if (need <= static_cast<size_t>(lds_max)) break;
+        if (c->block_nodes != 0 || nb <= 64)
+            return fail(c, GSPM_E_ARG, "upload_mesh: blocks of " + std::to_string(nb) + " nodes need " +
+                                           std::to_string(need) + " bytes of LDS per workgroup, the device has " +
+                                           std::to_string(lds_max) + "; use smaller block_nodes");
+        nb /= 2;                   // automatic block size: halve until the element kernels fit
+    }
     c->release_mesh();
     const size_t n = static_cast<size_t>(hm.n), n3 = 3 * n;
     auto &d = c->d;

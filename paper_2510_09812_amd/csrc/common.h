@@ -192,6 +192,9 @@ void launch_zero_ring(const CGScalars &cg, int ns, int rr_from, int rr_to, int p
 // --------------------------------------------------------------- utilities
 
 int nodes_per_block(int32_t requested, int64_t n);
+// Largest dynamic LDS request of the element kernels for blocks of nb owned
+// nodes and at most nloc_max staged nodes (elem_kernels.hip).
+size_t elem_lds_bytes(int32_t nb, int32_t nloc_max);
 double carlson_rd(double x, double y, double z);
 void demag_factors(double a, double b, double c, double N[3]);
 

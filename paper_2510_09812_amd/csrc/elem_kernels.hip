@@ -25,6 +25,8 @@
 //   field RHS   b_i     = sum_j M^e_ij (y_j + c h^e_j)
 // with h^e_j the local field of App. B at vertex j (anisotropy, Zeeman, far
 // field, magnetoelastic with the element's total strain).
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace gspm {
@@ -912,6 +914,14 @@ __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Mat
 }
 
 // --------------------------------------------------------------- launchers
+
+// The launches of this file request sizeof(double) NC nb + sizeof(T) (3 + NF)
+// nloc_max bytes (energy pass: 8 (nb + 9 nloc_max)); the field right-hand
+// side (FP64, NC = NF = 6) is the largest.
+size_t elem_lds_bytes(int32_t nb, int32_t nloc_max) {
+    const size_t b = static_cast<size_t>(nb), l = static_cast<size_t>(nloc_max);
+    return std::max(sizeof(double) * 6 * b + sizeof(double) * 9 * l, sizeof(double) * (b + 9 * l));
+}
 
 namespace {
 template <class T>

@@ -224,3 +224,16 @@ def test_cube47_sphere_steps_match_oracle():
     sim, orc, st, ost = _run_both(case, 3)
     _compare_states(sim, orc, st, ost, 1e-6)
     sim.close()
+
+
+def test_block_size_beyond_lds_is_rejected_at_upload():
+    """Blocks whose staged nodes do not fit the workgroup's LDS are refused at
+    upload with GSPM_E_ARG (an explicit block size) instead of failing at the
+    first launch; the automatic block size fits."""
+    case = w.cube47_sphere()
+    with pytest.raises(gspm.GspmError) as e:
+        gspm.Simulation(case.mesh, case.params, block_nodes=1024)
+    assert e.value.status == gspm.GSPM_E_ARG and "LDS" in str(e.value)
+    sim = gspm.Simulation(case.mesh, case.params)
+    assert sim.mesh_info()["n_unique"] == 97336
+    sim.close()
