@@ -126,7 +126,7 @@ void gspm_ctx::release_mesh() {
     auto &b = d;
     dev_free(b.x); dev_free(b.lconn); dev_free(b.blk_ptr); dev_free(b.blk_nmag); dev_free(b.w);
     dev_free(b.halo_ptr); dev_free(b.halo_ids); dev_free(b.halo_lo); dev_free(b.img);
-    dev_free(b.seg_ent); dev_free(b.seg_off); dev_free(b.seg_nel); dev_free(b.seg_ptr); dev_free(b.seg_nmag);
+    dev_free(b.stc64); dev_free(b.stc32); dev_free(b.seg_ent); dev_free(b.seg_off); dev_free(b.seg_nel); dev_free(b.seg_ptr); dev_free(b.seg_nmag);
     dev_free(b.m); dev_free(b.mnext); dev_free(b.u); dev_free(b.unext);
     dev_free(b.ms); dev_free(b.g); dev_free(b.gs); dev_free(b.b); dev_free(b.ch2);
     dev_free(b.r); dev_free(b.p); dev_free(b.p2); dev_free(b.q);
@@ -260,6 +260,9 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     rc = rc ? rc : dev_alloc(c, &d.halo_lo, hm.halo_lo.size());
     rc = rc ? rc : dev_alloc(c, &d.img, hm.img.size());
     rc = rc ? rc : dev_alloc(c, &d.w, n);
+    const size_t nstc = static_cast<size_t>(hm.nblk) * hm.nb + hm.halo_ids.size();
+    rc = rc ? rc : dev_alloc(c, &d.stc64, 3 * nstc);
+    rc = rc ? rc : dev_alloc(c, &d.stc32, 3 * nstc);
     const size_t nseg = hm.seg_nel.size();
     rc = rc ? rc : dev_alloc(c, &d.seg_ent, hm.seg_ent.size() / 8);
     rc = rc ? rc : dev_alloc(c, &d.seg_off, nseg);
@@ -346,6 +349,9 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     mv.halo_ids = d.halo_ids;
     mv.halo_lo = d.halo_lo;
     mv.img = d.img;
+    mv.stc64 = d.stc64;
+    mv.stc32 = d.stc32;
+    mv.nstc = static_cast<int64_t>(static_cast<size_t>(hm.nblk) * hm.nb + hm.halo_ids.size());
     mv.seg_ent = d.seg_ent;
     mv.seg_off = d.seg_off;
     mv.seg_nel = d.seg_nel;
@@ -373,6 +379,12 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->cg_in.iters = d.cgi_flags ? d.cgi_flags + kMaxComp : nullptr;
     c->cg_in.ring = kRing;
     c->dargs.vc = hm.vc;
+    launch_stage_coords(mv, d.stc64, d.stc32, c->stream);
+    rc = hip_check(c, hipStreamSynchronize(c->stream), "upload_mesh");
+    if (rc) {
+        c->release_mesh();
+        return static_cast<gspm_status>(rc);
+    }
     c->have_mesh = true;
     c->have_m = false;
     return GSPM_OK;

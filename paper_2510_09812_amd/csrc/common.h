@@ -74,6 +74,9 @@ struct MeshView {
     const int32_t *blk_ptr, *blk_nmag, *halo_ptr, *halo_ids, *halo_lo;
     const uint8_t *img;
     const double *w;              // n
+    const double *stc64;          // staged coordinates per block, FP64: [3][sum of n_staged] (see stage_coords)
+    const float *stc32;           // the same scaled by 1 / len_scale, FP32
+    int64_t nstc;                 // sum over blocks of staged nodes (nb + halo count)
     const uint4 *seg_ent;         // strip entries, 8 per uint4
     const uint32_t *seg_off;      // per segment: first uint4 of its entries
     const uint16_t *seg_nel;      // per segment: entries
@@ -192,6 +195,10 @@ void launch_zero_ring(const CGScalars &cg, int ns, int rr_from, int rr_to, int p
 // --------------------------------------------------------------- utilities
 
 int nodes_per_block(int32_t requested, int64_t n);
+// Staged coordinates of every block, in block order: slot l of block b is at
+// b nb + halo_ptr[b] + l; coordinates relative to the block's first node
+// (nearest image), FP64 as is and FP32 scaled by 1 / len_scale.
+void launch_stage_coords(const MeshView &mv, double *stc64, float *stc32, hipStream_t s);
 // Largest dynamic LDS request of the element kernels for blocks of nb owned
 // nodes and at most nloc_max staged nodes (elem_kernels.hip).
 size_t elem_lds_bytes(int32_t nb, int32_t nloc_max);

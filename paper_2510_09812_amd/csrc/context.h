@@ -19,6 +19,8 @@ struct DeviceBuffers {
     int32_t *blk_ptr = nullptr, *blk_nmag = nullptr, *halo_ptr = nullptr, *halo_ids = nullptr, *halo_lo = nullptr;
     uint8_t *img = nullptr;
     double *w = nullptr;
+    double *stc64 = nullptr;
+    float *stc32 = nullptr;
     uint4 *seg_ent = nullptr;
     uint32_t *seg_off = nullptr;
     uint16_t *seg_nel = nullptr;

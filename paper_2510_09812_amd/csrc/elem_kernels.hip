@@ -129,6 +129,40 @@ static void run_elem(const MeshView &mv, const Op &op, hipStream_t s) {
     hipLaunchKernelGGL((k_elem<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
 }
 
+__global__ void __launch_bounds__(kThreads) k_stage_coords(const MeshView mv, double *stc64, float *stc32) {
+    const int b = blockIdx.x;
+    const int nb = mv.nb, n0 = b * nb, cnt = min(nb, mv.n - n0);
+    const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg);
+    const size_t base = static_cast<size_t>(b) * nb + hbeg;
+    const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0], sc = 1.0 / mv.len_scale;
+    for (int l = threadIdx.x; l < nloc; l += kThreads) {
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+        if (!(l >= cnt && l < nb)) {
+            const int g = l < nb ? n0 + l : mv.halo_ids[hbeg + l - nb];
+            cx = near_image(mv.x[g] - xr, mv.Lx, mv.iLx);
+            cy = near_image(mv.y[g] - yr, mv.Ly, mv.iLy);
+            cz = near_image(mv.z[g] - zr, mv.Lz, mv.iLz);
+        }
+        stc64[base + l] = cx;
+        stc64[mv.nstc + base + l] = cy;
+        stc64[2 * mv.nstc + base + l] = cz;
+        stc32[base + l] = static_cast<float>(sc * cx);
+        stc32[mv.nstc + base + l] = static_cast<float>(sc * cy);
+        stc32[2 * mv.nstc + base + l] = static_cast<float>(sc * cz);
+    }
+}
+
+void launch_stage_coords(const MeshView &mv, double *stc64, float *stc32, hipStream_t s) {
+    hipLaunchKernelGGL(k_stage_coords, dim3(mv.nblk), dim3(kThreads), 0, s, mv, stc64, stc32);
+}
+
+template <class T>
+__device__ __forceinline__ const T *staged_coords(const MeshView &mv);
+template <>
+__device__ __forceinline__ const double *staged_coords<double>(const MeshView &mv) { return mv.stc64; }
+template <>
+__device__ __forceinline__ const float *staged_coords<float>(const MeshView &mv) { return mv.stc32; }
+
 // The matrix-free operators walk tet strips instead of element lists.  Each
 // thread takes one strip segment (at most one per thread; a block's segments
 // have about the same number of window updates) and keeps a window of four
@@ -159,13 +193,44 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
     st.f = st.sz + mv.nloc_max;
     for (int i = threadIdx.x; i < NC * nb; i += kThreads) st.acc[i] = 0.0;
     const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0], sc = op.coord_scale;
-    for (int l = threadIdx.x; l < nloc; l += kThreads) {
-        if (l >= cnt && l < nb) continue;      // owned slots past the last node
-        const int g = l < nb ? n0 + l : mv.halo_ids[hbeg + l - nb];
-        st.sx[l] = static_cast<T>(sc * near_image(mv.x[g] - xr, mv.Lx, mv.iLx));
-        st.sy[l] = static_cast<T>(sc * near_image(mv.y[g] - yr, mv.Ly, mv.iLy));
-        st.sz[l] = static_cast<T>(sc * near_image(mv.z[g] - zr, mv.Lz, mv.iLz));
-        op.stage(st, l, g);
+    // staging, four nodes per thread at a time: all their index loads, then
+    // all their data loads, then the LDS stores (the halo gather is a chain of
+    // two dependent loads; batching keeps many of them in flight).  The
+    // coordinates come precomputed per block (contiguous, in the working
+    // precision and units), only the operand is gathered.
+    const T *stc = staged_coords<T>(mv);
+    const size_t sbase = static_cast<size_t>(b) * nb + hbeg;
+    (void)xr; (void)yr; (void)zr;
+    constexpr int kU = 4;
+    for (int l0 = threadIdx.x; l0 < nloc; l0 += kU * kThreads) {
+        int ls[kU], gs[kU];
+        bool ok[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            ls[u] = l0 + u * kThreads;
+            ok[u] = ls[u] < nloc && !(ls[u] >= cnt && ls[u] < nb);   // owned slots past the last node are empty
+            gs[u] = !ok[u] ? n0 : (ls[u] < nb ? n0 + ls[u] : mv.halo_ids[hbeg + ls[u] - nb]);
+        }
+        T cx[kU], cy[kU], cz[kU];
+        T v[kU][NF];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t o = sbase + static_cast<size_t>(ok[u] ? ls[u] : 0);
+            cx[u] = stc[o];
+            cy[u] = stc[mv.nstc + o];
+            cz[u] = stc[2 * mv.nstc + o];
+            op.fetch(gs[u], v[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (!ok[u]) continue;
+            const int l = ls[u];
+            st.sx[l] = cx[u];
+            st.sy[l] = cy[u];
+            st.sz[l] = cz[u];
+#pragma unroll
+            for (int q = 0; q < NF; ++q) st.fld(q, l) = v[u][q];
+        }
     }
     __syncthreads();
     const bool img = mv.img[b] != 0;
@@ -425,13 +490,19 @@ struct ElasticMatvecOp {
 
     template <int NF>
     __device__ __forceinline__ void stage(const Staged<T, 3, NF> &st, int l, int g) const {
+        T v[3];
+        fetch(g, v);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) st.fld(a, l) = v[a];
+    }
+
+    // the staged operand at node g: p_new = r + beta p_old (ITER), else in
+    __device__ __forceinline__ void fetch(int g, T (&v)[3]) const {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const size_t o = static_cast<size_t>(a) * n + g;
-            T v;
-            if (mode == MV_ITER) v = (k == 0) ? r[o] : r[o] + static_cast<T>(beta[0]) * in[o];
-            else v = in[o];
-            st.fld(a, l) = v;
+            if (mode == MV_ITER) v[a] = (k == 0) ? r[o] : r[o] + static_cast<T>(beta[0]) * in[o];
+            else v[a] = in[o];
         }
     }
 
@@ -580,14 +651,20 @@ struct GsMatvecOp {
 
     template <int NF>
     __device__ __forceinline__ void stage(const Staged<T, NC, NF> &st, int l, int g) const {
+        T v[NC];
+        fetch(g, v);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) st.fld(q, l) = v[q];
+    }
+
+    // the staged operand at node g (zero for components that are not live)
+    __device__ __forceinline__ void fetch(int g, T (&v)[NC]) const {
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-            if (!live[q]) continue;
             const size_t o = static_cast<size_t>(q) * n + g;
-            T v;
-            if (mode == MV_ITER) v = (k == 0) ? r[o] : r[o] + static_cast<T>(beta[q]) * in[o];
-            else v = in[o];
-            st.fld(q, l) = v;
+            if (!live[q]) v[q] = T(0);
+            else if (mode == MV_ITER) v[q] = (k == 0) ? r[o] : r[o] + static_cast<T>(beta[q]) * in[o];
+            else v[q] = in[o];
         }
     }
 
