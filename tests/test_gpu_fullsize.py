@@ -1,0 +1,74 @@
+"""Parity at the benchmark's full size and launch configuration.
+
+The 1M-node cube (970,299 unique nodes, 5,821,794 tetrahedra, three
+ellipsoidal inclusions, H = -0.5 Ms [100], dt = 10 ps, CG tolerance 1e-8),
+three steps from the workload's initial state, on the paths bench.py times:
+FP64, mixed, and mixed with the learned warm start (which is active from the
+second step, with the previous-increment term from the third).  The CPU
+oracle runs the same three steps (about a minute and a half on 16 threads).
+
+Bounds: m and mean-removed u within 1e-6 relative of the oracle (the CG
+tolerance 1e-8 and the different iteration counts of the paths leave
+differences of order 1e-8 in u); energies evaluated by the oracle on each
+GPU state within 1e-9 of the GPU's own; unit length on magnetic nodes.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as w
+from paper_2510_09812_amd import gspm
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 3
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _demean(u):
+    return u - u.mean(axis=0)
+
+
+@pytest.fixture(scope="module")
+def reference():
+    case = w.cube100_ellipsoids()
+    print("[fullsize] oracle: 3 steps of the 1M-node cube", flush=True)
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(case.params, hext=case.hext)
+    orc.set_m(case.m0)
+    st = orc.step(case.dt, STEPS)
+    print(f"[fullsize] oracle done: mech iters {st['mech_iters']}", flush=True)
+    return case, orc, orc.get_m(), orc.get_u()
+
+
+@pytest.mark.parametrize("path", ["fp64", "mixed", "mixed+learned"])
+def test_full_size_steps_match_oracle(reference, path):
+    case, orc, m_ref, u_ref = reference
+    precision = gspm.GSPM_FP64 if path == "fp64" else gspm.GSPM_MIXED
+    sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, precision=precision)
+    if path == "mixed+learned":
+        import os
+        wf = os.path.join(os.path.dirname(gspm.__file__), "weights", "warm_start.f32")
+        sim.mpnn_set_params(np.fromfile(wf, dtype=np.float32))
+        sim.set_warm_start(gspm.GSPM_WARM_LEARNED)
+    sim.set_m(case.m0)
+    st = sim.step(case.dt, STEPS)
+    m, u = sim.get_m(), sim.get_u()
+    em, eu = _rel(m, m_ref), _rel(_demean(u), _demean(u_ref))
+    eg = sim.energies()
+    orc.set_m(m)          # the reference state is already saved: reuse the assembled oracle
+    orc.set_u(u)
+    er = orc.energies()
+    ee = max(abs(eg[k] - er[k]) / abs(er["total"]) for k in er)
+    print(f"[fullsize] {path}: m {em:.2e} u {eu:.2e} energies on state {ee:.2e} | mech iters {st['mech_iters']} "
+          f"learned starts {st['learned_starts']} Galerkin starts {st['galerkin_starts']}", flush=True)
+    assert em < 1e-6 and eu < 1e-6
+    assert ee < 1e-9
+    r = np.linalg.norm(m, axis=1)
+    assert np.abs(r[r > 0] - 1.0).max() < 1e-14
+    if path == "mixed+learned":
+        assert st["learned_starts"] == STEPS - 1 and st["galerkin_starts"] == STEPS - 1
+    sim.close()
