@@ -180,6 +180,11 @@ gspm_status gspm_solve(gspm_ctx *ctx, gspm_op op, double eps, const double *b, d
  * GSPM_OP_ELASTIC needs gspm_set_params.  Changes no field. */
 gspm_status gspm_time_operator(gspm_ctx *ctx, gspm_op op, double eps, int32_t reps, double *avg_ms);
 
+/* Switch the per-launch timing of the elastic matvec (the create option
+ * `profile`) on or off for later gspm_step calls; the events it records add a
+ * little host and device overhead to each CG iteration. */
+gspm_status gspm_set_profile(gspm_ctx *ctx, int32_t enable);
+
 /* Mesh facts after upload: unique nodes, tetrahedra, owner blocks, element
  * copies processed per element pass, cell volume [m^3]. Pointers may be NULL. */
 gspm_status gspm_mesh_info(gspm_ctx *ctx, int64_t *n_unique, int64_t *n_tets, int64_t *n_blocks,

@@ -22,11 +22,12 @@ displacement increment from the magnetisation increment):
                h_i <- h_i + Wu [h_i ; a_i] + bu
   decoder      y_i = Wd h_i + bd                                    (3)
   increment    d = (lambda100 hbar s_m) (y - y_p0)   (zero at the pinned node)
-  start        u0 = u_prev + s d,  s = d.r0 / d.K d,  r0 = b - K u_prev
-               (the Galerkin step along d: the K-norm error of u0 is never
-               larger than that of u_prev); with the previous increment
-               e = u_prev - u_prev2 also available, u0 = u_prev + a d + c e
-               with (a, c) the Galerkin solution on span{d, e}
+  start        u0 = u_prev + s d,  s = (K d).r0 / |K d|^2,  r0 = b - K u_prev
+               (the step along d that minimises the residual 2-norm, the
+               quantity CG's stopping test measures: |b - K u0| <= |r0|);
+               with the previous increment e = u_prev - u_prev2 also
+               available, u0 = u_prev + a d + c e with (a, c) minimising
+               |r0 - a K d - c K e| (least squares on span{K d, K e})
 
 Training minimises the mean squared difference between the mean-removed
 network output and the mean-removed normalised target
@@ -232,20 +233,20 @@ def increment(y, sm, lambda100, hbar, p0):
     return (lambda100 * hbar * sm) * (y - y[p0])
 
 
-def galerkin_scale(d, r0, Kd):
-    """Step length along d minimising the K-norm error: s = d.r0 / d.Kd."""
-    den = float(np.sum(d * Kd))
-    return float(np.sum(d * r0)) / den if den > 0 else 0.0
+def start_scale(r0, Kd):
+    """Step length along d minimising the residual 2-norm |r0 - s K d|:
+    s = (K d).r0 / (K d).(K d) (0 if K d vanishes)."""
+    den = float(np.sum(Kd * Kd))
+    return float(np.sum(Kd * r0)) / den if den > 0 else 0.0
 
 
-def galerkin2(d, e, r0, Kd, Ke):
-    """Coefficients (a, c) minimising the K-norm error of u_prev + a d + c e:
-    the 2 x 2 Galerkin system [[d.Kd, d.Ke], [e.Kd, e.Ke]] (a, c) = (d.r0, e.r0).
-    When d and e are nearly parallel (determinant below 1e-10 of the diagonal
-    product) the one of the two single-direction steps that lowers the error
-    more is taken."""
-    dd, de, ee = float(np.sum(d * Kd)), float(np.sum(d * Ke)), float(np.sum(e * Ke))
-    dr, er = float(np.sum(d * r0)), float(np.sum(e * r0))
+def start_scale2(r0, Kd, Ke):
+    """Coefficients (a, c) minimising |r0 - a K d - c K e| (normal equations
+    of the 2-column least-squares problem).  When K d and K e are nearly
+    parallel (determinant below 1e-10 of the diagonal product) the one of the
+    two single-direction steps that lowers the residual more is taken."""
+    dd, de, ee = float(np.sum(Kd * Kd)), float(np.sum(Kd * Ke)), float(np.sum(Ke * Ke))
+    dr, er = float(np.sum(Kd * r0)), float(np.sum(Ke * r0))
     det = dd * ee - de * de
     if dd > 0 and ee > 0 and det > 1e-10 * dd * ee:
         return (dr * ee - er * de) / det, (er * dd - dr * de) / det

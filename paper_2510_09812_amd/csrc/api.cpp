@@ -633,6 +633,12 @@ gspm_status gspm_time_operator(gspm_ctx *c, gspm_op op, double eps, int32_t reps
     return GSPM_OK;
 }
 
+gspm_status gspm_set_profile(gspm_ctx *c, int32_t enable) {
+    if (!c) return GSPM_E_ARG;
+    c->profile = enable != 0;
+    return GSPM_OK;
+}
+
 gspm_status gspm_mesh_info(gspm_ctx *c, int64_t *n_unique, int64_t *n_tets, int64_t *n_blocks, int64_t *n_copies,
                            double *volume) {
     if (!c) return GSPM_E_ARG;

@@ -28,7 +28,7 @@ constexpr int kPartStride = 8192;           // floats of one workgroup's gradien
 // Reduction slots (each kShards doubles) of the network's scalar buffer.
 enum RedSlot { R_DM2 = 0, R_W = 1, R_Y = 2, R_T = 5, R_LOSS = 8, R_COUNT = 9 };
 // Sharded sums of the Galerkin start (their own buffer of kGalSums x kShards).
-enum GalSlot { G_DKD = 0, G_DKE = 1, G_EKE = 2, G_DR = 3, G_ER = 4, kGalSums = 5 };
+enum GalSlot { G_DKD = 0, G_DKE = 1, G_EKE = 2, G_DR = 3, G_ER = 4, kGalSums = 5 };   // Kd.Kd, Kd.Ke, Ke.Ke, Kd.r0, Ke.r0
 
 struct Graph {
     const int32_t *ptr, *nbr;                // CSR over unique nodes, neighbours sorted
@@ -71,8 +71,9 @@ void launch_loss_backward(const Graph &g, const MeshView &mv, const Net &net, co
                           float *grad, hipStream_t s);
 void launch_adam(float *master, const float *grad, float *m1, float *m2, float lr, int64_t t, hipStream_t s);
 void launch_prepare_weights(const float *master, float *wr, uint16_t *mats, hipStream_t s);
-// Galerkin start on span{d, e} (either may be null): x += a d + c e with (a, c)
-// solving [[d.Kd, d.Ke], [e.Kd, e.Ke]] (a, c) = (d.r0, e.r0); when d and e are
+// Start on span{d, e} (either may be null): x += a d + c e with (a, c)
+// minimising |r0 - a K d - c K e|, i.e. solving
+// [[Kd.Kd, Kd.Ke], [Ke.Kd, Ke.Ke]] (a, c) = (Kd.r0, Ke.r0); when K d and K e are
 // nearly parallel (determinant below 1e-10 of the diagonal product) the better
 // single-direction step; a non-finite or non-positive system gives 0.  red
 // holds 5 sharded sums; coef (device, 2 doubles) receives (a, c).

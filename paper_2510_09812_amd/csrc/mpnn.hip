@@ -585,18 +585,19 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const float *p, float *wr,
     }
 }
 
-// Sums of the Galerkin system on span{d, e}; a null direction contributes 0.
+// Sums of the least-squares system of the start on span{d, e}: (Kd.Kd, Kd.Ke,
+// Ke.Ke, Kd.r0, Ke.r0); a null direction contributes 0.
 __global__ void __launch_bounds__(kThreads) k_galerkin_sums(int n3, const double *d, const double *kd, const double *e,
                                                             const double *ke, const double *r0, double *red) {
     double a[kGalSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n3; i += gridDim.x * kThreads) {
-        const double di = d ? d[i] : 0.0, ei = e ? e[i] : 0.0, r = r0[i];
+        const double r = r0[i];
         const double kdi = d ? kd[i] : 0.0, kei = e ? ke[i] : 0.0;
-        a[G_DKD] += di * kdi;
-        a[G_DKE] += di * kei;
-        a[G_EKE] += ei * kei;
-        a[G_DR] += di * r;
-        a[G_ER] += ei * r;
+        a[G_DKD] += kdi * kdi;
+        a[G_DKE] += kdi * kei;
+        a[G_EKE] += kei * kei;
+        a[G_DR] += kdi * r;
+        a[G_ER] += kei * r;
     }
     block_atomic_add<kGalSums>(a, red, kShards);
 }

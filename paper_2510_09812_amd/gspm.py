@@ -31,7 +31,7 @@ EXPORTS = ("gspm_create", "gspm_destroy", "gspm_upload_mesh", "gspm_set_params",
            "gspm_get_field", "gspm_step", "gspm_energies", "gspm_averages", "gspm_apply", "gspm_solve",
            "gspm_mesh_info", "gspm_demag_factors", "gspm_time_operator", "gspm_last_error",
            "gspm_set_warm_start", "gspm_mpnn_set_params", "gspm_mpnn_get_params", "gspm_mpnn_forward",
-           "gspm_mpnn_train_step", "gspm_mpnn_warm_start")
+           "gspm_mpnn_train_step", "gspm_mpnn_warm_start", "gspm_set_profile")
 
 
 class GspmError(RuntimeError):
@@ -97,6 +97,7 @@ def load() -> ctypes.CDLL:
     lib.gspm_last_error.argtypes = [P]; lib.gspm_last_error.restype = ctypes.c_char_p
     fp = ctypes.POINTER(ctypes.c_float)
     lib.gspm_set_warm_start.argtypes = [P, ctypes.c_int32]; lib.gspm_set_warm_start.restype = S
+    lib.gspm_set_profile.argtypes = [P, ctypes.c_int32]; lib.gspm_set_profile.restype = S
     lib.gspm_mpnn_set_params.argtypes = [P, fp, i64]; lib.gspm_mpnn_set_params.restype = S
     lib.gspm_mpnn_get_params.argtypes = [P, fp, i64]; lib.gspm_mpnn_get_params.restype = S
     lib.gspm_mpnn_forward.argtypes = [P, dp, dp, i64, dp, dp]; lib.gspm_mpnn_forward.restype = S
@@ -268,6 +269,10 @@ def _f32(a, n) -> np.ndarray:
     return a
 
 
+def gspm_set_profile(ctx, enable: bool) -> None:
+    _check(ctx, load().gspm_set_profile(ctx, 1 if enable else 0))
+
+
 def gspm_set_warm_start(ctx, mode: int) -> None:
     _check(ctx, load().gspm_set_warm_start(ctx, mode))
 
@@ -362,6 +367,9 @@ class Simulation:
 
     def mesh_info(self) -> dict:
         return gspm_mesh_info(self.ctx)
+
+    def set_profile(self, enable: bool):
+        gspm_set_profile(self.ctx, enable)
 
     def set_warm_start(self, mode: int):
         gspm_set_warm_start(self.ctx, mode)

@@ -161,7 +161,7 @@ def test_learned_start_matches_oracle_galerkin_step():
     sim.set_u(u)
     u0, (s, c0) = sim.mpnn_warm_start(mp)
     assert c0 == 0.0
-    # oracle: d from the emulated network, r0 = b - K u, s = d.r0 / d.K d
+    # oracle: d from the emulated network, r0 = b - K u, s = (K d).r0 / |K d|^2
     mu, mpu, wts = _oracle_inputs(orc, m, mp)
     orc.set_m(m)
     x, sm = N.features(mu, mpu, wts)
@@ -174,15 +174,14 @@ def test_learned_start_matches_oracle_galerkin_step():
     r0 = b - orc.apply(O.OP_ELASTIC, uu)
     r0[p0] = 0.0
     kd = orc.apply(O.OP_ELASTIC, d)
-    s_ref = N.galerkin_scale(d, r0, kd)
+    s_ref = N.start_scale(r0, kd)
     step_gpu = _unique(orc, u0) - uu
     print(f"s gpu {s:.6e} oracle {s_ref:.6e}; step rel err {_rel(step_gpu, s_ref * d):.2e}", flush=True)
     assert abs(s - s_ref) <= 3e-2 * abs(s_ref)
     assert _rel(step_gpu, s_ref * d) < 3e-2
-    # the K-norm error of the learned start is not larger than the previous start's
-    xs, _ = orc.solve(O.OP_ELASTIC, b, uu, tol=1e-13)
-    en = lambda v: float(np.sum((xs - v) * orc.apply(O.OP_ELASTIC, xs - v)))
-    assert en(_unique(orc, u0)) <= en(uu) * (1 + 1e-9)
+    # the residual of the learned start is not larger than the previous start's
+    res = lambda v: np.linalg.norm(np.delete(b - orc.apply(O.OP_ELASTIC, v), p0, axis=0))
+    assert res(_unique(orc, u0)) <= res(uu) * (1 + 1e-9)
     sim.close()
 
 
@@ -210,7 +209,7 @@ def test_steps_with_learned_start_match_plain_steps():
 
 def test_two_direction_start_matches_oracle():
     """Network increment and previous displacement increment together: the
-    GPU start against the oracle's Galerkin solution on span{d, e}."""
+    GPU start against the oracle's least-squares residual step on span{d, e}."""
     case, orc, g, m, mp = _setup(n=9, seed=407)
     params = _init_params(17, scale=0.6)
     sim = gspm.Simulation(case.mesh, case.params)
@@ -234,16 +233,15 @@ def test_two_direction_start_matches_oracle():
     b = orc.elastic_rhs()
     r0 = b - orc.apply(O.OP_ELASTIC, uu)
     r0[p0] = 0.0
-    a_ref, c_ref = N.galerkin2(d, e, r0, orc.apply(O.OP_ELASTIC, d), orc.apply(O.OP_ELASTIC, e))
+    a_ref, c_ref = N.start_scale2(r0, orc.apply(O.OP_ELASTIC, d), orc.apply(O.OP_ELASTIC, e))
     step_gpu = _unique(orc, u0) - uu
     step_ref = a_ref * d + c_ref * e
     print(f"a gpu {a:.6e} oracle {a_ref:.6e}; c gpu {c:.6e} oracle {c_ref:.6e}; "
           f"step rel err {_rel(step_gpu, step_ref):.2e}", flush=True)
     assert _rel(step_gpu, step_ref) < 3e-2
     assert abs(c - c_ref) <= 3e-2 * abs(c_ref) + 3e-2 * abs(a_ref) * np.linalg.norm(d) / np.linalg.norm(e)
-    xs, _ = orc.solve(O.OP_ELASTIC, b, uu, tol=1e-13)
-    en = lambda v: float(np.sum((xs - v) * orc.apply(O.OP_ELASTIC, xs - v)))
-    assert en(_unique(orc, u0)) <= en(uu) * (1 + 1e-9)
+    res = lambda v: np.linalg.norm(np.delete(b - orc.apply(O.OP_ELASTIC, v), p0, axis=0))
+    assert res(_unique(orc, u0)) <= res(uu) * (1 + 1e-9)
     sim.close()
 
 

@@ -5,7 +5,7 @@ what the reading defines: the graph of a Kuhn lattice (14 neighbours along
 the 7 lattice directions), BF16 rounding against torch's conversion and hand
 values, mean aggregation and the i/j roles against a per-edge brute force,
 equivariance under node relabelling, the backward pass against central
-differences, the Galerkin step against a dense solve, and Adam's first step
+differences, the residual-minimising start steps against dense least squares, and Adam's first step
 against its closed form."""
 import numpy as np
 import pytest
@@ -148,7 +148,7 @@ def test_loss_ignores_constant_offsets():
     assert np.allclose(g1.sum(axis=0), 0.0, atol=1e-14)
 
 
-def test_galerkin_step_minimises_energy_error():
+def test_start_step_minimises_the_residual():
     rng = np.random.default_rng(10)
     Q = rng.standard_normal((40, 40))
     K = Q @ Q.T + 40 * np.eye(40)
@@ -156,15 +156,16 @@ def test_galerkin_step_minimises_energy_error():
     xs = np.linalg.solve(K, b)
     u = xs + 0.3 * rng.standard_normal(40)
     d = (xs - u) + 0.2 * rng.standard_normal(40)
-    s = N.galerkin_scale(d, b - K @ u, K @ d)
-    err = lambda v: (xs - v) @ K @ (xs - v)
+    r0 = b - K @ u
+    s = N.start_scale(r0, K @ d)
+    res = lambda v: np.linalg.norm(b - K @ v)
     grid = np.linspace(s - 1, s + 1, 2001)
-    assert err(u + s * d) <= min(err(u + q * d) for q in grid) + 1e-12
-    assert err(u + s * d) <= err(u)
-    assert N.galerkin_scale(np.zeros(40), b, np.zeros(40)) == 0.0
+    assert res(u + s * d) <= min(res(u + q * d) for q in grid) + 1e-12
+    assert res(u + s * d) <= res(u)
+    assert N.start_scale(r0, np.zeros(40)) == 0.0
 
 
-def test_two_direction_galerkin_step_is_the_energy_projection():
+def test_two_direction_start_is_the_least_squares_residual():
     rng = np.random.default_rng(14)
     Q = rng.standard_normal((50, 50))
     K = Q @ Q.T + 50 * np.eye(50)
@@ -173,16 +174,16 @@ def test_two_direction_galerkin_step_is_the_energy_projection():
     u = xs + 0.3 * rng.standard_normal(50)
     d = (xs - u) + 0.3 * rng.standard_normal(50)
     e = 0.5 * (xs - u) + 0.3 * rng.standard_normal(50)
-    a, c = N.galerkin2(d, e, b - K @ u, K @ d, K @ e)
-    # the K-orthogonal projection of the error onto span{d, e}, by a dense solve
-    V = np.stack([d, e], axis=1)
-    coef = np.linalg.solve(V.T @ K @ V, V.T @ K @ (xs - u))
+    r0 = b - K @ u
+    a, c = N.start_scale2(r0, K @ d, K @ e)
+    # least squares on span{K d, K e}, by a dense solver
+    coef, *_ = np.linalg.lstsq(np.stack([K @ d, K @ e], axis=1), r0, rcond=None)
     assert np.allclose([a, c], coef, rtol=1e-10)
-    err = lambda v: (xs - v) @ K @ (xs - v)
-    assert err(u + a * d + c * e) <= min(err(u), err(u + N.galerkin_scale(d, b - K @ u, K @ d) * d)) + 1e-12
+    res = lambda v: np.linalg.norm(b - K @ v)
+    assert res(u + a * d + c * e) <= min(res(u), res(u + N.start_scale(r0, K @ d) * d)) + 1e-12
     # parallel directions fall back to one step
-    a2, c2 = N.galerkin2(d, 2 * d, b - K @ u, K @ d, 2 * (K @ d))
-    assert np.isclose(a2 + 2 * c2, N.galerkin_scale(d, b - K @ u, K @ d))
+    a2, c2 = N.start_scale2(r0, K @ d, 2 * (K @ d))
+    assert np.isclose(a2 + 2 * c2, N.start_scale(r0, K @ d))
 
 
 def test_increment_zero_at_pinned_node():
