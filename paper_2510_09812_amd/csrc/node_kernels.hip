@@ -8,6 +8,17 @@ namespace gspm {
 
 namespace {
 
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+};
+
 inline int node_grid(int64_t n) {
     const int64_t g = (n + kThreads - 1) / kThreads;
     return static_cast<int>(g < 2048 ? (g > 0 ? g : 1) : 2048);
@@ -176,17 +187,45 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint
     double alpha[3];
     for (int s = 0; s < 3; ++s) alpha[s] = live[s] ? t[s] / t[3 + s] : 0.0;
     double part[3] = {0.0, 0.0, 0.0};
-    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
-        for (int c = 0; c < nc; ++c) {
-            const int s = set_of(c, joint);
-            if (!live[s]) continue;
-            const size_t o = static_cast<size_t>(c) * n + i;
-            const T a = static_cast<T>(alpha[s]);
+    // per component: a scalar head up to the first 16-byte boundary, a body of
+    // 16-byte vectors (4 floats or 2 doubles per lane per load), a scalar tail
+    constexpr int W = 16 / sizeof(T);
+    using V = typename Vec16<T>::type;
+    const int tid = blockIdx.x * kThreads + threadIdx.x, nthr = gridDim.x * kThreads;
+    for (int c = 0; c < nc; ++c) {
+        const int s = set_of(c, joint);
+        if (!live[s]) continue;
+        const size_t c0 = static_cast<size_t>(c) * n;
+        const T a = static_cast<T>(alpha[s]);
+        const int head = min(n, static_cast<int>((W - c0 % W) % W));
+        const int nv = (n - head) / W;
+        auto scalar = [&](int i) {
+            const size_t o = c0 + i;
             x[o] += a * p[o];
             const T rv = r[o] - a * q[o];
             r[o] = rv;
             part[s] += static_cast<double>(rv) * rv;
+        };
+        if (tid < head) scalar(tid);
+        for (int v = tid; v < nv; v += nthr) {
+            const size_t o = c0 + head + static_cast<size_t>(v) * W;
+            V xv = *reinterpret_cast<const V *>(x + o);
+            V rv = *reinterpret_cast<const V *>(r + o);
+            const V pv = *reinterpret_cast<const V *>(p + o);
+            const V qv = *reinterpret_cast<const V *>(q + o);
+            T *xe = reinterpret_cast<T *>(&xv), *re = reinterpret_cast<T *>(&rv);
+            const T *pe = reinterpret_cast<const T *>(&pv), *qe = reinterpret_cast<const T *>(&qv);
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                xe[j] += a * pe[j];
+                re[j] -= a * qe[j];
+                part[s] += static_cast<double>(re[j]) * re[j];
+            }
+            *reinterpret_cast<V *>(x + o) = xv;
+            *reinterpret_cast<V *>(r + o) = rv;
         }
+        for (int i = head + nv * W + tid; i < n; i += nthr) scalar(i);
+    }
     block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride());
 }
 
