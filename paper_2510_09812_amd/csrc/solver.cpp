@@ -151,7 +151,7 @@ CgResult cg_fp64(gspm_ctx *c, int nc, bool joint, double *x, double tol, int max
 template <class Resid, class Iter32>
 CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int maxit, SolveKind kind, double scale,
                   Resid resid, Iter32 iter32) {
-    constexpr double kInnerFloor = 1e-5;
+    constexpr double kInnerFloor = 1e-6;
     hipStream_t s = c->stream;
     const int ns = joint ? 1 : nc, n = c->n;
     const size_t n3 = 3 * static_cast<size_t>(n);
