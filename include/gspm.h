@@ -110,12 +110,13 @@ typedef struct {
     int64_t gs_iters_stage[8]; /* per scalar solve: g1 g2 g3, g*1 g*2, m**1 m**2 m**3 */
     double dm_avg;          /* mean |m^{n+1} - m^n| over magnetic nodes, last step (Sec. 3.2) */
     double elapsed_ms;      /* wall time of the call on the device stream */
-    double matvec_ms;       /* profile mode: summed duration of the elastic matvec launches */
+    double matvec_ms;       /* profile mode: summed kernel duration of the working elastic matvec
+                               launches (those issued after convergence, which exit at once, excluded) */
     int64_t matvec_launches;/* profile mode: number of elastic matvec launches timed */
     int64_t refinements;    /* GSPM_MIXED: outer FP64 residual evaluations that started an FP32 inner solve */
     int64_t learned_starts; /* steps whose elastic start used the network's increment */
-    int64_t galerkin_starts;/* steps whose elastic start was a Galerkin step (learned or extrapolated) */
-    double warm_coef[2];    /* last Galerkin start: coefficients of the network increment and of the
+    int64_t minres_starts; /* steps whose elastic start was a minimum-residual step (learned or extrapolated) */
+    double warm_coef[2];    /* last minimum-residual start: coefficients of the network increment and of the
                                previous displacement increment (0 if unused) */
 } gspm_step_stats;
 
@@ -181,8 +182,10 @@ gspm_status gspm_solve(gspm_ctx *ctx, gspm_op op, double eps, const double *b, d
 gspm_status gspm_time_operator(gspm_ctx *ctx, gspm_op op, double eps, int32_t reps, double *avg_ms);
 
 /* Switch the per-launch timing of the elastic matvec (the create option
- * `profile`) on or off for later gspm_step calls; the events it records add a
- * little host and device overhead to each CG iteration. */
+ * `profile`) on or off for later gspm_step calls.  Each matvec kernel is
+ * launched with a start/stop event pair that the runtime records at the
+ * kernel's own execution (its duration alone, as a kernel trace reports it);
+ * the events add a little host overhead to each CG iteration. */
 gspm_status gspm_set_profile(gspm_ctx *ctx, int32_t enable);
 
 /* Mesh facts after upload: unique nodes, tetrahedra, owner blocks, element
@@ -206,10 +209,11 @@ gspm_status gspm_demag_factors(double a, double b, double c, double N[3]);
  * the magnetisation increment m^n - m^{n-1}.  With e = u^{n-1} - u^{n-2} the
  * previous displacement increment (the long-wavelength response a local
  * network cannot see), the solve starts from u^{n-1} + a d + c e with (a, c)
- * the Galerkin coefficients on span{d, e}:
- *   [[d.Kd, d.Ke], [e.Kd, e.Ke]] (a, c) = (d.r0, e.r0),  r0 = b - K u^{n-1},
- * which never increases the K-norm error of the start (nearly parallel d, e:
- * the better single-direction step).  CG then runs to the same tolerance, so
+ * the coefficients that minimise the start's residual 2-norm (the quantity
+ * the CG stopping test measures) on span{d, e}:
+ *   [[Kd.Kd, Kd.Ke], [Ke.Kd, Ke.Ke]] (a, c) = (Kd.r0, Ke.r0),  r0 = b - K u^{n-1},
+ * so |b - K u0| <= |r0| whatever the network predicts (nearly parallel K d,
+ * K e: the better single-direction step).  CG then runs to the same tolerance, so
  * the solution is that of the plain path within the CG tolerance.
  *
  * Network (hidden width 64, weights and stored activations BF16, FP32
@@ -264,7 +268,8 @@ gspm_status gspm_mpnn_train_step(gspm_ctx *ctx, const double *m_prev, const doub
 /* The learned start for the current state (M and U as set): forms the
  * elastic right-hand side at m, evaluates the network at (m_prev, m) and
  * writes u0 = u + a d + c e (n_nodes x 3) with e = u - u_prev when u_prev is
- * given (else c = 0), and coef = (a, c) (nullable).  Changes no field. */
+ * given (else c = 0), and coef = (a, c) (nullable), (a, c) minimising
+ * |b - K u0| as above.  Changes no field. */
 gspm_status gspm_mpnn_warm_start(gspm_ctx *ctx, const double *m_prev, const double *u_prev, int64_t n_nodes,
                                  double *u0, double coef[2]);
 

@@ -272,7 +272,7 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.mprev,
                         &d.uprev, &d.du_prev, &d.kdu})
         rc = rc ? rc : dev_alloc(c, p, n3);
-    rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kGalSums) * kShards);
+    rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kMrSums) * kShards);
     rc = rc ? rc : dev_alloc(c, &d.wcoef, 2);
     rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
     rc = rc ? rc : dev_alloc(c, &d.sums, 9 * kShards);

@@ -158,9 +158,12 @@ void launch_mass_rhs(const MeshView &mv, const double *y, const double *ch2, dou
 // rr[0] += r.r.  ITER (CG iteration k): p_new = r + beta_k p_old (p_new = r at
 // k = 0, with beta_k = rr[k] / rr[k-1] and the convergence test of rr[k] done
 // first), q = A p_new, pq[k] += p_new.q; p_old = in, p_new = pout.
+// ev (nullable): two events the runtime records at the kernel's own start and
+// end (profiling: the pair times the kernel alone, without launch gaps).
 template <class T>
 void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode mode, const T *in, T *out, const T *b,
-                           const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);
+                           const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s,
+                           const hipEvent_t *ev = nullptr);
 template <class T>
 void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
                       const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);

@@ -43,8 +43,8 @@ struct DeviceBuffers {
     double *uprev = nullptr;      // 3n: u^{n-2}, for the previous displacement increment
     double *du_prev = nullptr;    // 3n: u^{n-1} - u^{n-2} (warm start scratch)
     double *kdu = nullptr;        // 3n: K (u^{n-1} - u^{n-2}) (warm start scratch)
-    double *wred = nullptr;       // kGalSums x kShards: Galerkin sums
-    double *wcoef = nullptr;      // 2: coefficients of the last Galerkin start
+    double *wred = nullptr;       // kMrSums x kShards: minimum-residual sums
+    double *wcoef = nullptr;      // 2: coefficients of the last minimum-residual start
 };
 
 // Device state of the learned warm start (allocated on first use).
@@ -129,9 +129,9 @@ int hip_check(gspm_ctx *c, hipError_t e, const char *what);
 // Warm start of the elastic solve on the right-hand side b: x (holding u^{n-1})
 // becomes u^{n-1} + a d + c e, d the network's increment at (m, mprev) (when
 // mprev != nullptr), e = u^{n-1} - uprev (when uprev != nullptr), (a, c) the
-// Galerkin coefficients (stored at d.wcoef).  Leaves the CG scalars as
+// coefficients minimising |b - K x| (stored at d.wcoef).  Leaves the CG scalars as
 // cg_prepare set them.
-int galerkin_start(gspm_ctx *c, const double *m, const double *mprev, const double *uprev, double *x, const double *b);
+int minres_start(gspm_ctx *c, const double *m, const double *mprev, const double *uprev, double *x, const double *b);
 // Caller-order n0 x 3 <-> internal component-major 3 x n (api.cpp).
 int gather_user(gspm_ctx *c, const double *v, std::vector<double> &out);
 void scatter_user(const gspm_ctx *c, const std::vector<double> &in, double *out);

@@ -27,6 +27,8 @@
 // field, magnetoelastic with the element's total strain).
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "device_common.h"
 
 namespace gspm {
@@ -340,9 +342,12 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
 }
 
 template <class T, int NC, int NF, class Op>
-static void run_strip(const MeshView &mv, const Op &op, hipStream_t s) {
+static void run_strip(const MeshView &mv, const Op &op, hipStream_t s, const hipEvent_t *ev = nullptr) {
     const size_t lds = sizeof(double) * NC * static_cast<size_t>(mv.nb) + sizeof(T) * (3 + NF) * static_cast<size_t>(mv.nloc_max);
-    hipLaunchKernelGGL((k_strip<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
+    if (ev)
+        hipExtLaunchKernelGGL((k_strip<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, ev[0], ev[1], 0, mv, op);
+    else
+        hipLaunchKernelGGL((k_strip<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
 }
 
 // --------------------------------------------------------- cubic material
@@ -1012,7 +1017,8 @@ Cubic<T> cubic_of(const Material &m) {
 // stiffness divided by c11, which keeps every product inside FP32's normal range.
 template <class T>
 void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode mode, const T *in, T *out, const T *b,
-                           const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s) {
+                           const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s,
+                           const hipEvent_t *ev) {
     const bool nd = sizeof(T) == sizeof(float);
     Material m2 = mat;
     if (nd) {
@@ -1022,15 +1028,15 @@ void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode m
     }
     ElasticMatvecOp<T> op{in, out, b, r, pout, cg, k, static_cast<int>(mode), mv.n, tol * tol, cubic_of<T>(m2), {0},
                           {0.0}, nd ? 1.0 / mv.len_scale : 1.0};
-    run_strip<T, 3, 3>(mv, op, s);
+    run_strip<T, 3, 3>(mv, op, s, ev);
 }
 
 template void launch_elastic_matvec<double>(const MeshView &, const Material &, MatvecMode, const double *, double *,
                                             const double *, const double *, double *, const CGScalars &, int, double,
-                                            hipStream_t);
+                                            hipStream_t, const hipEvent_t *);
 template void launch_elastic_matvec<float>(const MeshView &, const Material &, MatvecMode, const float *, float *,
                                            const float *, const float *, float *, const CGScalars &, int, double,
-                                           hipStream_t);
+                                           hipStream_t, const hipEvent_t *);
 
 void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x, double *bb,
                         hipStream_t s) {

@@ -121,7 +121,7 @@ int nn_setup(gspm_ctx *c) {
 
 }  // namespace
 
-int galerkin_start(gspm_ctx *c, const double *m, const double *mprev, const double *uprev, double *x, const double *b) {
+int minres_start(gspm_ctx *c, const double *m, const double *mprev, const double *uprev, double *x, const double *b) {
     auto &nn = c->nn;
     auto &d = c->d;
     hipStream_t s = c->stream;
@@ -139,7 +139,7 @@ int galerkin_start(gspm_ctx *c, const double *m, const double *mprev, const doub
         ev = d.du_prev;
     }
     launch_elastic_matvec<double>(c->mv, c->mat, MV_RESID, x, nullptr, b, d.r, nullptr, c->cg, 0, 0.0, s);
-    mpnn::launch_galerkin(c->n, dv, d.q, ev, d.kdu, d.r, x, d.wred, d.wcoef, s);
+    mpnn::launch_minres(c->n, dv, d.q, ev, d.kdu, d.r, x, d.wred, d.wcoef, s);
     launch_zero_ring(c->cg, 1, 0, 1, 0, 0, s);
     return GSPM_OK;
 }
@@ -313,7 +313,7 @@ gspm_status gspm_mpnn_warm_start(gspm_ctx *c, const double *m_prev, const double
             hipMemcpyAsync(nn.du + static_cast<size_t>(a) * c->n + c->p0, z.data(), sizeof(double),
                            hipMemcpyHostToDevice, s);
     }
-    galerkin_start(c, d.m, nn.mp_in, u_prev ? nn.du : nullptr, d.unext, d.b);
+    minres_start(c, d.m, nn.mp_in, u_prev ? nn.du : nullptr, d.unext, d.b);
     std::vector<double> h(3 * static_cast<size_t>(c->n));
     double ch[2] = {0.0, 0.0};
     hipMemcpyAsync(h.data(), d.unext, bytes3, hipMemcpyDeviceToHost, s);

@@ -27,8 +27,8 @@ constexpr int kPartStride = 8192;           // floats of one workgroup's gradien
 
 // Reduction slots (each kShards doubles) of the network's scalar buffer.
 enum RedSlot { R_DM2 = 0, R_W = 1, R_Y = 2, R_T = 5, R_LOSS = 8, R_COUNT = 9 };
-// Sharded sums of the Galerkin start (their own buffer of kGalSums x kShards).
-enum GalSlot { G_DKD = 0, G_DKE = 1, G_EKE = 2, G_DR = 3, G_ER = 4, kGalSums = 5 };   // Kd.Kd, Kd.Ke, Ke.Ke, Kd.r0, Ke.r0
+// Sharded sums of the minimum-residual start (their own buffer of kMrSums x kShards).
+enum MrSlot { G_DKD = 0, G_DKE = 1, G_EKE = 2, G_DR = 3, G_ER = 4, kMrSums = 5 };   // Kd.Kd, Kd.Ke, Ke.Ke, Kd.r0, Ke.r0
 
 struct Graph {
     const int32_t *ptr, *nbr;                // CSR over unique nodes, neighbours sorted
@@ -77,7 +77,7 @@ void launch_prepare_weights(const float *master, float *wr, uint16_t *mats, hipS
 // nearly parallel (determinant below 1e-10 of the diagonal product) the better
 // single-direction step; a non-finite or non-positive system gives 0.  red
 // holds 5 sharded sums; coef (device, 2 doubles) receives (a, c).
-void launch_galerkin(int n, const double *d, const double *kd, const double *e, const double *ke, const double *r0,
+void launch_minres(int n, const double *d, const double *kd, const double *e, const double *ke, const double *r0,
                      double *x, double *red, double *coef, hipStream_t s);
 // out = a - b over n3 values.
 void launch_sub(int64_t n3, const double *a, const double *b, double *out, hipStream_t s);

@@ -587,9 +587,9 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const float *p, float *wr,
 
 // Sums of the least-squares system of the start on span{d, e}: (Kd.Kd, Kd.Ke,
 // Ke.Ke, Kd.r0, Ke.r0); a null direction contributes 0.
-__global__ void __launch_bounds__(kThreads) k_galerkin_sums(int n3, const double *d, const double *kd, const double *e,
+__global__ void __launch_bounds__(kThreads) k_minres_sums(int n3, const double *d, const double *kd, const double *e,
                                                             const double *ke, const double *r0, double *red) {
-    double a[kGalSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double a[kMrSums] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n3; i += gridDim.x * kThreads) {
         const double r = r0[i];
         const double kdi = d ? kd[i] : 0.0, kei = e ? ke[i] : 0.0;
@@ -599,10 +599,10 @@ __global__ void __launch_bounds__(kThreads) k_galerkin_sums(int n3, const double
         a[G_DR] += kdi * r;
         a[G_ER] += kei * r;
     }
-    block_atomic_add<kGalSums>(a, red, kShards);
+    block_atomic_add<kMrSums>(a, red, kShards);
 }
 
-__device__ __forceinline__ void galerkin_coef(const double (&t)[kGalSums], double &ca, double &cc) {
+__device__ __forceinline__ void minres_coef(const double (&t)[kMrSums], double &ca, double &cc) {
     const double dd = t[G_DKD], de = t[G_DKE], ee = t[G_EKE], dr = t[G_DR], er = t[G_ER];
     const double det = dd * ee - de * de;
     ca = cc = 0.0;
@@ -617,14 +617,14 @@ __device__ __forceinline__ void galerkin_coef(const double (&t)[kGalSums], doubl
     if (!__builtin_isfinite(ca) || !__builtin_isfinite(cc)) ca = cc = 0.0;
 }
 
-__global__ void __launch_bounds__(kThreads) k_galerkin_apply(int n3, const double *d, const double *e, double *x,
+__global__ void __launch_bounds__(kThreads) k_minres_apply(int n3, const double *d, const double *e, double *x,
                                                              const double *red, double *coef) {
-    const double *const src[kGalSums] = {red, red + kShards, red + 2 * kShards, red + 3 * kShards,
+    const double *const src[kMrSums] = {red, red + kShards, red + 2 * kShards, red + 3 * kShards,
                                          red + 4 * kShards};
-    double t[kGalSums];
-    shard_totals<kGalSums>(src, t);
+    double t[kMrSums];
+    shard_totals<kMrSums>(src, t);
     double ca, cc;
-    galerkin_coef(t, ca, cc);
+    minres_coef(t, ca, cc);
     if (blockIdx.x == 0 && threadIdx.x == 0 && coef) {
         coef[0] = ca;
         coef[1] = cc;
@@ -735,12 +735,12 @@ void launch_prepare_weights(const float *master, float *wr, uint16_t *mats, hipS
     hipLaunchKernelGGL(k_prepare, dim3(grid_for(kNParam, kThreads)), dim3(kThreads), 0, s, master, wr, mats);
 }
 
-void launch_galerkin(int n, const double *d, const double *kd, const double *e, const double *ke, const double *r0,
+void launch_minres(int n, const double *d, const double *kd, const double *e, const double *ke, const double *r0,
                      double *x, double *red, double *coef, hipStream_t s) {
     const int n3 = 3 * n;
-    launch_fill(red, kGalSums * kShards, 0.0, s);
-    hipLaunchKernelGGL(k_galerkin_sums, dim3(grid_for(n3, kThreads)), dim3(kThreads), 0, s, n3, d, kd, e, ke, r0, red);
-    hipLaunchKernelGGL(k_galerkin_apply, dim3(grid_for(n3, kThreads)), dim3(kThreads), 0, s, n3, d, e, x, red, coef);
+    launch_fill(red, kMrSums * kShards, 0.0, s);
+    hipLaunchKernelGGL(k_minres_sums, dim3(grid_for(n3, kThreads)), dim3(kThreads), 0, s, n3, d, kd, e, ke, r0, red);
+    hipLaunchKernelGGL(k_minres_apply, dim3(grid_for(n3, kThreads)), dim3(kThreads), 0, s, n3, d, e, x, red, coef);
 }
 
 void launch_sub(int64_t n3, const double *a, const double *b, double *out, hipStream_t s) {

@@ -102,10 +102,12 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
     }
 }
 
-// Profile mode: an event pair around every elastic matvec of an iteration;
-// pairs of launches issued after convergence (immediate exits) are dropped.
-void prof_begin(gspm_ctx *c, int k) {
-    if (!c->profile) return;
+// Profile mode: an event pair that the runtime records at the start and end of
+// every elastic matvec kernel of an iteration (the kernel alone, as a kernel
+// trace times it); pairs of launches issued after convergence (immediate
+// exits) are dropped.  Returns the pair to launch with, or null.
+const hipEvent_t *prof_begin(gspm_ctx *c, int k) {
+    if (!c->profile) return nullptr;
     if (c->prof_used + 2 > c->prof_ev.size()) {
         for (int i = 0; i < 256; ++i) {
             hipEvent_t e;
@@ -115,13 +117,11 @@ void prof_begin(gspm_ctx *c, int k) {
     }
     c->prof_iter.resize(c->prof_ev.size() / 2);
     c->prof_iter[c->prof_used / 2] = k;
-    hipEventRecord(c->prof_ev[c->prof_used], c->stream);
+    return &c->prof_ev[c->prof_used];
 }
 
 void prof_end(gspm_ctx *c) {
-    if (!c->profile) return;
-    hipEventRecord(c->prof_ev[c->prof_used + 1], c->stream);
-    c->prof_used += 2;
+    if (c->profile) c->prof_used += 2;
 }
 
 void prof_drop_after(gspm_ctx *c, size_t first_pair, int iters) {
@@ -246,18 +246,18 @@ CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int max
         float *P[2] = {c->d.p32, c->d.p32b};
         const double scale = 1.0 / (c->mv.len_scale * c->mat.c11);
         r = cg_mixed(c, 3, true, x, tol, maxit, kind, scale, resid, [&](int k) {
-            prof_begin(c, k);
+            const hipEvent_t *ev = prof_begin(c, k);
             launch_elastic_matvec<float>(c->mv, c->mat, MV_ITER, P[k & 1], c->d.q32, nullptr, c->d.r32,
-                                         P[(k + 1) & 1], c->cg_in, k, 1.0, s);
+                                         P[(k + 1) & 1], c->cg_in, k, 1.0, s, ev);
             prof_end(c);
             launch_cg_update<float>(c->n, 3, true, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, c->cg_in, k, s);
         });
     } else {
         double *P[2] = {c->d.p, c->d.p2};
         r = cg_fp64(c, 3, true, x, tol, maxit, kind, resid, [&](int k) {
-            prof_begin(c, k);
+            const hipEvent_t *ev = prof_begin(c, k);
             launch_elastic_matvec<double>(c->mv, c->mat, MV_ITER, P[k & 1], c->d.q, nullptr, c->d.r, P[(k + 1) & 1],
-                                          c->cg, k, tol, s);
+                                          c->cg, k, tol, s, ev);
             prof_end(c);
             launch_cg_update<double>(c->n, 3, true, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
         });
@@ -316,9 +316,9 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
         const bool net = c->warm_mode == GSPM_WARM_LEARNED && c->have_prev;
         const bool extrap = c->warm_mode != GSPM_WARM_PREVIOUS && c->commits >= 2;
         if (net || extrap) {
-            galerkin_start(c, d.m, net ? d.mprev : nullptr, extrap ? d.uprev : nullptr, d.unext, d.b);
+            minres_start(c, d.m, net ? d.mprev : nullptr, extrap ? d.uprev : nullptr, d.unext, d.b);
             st->learned_starts += net;
-            ++st->galerkin_starts;
+            ++st->minres_starts;
         }
     }
     CgResult r = cg_elastic(c, d.unext, d.b, tol, maxit, SK_MECH);
@@ -412,7 +412,7 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     st->elapsed_ms = ms;
     for (int q = 0; q < 8; ++q) st->gs_iters += st->gs_iters_stage[q];
     st->refinements = c->refinements - ref0;
-    if (st->galerkin_starts > 0) hipMemcpy(st->warm_coef, c->d.wcoef, 2 * sizeof(double), hipMemcpyDeviceToHost);
+    if (st->minres_starts > 0) hipMemcpy(st->warm_coef, c->d.wcoef, 2 * sizeof(double), hipMemcpyDeviceToHost);
     if (c->profile) {
         double tot = 0.0;
         int64_t cnt = 0;

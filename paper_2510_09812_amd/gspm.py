@@ -57,7 +57,7 @@ class gspm_step_stats(ctypes.Structure):
                 ("gs_iters", ctypes.c_int64), ("gs_iters_stage", ctypes.c_int64 * 8), ("dm_avg", ctypes.c_double),
                 ("elapsed_ms", ctypes.c_double), ("matvec_ms", ctypes.c_double),
                 ("matvec_launches", ctypes.c_int64), ("refinements", ctypes.c_int64),
-                ("learned_starts", ctypes.c_int64), ("galerkin_starts", ctypes.c_int64),
+                ("learned_starts", ctypes.c_int64), ("minres_starts", ctypes.c_int64),
                 ("warm_coef", ctypes.c_double * 2)]
 
 
@@ -192,7 +192,7 @@ def stats_dict(st: gspm_step_stats) -> dict:
     return dict(steps_done=st.steps_done, failed_step=st.failed_step, mech_iters=st.mech_iters,
                 gs_iters=st.gs_iters, gs_iters_stage=list(st.gs_iters_stage), dm_avg=st.dm_avg,
                 elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches,
-                refinements=st.refinements, learned_starts=st.learned_starts, galerkin_starts=st.galerkin_starts,
+                refinements=st.refinements, learned_starts=st.learned_starts, minres_starts=st.minres_starts,
                 warm_coef=list(st.warm_coef))
 
 

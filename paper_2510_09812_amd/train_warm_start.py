@@ -7,9 +7,10 @@ dt = 10 ps).  Step n of a trajectory gives the sample (m^{n-1}, m^n,
 u^n - u^{n-1}), u^n being the elastic solution at m^n.  Training runs Adam
 on the mean-removed MSE (gspm_mpnn_train_step: forward, loss, backward and
 update all in the library's HIP kernels), one mesh at a time.  The held-out
-trajectory reports the K-norm error left by the network start, by the
-extrapolated start and by the learned start (both directions), each as a
-fraction of the previous-step start's.
+trajectory reports, for the network start, the extrapolated start and the
+learned start (both directions), the K-norm error and the residual 2-norm
+each leaves, as a fraction of the previous-step start's.  With --eval-only
+the same evaluation of existing weights is written into their .json log.
 
     python -m paper_2510_09812_amd.train_warm_start --out paper_2510_09812_amd/weights/warm_start.f32
 """
@@ -64,17 +65,23 @@ def trajectory(sim, case, steps: int):
     return [(ms[k - 1], ms[k], us[k] - us[k - 1]) for k in range(1, steps)]
 
 
-def knorm_ratios(sim, ms, us):
-    """For held-out steps n >= 2, the K-norm error of three starts relative to
-    the previous-step start's: the network increment alone, the previous
-    increment alone (extrapolation), and both (the learned start)."""
-    out = {"network": [], "extrapolated": [], "learned": []}
+def start_ratios(sim, ms, us):
+    """For held-out steps n >= 2, the K-norm error and the residual 2-norm of
+    three starts, each relative to the previous-step start's: the network
+    increment alone, the previous increment alone (extrapolation) and both
+    (the learned start).  The network starts come from the library; the
+    extrapolated start takes the same residual-minimising coefficient the
+    library would, c = (K e).r0 / |K e|^2 with r0 = K (u^n - u^{n-1})
+    (u^n solves the step's system to the CG tolerance)."""
+    out = {"knorm": {"network": [], "extrapolated": [], "learned": []},
+           "residual": {"network": [], "extrapolated": [], "learned": []}}
     K = lambda v: sim.apply(gspm.GSPM_OP_ELASTIC, v)
     for n in range(2, len(us)):
         m_prev, m, u_prev, u_prev2, u_sol = ms[n - 1], ms[n], us[n - 1], us[n - 2], us[n]
         e0 = u_sol - u_prev
-        k0 = float(np.sum(e0 * K(e0)))
-        if k0 <= 0:
+        r0 = K(e0)
+        k0, n0 = float(np.sum(e0 * r0)), float(np.linalg.norm(r0))
+        if k0 <= 0 or n0 <= 0:
             continue
         sim.set_m(m)
         sim.set_u(u_prev)
@@ -82,10 +89,12 @@ def knorm_ratios(sim, ms, us):
         u_both, _ = sim.mpnn_warm_start(m_prev, u_prev2)
         e = u_prev - u_prev2
         ke = K(e)
-        c = float(np.sum(e * K(e0))) / float(np.sum(e * ke))
+        c = float(np.sum(ke * r0)) / float(np.sum(ke * ke))
         for key, u0 in (("network", u_net), ("learned", u_both), ("extrapolated", u_prev + c * e)):
-            r = u_sol - u0
-            out[key].append(float(np.sqrt(max(float(np.sum(r * K(r))), 0.0) / k0)))
+            err = u_sol - u0
+            kerr = K(err)
+            out["knorm"][key].append(float(np.sqrt(max(float(np.sum(err * kerr)), 0.0) / k0)))
+            out["residual"][key].append(float(np.linalg.norm(kerr)) / n0)
     return out
 
 
@@ -106,7 +115,7 @@ def main() -> int:
         params = np.fromfile(args.eval_only, dtype=np.float32)
     rng = np.random.default_rng(args.seed)
     t0 = time.perf_counter()
-    log = {"train_loss": [], "heldout_knorm_ratio": None}
+    log = {"train_loss": [], "heldout": None}
     for mi in range(0 if args.eval_only else args.meshes):
         case = w.warm_start_training(100 + mi, n=args.n)
         sim = gspm.Simulation(case.mesh, case.params, hext=case.hext)
@@ -134,15 +143,25 @@ def main() -> int:
         us.append(sim.get_u())
         ms.append(sim.get_m())
     sim.mpnn_set_params(params)
-    ratios = knorm_ratios(sim, ms, us)
+    ratios = start_ratios(sim, ms, us)
     sim.close()
-    log["heldout_knorm_ratio"] = ratios
-    for key, v in ratios.items():
-        print(f"[train] held-out K-norm error ratio {key}/previous: median {np.median(v):.3f}, mean {np.mean(v):.3f} "
-              f"over {len(v)} steps", flush=True)
+    for metric, per in ratios.items():
+        for key, v in per.items():
+            print(f"[train] held-out {metric} ratio {key}/previous: median {np.median(v):.3f}, "
+                  f"mean {np.mean(v):.3f} over {len(v)} steps", flush=True)
     print(f"[train] {time.perf_counter() - t0:.1f} s", flush=True)
     if args.eval_only:
+        logf = os.path.splitext(args.eval_only)[0] + ".json"
+        prev = {}
+        if os.path.exists(logf):
+            with open(logf) as f:
+                prev = json.load(f)
+        prev.pop("heldout_knorm_ratio", None)
+        prev["heldout"] = ratios
+        with open(logf, "w") as f:
+            json.dump(prev, f)
         return 0
+    log["heldout"] = ratios
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     params.astype(np.float32).tofile(args.out)
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:

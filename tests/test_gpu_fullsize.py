@@ -64,11 +64,11 @@ def test_full_size_steps_match_oracle(reference, path):
     er = orc.energies()
     ee = max(abs(eg[k] - er[k]) / abs(er["total"]) for k in er)
     print(f"[fullsize] {path}: m {em:.2e} u {eu:.2e} energies on state {ee:.2e} | mech iters {st['mech_iters']} "
-          f"learned starts {st['learned_starts']} Galerkin starts {st['galerkin_starts']}", flush=True)
+          f"learned starts {st['learned_starts']} min-residual starts {st['minres_starts']}", flush=True)
     assert em < 1e-6 and eu < 1e-6
     assert ee < 1e-9
     r = np.linalg.norm(m, axis=1)
     assert np.abs(r[r > 0] - 1.0).max() < 1e-14
     if path == "mixed+learned":
-        assert st["learned_starts"] == STEPS - 1 and st["galerkin_starts"] == STEPS - 1
+        assert st["learned_starts"] == STEPS - 1 and st["minres_starts"] == STEPS - 1
     sim.close()

@@ -8,7 +8,7 @@ the two differ only where an FP32-vs-FP64 difference flips a BF16 rounding
 output difference to a few ulps: relative 2-norm <= 1e-2 on y.  Gradients on
 the GPU also round the backward GEMM operands (gradients and activations) to
 BF16 once per product, the oracle's backward is exact: relative 2-norm <= 5e-2
-per parameter block and cosine >= 0.998 over the whole vector.  The Galerkin
+per parameter block and cosine >= 0.998 over the whole vector.  The residual-minimising
 step s and the start u0 follow from d: 3e-2.  The step with the learned start
 solves to the same CG tolerance as the plain step, so the states agree like
 two FP64 runs with different starts: 1e-6 relative at CG tolerance 1e-10.
@@ -150,7 +150,7 @@ def test_adam_first_step_matches_closed_form():
     sim.close()
 
 
-def test_learned_start_matches_oracle_galerkin_step():
+def test_learned_start_matches_oracle_minres_step():
     case, orc, g, m, mp = _setup(n=9, seed=405)
     params = _init_params(15, scale=0.6)
     sim = gspm.Simulation(case.mesh, case.params)
@@ -203,7 +203,7 @@ def test_steps_with_learned_start_match_plain_steps():
     print(f"plain mech {s0['mech_iters']} learned mech {s1['mech_iters']} starts {s1['learned_starts']} "
           f"coef {s1['warm_coef']} | m {_rel(m1, m0):.2e} u {_rel(dm(u1), dm(u0)):.2e}", flush=True)
     assert s1["learned_starts"] == 4 and s0["learned_starts"] == 0
-    assert s1["galerkin_starts"] == 4 and np.all(np.isfinite(s1["warm_coef"]))
+    assert s1["minres_starts"] == 4 and np.all(np.isfinite(s1["warm_coef"]))
     assert _rel(m1, m0) < 1e-6 and _rel(dm(u1), dm(u0)) < 1e-6
 
 
@@ -260,6 +260,6 @@ def test_extrapolated_start_steps_match_plain_steps():
     (m0, u0, s0), (m1, u1, s1) = out[gspm.GSPM_WARM_PREVIOUS], out[gspm.GSPM_WARM_EXTRAPOLATE]
     dm = lambda u: u - u.mean(axis=0)
     print(f"plain mech {s0['mech_iters']} extrapolated mech {s1['mech_iters']} "
-          f"Galerkin starts {s1['galerkin_starts']} coef {s1['warm_coef']}", flush=True)
-    assert s1["galerkin_starts"] == 4 and s1["learned_starts"] == 0
+          f"min-residual starts {s1['minres_starts']} coef {s1['warm_coef']}", flush=True)
+    assert s1["minres_starts"] == 4 and s1["learned_starts"] == 0
     assert _rel(m1, m0) < 1e-6 and _rel(dm(u1), dm(u0)) < 1e-6
