@@ -29,6 +29,34 @@ struct Geo {
     T g[4][3];
     T vol;
 };
+// Unscaled P1 geometry, for operators that only need products of gradients:
+// with e_k = x_k - x_0, c_k = e_{k+1} x e_{k+2} (k = 1..3, cyclic) equals
+// det * grad(lambda_k), det = e_1 . c_1 = 6 V with the orientation's sign, and
+// w = 1 / (6 |det|) = V / det^2, so that V grad(lambda_i) . grad(lambda_j) =
+// w c_i . c_j and V = |det| / 6.  (c_0 = -(c_1 + c_2 + c_3) is left implicit.)
+// One reciprocal and no gradient scaling per element.
+template <class T>
+struct RawGeo {
+    T c[4][3];                               // c[1..3] set; c[0] unused
+    T adet, w;                               // |det|, 1 / (6 |det|)
+};
+
+__device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_approx(double x) { return 1.0 / x; }
+
+template <class T>
+__device__ __forceinline__ void tet_raw_geometry(const T (&e)[3][3], RawGeo<T> &R) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T *a = e[(k + 1) % 3], *b = e[(k + 2) % 3];
+        R.c[k + 1][0] = a[1] * b[2] - a[2] * b[1];
+        R.c[k + 1][1] = a[2] * b[0] - a[0] * b[2];
+        R.c[k + 1][2] = a[0] * b[1] - a[1] * b[0];
+    }
+    R.adet = fabs(e[0][0] * R.c[1][0] + e[0][1] * R.c[1][1] + e[0][2] * R.c[1][2]);
+    R.w = rcp_approx(T(6) * R.adet);
+}
+
 template <class T>
 __device__ __forceinline__ void tet_geometry_from_edges(const T (&e)[3][3], Geo<T> &G) {
 #pragma unroll

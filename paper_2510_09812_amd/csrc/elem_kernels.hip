@@ -320,10 +320,10 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
                         ed[kk][2] = near_image(ed[kk][2], Lz, iLz);
                     }
                 }
-                Geo<T> G;
-                tet_geometry_from_edges(ed, G);
+                RawGeo<T> R;
+                tet_raw_geometry(ed, R);
                 T y[4][NC];
-                op.element_w(f, G, y);
+                op.element_raw(f, R, y);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -364,6 +364,17 @@ struct Cubic {
         s[3] = T(2) * c44 * e[3];
         s[4] = T(2) * c44 * e[4];
         s[5] = T(2) * c44 * e[5];
+    }
+    // the same with the shear components given as engineering strains
+    // (gamma = 2 eps_ij): s_ij = c44 gamma_ij
+    __device__ __forceinline__ void stress_eng(const T (&e)[6], T (&s)[6]) const {
+        const T tr = e[0] + e[1] + e[2], d = c11 - c12;
+        s[0] = d * e[0] + c12 * tr;
+        s[1] = d * e[1] + c12 * tr;
+        s[2] = d * e[2] + c12 * tr;
+        s[3] = c44 * e[3];
+        s[4] = c44 * e[4];
+        s[5] = c44 * e[5];
     }
 };
 
@@ -511,22 +522,32 @@ struct ElasticMatvecOp {
         }
     }
 
-    template <int NF>
-    __device__ __forceinline__ void element(const Staged<T, 3, NF> &st, const ushort4 c, const Geo<T> &G, bool,
-                                            T (&y)[4][3]) const {
-        T v[4][3];
-        vertex3(st, 0, c, v);
-        element_w(v, G, y);
-    }
-
-    // the element with its vertex values given (strip form)
-    __device__ __forceinline__ void element_w(const T (&v)[4][3], const Geo<T> &G, T (&y)[4][3]) const {
-        T e[6], s[6];
-        sym_grad(v, G, e);
-        C.stress(e, s);
+    // the element with its vertex values given (strip form), on the unscaled
+    // geometry: H' = sum_k (v_k - v_0) (x) c_k = det grad v, so C sym(H') =
+    // det sigma, and V sigma grad(lambda_j) = w (C sym H') c_j; vertex 0 takes
+    // minus the sum of the others (the gradients sum to zero)
+    __device__ __forceinline__ void element_raw(const T (&v)[4][3], const RawGeo<T> &R, T (&y)[4][3]) const {
+        T H[3][3];
 #pragma unroll
-        for (int t = 0; t < 6; ++t) s[t] *= G.vol;
-        sym_times_grads(s, G, y);
+        for (int a = 0; a < 3; ++a) {
+            const T d1 = v[1][a] - v[0][a], d2 = v[2][a] - v[0][a], d3 = v[3][a] - v[0][a];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) H[a][b] = d1 * R.c[1][b] + d2 * R.c[2][b] + d3 * R.c[3][b];
+        }
+        const T e[6] = {H[0][0], H[1][1], H[2][2], H[1][2] + H[2][1], H[0][2] + H[2][0], H[0][1] + H[1][0]};
+        T s[6];
+        C.stress_eng(e, s);
+#pragma unroll
+        for (int t = 0; t < 6; ++t) s[t] *= R.w;
+#pragma unroll
+        for (int j = 1; j < 4; ++j) {
+            const T *c = R.c[j];
+            y[j][0] = s[0] * c[0] + s[5] * c[1] + s[4] * c[2];
+            y[j][1] = s[5] * c[0] + s[1] * c[1] + s[3] * c[2];
+            y[j][2] = s[4] * c[0] + s[3] * c[1] + s[2] * c[2];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) y[0][a] = -(y[1][a] + y[2][a] + y[3][a]);
     }
 
     template <int NF>
@@ -673,21 +694,10 @@ struct GsMatvecOp {
         }
     }
 
-    template <int NF>
-    __device__ __forceinline__ void element(const Staged<T, NC, NF> &st, const ushort4 c, const Geo<T> &G, bool,
-                                            T (&y)[4][NC]) const {
-        const int id[4] = {c.x, c.y, c.z, c.w};
-        T f[4][NC];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int q = 0; q < NC; ++q) f[j][q] = live[q] ? st.fld(q, id[j]) : T(0);
-        element_w(f, G, y);
-    }
-
-    // the element with its vertex values given (strip form)
-    __device__ __forceinline__ void element_w(const T (&f)[4][NC], const Geo<T> &G, T (&y)[4][NC]) const {
-        const T ev = eps * G.vol, mv20 = mass * G.vol * T(0.05);
+    // the element with its vertex values given (strip form), on the unscaled
+    // geometry: eps V g_i . g_j = (eps w) c_i . c_j and V / 20 = |det| / 120
+    __device__ __forceinline__ void element_raw(const T (&f)[4][NC], const RawGeo<T> &R, T (&y)[4][NC]) const {
+        const T ev = eps * R.w, mv20 = mass * R.adet * T(1.0 / 120.0);
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             if (!live[q]) {
@@ -701,11 +711,14 @@ struct GsMatvecOp {
             const T d1 = v[1] - v[0], d2 = v[2] - v[0], d3 = v[3] - v[0];
             T gp[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) gp[a] = d1 * G.g[1][a] + d2 * G.g[2][a] + d3 * G.g[3][a];
+            for (int a = 0; a < 3; ++a) gp[a] = d1 * R.c[1][a] + d2 * R.c[2][a] + d3 * R.c[3][a];
             const T sum = v[0] + v[1] + v[2] + v[3];
+            T t[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                y[j][q] = ev * (G.g[j][0] * gp[0] + G.g[j][1] * gp[1] + G.g[j][2] * gp[2]) + mv20 * (v[j] + sum);
+            for (int j = 1; j < 4; ++j) t[j] = R.c[j][0] * gp[0] + R.c[j][1] * gp[1] + R.c[j][2] * gp[2];
+            t[0] = -(t[1] + t[2] + t[3]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) y[j][q] = ev * t[j] + mv20 * (v[j] + sum);
         }
     }
 
