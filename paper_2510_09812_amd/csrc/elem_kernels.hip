@@ -249,18 +249,57 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
         uint4 q = src[0], qn = src[1];
         src += 2;
         int avail = 8;
-        int ids[4] = {-1, -1, -1, -1};
+        int ids[4];
         T x[4][3], f[4][NF], acc[4][NC];
+        // the element on the window: its contributions go to the four slots
+        auto element = [&]() {
+            T ed[3][3];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+            for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) x[j][a] = T(0);
+                for (int a = 0; a < 3; ++a) ed[kk][a] = x[kk + 1][a] - x[0][a];
+            if (img) {
 #pragma unroll
-            for (int c = 0; c < NF; ++c) f[j][c] = T(0);
+                for (int kk = 0; kk < 3; ++kk) {
+                    ed[kk][0] = near_image(ed[kk][0], Lx, iLx);
+                    ed[kk][1] = near_image(ed[kk][1], Ly, iLy);
+                    ed[kk][2] = near_image(ed[kk][2], Lz, iLz);
+                }
+            }
+            RawGeo<T> R;
+            tet_raw_geometry(ed, R);
+            T y[4][NC];
+            op.element_raw(f, R, y);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[j][c] = T(0);
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[j][c] += y[j][c];
+        };
+        // A segment opens with its first element's four vertices loaded into
+        // the empty slots 0..3 in order (the fourth entry flagged): all lanes
+        // start together, so this part is peeled and loads without selects.
+        {
+            const uint32_t first[4] = {q.x & 0xFFFFu, q.x >> 16, q.y & 0xFFFFu, q.y >> 16};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int id = static_cast<int>(first[j] & kEntIdMask);
+                ids[j] = id;
+                x[j][0] = st.sx[id];
+                x[j][1] = st.sy[id];
+                x[j][2] = st.sz[id];
+#pragma unroll
+                for (int c = 0; c < NF; ++c) f[j][c] = st.fld(c, id);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[j][c] = T(0);
+            }
+            q.x = q.z;
+            q.y = q.w;
+            q.z = 0u;
+            q.w = 0u;
+            avail = 4;
+            element();
         }
-        for (int k = 0; k < nel; ++k) {
+        for (int k = 4; k < nel; ++k) {
             if (avail == 0) {
                 q = qn;
                 qn = *src++;
@@ -285,7 +324,7 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
 #pragma unroll
                 for (int c = 0; c < NC; ++c) oacc[c] = hit ? acc[j][c] : oacc[c];
             }
-            if (oid >= 0 && oid < nb) {
+            if (oid < nb) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) atomicAdd(&st.acc[c * nb + oid], static_cast<double>(oacc[c]));
             }
@@ -306,33 +345,11 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
 #pragma unroll
                 for (int c = 0; c < NC; ++c) acc[j][c] = hit ? T(0) : acc[j][c];
             }
-            if (e & kEntElem) {
-                T ed[3][3];
-#pragma unroll
-                for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) ed[kk][a] = x[kk + 1][a] - x[0][a];
-                if (img) {
-#pragma unroll
-                    for (int kk = 0; kk < 3; ++kk) {
-                        ed[kk][0] = near_image(ed[kk][0], Lx, iLx);
-                        ed[kk][1] = near_image(ed[kk][1], Ly, iLy);
-                        ed[kk][2] = near_image(ed[kk][2], Lz, iLz);
-                    }
-                }
-                RawGeo<T> R;
-                tet_raw_geometry(ed, R);
-                T y[4][NC];
-                op.element_raw(f, R, y);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) acc[j][c] += y[j][c];
-            }
+            if (e & kEntElem) element();
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (ids[j] >= 0 && ids[j] < nb) {
+            if (ids[j] < nb) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) atomicAdd(&st.acc[c * nb + ids[j]], static_cast<double>(acc[j][c]));
             }

@@ -116,8 +116,10 @@ static void strip_order(const uint16_t *lc, int32_t m, std::vector<int32_t> &ord
 // costs one vertex load; at a strip break or a segment start the missing
 // vertices are loaded first.  A new vertex replaces a slot whose vertex the
 // element does not use (empty first, else the least recently used), so the
-// four slots hold exactly the element's vertices at its flagged entry.
-// With `emit` false only the number of segments is returned.
+// four slots hold exactly the element's vertices at its flagged entry; a
+// segment therefore opens with its first element's vertices in slots 0..3,
+// in order (the operator kernels rely on it).  With `emit` false only the
+// number of segments is returned.
 static int32_t pack_strips(const uint16_t *lc, const std::vector<int32_t> &order, int budget, bool emit,
                            std::vector<uint16_t> &ent, std::vector<uint32_t> &off, std::vector<uint16_t> &nent) {
     int32_t win[4] = {-1, -1, -1, -1};

@@ -47,6 +47,16 @@ int main(int argc, char **argv) {
             const int nent = M.seg_nel[s];
             maxnel = std::max(maxnel, nent); minnel = std::min(minnel, nent);
             if (k + nent > kend) { bad++; printf("segment overrun\n"); continue; }
+            // the operator kernels load the first element of a segment straight
+            // into slots 0..3: its four entries take those slots in order, and
+            // only the fourth completes an element
+            if (nent < 4) { bad++; printf("segment shorter than one element\n"); }
+            for (int i = 0; i < 4 && i < nent; ++i) {
+                unsigned e = M.seg_ent[k + i];
+                if ((e >> 14) != static_cast<unsigned>(i) || ((e & kEntElem) != 0) != (i == 3)) {
+                    bad++; printf("segment does not open with slots 0..3\n"); break;
+                }
+            }
             for (int i = 0; i < nent; ++i) {
                 unsigned e = M.seg_ent[k++];
                 int id = e & kEntIdMask, sl = e >> 14;
