@@ -12,10 +12,11 @@ timed region starts.
 Paths: FP64, mixed (FP64 refinement around FP32 inner CG), mixed with the
 extrapolated elastic start and mixed with the learned elastic start; `value`
 is the learned path when trained weights exist.  Prints one JSON line,
-including the roofline of the dominant kernel (the elastic matvec, its
-launches timed by start and end events the HIP runtime records at each
-kernel's own execution, in extra untimed steps after the timed region) and the CPU oracle's throughput on a bounded sample of the same
-workload.
+including the roofline of the dominant kernel (the fused elastic CG
+iteration, its launches timed by start and end events the HIP runtime
+records at each kernel's own execution, in extra untimed steps after the
+timed region) and the CPU oracle's throughput on a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -33,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GSPM node-steps/s at 1M nodes, mixed vs FP64 at 1e-6 rel err; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_elastic_matvec_cube100.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_elastic_cg_cube100.json")
 WEIGHTS_FILE = os.path.join(ROOT, "paper_2510_09812_amd", "weights", "warm_start.f32")
 KERNEL_SOURCES = ["paper_2510_09812_amd/csrc/elem_kernels.hip", "paper_2510_09812_amd/csrc/device_common.h"]
 
@@ -46,23 +47,24 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def matvec_bytes(n_nodes: int, n_tets: int, real_bytes: int = 8) -> int:
-    """Algorithmic bytes of one elastic matvec: connectivity (4 x int32 per
-    tetrahedron), FP64 coordinates, and the input and output vectors (3
-    values per node each, in the working precision), each read or written
-    once: 163.0 MB (FP64) and 139.7 MB (FP32 vectors) at 1M nodes."""
-    return 16 * n_tets + 24 * n_nodes + 2 * 3 * real_bytes * n_nodes
+def cg_iteration_bytes(n_nodes: int, n_tets: int, real_bytes: int = 8) -> int:
+    """Algorithmic bytes of one fused elastic CG iteration (one launch):
+    connectivity (4 x int32 per tetrahedron), FP64 coordinates, and eight
+    vectors of 3 values per node in the working precision, each read or
+    written once: r, p, q of the previous iteration and x read; r, p, q of
+    this iteration and x written.  302.7 MB (FP64) and 209.6 MB (FP32
+    vectors) at 1M nodes."""
+    return 16 * n_tets + 24 * n_nodes + 8 * 3 * real_bytes * n_nodes
 
 
 def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float) -> float:
     """Algorithmic bytes of one step (FP64): per elastic CG iteration the
-    matvec plus 7 vector passes (x, r, p read and written, Ap read); per
-    scalar GS CG iteration the connectivity and coordinates plus 8 scalar
-    vector passes; three element right-hand-side passes (connectivity,
-    coordinates, m, u, b) and the node passes (averages, updates,
-    projection)."""
+    fused launch (cg_iteration_bytes); per scalar GS CG iteration the
+    connectivity and coordinates plus 8 scalar vector passes; three element
+    right-hand-side passes (connectivity, coordinates, m, u, b) and the node
+    passes (averages, updates, projection)."""
     conn = 16 * n_tets
-    mech = conn + 24 * n_nodes * (3 + 7)
+    mech = cg_iteration_bytes(n_nodes, n_tets, 8)
     gs = conn + 24 * n_nodes + 8 * n_nodes * 9
     rhs = 3 * (conn + 24 * n_nodes * 4)
     nodes = 24 * n_nodes * 12
@@ -70,7 +72,7 @@ def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float) ->
 
 
 def traffic_from_profile(path: str):
-    """HBM bytes per launch of the path's elastic matvec from the committed
+    """HBM bytes per launch of the path's fused elastic CG iteration from the committed
     rocprofv3 counter summary, if it was taken on the current kernel sources."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -107,9 +109,9 @@ def main() -> int:
     ap.add_argument("--workload", default="cube100_ellipsoids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
-    ap.add_argument("--no-profile", action="store_true", help="skip the per-launch matvec timing steps")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-launch timing steps of the elastic CG iteration")
     ap.add_argument("--profile-steps", type=int, default=2,
-                    help="untimed steps after the timed region that time every elastic matvec kernel")
+                    help="untimed steps after the timed region that time every elastic CG iteration kernel")
     ap.add_argument("--block-nodes", type=int, default=0, help="nodes per owner block (0 = library default)")
     ap.add_argument("--precision", choices=("fp64", "mixed", "both"), default="both",
                     help="paths to run; with both, `value` is the mixed path (with the learned warm start when "
@@ -176,13 +178,13 @@ def main() -> int:
         out = dict(info=info, st=st, wall=wall, value=info["n_unique"] * args.steps / wall, m=sim.get_m(),
                    u=sim.get_u(), tag=tag)
         if not args.no_profile:
-            # kernel durations from extra untimed steps: every elastic matvec is
+            # kernel durations from extra untimed steps: every elastic CG iteration is
             # launched with a start/stop event pair that the runtime records at
             # the kernel's own execution (hipExtLaunchKernelGGL), not in the timed region
             sim.set_profile(True)
             pst = sim.step(case.dt, args.profile_steps)
             out["prof"] = pst
-            print(f"[bench] {tag}: {pst['matvec_launches']} matvec launches timed, "
+            print(f"[bench] {tag}: {pst['matvec_launches']} elastic CG launches timed, "
                   f"{pst['matvec_ms'] / max(pst['matvec_launches'], 1) * 1e3:.1f} us each", file=sys.stderr, flush=True)
         sim.close()
         return out
@@ -206,14 +208,14 @@ def main() -> int:
     pst = head.get("prof")
     if pst and pst["matvec_launches"] > 0:
         avg_s = pst["matvec_ms"] / pst["matvec_launches"] * 1e-3
-        mb = matvec_bytes(n, ne, 4 if mixed else 8)
+        mb = cg_iteration_bytes(n, ne, 4 if mixed else 8)
         achieved = mb / avg_s / 1e9
-        kname = "k_strip<float,3,3,ElasticMatvecOp>" if mixed else "k_strip<double,3,3,ElasticMatvecOp>"
+        kname = "k_strip<float,3,3,ElasticCgOp>" if mixed else "k_strip<double,3,3,ElasticCgOp>"
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("mixed" if mixed else "fp64"),
                     "kernel": kname, "bytes_per_launch": mb,
                     "avg_launch_us": avg_s * 1e6, "launches": pst["matvec_launches"],
-                    "timing": f"kernel start/end events (hipExtLaunchKernelGGL) on every elastic matvec of "
+                    "timing": f"kernel start/end events (hipExtLaunchKernelGGL) on every elastic CG iteration of "
                               f"{args.profile_steps} untimed steps after the timed region"}
     mech_per_step = st["mech_iters"] / args.steps
     gs_per_step = st["gs_iters"] / args.steps

@@ -11,7 +11,8 @@
  * n steps: volume averages (Sec. 2.4) feed the far-field demagnetising field
  * -Ms N_d mbar (Sec. 2.1, ellipsoid theorem) and the homogeneous strain;
  * mechanical equilibrium (Eq. elasticity, weak form Eq. weak_elasticity) is
- * solved by unpreconditioned CG with one pinned node (Sec. 2.5); the three
+ * solved by unpreconditioned CG with one pinned node (Sec. 2.5; run in the
+ * single-reduction form, one fused kernel launch per iteration); the three
  * stages of (1 - eps lap) g = f (Eq. GS, weak form Eq. weak_GS) are solved by
  * unpreconditioned CG; the cross-product update and the unit-length
  * projection close the step.
@@ -80,7 +81,7 @@ typedef struct {
                                arithmetic; state, right-hand sides, dot products,
                                norms and averages stay FP64 */
     int32_t block_nodes;    /* nodes per owner block (power of two, 64..1024), 0 = automatic */
-    int32_t profile;        /* nonzero: time every elastic matvec launch with HIP events */
+    int32_t profile;        /* nonzero: time every elastic CG iteration launch with HIP events */
     void *stream;           /* hipStream_t to run on, or NULL for a stream owned by the context */
 } gspm_create_opts;
 
@@ -110,9 +111,10 @@ typedef struct {
     int64_t gs_iters_stage[8]; /* per scalar solve: g1 g2 g3, g*1 g*2, m**1 m**2 m**3 */
     double dm_avg;          /* mean |m^{n+1} - m^n| over magnetic nodes, last step (Sec. 3.2) */
     double elapsed_ms;      /* wall time of the call on the device stream */
-    double matvec_ms;       /* profile mode: summed kernel duration of the working elastic matvec
-                               launches (those issued after convergence, which exit at once, excluded) */
-    int64_t matvec_launches;/* profile mode: number of elastic matvec launches timed */
+    double matvec_ms;       /* profile mode: summed kernel duration of the working elastic CG
+                               iteration launches (the matvec fused with the CG vector updates; those
+                               issued after convergence, which exit at once, excluded) */
+    int64_t matvec_launches;/* profile mode: number of elastic CG iteration launches timed */
     int64_t refinements;    /* GSPM_MIXED: outer FP64 residual evaluations that started an FP32 inner solve */
     int64_t learned_starts; /* steps whose elastic start used the network's increment */
     int64_t minres_starts; /* steps whose elastic start was a minimum-residual step (learned or extrapolated) */
@@ -181,8 +183,8 @@ gspm_status gspm_solve(gspm_ctx *ctx, gspm_op op, double eps, const double *b, d
  * GSPM_OP_ELASTIC needs gspm_set_params.  Changes no field. */
 gspm_status gspm_time_operator(gspm_ctx *ctx, gspm_op op, double eps, int32_t reps, double *avg_ms);
 
-/* Switch the per-launch timing of the elastic matvec (the create option
- * `profile`) on or off for later gspm_step calls.  Each matvec kernel is
+/* Switch the per-launch timing of the elastic CG iteration (the create option
+ * `profile`) on or off for later gspm_step calls.  Each iteration kernel is
  * launched with a start/stop event pair that the runtime records at the
  * kernel's own execution (its duration alone, as a kernel trace reports it);
  * the events add a little host overhead to each CG iteration. */

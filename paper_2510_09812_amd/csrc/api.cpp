@@ -129,11 +129,13 @@ void gspm_ctx::release_mesh() {
     dev_free(b.stc64); dev_free(b.stc32); dev_free(b.seg_ent); dev_free(b.seg_off); dev_free(b.seg_nel); dev_free(b.seg_ptr); dev_free(b.seg_nmag);
     dev_free(b.m); dev_free(b.mnext); dev_free(b.u); dev_free(b.unext);
     dev_free(b.ms); dev_free(b.g); dev_free(b.gs); dev_free(b.b); dev_free(b.ch2);
-    dev_free(b.r); dev_free(b.p); dev_free(b.p2); dev_free(b.q);
+    dev_free(b.r); dev_free(b.p); dev_free(b.p2); dev_free(b.q); dev_free(b.r2); dev_free(b.q2);
     dev_free(b.sums); dev_free(b.esums); dev_free(b.dm); dev_free(b.der); dev_free(b.bad);
-    dev_free(b.cg_rr); dev_free(b.cg_pq); dev_free(b.cg_bb); dev_free(b.cg_flags);
-    dev_free(b.r32); dev_free(b.p32); dev_free(b.p32b); dev_free(b.q32); dev_free(b.x32);
-    dev_free(b.cgi_rr); dev_free(b.cgi_pq); dev_free(b.cgi_bb); dev_free(b.cgi_flags);
+    dev_free(b.cg_rr); dev_free(b.cg_pq); dev_free(b.cg_bb); dev_free(b.cg_rq); dev_free(b.cg_qq); dev_free(b.cg_flags);
+    dev_free(b.r32); dev_free(b.p32); dev_free(b.p32b); dev_free(b.q32); dev_free(b.x32); dev_free(b.r32b);
+    dev_free(b.q32b);
+    dev_free(b.cgi_rr); dev_free(b.cgi_pq); dev_free(b.cgi_bb); dev_free(b.cgi_rq); dev_free(b.cgi_qq);
+    dev_free(b.cgi_flags);
     dev_free(b.mprev); dev_free(b.uprev); dev_free(b.du_prev); dev_free(b.kdu); dev_free(b.wred); dev_free(b.wcoef);
     have_mesh = have_m = have_prev = false;
     commits = 0;
@@ -269,8 +271,8 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     rc = rc ? rc : dev_alloc(c, &d.seg_nel, nseg);
     rc = rc ? rc : dev_alloc(c, &d.seg_ptr, hm.seg_ptr.size());
     rc = rc ? rc : dev_alloc(c, &d.seg_nmag, hm.seg_nmag.size());
-    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.mprev,
-                        &d.uprev, &d.du_prev, &d.kdu})
+    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.r2, &d.q2,
+                        &d.mprev, &d.uprev, &d.du_prev, &d.kdu})
         rc = rc ? rc : dev_alloc(c, p, n3);
     rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kMrSums) * kShards);
     rc = rc ? rc : dev_alloc(c, &d.wcoef, 2);
@@ -283,9 +285,13 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     rc = rc ? rc : dev_alloc(c, &d.cg_rr, static_cast<size_t>(kMaxComp) * kRing * kShards);
     rc = rc ? rc : dev_alloc(c, &d.cg_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
     rc = rc ? rc : dev_alloc(c, &d.cg_bb, static_cast<size_t>(kMaxComp) * kShards);
+    rc = rc ? rc : dev_alloc(c, &d.cg_rq, static_cast<size_t>(kRing) * kShards);
+    rc = rc ? rc : dev_alloc(c, &d.cg_qq, static_cast<size_t>(kRing) * kShards);
     rc = rc ? rc : dev_alloc(c, &d.cg_flags, 2 * kMaxComp);
     if (c->precision == GSPM_MIXED) {
-        for (float **p : {&d.r32, &d.p32, &d.p32b, &d.q32, &d.x32}) rc = rc ? rc : dev_alloc(c, p, n3);
+        for (float **p : {&d.r32, &d.p32, &d.p32b, &d.q32, &d.x32, &d.r32b, &d.q32b}) rc = rc ? rc : dev_alloc(c, p, n3);
+        rc = rc ? rc : dev_alloc(c, &d.cgi_rq, static_cast<size_t>(kRing) * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cgi_qq, static_cast<size_t>(kRing) * kShards);
         rc = rc ? rc : dev_alloc(c, &d.cgi_rr, static_cast<size_t>(kMaxComp) * kRing * kShards);
         rc = rc ? rc : dev_alloc(c, &d.cgi_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
         rc = rc ? rc : dev_alloc(c, &d.cgi_bb, static_cast<size_t>(kMaxComp) * kShards);
@@ -369,12 +375,16 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->cg.rr = d.cg_rr;
     c->cg.pq = d.cg_pq;
     c->cg.bb = d.cg_bb;
+    c->cg.rq = d.cg_rq;
+    c->cg.qq = d.cg_qq;
     c->cg.done = d.cg_flags;
     c->cg.iters = d.cg_flags + kMaxComp;
     c->cg.ring = kRing;
     c->cg_in.rr = d.cgi_rr;
     c->cg_in.pq = d.cgi_pq;
     c->cg_in.bb = d.cgi_bb;
+    c->cg_in.rq = d.cgi_rq;
+    c->cg_in.qq = d.cgi_qq;
     c->cg_in.done = d.cgi_flags;
     c->cg_in.iters = d.cgi_flags ? d.cgi_flags + kMaxComp : nullptr;
     c->cg_in.ring = kRing;

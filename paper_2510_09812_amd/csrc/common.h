@@ -114,6 +114,7 @@ struct CGScalars {
     double *rr;                   // [comp][ring][kShards]: r_k . r_k
     double *pq;                   // [comp][ring][kShards]: p_k . A p_k
     double *bb;                   // [comp][kShards]: b . b
+    double *rq, *qq;              // [ring][kShards]: r_k . A p_k, |A p_k|^2 (single-reduction CG, one scalar set)
     int32_t *done;                // [comp]: 0 running, 1 converged, 2 broke down (non-finite)
     int32_t *iters;               // [comp]: iterations at convergence
     int32_t ring;
@@ -125,6 +126,8 @@ struct CGScalars {
         return pq + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
     }
     __host__ __device__ double *bb_at(int c) const { return bb + static_cast<size_t>(c) * kShards; }
+    __host__ __device__ double *rq_at(int k) const { return rq + static_cast<size_t>(k % ring) * kShards; }
+    __host__ __device__ double *qq_at(int k) const { return qq + static_cast<size_t>(k % ring) * kShards; }
     __host__ __device__ int comp_stride() const { return ring * kShards; }
 };
 
@@ -164,6 +167,18 @@ template <class T>
 void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode mode, const T *in, T *out, const T *b,
                            const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s,
                            const hipEvent_t *ev = nullptr);
+// Single-reduction CG iteration k on the elastic system (one launch per
+// iteration): tests |r_{k-1}|, completes iteration k-1 (x, r) and computes
+// q_k = A p_k with the sums p.q, r.q, q.q, r.r of iteration k.  Buffers
+// alternate by the parity of k: (rin, pin, qin) hold iteration k-1, (rout,
+// pout, qout) receive iteration k; at k = 0, rin holds r_0 and rout is unused.
+// A solve that converges at iteration j is recorded (iters = j) by launch
+// j + 1.  last: the launch after the last permitted iteration (the test of
+// |r_{k-1}|, and the x update when it fails).  ev as for launch_elastic_matvec.
+template <class T>
+void launch_elastic_cg(const MeshView &mv, const Material &mat, int k, bool last, const T *rin, const T *pin,
+                       const T *qin, T *rout, T *pout, T *qout, T *x, const CGScalars &cg, double tol, hipStream_t s,
+                       const hipEvent_t *ev = nullptr);
 template <class T>
 void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
                       const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);

@@ -33,11 +33,13 @@ struct DeviceBuffers {
     double *dm = nullptr;         // kShards
     Derived *der = nullptr;       // [2]: stage at m^n, stage at m*
     int32_t *bad = nullptr;
-    double *cg_rr = nullptr, *cg_pq = nullptr, *cg_bb = nullptr;
+    double *cg_rr = nullptr, *cg_pq = nullptr, *cg_bb = nullptr, *cg_rq = nullptr, *cg_qq = nullptr;
     int32_t *cg_flags = nullptr;  // done[3], iters[3]
     // mixed form: FP32 inner-solve vectors and scalars
     float *r32 = nullptr, *p32 = nullptr, *p32b = nullptr, *q32 = nullptr, *x32 = nullptr;
-    double *cgi_rr = nullptr, *cgi_pq = nullptr, *cgi_bb = nullptr;
+    double *cgi_rr = nullptr, *cgi_pq = nullptr, *cgi_bb = nullptr, *cgi_rq = nullptr, *cgi_qq = nullptr;
+    double *r2 = nullptr, *q2 = nullptr;          // 3n: second r and q of the single-reduction elastic CG
+    float *r32b = nullptr, *q32b = nullptr;       // 3n: the same for the FP32 inner solves
     int32_t *cgi_flags = nullptr;
     double *mprev = nullptr;      // 3n: m^{n-1} (previous committed state), for the learned warm start
     double *uprev = nullptr;      // 3n: u^{n-2}, for the previous displacement increment

@@ -102,6 +102,28 @@ __device__ __forceinline__ void block_atomic_add(const double (&v)[NR], double *
     }
 }
 
+// The same with the NR totals going to NR separate sharded scalars (a null
+// destination drops its total).
+template <int NR>
+__device__ __forceinline__ void block_atomic_add_to(const double (&v)[NR], double *const (&dst)[NR]) {
+    __shared__ double red[kThreads / 64][NR];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        double s = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NR && dst[threadIdx.x] != nullptr) {
+        double s = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < kThreads / 64; ++w2) s += red[w2][threadIdx.x];
+        unsafeAtomicAdd(dst[threadIdx.x] + (blockIdx.x % kShards), s);
+    }
+}
+
 __device__ __forceinline__ void block_atomic_add1(double v, double *dst) {
     const double a[1] = {v};
     block_atomic_add<1>(a, dst, 0);

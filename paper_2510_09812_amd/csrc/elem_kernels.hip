@@ -182,8 +182,8 @@ template <class T, int NC, int NF, class Op>
 __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op op_in) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Op op = op_in;
-    if (!op.prepare()) return;                 // uniform: e.g. every CG component converged
     const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (!op.prepare(mv, b)) return;            // uniform: e.g. every CG component converged
     const int nb = mv.nb, n0 = b * nb, cnt = min(nb, mv.n - n0);
     const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg);
     Staged<T, NC, NF> st;
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
             cx[u] = stc[o];
             cy[u] = stc[mv.nstc + o];
             cz[u] = stc[2 * mv.nstc + o];
-            op.fetch(gs[u], v[u]);
+            op.fetch(gs[u], v[u], ok[u] && ls[u] < nb);
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -498,6 +498,36 @@ __device__ __forceinline__ bool cg_direction_scalars(const CGScalars &cg, int k,
 
 // ------------------------------------------------------------- elasticity
 
+// K^mech of one element (Eq. LHS) applied to its vertex values (strip form), on
+// the unscaled geometry: H' = sum_k (v_k - v_0) (x) c_k = det grad v, so
+// C sym(H') = det sigma, and V sigma grad(lambda_j) = w (C sym H') c_j; vertex
+// 0 takes minus the sum of the others (the gradients sum to zero).
+template <class T>
+__device__ __forceinline__ void elastic_element_raw(const Cubic<T> &C, const T (&v)[4][3], const RawGeo<T> &R,
+                                                    T (&y)[4][3]) {
+    T H[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T d1 = v[1][a] - v[0][a], d2 = v[2][a] - v[0][a], d3 = v[3][a] - v[0][a];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) H[a][b] = d1 * R.c[1][b] + d2 * R.c[2][b] + d3 * R.c[3][b];
+    }
+    const T e[6] = {H[0][0], H[1][1], H[2][2], H[1][2] + H[2][1], H[0][2] + H[2][0], H[0][1] + H[1][0]};
+    T s[6];
+    C.stress_eng(e, s);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) s[t] *= R.w;
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+        const T *c = R.c[j];
+        y[j][0] = s[0] * c[0] + s[5] * c[1] + s[4] * c[2];
+        y[j][1] = s[5] * c[0] + s[1] * c[1] + s[3] * c[2];
+        y[j][2] = s[4] * c[0] + s[3] * c[1] + s[2] * c[2];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) y[0][a] = -(y[1][a] + y[2][a] + y[3][a]);
+}
+
 // Matrix-free K^mech (Eq. LHS): y_i = V sigma(u) g_i over all elements; rows of
 // the pinned node are zero.  See launch_elastic_matvec for the modes.
 template <class T>
@@ -516,21 +546,13 @@ struct ElasticMatvecOp {
     double beta[1];
     double coord_scale;           // staged coordinates in units of 1/coord_scale metres
 
-    __device__ bool prepare() {
+    __device__ bool prepare(const MeshView &, int) {
         if (mode != MV_ITER) return mode == MV_APPLY || cg.done[0] == 0;
         return cg_direction_scalars<1>(cg, k, tol2, live, beta);
     }
 
-    template <int NF>
-    __device__ __forceinline__ void stage(const Staged<T, 3, NF> &st, int l, int g) const {
-        T v[3];
-        fetch(g, v);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) st.fld(a, l) = v[a];
-    }
-
     // the staged operand at node g: p_new = r + beta p_old (ITER), else in
-    __device__ __forceinline__ void fetch(int g, T (&v)[3]) const {
+    __device__ __forceinline__ void fetch(int g, T (&v)[3], bool) const {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const size_t o = static_cast<size_t>(a) * n + g;
@@ -539,32 +561,8 @@ struct ElasticMatvecOp {
         }
     }
 
-    // the element with its vertex values given (strip form), on the unscaled
-    // geometry: H' = sum_k (v_k - v_0) (x) c_k = det grad v, so C sym(H') =
-    // det sigma, and V sigma grad(lambda_j) = w (C sym H') c_j; vertex 0 takes
-    // minus the sum of the others (the gradients sum to zero)
     __device__ __forceinline__ void element_raw(const T (&v)[4][3], const RawGeo<T> &R, T (&y)[4][3]) const {
-        T H[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const T d1 = v[1][a] - v[0][a], d2 = v[2][a] - v[0][a], d3 = v[3][a] - v[0][a];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) H[a][b] = d1 * R.c[1][b] + d2 * R.c[2][b] + d3 * R.c[3][b];
-        }
-        const T e[6] = {H[0][0], H[1][1], H[2][2], H[1][2] + H[2][1], H[0][2] + H[2][0], H[0][1] + H[1][0]};
-        T s[6];
-        C.stress_eng(e, s);
-#pragma unroll
-        for (int t = 0; t < 6; ++t) s[t] *= R.w;
-#pragma unroll
-        for (int j = 1; j < 4; ++j) {
-            const T *c = R.c[j];
-            y[j][0] = s[0] * c[0] + s[5] * c[1] + s[4] * c[2];
-            y[j][1] = s[5] * c[0] + s[1] * c[1] + s[3] * c[2];
-            y[j][2] = s[4] * c[0] + s[3] * c[1] + s[2] * c[2];
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) y[0][a] = -(y[1][a] + y[2][a] + y[3][a]);
+        elastic_element_raw(C, v, R, y);
     }
 
     template <int NF>
@@ -593,6 +591,123 @@ struct ElasticMatvecOp {
         }
         if (mode == MV_ITER) block_atomic_add1(part, cg.pq_at(0, k));
         else if (mode == MV_RESID) block_atomic_add1(part, cg.rr_at(0, 0));
+    }
+};
+
+// One launch of single-reduction CG on the elastic system (one scalar set,
+// Sec. 2.5; the iterates of the two-launch form up to rounding).  Launch k
+// completes iteration k-1 from the sums of its epilogue, r.r, p.q, r.q and
+// q.q with q = A p:
+//   alpha = rr_{k-1} / (p.q) (rr_{k-1} the true |r_{k-1}|^2),
+//   beta  = rr~_k / rr_{k-1},  rr~_k = rr_{k-1} - 2 alpha (r.q) + alpha^2 (q.q)
+// (the expansion of |r_{k-1} - alpha q|^2, which cancels badly near tight
+// tolerances, so it only sets the direction; the step length and the
+// stopping test use the true norms, the test one launch later), forms
+// r_k = r_{k-1} - alpha q_{k-1} and p_k = r_k + beta p_{k-1} while staging,
+// adds alpha p_{k-1} to x on its owned nodes, and computes q_k = A p_k with
+// the four sums of iteration k.  r, p and q alternate between two buffers
+// (other workgroups still read iteration k-1's values as halo).  The launch
+// that finds rr_{k-1} converged records it (x_{k-1} is the answer) and does
+// nothing else; the final launch after the last permitted iteration only adds
+// the pending alpha p_{k-1} to x when rr_{k-1} has not converged.
+template <class T>
+struct ElasticCgOp {
+    static constexpr bool kMagneticOnly = false;
+    const T *rin, *pin, *qin;     // r_{k-1}, p_{k-1}, q_{k-1} (rin = r_0 at k = 0)
+    T *rout, *pout, *qout;        // r_k, p_k, q_k
+    T *x;
+    CGScalars cg;
+    int k, n, last;               // last: the launch after the last permitted iteration
+    double tol2;
+    Cubic<T> C;
+    double alpha, beta;
+    double coord_scale;
+
+    __device__ bool prepare(const MeshView &mv, int b) {
+        alpha = beta = 0.0;
+        // a test recorded by an earlier launch (or by workgroup 0 of this one,
+        // which then leaves nothing to do either)
+        if (cg.done[0] != 0) return false;
+        if (k == 0) return !last;                // the start test ran in an earlier launch
+        const double *const src[5] = {cg.rr_at(0, k - 1), cg.pq_at(0, k - 1), cg.rq_at(k - 1), cg.qq_at(k - 1),
+                                      cg.bb_at(0)};
+        double t[5];
+        shard_totals<5>(src, t);
+        const double rrp = t[0];
+        const int stop = !isfinite(rrp) ? 2 : (rrp <= tol2 * t[4] ? 1 : 0);
+        if (stop) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                cg.done[0] = stop;
+                cg.iters[0] = k - 1;
+            }
+            return false;
+        }
+        alpha = rrp / t[1];
+        const double est = rrp - 2.0 * alpha * t[2] + alpha * alpha * t[3];
+        beta = (est > 0.0 ? est : 0.0) / rrp;
+        if (last) {
+            const int n0 = b * mv.nb, cnt = min(mv.nb, mv.n - n0);
+            const T a = static_cast<T>(alpha);
+            for (int i = threadIdx.x; i < cnt; i += kThreads)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const size_t o = static_cast<size_t>(c) * n + n0 + i;
+                    x[o] += a * pin[o];
+                }
+            return false;
+        }
+        return true;
+    }
+
+    // the staged operand p_k at node g; owned nodes also store r_k and take
+    // the pending step of x
+    __device__ __forceinline__ void fetch(int g, T (&v)[3], bool owned) const {
+        const T a = static_cast<T>(alpha), bt = static_cast<T>(beta);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t o = static_cast<size_t>(c) * n + g;
+            if (k == 0) {
+                v[c] = rin[o];
+                continue;
+            }
+            const T pold = pin[o];
+            const T rk = rin[o] - a * qin[o];
+            v[c] = rk + bt * pold;
+            if (owned) {
+                rout[o] = rk;
+                x[o] += a * pold;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void element_raw(const T (&v)[4][3], const RawGeo<T> &R, T (&y)[4][3]) const {
+        elastic_element_raw(C, v, R, y);
+    }
+
+    template <int NF>
+    __device__ void finish(const MeshView &mv, const Staged<T, 3, NF> &st, int n0, int cnt) const {
+        double part[4] = {0.0, 0.0, 0.0, 0.0};   // p.q, r.q, q.q, r.r
+        const T *rk = k == 0 ? rin : rout;
+        for (int i = threadIdx.x; i < cnt; i += kThreads) {
+            const int node = n0 + i;
+            const bool pinned = node == mv.p0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const size_t o = static_cast<size_t>(a) * n + node;
+                const T q = pinned ? T(0) : st.acc[a * mv.nb + i];
+                const T pv = st.fld(a, i);
+                pout[o] = pv;
+                qout[o] = q;
+                const double rv = static_cast<double>(rk[o]);
+                part[0] += static_cast<double>(pv) * q;
+                part[1] += rv * q;
+                part[2] += static_cast<double>(q) * q;
+                part[3] += rv * rv;
+            }
+        }
+        // r_0.r_0 is already in slot 0 (the residual launch wrote it)
+        double *const dst[4] = {cg.pq_at(0, k), cg.rq_at(k), cg.qq_at(k), k == 0 ? nullptr : cg.rr_at(0, k)};
+        block_atomic_add_to<4>(part, dst);
     }
 };
 
@@ -680,7 +795,7 @@ struct GsMatvecOp {
     double beta[NC];
     double coord_scale;
 
-    __device__ bool prepare() {
+    __device__ bool prepare(const MeshView &, int) {
         if (mode == MV_ITER) return cg_direction_scalars<NC>(cg, k, tol2, live, beta);
         bool any = false;
 #pragma unroll
@@ -692,16 +807,8 @@ struct GsMatvecOp {
         return any;
     }
 
-    template <int NF>
-    __device__ __forceinline__ void stage(const Staged<T, NC, NF> &st, int l, int g) const {
-        T v[NC];
-        fetch(g, v);
-#pragma unroll
-        for (int q = 0; q < NC; ++q) st.fld(q, l) = v[q];
-    }
-
     // the staged operand at node g (zero for components that are not live)
-    __device__ __forceinline__ void fetch(int g, T (&v)[NC]) const {
+    __device__ __forceinline__ void fetch(int g, T (&v)[NC], bool) const {
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const size_t o = static_cast<size_t>(q) * n + g;
@@ -1067,6 +1174,29 @@ template void launch_elastic_matvec<double>(const MeshView &, const Material &, 
 template void launch_elastic_matvec<float>(const MeshView &, const Material &, MatvecMode, const float *, float *,
                                            const float *, const float *, float *, const CGScalars &, int, double,
                                            hipStream_t, const hipEvent_t *);
+
+template <class T>
+void launch_elastic_cg(const MeshView &mv, const Material &mat, int k, bool last, const T *rin, const T *pin,
+                       const T *qin, T *rout, T *pout, T *qout, T *x, const CGScalars &cg, double tol, hipStream_t s,
+                       const hipEvent_t *ev) {
+    const bool nd = sizeof(T) == sizeof(float);
+    Material m2 = mat;
+    if (nd) {
+        m2.c12 = mat.c12 / mat.c11;
+        m2.c44 = mat.c44 / mat.c11;
+        m2.c11 = 1.0;
+    }
+    ElasticCgOp<T> op{rin, pin, qin, rout, pout, qout, x, cg, k, mv.n, last ? 1 : 0, tol * tol, cubic_of<T>(m2),
+                      0.0, 0.0, nd ? 1.0 / mv.len_scale : 1.0};
+    run_strip<T, 3, 3>(mv, op, s, ev);
+}
+
+template void launch_elastic_cg<double>(const MeshView &, const Material &, int, bool, const double *, const double *,
+                                        const double *, double *, double *, double *, double *, const CGScalars &,
+                                        double, hipStream_t, const hipEvent_t *);
+template void launch_elastic_cg<float>(const MeshView &, const Material &, int, bool, const float *, const float *,
+                                       const float *, float *, float *, float *, float *, const CGScalars &, double,
+                                       hipStream_t, const hipEvent_t *);
 
 void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x, double *bb,
                         hipStream_t s) {

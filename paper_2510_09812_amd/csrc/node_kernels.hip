@@ -175,8 +175,8 @@ __global__ void __launch_bounds__(kThreads) k_cg_start(int n, int nc, int joint,
 // convergence test of rr[k+1] and the next direction happen in the next
 // iteration's matvec.
 template <class T>
-__global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint, T *x, T *r, const T *p, const T *q,
-                                                        CGScalars cg, int k) {
+__global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint, int flat, T *x, T *r, const T *p,
+                                                        const T *q, CGScalars cg, int k) {
     const int ns = joint ? 1 : nc;
     bool live[3];
     if (!read_live(cg.done, ns, live)) return;
@@ -187,11 +187,50 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint
     double alpha[3];
     for (int s = 0; s < 3; ++s) alpha[s] = live[s] ? t[s] / t[3 + s] : 0.0;
     double part[3] = {0.0, 0.0, 0.0};
-    // per component: a scalar head up to the first 16-byte boundary, a body of
-    // 16-byte vectors (4 floats or 2 doubles per lane per load), a scalar tail
     constexpr int W = 16 / sizeof(T);
     using V = typename Vec16<T>::type;
     const int tid = blockIdx.x * kThreads + threadIdx.x, nthr = gridDim.x * kThreads;
+    auto vec = [&](size_t o, T a, double &acc) {
+        V xv = *reinterpret_cast<const V *>(x + o);
+        V rv = *reinterpret_cast<const V *>(r + o);
+        const V pv = *reinterpret_cast<const V *>(p + o);
+        const V qv = *reinterpret_cast<const V *>(q + o);
+        T *xe = reinterpret_cast<T *>(&xv), *re = reinterpret_cast<T *>(&rv);
+        const T *pe = reinterpret_cast<const T *>(&pv), *qe = reinterpret_cast<const T *>(&qv);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            xe[j] += a * pe[j];
+            re[j] -= a * qe[j];
+            acc += static_cast<double>(re[j]) * re[j];
+        }
+        *reinterpret_cast<V *>(x + o) = xv;
+        *reinterpret_cast<V *>(r + o) = rv;
+    };
+    if (flat) {
+        // joint solve, one step length for every component: the nc components
+        // are one contiguous array of nc * n values (each 16-byte aligned at
+        // its start, the host checks), streamed as 16-byte vectors, two per
+        // lane per pass, then a scalar tail
+        if (!live[0]) return;
+        const T a = static_cast<T>(alpha[0]);
+        const size_t m = static_cast<size_t>(nc) * n, nv = m / W;
+        size_t v = tid;
+        for (; v + nthr < nv; v += 2 * static_cast<size_t>(nthr)) {
+            vec(v * W, a, part[0]);
+            vec((v + nthr) * W, a, part[0]);
+        }
+        if (v < nv) vec(v * W, a, part[0]);
+        for (size_t i = nv * W + tid; i < m; i += nthr) {
+            x[i] += a * p[i];
+            const T rv = r[i] - a * q[i];
+            r[i] = rv;
+            part[0] += static_cast<double>(rv) * rv;
+        }
+        block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride());
+        return;
+    }
+    // per component: a scalar head up to the first 16-byte boundary, a body of
+    // 16-byte vectors (4 floats or 2 doubles per lane per load), a scalar tail
     for (int c = 0; c < nc; ++c) {
         const int s = set_of(c, joint);
         if (!live[s]) continue;
@@ -207,23 +246,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint
             part[s] += static_cast<double>(rv) * rv;
         };
         if (tid < head) scalar(tid);
-        for (int v = tid; v < nv; v += nthr) {
-            const size_t o = c0 + head + static_cast<size_t>(v) * W;
-            V xv = *reinterpret_cast<const V *>(x + o);
-            V rv = *reinterpret_cast<const V *>(r + o);
-            const V pv = *reinterpret_cast<const V *>(p + o);
-            const V qv = *reinterpret_cast<const V *>(q + o);
-            T *xe = reinterpret_cast<T *>(&xv), *re = reinterpret_cast<T *>(&rv);
-            const T *pe = reinterpret_cast<const T *>(&pv), *qe = reinterpret_cast<const T *>(&qv);
-#pragma unroll
-            for (int j = 0; j < W; ++j) {
-                xe[j] += a * pe[j];
-                re[j] -= a * qe[j];
-                part[s] += static_cast<double>(re[j]) * re[j];
-            }
-            *reinterpret_cast<V *>(x + o) = xv;
-            *reinterpret_cast<V *>(r + o) = rv;
-        }
+        for (int v = tid; v < nv; v += nthr) vec(c0 + head + static_cast<size_t>(v) * W, a, part[s]);
         for (int i = head + nv * W + tid; i < n; i += nthr) scalar(i);
     }
     block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride());
@@ -261,7 +284,10 @@ void launch_cg_start(int n, int nc, bool joint, T *x, const CGScalars &cg, doubl
 template <class T>
 void launch_cg_update(int n, int nc, bool joint, T *x, T *r, const T *p, const T *q, const CGScalars &cg, int k,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, x, r, p, q, cg, k);
+    auto a16 = [](const void *v) { return (reinterpret_cast<uintptr_t>(v) & 15u) == 0; };
+    const int flat = joint && a16(x) && a16(r) && a16(p) && a16(q) ? 1 : 0;
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, flat, x, r, p, q,
+                       cg, k);
 }
 
 template void launch_cg_start<double>(int, int, bool, double *, const CGScalars &, double, hipStream_t);
@@ -394,6 +420,11 @@ __global__ void __launch_bounds__(kThreads) k_zero_ring(CGScalars cg, int ns, in
         const int c = rest % ns, slot = rest / ns;
         double *base = slot < nrr ? cg.rr_at(c, rr_from + slot) : cg.pq_at(c, pq_from + slot - nrr);
         base[sh] = 0.0;
+        // the single-reduction sums of one scalar set share the p.q slots
+        if (slot >= nrr && c == 0 && cg.rq) {
+            cg.rq_at(pq_from + slot - nrr)[sh] = 0.0;
+            cg.qq_at(pq_from + slot - nrr)[sh] = 0.0;
+        }
     }
 }
 

@@ -32,13 +32,13 @@ void cg_prepare(gspm_ctx *c, int ns) {
 
 namespace {
 
-// Batched CG iterations with device-side convergence.  iter(k) enqueues
-// iteration k (matvec with fused direction, then the x/r update) on the
-// scalar set `cg`.  Returns when every component of `cg` has converged (or
+// Batched CG iterations with device-side convergence.  iter(k, false)
+// enqueues iteration k on the scalar set `cg`; iter(maxit, true) the launch
+// after the last permitted iteration, which tests (and, for single-reduction
+// CG, completes) it.  Returns when every component of `cg` has converged (or
 // broken down), or after maxit iterations.
 template <class Iter>
-CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int maxit, double tol, SolveKind kind,
-                    Iter iter) {
+CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int maxit, SolveKind kind, Iter iter) {
     hipStream_t s = c->stream;
     const int ns = joint ? 1 : nc;
     CgResult res;
@@ -49,8 +49,8 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
     auto enqueue = [&](int cnt) {
         const int k1 = std::min(k + cnt, maxit);
         launch_zero_ring(cg, ns, k + 1, k1 + 1, k, k1, s);
-        for (int it = k; it < k1; ++it) iter(it);
-        if (k1 == maxit) launch_cg_check(nc, joint, cg, maxit, tol, s);
+        for (int it = k; it < k1; ++it) iter(it, false);
+        if (k1 == maxit) iter(maxit, true);
         k = k1;
     };
     auto post = [&](int slot) {
@@ -137,7 +137,7 @@ CgResult cg_fp64(gspm_ctx *c, int nc, bool joint, double *x, double tol, int max
                  Iter iter) {
     resid();
     launch_cg_start<double>(c->n, nc, joint, x, c->cg, tol, c->stream);
-    return cg_iterate(c, c->cg, nc, joint, maxit, tol, kind, iter);
+    return cg_iterate(c, c->cg, nc, joint, maxit, kind, iter);
 }
 
 // Mixed form: FP64 iterative refinement around FP32 CG.  Each outer step
@@ -218,7 +218,7 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
         launch_fill_f32(c->d.x32, n3, s);
         const int budget = maxit - used;
         const size_t first_pair = c->prof_used / 2;
-        CgResult in = cg_iterate(c, ci, nc, joint, budget, 1.0, kind, iter32);
+        CgResult in = cg_iterate(c, ci, nc, joint, budget, kind, iter32);
         prof_drop_after(c, first_pair, std::max(in.iters[0], std::max(in.iters[1], in.iters[2])));
         if (in.status == GSPM_E_NONFINITE || in.status == GSPM_E_DEVICE || in.status == GSPM_E_OOM) {
             res.status = in.status;
@@ -235,32 +235,35 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
 
 }  // namespace
 
+// The elastic solve runs single-reduction CG: one fused launch per iteration
+// (launch_elastic_cg), r, p and q alternating between two buffers.
 CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int maxit, SolveKind kind) {
     const size_t first_pair = c->prof_used / 2;
     hipStream_t s = c->stream;
     auto resid = [&]() {
         launch_elastic_matvec<double>(c->mv, c->mat, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
     };
+    // iteration k reads the buffers of iteration k-1 and writes those of k
+    auto fused = [&](auto *R0, auto *R1, auto *P0, auto *P1, auto *Q0, auto *Q1, auto *xv, const CGScalars &cg,
+                     double t) {
+        return [=](int k, bool last) {
+            auto *R = k & 1 ? R1 : R0, *P = k & 1 ? P1 : P0, *Q = k & 1 ? Q1 : Q0;
+            auto *Rp = k & 1 ? R0 : R1, *Pp = k & 1 ? P0 : P1, *Qp = k & 1 ? Q0 : Q1;
+            if (k == 0) Rp = R0;
+            const hipEvent_t *ev = last ? nullptr : prof_begin(c, k);
+            launch_elastic_cg(c->mv, c->mat, k, last, Rp, Pp, Qp, R, P, Q, xv, cg, t, s, ev);
+            if (!last) prof_end(c);
+        };
+    };
     CgResult r;
     if (c->precision == GSPM_MIXED) {
-        float *P[2] = {c->d.p32, c->d.p32b};
+        auto &d = c->d;
         const double scale = 1.0 / (c->mv.len_scale * c->mat.c11);
-        r = cg_mixed(c, 3, true, x, tol, maxit, kind, scale, resid, [&](int k) {
-            const hipEvent_t *ev = prof_begin(c, k);
-            launch_elastic_matvec<float>(c->mv, c->mat, MV_ITER, P[k & 1], c->d.q32, nullptr, c->d.r32,
-                                         P[(k + 1) & 1], c->cg_in, k, 1.0, s, ev);
-            prof_end(c);
-            launch_cg_update<float>(c->n, 3, true, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, c->cg_in, k, s);
-        });
+        r = cg_mixed(c, 3, true, x, tol, maxit, kind, scale, resid,
+                     fused(d.r32, d.r32b, d.p32, d.p32b, d.q32, d.q32b, d.x32, c->cg_in, 1.0));
     } else {
-        double *P[2] = {c->d.p, c->d.p2};
-        r = cg_fp64(c, 3, true, x, tol, maxit, kind, resid, [&](int k) {
-            const hipEvent_t *ev = prof_begin(c, k);
-            launch_elastic_matvec<double>(c->mv, c->mat, MV_ITER, P[k & 1], c->d.q, nullptr, c->d.r, P[(k + 1) & 1],
-                                          c->cg, k, tol, s, ev);
-            prof_end(c);
-            launch_cg_update<double>(c->n, 3, true, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
-        });
+        auto &d = c->d;
+        r = cg_fp64(c, 3, true, x, tol, maxit, kind, resid, fused(d.r, d.r2, d.p, d.p2, d.q, d.q2, x, c->cg, tol));
         prof_drop_after(c, first_pair, r.iters[0]);
     }
     return r;
@@ -274,14 +277,22 @@ CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, doub
     if (c->precision == GSPM_MIXED) {
         float *P[2] = {c->d.p32, c->d.p32b};
         const double ls = c->mv.len_scale, scale = 1.0 / (ls * ls * ls);
-        return cg_mixed(c, nc, false, x, tol, maxit, kind, scale, resid, [&](int k) {
+        return cg_mixed(c, nc, false, x, tol, maxit, kind, scale, resid, [&](int k, bool last) {
+            if (last) {
+                launch_cg_check(nc, false, c->cg_in, k, 1.0, s);
+                return;
+            }
             launch_gs_matvec<float>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q32, nullptr, c->d.r32, P[(k + 1) & 1],
                                     c->cg_in, k, 1.0, s);
             launch_cg_update<float>(c->n, nc, false, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, c->cg_in, k, s);
         });
     }
     double *P[2] = {c->d.p, c->d.p2};
-    return cg_fp64(c, nc, false, x, tol, maxit, kind, resid, [&](int k) {
+    return cg_fp64(c, nc, false, x, tol, maxit, kind, resid, [&](int k, bool last) {
+        if (last) {
+            launch_cg_check(nc, false, c->cg, k, tol, s);
+            return;
+        }
         launch_gs_matvec<double>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q, nullptr, c->d.r, P[(k + 1) & 1], c->cg,
                                  k, tol, s);
         launch_cg_update<double>(c->n, nc, false, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
