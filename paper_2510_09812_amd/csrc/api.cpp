@@ -21,10 +21,28 @@ gspm_status fail(gspm_ctx *c, gspm_status s, const std::string &msg) {
     return s;
 }
 
+// Device buffers of a mesh upload come from one arena (one hipMalloc, each
+// buffer 256-byte aligned): one large allocation is placed in large
+// contiguous fragments, where separate ones can land fragmented among other
+// allocations of the process and run the gathers of the element kernels
+// measurably slower.  In planning mode dev_alloc only adds up the sizes;
+// outside the arena (or past its end) it falls back to hipMalloc.
+constexpr size_t kArenaAlign = 256;
+
 template <class T>
 int dev_alloc(gspm_ctx *c, T **p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
+    const size_t bytes = (sizeof(T) * count + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+    if (c->arena_planning) {
+        c->arena_size += bytes;
+        return GSPM_OK;
+    }
+    if (c->arena && c->arena_used + bytes <= c->arena_size) {
+        *p = reinterpret_cast<T *>(c->arena + c->arena_used);
+        c->arena_used += bytes;
+        return GSPM_OK;
+    }
     hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count);
     if (e != hipSuccess) {
         *p = nullptr;
@@ -34,8 +52,9 @@ int dev_alloc(gspm_ctx *c, T **p, size_t count) {
 }
 
 template <class T>
-void dev_free(T *&p) {
-    if (p) hipFree(p);
+void dev_free(const gspm_ctx *c, T *&p) {
+    const char *q = reinterpret_cast<const char *>(p);
+    if (p && !(c->arena && q >= c->arena && q < c->arena + c->arena_size)) hipFree(p);
     p = nullptr;
 }
 
@@ -124,19 +143,22 @@ gspm_ctx::~gspm_ctx() {
 void gspm_ctx::release_mesh() {
     if (stream) hipStreamSynchronize(stream);
     auto &b = d;
-    dev_free(b.x); dev_free(b.lconn); dev_free(b.blk_ptr); dev_free(b.blk_nmag); dev_free(b.w);
-    dev_free(b.halo_ptr); dev_free(b.halo_ids); dev_free(b.halo_lo); dev_free(b.img);
-    dev_free(b.stc64); dev_free(b.stc32); dev_free(b.seg_ent); dev_free(b.seg_off); dev_free(b.seg_nel); dev_free(b.seg_ptr); dev_free(b.seg_nmag);
-    dev_free(b.m); dev_free(b.mnext); dev_free(b.u); dev_free(b.unext);
-    dev_free(b.ms); dev_free(b.g); dev_free(b.gs); dev_free(b.b); dev_free(b.ch2);
-    dev_free(b.r); dev_free(b.p); dev_free(b.p2); dev_free(b.q); dev_free(b.r2); dev_free(b.q2);
-    dev_free(b.sums); dev_free(b.esums); dev_free(b.dm); dev_free(b.der); dev_free(b.bad);
-    dev_free(b.cg_rr); dev_free(b.cg_pq); dev_free(b.cg_bb); dev_free(b.cg_rq); dev_free(b.cg_qq); dev_free(b.cg_flags);
-    dev_free(b.r32); dev_free(b.p32); dev_free(b.p32b); dev_free(b.q32); dev_free(b.x32); dev_free(b.r32b);
-    dev_free(b.q32b);
-    dev_free(b.cgi_rr); dev_free(b.cgi_pq); dev_free(b.cgi_bb); dev_free(b.cgi_rq); dev_free(b.cgi_qq);
-    dev_free(b.cgi_flags);
-    dev_free(b.mprev); dev_free(b.uprev); dev_free(b.du_prev); dev_free(b.kdu); dev_free(b.wred); dev_free(b.wcoef);
+    dev_free(this, b.x); dev_free(this, b.lconn); dev_free(this, b.blk_ptr); dev_free(this, b.blk_nmag); dev_free(this, b.w);
+    dev_free(this, b.halo_ptr); dev_free(this, b.halo_ids); dev_free(this, b.halo_lo); dev_free(this, b.img);
+    dev_free(this, b.stc64); dev_free(this, b.stc32); dev_free(this, b.seg_ent); dev_free(this, b.seg_off); dev_free(this, b.seg_nel); dev_free(this, b.seg_ptr); dev_free(this, b.seg_nmag);
+    dev_free(this, b.m); dev_free(this, b.mnext); dev_free(this, b.u); dev_free(this, b.unext);
+    dev_free(this, b.ms); dev_free(this, b.g); dev_free(this, b.gs); dev_free(this, b.b); dev_free(this, b.ch2);
+    dev_free(this, b.r); dev_free(this, b.p); dev_free(this, b.p2); dev_free(this, b.q); dev_free(this, b.r2); dev_free(this, b.q2);
+    dev_free(this, b.sums); dev_free(this, b.esums); dev_free(this, b.dm); dev_free(this, b.der); dev_free(this, b.bad);
+    dev_free(this, b.cg_rr); dev_free(this, b.cg_pq); dev_free(this, b.cg_bb); dev_free(this, b.cg_rq); dev_free(this, b.cg_qq); dev_free(this, b.cg_flags);
+    dev_free(this, b.r32); dev_free(this, b.p32); dev_free(this, b.p32b); dev_free(this, b.q32); dev_free(this, b.x32); dev_free(this, b.r32b);
+    dev_free(this, b.q32b);
+    dev_free(this, b.cgi_rr); dev_free(this, b.cgi_pq); dev_free(this, b.cgi_bb); dev_free(this, b.cgi_rq); dev_free(this, b.cgi_qq);
+    dev_free(this, b.cgi_flags);
+    dev_free(this, b.mprev); dev_free(this, b.uprev); dev_free(this, b.du_prev); dev_free(this, b.kdu); dev_free(this, b.wred); dev_free(this, b.wcoef);
+    if (arena) hipFree(arena);
+    arena = nullptr;
+    arena_size = arena_used = 0;
     have_mesh = have_m = have_prev = false;
     commits = 0;
     tets_int.clear();
@@ -146,10 +168,10 @@ void gspm_ctx::release_mesh() {
 void gspm_ctx::release_nn() {
     if (stream) hipStreamSynchronize(stream);
     auto &q = nn;
-    dev_free(q.gptr); dev_free(q.gnbr); dev_free(q.master); dev_free(q.wr); dev_free(q.m1); dev_free(q.m2);
-    dev_free(q.grad); dev_free(q.mats); dev_free(q.acts); dev_free(q.y); dev_free(q.red); dev_free(q.dvec);
-    dev_free(q.du); dev_free(q.mp_in); dev_free(q.m_in);
-    dev_free(q.gh); dev_free(q.gha); dev_free(q.gab); dev_free(q.gy); dev_free(q.part);
+    dev_free(this, q.gptr); dev_free(this, q.gnbr); dev_free(this, q.master); dev_free(this, q.wr); dev_free(this, q.m1); dev_free(this, q.m2);
+    dev_free(this, q.grad); dev_free(this, q.mats); dev_free(this, q.acts); dev_free(this, q.y); dev_free(this, q.red); dev_free(this, q.dvec);
+    dev_free(this, q.du); dev_free(this, q.mp_in); dev_free(this, q.m_in);
+    dev_free(this, q.gh); dev_free(this, q.gha); dev_free(this, q.gab); dev_free(this, q.gy); dev_free(this, q.part);
     q = gspm::MpnnState{};
     warm_mode = GSPM_WARM_PREVIOUS;
 }
@@ -252,50 +274,65 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->release_mesh();
     const size_t n = static_cast<size_t>(hm.n), n3 = 3 * n;
     auto &d = c->d;
-    rc = 0;
-    rc = rc ? rc : dev_alloc(c, &d.x, n3);
-    rc = rc ? rc : dev_alloc(c, &d.lconn, static_cast<size_t>(hm.ncopies));
-    rc = rc ? rc : dev_alloc(c, &d.blk_ptr, hm.blk_ptr.size());
-    rc = rc ? rc : dev_alloc(c, &d.blk_nmag, hm.blk_nmag.size());
-    rc = rc ? rc : dev_alloc(c, &d.halo_ptr, hm.halo_ptr.size());
-    rc = rc ? rc : dev_alloc(c, &d.halo_ids, hm.halo_ids.size());
-    rc = rc ? rc : dev_alloc(c, &d.halo_lo, hm.halo_lo.size());
-    rc = rc ? rc : dev_alloc(c, &d.img, hm.img.size());
-    rc = rc ? rc : dev_alloc(c, &d.w, n);
     const size_t nstc = static_cast<size_t>(hm.nblk) * hm.nb + hm.halo_ids.size();
-    rc = rc ? rc : dev_alloc(c, &d.stc64, 3 * nstc);
-    rc = rc ? rc : dev_alloc(c, &d.stc32, 3 * nstc);
     const size_t nseg = hm.seg_nel.size();
-    rc = rc ? rc : dev_alloc(c, &d.seg_ent, hm.seg_ent.size() / 8);
-    rc = rc ? rc : dev_alloc(c, &d.seg_off, nseg);
-    rc = rc ? rc : dev_alloc(c, &d.seg_nel, nseg);
-    rc = rc ? rc : dev_alloc(c, &d.seg_ptr, hm.seg_ptr.size());
-    rc = rc ? rc : dev_alloc(c, &d.seg_nmag, hm.seg_nmag.size());
-    for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.r2, &d.q2,
-                        &d.mprev, &d.uprev, &d.du_prev, &d.kdu})
-        rc = rc ? rc : dev_alloc(c, p, n3);
-    rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kMrSums) * kShards);
-    rc = rc ? rc : dev_alloc(c, &d.wcoef, 2);
-    rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
-    rc = rc ? rc : dev_alloc(c, &d.sums, 9 * kShards);
-    rc = rc ? rc : dev_alloc(c, &d.esums, 4 * kShards);
-    rc = rc ? rc : dev_alloc(c, &d.dm, kShards);
-    rc = rc ? rc : dev_alloc(c, &d.der, 2);
-    rc = rc ? rc : dev_alloc(c, &d.bad, 1);
-    rc = rc ? rc : dev_alloc(c, &d.cg_rr, static_cast<size_t>(kMaxComp) * kRing * kShards);
-    rc = rc ? rc : dev_alloc(c, &d.cg_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
-    rc = rc ? rc : dev_alloc(c, &d.cg_bb, static_cast<size_t>(kMaxComp) * kShards);
-    rc = rc ? rc : dev_alloc(c, &d.cg_rq, static_cast<size_t>(kRing) * kShards);
-    rc = rc ? rc : dev_alloc(c, &d.cg_qq, static_cast<size_t>(kRing) * kShards);
-    rc = rc ? rc : dev_alloc(c, &d.cg_flags, 2 * kMaxComp);
-    if (c->precision == GSPM_MIXED) {
-        for (float **p : {&d.r32, &d.p32, &d.p32b, &d.q32, &d.x32, &d.r32b, &d.q32b}) rc = rc ? rc : dev_alloc(c, p, n3);
-        rc = rc ? rc : dev_alloc(c, &d.cgi_rq, static_cast<size_t>(kRing) * kShards);
-        rc = rc ? rc : dev_alloc(c, &d.cgi_qq, static_cast<size_t>(kRing) * kShards);
-        rc = rc ? rc : dev_alloc(c, &d.cgi_rr, static_cast<size_t>(kMaxComp) * kRing * kShards);
-        rc = rc ? rc : dev_alloc(c, &d.cgi_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
-        rc = rc ? rc : dev_alloc(c, &d.cgi_bb, static_cast<size_t>(kMaxComp) * kShards);
-        rc = rc ? rc : dev_alloc(c, &d.cgi_flags, 2 * kMaxComp);
+    auto alloc_all = [&]() -> int {
+        int rc = 0;
+        rc = rc ? rc : dev_alloc(c, &d.x, n3);
+        rc = rc ? rc : dev_alloc(c, &d.lconn, static_cast<size_t>(hm.ncopies));
+        rc = rc ? rc : dev_alloc(c, &d.blk_ptr, hm.blk_ptr.size());
+        rc = rc ? rc : dev_alloc(c, &d.blk_nmag, hm.blk_nmag.size());
+        rc = rc ? rc : dev_alloc(c, &d.halo_ptr, hm.halo_ptr.size());
+        rc = rc ? rc : dev_alloc(c, &d.halo_ids, hm.halo_ids.size());
+        rc = rc ? rc : dev_alloc(c, &d.halo_lo, hm.halo_lo.size());
+        rc = rc ? rc : dev_alloc(c, &d.img, hm.img.size());
+        rc = rc ? rc : dev_alloc(c, &d.w, n);
+        rc = rc ? rc : dev_alloc(c, &d.stc64, 3 * nstc);
+        rc = rc ? rc : dev_alloc(c, &d.stc32, 3 * nstc);
+        rc = rc ? rc : dev_alloc(c, &d.seg_ent, hm.seg_ent.size() / 8);
+        rc = rc ? rc : dev_alloc(c, &d.seg_off, nseg);
+        rc = rc ? rc : dev_alloc(c, &d.seg_nel, nseg);
+        rc = rc ? rc : dev_alloc(c, &d.seg_ptr, hm.seg_ptr.size());
+        rc = rc ? rc : dev_alloc(c, &d.seg_nmag, hm.seg_nmag.size());
+        for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.r2, &d.q2,
+                            &d.mprev, &d.uprev, &d.du_prev, &d.kdu})
+            rc = rc ? rc : dev_alloc(c, p, n3);
+        rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kMrSums) * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.wcoef, 2);
+        rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
+        rc = rc ? rc : dev_alloc(c, &d.sums, 9 * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.esums, 4 * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.dm, kShards);
+        rc = rc ? rc : dev_alloc(c, &d.der, 2);
+        rc = rc ? rc : dev_alloc(c, &d.bad, 1);
+        rc = rc ? rc : dev_alloc(c, &d.cg_rr, static_cast<size_t>(kMaxComp) * kRing * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cg_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cg_bb, static_cast<size_t>(kMaxComp) * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cg_rq, static_cast<size_t>(kRing) * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cg_qq, static_cast<size_t>(kRing) * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cg_flags, 2 * kMaxComp);
+        if (c->precision == GSPM_MIXED) {
+            for (float **p : {&d.r32, &d.p32, &d.p32b, &d.q32, &d.x32, &d.r32b, &d.q32b}) rc = rc ? rc : dev_alloc(c, p, n3);
+            rc = rc ? rc : dev_alloc(c, &d.cgi_rq, static_cast<size_t>(kRing) * kShards);
+            rc = rc ? rc : dev_alloc(c, &d.cgi_qq, static_cast<size_t>(kRing) * kShards);
+            rc = rc ? rc : dev_alloc(c, &d.cgi_rr, static_cast<size_t>(kMaxComp) * kRing * kShards);
+            rc = rc ? rc : dev_alloc(c, &d.cgi_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
+            rc = rc ? rc : dev_alloc(c, &d.cgi_bb, static_cast<size_t>(kMaxComp) * kShards);
+            rc = rc ? rc : dev_alloc(c, &d.cgi_flags, 2 * kMaxComp);
+        }
+        return rc;
+    };
+    c->arena_planning = true;
+    c->arena_size = 0;
+    alloc_all();
+    c->arena_planning = false;
+    rc = hip_check(c, hipMalloc(reinterpret_cast<void **>(&c->arena), c->arena_size), "hipMalloc (mesh arena)");
+    if (rc) {
+        c->arena = nullptr;
+        c->arena_size = 0;
+    } else {
+        c->arena_used = 0;
+        rc = alloc_all();
     }
     if (rc) {
         c->release_mesh();

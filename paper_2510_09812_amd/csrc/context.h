@@ -86,6 +86,9 @@ struct gspm_ctx {
     std::vector<double> w_host;   // lumped weights (internal order)
 
     gspm::DeviceBuffers d;
+    char *arena = nullptr;                // one allocation holding the mesh upload's buffers
+    size_t arena_size = 0, arena_used = 0;
+    bool arena_planning = false;
     gspm::MeshView mv{};
     gspm::CGScalars cg{};
     gspm::CGScalars cg_in{};      // inner FP32 solves of the mixed form
