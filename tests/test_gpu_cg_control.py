@@ -12,7 +12,7 @@ the edge cases of that control on a small mesh with an inclusion:
   - a zero right-hand side: x = 0 exactly, no iteration;
   - a start that already meets the tolerance: no iteration, x unchanged;
   - tolerances from loose to tight: the oracle's iteration count (within 1)
-    and its solution (1e-9 relative at equal counts, 100 tol one apart).
+    and its solution (0.1 tol relative at equal counts, 100 tol one apart).
 
 The elastic cases run in FP64 and in the mixed form (zero right-hand side and
 converged start only: the mixed form's iterates differ from FP64 CG's by
@@ -138,7 +138,8 @@ def test_elastic_iterations_and_solution_match_oracle(case, tol):
     assert st == gspm.GSPM_OK and rc == 0
     assert abs(it - itr) <= 1
     # the same iteration count: the same steps up to rounding (summation
-    # orders differ); one apart (a residual within rounding of the threshold):
-    # both iterates meet the tolerance, and differ by one step of that size
-    assert err < (1e-9 if it == itr else 100 * tol)
+    # orders differ), which moves an iterate by a small fraction of its
+    # remaining error (of order tol); one apart (a residual within rounding of
+    # the threshold): both meet the tolerance and differ by one step
+    assert err < (0.1 * tol if it == itr else 100 * tol)
     sim.close()
