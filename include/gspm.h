@@ -155,6 +155,32 @@ gspm_status gspm_get_field(gspm_ctx *ctx, gspm_field which, double *out, int64_t
  * completed step and stats->failed_step names the step that failed. */
 gspm_status gspm_step(gspm_ctx *ctx, double dt, int32_t n_steps, gspm_step_stats *stats);
 
+/* Relax at the current applied field and stress (Sec. 3.3): steps of dt
+ * seconds until the mean per-node change of m over one step, dm_avg =
+ * <|m^n - m^{n-1}|> on the magnetic nodes (Sec. 3.2), falls below dm_tol (the
+ * paper uses 5e-10), at most max_steps.  stats (nullable) sums the
+ * iterations of the steps taken; steps_done counts them, dm_avg is the last
+ * step's.  Returns GSPM_E_NOCONV after max_steps steps without convergence
+ * (the state is that after the last step, so the call can be repeated); a
+ * failing step returns its status with the state after the step before. */
+gspm_status gspm_relax(gspm_ctx *ctx, double dt, double dm_tol, int32_t max_steps, gspm_step_stats *stats);
+
+/* A field (and stress) sweep, as the hysteresis runs of Sec. 3.3 (the field
+ * lowered in steps of 20 A/m until the magnetisation reverses; a uniaxial
+ * stress as a second parameter): for point k = 0 .. n_points-1 the applied
+ * field becomes hext[3k .. 3k+2] and, when sigma_ext is not NULL, the applied
+ * stress sigma_ext[6k .. 6k+5] (the other parameters stay as set), the state
+ * relaxes as in gspm_relax, and mbar[3k .. 3k+2] receives the cell-averaged
+ * magnetisation and steps[k] the steps taken.  With stop_on_reversal nonzero
+ * the sweep ends after the first point whose mbar has a non-positive
+ * component along the first point's field (the coercive point; that field
+ * must be nonzero).  points_done (nullable) receives the points completed.
+ * The first point that fails to relax ends the sweep with its status (steps
+ * filled for it, mbar not).  The parameters keep the last point's field. */
+gspm_status gspm_sweep(gspm_ctx *ctx, double dt, double dm_tol, int32_t max_steps, int32_t n_points,
+                       const double *hext, const double *sigma_ext, int32_t stop_on_reversal, double *mbar,
+                       int32_t *steps, int32_t *points_done);
+
 /* Energy densities of Eq. (MicromagneticsEnergy) averaged over the cell
  * [J/m^3] at the current state: out = {exchange, anisotropy, zeeman,
  * magnetoelastic, stress work, far-field demagnetisation, total}. */

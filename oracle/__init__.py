@@ -225,6 +225,37 @@ class Oracle:
         self._check(rc)
         return stats
 
+    def relax(self, dt: float, dm_tol: float, max_steps: int):
+        """Sec. 3.3: steps of dt until the step's mean per-node |m^n - m^{n-1}|
+        over the magnetic nodes drops below dm_tol.  Returns (steps taken,
+        converged)."""
+        for k in range(1, max_steps + 1):
+            if self.step(dt, 1)["dm_avg"] < dm_tol:
+                return k, True
+        return max_steps, False
+
+    def sweep(self, params: dict, dt: float, dm_tol: float, max_steps: int, hext, sigma_ext=None,
+              stop_on_reversal: bool = False, precession: bool = True):
+        """Sec. 3.3 hysteresis protocol: for each applied field (and stress),
+        relax and record the cell-averaged m; optionally stop after the first
+        point whose mbar points against the first field.  Returns (mbar list,
+        steps list)."""
+        hext = np.asarray(hext, dtype=np.float64).reshape(-1, 3)
+        first = hext[0]
+        mbars, steps = [], []
+        for k in range(hext.shape[0]):
+            sig = (0.0,) * 6 if sigma_ext is None else tuple(np.asarray(sigma_ext, dtype=np.float64).reshape(-1, 6)[k])
+            self.set_params(params, hext=tuple(hext[k]), sigma_ext=sig, precession=precession)
+            n, ok = self.relax(dt, dm_tol, max_steps)
+            steps.append(n)
+            if not ok:
+                break
+            mbar, _ = self.averages()
+            mbars.append(mbar)
+            if stop_on_reversal and float(np.dot(mbar, first)) <= 0.0:
+                break
+        return mbars, steps
+
     def energies(self) -> dict:
         out = np.zeros(7)
         self._check(self._lib.or_energies(self._h, _dp(out)))

@@ -31,7 +31,7 @@ EXPORTS = ("gspm_create", "gspm_destroy", "gspm_upload_mesh", "gspm_set_params",
            "gspm_get_field", "gspm_step", "gspm_energies", "gspm_averages", "gspm_apply", "gspm_solve",
            "gspm_mesh_info", "gspm_demag_factors", "gspm_time_operator", "gspm_last_error",
            "gspm_set_warm_start", "gspm_mpnn_set_params", "gspm_mpnn_get_params", "gspm_mpnn_forward",
-           "gspm_mpnn_train_step", "gspm_mpnn_warm_start", "gspm_set_profile")
+           "gspm_mpnn_train_step", "gspm_mpnn_warm_start", "gspm_set_profile", "gspm_relax", "gspm_sweep")
 
 
 class GspmError(RuntimeError):
@@ -82,6 +82,12 @@ def load() -> ctypes.CDLL:
     lib.gspm_get_field.argtypes = [P, ctypes.c_int, dp, i64]; lib.gspm_get_field.restype = S
     lib.gspm_step.argtypes = [P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(gspm_step_stats)]
     lib.gspm_step.restype = S
+    lib.gspm_relax.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(gspm_step_stats)]
+    lib.gspm_relax.restype = S
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.gspm_sweep.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, dp, dp,
+                               ctypes.c_int32, dp, i32p, i32p]
+    lib.gspm_sweep.restype = S
     lib.gspm_energies.argtypes = [P, dp]; lib.gspm_energies.restype = S
     lib.gspm_averages.argtypes = [P, dp, dp]; lib.gspm_averages.restype = S
     lib.gspm_apply.argtypes = [P, ctypes.c_int, ctypes.c_double, dp, dp, i64]; lib.gspm_apply.restype = S
@@ -206,6 +212,44 @@ def gspm_step(ctx, dt: float, n_steps: int = 1) -> dict:
         err.stats = stats_dict(st)
         raise err
     return stats_dict(st)
+
+
+def gspm_relax(ctx, dt: float, dm_tol: float, max_steps: int) -> dict:
+    """Steps until <|dm|> < dm_tol; returns the summed stats.  On failure
+    (GSPM_E_NOCONV after max_steps included) the GspmError carries them in
+    its `stats` attribute."""
+    st = gspm_step_stats()
+    status = load().gspm_relax(ctx, dt, dm_tol, max_steps, ctypes.byref(st))
+    if status != GSPM_OK:
+        err = GspmError(status, gspm_last_error(ctx))
+        err.stats = stats_dict(st)
+        raise err
+    return stats_dict(st)
+
+
+def gspm_sweep(ctx, dt: float, dm_tol: float, max_steps: int, hext, sigma_ext=None,
+               stop_on_reversal: bool = False) -> dict:
+    """Relaxes at each applied field (n x 3) and stress (n x 6, or None);
+    returns mbar (points done x 3), steps (points done) and points_done.  On
+    failure the GspmError carries them in its `sweep` attribute."""
+    h = _f64(hext, (-1, 3))
+    n = h.shape[0]
+    sg = None if sigma_ext is None else _f64(sigma_ext, (n, 6))
+    mbar = np.zeros((n, 3))
+    steps = np.zeros(n, dtype=np.int32)
+    done = ctypes.c_int32(0)
+    status = load().gspm_sweep(ctx, dt, dm_tol, max_steps, n, _dp(h), None if sg is None else _dp(sg),
+                               1 if stop_on_reversal else 0, _dp(mbar), steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               ctypes.byref(done))
+    k = done.value
+    # a failing point has its steps filled but no mbar
+    ns = k + 1 if status != GSPM_OK and k < n else k
+    out = dict(mbar=mbar[:k].copy(), steps=steps[:ns].copy(), points_done=k)
+    if status != GSPM_OK:
+        err = GspmError(status, gspm_last_error(ctx))
+        err.sweep = out
+        raise err
+    return out
 
 
 ENERGY_KEYS = ("exchange", "anisotropy", "zeeman", "magnetoelastic", "stress", "demag_far", "total")
@@ -349,6 +393,12 @@ class Simulation:
 
     def step(self, dt: float, n: int = 1) -> dict:
         return gspm_step(self.ctx, dt, n)
+
+    def relax(self, dt: float, dm_tol: float, max_steps: int) -> dict:
+        return gspm_relax(self.ctx, dt, dm_tol, max_steps)
+
+    def sweep(self, dt: float, dm_tol: float, max_steps: int, hext, sigma_ext=None, stop_on_reversal=False) -> dict:
+        return gspm_sweep(self.ctx, dt, dm_tol, max_steps, hext, sigma_ext, stop_on_reversal)
 
     def energies(self) -> dict:
         return gspm_energies(self.ctx)

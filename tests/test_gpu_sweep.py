@@ -1,0 +1,110 @@
+"""Relaxation and field/stress sweeps (Sec. 3.3) against the oracle's loops.
+
+The hysteresis protocol steps at a fixed applied field until the mean
+per-node change of m over one step drops below a threshold, records the
+cell-averaged magnetisation, and moves to the next field (the paper lowers it
+in steps of 20 A/m until the magnetisation reverses); a uniaxial stress is the
+second swept parameter.  The library runs the loop on the host around its
+device steps (gspm_relax, gspm_sweep); the oracle runs the same protocol
+around its own steps (written separately in oracle/).  Both take the same
+steps to 1e-12, so they stop at the same step of every point: the step counts
+must agree exactly and the recorded averages to 1e-8.
+
+Workload: a ragged 8-node-per-axis cube (343 unique nodes) with a spherical
+inclusion, Fe-Ga constants, no far-field demagnetisation (Nd = 0, so the
+uniform state is stable and the field alone reverses it), m along +x with 2%
+noise, dt = 10 ps, threshold 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as w
+from paper_2510_09812_amd import gspm
+
+pytestmark = pytest.mark.gpu
+
+DT, TOL = 1e-11, 1e-6
+
+
+@pytest.fixture(scope="module")
+def setup():
+    case = w.small_cube(8, seed=71, L=8e-8, jitter=0.15, sphere=0.3)
+    params = dict(case.params)
+    params["Nd"] = np.zeros((3, 3))
+    m0 = np.zeros((case.mesh.n_nodes, 3))
+    m0[:, 0] = 1.0
+    rng = np.random.default_rng(3)
+    m0 += 0.02 * case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)))
+    return case, params, m0
+
+
+def _pair(setup, hext=(2e4, 0.0, 0.0)):
+    case, params, m0 = setup
+    sim = gspm.Simulation(case.mesh, params, hext=hext)
+    sim.set_m(m0)
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(params, hext=hext)
+    orc.set_m(m0)
+    return sim, orc, params
+
+
+def test_field_sweep_to_reversal_matches_oracle(setup):
+    sim, orc, params = _pair(setup)
+    H = [(2e4, 0.0, 0.0), (-1e4, 0.0, 0.0), (-3e4, 0.0, 0.0), (-6e4, 0.0, 0.0), (-1.2e5, 0.0, 0.0)]
+    out = sim.sweep(DT, TOL, 3000, H, stop_on_reversal=True)
+    mb, steps = orc.sweep(params, DT, TOL, 3000, H, stop_on_reversal=True)
+    print(f"gpu steps {out['steps'].tolist()} mbar_x {np.round(out['mbar'][:, 0], 5).tolist()} | "
+          f"oracle steps {steps} mbar_x {[round(m[0], 5) for m in mb]}", flush=True)
+    assert out["points_done"] == len(mb) == len(steps)
+    assert out["steps"].tolist() == steps
+    assert np.abs(out["mbar"] - np.array(mb)).max() < 1e-8
+    # it stopped at the first reversed point, before the end of the list
+    assert out["points_done"] < len(H)
+    assert out["mbar"][-1, 0] < 0 and np.all(out["mbar"][:-1, 0] > 0)
+    sim.close()
+
+
+def test_stress_sweep_matches_oracle(setup):
+    sim, orc, params = _pair(setup)
+    H = [(2e4, 0.0, 0.0)] * 3
+    S = [(0.0,) * 6, (-1e8, 0.0, 0.0, 0.0, 0.0, 0.0), (-3e8, 0.0, 0.0, 0.0, 0.0, 0.0)]
+    out = sim.sweep(DT, TOL, 3000, H, sigma_ext=S)
+    mb, steps = orc.sweep(params, DT, TOL, 3000, H, sigma_ext=S)
+    print(f"gpu steps {out['steps'].tolist()} mbar {np.round(out['mbar'], 5).tolist()} | oracle steps {steps}",
+          flush=True)
+    assert out["points_done"] == 3 and out["steps"].tolist() == steps
+    assert np.abs(out["mbar"] - np.array(mb)).max() < 1e-8
+    # the compressive stress along x turns m away from x (lambda100 > 0)
+    assert abs(out["mbar"][2, 0]) < 0.5 * out["mbar"][0, 0]
+    sim.close()
+
+
+def test_relax_budget_then_continuation(setup):
+    sim, orc, params = _pair(setup)
+    with pytest.raises(gspm.GspmError) as e:
+        sim.relax(DT, TOL, 5)
+    assert e.value.status == gspm.GSPM_E_NOCONV and e.value.stats["steps_done"] == 5
+    assert e.value.stats["dm_avg"] >= TOL
+    st = sim.relax(DT, TOL, 3000)
+    n, ok = orc.relax(DT, TOL, 3000)
+    print(f"gpu 5 + {st['steps_done']} steps, oracle {n}", flush=True)
+    assert ok and 5 + st["steps_done"] == n and st["dm_avg"] < TOL
+    assert np.abs(sim.averages()[0] - orc.averages()[0]).max() < 1e-8
+    sim.close()
+
+
+def test_argument_errors(setup):
+    sim, orc, params = _pair(setup)
+    for bad in (dict(dt=0.0, dm_tol=TOL, max_steps=10), dict(dt=DT, dm_tol=0.0, max_steps=10),
+                dict(dt=DT, dm_tol=TOL, max_steps=0)):
+        with pytest.raises(gspm.GspmError) as e:
+            sim.relax(**bad)
+        assert e.value.status == gspm.GSPM_E_ARG
+    with pytest.raises(gspm.GspmError) as e:
+        sim.sweep(DT, TOL, 10, [(0.0, 0.0, 0.0)], stop_on_reversal=True)
+    assert e.value.status == gspm.GSPM_E_ARG
+    with pytest.raises(gspm.GspmError) as e:
+        sim.sweep(DT, TOL, 10, np.zeros((0, 3)))
+    assert e.value.status == gspm.GSPM_E_ARG
+    sim.close()
