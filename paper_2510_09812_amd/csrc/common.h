@@ -52,10 +52,11 @@ struct HostMesh {
 };
 
 // A strip segment is a sequence of window updates.  Entry = local vertex id
-// (13 bits) | element-complete flag (bit 13) | slot (2 bits) << 14: load that
-// staged vertex into one of four window slots (replacing the vertex held
-// there); when the flag is set, the window now holds exactly the four
-// vertices of the segment's next element.
+// (13 bits) | element-complete flag (bit 13) | slot (2 bits) << 14.  The
+// first four entries of a segment fill slots 0..3 in order; every later one
+// makes the vertex in the named slot leave, moves the vertex of slot 3 into
+// that slot and puts the new vertex in slot 3.  When the flag is set, the
+// window holds exactly the four vertices of the segment's next element.
 constexpr uint32_t kEntIdMask = 0x1FFFu;
 constexpr uint32_t kEntElem = 1u << 13;
 constexpr int kMaxLocal = 8191;           // staged nodes per block the entries can address

@@ -328,23 +328,27 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
 #pragma unroll
                 for (int c = 0; c < NC; ++c) atomicAdd(&st.acc[c * nb + oid], static_cast<double>(oacc[c]));
             }
-            // load the new vertex into slot sl
-            const T nx = st.sx[id], ny = st.sy[id], nz = st.sz[id];
-            T nf[NF];
+            // the vertex of slot 3 moves into the freed slot, the new vertex
+            // takes slot 3 (so only three slots need data-dependent selects)
 #pragma unroll
-            for (int c = 0; c < NF; ++c) nf[c] = st.fld(c, id);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 3; ++j) {
                 const bool hit = sl == j;
-                ids[j] = hit ? id : ids[j];
-                x[j][0] = hit ? nx : x[j][0];
-                x[j][1] = hit ? ny : x[j][1];
-                x[j][2] = hit ? nz : x[j][2];
+                ids[j] = hit ? ids[3] : ids[j];
 #pragma unroll
-                for (int c = 0; c < NF; ++c) f[j][c] = hit ? nf[c] : f[j][c];
+                for (int a = 0; a < 3; ++a) x[j][a] = hit ? x[3][a] : x[j][a];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[j][c] = hit ? T(0) : acc[j][c];
+                for (int c = 0; c < NF; ++c) f[j][c] = hit ? f[3][c] : f[j][c];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[j][c] = hit ? acc[3][c] : acc[j][c];
             }
+            ids[3] = id;
+            x[3][0] = st.sx[id];
+            x[3][1] = st.sy[id];
+            x[3][2] = st.sz[id];
+#pragma unroll
+            for (int c = 0; c < NF; ++c) f[3][c] = st.fld(c, id);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[3][c] = T(0);
             if (e & kEntElem) element();
         }
 #pragma unroll

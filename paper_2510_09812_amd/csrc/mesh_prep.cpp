@@ -113,13 +113,14 @@ static void strip_order(const uint16_t *lc, int32_t m, std::vector<int32_t> &ord
 
 // Packs a strip order into segments of at most `budget` window updates (an
 // element's updates never straddle two segments).  Along a strip an element
-// costs one vertex load; at a strip break or a segment start the missing
-// vertices are loaded first.  A new vertex replaces a slot whose vertex the
-// element does not use (empty first, else the least recently used), so the
-// four slots hold exactly the element's vertices at its flagged entry; a
-// segment therefore opens with its first element's vertices in slots 0..3,
-// in order (the operator kernels rely on it).  With `emit` false only the
-// number of segments is returned.
+// costs one vertex load; at a strip break the missing vertices are loaded
+// first.  A segment opens with its first element's four vertices in slots
+// 0..3, in order.  After that every load follows the kernels' rotation: the
+// entering vertex takes slot 3 and the vertex held in slot 3 moves into the
+// slot of the vertex that leaves, which is one the element does not use (the
+// least recently used).  An entry names the leaving vertex's slot, so at a
+// flagged entry the four slots hold exactly the element's vertices.  With
+// `emit` false only the number of segments is returned.
 static int32_t pack_strips(const uint16_t *lc, const std::vector<int32_t> &order, int budget, bool emit,
                            std::vector<uint16_t> &ent, std::vector<uint32_t> &off, std::vector<uint16_t> &nent) {
     int32_t win[4] = {-1, -1, -1, -1};
@@ -140,27 +141,33 @@ static int32_t pack_strips(const uint16_t *lc, const std::vector<int32_t> &order
         auto in_elem = [&](int32_t x) { return x == v[0] || x == v[1] || x == v[2] || x == v[3]; };
         int nnew = 0;
         for (int j = 0; j < 4; ++j) nnew += !in_win(v[j]);
-        if (used > 0 && used + nnew > budget) {
-            close();
-            nnew = 4;
-        }
+        if (used > 0 && used + nnew > budget) close();
         if (used == 0) {
+            // the opening element: its vertices straight into slots 0..3
             ++segs;
             if (emit) off.push_back(static_cast<uint32_t>(ent.size() / 8));
-        }
-        for (int j = 0; j < 4; ++j) {
-            if (in_win(v[j])) continue;
-            int slot = -1;
-            for (int k = 0; k < 4; ++k) {
-                if (in_elem(win[k])) continue;          // the element still needs this vertex
-                if (win[k] < 0) { slot = k; break; }    // an empty slot first
-                if (slot < 0 || lru[k] < lru[slot]) slot = k;
+            for (int j = 0; j < 4; ++j) {
+                win[j] = v[j];
+                if (emit) ent.push_back(static_cast<uint16_t>(v[j] | (j << 14) | (j == 3 ? kEntElem : 0u)));
             }
-            win[slot] = v[j];
-            ++used;
-            if (emit) ent.push_back(static_cast<uint16_t>(v[j] | (slot << 14)));
+            used = 4;
+        } else {
+            for (int j = 0; j < 4; ++j) {
+                if (in_win(v[j])) continue;
+                int slot = -1;
+                for (int k = 0; k < 4; ++k) {
+                    if (in_elem(win[k])) continue;      // the element still needs this vertex
+                    if (slot < 0 || lru[k] < lru[slot]) slot = k;
+                }
+                win[slot] = win[3];                     // slot 3's vertex moves into the freed slot
+                lru[slot] = lru[3];
+                win[3] = v[j];                          // the entering vertex takes slot 3
+                lru[3] = 0;
+                ++used;
+                if (emit) ent.push_back(static_cast<uint16_t>(v[j] | (slot << 14)));
+            }
+            if (emit) ent.back() = static_cast<uint16_t>(ent.back() | kEntElem);
         }
-        if (emit) ent.back() = static_cast<uint16_t>(ent.back() | kEntElem);
         for (int k = 0; k < 4; ++k)
             if (in_elem(win[k])) lru[k] = ++clock;
     }

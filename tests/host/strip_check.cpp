@@ -61,8 +61,14 @@ int main(int argc, char **argv) {
                 unsigned e = M.seg_ent[k++];
                 int id = e & kEntIdMask, sl = e >> 14;
                 if (id >= nloc) { bad++; printf("id %d >= nloc %d\n", id, nloc); }
-                if (win[sl] >= 0 && win[sl] < M.nb) flush++;
-                win[sl] = id; loads++;
+                if (i < 4) {
+                    win[i] = id;                               // the opening element fills slots 0..3
+                } else {
+                    if (win[sl] >= 0 && win[sl] < M.nb) flush++;
+                    win[sl] = win[3];                          // slot 3 moves into the freed slot
+                    win[3] = id;                               // the new vertex takes slot 3
+                }
+                loads++;
                 if (e & kEntElem) {
                     std::array<int,4> v{win[0], win[1], win[2], win[3]};
                     std::sort(v.begin(), v.end());
