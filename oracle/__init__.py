@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gspm_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-OP_LAPLACE, OP_MASS, OP_GS, OP_ELASTIC, OP_LAPLACE_ALL = 0, 1, 2, 3, 4
+OP_LAPLACE, OP_MASS, OP_GS, OP_ELASTIC, OP_LAPLACE_ALL, OP_MS = 0, 1, 2, 3, 4, 5
 
 
 def build() -> str:
@@ -36,12 +36,13 @@ class _Params(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0")] + [
         ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
-        ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32)]
+        ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32),
+        ("local_demag", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int32), ("mech_iters", ctypes.c_int32),
-                ("gs_iters", ctypes.c_int32 * 8), ("dm_avg", ctypes.c_double)]
+                ("gs_iters", ctypes.c_int32 * 8), ("dm_avg", ctypes.c_double), ("ms_iters", ctypes.c_int32)]
 
 
 _lib = None
@@ -68,6 +69,12 @@ def _load():
     lib.or_set_params.argtypes = [P, ctypes.POINTER(_Params)]
     lib.or_set_m.argtypes = [P, dp]; lib.or_set_u.argtypes = [P, dp]
     lib.or_get_m.argtypes = [P, dp]; lib.or_get_u.argtypes = [P, dp]
+    lib.or_set_ud.argtypes = [P, dp]; lib.or_get_ud.argtypes = [P, dp]
+    lib.or_demag_local_energy.argtypes = [P, dp]
+    lib.or_ms_rhs_at.argtypes = [P, dp, dp]
+    lib.or_ms_solve_at.argtypes = [P, dp, dp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.or_ms_field.argtypes = [P, dp, dp]
+    lib.or_ms_energy.argtypes = [P, dp, dp]
     lib.or_apply.argtypes = [P, ctypes.c_int32, ctypes.c_double, dp, dp]
     lib.or_solve.argtypes = [P, ctypes.c_int32, ctypes.c_double, dp, dp, ctypes.c_double, ctypes.c_int32,
                              ctypes.POINTER(ctypes.c_int32)]
@@ -104,7 +111,7 @@ class OracleError(RuntimeError):
 
 
 def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession: bool = True,
-                cg_maxit: int = 10000) -> _Params:
+                cg_maxit: int = 10000, local_demag: bool = False) -> _Params:
     p = _Params()
     for k in ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0"):
         setattr(p, k, float(params[k]))
@@ -118,6 +125,7 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
     p.cg_tol = float(params.get("cg_tol", 1e-8))
     p.cg_maxit = int(params.get("cg_maxit", cg_maxit))
     p.precession = 1 if precession else 0
+    p.local_demag = 1 if local_demag else 0
     return p
 
 
@@ -201,8 +209,9 @@ class Oracle:
         return int(self._lib.or_pinned_node(self._h))
 
     # ---- state
-    def set_params(self, params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession=True):
-        self._p = make_params(params, hext, sigma_ext, precession)
+    def set_params(self, params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession=True,
+                   local_demag=False):
+        self._p = make_params(params, hext, sigma_ext, precession, local_demag=local_demag)
         self._check(self._lib.or_set_params(self._h, ctypes.byref(self._p)))
 
     def set_m(self, m):
@@ -217,11 +226,43 @@ class Oracle:
     def get_u(self) -> np.ndarray:
         out = np.zeros((self.n0, 3)); self._lib.or_get_u(self._h, _dp(out)); return out
 
+    def set_ud(self, ud):
+        self._check(self._lib.or_set_ud(self._h, _dp(_f64(ud, (-1,)))))
+
+    def get_ud(self) -> np.ndarray:
+        out = np.zeros(self.n0); self._lib.or_get_ud(self._h, _dp(out)); return out
+
+    def demag_local_energy(self) -> float:
+        e = np.zeros(1); self._check(self._lib.or_demag_local_energy(self._h, _dp(e))); return float(e[0])
+
+    # ---- local magnetostatics on explicit unique-order arrays (state untouched)
+    def ms_rhs(self, m_unique) -> np.ndarray:
+        b = np.zeros(self.n)
+        self._check(self._lib.or_ms_rhs_at(self._h, _dp(_f64(m_unique, (self.n, 3))), _dp(b)))
+        return b
+
+    def ms_solve(self, m_unique, U0=None, tol: float = 1e-12, maxit: int = 100000):
+        U = np.zeros(self.n) if U0 is None else _f64(U0, (self.n,)).copy()
+        it = ctypes.c_int32(0)
+        self._check(self._lib.or_ms_solve_at(self._h, _dp(_f64(m_unique, (self.n, 3))), _dp(U), tol, maxit,
+                                             ctypes.byref(it)))
+        return U, int(it.value)
+
+    def ms_field(self, U) -> np.ndarray:
+        hd = np.zeros((self.ne, 3))
+        self._check(self._lib.or_ms_field(self._h, _dp(_f64(U, (self.n,))), _dp(hd)))
+        return hd
+
+    def ms_energy(self, U) -> float:
+        e = np.zeros(1)
+        self._check(self._lib.or_ms_energy(self._h, _dp(_f64(U, (self.n,))), _dp(e)))
+        return float(e[0])
+
     def step(self, dt: float, n: int = 1) -> dict:
         st = _Stats()
         rc = self._lib.or_step(self._h, dt, n, ctypes.byref(st))
         stats = dict(steps_done=st.steps_done, mech_iters=st.mech_iters, gs_iters=list(st.gs_iters),
-                     dm_avg=st.dm_avg)
+                     dm_avg=st.dm_avg, ms_iters=st.ms_iters)
         self._check(rc)
         return stats
 

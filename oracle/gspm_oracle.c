@@ -14,6 +14,9 @@
  *     far-field demagnetising field -N_d mbar (Sec. 2.1);
  *   - unpreconditioned CG with d pinned DOFs (Sec. 2.5) and the relative
  *     residual criterion of Sec. 3.1;
+ *   - optionally the local magnetostatic potential of Eq. (demag) in the weak
+ *     form (weak_demag), with K^ms and F^ms of Eqs. (LHS), (RHS_F) and
+ *     (RHS_b), and its field -grad U~ (Sec. 2.1);
  *   - one step of the Gauss-Seidel projection method, Algorithm B.1 (App. B),
  *     with the effective field of App. B and the energy of Eq.
  *     (MicromagneticsEnergy), spontaneous strain from App. A.
@@ -51,6 +54,7 @@ struct or_sim {
     double C[3][3][3][3];
     int p0;
     double *m, *u;       /* n x 3 */
+    double *ud;          /* n: local magnetostatic potential U~ */
     char err[256];
 };
 
@@ -458,6 +462,7 @@ void or_destroy(or_sim *s) {
     free(s->map); free(s->x); free(s->tet); free(s->tag); free(s->vol); free(s->grad); free(s->w); free(s->mag);
     free(s->n2e_ptr); free(s->n2e); free(s->adj_ptr); free(s->adj);
     free(s->Kmag); free(s->Mmag); free(s->Kall); free(s->Kmech); free(s->m); free(s->u);
+    free(s->ud);
     free(s);
 }
 
@@ -514,11 +519,17 @@ int or_set_params(or_sim *s, const or_params *p) {
         seterr(s, "invalid parameters");
         return OR_E_ARG;
     }
+    if (p->local_demag != 0 && p->local_demag != 1) { seterr(s, "local_demag must be 0 or 1"); return OR_E_ARG; }
+    if (p->local_demag && !s->periodic) {
+        seterr(s, "the local magnetostatic solve needs a periodic mesh");
+        return OR_E_ARG;
+    }
     s->p = *p;
     cubic_tensor(p, s->C);
     assemble_elastic(s);
     s->have_params = 1;
     if (!s->u) s->u = (double *)calloc((size_t)s->n * 3, sizeof(double));
+    if (!s->ud) s->ud = (double *)calloc((size_t)s->n, sizeof(double));
     return OR_OK;
 }
 
@@ -562,6 +573,26 @@ int or_set_m(or_sim *s, const double *m) {
 int or_set_u(or_sim *s, const double *u) {
     if (!s->u) s->u = (double *)calloc((size_t)s->n * 3, sizeof(double));
     return set_nodal(s, u, s->u);
+}
+
+int or_set_ud(or_sim *s, const double *ud) {
+    if (!s->ud) s->ud = (double *)calloc((size_t)s->n, sizeof(double));
+    unsigned char *seen = (unsigned char *)calloc((size_t)s->n, 1);
+    for (int i = 0; i < s->n0; ++i) {
+        int g = s->map[i];
+        if (!isfinite(ud[i])) { free(seen); seterr(s, "non-finite field value"); return OR_E_ARG; }
+        if (seen[g] && fabs(s->ud[g] - ud[i]) > 1e-12 * (1.0 + fabs(s->ud[g]))) {
+            free(seen); seterr(s, "periodic copies disagree"); return OR_E_ARG;
+        }
+        s->ud[g] = ud[i];
+        seen[g] = 1;
+    }
+    free(seen);
+    return OR_OK;
+}
+
+void or_get_ud(const or_sim *s, double *ud) {
+    for (int i = 0; i < s->n0; ++i) ud[i] = s->ud ? s->ud[s->map[i]] : 0.0;
 }
 
 void or_get_m(const or_sim *s, double *m) {
@@ -617,6 +648,10 @@ int or_apply(const or_sim *s, int32_t which, double eps, const double *x, double
         if (which == 0) spmv_scalar(s, s->Kmag, x, y, 3, c);
         else if (which == 1) spmv_scalar(s, s->Mmag, x, y, 3, c);
         else if (which == 4) spmv_scalar(s, s->Kall, x, y, 3, c);
+        else if (which == 5) {
+            spmv_scalar(s, s->Kall, x, y, 3, c);
+            y[s->p0 * 3 + c] = 0.0;
+        }
         else if (which == 2) {
 #pragma omp parallel for schedule(static)
             for (int i = 0; i < s->n; ++i) {
@@ -689,6 +724,21 @@ static void cg_apply_gs(const or_sim *s, const void *ctx, const double *x, doubl
     apply_gs_scalar(s, *(const double *)ctx, x, y);
 }
 
+static void cg_apply_ms(const or_sim *s, const void *ctx, const double *x, double *y) {
+    (void)ctx;
+    spmv_scalar(s, s->Kall, x, y, 1, 0);
+}
+
+/* K^ms U = b (Eq. weak_demag): the Laplacian over the whole cell with the
+ * potential pinned to zero at node p0 (d = 1 pinned DOF, Sec. 2.5). */
+static int solve_ms(const or_sim *s, const double *b, double *U, double tol, int maxit, int *iters) {
+    uint8_t *fixed = (uint8_t *)calloc((size_t)s->n, 1);
+    fixed[s->p0] = 1;
+    int rc = cg(s, cg_apply_ms, NULL, s->n, fixed, b, U, tol, maxit, iters);
+    free(fixed);
+    return rc;
+}
+
 static int solve_elastic(const or_sim *s, const double *b, double *u, double tol, int maxit, int *iters) {
     int len = 3 * s->n;
     uint8_t *fixed = (uint8_t *)calloc((size_t)len, 1);
@@ -715,13 +765,13 @@ int or_solve(const or_sim *s, int32_t which, double eps, const double *b, double
         *iters = it;
         return rc;
     }
-    if (which != 2) return OR_E_ARG;
+    if (which != 2 && which != 5) return OR_E_ARG;
     int n = s->n, total = 0, rc = OR_OK;
     double *bc = (double *)malloc(sizeof(double) * (size_t)n), *xc = (double *)malloc(sizeof(double) * (size_t)n);
     for (int c = 0; c < 3 && rc == OR_OK; ++c) {
         for (int i = 0; i < n; ++i) { bc[i] = b[i * 3 + c]; xc[i] = x[i * 3 + c]; }
         int it = 0;
-        rc = solve_gs(s, eps, bc, xc, tol, maxit, &it);
+        rc = which == 2 ? solve_gs(s, eps, bc, xc, tol, maxit, &it) : solve_ms(s, bc, xc, tol, maxit, &it);
         total += it;
         for (int i = 0; i < n; ++i) x[i * 3 + c] = xc[i];
     }
@@ -786,12 +836,88 @@ static void elastic_rhs_at(const or_sim *s, const double *m, double *b) {
     for (int a = 0; a < 3; ++a) b[s->p0 * 3 + a] = 0.0;
 }
 
+/* ------------------------------------------------ local magnetostatics */
+
+/* Right-hand side of Eq. (weak_demag) as assembled in Eqs. (RHS_F) and
+ * (RHS_b): b_i = Ms F^ms_{ij,a} m_{j,a} with F^ms_{ij,a} = -int phi_i d_a phi_j
+ * over the whole cell, i.e. b_i = -Ms int phi_i div(m_h).  On a tetrahedron
+ * div(m_h) = sum_j m_j . grad(lambda_j) is constant and int phi_i = V_e / 4.
+ * m is the nodal field (zero at nodes inside the inclusions only); the mean
+ * mbar drops out (its divergence is zero), so this is the right-hand side for
+ * m~ as well.  The pinned node's row is zero. */
+static void ms_rhs_at(const or_sim *s, const double *m, double *b) {
+    memset(b, 0, sizeof(double) * (size_t)s->n);
+    for (int e = 0; e < s->ne; ++e) {
+        double div = 0.0;
+        for (int v = 0; v < 4; ++v) {
+            const double *g = &s->grad[e * 12 + v * 3];
+            const double *mv = &m[s->tet[e * 4 + v] * 3];
+            div += mv[0] * g[0] + mv[1] * g[1] + mv[2] * g[2];
+        }
+        for (int v = 0; v < 4; ++v) b[s->tet[e * 4 + v]] += -s->p.Ms * 0.25 * s->vol[e] * div;
+    }
+    b[s->p0] = 0.0;
+}
+
+/* The local demagnetising field of element e in units of Ms (Sec. 2.1):
+ * h~_d = H~_d / Ms = -grad(U~) / Ms, constant on a P1 element. */
+static void ms_field_elem(const or_sim *s, const double *U, int e, double hd[3]) {
+    hd[0] = hd[1] = hd[2] = 0.0;
+    for (int v = 0; v < 4; ++v) {
+        const double *g = &s->grad[e * 12 + v * 3];
+        const double uv = U[s->tet[e * 4 + v]];
+        for (int a = 0; a < 3; ++a) hd[a] -= uv * g[a] / s->p.Ms;
+    }
+}
+
+/* (mu0 / 2) int |H~_d|^2 over the cell, averaged over V_c: the local part of
+ * the magnetostatic energy of Eq. (MicromagneticsEnergy) (the cross term with
+ * the uniform far field vanishes because grad U~ has zero mean). */
+static double ms_energy(const or_sim *s, const double *U) {
+    double acc = 0.0;
+    for (int e = 0; e < s->ne; ++e) {
+        double hd[3];
+        ms_field_elem(s, U, e, hd);
+        acc += s->vol[e] * (hd[0] * hd[0] + hd[1] * hd[1] + hd[2] * hd[2]);
+    }
+    return 0.5 * s->p.mu0 * s->p.Ms * s->p.Ms * acc / s->vc;
+}
+
+int or_ms_rhs_at(or_sim *s, const double *m, double *b) {
+    if (!s->have_params) return OR_E_STATE;
+    ms_rhs_at(s, m, b);
+    return OR_OK;
+}
+
+int or_ms_solve_at(or_sim *s, const double *m, double *U, double tol, int32_t maxit, int32_t *iters) {
+    if (!s->have_params) return OR_E_STATE;
+    double *b = (double *)malloc(sizeof(double) * (size_t)s->n);
+    ms_rhs_at(s, m, b);
+    int it = 0, rc = solve_ms(s, b, U, tol, maxit, &it);
+    *iters = it;
+    free(b);
+    return rc;
+}
+
+int or_ms_field(or_sim *s, const double *U, double *hd) {
+    if (!s->have_params) return OR_E_STATE;
+    for (int e = 0; e < s->ne; ++e) ms_field_elem(s, U, e, &hd[e * 3]);
+    return OR_OK;
+}
+
+int or_ms_energy(or_sim *s, const double *U, double *e) {
+    if (!s->have_params) return OR_E_STATE;
+    *e = ms_energy(s, U);
+    return OR_OK;
+}
+
 /* Right-hand side of Eq. (RHS_b) for the GS equation (Eq. weak_GS) with
  * f = y + c h: b = M y + ch, ch = sum_e M^e (c h^e) over magnetic elements.
  * h^e at vertex j uses m_j and the element's total strain Ebar + sym grad u
- * (constant on a P1 element). */
-static void field_rhs_at(const or_sim *s, const double *m, const double *y, const double *u, const double ebar[6],
-                         const double mbar[3], double c, double *b, double *ch) {
+ * (constant on a P1 element); with a potential U (local magnetostatics on)
+ * it also holds the element's local demagnetising field -grad U / Ms. */
+static void field_rhs_at(const or_sim *s, const double *m, const double *y, const double *u, const double *U,
+                         const double ebar[6], const double mbar[3], double c, double *b, double *ch) {
     memset(ch, 0, sizeof(double) * 3 * (size_t)s->n);
     for (int e = 0; e < s->ne; ++e) {
         if (!s->tag[e]) continue;
@@ -806,11 +932,12 @@ static void field_rhs_at(const or_sim *s, const double *m, const double *y, cons
         for (int a = 0; a < 3; ++a)
             for (int d = 0; d < 3; ++d) E[a][d] = Eb[a][d] + 0.5 * (H[a][d] + H[d][a]);
         sym_to6(E, E6);
-        double f[4][3];
+        double f[4][3], hd[3] = {0.0, 0.0, 0.0};
+        if (U) ms_field_elem(s, U, e, hd);
         for (int v = 0; v < 4; ++v) {
             double h[3];
             or_h_local(&s->p, &m[s->tet[e * 4 + v] * 3], E6, mbar, h);
-            for (int a = 0; a < 3; ++a) f[v][a] = c * h[a];
+            for (int a = 0; a < 3; ++a) f[v][a] = c * (h[a] + hd[a]);
         }
         for (int i = 0; i < 4; ++i) {
             int node = s->tet[e * 4 + i];
@@ -834,7 +961,7 @@ int or_field_rhs(or_sim *s, double c, double *b, double *ch) {
     if (!s->have_params || !s->have_m) return OR_E_STATE;
     double mbar[3], ebar[6];
     averages_at(s, s->m, mbar, ebar);
-    field_rhs_at(s, s->m, s->m, s->u, ebar, mbar, c, b, ch);
+    field_rhs_at(s, s->m, s->m, s->u, s->p.local_demag ? s->ud : NULL, ebar, mbar, c, b, ch);
     return OR_OK;
 }
 
@@ -879,6 +1006,7 @@ int or_step(or_sim *s, double dt, int32_t nsteps, or_stats *st) {
     double *b = (double *)malloc(sz), *ch = (double *)malloc(sz), *g = (double *)malloc(sz);
     double *ms = (double *)malloc(sz), *gs = (double *)malloc(sz), *mss = (double *)malloc(sz);
     double *u = (double *)malloc(sz), *bm = (double *)malloc(sz);
+    double *U = p->local_demag ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
     double dtau = p->gamma0 * p->Ms * dt;
     double lex2 = 2.0 * p->A / (p->mu0 * p->Ms * p->Ms);
     double eps1 = lex2 * dtau, eps3 = p->alpha * eps1;
@@ -896,9 +1024,18 @@ int or_step(or_sim *s, double dt, int32_t nsteps, or_stats *st) {
         rc = solve_elastic(s, bm, u, p->cg_tol, p->cg_maxit, &it);
         if (st) st->mech_iters += it;
         if (rc) break;
+        /* local magnetostatics, Eq. (weak_demag), at m^n, warm start U~^{n-1};
+         * held for h[m*] like the displacement */
+        if (U) {
+            ms_rhs_at(s, m, bm);
+            memcpy(U, s->ud, sizeof(double) * (size_t)n);
+            rc = solve_ms(s, bm, U, p->cg_tol, p->cg_maxit, &it);
+            if (st) st->ms_iters += it;
+            if (rc) break;
+        }
         if (p->precession) {
             /* Step 1: g^n for all three components */
-            field_rhs_at(s, m, m, u, ebar, mbar, dtau, b, ch);
+            field_rhs_at(s, m, m, u, U, ebar, mbar, dtau, b, ch);
             for (int c = 0; c < 3 && !rc; ++c) {
                 rc = gs_component(s, eps1, b, m, ch, c, g, &it);
                 if (st) st->gs_iters[c] += it;
@@ -930,7 +1067,7 @@ int or_step(or_sim *s, double dt, int32_t nsteps, or_stats *st) {
         {
             double mbar2[3], ebar2[6];
             averages_at(s, ms, mbar2, ebar2);
-            field_rhs_at(s, ms, ms, u, ebar2, mbar2, p->alpha * dtau, b, ch);
+            field_rhs_at(s, ms, ms, u, U, ebar2, mbar2, p->alpha * dtau, b, ch);
             for (int c = 0; c < 3 && !rc; ++c) {
                 rc = gs_component(s, eps3, b, ms, ch, c, mss, &it);
                 if (st) st->gs_iters[5 + c] += it;
@@ -956,10 +1093,11 @@ int or_step(or_sim *s, double dt, int32_t nsteps, or_stats *st) {
         if (bad) { rc = OR_E_NONFINITE; seterr(s, "non-finite magnetisation"); break; }
         memcpy(s->m, mss, sz);
         memcpy(s->u, u, sz);
+        if (U) memcpy(s->ud, U, sizeof(double) * (size_t)n);
         if (st) { st->steps_done = step + 1; st->dm_avg = nmag ? dsum / nmag : 0.0; }
     }
     if (rc == OR_E_NOCONV) seterr(s, "CG did not converge");
-    free(b); free(ch); free(g); free(ms); free(gs); free(mss); free(u); free(bm);
+    free(b); free(ch); free(g); free(ms); free(gs); free(mss); free(u); free(bm); free(U);
     return rc;
 }
 
@@ -1018,6 +1156,13 @@ int or_energies(or_sim *s, double out[7]) {
     out[0] = ex / s->vc; out[1] = an / s->vc; out[2] = ze / s->vc; out[3] = me / s->vc;
     out[4] = work; out[5] = dem;
     out[6] = out[0] + out[1] + out[2] + out[3] + out[4] + out[5];
+    if (p->local_demag) out[6] += ms_energy(s, s->ud);
+    return OR_OK;
+}
+
+int or_demag_local_energy(or_sim *s, double *e) {
+    if (!s->have_params) return OR_E_STATE;
+    *e = ms_energy(s, s->ud);
     return OR_OK;
 }
 

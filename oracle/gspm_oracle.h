@@ -29,6 +29,7 @@ typedef struct {
     double cg_tol;         /* relative residual ||r|| <= tol ||b|| */
     int32_t cg_maxit;
     int32_t precession;    /* 1: full Algorithm B.1; 0: damping stage only (m* = m^n) */
+    int32_t local_demag;   /* 1: solve the local magnetostatic potential U~ each step (periodic meshes only) */
 } or_params;
 
 typedef struct {
@@ -36,6 +37,7 @@ typedef struct {
     int32_t mech_iters;    /* elastic CG iterations summed over the steps */
     int32_t gs_iters[8];   /* per scalar GS solve, summed: g1 g2 g3, g*1 g*2, m**1 m**2 m**3 */
     double dm_avg;         /* mean |m^{n+1} - m^n| over magnetic nodes, last step */
+    int32_t ms_iters;      /* magnetostatic CG iterations summed over the steps */
 } or_stats;
 
 typedef struct or_sim or_sim;
@@ -60,25 +62,31 @@ int or_set_m(or_sim *s, const double *m);                 /* n0 x 3 */
 int or_set_u(or_sim *s, const double *u);                 /* n0 x 3 */
 void or_get_m(const or_sim *s, double *m);
 void or_get_u(const or_sim *s, double *u);
+int or_set_ud(or_sim *s, const double *ud);               /* n0 values: the potential U~ [A] */
+void or_get_ud(const or_sim *s, double *ud);
 
 /* Operators in unique-node order, x and y are n x 3.
  * which: 0 Laplacian K over magnetic elements (per component)
  *        1 mass M over magnetic elements (per component)
  *        2 eps K + M (per component)
  *        3 elastic K^mech over all elements, pinned node rows zeroed
- *        4 Laplacian over all elements (per component) */
+ *        4 Laplacian over all elements (per component)
+ *        5 K^ms: Laplacian over all elements, pinned node rows zeroed (per component) */
 int or_apply(const or_sim *s, int32_t which, double eps, const double *x, double *y);
 
-/* CG on operator `which` (2 or 3 above), unique-node order; x holds x0 on
- * entry.  Components of the GS operator are solved independently. */
+/* CG on operator `which` (2, 3 or 5 above), unique-node order; x holds x0 on
+ * entry.  Components of the GS and K^ms operators are solved independently. */
 int or_solve(const or_sim *s, int32_t which, double eps, const double *b, double *x, double tol,
              int32_t maxit, int32_t *iters);
 
 int or_step(or_sim *s, double dt, int32_t n, or_stats *st);
 
 /* Energy densities averaged over the computational cell [J/m^3]:
- * out = {exchange, anisotropy, zeeman, magnetoelastic, stress work, far-field demag, total}. */
+ * out = {exchange, anisotropy, zeeman, magnetoelastic, stress work, far-field demag, total}.
+ * With local_demag the total includes the local magnetostatic energy of the stored U~. */
 int or_energies(or_sim *s, double out[7]);
+/* (mu0 / 2 V_c) int |grad U~|^2 of the stored potential [J/m^3]. */
+int or_demag_local_energy(or_sim *s, double *e);
 /* mbar[3]; ebar[6] = mean strain, order xx yy zz yz xz xy. */
 int or_averages(or_sim *s, double mbar[3], double ebar[6]);
 
@@ -89,6 +97,14 @@ void or_demag_factors(double a, double b, double c, double N[3]);
 void or_h_local(const or_params *p, const double m[3], const double E[6], const double mbar[3],
                 double h[3]);
 double or_energy_density_local(const or_params *p, const double m[3], const double E[6]);
+/* Local magnetostatics (Eq. weak_demag) on explicit arrays in unique-node
+ * order, state untouched (need set_params for Ms): the right-hand side b (n)
+ * for a field m (n x 3, any values); the CG solve for U~ (n, x0 on entry);
+ * the element fields h~_d = -grad U~ / Ms (ne x 3); the energy density. */
+int or_ms_rhs_at(or_sim *s, const double *m, double *b);
+int or_ms_solve_at(or_sim *s, const double *m, double *U, double tol, int32_t maxit, int32_t *iters);
+int or_ms_field(or_sim *s, const double *U, double *hd);
+int or_ms_energy(or_sim *s, const double *U, double *e);
 
 const char *or_last_error(const or_sim *s);
 int32_t or_num_threads(void);   /* OpenMP threads the oracle's loops use */
