@@ -15,7 +15,9 @@
  * single-reduction form, one fused kernel launch per iteration); the three
  * stages of (1 - eps lap) g = f (Eq. GS, weak form Eq. weak_GS) are solved by
  * unpreconditioned CG; the cross-product update and the unit-length
- * projection close the step.
+ * projection close the step.  Optionally (gspm_params.local_demag) each step
+ * also solves the local magnetostatic potential U~ of Eq. (demag) in the weak
+ * form (weak_demag) by CG and adds its field -grad U~ to the effective field.
  *
  * Conventions shared by every entry point
  *   - Units are SI (metres, A/m, Pa, J/m^3, seconds).
@@ -61,14 +63,20 @@ typedef enum {
 
 typedef enum { GSPM_FP64 = 0, GSPM_MIXED = 1 } gspm_precision;
 
-typedef enum { GSPM_FIELD_M = 0, GSPM_FIELD_U = 1 } gspm_field;
+typedef enum {
+    GSPM_FIELD_M = 0,       /* magnetisation direction m, n_nodes x 3 */
+    GSPM_FIELD_U = 1,       /* displacement u~ [m], n_nodes x 3 */
+    GSPM_FIELD_UD = 2       /* local magnetostatic potential U~ of Eq. (demag) [A], ONE value per node */
+} gspm_field;
 
 /* Operators of Eq. (LHS) and Eq. (RHS_F), Sec. 2.3, for gspm_apply/gspm_solve. */
 typedef enum {
     GSPM_OP_LAPLACE = 0,    /* K_ij = int grad phi_i . grad phi_j over magnetic elements, per component */
     GSPM_OP_MASS = 1,       /* M_ij = int phi_i phi_j over magnetic elements (F^GS), per component */
     GSPM_OP_GS = 2,         /* eps K + M: the GSPM operator of Eq. (weak_GS), per component */
-    GSPM_OP_ELASTIC = 3     /* K^mech over all elements; rows of the pinned node are zero */
+    GSPM_OP_ELASTIC = 3,    /* K^mech over all elements; rows of the pinned node are zero */
+    GSPM_OP_MS = 4          /* K^ms: int grad phi_i . grad phi_j over all elements (Eq. weak_demag), rows of
+                               the pinned node zero, per component */
 } gspm_op;
 
 #define GSPM_PERIODIC 1u
@@ -101,6 +109,10 @@ typedef struct {
     double cg_tol;          /* CG stops at ||r||_2 <= cg_tol ||b||_2 (Sec. 3.1 criterion) */
     int32_t cg_maxit;       /* CG iteration cap per scalar or vector solve; exceeding it is GSPM_E_NOCONV */
     int32_t precession;     /* 1: full Algorithm B.1; 0: damping stage only (m* = m^n) */
+    int32_t local_demag;    /* 1: each step solves K^ms U~ = Ms F^ms m (Eqs. weak_demag, RHS_F, RHS_b) at m^n,
+                               pinned at the caller's node 0 and warm-started from the previous U~, and adds
+                               the element field -grad U~ / Ms to h on magnetic elements (held for h[m*]);
+                               the energy total gains (mu0/2) <|grad U~|^2>.  0: far field only. */
 } gspm_params;
 
 typedef struct {
@@ -120,6 +132,7 @@ typedef struct {
     int64_t minres_starts; /* steps whose elastic start was a minimum-residual step (learned or extrapolated) */
     double warm_coef[2];    /* last minimum-residual start: coefficients of the network increment and of the
                                previous displacement increment (0 if unused) */
+    int64_t ms_iters;       /* local_demag: magnetostatic CG iterations (GSPM_MIXED: inner FP32), summed */
 } gspm_step_stats;
 
 /* Create a context on opts->device (NULL opts: device 0, FP64, own stream).
@@ -143,10 +156,12 @@ gspm_status gspm_upload_mesh(gspm_ctx *ctx, int64_t n_nodes, const double *xyz, 
  * example to change hext along a hysteresis sweep). */
 gspm_status gspm_set_params(gspm_ctx *ctx, const gspm_params *params);
 
-/* Set or read a nodal field (n_nodes x 3, caller's order).  Setting M
- * normalises m on magnetic nodes and zeroes it on nodes that lie in
- * inclusions only; a zero or non-finite vector on a magnetic node is
- * GSPM_E_ARG.  U is the periodic displacement [m]. */
+/* Set or read a nodal field (n_nodes x 3, caller's order; GSPM_FIELD_UD:
+ * n_nodes values).  Setting M normalises m on magnetic nodes and zeroes it on
+ * nodes that lie in inclusions only; a zero or non-finite vector on a
+ * magnetic node is GSPM_E_ARG.  U is the periodic displacement [m]; UD the
+ * local magnetostatic potential [A] (the warm start of the next solve and
+ * the potential the energies use). */
 gspm_status gspm_set_field(gspm_ctx *ctx, gspm_field which, const double *values, int64_t n_nodes);
 gspm_status gspm_get_field(gspm_ctx *ctx, gspm_field which, double *out, int64_t n_nodes);
 
@@ -183,8 +198,16 @@ gspm_status gspm_sweep(gspm_ctx *ctx, double dt, double dm_tol, int32_t max_step
 
 /* Energy densities of Eq. (MicromagneticsEnergy) averaged over the cell
  * [J/m^3] at the current state: out = {exchange, anisotropy, zeeman,
- * magnetoelastic, stress work, far-field demagnetisation, total}. */
+ * magnetoelastic, stress work, far-field demagnetisation, total}.  With
+ * local_demag the total also holds the local magnetostatic energy of the
+ * stored U~ (gspm_demag_local_energy). */
 gspm_status gspm_energies(gspm_ctx *ctx, double out[7]);
+
+/* The local magnetostatic energy density (mu0 / 2 V_c) int |grad U~|^2 over
+ * the cell [J/m^3] of the stored potential U~ (Sec. 2.1; the cross term with
+ * the uniform far field vanishes since grad U~ has zero mean).  Needs
+ * set_params. */
+gspm_status gspm_demag_local_energy(gspm_ctx *ctx, double *e);
 
 /* Volume averages over the cell (Sec. 2.4): mbar[3] and the homogeneous
  * strain ebar[6] (order xx yy zz yz xz xy). */
@@ -196,9 +219,10 @@ gspm_status gspm_averages(gspm_ctx *ctx, double mbar[3], double ebar[6]);
 gspm_status gspm_apply(gspm_ctx *ctx, gspm_op op, double eps, const double *x, double *y, int64_t n_nodes);
 
 /* Solve A x = b by the library's CG (GSPM_OP_GS per component on the magnetic
- * nodes, or GSPM_OP_ELASTIC with the pinned node).  x holds the initial guess
- * on entry and the solution on return; iters (nullable) receives the
- * iteration count (summed over components for GSPM_OP_GS). */
+ * nodes, GSPM_OP_ELASTIC with the pinned node, or GSPM_OP_MS per component
+ * with the pinned node).  x holds the initial guess on entry and the solution
+ * on return; iters (nullable) receives the iteration count (summed over
+ * components for GSPM_OP_GS and GSPM_OP_MS). */
 gspm_status gspm_solve(gspm_ctx *ctx, gspm_op op, double eps, const double *b, double *x, int64_t n_nodes,
                        double tol, int32_t maxit, int32_t *iters);
 

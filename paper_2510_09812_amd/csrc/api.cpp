@@ -156,6 +156,7 @@ void gspm_ctx::release_mesh() {
     dev_free(this, b.cgi_rr); dev_free(this, b.cgi_pq); dev_free(this, b.cgi_bb); dev_free(this, b.cgi_rq); dev_free(this, b.cgi_qq);
     dev_free(this, b.cgi_flags);
     dev_free(this, b.mprev); dev_free(this, b.uprev); dev_free(this, b.du_prev); dev_free(this, b.kdu); dev_free(this, b.wred); dev_free(this, b.wcoef);
+    dev_free(this, b.ud); dev_free(this, b.udnext);
     if (arena) hipFree(arena);
     arena = nullptr;
     arena_size = arena_used = 0;
@@ -297,11 +298,13 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
         for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.r2, &d.q2,
                             &d.mprev, &d.uprev, &d.du_prev, &d.kdu})
             rc = rc ? rc : dev_alloc(c, p, n3);
+        rc = rc ? rc : dev_alloc(c, &d.ud, n);
+        rc = rc ? rc : dev_alloc(c, &d.udnext, n);
         rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kMrSums) * kShards);
         rc = rc ? rc : dev_alloc(c, &d.wcoef, 2);
         rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
         rc = rc ? rc : dev_alloc(c, &d.sums, 9 * kShards);
-        rc = rc ? rc : dev_alloc(c, &d.esums, 4 * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.esums, 5 * kShards);
         rc = rc ? rc : dev_alloc(c, &d.dm, kShards);
         rc = rc ? rc : dev_alloc(c, &d.der, 2);
         rc = rc ? rc : dev_alloc(c, &d.bad, 1);
@@ -360,6 +363,8 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
                       d.kdu})
         launch_fill(p, n3, 0.0, s);
     launch_fill(d.wcoef, 2, 0.0, s);
+    launch_fill(d.ud, n, 0.0, s);
+    launch_fill(d.udnext, n, 0.0, s);
     if (c->precision == GSPM_MIXED)
         for (float *p : {d.r32, d.p32, d.p32b, d.q32, d.x32}) launch_fill_f32(p, n3, s);
     launch_fill(d.ch2, 2 * n, 0.0, s);
@@ -449,6 +454,7 @@ gspm_status gspm_set_params(gspm_ctx *c, const gspm_params *p) {
         return fail(c, GSPM_E_ARG, "set_params: Ms, mu0, gamma0, cg_tol, cg_maxit must be positive; A, alpha >= 0");
     if (!(p->c44 > 0 && p->c11 - p->c12 > 0 && p->c11 + 2 * p->c12 > 0))
         return fail(c, GSPM_E_ARG, "set_params: elastic constants are not positive definite");
+    if (p->local_demag != 0 && p->local_demag != 1) return fail(c, GSPM_E_ARG, "set_params: local_demag must be 0 or 1");
     c->p = *p;
     auto &m = c->mat;
     m.c11 = p->c11; m.c12 = p->c12; m.c44 = p->c44;
@@ -468,9 +474,19 @@ gspm_status gspm_set_field(gspm_ctx *c, gspm_field which, const double *v, int64
     if (!v) return fail(c, GSPM_E_ARG, "set_field: null array");
     if (!c->have_mesh) return fail(c, GSPM_E_STATE, "set_field before upload_mesh");
     if (n_nodes != c->n0) return fail(c, GSPM_E_ARG, "set_field: node count differs from the mesh");
-    if (which != GSPM_FIELD_M && which != GSPM_FIELD_U) return fail(c, GSPM_E_ARG, "set_field: unknown field");
+    if (which != GSPM_FIELD_M && which != GSPM_FIELD_U && which != GSPM_FIELD_UD)
+        return fail(c, GSPM_E_ARG, "set_field: unknown field");
     hipSetDevice(c->device);
     std::vector<double> h;
+    if (which == GSPM_FIELD_UD) {
+        // one value per node: spread into the first column of the n0 x 3 layout
+        std::vector<double> v3(3 * static_cast<size_t>(c->n0), 0.0);
+        for (int64_t i = 0; i < c->n0; ++i) v3[3 * i] = v[i];
+        int rc = gather_user(c, v3.data(), h);
+        if (rc) return static_cast<gspm_status>(rc);
+        h.resize(static_cast<size_t>(c->n));
+        return static_cast<gspm_status>(upload(c, c->d.ud, h));
+    }
     int rc = gather_user(c, v, h);
     if (rc) return static_cast<gspm_status>(rc);
     const int n = c->n;
@@ -503,8 +519,16 @@ gspm_status gspm_get_field(gspm_ctx *c, gspm_field which, double *out, int64_t n
     if (!out) return fail(c, GSPM_E_ARG, "get_field: null array");
     if (!c->have_mesh) return fail(c, GSPM_E_STATE, "get_field before upload_mesh");
     if (n_nodes != c->n0) return fail(c, GSPM_E_ARG, "get_field: node count differs from the mesh");
-    if (which != GSPM_FIELD_M && which != GSPM_FIELD_U) return fail(c, GSPM_E_ARG, "get_field: unknown field");
+    if (which != GSPM_FIELD_M && which != GSPM_FIELD_U && which != GSPM_FIELD_UD)
+        return fail(c, GSPM_E_ARG, "get_field: unknown field");
     hipSetDevice(c->device);
+    if (which == GSPM_FIELD_UD) {
+        std::vector<double> h(static_cast<size_t>(c->n));
+        int rc = download(c, c->d.ud, h);
+        if (rc) return static_cast<gspm_status>(rc);
+        for (int64_t i = 0; i < c->n0; ++i) out[i] = h[static_cast<size_t>(c->user2int[i])];
+        return GSPM_OK;
+    }
     std::vector<double> h(3 * static_cast<size_t>(c->n));
     int rc = download(c, which == GSPM_FIELD_M ? c->d.m : c->d.u, h);
     if (rc) return static_cast<gspm_status>(rc);
@@ -532,10 +556,10 @@ gspm_status gspm_energies(gspm_ctx *c, double out[7]) {
     hipStream_t s = c->stream;
     launch_avg_sums(c->n, d.w, d.m, c->mat.l100, c->mat.l111, d.sums, s);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
-    launch_fill(d.esums, 4 * kShards, 0.0, s);
-    launch_energy_elem(c->mv, c->mat, d.m, d.u, &d.der[0], d.esums, s);
+    launch_fill(d.esums, 5 * kShards, 0.0, s);
+    launch_energy_elem(c->mv, c->mat, d.m, d.u, c->p.local_demag ? d.ud : nullptr, &d.der[0], d.esums, s);
     launch_energy_nodes(c->n, d.w, d.m, c->mat, c->p.hext, d.esums + 2 * kShards, s);
-    double es[4 * kShards];
+    double es[5 * kShards];
     Derived der;
     hipMemcpyAsync(es, d.esums, sizeof es, hipMemcpyDeviceToHost, s);
     hipMemcpyAsync(&der, &d.der[0], sizeof der, hipMemcpyDeviceToHost, s);
@@ -556,6 +580,34 @@ gspm_status gspm_energies(gspm_ctx *c, double out[7]) {
         for (int b = 0; b < 3; ++b) dem += der.mbar[a] * p.Nd[a * 3 + b] * der.mbar[b];
     out[5] = 0.5 * p.mu0 * p.Ms * p.Ms * dem;
     out[6] = out[0] + out[1] + out[2] + out[3] + out[4] + out[5];
+    if (p.local_demag) {
+        double dl = 0.0;
+        for (int q = 0; q < kShards; ++q) dl += es[4 * kShards + q];
+        out[6] += 0.5 * p.mu0 * dl / c->vc;
+    }
+    return GSPM_OK;
+}
+
+gspm_status gspm_demag_local_energy(gspm_ctx *c, double *e) {
+    if (!c) return GSPM_E_ARG;
+    if (!e) return fail(c, GSPM_E_ARG, "demag_local_energy: null output");
+    if (!c->have_mesh || !c->have_params || !c->have_m)
+        return fail(c, GSPM_E_STATE, "demag_local_energy needs mesh, params and m");
+    hipSetDevice(c->device);
+    auto &d = c->d;
+    hipStream_t s = c->stream;
+    // the element pass also needs m, u and the averages; only its potential sum is used here
+    launch_avg_sums(c->n, d.w, d.m, c->mat.l100, c->mat.l111, d.sums, s);
+    launch_derive(d.sums, c->dargs, &d.der[0], s);
+    launch_fill(d.esums, 5 * kShards, 0.0, s);
+    launch_energy_elem(c->mv, c->mat, d.m, d.u, d.ud, &d.der[0], d.esums, s);
+    double es[kShards];
+    hipMemcpyAsync(es, d.esums + 4 * kShards, sizeof es, hipMemcpyDeviceToHost, s);
+    int rc = hip_check(c, hipStreamSynchronize(s), "demag_local_energy");
+    if (rc) return static_cast<gspm_status>(rc);
+    double dl = 0.0;
+    for (int q = 0; q < kShards; ++q) dl += es[q];
+    *e = 0.5 * c->p.mu0 * dl / c->vc;
     return GSPM_OK;
 }
 
@@ -580,7 +632,7 @@ gspm_status gspm_apply(gspm_ctx *c, gspm_op op, double eps, const double *x, dou
     if (!x || !y) return fail(c, GSPM_E_ARG, "apply: null array");
     if (!c->have_mesh) return fail(c, GSPM_E_STATE, "apply before upload_mesh");
     if (n_nodes != c->n0) return fail(c, GSPM_E_ARG, "apply: node count differs from the mesh");
-    if (op < GSPM_OP_LAPLACE || op > GSPM_OP_ELASTIC) return fail(c, GSPM_E_ARG, "apply: unknown operator");
+    if (op < GSPM_OP_LAPLACE || op > GSPM_OP_MS) return fail(c, GSPM_E_ARG, "apply: unknown operator");
     if (op == GSPM_OP_ELASTIC && !c->have_params) return fail(c, GSPM_E_STATE, "apply(ELASTIC) needs set_params");
     if (!std::isfinite(eps)) return fail(c, GSPM_E_ARG, "apply: non-finite eps");
     hipSetDevice(c->device);
@@ -592,6 +644,9 @@ gspm_status gspm_apply(gspm_ctx *c, gspm_op op, double eps, const double *x, dou
     if (op == GSPM_OP_ELASTIC) {
         launch_elastic_matvec<double>(c->mv, c->mat, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0,
                                       0.0, c->stream);
+    } else if (op == GSPM_OP_MS) {
+        launch_ms_matvec<double>(c->mv, 3, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0, 0.0,
+                                 c->stream);
     } else {
         const double e = op == GSPM_OP_LAPLACE ? 1.0 : (op == GSPM_OP_MASS ? 0.0 : eps);
         const double mass = op == GSPM_OP_LAPLACE ? 0.0 : 1.0;
@@ -610,7 +665,8 @@ gspm_status gspm_solve(gspm_ctx *c, gspm_op op, double eps, const double *b, dou
     if (!b || !x) return fail(c, GSPM_E_ARG, "solve: null array");
     if (!c->have_mesh) return fail(c, GSPM_E_STATE, "solve before upload_mesh");
     if (n_nodes != c->n0) return fail(c, GSPM_E_ARG, "solve: node count differs from the mesh");
-    if (op != GSPM_OP_GS && op != GSPM_OP_ELASTIC) return fail(c, GSPM_E_ARG, "solve: operator must be GS or ELASTIC");
+    if (op != GSPM_OP_GS && op != GSPM_OP_ELASTIC && op != GSPM_OP_MS)
+        return fail(c, GSPM_E_ARG, "solve: operator must be GS, ELASTIC or MS");
     if (op == GSPM_OP_ELASTIC && !c->have_params) return fail(c, GSPM_E_STATE, "solve(ELASTIC) needs set_params");
     if (!(tol > 0) || maxit <= 0 || !std::isfinite(eps)) return fail(c, GSPM_E_ARG, "solve: tol and maxit must be positive");
     hipSetDevice(c->device);
@@ -619,10 +675,10 @@ gspm_status gspm_solve(gspm_ctx *c, gspm_op op, double eps, const double *b, dou
     if (!rc) rc = gather_user(c, x, hx);
     if (rc) return static_cast<gspm_status>(rc);
     const int n = c->n;
-    const bool el = op == GSPM_OP_ELASTIC;
+    const bool el = op == GSPM_OP_ELASTIC, msop = op == GSPM_OP_MS;
     const int ns = el ? 1 : 3;
     for (int k = 0; k < n; ++k) {
-        const bool fixed = el ? (k == c->p0) : !(c->w_host[k] > 0.0);
+        const bool fixed = (el || msop) ? (k == c->p0) : !(c->w_host[k] > 0.0);
         if (!fixed) continue;
         for (int a = 0; a < 3; ++a) hb[static_cast<size_t>(a) * n + k] = hx[static_cast<size_t>(a) * n + k] = 0.0;
     }
@@ -635,7 +691,8 @@ gspm_status gspm_solve(gspm_ctx *c, gspm_op op, double eps, const double *b, dou
     if (!rc) rc = upload(c, c->d.mnext, hx);
     if (rc) return static_cast<gspm_status>(rc);
     CgResult r = el ? cg_elastic(c, c->d.mnext, c->d.b, tol, maxit, SK_OTHER)
-                    : cg_gs(c, 3, eps, c->d.mnext, c->d.b, tol, maxit, SK_OTHER);
+                 : msop ? cg_ms(c, 3, c->d.mnext, c->d.b, tol, maxit, SK_OTHER)
+                        : cg_gs(c, 3, eps, c->d.mnext, c->d.b, tol, maxit, SK_OTHER);
     if (iters) *iters = r.iters[0] + r.iters[1] + r.iters[2];
     rc = download(c, c->d.mnext, hx);
     if (rc) return static_cast<gspm_status>(rc);
@@ -647,7 +704,7 @@ gspm_status gspm_time_operator(gspm_ctx *c, gspm_op op, double eps, int32_t reps
     if (!c) return GSPM_E_ARG;
     if (!avg_ms || reps <= 0 || !std::isfinite(eps)) return fail(c, GSPM_E_ARG, "time_operator: bad arguments");
     if (!c->have_mesh) return fail(c, GSPM_E_STATE, "time_operator before upload_mesh");
-    if (op < GSPM_OP_LAPLACE || op > GSPM_OP_ELASTIC) return fail(c, GSPM_E_ARG, "time_operator: unknown operator");
+    if (op < GSPM_OP_LAPLACE || op > GSPM_OP_MS) return fail(c, GSPM_E_ARG, "time_operator: unknown operator");
     if (op == GSPM_OP_ELASTIC && !c->have_params) return fail(c, GSPM_E_STATE, "time_operator(ELASTIC) needs set_params");
     hipSetDevice(c->device);
     const double e = op == GSPM_OP_LAPLACE ? 1.0 : (op == GSPM_OP_MASS ? 0.0 : eps);
@@ -662,6 +719,14 @@ gspm_status gspm_time_operator(gspm_ctx *c, gspm_op op, double eps, int32_t reps
             else
                 launch_elastic_matvec<double>(c->mv, c->mat, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr,
                                               c->cg, 0, 0.0, c->stream);
+        } else if (op == GSPM_OP_MS) {
+            // one component, as the step's solve
+            if (f32)
+                launch_ms_matvec<float>(c->mv, 1, MV_APPLY, c->d.r32, c->d.q32, nullptr, nullptr, nullptr, c->cg, 0,
+                                        0.0, c->stream);
+            else
+                launch_ms_matvec<double>(c->mv, 1, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0,
+                                         0.0, c->stream);
         } else {
             if (f32)
                 launch_gs_matvec<float>(c->mv, 3, e, mass, MV_APPLY, c->d.r32, c->d.q32, nullptr, nullptr, nullptr,

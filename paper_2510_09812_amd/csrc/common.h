@@ -153,9 +153,16 @@ void launch_derive(const double *sums, const DeriveArgs &a, Derived *out, hipStr
 // Element passes (one workgroup per owner block).
 void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x,
                         double *bb, hipStream_t s);
+// ud (nullable): the local magnetostatic potential; its element field
+// -grad ud * inv_ms joins h on every vertex of a magnetic element.
 void launch_field_rhs(const MeshView &mv, const Material &mat, const double *m, const double *u,
                       const Derived *d, double c, double *b, double *x0, double *ch2, double *bb, int bbstride,
-                      hipStream_t s);
+                      const double *ud, double inv_ms, hipStream_t s);
+// Right-hand side of Eq. (weak_demag): b_i = Ms sum_e V_e grad(lambda_i) . <m>_e
+// over all elements (zero at the pinned node, whose potential x is zeroed);
+// bb[0] += b.b.
+void launch_ms_rhs(const MeshView &mv, double Ms, const double *m, double *b, double *x, double *bb,
+                   hipStream_t s);
 void launch_mass_rhs(const MeshView &mv, const double *y, const double *ch2, double *b, double *x0,
                      double *bb, int bbstride, hipStream_t s);
 // Matrix-free operators.  APPLY: out = A in.  RESID: r = b - A x (x = in),
@@ -183,8 +190,15 @@ void launch_elastic_cg(const MeshView &mv, const Material &mat, int k, bool last
 template <class T>
 void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
                       const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);
+// K^ms (Laplacian over all elements) on nc = 1 or 3 components, rows of the
+// pinned node zero; modes as above.  FP32: A' = K^ms / len_scale^3.
+template <class T>
+void launch_ms_matvec(const MeshView &mv, int nc, MatvecMode mode, const T *in, T *out, const T *b, const T *r,
+                      T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);
+// out2[0 .. kShards), out2[kShards .. 2 kShards): exchange and magnetoelastic
+// sums; with ud, out2[4 kShards .. 5 kShards): sum_e V_e |grad ud|^2.
 void launch_energy_elem(const MeshView &mv, const Material &mat, const double *m, const double *u,
-                        const Derived *d, double *out2, hipStream_t s);
+                        const double *ud, const Derived *d, double *out2, hipStream_t s);
 void launch_energy_nodes(int n, const double *w, const double *m, const Material &mat, const double hext[3],
                          double *out2, hipStream_t s);
 

@@ -11,7 +11,7 @@ namespace gspm {
 
 // Which solve a CG call belongs to, for the iteration-count predictor that
 // sizes the first batch of iterations launched before polling.
-enum SolveKind { SK_MECH = 0, SK_GS1 = 1, SK_GS2 = 2, SK_GS3 = 3, SK_OTHER = 4, SK_COUNT = 5 };
+enum SolveKind { SK_MECH = 0, SK_GS1 = 1, SK_GS2 = 2, SK_GS3 = 3, SK_OTHER = 4, SK_MS = 5, SK_COUNT = 6 };
 
 struct DeviceBuffers {
     double *x = nullptr;          // 3n coordinates
@@ -47,6 +47,7 @@ struct DeviceBuffers {
     double *kdu = nullptr;        // 3n: K (u^{n-1} - u^{n-2}) (warm start scratch)
     double *wred = nullptr;       // kMrSums x kShards: minimum-residual sums
     double *wcoef = nullptr;      // 2: coefficients of the last minimum-residual start
+    double *ud = nullptr, *udnext = nullptr;   // n: local magnetostatic potential (committed, in progress)
 };
 
 // Device state of the learned warm start (allocated on first use).
@@ -104,7 +105,7 @@ struct gspm_ctx {
     gspm_params p{};
     gspm::Material mat{};
     gspm::DeriveArgs dargs{};
-    int predict[gspm::SK_COUNT] = {32, 8, 8, 8, 16};
+    int predict[gspm::SK_COUNT] = {32, 8, 8, 8, 16, 32};
 
     // learned warm start
     gspm::MpnnState nn;
@@ -129,6 +130,8 @@ struct CgResult {
 void cg_prepare(gspm_ctx *c, int ns);
 CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int maxit, SolveKind kind);
 CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit, SolveKind kind);
+// K^ms x = b (Eq. weak_demag) on nc components, pinned node p0.
+CgResult cg_ms(gspm_ctx *c, int nc, double *x, const double *b, double tol, int maxit, SolveKind kind);
 int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st);
 int hip_check(gspm_ctx *c, hipError_t e, const char *what);
 // Warm start of the elastic solve on the right-hand side b: x (holding u^{n-1})

@@ -22,6 +22,7 @@ void add_stats(gspm_step_stats &acc, const gspm_step_stats &s) {
     acc.refinements += s.refinements;
     acc.learned_starts += s.learned_starts;
     acc.minres_starts += s.minres_starts;
+    acc.ms_iters += s.ms_iters;
     acc.dm_avg = s.dm_avg;
     acc.warm_coef[0] = s.warm_coef[0];
     acc.warm_coef[1] = s.warm_coef[1];

@@ -783,9 +783,11 @@ struct ElasticRhsOp {
 // (eps K + mass M) on NC scalar components stored [c][n], magnetic elements
 // only (Eq. weak_GS), with one CG scalar set per component; a converged
 // component is skipped.
-template <class T, int NC>
+template <class T, int NC, bool kMs = false>
 struct GsMatvecOp {
-    static constexpr bool kMagneticOnly = true;
+    // kMs: K^ms of Eq. (weak_demag) instead, the Laplacian over all elements
+    // (eps = 1, no mass) with the pinned node's rows zero
+    static constexpr bool kMagneticOnly = !kMs;
     const T *in;
     T *out;
     const T *b;
@@ -840,13 +842,18 @@ struct GsMatvecOp {
             T gp[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) gp[a] = d1 * R.c[1][a] + d2 * R.c[2][a] + d3 * R.c[3][a];
-            const T sum = v[0] + v[1] + v[2] + v[3];
             T t[4];
 #pragma unroll
             for (int j = 1; j < 4; ++j) t[j] = R.c[j][0] * gp[0] + R.c[j][1] * gp[1] + R.c[j][2] * gp[2];
             t[0] = -(t[1] + t[2] + t[3]);
+            if constexpr (kMs) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) y[j][q] = ev * t[j] + mv20 * (v[j] + sum);
+                for (int j = 0; j < 4; ++j) y[j][q] = ev * t[j];
+            } else {
+                const T sum = v[0] + v[1] + v[2] + v[3];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) y[j][q] = ev * t[j] + mv20 * (v[j] + sum);
+            }
         }
     }
 
@@ -861,7 +868,7 @@ struct GsMatvecOp {
             for (int q = 0; q < NC; ++q) {
                 if (!live[q]) continue;
                 const size_t o = static_cast<size_t>(q) * n + node;
-                const T av = st.acc[q * mv.nb + i];
+                const T av = (kMs && node == mv.p0) ? T(0) : static_cast<T>(st.acc[q * mv.nb + i]);
                 if (mode == MV_RESID) {
                     const T rv = b[o] - av;
                     const_cast<T *>(r)[o] = rv;
@@ -878,6 +885,59 @@ struct GsMatvecOp {
         }
         if (mode == MV_ITER) block_atomic_add<NC>(part, cg.pq_at(0, k), cg.comp_stride());
         else if (mode == MV_RESID) block_atomic_add<NC>(part, cg.rr_at(0, 0), cg.comp_stride());
+    }
+};
+
+// ------------------------------------------------- magnetostatic RHS
+
+// Right-hand side of Eq. (weak_demag), b = Ms F^ms m (Eqs. RHS_F, RHS_b), in
+// the element form b_i = Ms V_e grad(lambda_i) . <m>_e summed over all
+// elements (<m>_e the vertex mean).  This equals -Ms int phi_i div(m_h) on a
+// periodic mesh: int d_a(phi_i phi_j) over the cell vanishes.  Zero at the
+// pinned node, whose potential x is also zeroed; bb += b.b.
+template <class T>
+struct MsRhsOp {
+    static constexpr bool kMagneticOnly = false;
+    const T *m;
+    T *b, *x;
+    double *bb;
+    int n;
+    T Ms;
+    double coord_scale = 1.0;
+
+    __device__ bool prepare() { return true; }
+
+    template <int NF>
+    __device__ __forceinline__ void stage(const Staged<T, 1, NF> &st, int l, int g) const {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) st.fld(a, l) = m[static_cast<size_t>(a) * n + g];
+    }
+
+    template <int NF>
+    __device__ __forceinline__ void element(const Staged<T, 1, NF> &st, const ushort4 cn, const Geo<T> &G, bool,
+                                            T (&y)[4][1]) const {
+        T mv[4][3];
+        vertex3(st, 0, cn, mv);
+        const T q = Ms * G.vol * T(0.25);
+        T mm[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) mm[a] = q * (mv[0][a] + mv[1][a] + mv[2][a] + mv[3][a]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) y[j][0] = G.g[j][0] * mm[0] + G.g[j][1] * mm[1] + G.g[j][2] * mm[2];
+    }
+
+    template <int NF>
+    __device__ void finish(const MeshView &mv, const Staged<T, 1, NF> &st, int n0, int cnt) const {
+        double part = 0.0;
+        for (int i = threadIdx.x; i < cnt; i += kThreads) {
+            const int node = n0 + i;
+            const bool pinned = node == mv.p0;
+            const T v = pinned ? T(0) : static_cast<T>(st.acc[i]);
+            b[node] = v;
+            if (pinned) x[node] = T(0);
+            part += static_cast<double>(v) * v;
+        }
+        block_atomic_add1(part, bb);
     }
 };
 
@@ -903,11 +963,13 @@ __device__ __forceinline__ void local_field(const Cubic<T> &C, T l100, T l111, T
 // b = M m + ch with ch = sum_e M^e (c h^e), per Eq. (RHS_b) with f = m + c h.
 // Writes b, the initial guess x0 = m + ch / w (zero off the magnetic nodes),
 // optionally ch's first two components, and bb[c] += b_c . b_c.
-template <class T>
+template <class T, bool kUd = false>
 struct FieldRhsOp {
     static constexpr bool kMagneticOnly = true;
     const T *m, *u;
     const Derived *d;
+    const T *ud;                  // kUd: the local magnetostatic potential
+    T inv_ms;
     T *b, *x0, *ch2;
     double *bb;
     int n, bbstride;
@@ -932,6 +994,7 @@ struct FieldRhsOp {
             st.fld(a, l) = m[static_cast<size_t>(a) * n + g];
             st.fld(3 + a, l) = u[static_cast<size_t>(a) * n + g];
         }
+        if constexpr (kUd) st.fld(6, l) = ud[g];
     }
 
     template <int NF>
@@ -943,12 +1006,23 @@ struct FieldRhsOp {
         sym_grad(uv, G, E);
 #pragma unroll
         for (int t = 0; t < 6; ++t) E[t] += E0bar[t];
+        T hce[3] = {hc[0], hc[1], hc[2]};
+        if constexpr (kUd) {
+            // the element's local demagnetising field -grad(U~) / Ms (Sec. 2.1)
+            const int id[4] = {cn.x, cn.y, cn.z, cn.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T uj = st.fld(6, id[j]) * inv_ms;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) hce[a] -= uj * G.g[j][a];
+            }
+        }
         T f[4][3], sf[3] = {0, 0, 0}, sm[3] = {0, 0, 0};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const T mj[3] = {mv[j][0], mv[j][1], mv[j][2]};
             T h[3];
-            local_field(C, l100, l111, kan, kme, hc, E, mj, h);
+            local_field(C, l100, l111, kan, kme, hce, E, mj, h);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 f[j][a] = c * h[a];
@@ -1051,12 +1125,12 @@ struct MassRhsOp {
 // vertices is a halo node below the block's range (halo slots [nb, nb + halo_lo)).
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Material mat, const T *m, const T *u,
-                                                          const Derived *d, double *out) {
+                                                          const T *ud, const Derived *d, double *out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int nb = mv.nb, n0 = b * nb, cnt = min(nb, mv.n - n0);
     const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg), below = mv.halo_lo[b];
-    Staged<T, 1, 6> st;
+    Staged<T, 1, 7> st;
     st.nloc_max = mv.nloc_max;
     st.acc = reinterpret_cast<double *>(smem_raw);
     st.sx = reinterpret_cast<T *>(st.acc + nb);
@@ -1075,6 +1149,7 @@ __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Mat
             st.fld(a, l) = m[static_cast<size_t>(a) * mv.n + g];
             st.fld(3 + a, l) = u[static_cast<size_t>(a) * mv.n + g];
         }
+        st.fld(6, l) = ud ? ud[g] : T(0);
     }
     __syncthreads();
     const Cubic<T> C{static_cast<T>(mat.c11), static_cast<T>(mat.c12), static_cast<T>(mat.c44)};
@@ -1082,7 +1157,7 @@ __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Mat
 #pragma unroll
     for (int t = 0; t < 6; ++t) Eb[t] = static_cast<T>(d->ebar[t]);
     const bool img = mv.img[b] != 0;
-    double ex = 0.0, me = 0.0;
+    double ex = 0.0, me = 0.0, dl = 0.0;
     const int e_beg = mv.blk_ptr[b], e_mag = e_beg + mv.blk_nmag[b], e_end = mv.blk_ptr[b + 1];
     for (int e = e_beg + static_cast<int>(threadIdx.x); e < e_end; e += kThreads) {
         const ushort4 c = mv.lconn[e];
@@ -1131,19 +1206,31 @@ __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Mat
             el += 0.5 * (R[0] * s[0] + R[1] * s[1] + R[2] * s[2] + T(2) * (R[3] * s[3] + R[4] * s[4] + R[5] * s[5]));
         }
         me += 0.25 * static_cast<double>(G.vol) * el;
+        if (ud) {
+            // |grad U~|^2 over the element (all elements: the field fills the inclusions too)
+            double gu[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double uj = st.fld(6, v[j]);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) gu[a] += uj * G.g[j][a];
+            }
+            dl += static_cast<double>(G.vol) * (gu[0] * gu[0] + gu[1] * gu[1] + gu[2] * gu[2]);
+        }
     }
     const double v2[2] = {ex, me};
     block_atomic_add<2>(v2, out, kShards);
+    if (ud) block_atomic_add1(dl, out + 4 * kShards);
 }
 
 // --------------------------------------------------------------- launchers
 
 // The launches of this file request sizeof(double) NC nb + sizeof(T) (3 + NF)
-// nloc_max bytes (energy pass: 8 (nb + 9 nloc_max)); the field right-hand
-// side (FP64, NC = NF = 6) is the largest.
+// nloc_max bytes (energy pass: 8 (nb + 10 nloc_max)); the field right-hand
+// side with the local potential (FP64, NC = 6, NF = 7) is the largest.
 size_t elem_lds_bytes(int32_t nb, int32_t nloc_max) {
     const size_t b = static_cast<size_t>(nb), l = static_cast<size_t>(nloc_max);
-    return std::max(sizeof(double) * 6 * b + sizeof(double) * 9 * l, sizeof(double) * (b + 9 * l));
+    return std::max(sizeof(double) * 6 * b + sizeof(double) * 10 * l, sizeof(double) * (b + 10 * l));
 }
 
 namespace {
@@ -1232,11 +1319,46 @@ template void launch_gs_matvec<float>(const MeshView &, int, double, double, Mat
                                       const float *, const float *, float *, const CGScalars &, int, double,
                                       hipStream_t);
 
+// K^ms on the same strips (all segments), eps = 1 and no mass; FP32 uses the
+// GS operator's scaling, A' = K^ms / len_scale^3.
+template <class T>
+void launch_ms_matvec(const MeshView &mv, int nc, MatvecMode mode, const T *in, T *out, const T *b, const T *r,
+                      T *pout, const CGScalars &cg, int k, double tol, hipStream_t s) {
+    const bool nd = sizeof(T) == sizeof(float);
+    const double sc = nd ? 1.0 / mv.len_scale : 1.0;
+    const int md = static_cast<int>(mode);
+    const double t2 = tol * tol;
+    const T e = static_cast<T>(sc * sc), ms = T(0);
+    if (nc == 1)
+        run_strip<T, 1, 1>(mv, GsMatvecOp<T, 1, true>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc}, s);
+    else
+        run_strip<T, 3, 3>(mv, GsMatvecOp<T, 3, true>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0},
+                                                       {0.0, 0.0, 0.0}, sc}, s);
+}
+
+template void launch_ms_matvec<double>(const MeshView &, int, MatvecMode, const double *, double *, const double *,
+                                       const double *, double *, const CGScalars &, int, double, hipStream_t);
+template void launch_ms_matvec<float>(const MeshView &, int, MatvecMode, const float *, float *, const float *,
+                                      const float *, float *, const CGScalars &, int, double, hipStream_t);
+
 void launch_field_rhs(const MeshView &mv, const Material &mat, const double *m, const double *u, const Derived *d,
-                      double c, double *b, double *x0, double *ch2, double *bb, int bbstride, hipStream_t s) {
-    FieldRhsOp<double> op{m, u, d, b, x0, ch2, bb, mv.n, bbstride, c, cubic_of<double>(mat), mat.l100, mat.l111,
-                          mat.kan, mat.kme, {0, 0, 0, 0, 0, 0}, {0, 0, 0}};
-    run_elem<double, 6, 6>(mv, op, s);
+                      double c, double *b, double *x0, double *ch2, double *bb, int bbstride, const double *ud,
+                      double inv_ms, hipStream_t s) {
+    if (ud) {
+        FieldRhsOp<double, true> op{m, u, d, ud, inv_ms, b, x0, ch2, bb, mv.n, bbstride, c, cubic_of<double>(mat),
+                                    mat.l100, mat.l111, mat.kan, mat.kme, {0, 0, 0, 0, 0, 0}, {0, 0, 0}};
+        run_elem<double, 6, 7>(mv, op, s);
+    } else {
+        FieldRhsOp<double> op{m, u, d, nullptr, 0.0, b, x0, ch2, bb, mv.n, bbstride, c, cubic_of<double>(mat),
+                              mat.l100, mat.l111, mat.kan, mat.kme, {0, 0, 0, 0, 0, 0}, {0, 0, 0}};
+        run_elem<double, 6, 6>(mv, op, s);
+    }
+}
+
+void launch_ms_rhs(const MeshView &mv, double Ms, const double *m, double *b, double *x, double *bb,
+                   hipStream_t s) {
+    MsRhsOp<double> op{m, b, x, bb, mv.n, Ms};
+    run_elem<double, 1, 3>(mv, op, s);
 }
 
 void launch_mass_rhs(const MeshView &mv, const double *y, const double *ch2, double *b, double *x0, double *bb,
@@ -1245,10 +1367,10 @@ void launch_mass_rhs(const MeshView &mv, const double *y, const double *ch2, dou
     run_elem<double, 2, 2>(mv, op, s);
 }
 
-void launch_energy_elem(const MeshView &mv, const Material &mat, const double *m, const double *u, const Derived *d,
-                        double *out2, hipStream_t s) {
-    const size_t lds = sizeof(double) * (static_cast<size_t>(mv.nb) + 9 * static_cast<size_t>(mv.nloc_max));
-    hipLaunchKernelGGL(k_energy_elem<double>, dim3(mv.nblk), dim3(kThreads), lds, s, mv, mat, m, u, d, out2);
+void launch_energy_elem(const MeshView &mv, const Material &mat, const double *m, const double *u, const double *ud,
+                        const Derived *d, double *out2, hipStream_t s) {
+    const size_t lds = sizeof(double) * (static_cast<size_t>(mv.nb) + 10 * static_cast<size_t>(mv.nloc_max));
+    hipLaunchKernelGGL(k_energy_elem<double>, dim3(mv.nblk), dim3(kThreads), lds, s, mv, mat, m, u, ud, d, out2);
 }
 
 }  // namespace gspm

@@ -299,13 +299,47 @@ CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, doub
     });
 }
 
+// K^ms x = b (Eq. weak_demag): the GS solves' two-launch CG on the pinned
+// all-element Laplacian.  The pinned node has b = 0 and x = 0, and its rows
+// of K^ms are zero, so it stays zero.
+CgResult cg_ms(gspm_ctx *c, int nc, double *x, const double *b, double tol, int maxit, SolveKind kind) {
+    hipStream_t s = c->stream;
+    auto resid = [&]() {
+        launch_ms_matvec<double>(c->mv, nc, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
+    };
+    if (c->precision == GSPM_MIXED) {
+        float *P[2] = {c->d.p32, c->d.p32b};
+        const double ls = c->mv.len_scale, scale = 1.0 / (ls * ls * ls);
+        return cg_mixed(c, nc, false, x, tol, maxit, kind, scale, resid, [&](int k, bool last) {
+            if (last) {
+                launch_cg_check(nc, false, c->cg_in, k, 1.0, s);
+                return;
+            }
+            launch_ms_matvec<float>(c->mv, nc, MV_ITER, P[k & 1], c->d.q32, nullptr, c->d.r32, P[(k + 1) & 1],
+                                    c->cg_in, k, 1.0, s);
+            launch_cg_update<float>(c->n, nc, false, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, c->cg_in, k, s);
+        });
+    }
+    double *P[2] = {c->d.p, c->d.p2};
+    return cg_fp64(c, nc, false, x, tol, maxit, kind, resid, [&](int k, bool last) {
+        if (last) {
+            launch_cg_check(nc, false, c->cg, k, tol, s);
+            return;
+        }
+        launch_ms_matvec<double>(c->mv, nc, MV_ITER, P[k & 1], c->d.q, nullptr, c->d.r, P[(k + 1) & 1], c->cg, k,
+                                 tol, s);
+        launch_cg_update<double>(c->n, nc, false, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
+    });
+}
+
 namespace {
 
 // One step of Algorithm B.1 (App. B) in the finite-element form of Eq.
 // (weak_GS); (1 - eps lap)^-1 [y + c h] is the solution g of
 // (eps K + M) g = M y + c M h with eps = l_ex^2 dtau.  Rows 1 and 2 of Step 2
 // use m^n and g^n as printed, row 3 uses m* and g*; g* uses h[m^n];
-// elasticity is solved once per step at m^n and held for h[m*].
+// elasticity (and, with local_demag, the local magnetostatic potential of
+// Eq. weak_demag) is solved once per step at m^n and held for h[m*].
 int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats *st) {
     auto &d = c->d;
     hipStream_t s = c->stream;
@@ -336,10 +370,24 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     st->mech_iters += r.iters[0];
     if (r.status) return r.status;
 
+    // local magnetostatics at m^n, warm start from the previous potential
+    const double *ud = nullptr;
+    if (c->p.local_demag) {
+        hipMemcpyAsync(d.udnext, d.ud, sizeof(double) * static_cast<size_t>(n), hipMemcpyDeviceToDevice, s);
+        cg_prepare(c, 1);
+        launch_ms_rhs(c->mv, c->p.Ms, d.m, d.b, d.udnext, c->cg.bb, s);
+        r = cg_ms(c, 1, d.udnext, d.b, tol, maxit, SK_MS);
+        st->ms_iters += r.iters[0];
+        if (r.status) return r.status;
+        ud = d.udnext;
+    }
+    const double inv_ms = 1.0 / c->p.Ms;
+
     if (c->p.precession) {
         // Step 1: g^n, three components
         cg_prepare(c, 3);
-        launch_field_rhs(c->mv, c->mat, d.m, d.unext, &d.der[0], dtau, d.b, d.g, d.ch2, c->cg.bb, kShards, s);
+        launch_field_rhs(c->mv, c->mat, d.m, d.unext, &d.der[0], dtau, d.b, d.g, d.ch2, c->cg.bb, kShards, ud,
+                         inv_ms, s);
         r = cg_gs(c, 3, eps1, d.g, d.b, tol, maxit, SK_GS1);
         for (int q = 0; q < 3; ++q) st->gs_iters_stage[q] += r.iters[q];
         if (r.status) return r.status;
@@ -362,7 +410,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     launch_derive(d.sums, c->dargs, &d.der[1], s);
     cg_prepare(c, 3);
     launch_field_rhs(c->mv, c->mat, d.ms, d.unext, &d.der[1], c->p.alpha * dtau, d.b, d.g, nullptr, c->cg.bb,
-                     kShards, s);
+                     kShards, ud, inv_ms, s);
     r = cg_gs(c, 3, eps3, d.g, d.b, tol, maxit, SK_GS3);
     for (int q = 0; q < 3; ++q) st->gs_iters_stage[5 + q] += r.iters[q];
     if (r.status) return r.status;
@@ -390,6 +438,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     std::swap(d.m, d.mnext);
     std::swap(d.uprev, d.u);
     std::swap(d.u, d.unext);
+    if (ud) std::swap(d.ud, d.udnext);
     c->have_prev = true;
     ++c->commits;
     return GSPM_OK;

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(_PKG, "libgspm.so")
 GSPM_OK, GSPM_E_ARG, GSPM_E_MESH, GSPM_E_STATE, GSPM_E_DEVICE, GSPM_E_NOCONV, GSPM_E_NONFINITE, GSPM_E_OOM = \
     0, -1, -2, -3, -4, -5, -6, -7
 GSPM_FP64, GSPM_MIXED = 0, 1
-GSPM_FIELD_M, GSPM_FIELD_U = 0, 1
-GSPM_OP_LAPLACE, GSPM_OP_MASS, GSPM_OP_GS, GSPM_OP_ELASTIC = 0, 1, 2, 3
+GSPM_FIELD_M, GSPM_FIELD_U, GSPM_FIELD_UD = 0, 1, 2
+GSPM_OP_LAPLACE, GSPM_OP_MASS, GSPM_OP_GS, GSPM_OP_ELASTIC, GSPM_OP_MS = 0, 1, 2, 3, 4
 GSPM_PERIODIC = 1
 GSPM_WARM_PREVIOUS, GSPM_WARM_LEARNED, GSPM_WARM_EXTRAPOLATE = 0, 1, 2
 GSPM_MPNN_PARAMS = 50819
@@ -31,7 +31,8 @@ EXPORTS = ("gspm_create", "gspm_destroy", "gspm_upload_mesh", "gspm_set_params",
            "gspm_get_field", "gspm_step", "gspm_energies", "gspm_averages", "gspm_apply", "gspm_solve",
            "gspm_mesh_info", "gspm_demag_factors", "gspm_time_operator", "gspm_last_error",
            "gspm_set_warm_start", "gspm_mpnn_set_params", "gspm_mpnn_get_params", "gspm_mpnn_forward",
-           "gspm_mpnn_train_step", "gspm_mpnn_warm_start", "gspm_set_profile", "gspm_relax", "gspm_sweep")
+           "gspm_mpnn_train_step", "gspm_mpnn_warm_start", "gspm_set_profile", "gspm_relax", "gspm_sweep",
+           "gspm_demag_local_energy")
 
 
 class GspmError(RuntimeError):
@@ -49,7 +50,8 @@ class gspm_params(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0")] + [
         ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
-        ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32)]
+        ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32),
+        ("local_demag", ctypes.c_int32)]
 
 
 class gspm_step_stats(ctypes.Structure):
@@ -58,7 +60,7 @@ class gspm_step_stats(ctypes.Structure):
                 ("elapsed_ms", ctypes.c_double), ("matvec_ms", ctypes.c_double),
                 ("matvec_launches", ctypes.c_int64), ("refinements", ctypes.c_int64),
                 ("learned_starts", ctypes.c_int64), ("minres_starts", ctypes.c_int64),
-                ("warm_coef", ctypes.c_double * 2)]
+                ("warm_coef", ctypes.c_double * 2), ("ms_iters", ctypes.c_int64)]
 
 
 _lib = None
@@ -89,6 +91,7 @@ def load() -> ctypes.CDLL:
                                ctypes.c_int32, dp, i32p, i32p]
     lib.gspm_sweep.restype = S
     lib.gspm_energies.argtypes = [P, dp]; lib.gspm_energies.restype = S
+    lib.gspm_demag_local_energy.argtypes = [P, dp]; lib.gspm_demag_local_energy.restype = S
     lib.gspm_averages.argtypes = [P, dp, dp]; lib.gspm_averages.restype = S
     lib.gspm_apply.argtypes = [P, ctypes.c_int, ctypes.c_double, dp, dp, i64]; lib.gspm_apply.restype = S
     lib.gspm_solve.argtypes = [P, ctypes.c_int, ctypes.c_double, dp, dp, i64, ctypes.c_double, ctypes.c_int32,
@@ -160,7 +163,7 @@ def gspm_upload_mesh(ctx, xyz, tets, tags, lo, hi, flags: int = GSPM_PERIODIC) -
 
 
 def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession: bool = True,
-                cg_maxit: int = 10000) -> gspm_params:
+                cg_maxit: int = 10000, local_demag: bool = False) -> gspm_params:
     p = gspm_params()
     for k in ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0"):
         setattr(p, k, float(params[k]))
@@ -174,6 +177,7 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
     p.cg_tol = float(params.get("cg_tol", 1e-8))
     p.cg_maxit = int(params.get("cg_maxit", cg_maxit))
     p.precession = 1 if precession else 0
+    p.local_demag = 1 if local_demag else 0
     return p
 
 
@@ -184,12 +188,12 @@ def gspm_set_params(ctx, params) -> None:
 
 
 def gspm_set_field(ctx, which: int, values) -> None:
-    v = _f64(values, (-1, 3))
+    v = _f64(values, (-1,) if which == GSPM_FIELD_UD else (-1, 3))
     _check(ctx, load().gspm_set_field(ctx, which, _dp(v), v.shape[0]))
 
 
 def gspm_get_field(ctx, which: int, n_nodes: int) -> np.ndarray:
-    out = np.zeros((n_nodes, 3))
+    out = np.zeros(n_nodes if which == GSPM_FIELD_UD else (n_nodes, 3))
     _check(ctx, load().gspm_get_field(ctx, which, _dp(out), n_nodes))
     return out
 
@@ -199,7 +203,7 @@ def stats_dict(st: gspm_step_stats) -> dict:
                 gs_iters=st.gs_iters, gs_iters_stage=list(st.gs_iters_stage), dm_avg=st.dm_avg,
                 elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches,
                 refinements=st.refinements, learned_starts=st.learned_starts, minres_starts=st.minres_starts,
-                warm_coef=list(st.warm_coef))
+                warm_coef=list(st.warm_coef), ms_iters=st.ms_iters)
 
 
 def gspm_step(ctx, dt: float, n_steps: int = 1) -> dict:
@@ -259,6 +263,12 @@ def gspm_energies(ctx) -> dict:
     out = np.zeros(7)
     _check(ctx, load().gspm_energies(ctx, _dp(out)))
     return dict(zip(ENERGY_KEYS, out.tolist()))
+
+
+def gspm_demag_local_energy(ctx) -> float:
+    out = np.zeros(1)
+    _check(ctx, load().gspm_demag_local_energy(ctx, _dp(out)))
+    return float(out[0])
 
 
 def gspm_averages(ctx):
@@ -369,15 +379,16 @@ class Simulation:
     """Owns one context; thin convenience over the functions above."""
 
     def __init__(self, mesh, params: dict | None = None, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6,
-                 precession: bool = True, **create_kw):
+                 precession: bool = True, local_demag: bool = False, **create_kw):
         self.ctx = gspm_create(**create_kw)
         self.n0 = int(np.asarray(mesh.xyz).shape[0])
         gspm_upload_mesh(self.ctx, mesh.xyz, mesh.tets, mesh.tags, mesh.lo, mesh.hi)
         if params is not None:
-            self.set_params(params, hext, sigma_ext, precession)
+            self.set_params(params, hext, sigma_ext, precession, local_demag)
 
-    def set_params(self, params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession: bool = True):
-        gspm_set_params(self.ctx, make_params(params, hext, sigma_ext, precession))
+    def set_params(self, params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession: bool = True,
+                   local_demag: bool = False):
+        gspm_set_params(self.ctx, make_params(params, hext, sigma_ext, precession, local_demag=local_demag))
 
     def set_m(self, m):
         gspm_set_field(self.ctx, GSPM_FIELD_M, m)
@@ -390,6 +401,15 @@ class Simulation:
 
     def get_u(self) -> np.ndarray:
         return gspm_get_field(self.ctx, GSPM_FIELD_U, self.n0)
+
+    def set_ud(self, ud):
+        gspm_set_field(self.ctx, GSPM_FIELD_UD, ud)
+
+    def get_ud(self) -> np.ndarray:
+        return gspm_get_field(self.ctx, GSPM_FIELD_UD, self.n0)
+
+    def demag_local_energy(self) -> float:
+        return gspm_demag_local_energy(self.ctx)
 
     def step(self, dt: float, n: int = 1) -> dict:
         return gspm_step(self.ctx, dt, n)
