@@ -57,6 +57,13 @@ def cg_iteration_bytes(n_nodes: int, n_tets: int, real_bytes: int = 8) -> int:
     return 16 * n_tets + 24 * n_nodes + 8 * 3 * real_bytes * n_nodes
 
 
+def ms_matvec_bytes(n_nodes: int, n_tets: int, real_bytes: int = 4) -> int:
+    """Algorithmic bytes of one K^ms matvec launch (y = K^ms x, one scalar
+    component): connectivity, FP64 coordinates, x read and y written once.
+    124.2 MB with FP32 vectors at 1M nodes."""
+    return 16 * n_tets + 24 * n_nodes + 2 * real_bytes * n_nodes
+
+
 def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float) -> float:
     """Algorithmic bytes of one step (FP64): per elastic CG iteration the
     fused launch (cg_iteration_bytes); per scalar GS CG iteration the
@@ -117,6 +124,8 @@ def main() -> int:
                     help="paths to run; with both, `value` is the mixed path (with the learned warm start when "
                          "trained weights exist) and the other paths are reported beside it")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start path")
+    ap.add_argument("--no-local-demag", action="store_true",
+                    help="skip the paths with the local magnetostatic solve (reported beside the headline)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first fill and sum a buffer of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -151,17 +160,18 @@ def main() -> int:
         if weights.size != gspm.GSPM_MPNN_PARAMS:
             weights = None
 
-    def run_path(precision: int, warm: int = 0) -> dict:
+    def run_path(precision: int, warm: int = 0, local_demag: bool = False) -> dict:
         t_up = time.perf_counter()
         sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, device=0, profile=False,
-                              block_nodes=args.block_nodes, precision=precision)
+                              block_nodes=args.block_nodes, precision=precision, local_demag=local_demag)
         sim.set_m(case.m0)
         if warm == gspm.GSPM_WARM_LEARNED:
             sim.mpnn_set_params(weights)
         sim.set_warm_start(warm)
         info = sim.mesh_info()
         t_up = time.perf_counter() - t_up
-        tag = f"{'mixed' if precision else 'fp64'}" + {0: "", 1: "+learned", 2: "+extrapolated"}[warm]
+        tag = (f"{'mixed' if precision else 'fp64'}" + {0: "", 1: "+learned", 2: "+extrapolated"}[warm]
+               + ("+local_demag" if local_demag else ""))
         print(f"[bench] {tag}: uploaded {info['n_unique']} nodes, {info['n_tets']} tets in "
               f"{t_up:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
         if args.warmup:
@@ -172,12 +182,19 @@ def main() -> int:
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         print(f"[bench] {tag}: {args.steps} steps in {wall:.3f} s, mech iters {st['mech_iters']}, "
-              f"gs iters {st['gs_iters']}, refinements {st['refinements']}, learned starts {st['learned_starts']}, "
-              f"min-residual starts {st['minres_starts']}, last coefficients {st['warm_coef']}",
-              file=sys.stderr, flush=True)
+              f"gs iters {st['gs_iters']}, ms iters {st['ms_iters']}, refinements {st['refinements']}, "
+              f"learned starts {st['learned_starts']}, min-residual starts {st['minres_starts']}, "
+              f"last coefficients {st['warm_coef']}", file=sys.stderr, flush=True)
         out = dict(info=info, st=st, wall=wall, value=info["n_unique"] * args.steps / wall, m=sim.get_m(),
                    u=sim.get_u(), tag=tag)
-        if not args.no_profile:
+        if local_demag:
+            out["ud"] = sim.get_ud()
+            if precision == gspm.GSPM_MIXED:
+                # the K^ms operator the inner solves run: device-resident launches between events
+                out["ms_matvec_ms"] = sim.time_operator(gspm.GSPM_OP_MS, reps=50)
+                print(f"[bench] {tag}: K^ms matvec {out['ms_matvec_ms'] * 1e3:.1f} us per launch (FP32)",
+                      file=sys.stderr, flush=True)
+        elif not args.no_profile:
             # kernel durations from extra untimed steps: every elastic CG iteration is
             # launched with a start/stop event pair that the runtime records at
             # the kernel's own execution (hipExtLaunchKernelGGL), not in the timed region
@@ -198,6 +215,9 @@ def main() -> int:
             paths["mixed+extrapolated"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_EXTRAPOLATE)
         if weights is not None:
             paths["mixed+learned"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_LEARNED)
+    if not args.no_local_demag and args.precision == "both":
+        paths["fp64+local_demag"] = run_path(gspm.GSPM_FP64, local_demag=True)
+        paths["mixed+local_demag"] = run_path(gspm.GSPM_MIXED, local_demag=True)
     head_name = next(k for k in ("mixed+learned", "mixed", "fp64") if k in paths)
     head = paths[head_name]
     mixed = head_name.startswith("mixed")
@@ -228,12 +248,27 @@ def main() -> int:
                "gs_iters_per_step": p["st"]["gs_iters"] / args.steps,
                "refinements_per_step": p["st"]["refinements"] / args.steps,
                "learned_starts": p["st"]["learned_starts"], "minres_starts": p["st"]["minres_starts"]}
-        if "fp64" in paths and k != "fp64":
-            f = paths["fp64"]
-            row["speedup_vs_fp64"] = p["value"] / f["value"]
-            row["rel_err_m_vs_fp64"] = float(np.linalg.norm(p["m"] - f["m"]) / np.linalg.norm(f["m"]))
-            row["rel_err_u_vs_fp64"] = float(np.linalg.norm(um(p["u"]) - um(f["u"])) / np.linalg.norm(um(f["u"])))
+        ld = k.endswith("+local_demag")
+        if ld:
+            row["ms_iters_per_step"] = p["st"]["ms_iters"] / args.steps
+        ref = "fp64+local_demag" if ld else "fp64"
+        if ref in paths and k != ref:
+            f = paths[ref]
+            row["speedup_vs_" + ref] = p["value"] / f["value"]
+            row["rel_err_m_vs_" + ref] = float(np.linalg.norm(p["m"] - f["m"]) / np.linalg.norm(f["m"]))
+            row["rel_err_u_vs_" + ref] = float(np.linalg.norm(um(p["u"]) - um(f["u"])) / np.linalg.norm(um(f["u"])))
+            if ld:
+                row["rel_err_ud_vs_" + ref] = float(np.linalg.norm(p["ud"] - f["ud"]) / np.linalg.norm(f["ud"]))
         per_path[k] = row
+    ms_roofline = None
+    if "mixed+local_demag" in paths:
+        t = paths["mixed+local_demag"]["ms_matvec_ms"] * 1e-3
+        mb = ms_matvec_bytes(n, ne, 4)
+        ms_roofline = {"bound": "hbm", "achieved": mb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": mb / t / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_strip<float,1,1,GsMatvecOp<float,1,true>>", "bytes_per_launch": mb,
+                       "avg_launch_us": t * 1e6,
+                       "timing": "50 device-resident launches of y = K^ms x between HIP events on the library's stream"}
     out = {
         "metric": METRIC, "value": value, "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
@@ -246,6 +281,7 @@ def main() -> int:
         "step_roofline": {"bytes_per_node_step": b_step / n, "roofline_node_steps_per_s": HBM_PEAK_GBS * 1e9 / b_step * n,
                           "frac": value / (HBM_PEAK_GBS * 1e9 / b_step * n)},
         "paths": per_path,
+        "ms_roofline": ms_roofline,
     }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

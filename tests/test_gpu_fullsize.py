@@ -72,3 +72,33 @@ def test_full_size_steps_match_oracle(reference, path):
     if path == "mixed+learned":
         assert st["learned_starts"] == STEPS - 1 and st["minres_starts"] == STEPS - 1
     sim.close()
+
+
+def test_full_size_local_magnetostatic_potential(reference):
+    """The local magnetostatic solve at the full size: one step with
+    local_demag from the initial state stores U~ solved at m^0 from zero,
+    which the oracle's CG reproduces on the same m (1e-9 in FP64, the same
+    iterations up to one); the mixed form keeps m and u within 1e-6 of FP64."""
+    case, orc, _, _ = reference
+    nmap = orc.node_map()
+    mag = orc.lumped_weights() > 0
+    m0 = case.m0 / np.linalg.norm(case.m0, axis=1, keepdims=True)
+    mu = np.zeros((orc.n, 3)); mu[nmap] = m0
+    mu[~mag] = 0.0
+    print("[fullsize] oracle: K^ms solve at m^0", flush=True)
+    U, it = orc.ms_solve(mu, tol=case.cg_tol)
+    out = {}
+    for precision in (gspm.GSPM_FP64, gspm.GSPM_MIXED):
+        sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, precision=precision, local_demag=True)
+        sim.set_m(case.m0)
+        st = sim.step(case.dt, 1)
+        out[precision] = (sim.get_m(), sim.get_u(), sim.get_ud(), st)
+        sim.close()
+    m64, u64, ud64, st64 = out[gspm.GSPM_FP64]
+    m32, u32, ud32, st32 = out[gspm.GSPM_MIXED]
+    e_ud = _rel(ud64, U[nmap])
+    em, eu, eud = _rel(m32, m64), _rel(_demean(u32), _demean(u64)), _rel(ud32, ud64)
+    print(f"[fullsize] K^ms: iters gpu {st64['ms_iters']} oracle {it}, U~ rel err {e_ud:.2e}; "
+          f"mixed vs FP64 m {em:.2e} u {eu:.2e} U~ {eud:.2e}", flush=True)
+    assert abs(st64["ms_iters"] - it) <= 1 and e_ud < 1e-9
+    assert em < 1e-6 and eu < 1e-6
