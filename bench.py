@@ -265,7 +265,7 @@ def main() -> int:
         t = paths["mixed+local_demag"]["ms_matvec_ms"] * 1e-3
         mb = ms_matvec_bytes(n, ne, 4)
         ms_roofline = {"bound": "hbm", "achieved": mb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": mb / t / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                       "frac": mb / t / 1e9 / HBM_PEAK_GBS, "traffic": traffic_from_profile("ms_mixed"),
                        "kernel": "k_strip<float,1,1,GsMatvecOp<float,1,true>>", "bytes_per_launch": mb,
                        "avg_launch_us": t * 1e6,
                        "timing": "50 device-resident launches of y = K^ms x between HIP events on the library's stream"}
