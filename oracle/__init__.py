@@ -37,7 +37,7 @@ class _Params(ctypes.Structure):
                 ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0")] + [
         ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
         ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32),
-        ("local_demag", ctypes.c_int32)]
+        ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9)]
 
 
 class _Stats(ctypes.Structure):
@@ -85,6 +85,8 @@ def _load():
     lib.or_field_rhs.argtypes = [P, ctypes.c_double, dp, dp]
     lib.or_demag_factors.argtypes = [ctypes.c_double] * 3 + [dp]
     lib.or_h_local.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, dp]
+    lib.or_stiffness_voigt.argtypes = [ctypes.POINTER(_Params), dp]
+    lib.or_spont_strain.argtypes = [ctypes.POINTER(_Params), dp, dp]
     lib.or_energy_density_local.argtypes = [ctypes.POINTER(_Params), dp, dp]
     lib.or_energy_density_local.restype = ctypes.c_double
     lib.or_last_error.argtypes = [P]; lib.or_last_error.restype = ctypes.c_char_p
@@ -112,6 +114,7 @@ class OracleError(RuntimeError):
 
 def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession: bool = True,
                 cg_maxit: int = 10000, local_demag: bool = False) -> _Params:
+    """params may carry "crystal_rot" (3 x 3, v_sample = R v_crystal, App. D)."""
     p = _Params()
     for k in ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0"):
         setattr(p, k, float(params[k]))
@@ -126,6 +129,9 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
     p.cg_maxit = int(params.get("cg_maxit", cg_maxit))
     p.precession = 1 if precession else 0
     p.local_demag = 1 if local_demag else 0
+    rot = np.asarray(params.get("crystal_rot", np.eye(3)), dtype=np.float64).reshape(9)
+    for i in range(9):
+        p.crystal_rot[i] = rot[i]
     return p
 
 
@@ -144,6 +150,20 @@ def h_local(params: dict, m, E6, mbar, hext=(0.0, 0.0, 0.0)) -> np.ndarray:
     h = np.zeros(3)
     _load().or_h_local(ctypes.byref(p), _dp(_f64(m)), _dp(_f64(E6)), _dp(_f64(mbar)), _dp(h))
     return h
+
+
+def stiffness_voigt(params: dict) -> np.ndarray:
+    p = make_params(params)
+    out = np.zeros(36)
+    _load().or_stiffness_voigt(ctypes.byref(p), _dp(out))
+    return out.reshape(6, 6)
+
+
+def spont_strain(params: dict, m) -> np.ndarray:
+    p = make_params(params)
+    out = np.zeros(6)
+    _load().or_spont_strain(ctypes.byref(p), _dp(_f64(m)), _dp(out))
+    return out
 
 
 def energy_density_local(params: dict, m, E6, hext=(0.0, 0.0, 0.0)) -> float:

@@ -17,6 +17,9 @@
  *   - optionally the local magnetostatic potential of Eq. (demag) in the weak
  *     form (weak_demag), with K^ms and F^ms of Eqs. (LHS), (RHS_F) and
  *     (RHS_b), and its field -grad U~ (Sec. 2.1);
+ *   - optionally a rotated crystal frame (App. D): the cubic stiffness, the
+ *     spontaneous strain, the anisotropy and the magnetoelastic field taken
+ *     in the crystal frame and carried to the sample frame of the mesh;
  *   - one step of the Gauss-Seidel projection method, Algorithm B.1 (App. B),
  *     with the effective field of App. B and the energy of Eq.
  *     (MicromagneticsEnergy), spontaneous strain from App. A.
@@ -116,17 +119,81 @@ static double gauss_solve(int n, double *A, int k, double *B) {
 
 /* ------------------------------------------------------------- material */
 
-/* Cubic stiffness as a full fourth-order tensor:
- * C_ijkl = c12 d_ij d_kl + c44 (d_ik d_jl + d_il d_jk) + (c11 - c12 - 2 c44) sum_p d_ip d_jp d_kp d_lp. */
+/* The crystal orientation of App. D: v_sample = R v_crystal (an all-zero
+ * matrix means the crystal axes are the sample axes). */
+static void crystal_rot(const or_params *p, double R[3][3]) {
+    int zero = 1;
+    for (int k = 0; k < 9; ++k) zero &= p->crystal_rot[k] == 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R[i][j] = zero ? (i == j) : p->crystal_rot[i * 3 + j];
+}
+
+/* Crystal axes along the sample axes (no rotation to apply). */
+static int crystal_aligned(const or_params *p) {
+    double R[3][3];
+    crystal_rot(p, R);
+    int ident = 1;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) ident &= R[i][j] == (double)(i == j);
+    return ident;
+}
+
+/* Cubic stiffness as a full fourth-order tensor in the crystal frame:
+ * C_ijkl = c12 d_ij d_kl + c44 (d_ik d_jl + d_il d_jk) + (c11 - c12 - 2 c44) sum_p d_ip d_jp d_kp d_lp,
+ * carried to the sample frame as a fourth-order tensor (App. D):
+ * C'_ijkl = R_ia R_jb R_kc R_ld C_abcd. */
 static void cubic_tensor(const or_params *p, double C[3][3][3][3]) {
+    double Cc[3][3][3][3], R[3][3];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             for (int k = 0; k < 3; ++k)
                 for (int l = 0; l < 3; ++l) {
                     double v = p->c12 * (i == j) * (k == l) + p->c44 * ((i == k) * (j == l) + (i == l) * (j == k));
                     if (i == j && j == k && k == l) v += p->c11 - p->c12 - 2.0 * p->c44;
-                    C[i][j][k][l] = v;
+                    Cc[i][j][k][l] = v;
                 }
+    crystal_rot(p, R);
+    /* one index at a time: T <- R applied to the first, second, third, fourth index */
+    double T[3][3][3][3];
+    memcpy(C, Cc, sizeof Cc);
+    for (int pass = 0; pass < (crystal_aligned(p) ? 0 : 4); ++pass) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) {
+                        double v = 0.0;
+                        for (int a = 0; a < 3; ++a) {
+                            if (pass == 0) v += R[i][a] * C[a][j][k][l];
+                            else if (pass == 1) v += R[j][a] * C[i][a][k][l];
+                            else if (pass == 2) v += R[k][a] * C[i][j][a][l];
+                            else v += R[l][a] * C[i][j][k][a];
+                        }
+                        T[i][j][k][l] = v;
+                    }
+        memcpy(C, T, sizeof T);
+    }
+}
+
+/* m in the crystal frame: m_c = R^T m. */
+static void to_crystal(const or_params *p, const double m[3], double mc[3]) {
+    double R[3][3];
+    crystal_rot(p, R);
+    for (int a = 0; a < 3; ++a) mc[a] = R[0][a] * m[0] + R[1][a] * m[1] + R[2][a] * m[2];
+}
+
+/* A symmetric tensor from the crystal frame to the sample frame: R T R^T. */
+static void tensor_to_sample(const or_params *p, double T[3][3]) {
+    double R[3][3], X[3][3];
+    if (crystal_aligned(p)) return;
+    crystal_rot(p, R);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double v = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) v += R[i][a] * T[a][b] * R[j][b];
+            X[i][j] = v;
+        }
+    memcpy(T, X, sizeof X);
 }
 
 static void contract(double C[3][3][3][3], double E[3][3], double S[3][3]) {
@@ -139,21 +206,79 @@ static void contract(double C[3][3][3][3], double E[3][3], double S[3][3]) {
         }
 }
 
-/* Spontaneous strain of a cubic crystal, App. A. */
+/* Spontaneous strain of a cubic crystal, App. A, for a sample-frame m: the
+ * crystal-frame form at m_c = R^T m, carried to the sample frame (App. D,
+ * Step 1). */
 static void spont_strain(const or_params *p, const double m[3], double E0[3][3]) {
+    double mc[3];
+    to_crystal(p, m, mc);
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
-            E0[i][j] = (i == j) ? 1.5 * p->lambda100 * (m[i] * m[i] - 1.0 / 3.0)
-                                : 1.5 * p->lambda111 * m[i] * m[j];
+            E0[i][j] = (i == j) ? 1.5 * p->lambda100 * (mc[i] * mc[i] - 1.0 / 3.0)
+                                : 1.5 * p->lambda111 * mc[i] * mc[j];
+    tensor_to_sample(p, E0);
 }
 
-/* d E0_ij / d m_k. */
+/* d E0_ij / d m_k for the sample-frame m: sum_c R (dE0/dm_c) R^T R_kc. */
 static void spont_strain_deriv(const or_params *p, const double m[3], int k, double D[3][3]) {
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            if (i == j) D[i][j] = (i == k) ? 3.0 * p->lambda100 * m[i] : 0.0;
-            else D[i][j] = 1.5 * p->lambda111 * ((i == k) * m[j] + (j == k) * m[i]);
-        }
+    double mc[3], R[3][3];
+    if (crystal_aligned(p)) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                if (i == j) D[i][j] = (i == k) ? 3.0 * p->lambda100 * m[i] : 0.0;
+                else D[i][j] = 1.5 * p->lambda111 * ((i == k) * m[j] + (j == k) * m[i]);
+            }
+        return;
+    }
+    to_crystal(p, m, mc);
+    crystal_rot(p, R);
+    memset(D, 0, sizeof(double) * 9);
+    for (int c = 0; c < 3; ++c) {
+        double Dc[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                if (i == j) Dc[i][j] = (i == c) ? 3.0 * p->lambda100 * mc[i] : 0.0;
+                else Dc[i][j] = 1.5 * p->lambda111 * ((i == c) * mc[j] + (j == c) * mc[i]);
+            }
+        tensor_to_sample(p, Dc);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) D[i][j] += Dc[i][j] * R[k][c];
+    }
+}
+
+/* Cubic anisotropy kappa_1 (m1^2 m2^2 + m2^2 m3^2 + m3^2 m1^2) of the
+ * crystal-frame components, and its sample-frame gradient R (dpsi/dm_c). */
+static double anis_energy(const or_params *p, const double m[3]) {
+    double c[3];
+    to_crystal(p, m, c);
+    return p->K1 * (c[0] * c[0] * c[1] * c[1] + c[1] * c[1] * c[2] * c[2] + c[2] * c[2] * c[0] * c[0]);
+}
+
+static void anis_gradient(const or_params *p, const double m[3], double g[3]) {
+    double c[3], gc[3], R[3][3];
+    to_crystal(p, m, c);
+    crystal_rot(p, R);
+    for (int k = 0; k < 3; ++k) {
+        double others = 0.0;
+        for (int l = 0; l < 3; ++l)
+            if (l != k) others += c[l] * c[l];
+        gc[k] = 2.0 * p->K1 * c[k] * others;
+    }
+    for (int k = 0; k < 3; ++k) g[k] = R[k][0] * gc[0] + R[k][1] * gc[1] + R[k][2] * gc[2];
+}
+
+void or_stiffness_voigt(const or_params *p, double C6[36]) {
+    static const int ij[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+    double C[3][3][3][3];
+    cubic_tensor(p, C);
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) C6[r * 6 + c] = C[ij[r][0]][ij[r][1]][ij[c][0]][ij[c][1]];
+}
+
+void or_spont_strain(const or_params *p, const double m[3], double E6[6]) {
+    double E0[3][3];
+    spont_strain(p, m, E0);
+    sym_to6(E0, E6);
 }
 
 /* Solve C : X = S for symmetric X in the six independent components. */
@@ -183,12 +308,10 @@ void or_h_local(const or_params *p, const double m[3], const double E6[6], const
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) R[i][j] = E[i][j] - E0[i][j];
     contract(C, R, S);
-    double scale = 1.0 / (p->mu0 * p->Ms * p->Ms);
+    double scale = 1.0 / (p->mu0 * p->Ms * p->Ms), ga[3];
+    anis_gradient(p, m, ga);
     for (int k = 0; k < 3; ++k) {
-        double others = 0.0;
-        for (int l = 0; l < 3; ++l)
-            if (l != k) others += m[l] * m[l];
-        double h_anis = -2.0 * p->K1 * scale * m[k] * others;
+        double h_anis = -scale * ga[k];
         double h_zee = p->hext[k] / p->Ms;
         double h_dem = 0.0;
         for (int l = 0; l < 3; ++l) h_dem -= p->Nd[k * 3 + l] * mbar[l];
@@ -213,7 +336,7 @@ double or_energy_density_local(const or_params *p, const double m[3], const doub
     double el = 0.0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) el += 0.5 * R[i][j] * S[i][j];
-    double an = p->K1 * (m[0] * m[0] * m[1] * m[1] + m[1] * m[1] * m[2] * m[2] + m[2] * m[2] * m[0] * m[0]);
+    double an = anis_energy(p, m);
     double ze = -p->mu0 * p->Ms * (p->hext[0] * m[0] + p->hext[1] * m[1] + p->hext[2] * m[2]);
     return an + el + ze;
 }
@@ -520,6 +643,19 @@ int or_set_params(or_sim *s, const or_params *p) {
         return OR_E_ARG;
     }
     if (p->local_demag != 0 && p->local_demag != 1) { seterr(s, "local_demag must be 0 or 1"); return OR_E_ARG; }
+    {
+        /* the crystal orientation must be a proper rotation (or all zeros) */
+        double R[3][3], err = 0.0;
+        crystal_rot(p, R);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double v = R[i][0] * R[j][0] + R[i][1] * R[j][1] + R[i][2] * R[j][2];
+                err = fmax(err, fabs(v - (i == j)));
+            }
+        double det = R[0][0] * (R[1][1] * R[2][2] - R[1][2] * R[2][1]) - R[0][1] * (R[1][0] * R[2][2] - R[1][2] * R[2][0]) +
+                     R[0][2] * (R[1][0] * R[2][1] - R[1][1] * R[2][0]);
+        if (!(err < 1e-12) || !(det > 0)) { seterr(s, "crystal_rot is not a proper rotation"); return OR_E_ARG; }
+    }
     if (p->local_demag && !s->periodic) {
         seterr(s, "the local magnetostatic solve needs a periodic mesh");
         return OR_E_ARG;
@@ -1135,7 +1271,7 @@ int or_energies(or_sim *s, double out[7]) {
             double E0[3][3] = {{0}}, R[3][3], S[3][3];
             if (s->tag[e]) {
                 spont_strain(p, mv, E0);
-                an += 0.25 * V * p->K1 * (mv[0] * mv[0] * mv[1] * mv[1] + mv[1] * mv[1] * mv[2] * mv[2] + mv[2] * mv[2] * mv[0] * mv[0]);
+                an += 0.25 * V * anis_energy(p, mv);
                 ze += -0.25 * V * p->mu0 * p->Ms * (p->hext[0] * mv[0] + p->hext[1] * mv[1] + p->hext[2] * mv[2]);
             }
             for (int a = 0; a < 3; ++a)

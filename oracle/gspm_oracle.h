@@ -30,6 +30,7 @@ typedef struct {
     int32_t cg_maxit;
     int32_t precession;    /* 1: full Algorithm B.1; 0: damping stage only (m* = m^n) */
     int32_t local_demag;   /* 1: solve the local magnetostatic potential U~ each step (periodic meshes only) */
+    double crystal_rot[9]; /* R of App. D, row-major: v_sample = R v_crystal; all zeros = identity */
 } or_params;
 
 typedef struct {
@@ -97,6 +98,11 @@ void or_demag_factors(double a, double b, double c, double N[3]);
 void or_h_local(const or_params *p, const double m[3], const double E[6], const double mbar[3],
                 double h[3]);
 double or_energy_density_local(const or_params *p, const double m[3], const double E[6]);
+/* The material in the sample frame (App. D): the stiffness as a 6x6 Voigt
+ * matrix (order xx yy zz yz xz xy, engineering shear), and the spontaneous
+ * strain E0(m) for a sample-frame m (tensor components, same order). */
+void or_stiffness_voigt(const or_params *p, double C6[36]);
+void or_spont_strain(const or_params *p, const double m[3], double E6[6]);
 /* Local magnetostatics (Eq. weak_demag) on explicit arrays in unique-node
  * order, state untouched (need set_params for Ms): the right-hand side b (n)
  * for a field m (n x 3, any values); the CG solve for U~ (n, x0 on entry);
