@@ -113,6 +113,13 @@ typedef struct {
                                pinned at the caller's node 0 and warm-started from the previous U~, and adds
                                the element field -grad U~ / Ms to h on magnetic elements (held for h[m*]);
                                the energy total gains (mu0/2) <|grad U~|^2>.  0: far field only. */
+    double crystal_rot[9];  /* crystal orientation of App. D, row-major R with v_sample = R v_crystal (the rows
+                               are the sample axes in crystal coordinates; App. D's <111>, <-110>, <11-2> frame
+                               is one example).  The stiffness, spontaneous strain, anisotropy and
+                               magnetoelastic field are taken in the crystal frame; the mesh, u, hext,
+                               sigma_ext and Nd are in the sample frame.  All zeros (or the identity): crystal
+                               axes along the sample axes.  Otherwise R must be a proper rotation to 1e-12
+                               (GSPM_E_ARG). */
 } gspm_params;
 
 typedef struct {

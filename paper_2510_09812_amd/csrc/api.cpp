@@ -87,6 +87,50 @@ void cubic_compliance(const gspm_params &p, const double s[6], double e[6]) {
     for (int k = 3; k < 6; ++k) e[k] = s[k] / (2.0 * p.c44);
 }
 
+// A symmetric tensor (xx yy zz yz xz xy): R A R^T or R^T A R.
+void rotate_sym(const double R[9], bool to_sample, const double a[6], double b[6]) {
+    const double A[3][3] = {{a[0], a[5], a[4]}, {a[5], a[1], a[3]}, {a[4], a[3], a[2]}};
+    double Q[3][3], B[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Q[i][j] = to_sample ? R[3 * i + j] : R[3 * j + i];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) v += Q[i][k] * A[k][l] * Q[j][l];
+            B[i][j] = v;
+        }
+    b[0] = B[0][0]; b[1] = B[1][1]; b[2] = B[2][2]; b[3] = B[1][2]; b[4] = B[0][2]; b[5] = B[0][1];
+}
+
+// The cubic stiffness seen from the sample frame (App. D) as a Voigt matrix
+// (xx yy zz yz xz xy, engineering shear): the Bond transformation M C M^T,
+// with M the stress-type rotation of Voigt vectors built from R.
+void sample_stiffness(const gspm_params &p, const double R[9], double C6[36]) {
+    static const int ij[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+    double C[6][6] = {}, M[6][6];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) C[i][j] = p.c12;
+        C[i][i] = p.c11;
+        C[3 + i][3 + i] = p.c44;
+    }
+    // row r of M: sigma'_r = sum_c M_rc sigma_c for sigma' = R sigma R^T
+    for (int r = 0; r < 6; ++r) {
+        const int a = ij[r][0], b = ij[r][1];
+        for (int col = 0; col < 6; ++col) {
+            const int k = ij[col][0], l = ij[col][1];
+            M[r][col] = k == l ? R[3 * a + k] * R[3 * b + k] : R[3 * a + k] * R[3 * b + l] + R[3 * a + l] * R[3 * b + k];
+        }
+    }
+    for (int r = 0; r < 6; ++r)
+        for (int col = 0; col < 6; ++col) {
+            double v = 0.0;
+            for (int x = 0; x < 6; ++x)
+                for (int y = 0; y < 6; ++y) v += M[r][x] * C[x][y] * M[col][y];
+            C6[6 * r + col] = v;
+        }
+}
+
 }  // namespace
 
 namespace gspm {
@@ -455,6 +499,24 @@ gspm_status gspm_set_params(gspm_ctx *c, const gspm_params *p) {
     if (!(p->c44 > 0 && p->c11 - p->c12 > 0 && p->c11 + 2 * p->c12 > 0))
         return fail(c, GSPM_E_ARG, "set_params: elastic constants are not positive definite");
     if (p->local_demag != 0 && p->local_demag != 1) return fail(c, GSPM_E_ARG, "set_params: local_demag must be 0 or 1");
+    double R[9];
+    bool zero = true, ident = true;
+    for (int k = 0; k < 9; ++k) {
+        zero &= p->crystal_rot[k] == 0.0;
+        ident &= p->crystal_rot[k] == ((k % 4 == 0) ? 1.0 : 0.0);
+    }
+    for (int k = 0; k < 9; ++k) R[k] = zero ? ((k % 4 == 0) ? 1.0 : 0.0) : p->crystal_rot[k];
+    if (!all_finite(R, 9)) return fail(c, GSPM_E_ARG, "set_params: non-finite crystal_rot");
+    {
+        double err = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                err = std::max(err, std::fabs(R[3 * i] * R[3 * j] + R[3 * i + 1] * R[3 * j + 1] +
+                                              R[3 * i + 2] * R[3 * j + 2] - (i == j ? 1.0 : 0.0)));
+        const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                           R[2] * (R[3] * R[7] - R[4] * R[6]);
+        if (!(err < 1e-12) || !(det > 0.0)) return fail(c, GSPM_E_ARG, "set_params: crystal_rot is not a proper rotation");
+    }
     c->p = *p;
     auto &m = c->mat;
     m.c11 = p->c11; m.c12 = p->c12; m.c44 = p->c44;
@@ -462,9 +524,20 @@ gspm_status gspm_set_params(gspm_ctx *c, const gspm_params *p) {
     m.kan = 2.0 * p->K1 / (p->mu0 * p->Ms * p->Ms);
     m.kme = 1.0 / (p->mu0 * p->Ms * p->Ms);
     m.A = p->A; m.K1 = p->K1; m.mu0Ms = p->mu0 * p->Ms;
+    m.rot = (zero || ident) ? 0 : 1;
+    for (int k = 0; k < 9; ++k) m.R[k] = R[k];
+    sample_stiffness(*p, R, m.C6);
+    c->dargs.rot = m.rot;
+    for (int k = 0; k < 9; ++k) c->dargs.R[k] = R[k];
     for (int k = 0; k < 9; ++k) c->dargs.Nd[k] = p->Nd[k];
     for (int k = 0; k < 3; ++k) c->dargs.hz[k] = p->hext[k] / p->Ms;
-    cubic_compliance(*p, p->sigma_ext, c->dargs.csig);
+    {
+        // C^-1 sigma_ext in the crystal frame, carried back: R (C^-1 (R^T sigma R)) R^T
+        double sc[6], ec[6];
+        rotate_sym(R, false, p->sigma_ext, sc);
+        cubic_compliance(*p, sc, ec);
+        rotate_sym(R, true, ec, c->dargs.csig);
+    }
     c->have_params = true;
     return GSPM_OK;
 }
@@ -554,7 +627,7 @@ gspm_status gspm_energies(gspm_ctx *c, double out[7]) {
     hipSetDevice(c->device);
     auto &d = c->d;
     hipStream_t s = c->stream;
-    launch_avg_sums(c->n, d.w, d.m, c->mat.l100, c->mat.l111, d.sums, s);
+    launch_avg_sums(c->n, d.w, d.m, c->mat, d.sums, s);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
     launch_fill(d.esums, 5 * kShards, 0.0, s);
     launch_energy_elem(c->mv, c->mat, d.m, d.u, c->p.local_demag ? d.ud : nullptr, &d.der[0], d.esums, s);
@@ -597,7 +670,7 @@ gspm_status gspm_demag_local_energy(gspm_ctx *c, double *e) {
     auto &d = c->d;
     hipStream_t s = c->stream;
     // the element pass also needs m, u and the averages; only its potential sum is used here
-    launch_avg_sums(c->n, d.w, d.m, c->mat.l100, c->mat.l111, d.sums, s);
+    launch_avg_sums(c->n, d.w, d.m, c->mat, d.sums, s);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
     launch_fill(d.esums, 5 * kShards, 0.0, s);
     launch_energy_elem(c->mv, c->mat, d.m, d.u, d.ud, &d.der[0], d.esums, s);
@@ -616,7 +689,7 @@ gspm_status gspm_averages(gspm_ctx *c, double mbar[3], double ebar[6]) {
     if (!mbar || !ebar) return fail(c, GSPM_E_ARG, "averages: null output");
     if (!c->have_mesh || !c->have_params || !c->have_m) return fail(c, GSPM_E_STATE, "averages need mesh, params and m");
     hipSetDevice(c->device);
-    launch_avg_sums(c->n, c->d.w, c->d.m, c->mat.l100, c->mat.l111, c->d.sums, c->stream);
+    launch_avg_sums(c->n, c->d.w, c->d.m, c->mat, c->d.sums, c->stream);
     launch_derive(c->d.sums, c->dargs, &c->d.der[0], c->stream);
     Derived der;
     hipMemcpyAsync(&der, &c->d.der[0], sizeof der, hipMemcpyDeviceToHost, c->stream);

@@ -96,6 +96,12 @@ struct Material {
     double A;                     // exchange coefficient (energies)
     double K1;                    // anisotropy (energies)
     double mu0Ms;                 // mu0 Ms (energies)
+    // crystal orientation (App. D): v_sample = R v_crystal, row-major; rot = 0
+    // when the crystal axes are the sample axes.  C6 is the stiffness in the
+    // sample frame as a Voigt matrix (xx yy zz yz xz xy, engineering shear).
+    int32_t rot;
+    double R[9];
+    double C6[36];
 };
 
 // Per-stage quantities derived from the volume averages (device resident).
@@ -140,13 +146,15 @@ void launch_fill(double *p, int64_t n, double v, hipStream_t s);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 
 // Volume-average sums (sharded, 9 x kShards): sum w m (3), sum w E0(m) (6).
-void launch_avg_sums(int n, const double *w, const double *m, double l100, double l111, double *sums,
-                     hipStream_t s);
+// <E0> is summed in the crystal frame when mat.rot (k_derive rotates it).
+void launch_avg_sums(int n, const double *w, const double *m, const Material &mat, double *sums, hipStream_t s);
 struct DeriveArgs {
     double vc;
     double Nd[9];
     double hz[3];                 // H_ext / Ms
-    double csig[6];               // C^-1 sigma_ext
+    double csig[6];               // C^-1 sigma_ext (sample frame)
+    int32_t rot;                  // the averaged E0 sums are crystal-frame: rotate them by R
+    double R[9];
 };
 void launch_derive(const double *sums, const DeriveArgs &a, Derived *out, hipStream_t s);
 

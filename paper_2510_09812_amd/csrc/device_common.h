@@ -44,6 +44,43 @@ struct RawGeo {
 __device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_approx(double x) { return 1.0 / x; }
 
+// Crystal orientation (App. D), R row-major with v_sample = R v_crystal.
+// c = R^T v (sample -> crystal) and v = R c (crystal -> sample).
+template <class T>
+__device__ __forceinline__ void to_crystal3(const double *R, const T (&v)[3], T (&c)[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[a] = R[a] * v[0] + R[3 + a] * v[1] + R[6 + a] * v[2];
+}
+
+template <class T>
+__device__ __forceinline__ void to_sample3(const double *R, const T (&c)[3], T (&v)[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[i] = R[3 * i] * c[0] + R[3 * i + 1] * c[1] + R[3 * i + 2] * c[2];
+}
+
+// A symmetric tensor (xx yy zz yz xz xy): R A R^T (to the sample frame) or
+// R^T A R (to the crystal frame).
+template <class T>
+__device__ __forceinline__ void sym_rotate(const double *R, bool to_sample, const T (&a)[6], T (&b)[6]) {
+    const T A[3][3] = {{a[0], a[5], a[4]}, {a[5], a[1], a[3]}, {a[4], a[3], a[2]}};
+    T Q[3][3], X[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Q[i][j] = static_cast<T>(to_sample ? R[3 * i + j] : R[3 * j + i]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) X[i][j] = Q[i][0] * A[0][j] + Q[i][1] * A[1][j] + Q[i][2] * A[2][j];
+    T B[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) B[i][j] = X[i][0] * Q[j][0] + X[i][1] * Q[j][1] + X[i][2] * Q[j][2];
+    b[0] = B[0][0]; b[1] = B[1][1]; b[2] = B[2][2];
+    b[3] = B[1][2]; b[4] = B[0][2]; b[5] = B[0][1];
+}
+
 template <class T>
 __device__ __forceinline__ void tet_raw_geometry(const T (&e)[3][3], RawGeo<T> &R) {
 #pragma unroll

@@ -399,6 +399,19 @@ struct Cubic {
     }
 };
 
+// A general stiffness as a Voigt matrix (xx yy zz yz xz xy, engineering
+// shear): the cubic crystal seen from a rotated sample frame (App. D).
+template <class T>
+struct Aniso {
+    T c[36];
+    __device__ __forceinline__ void stress_eng(const T (&e)[6], T (&s)[6]) const {
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+            s[r] = c[6 * r] * e[0] + c[6 * r + 1] * e[1] + c[6 * r + 2] * e[2] + c[6 * r + 3] * e[3] +
+                   c[6 * r + 4] * e[4] + c[6 * r + 5] * e[5];
+    }
+};
+
 // E0(m) of App. A: 3/2 [lambda100 (m_i^2 - 1/3); lambda111 m_i m_j]
 template <class T>
 __device__ __forceinline__ void spontaneous_strain(T l100, T l111, const T (&m)[3], T (&e)[6]) {
@@ -506,8 +519,8 @@ __device__ __forceinline__ bool cg_direction_scalars(const CGScalars &cg, int k,
 // the unscaled geometry: H' = sum_k (v_k - v_0) (x) c_k = det grad v, so
 // C sym(H') = det sigma, and V sigma grad(lambda_j) = w (C sym H') c_j; vertex
 // 0 takes minus the sum of the others (the gradients sum to zero).
-template <class T>
-__device__ __forceinline__ void elastic_element_raw(const Cubic<T> &C, const T (&v)[4][3], const RawGeo<T> &R,
+template <class T, class M>
+__device__ __forceinline__ void elastic_element_raw(const M &C, const T (&v)[4][3], const RawGeo<T> &R,
                                                     T (&y)[4][3]) {
     T H[3][3];
 #pragma unroll
@@ -534,7 +547,7 @@ __device__ __forceinline__ void elastic_element_raw(const Cubic<T> &C, const T (
 
 // Matrix-free K^mech (Eq. LHS): y_i = V sigma(u) g_i over all elements; rows of
 // the pinned node are zero.  See launch_elastic_matvec for the modes.
-template <class T>
+template <class T, class M = Cubic<T>>
 struct ElasticMatvecOp {
     static constexpr bool kMagneticOnly = false;
     const T *in;                  // APPLY/RESID: the vector; ITER: p_old
@@ -545,7 +558,7 @@ struct ElasticMatvecOp {
     CGScalars cg;
     int k, mode, n;
     double tol2;
-    Cubic<T> C;
+    M C;
     int live[1];
     double beta[1];
     double coord_scale;           // staged coordinates in units of 1/coord_scale metres
@@ -614,7 +627,7 @@ struct ElasticMatvecOp {
 // that finds rr_{k-1} converged records it (x_{k-1} is the answer) and does
 // nothing else; the final launch after the last permitted iteration only adds
 // the pending alpha p_{k-1} to x when rr_{k-1} has not converged.
-template <class T>
+template <class T, class M = Cubic<T>>
 struct ElasticCgOp {
     static constexpr bool kMagneticOnly = false;
     const T *rin, *pin, *qin;     // r_{k-1}, p_{k-1}, q_{k-1} (rin = r_0 at k = 0)
@@ -623,7 +636,7 @@ struct ElasticCgOp {
     CGScalars cg;
     int k, n, last;               // last: the launch after the last permitted iteration
     double tol2;
-    Cubic<T> C;
+    M C;
     double alpha, beta;
     double coord_scale;
 
@@ -727,6 +740,8 @@ struct ElasticRhsOp {
     int n;
     Cubic<T> C;
     T l100, l111;
+    int rot;                      // crystal orientation R (App. D)
+    double R[9];
     double coord_scale = 1.0;
 
     __device__ bool prepare() { return true; }
@@ -744,8 +759,11 @@ struct ElasticRhsOp {
         vertex3(st, 0, c, v);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            T ej[6];
-            const T mj[3] = {v[j][0], v[j][1], v[j][2]};
+            T ej[6], mj[3] = {v[j][0], v[j][1], v[j][2]};
+            if (rot) {
+                const T ms[3] = {mj[0], mj[1], mj[2]};
+                to_crystal3(R, ms, mj);
+            }
             spontaneous_strain(l100, l111, mj, ej);
 #pragma unroll
             for (int t = 0; t < 6; ++t) e0[t] += ej[t];
@@ -753,7 +771,11 @@ struct ElasticRhsOp {
 #pragma unroll
         for (int t = 0; t < 6; ++t) e0[t] *= T(0.25);
         T s[6];
-        C.stress(e0, s);
+        C.stress(e0, s);              // crystal frame when rotated
+        if (rot) {
+            const T sc[6] = {s[0], s[1], s[2], s[3], s[4], s[5]};
+            sym_rotate(R, true, sc, s);
+        }
 #pragma unroll
         for (int t = 0; t < 6; ++t) s[t] *= G.vol;
         sym_times_grads(s, G, y);
@@ -977,6 +999,8 @@ struct FieldRhsOp {
     Cubic<T> C;
     T l100, l111, kan, kme;
     T E0bar[6], hc[3];
+    int rot;                      // crystal orientation R (App. D)
+    double R[9];
     double coord_scale = 1.0;
 
     __device__ bool prepare() {
@@ -1018,11 +1042,24 @@ struct FieldRhsOp {
             }
         }
         T f[4][3], sf[3] = {0, 0, 0}, sm[3] = {0, 0, 0};
+        T Ec[6];
+        if (rot) sym_rotate(R, false, E, Ec);   // the element strain in the crystal frame
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const T mj[3] = {mv[j][0], mv[j][1], mv[j][2]};
             T h[3];
-            local_field(C, l100, l111, kan, kme, hce, E, mj, h);
+            if (rot) {
+                // anisotropy and magnetoelastic field in the crystal frame, rotated back (App. D, Step 4)
+                T mc[3], hcr[3];
+                const T zero[3] = {T(0), T(0), T(0)};
+                to_crystal3(R, mj, mc);
+                local_field(C, l100, l111, kan, kme, zero, Ec, mc, hcr);
+                to_sample3(R, hcr, h);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) h[a] += hce[a];
+            } else {
+                local_field(C, l100, l111, kan, kme, hce, E, mj, h);
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 f[j][a] = c * h[a];
@@ -1157,6 +1194,7 @@ __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Mat
 #pragma unroll
     for (int t = 0; t < 6; ++t) Eb[t] = static_cast<T>(d->ebar[t]);
     const bool img = mv.img[b] != 0;
+    const bool rot = mat.rot != 0;
     double ex = 0.0, me = 0.0, dl = 0.0;
     const int e_beg = mv.blk_ptr[b], e_mag = e_beg + mv.blk_nmag[b], e_end = mv.blk_ptr[b + 1];
     for (int e = e_beg + static_cast<int>(threadIdx.x); e < e_end; e += kThreads) {
@@ -1189,6 +1227,19 @@ __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Mat
             ex += mat.A * static_cast<double>(G.vol) * g2;
         }
         double el = 0.0;
+        if (rot) {
+            // the energy density is frame independent: evaluate it in the crystal frame
+            const T Es[6] = {E[0], E[1], E[2], E[3], E[4], E[5]};
+            sym_rotate(mat.R, false, Es, E);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T ms[3] = {mv4[j][0], mv4[j][1], mv4[j][2]};
+                T mc[3];
+                to_crystal3(mat.R, ms, mc);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) mv4[j][a] = mc[a];
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             T R[6], s[6];
@@ -1238,6 +1289,14 @@ template <class T>
 Cubic<T> cubic_of(const Material &m) {
     return Cubic<T>{static_cast<T>(m.c11), static_cast<T>(m.c12), static_cast<T>(m.c44)};
 }
+
+// The sample-frame stiffness; nd: divided by c11 (the FP32 operators' scaling).
+template <class T>
+Aniso<T> aniso_of(const Material &m, bool nd) {
+    Aniso<T> a;
+    for (int k = 0; k < 36; ++k) a.c[k] = static_cast<T>(nd ? m.C6[k] / m.c11 : m.C6[k]);
+    return a;
+}
 }  // namespace
 
 // FP64 works in SI units.  FP32 works on the non-dimensional operator
@@ -1253,6 +1312,12 @@ void launch_elastic_matvec(const MeshView &mv, const Material &mat, MatvecMode m
         m2.c12 = mat.c12 / mat.c11;
         m2.c44 = mat.c44 / mat.c11;
         m2.c11 = 1.0;
+    }
+    if (mat.rot) {
+        ElasticMatvecOp<T, Aniso<T>> op{in, out, b, r, pout, cg, k, static_cast<int>(mode), mv.n, tol * tol,
+                                        aniso_of<T>(mat, nd), {0}, {0.0}, nd ? 1.0 / mv.len_scale : 1.0};
+        run_strip<T, 3, 3>(mv, op, s, ev);
+        return;
     }
     ElasticMatvecOp<T> op{in, out, b, r, pout, cg, k, static_cast<int>(mode), mv.n, tol * tol, cubic_of<T>(m2), {0},
                           {0.0}, nd ? 1.0 / mv.len_scale : 1.0};
@@ -1277,6 +1342,12 @@ void launch_elastic_cg(const MeshView &mv, const Material &mat, int k, bool last
         m2.c44 = mat.c44 / mat.c11;
         m2.c11 = 1.0;
     }
+    if (mat.rot) {
+        ElasticCgOp<T, Aniso<T>> op{rin, pin, qin, rout, pout, qout, x, cg, k, mv.n, last ? 1 : 0, tol * tol,
+                                    aniso_of<T>(mat, nd), 0.0, 0.0, nd ? 1.0 / mv.len_scale : 1.0};
+        run_strip<T, 3, 3>(mv, op, s, ev);
+        return;
+    }
     ElasticCgOp<T> op{rin, pin, qin, rout, pout, qout, x, cg, k, mv.n, last ? 1 : 0, tol * tol, cubic_of<T>(m2),
                       0.0, 0.0, nd ? 1.0 / mv.len_scale : 1.0};
     run_strip<T, 3, 3>(mv, op, s, ev);
@@ -1291,7 +1362,8 @@ template void launch_elastic_cg<float>(const MeshView &, const Material &, int, 
 
 void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x, double *bb,
                         hipStream_t s) {
-    ElasticRhsOp<double> op{m, b, x, bb, mv.n, cubic_of<double>(mat), mat.l100, mat.l111};
+    ElasticRhsOp<double> op{m, b, x, bb, mv.n, cubic_of<double>(mat), mat.l100, mat.l111, mat.rot, {}};
+    for (int k = 0; k < 9; ++k) op.R[k] = mat.R[k];
     run_elem<double, 3, 3>(mv, op, s);
 }
 
@@ -1346,11 +1418,13 @@ void launch_field_rhs(const MeshView &mv, const Material &mat, const double *m, 
                       double inv_ms, hipStream_t s) {
     if (ud) {
         FieldRhsOp<double, true> op{m, u, d, ud, inv_ms, b, x0, ch2, bb, mv.n, bbstride, c, cubic_of<double>(mat),
-                                    mat.l100, mat.l111, mat.kan, mat.kme, {0, 0, 0, 0, 0, 0}, {0, 0, 0}};
+                                    mat.l100, mat.l111, mat.kan, mat.kme, {0, 0, 0, 0, 0, 0}, {0, 0, 0}, mat.rot, {}};
+        for (int k = 0; k < 9; ++k) op.R[k] = mat.R[k];
         run_elem<double, 6, 7>(mv, op, s);
     } else {
         FieldRhsOp<double> op{m, u, d, nullptr, 0.0, b, x0, ch2, bb, mv.n, bbstride, c, cubic_of<double>(mat),
-                              mat.l100, mat.l111, mat.kan, mat.kme, {0, 0, 0, 0, 0, 0}, {0, 0, 0}};
+                              mat.l100, mat.l111, mat.kan, mat.kme, {0, 0, 0, 0, 0, 0}, {0, 0, 0}, mat.rot, {}};
+        for (int k = 0; k < 9; ++k) op.R[k] = mat.R[k];
         run_elem<double, 6, 6>(mv, op, s);
     }
 }

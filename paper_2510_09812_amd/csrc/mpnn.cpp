@@ -301,7 +301,7 @@ gspm_status gspm_mpnn_warm_start(gspm_ctx *c, const double *m_prev, const double
     hipStream_t s = c->stream;
     const size_t bytes3 = sizeof(double) * 3 * static_cast<size_t>(c->n);
     // the elastic right-hand side at the current m, as the step forms it
-    launch_avg_sums(c->n, d.w, d.m, c->mat.l100, c->mat.l111, d.sums, s);
+    launch_avg_sums(c->n, d.w, d.m, c->mat, d.sums, s);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
     hipMemcpyAsync(d.unext, d.u, bytes3, hipMemcpyDeviceToDevice, s);
     cg_prepare(c, 1);

@@ -52,16 +52,24 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
 
 // Volume averages of Sec. 2.4 for P1 fields: int_Omega g = sum_j w_j g_j with
 // the magnetic lumped weights w_j (m and E0(m) vanish in the inclusions).
-__global__ void __launch_bounds__(kThreads) k_avg_sums(int n, const double *w, const double *m, double l100,
-                                                       double l111, double *sums) {
+// With a rotated crystal (App. D) the E0 sums are taken at the crystal-frame
+// m_c = R^T m and k_derive carries their mean back to the sample frame.
+__global__ void __launch_bounds__(kThreads) k_avg_sums(int n, const double *w, const double *m, Material mat,
+                                                       double *sums) {
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const double a = 1.5 * l100, b = 1.5 * l111, third = 1.0 / 3.0;
+    const double a = 1.5 * mat.l100, b = 1.5 * mat.l111, third = 1.0 / 3.0;
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
         const double wi = w[i];
-        const double m0 = m[i], m1 = m[n + i], m2 = m[2 * static_cast<size_t>(n) + i];
+        double m0 = m[i], m1 = m[n + i], m2 = m[2 * static_cast<size_t>(n) + i];
         acc[0] += wi * m0;
         acc[1] += wi * m1;
         acc[2] += wi * m2;
+        if (mat.rot) {
+            const double ms[3] = {m0, m1, m2};
+            double mc[3];
+            to_crystal3(mat.R, ms, mc);
+            m0 = mc[0]; m1 = mc[1]; m2 = mc[2];
+        }
         acc[3] += wi * a * (m0 * m0 - third);
         acc[4] += wi * a * (m1 * m1 - third);
         acc[5] += wi * a * (m2 * m2 - third);
@@ -72,10 +80,9 @@ __global__ void __launch_bounds__(kThreads) k_avg_sums(int n, const double *w, c
     block_atomic_add<9>(acc, sums, kShards);
 }
 
-void launch_avg_sums(int n, const double *w, const double *m, double l100, double l111, double *sums,
-                     hipStream_t s) {
+void launch_avg_sums(int n, const double *w, const double *m, const Material &mat, double *sums, hipStream_t s) {
     launch_fill(sums, 9 * kShards, 0.0, s);
-    hipLaunchKernelGGL(k_avg_sums, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, m, l100, l111, sums);
+    hipLaunchKernelGGL(k_avg_sums, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, m, mat, sums);
 }
 
 // mbar = sum w m / V_c; Ebar = <E0(m)> + C^-1 sigma_ext (the homogeneous strain
@@ -90,7 +97,13 @@ __global__ void __launch_bounds__(kThreads) k_derive(const double *sums, DeriveA
         double mb[3];
         for (int k = 0; k < 3; ++k) mb[k] = t[k] / a.vc;
         for (int k = 0; k < 3; ++k) out->mbar[k] = mb[k];
-        for (int k = 0; k < 6; ++k) out->ebar[k] = t[3 + k] / a.vc + a.csig[k];
+        double e0[6];
+        for (int k = 0; k < 6; ++k) e0[k] = t[3 + k] / a.vc;
+        if (a.rot) {
+            const double ec[6] = {e0[0], e0[1], e0[2], e0[3], e0[4], e0[5]};
+            sym_rotate(a.R, true, ec, e0);
+        }
+        for (int k = 0; k < 6; ++k) out->ebar[k] = e0[k] + a.csig[k];
         for (int k = 0; k < 3; ++k)
             out->hc[k] = a.hz[k] - (a.Nd[3 * k] * mb[0] + a.Nd[3 * k + 1] * mb[1] + a.Nd[3 * k + 2] * mb[2]);
     }
@@ -101,22 +114,26 @@ void launch_derive(const double *sums, const DeriveArgs &a, Derived *out, hipStr
 }
 
 // Anisotropy and Zeeman energies by the vertex rule: sum_j w_j psi(m_j).
-__global__ void __launch_bounds__(kThreads) k_energy_nodes(int n, const double *w, const double *m, double K1,
-                                                           double mu0Ms, double h0, double h1, double h2,
-                                                           double *out) {
+__global__ void __launch_bounds__(kThreads) k_energy_nodes(int n, const double *w, const double *m, Material mat,
+                                                           double h0, double h1, double h2, double *out) {
     double acc[2] = {0.0, 0.0};
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
         const double m0 = m[i], m1 = m[n + i], m2 = m[2 * static_cast<size_t>(n) + i];
-        acc[0] += w[i] * K1 * (m0 * m0 * m1 * m1 + m1 * m1 * m2 * m2 + m2 * m2 * m0 * m0);
-        acc[1] -= w[i] * mu0Ms * (h0 * m0 + h1 * m1 + h2 * m2);
+        double c[3] = {m0, m1, m2};
+        if (mat.rot) {
+            const double ms[3] = {m0, m1, m2};
+            to_crystal3(mat.R, ms, c);    // anisotropy of the crystal-frame components (App. D)
+        }
+        acc[0] += w[i] * mat.K1 * (c[0] * c[0] * c[1] * c[1] + c[1] * c[1] * c[2] * c[2] + c[2] * c[2] * c[0] * c[0]);
+        acc[1] -= w[i] * mat.mu0Ms * (h0 * m0 + h1 * m1 + h2 * m2);
     }
     block_atomic_add<2>(acc, out, kShards);
 }
 
 void launch_energy_nodes(int n, const double *w, const double *m, const Material &mat, const double hext[3],
                          double *out2, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy_nodes, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, m, mat.K1, mat.mu0Ms,
-                       hext[0], hext[1], hext[2], out2);
+    hipLaunchKernelGGL(k_energy_nodes, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, m, mat, hext[0], hext[1],
+                       hext[2], out2);
 }
 
 // ---------------------------------------------------------------------- CG

@@ -347,10 +347,9 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     const size_t bytes3 = sizeof(double) * 3 * static_cast<size_t>(n);
     const double tol = c->p.cg_tol;
     const int maxit = c->p.cg_maxit;
-    const double l100 = c->mat.l100, l111 = c->mat.l111;
 
     // volume averages at m^n: far field and homogeneous strain
-    launch_avg_sums(n, d.w, d.m, l100, l111, d.sums, s);
+    launch_avg_sums(n, d.w, d.m, c->mat, d.sums, s);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
 
     // mechanical equilibrium at m^n, warm start from u^{n-1}
@@ -406,7 +405,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     }
 
     // Step 3: damped solve with h[m*], averages re-evaluated at m*
-    launch_avg_sums(n, d.w, d.ms, l100, l111, d.sums, s);
+    launch_avg_sums(n, d.w, d.ms, c->mat, d.sums, s);
     launch_derive(d.sums, c->dargs, &d.der[1], s);
     cg_prepare(c, 3);
     launch_field_rhs(c->mv, c->mat, d.ms, d.unext, &d.der[1], c->p.alpha * dtau, d.b, d.g, nullptr, c->cg.bb,

@@ -51,7 +51,7 @@ class gspm_params(ctypes.Structure):
                 ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0")] + [
         ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
         ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32),
-        ("local_demag", ctypes.c_int32)]
+        ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9)]
 
 
 class gspm_step_stats(ctypes.Structure):
@@ -178,6 +178,9 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
     p.cg_maxit = int(params.get("cg_maxit", cg_maxit))
     p.precession = 1 if precession else 0
     p.local_demag = 1 if local_demag else 0
+    rot = np.asarray(params.get("crystal_rot", np.eye(3)), dtype=np.float64).reshape(9)
+    for i in range(9):
+        p.crystal_rot[i] = rot[i]
     return p
 
 
