@@ -36,6 +36,8 @@ METRIC = "GSPM node-steps/s at 1M nodes, mixed vs FP64 at 1e-6 rel err; HBM GB/s
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_elastic_cg_cube100.json")
 WEIGHTS_FILE = os.path.join(ROOT, "paper_2510_09812_amd", "weights", "warm_start.f32")
+# App. D's rotated frame: the sample axes along the crystal's <111>, <-110>, <11-2>
+R111 = np.array([[1, 1, 1], [-1, 1, 0], [-1, -1, 2]], dtype=np.float64) / np.sqrt([[3.0], [2.0], [6.0]])
 KERNEL_SOURCES = ["paper_2510_09812_amd/csrc/elem_kernels.hip", "paper_2510_09812_amd/csrc/device_common.h"]
 
 
@@ -124,6 +126,8 @@ def main() -> int:
                     help="paths to run; with both, `value` is the mixed path (with the learned warm start when "
                          "trained weights exist) and the other paths are reported beside it")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start path")
+    ap.add_argument("--no-rotated", action="store_true",
+                    help="skip the path with the crystal rotated to the <111> frame of App. D")
     ap.add_argument("--no-local-demag", action="store_true",
                     help="skip the paths with the local magnetostatic solve (reported beside the headline)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -160,9 +164,12 @@ def main() -> int:
         if weights.size != gspm.GSPM_MPNN_PARAMS:
             weights = None
 
-    def run_path(precision: int, warm: int = 0, local_demag: bool = False) -> dict:
+    def run_path(precision: int, warm: int = 0, local_demag: bool = False, rotated: bool = False) -> dict:
         t_up = time.perf_counter()
-        sim = gspm.Simulation(case.mesh, case.params, hext=case.hext, device=0, profile=False,
+        params = dict(case.params)
+        if rotated:
+            params["crystal_rot"] = R111
+        sim = gspm.Simulation(case.mesh, params, hext=case.hext, device=0, profile=False,
                               block_nodes=args.block_nodes, precision=precision, local_demag=local_demag)
         sim.set_m(case.m0)
         if warm == gspm.GSPM_WARM_LEARNED:
@@ -171,7 +178,7 @@ def main() -> int:
         info = sim.mesh_info()
         t_up = time.perf_counter() - t_up
         tag = (f"{'mixed' if precision else 'fp64'}" + {0: "", 1: "+learned", 2: "+extrapolated"}[warm]
-               + ("+local_demag" if local_demag else ""))
+               + ("+local_demag" if local_demag else "") + ("+rotated111" if rotated else ""))
         print(f"[bench] {tag}: uploaded {info['n_unique']} nodes, {info['n_tets']} tets in "
               f"{t_up:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
         if args.warmup:
@@ -215,6 +222,9 @@ def main() -> int:
             paths["mixed+extrapolated"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_EXTRAPOLATE)
         if weights is not None:
             paths["mixed+learned"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_LEARNED)
+    if not args.no_rotated and args.precision == "both":
+        paths["fp64+rotated111"] = run_path(gspm.GSPM_FP64, rotated=True)
+        paths["mixed+rotated111"] = run_path(gspm.GSPM_MIXED, rotated=True)
     if not args.no_local_demag and args.precision == "both":
         paths["fp64+local_demag"] = run_path(gspm.GSPM_FP64, local_demag=True)
         paths["mixed+local_demag"] = run_path(gspm.GSPM_MIXED, local_demag=True)
@@ -251,7 +261,9 @@ def main() -> int:
         ld = k.endswith("+local_demag")
         if ld:
             row["ms_iters_per_step"] = p["st"]["ms_iters"] / args.steps
-        ref = "fp64+local_demag" if ld else "fp64"
+        if "prof" in p and p["prof"]["matvec_launches"] > 0:
+            row["elastic_cg_launch_us"] = p["prof"]["matvec_ms"] / p["prof"]["matvec_launches"] * 1e3
+        ref = "fp64+local_demag" if ld else ("fp64+rotated111" if k.endswith("+rotated111") else "fp64")
         if ref in paths and k != ref:
             f = paths[ref]
             row["speedup_vs_" + ref] = p["value"] / f["value"]
