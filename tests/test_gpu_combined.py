@@ -1,0 +1,90 @@
+"""The optional terms together, and the failure path of the magnetostatic solve.
+
+  - the rotated crystal (App. D), the local magnetostatic potential
+    (Eq. demag) and an applied stress in one run: three steps match the CPU
+    oracle (m and mean-removed u within 1e-9, the potential within 1e-9,
+    energies within 1e-9 of the total, iteration counts within one per solve);
+  - a magnetostatic solve that runs out of iterations: GSPM_E_NOCONV on both
+    sides, failed_step 0, and m, u and the stored potential as they were
+    (the step commits by pointer swap only after every solve converged).
+    Magnetostriction is switched off there so that the elastic solve has a
+    zero right-hand side and the magnetostatic solve is the one that fails.
+Workload: a ragged 9-node cube (512 unique nodes) with a spherical inclusion.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as w
+from paper_2510_09812_amd import gspm
+
+pytestmark = pytest.mark.gpu
+
+S3, S2, S6 = np.sqrt(3.0), np.sqrt(2.0), np.sqrt(6.0)
+R111 = np.array([[1 / S3, 1 / S3, 1 / S3], [-1 / S2, 1 / S2, 0.0], [-1 / S6, -1 / S6, 2 / S6]])
+SIGMA = (-5e7, 2e7, 0.0, 1e7, 0.0, -3e6)
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _demean(u):
+    return u - u.mean(axis=0)
+
+
+@pytest.fixture(scope="module")
+def case():
+    return w.small_cube(9, seed=91, L=8e-8, jitter=0.15, sphere=0.3)
+
+
+def test_rotated_crystal_with_local_magnetostatics_matches_oracle(case):
+    steps = 3
+    p = {**case.params, "crystal_rot": R111}
+    hext = (-4e4, 1e4, 0.0)
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(p, hext=hext, sigma_ext=SIGMA, local_demag=True)
+    orc.set_m(case.m0)
+    ost = orc.step(case.dt, steps)
+    sim = gspm.Simulation(case.mesh, p, hext=hext, sigma_ext=SIGMA, local_demag=True)
+    sim.set_m(case.m0)
+    st = sim.step(case.dt, steps)
+    em = _rel(sim.get_m(), orc.get_m())
+    eu = _rel(_demean(sim.get_u()), _demean(orc.get_u()))
+    eud = _rel(sim.get_ud(), orc.get_ud())
+    eg, er = sim.energies(), orc.energies()
+    ee = max(abs(eg[k] - er[k]) / abs(er["total"]) for k in er)
+    print(f"rotated + local magnetostatics: m {em:.2e} u {eu:.2e} U~ {eud:.2e} energies {ee:.2e} | ms iters gpu "
+          f"{st['ms_iters']} oracle {ost['ms_iters']} | mech gpu {st['mech_iters']} oracle {ost['mech_iters']}",
+          flush=True)
+    assert em < 1e-9 and eu < 1e-9 and eud < 1e-9 and ee < 1e-9
+    assert abs(st["ms_iters"] - ost["ms_iters"]) <= steps
+    assert abs(st["mech_iters"] - ost["mech_iters"]) <= steps
+    assert all(abs(a - b) <= steps for a, b in zip(st["gs_iters_stage"], ost["gs_iters"]))
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", [gspm.GSPM_FP64, gspm.GSPM_MIXED])
+def test_magnetostatic_solve_out_of_iterations_keeps_the_state(case, precision):
+    p = {**case.params, "lambda100": 0.0, "lambda111": 0.0, "cg_maxit": 5}
+    sim = gspm.Simulation(case.mesh, p, local_demag=True, precision=precision)
+    sim.set_m(case.m0)
+    m0, u0, ud0 = sim.get_m(), sim.get_u(), sim.get_ud()
+    with pytest.raises(gspm.GspmError) as e:
+        sim.step(case.dt, 2)
+    st = e.value.stats
+    print(f"precision {precision}: status {e.value.status} failed step {st['failed_step']} ms iters {st['ms_iters']} "
+          f"mech iters {st['mech_iters']}", flush=True)
+    assert e.value.status == gspm.GSPM_E_NOCONV and st["failed_step"] == 0 and st["steps_done"] == 0
+    assert st["mech_iters"] == 0 and st["ms_iters"] >= 5
+    assert np.array_equal(sim.get_m(), m0) and np.array_equal(sim.get_u(), u0)
+    assert np.array_equal(sim.get_ud(), ud0)
+    sim.close()
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(p, local_demag=True)
+    orc.set_m(case.m0)
+    with pytest.raises(O.OracleError) as oe:
+        orc.step(case.dt, 2)
+    assert oe.value.code == gspm.GSPM_E_NOCONV
+    assert np.array_equal(orc.get_ud(), np.zeros(case.mesh.n_nodes))
