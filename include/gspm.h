@@ -17,7 +17,9 @@
  * unpreconditioned CG; the cross-product update and the unit-length
  * projection close the step.  Optionally (gspm_params.local_demag) each step
  * also solves the local magnetostatic potential U~ of Eq. (demag) in the weak
- * form (weak_demag) by CG and adds its field -grad U~ to the effective field.
+ * form (weak_demag) by CG and adds its field -grad U~ to the effective field,
+ * and (gspm_params.crystal_rot) the cubic crystal may be turned against the
+ * sample frame of the mesh as in App. D.
  *
  * Conventions shared by every entry point
  *   - Units are SI (metres, A/m, Pa, J/m^3, seconds).
