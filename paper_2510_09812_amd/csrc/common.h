@@ -200,6 +200,11 @@ void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, Matve
                       const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);
 // K^ms (Laplacian over all elements) on nc = 1 or 3 components, rows of the
 // pinned node zero; modes as above.  FP32: A' = K^ms / len_scale^3.
+// One launch of single-reduction CG on K^ms (one component), with the
+// buffer and scalar conventions of launch_elastic_cg.
+template <class T>
+void launch_ms_cg(const MeshView &mv, int k, bool last, const T *rin, const T *pin, const T *qin, T *rout, T *pout,
+                  T *qout, T *x, const CGScalars &cg, double tol, hipStream_t s);
 template <class T>
 void launch_ms_matvec(const MeshView &mv, int nc, MatvecMode mode, const T *in, T *out, const T *b, const T *r,
                       T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);

@@ -611,6 +611,49 @@ struct ElasticMatvecOp {
     }
 };
 
+// The prologue of single-reduction CG launch k (shared by the elastic and
+// magnetostatic operators, NV values per node): completes iteration k-1 from
+// the sums of launch k-1 (alpha, beta), records a stop (workgroup 0), and in
+// the last launch only adds the pending alpha p_{k-1} to x on the owned nodes.
+// Returns whether the launch has an iteration to run.
+template <int NV, class T>
+__device__ __forceinline__ bool sr_cg_prepare(const CGScalars &cg, int k, int last, double tol2, const MeshView &mv,
+                                              int b, int n, T *x, const T *pin, double &alpha, double &beta) {
+    alpha = beta = 0.0;
+    // a test recorded by an earlier launch (or by workgroup 0 of this one,
+    // which then leaves nothing to do either)
+    if (cg.done[0] != 0) return false;
+    if (k == 0) return !last;                // the start test ran in an earlier launch
+    const double *const src[5] = {cg.rr_at(0, k - 1), cg.pq_at(0, k - 1), cg.rq_at(k - 1), cg.qq_at(k - 1),
+                                  cg.bb_at(0)};
+    double t[5];
+    shard_totals<5>(src, t);
+    const double rrp = t[0];
+    const int stop = !isfinite(rrp) ? 2 : (rrp <= tol2 * t[4] ? 1 : 0);
+    if (stop) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            cg.done[0] = stop;
+            cg.iters[0] = k - 1;
+        }
+        return false;
+    }
+    alpha = rrp / t[1];
+    const double est = rrp - 2.0 * alpha * t[2] + alpha * alpha * t[3];
+    beta = (est > 0.0 ? est : 0.0) / rrp;
+    if (last) {
+        const int n0 = b * mv.nb, cnt = min(mv.nb, mv.n - n0);
+        const T a = static_cast<T>(alpha);
+        for (int i = threadIdx.x; i < cnt; i += kThreads)
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                const size_t o = static_cast<size_t>(c) * n + n0 + i;
+                x[o] += a * pin[o];
+            }
+        return false;
+    }
+    return true;
+}
+
 // One launch of single-reduction CG on the elastic system (one scalar set,
 // Sec. 2.5; the iterates of the two-launch form up to rounding).  Launch k
 // completes iteration k-1 from the sums of its epilogue, r.r, p.q, r.q and
@@ -641,39 +684,7 @@ struct ElasticCgOp {
     double coord_scale;
 
     __device__ bool prepare(const MeshView &mv, int b) {
-        alpha = beta = 0.0;
-        // a test recorded by an earlier launch (or by workgroup 0 of this one,
-        // which then leaves nothing to do either)
-        if (cg.done[0] != 0) return false;
-        if (k == 0) return !last;                // the start test ran in an earlier launch
-        const double *const src[5] = {cg.rr_at(0, k - 1), cg.pq_at(0, k - 1), cg.rq_at(k - 1), cg.qq_at(k - 1),
-                                      cg.bb_at(0)};
-        double t[5];
-        shard_totals<5>(src, t);
-        const double rrp = t[0];
-        const int stop = !isfinite(rrp) ? 2 : (rrp <= tol2 * t[4] ? 1 : 0);
-        if (stop) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                cg.done[0] = stop;
-                cg.iters[0] = k - 1;
-            }
-            return false;
-        }
-        alpha = rrp / t[1];
-        const double est = rrp - 2.0 * alpha * t[2] + alpha * alpha * t[3];
-        beta = (est > 0.0 ? est : 0.0) / rrp;
-        if (last) {
-            const int n0 = b * mv.nb, cnt = min(mv.nb, mv.n - n0);
-            const T a = static_cast<T>(alpha);
-            for (int i = threadIdx.x; i < cnt; i += kThreads)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const size_t o = static_cast<size_t>(c) * n + n0 + i;
-                    x[o] += a * pin[o];
-                }
-            return false;
-        }
-        return true;
+        return sr_cg_prepare<3>(cg, k, last, tol2, mv, b, n, x, pin, alpha, beta);
     }
 
     // the staged operand p_k at node g; owned nodes also store r_k and take
@@ -723,6 +734,78 @@ struct ElasticCgOp {
             }
         }
         // r_0.r_0 is already in slot 0 (the residual launch wrote it)
+        double *const dst[4] = {cg.pq_at(0, k), cg.rq_at(k), cg.qq_at(k), k == 0 ? nullptr : cg.rr_at(0, k)};
+        block_atomic_add_to<4>(part, dst);
+    }
+};
+
+// One launch of single-reduction CG on K^ms (Eq. weak_demag: the Laplacian
+// over all elements, one scalar component, the pinned node's rows zero), with
+// the control of ElasticCgOp: the direction and the residual formed in the
+// staging, q = K^ms p and the four sums p.q, r.q, q.q, r.r in the epilogue.
+template <class T>
+struct MsCgOp {
+    static constexpr bool kMagneticOnly = false;
+    const T *rin, *pin, *qin;     // r_{k-1}, p_{k-1}, q_{k-1} (rin = r_0 at k = 0)
+    T *rout, *pout, *qout;        // r_k, p_k, q_k
+    T *x;
+    CGScalars cg;
+    int k, n, last;
+    double tol2;
+    T eps;                        // 1 (FP64) or 1 / len_scale^2 (FP32 on scaled coordinates)
+    double alpha, beta;
+    double coord_scale;
+
+    __device__ bool prepare(const MeshView &mv, int b) {
+        return sr_cg_prepare<1>(cg, k, last, tol2, mv, b, n, x, pin, alpha, beta);
+    }
+
+    __device__ __forceinline__ void fetch(int g, T (&v)[1], bool owned) const {
+        if (k == 0) {
+            v[0] = rin[g];
+            return;
+        }
+        const T a = static_cast<T>(alpha), bt = static_cast<T>(beta);
+        const T pold = pin[g];
+        const T rk = rin[g] - a * qin[g];
+        v[0] = rk + bt * pold;
+        if (owned) {
+            rout[g] = rk;
+            x[g] += a * pold;
+        }
+    }
+
+    // V grad(lambda_i) . grad(u_h) = w c_i . (sum_k (u_k - u_0) c_k)
+    __device__ __forceinline__ void element_raw(const T (&f)[4][1], const RawGeo<T> &R, T (&y)[4][1]) const {
+        const T ev = eps * R.w;
+        const T d1 = f[1][0] - f[0][0], d2 = f[2][0] - f[0][0], d3 = f[3][0] - f[0][0];
+        T gp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gp[a] = d1 * R.c[1][a] + d2 * R.c[2][a] + d3 * R.c[3][a];
+        T t[4];
+#pragma unroll
+        for (int j = 1; j < 4; ++j) t[j] = R.c[j][0] * gp[0] + R.c[j][1] * gp[1] + R.c[j][2] * gp[2];
+        t[0] = -(t[1] + t[2] + t[3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) y[j][0] = ev * t[j];
+    }
+
+    template <int NF>
+    __device__ void finish(const MeshView &mv, const Staged<T, 1, NF> &st, int n0, int cnt) const {
+        double part[4] = {0.0, 0.0, 0.0, 0.0};   // p.q, r.q, q.q, r.r
+        const T *rk = k == 0 ? rin : rout;
+        for (int i = threadIdx.x; i < cnt; i += kThreads) {
+            const int node = n0 + i;
+            const T q = node == mv.p0 ? T(0) : static_cast<T>(st.acc[i]);
+            const T pv = st.fld(0, i);
+            pout[node] = pv;
+            qout[node] = q;
+            const double rv = static_cast<double>(rk[node]);
+            part[0] += static_cast<double>(pv) * q;
+            part[1] += rv * q;
+            part[2] += static_cast<double>(q) * q;
+            part[3] += rv * rv;
+        }
         double *const dst[4] = {cg.pq_at(0, k), cg.rq_at(k), cg.qq_at(k), k == 0 ? nullptr : cg.rr_at(0, k)};
         block_atomic_add_to<4>(part, dst);
     }
@@ -1407,6 +1490,21 @@ void launch_ms_matvec(const MeshView &mv, int nc, MatvecMode mode, const T *in, 
         run_strip<T, 3, 3>(mv, GsMatvecOp<T, 3, true>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0},
                                                        {0.0, 0.0, 0.0}, sc}, s);
 }
+
+template <class T>
+void launch_ms_cg(const MeshView &mv, int k, bool last, const T *rin, const T *pin, const T *qin, T *rout, T *pout,
+                  T *qout, T *x, const CGScalars &cg, double tol, hipStream_t s) {
+    const bool nd = sizeof(T) == sizeof(float);
+    const double sc = nd ? 1.0 / mv.len_scale : 1.0;
+    MsCgOp<T> op{rin, pin, qin, rout, pout, qout, x, cg, k, mv.n, last ? 1 : 0, tol * tol, static_cast<T>(sc * sc),
+                 0.0, 0.0, sc};
+    run_strip<T, 1, 1>(mv, op, s);
+}
+
+template void launch_ms_cg<double>(const MeshView &, int, bool, const double *, const double *, const double *,
+                                   double *, double *, double *, double *, const CGScalars &, double, hipStream_t);
+template void launch_ms_cg<float>(const MeshView &, int, bool, const float *, const float *, const float *, float *,
+                                  float *, float *, float *, const CGScalars &, double, hipStream_t);
 
 template void launch_ms_matvec<double>(const MeshView &, int, MatvecMode, const double *, double *, const double *,
                                        const double *, double *, const CGScalars &, int, double, hipStream_t);

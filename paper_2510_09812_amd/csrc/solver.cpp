@@ -299,14 +299,34 @@ CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, doub
     });
 }
 
-// K^ms x = b (Eq. weak_demag): the GS solves' two-launch CG on the pinned
-// all-element Laplacian.  The pinned node has b = 0 and x = 0, and its rows
-// of K^ms are zero, so it stays zero.
+// K^ms x = b (Eq. weak_demag) on the pinned all-element Laplacian.  The
+// pinned node has b = 0 and x = 0, and its rows of K^ms are zero, so it stays
+// zero.  One component (the step's solve) runs single-reduction CG, one fused
+// launch per iteration as the elastic solve; several (gspm_solve) run the GS
+// solves' two-launch form with per-component scalars.
 CgResult cg_ms(gspm_ctx *c, int nc, double *x, const double *b, double tol, int maxit, SolveKind kind) {
     hipStream_t s = c->stream;
     auto resid = [&]() {
         launch_ms_matvec<double>(c->mv, nc, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
     };
+    if (nc == 1) {
+        auto fused = [&](auto *R0, auto *R1, auto *P0, auto *P1, auto *Q0, auto *Q1, auto *xv, const CGScalars &cg,
+                         double t) {
+            return [=](int k, bool last) {
+                auto *R = k & 1 ? R1 : R0, *P = k & 1 ? P1 : P0, *Q = k & 1 ? Q1 : Q0;
+                auto *Rp = k & 1 ? R0 : R1, *Pp = k & 1 ? P0 : P1, *Qp = k & 1 ? Q0 : Q1;
+                if (k == 0) Rp = R0;
+                launch_ms_cg(c->mv, k, last, Rp, Pp, Qp, R, P, Q, xv, cg, t, s);
+            };
+        };
+        auto &d = c->d;
+        if (c->precision == GSPM_MIXED) {
+            const double ls = c->mv.len_scale;
+            return cg_mixed(c, 1, false, x, tol, maxit, kind, 1.0 / (ls * ls * ls), resid,
+                            fused(d.r32, d.r32b, d.p32, d.p32b, d.q32, d.q32b, d.x32, c->cg_in, 1.0));
+        }
+        return cg_fp64(c, 1, false, x, tol, maxit, kind, resid, fused(d.r, d.r2, d.p, d.p2, d.q, d.q2, x, c->cg, tol));
+    }
     if (c->precision == GSPM_MIXED) {
         float *P[2] = {c->d.p32, c->d.p32b};
         const double ls = c->mv.len_scale, scale = 1.0 / (ls * ls * ls);
