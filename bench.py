@@ -80,15 +80,15 @@ def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float) ->
     return mech_iters * mech + gs_iters * gs + rhs + nodes
 
 
-def traffic_from_profile(path: str):
-    """HBM bytes per launch of the path's fused elastic CG iteration from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel sources."""
+def traffic_from_profile(path: str, workload: str = "cube100_ellipsoids"):
+    """HBM bytes per launch of the path's kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources and on this workload."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash():
+    if t.get("kernel_hash") != kernel_hash() or not t.get("workload", "").startswith(workload + " "):
         return None
     return t.get(path, {}).get("bytes_per_launch")
 
@@ -242,7 +242,7 @@ def main() -> int:
         achieved = mb / avg_s / 1e9
         kname = "k_strip<float,3,3,ElasticCgOp>" if mixed else "k_strip<double,3,3,ElasticCgOp>"
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("mixed" if mixed else "fp64"),
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("mixed" if mixed else "fp64", case.name),
                     "kernel": kname, "bytes_per_launch": mb,
                     "avg_launch_us": avg_s * 1e6, "launches": pst["matvec_launches"],
                     "timing": f"kernel start/end events (hipExtLaunchKernelGGL) on every elastic CG iteration of "
@@ -277,7 +277,7 @@ def main() -> int:
         t = paths["mixed+local_demag"]["ms_matvec_ms"] * 1e-3
         mb = ms_matvec_bytes(n, ne, 4)
         ms_roofline = {"bound": "hbm", "achieved": mb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": mb / t / 1e9 / HBM_PEAK_GBS, "traffic": traffic_from_profile("ms_mixed"),
+                       "frac": mb / t / 1e9 / HBM_PEAK_GBS, "traffic": traffic_from_profile("ms_mixed", case.name),
                        "kernel": "k_strip<float,1,1,GsMatvecOp<float,1,true>>", "bytes_per_launch": mb,
                        "avg_launch_us": t * 1e6,
                        "timing": "50 device-resident launches of y = K^ms x between HIP events on the library's stream"}
