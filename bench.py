@@ -134,8 +134,8 @@ def main() -> int:
                     help="first fill and sum a buffer of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "and not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU; sharding across GPUs is designed, not implemented",
+                          "n_gpus": args.gpus}))
         return 2
 
     import torch
