@@ -1,0 +1,45 @@
+"""Host logic of bench.py (no GPU): the algorithmic byte counts behind the
+roofline lines and the rule that counter traffic is reported only for the
+kernel sources and the workload it was measured on."""
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+N1M, NE1M = 970299, 5821794
+
+
+def test_algorithmic_bytes_at_the_1m_node_cube():
+    # connectivity 16 B per tet, FP64 coordinates 24 B per node, eight 3-vectors
+    assert bench.cg_iteration_bytes(N1M, NE1M, 8) == 16 * NE1M + 24 * N1M + 192 * N1M
+    assert abs(bench.cg_iteration_bytes(N1M, NE1M, 8) / 1e6 - 302.7) < 0.1
+    assert abs(bench.cg_iteration_bytes(N1M, NE1M, 4) / 1e6 - 209.6) < 0.1
+    assert abs(bench.ms_matvec_bytes(N1M, NE1M, 4) / 1e6 - 124.2) < 0.1
+
+
+def test_traffic_is_tied_to_sources_and_workload(tmp_path, monkeypatch):
+    with open(bench.TRAFFIC_FILE) as f:
+        t = json.load(f)
+    assert t["workload"].startswith("cube100_ellipsoids ")
+    fake = dict(t)
+    path = tmp_path / "traffic.json"
+    path.write_text(json.dumps(fake))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    current = fake["kernel_hash"] == bench.kernel_hash()
+    got = bench.traffic_from_profile("mixed")
+    assert (got == fake["mixed"]["bytes_per_launch"]) if current else got is None
+    assert bench.traffic_from_profile("mixed", "cube144_ellipsoids") is None
+    fake["kernel_hash"] = "0" * 16
+    path.write_text(json.dumps(fake))
+    assert bench.traffic_from_profile("mixed") is None
+
+
+def test_rotation_of_the_bench_path_is_app_d_frame():
+    R = bench.R111
+    assert np.allclose(R @ R.T, np.eye(3), atol=1e-15) and abs(np.linalg.det(R) - 1.0) < 1e-15
+    assert np.allclose(R[0], np.ones(3) / np.sqrt(3.0))
