@@ -21,6 +21,7 @@ _SRC = os.path.join(_HERE, "gspm_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OP_LAPLACE, OP_MASS, OP_GS, OP_ELASTIC, OP_LAPLACE_ALL, OP_MS = 0, 1, 2, 3, 4, 5
+SOLVE_ELASTIC_JACOBI = 6
 
 
 def build() -> str:

@@ -884,6 +884,52 @@ static int solve_elastic(const or_sim *s, const double *b, double *u, double tol
     return rc;
 }
 
+/* Jacobi-preconditioned CG on the elastic system (the preconditioning the
+ * paper leaves aside, Sec. 2.5): M^-1 = diag(K^mech)^-1 on the free DOFs, the
+ * same recurrence-residual stopping rule ||r|| <= tol ||b|| as plain CG. */
+static int solve_elastic_jacobi(const or_sim *s, const double *b_in, double *u, double tol, int maxit, int *iters) {
+    int len = 3 * s->n, rc = OR_OK, k = 0;
+    double *b = (double *)calloc((size_t)len, sizeof(double)), *r = (double *)malloc(sizeof(double) * (size_t)len);
+    double *z = (double *)malloc(sizeof(double) * (size_t)len), *p = (double *)malloc(sizeof(double) * (size_t)len);
+    double *q = (double *)malloc(sizeof(double) * (size_t)len), *minv = (double *)calloc((size_t)len, sizeof(double));
+    for (int i = 0; i < s->n; ++i) {
+        int self = find_col(s, i, i);
+        for (int a = 0; a < 3; ++a) {
+            int dof = i * 3 + a;
+            if (i == s->p0) { u[dof] = 0.0; continue; }
+            b[dof] = b_in[dof];
+            minv[dof] = 1.0 / s->Kmech[(size_t)self * 9 + a * 3 + a];
+        }
+    }
+    double bb = dot(b, b, len);
+    if (bb == 0.0) {
+        for (int i = 0; i < len; ++i) u[i] = 0.0;
+        goto done;
+    }
+    spmv_elastic(s, u, q);
+    for (int i = 0; i < len; ++i) { r[i] = b[i] - q[i]; z[i] = minv[i] * r[i]; p[i] = z[i]; }
+    for (int a = 0; a < 3; ++a) r[s->p0 * 3 + a] = z[s->p0 * 3 + a] = p[s->p0 * 3 + a] = 0.0;
+    double rr = dot(r, r, len), rz = dot(r, z, len), thr = tol * tol * bb;
+    while (rr > thr) {
+        if (k >= maxit) { rc = OR_E_NOCONV; break; }
+        spmv_elastic(s, p, q);
+        double alpha = rz / dot(p, q, len);
+        for (int i = 0; i < len; ++i) { u[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+        ++k;
+        rr = dot(r, r, len);
+        if (!isfinite(rr)) { rc = OR_E_NONFINITE; break; }
+        if (rr <= thr) break;
+        for (int i = 0; i < len; ++i) z[i] = minv[i] * r[i];
+        double rz_new = dot(r, z, len), beta = rz_new / rz;
+        for (int i = 0; i < len; ++i) p[i] = z[i] + beta * p[i];
+        rz = rz_new;
+    }
+done:
+    *iters = k;
+    free(b); free(r); free(z); free(p); free(q); free(minv);
+    return rc;
+}
+
 /* One scalar GS solve (eps K + M) x = b on the magnetic nodes (Eq. weak_GS). */
 static int solve_gs(const or_sim *s, double eps, const double *b, double *x, double tol, int maxit, int *iters) {
     uint8_t *fixed = (uint8_t *)malloc((size_t)s->n);
@@ -895,9 +941,9 @@ static int solve_gs(const or_sim *s, double eps, const double *b, double *x, dou
 
 int or_solve(const or_sim *s, int32_t which, double eps, const double *b, double *x, double tol, int32_t maxit,
              int32_t *iters) {
-    if (which == 3) {
+    if (which == 3 || which == 6) {
         if (!s->have_params) return OR_E_STATE;
-        int it = 0, rc = solve_elastic(s, b, x, tol, maxit, &it);
+        int it = 0, rc = which == 3 ? solve_elastic(s, b, x, tol, maxit, &it) : solve_elastic_jacobi(s, b, x, tol, maxit, &it);
         *iters = it;
         return rc;
     }

@@ -76,7 +76,8 @@ void or_get_ud(const or_sim *s, double *ud);
 int or_apply(const or_sim *s, int32_t which, double eps, const double *x, double *y);
 
 /* CG on operator `which` (2, 3 or 5 above), unique-node order; x holds x0 on
- * entry.  Components of the GS and K^ms operators are solved independently. */
+ * entry.  Components of the GS and K^ms operators are solved independently.
+ * which = 6: the elastic system (3) by Jacobi-preconditioned CG. */
 int or_solve(const or_sim *s, int32_t which, double eps, const double *b, double *x, double tol,
              int32_t maxit, int32_t *iters);
 
