@@ -297,7 +297,7 @@ class Oracle:
         return max_steps, False
 
     def sweep(self, params: dict, dt: float, dm_tol: float, max_steps: int, hext, sigma_ext=None,
-              stop_on_reversal: bool = False, precession: bool = True):
+              stop_on_reversal: bool = False, precession: bool = True, local_demag: bool = False):
         """Sec. 3.3 hysteresis protocol: for each applied field (and stress),
         relax and record the cell-averaged m; optionally stop after the first
         point whose mbar points against the first field.  Returns (mbar list,
@@ -307,7 +307,7 @@ class Oracle:
         mbars, steps = [], []
         for k in range(hext.shape[0]):
             sig = (0.0,) * 6 if sigma_ext is None else tuple(np.asarray(sigma_ext, dtype=np.float64).reshape(-1, 6)[k])
-            self.set_params(params, hext=tuple(hext[k]), sigma_ext=sig, precession=precession)
+            self.set_params(params, hext=tuple(hext[k]), sigma_ext=sig, precession=precession, local_demag=local_demag)
             n, ok = self.relax(dt, dm_tol, max_steps)
             steps.append(n)
             if not ok:

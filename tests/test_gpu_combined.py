@@ -9,6 +9,8 @@
     (the step commits by pointer swap only after every solve converged).
     Magnetostriction is switched off there so that the elastic solve has a
     zero right-hand side and the magnetostatic solve is the one that fails.
+  - a field sweep (the hysteresis driver) with both optional terms takes the
+    oracle's steps at every point.
 Workload: a ragged 9-node cube (512 unique nodes) with a spherical inclusion.
 """
 import numpy as np
@@ -88,3 +90,29 @@ def test_magnetostatic_solve_out_of_iterations_keeps_the_state(case, precision):
         orc.step(case.dt, 2)
     assert oe.value.code == gspm.GSPM_E_NOCONV
     assert np.array_equal(orc.get_ud(), np.zeros(case.mesh.n_nodes))
+
+
+def test_field_sweep_with_the_optional_terms_matches_oracle():
+    """The hysteresis driver keeps the optional terms of the parameter block:
+    a two-point field sweep with the local potential and the rotated crystal
+    takes the oracle's steps at every point, with the same averages to 1e-8.
+    Workload: a ragged 8-node cube (343 unique nodes) with a spherical
+    inclusion, no far-field term, dt = 10 ps, threshold 1e-5."""
+    mesh_case = w.small_cube(8, seed=71, L=8e-8, jitter=0.15, sphere=0.3)
+    p = {**mesh_case.params, "Nd": np.zeros(9), "crystal_rot": R111}
+    m0 = np.zeros((mesh_case.mesh.n_nodes, 3)); m0[:, 0] = 1.0
+    rng = np.random.default_rng(3)
+    m0 += 0.02 * mesh_case.mesh.per_site(rng.standard_normal((mesh_case.mesh.n_sites, 3)))
+    H = [(2e4, 0.0, 0.0), (-1e4, 0.0, 0.0)]
+    sim = gspm.Simulation(mesh_case.mesh, p, hext=H[0], local_demag=True)
+    sim.set_m(m0)
+    out = sim.sweep(1e-11, 1e-5, 3000, H)
+    orc = O.Oracle.from_mesh(mesh_case.mesh)
+    orc.set_params(p, hext=H[0], local_demag=True)
+    orc.set_m(m0)
+    mb, steps = orc.sweep(p, 1e-11, 1e-5, 3000, H, local_demag=True)
+    print(f"sweep with the optional terms: gpu steps {out['steps'].tolist()} oracle {steps}; "
+          f"mbar diff {np.abs(out['mbar'] - np.array(mb)).max():.2e}", flush=True)
+    assert out["points_done"] == 2 and out["steps"].tolist() == steps
+    assert np.abs(out["mbar"] - np.array(mb)).max() < 1e-8
+    sim.close()
