@@ -4,7 +4,8 @@ decided not to build it on the GPU.
 
   - it converges to the same solution as a dense solve and as plain CG;
   - on the regular Kuhn lattice the diagonal of K^mech is one constant, so the
-    preconditioned iteration is plain CG rescaled: the same iteration count;
+    preconditioned iteration is plain CG rescaled: the same iteration count
+    (up to one iteration where rounding moves the stopping test's crossing);
   - on a jittered 13,824-node mesh with a spherical inclusion (the bench's
     lattice spacing), Jacobi saves only a few percent of the iterations.
 """
@@ -48,10 +49,15 @@ def test_constant_diagonal_gives_plain_cg():
     orc = O.Oracle.from_mesh(case.mesh)
     orc.set_params(case.params)
     b = _rhs(orc, case, 2)
-    xj, itj = orc.solve(O.SOLVE_ELASTIC_JACOBI, b, tol=1e-10)
-    xc, itc = orc.solve(O.OP_ELASTIC, b, tol=1e-10)
-    assert itj == itc
-    assert np.abs(xj - xc).max() < 1e-8 * np.abs(xc).max()
+    # In exact arithmetic the two iterations coincide.  The stopping test
+    # compares a residual norm with a threshold, so rounding (the OpenMP
+    # reduction order depends on the runtime loaded) can move the crossing by
+    # one iteration; a wrong diagonal or scaling moves it by many.
+    for tol in (1e-6, 1e-8, 1e-10, 1e-12):
+        xj, itj = orc.solve(O.SOLVE_ELASTIC_JACOBI, b, tol=tol)
+        xc, itc = orc.solve(O.OP_ELASTIC, b, tol=tol)
+        assert abs(itj - itc) <= 1, (tol, itj, itc)
+        assert np.abs(xj - xc).max() < 10 * tol * np.abs(xc).max()
 
 
 def test_jacobi_saves_little_on_the_bench_lattice():
