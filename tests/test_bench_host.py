@@ -43,3 +43,12 @@ def test_rotation_of_the_bench_path_is_app_d_frame():
     R = bench.R111
     assert np.allclose(R @ R.T, np.eye(3), atol=1e-15) and abs(np.linalg.det(R) - 1.0) < 1e-15
     assert np.allclose(R[0], np.ones(3) / np.sqrt(3.0))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
