@@ -627,3 +627,128 @@ def test_field_rhs_sees_only_symmetric_strain():
     assert np.abs(res["rot"] - res["zero"]).max() < 1e-10 * scale
     assert np.abs(res["lin"] - res["stress"]).max() < 1e-9 * scale
     assert np.abs(res["lin"] - res["zero"]).max() > 1e-6 * scale
+
+
+# ------------------------------------------------- energy terms, dm_avg
+
+def _e0_closed(p, m):
+    """App. A: E0 = (3/2)[lambda100 (m_i^2 - 1/3) on the diagonal, lambda111
+    m_i m_j off it], order xx yy zz yz xz xy."""
+    m = np.asarray(m, float)
+    l1, l2 = p["lambda100"], p["lambda111"]
+    return 1.5 * np.array([l1 * (m[0] ** 2 - 1 / 3), l1 * (m[1] ** 2 - 1 / 3), l1 * (m[2] ** 2 - 1 / 3),
+                           l2 * m[1] * m[2], l2 * m[0] * m[2], l2 * m[0] * m[1]])
+
+
+def _cubic_compliance_closed(p, s):
+    """Tensor strain of a stress for cubic C in closed form: normal part
+    s11 sigma_ii + s12 (sum of the other two), s11 = (c11 + c12) / D,
+    s12 = -c12 / D, D = (c11 - c12)(c11 + 2 c12); shear sigma_ij / (2 c44)."""
+    c11, c12, c44 = p["c11"], p["c12"], p["c44"]
+    D = (c11 - c12) * (c11 + 2 * c12)
+    s11, s12 = (c11 + c12) / D, -c12 / D
+    s = np.asarray(s, float)
+    tr = s[:3].sum()
+    return np.concatenate([s11 * s[:3] + s12 * (tr - s[:3]), s[3:] / (2 * c44)])
+
+
+def _tensor_contract(a6, b6):
+    """a : b of two symmetric tensors in xx yy zz yz xz xy order."""
+    return a6[:3] @ b6[:3] + 2.0 * (a6[3:] @ b6[3:])
+
+
+@pytest.mark.parametrize("direction", ["100", "111", "1-23"])
+def test_energy_terms_closed_forms_for_uniform_m_with_inclusion(direction):
+    """Eq. (MicromagneticsEnergy) with R16's quadrature on a uniform state:
+    the vertex rule integrates constants exactly, so with magnetic volume
+    fraction f the anisotropy is f kappa1 (m1^2 m2^2 + ...) (0 along [100],
+    kappa1/3 along [111]), the Zeeman term -mu0 Ms f H.m, the far field
+    (mu0 Ms^2 / 2) mbar.N mbar with mbar = f m, the stress work -sigma:Ebar
+    with Ebar = f E0(m) + C^-1 sigma, and exchange 0."""
+    case = w.small_cube(8, seed=61, L=7e-8, jitter=0.15, sphere=0.3, shuffle=True)
+    x = case.mesh.xyz[case.mesh.tets]
+    vol = np.abs(np.linalg.det(x[:, 1:] - x[:, :1])) / 6.0
+    f = vol[case.mesh.tags != 0].sum() / vol.sum()
+    assert 0.5 < f < 0.95
+    d = {"100": [1.0, 0, 0], "111": [1.0, 1.0, 1.0], "1-23": [1.0, -2.0, 3.0]}[direction]
+    d = np.asarray(d) / np.linalg.norm(d)
+    p = dict(MAT)
+    N = np.diag([0.2, 0.3, 0.5]); N[0, 1] = N[1, 0] = 0.05
+    p["Nd"] = N.reshape(9)
+    H = np.array([3e4, -1e4, 2e4])
+    sigma = np.array([4e7, -1e7, 2e7, 5e6, -3e6, 1e7])
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(p, hext=H, sigma_ext=sigma)
+    orc.set_m(np.tile(d, (case.mesh.n_nodes, 1)))
+    e = orc.energies()
+    Ms, mu0, K1 = p["Ms"], p["mu0"], p["K1"]
+    anis = f * K1 * (d[0] ** 2 * d[1] ** 2 + d[1] ** 2 * d[2] ** 2 + d[2] ** 2 * d[0] ** 2)
+    if direction == "100":
+        assert anis == 0.0
+    if direction == "111":
+        assert np.isclose(anis, f * K1 / 3, rtol=1e-14)
+    mbar = f * d
+    ebar = f * _e0_closed(p, d) + _cubic_compliance_closed(p, sigma)
+    scale = K1
+    assert abs(e["exchange"]) < 1e-12 * scale
+    assert abs(e["anisotropy"] - anis) < 1e-12 * scale
+    assert abs(e["zeeman"] - (-mu0 * Ms * f * H @ d)) < 1e-12 * abs(mu0 * Ms * H @ d)
+    assert abs(e["demag_far"] - 0.5 * mu0 * Ms ** 2 * mbar @ N @ mbar) < 1e-12 * mu0 * Ms ** 2
+    work = -_tensor_contract(sigma, ebar)
+    assert abs(e["stress"] - work) < 1e-10 * abs(work)
+    m_av, e_av = orc.averages()
+    assert np.allclose(m_av, mbar, rtol=1e-12, atol=1e-15)
+    assert np.allclose(e_av, ebar, rtol=1e-10, atol=1e-16)
+    parts = sum(e[k] for k in ("exchange", "anisotropy", "zeeman", "magnetoelastic", "stress", "demag_far"))
+    assert abs(e["total"] - parts) < 1e-12 * abs(e["total"])
+
+
+@pytest.mark.parametrize("direction", ["100", "111"])
+def test_magnetoelastic_energy_of_uniform_state_under_stress(direction):
+    """All-magnetic cell, uniform m, applied stress: E0 is uniform, so the
+    periodic displacement vanishes (Eq. elasticity has a zero right-hand
+    side), E - E0 = C^-1 sigma everywhere and the magnetoelastic density is
+    (1/2) sigma : C^-1 sigma; a rigid translation of u changes nothing."""
+    case = w.small_cube(6, seed=62, L=5e-8, jitter=0.15, shuffle=True)
+    d = np.array([1.0, 0, 0]) if direction == "100" else np.ones(3) / np.sqrt(3)
+    sigma = np.array([-3e7, 1e7, 2e7, -4e6, 6e6, 2e6])
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(MAT, sigma_ext=sigma)
+    orc.set_m(np.tile(d, (case.mesh.n_nodes, 1)))
+    b = orc.elastic_rhs()
+    assert np.abs(b).max() < 1e-12 * MAT["c11"] * MAT["lambda100"] * (5e-8 / 5) ** 2
+    eps = _cubic_compliance_closed(MAT, sigma)
+    me = 0.5 * _tensor_contract(sigma, eps)
+    e = orc.energies()
+    assert abs(e["magnetoelastic"] - me) < 1e-11 * me
+    orc.set_u(np.tile([3e-10, -1e-10, 2e-10], (case.mesh.n_nodes, 1)))
+    assert abs(orc.energies()["magnetoelastic"] - me) < 1e-11 * me
+    # the step keeps u = 0 up to the CG tolerance
+    orc.set_u(np.zeros((case.mesh.n_nodes, 3)))
+    orc.step(1e-12, 1)
+    u = orc.get_u()
+    assert np.abs(u - u.mean(0)).max() < 1e-12 * MAT["lambda100"] * 5e-8
+
+
+def test_dm_avg_is_the_mean_over_magnetic_nodes():
+    """Sec. 3.2's convergence measure, the mean over the magnetic nodes of
+    |m^{n+1} - m^n|: a uniform macrospin (no magnetostriction, so the
+    inclusion exerts no strain field) moves every magnetic node by the same
+    chord, so dm_avg must equal that chord even though some nodes lie inside
+    the inclusion only (and stay at zero)."""
+    case = w.small_cube(7, seed=63, L=6e-8, jitter=0.15, sphere=0.35, shuffle=True)
+    p = dict(MAT); p["lambda100"] = 0.0; p["lambda111"] = 0.0; p["cg_tol"] = 1e-12
+    orc = O.Oracle.from_mesh(case.mesh)
+    mag = orc.lumped_weights() > 0
+    assert (~mag).sum() > 0
+    mag_user = mag[orc.node_map()]
+    d0 = np.array([1.0, 0.4, -0.3]); d0 /= np.linalg.norm(d0)
+    orc.set_params(p, hext=(0.0, 0.2 * p["Ms"], 0.0))
+    orc.set_m(np.tile(d0, (case.mesh.n_nodes, 1)))
+    st = orc.step(3e-12, 1)
+    m1 = orc.get_m()
+    assert np.ptp(m1[mag_user], axis=0).max() < 1e-13
+    assert np.abs(m1[~mag_user]).max() == 0.0
+    chord = np.linalg.norm(m1[mag_user][0] - d0)
+    assert chord > 1e-3
+    assert abs(st["dm_avg"] - chord) < 1e-12 * chord
