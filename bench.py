@@ -50,13 +50,14 @@ def kernel_hash() -> str:
 
 
 def cg_iteration_bytes(n_nodes: int, n_tets: int, real_bytes: int = 8) -> int:
-    """Algorithmic bytes of one fused elastic CG iteration (one launch):
-    connectivity (4 x int32 per tetrahedron), FP64 coordinates, and eight
-    vectors of 3 values per node in the working precision, each read or
-    written once: r, p, q of the previous iteration and x read; r, p, q of
-    this iteration and x written.  302.7 MB (FP64) and 209.6 MB (FP32
-    vectors) at 1M nodes."""
-    return 16 * n_tets + 24 * n_nodes + 8 * 3 * real_bytes * n_nodes
+    """Algorithmic bytes of one elastic CG iteration (one fused launch), the
+    method's count: connectivity (4 x int32 per tetrahedron), FP64
+    coordinates, and nine passes over 3-vectors in the working precision
+    (p read and Ap written by the matvec; x, r, p, Ap read or written by the
+    CG updates: seven passes).  336 B per node in FP64 and 228 B with FP32
+    vectors at six tetrahedra per node; 326.0 MB (FP64) and 221.2 MB (FP32)
+    at the 1M-node cube."""
+    return 16 * n_tets + 24 * n_nodes + 9 * 3 * real_bytes * n_nodes
 
 
 def ms_matvec_bytes(n_nodes: int, n_tets: int, real_bytes: int = 4) -> int:
@@ -66,18 +67,37 @@ def ms_matvec_bytes(n_nodes: int, n_tets: int, real_bytes: int = 4) -> int:
     return 16 * n_tets + 24 * n_nodes + 2 * real_bytes * n_nodes
 
 
-def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float) -> float:
-    """Algorithmic bytes of one step (FP64): per elastic CG iteration the
-    fused launch (cg_iteration_bytes); per scalar GS CG iteration the
-    connectivity and coordinates plus 8 scalar vector passes; three element
-    right-hand-side passes (connectivity, coordinates, m, u, b) and the node
-    passes (averages, updates, projection)."""
-    conn = 16 * n_tets
-    mech = cg_iteration_bytes(n_nodes, n_tets, 8)
-    gs = conn + 24 * n_nodes + 8 * n_nodes * 9
-    rhs = 3 * (conn + 24 * n_nodes * 4)
-    nodes = 24 * n_nodes * 12
-    return mech_iters * mech + gs_iters * gs + rhs + nodes
+def gs_iteration_bytes(n_nodes: int, n_tets: int, real_bytes: int = 8) -> int:
+    """One scalar GS CG iteration: connectivity, coordinates and nine scalar
+    vector passes (192 B per node in FP64, 156 B in FP32)."""
+    return 16 * n_tets + 24 * n_nodes + 9 * real_bytes * n_nodes
+
+
+def refinement_bytes(n_nodes: int, n_tets: int, components: int) -> int:
+    """One FP64 refinement of the mixed form on `components` vector
+    components: the FP64 residual r = b - A x (connectivity, coordinates, x
+    and b read, r written), its conversion to FP32 (r read, r32 written) and
+    x += d (x read and written, d read)."""
+    c = components
+    return 16 * n_tets + 24 * n_nodes + c * n_nodes * (3 * 8 + (8 + 4) + (8 + 8 + 4))
+
+
+def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float, real_bytes: int = 8,
+               mech_refinements: float = 0.0, other_refinements: float = 0.0) -> float:
+    """Algorithmic bytes of one step: each elastic CG iteration and each
+    scalar GS CG iteration in the precision its vectors use (real_bytes: 8 on
+    the FP64 path, 4 for the inner iterations of the mixed path), each FP64
+    refinement of the mixed path (elastic ones on three components, the
+    others priced as one scalar component, a lower bound), three element
+    right-hand-side passes of about 190 B per node and about 200 B per node
+    of node passes (averages, updates, projection)."""
+    mech = cg_iteration_bytes(n_nodes, n_tets, real_bytes)
+    gs = gs_iteration_bytes(n_nodes, n_tets, real_bytes)
+    rhs = 3 * (16 * n_tets + 24 * n_nodes * 4)
+    nodes = 200 * n_nodes
+    ref = mech_refinements * refinement_bytes(n_nodes, n_tets, 3) + other_refinements * refinement_bytes(
+        n_nodes, n_tets, 1)
+    return mech_iters * mech + gs_iters * gs + rhs + nodes + ref
 
 
 def traffic_from_profile(path: str, workload: str = "cube100_ellipsoids"):
@@ -93,21 +113,42 @@ def traffic_from_profile(path: str, workload: str = "cube100_ellipsoids"):
     return t.get(path, {}).get("bytes_per_launch")
 
 
-def cpu_baseline(case, sample_steps: int = 1) -> dict:
-    """The CPU oracle as it stands, on the same workload: assembly is excluded
-    (the paper times setup separately); `sample_steps` steps from the initial
-    state are timed."""
+def cpu_baseline(case, single_core_case=None) -> dict:
+    """The CPU oracle as it stands, built -O3 -march=native on this host, on
+    the same workload: assembly is excluded (the paper times setup
+    separately); one untimed step from the initial state warms the elastic
+    start (as the GPU paths' warm-up steps do), then one step is timed on all
+    the threads OpenMP gives the oracle.  With single_core_case, one more
+    warm-started step of that (smaller) workload is timed on one thread (its
+    untimed first step runs on all of them)."""
     import oracle
-    orc = oracle.Oracle.from_mesh(case.mesh)
-    orc.set_params(case.params, hext=case.hext)
-    orc.set_m(case.m0)
-    t0 = time.perf_counter()
-    st = orc.step(case.dt, sample_steps)
-    dt = time.perf_counter() - t0
-    return {"value": orc.n * sample_steps / dt, "unit": "node-steps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{sample_steps} step(s) of {case.name} from the initial state (elastic CG from u = 0, "
-                      f"{st['mech_iters']} elastic iterations), global matrix assembly excluded, {dt:.1f} s"}
+    oracle.select_native()
+
+    threads = oracle.num_threads()
+
+    def one(c, timed_threads):
+        orc = oracle.Oracle.from_mesh(c.mesh)
+        orc.set_params(c.params, hext=c.hext)
+        orc.set_m(c.m0)
+        orc.step(c.dt, 1)
+        oracle.set_num_threads(timed_threads)
+        t0 = time.perf_counter()
+        st = orc.step(c.dt, 1)
+        dt = time.perf_counter() - t0
+        oracle.set_num_threads(threads)
+        return orc.n / dt, dt, st
+
+    v, dt, st = one(case, threads)
+    out = {"value": v, "unit": "node-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"step 2 of {case.name} after one untimed step from the initial state "
+                     f"({st['mech_iters']} elastic CG iterations), {threads} OpenMP threads, oracle built "
+                     f"-O3 -march=native, global matrix assembly excluded, {dt:.1f} s"}
+    if single_core_case is not None:
+        v1, dt1, st1 = one(single_core_case, 1)
+        out["single_core"] = {"value": v1, "unit": "node-steps/s", "cores": 1,
+                              "sample": f"step 2 of {single_core_case.name} after one untimed step "
+                                        f"({st1['mech_iters']} elastic CG iterations), 1 thread, {dt1:.1f} s"}
+    return out
 
 
 def main() -> int:
@@ -117,7 +158,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cube100_ellipsoids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-single-core", action="store_true",
+                    help="skip the one-thread oracle sample on the 100k-node cube")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-launch timing steps of the elastic CG iteration")
     ap.add_argument("--profile-steps", type=int, default=2,
                     help="untimed steps after the timed region that time every elastic CG iteration kernel")
@@ -249,7 +291,9 @@ def main() -> int:
                               f"{args.profile_steps} untimed steps after the timed region"}
     mech_per_step = st["mech_iters"] / args.steps
     gs_per_step = st["gs_iters"] / args.steps
-    b_step = step_bytes(n, ne, mech_per_step, gs_per_step)
+    mref = st["mech_refinements"] / args.steps
+    b_step = step_bytes(n, ne, mech_per_step, gs_per_step, 4 if mixed else 8, mref,
+                        st["refinements"] / args.steps - mref)
     um = lambda u: u - u.mean(axis=0)
     per_path = {}
     for k, p in paths.items():
@@ -291,13 +335,16 @@ def main() -> int:
                    "mech_iters_per_step": mech_per_step, "gs_iters_per_step": gs_per_step},
         "roofline": roofline,
         "step_roofline": {"bytes_per_node_step": b_step / n, "roofline_node_steps_per_s": HBM_PEAK_GBS * 1e9 / b_step * n,
-                          "frac": value / (HBM_PEAK_GBS * 1e9 / b_step * n)},
+                          "frac": value / (HBM_PEAK_GBS * 1e9 / b_step * n),
+                          "inputs": {"mech_iters_per_step": mech_per_step, "gs_iters_per_step": gs_per_step,
+                                     "real_bytes": 4 if mixed else 8, "mech_refinements_per_step": mref,
+                                     "other_refinements_per_step": st["refinements"] / args.steps - mref}},
         "paths": per_path,
         "ms_roofline": ms_roofline,
     }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(case, None if args.no_single_core else w.cube47_sphere())
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

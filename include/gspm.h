@@ -142,6 +142,7 @@ typedef struct {
     double warm_coef[2];    /* last minimum-residual start: coefficients of the network increment and of the
                                previous displacement increment (0 if unused) */
     int64_t ms_iters;       /* local_demag: magnetostatic CG iterations (GSPM_MIXED: inner FP32), summed */
+    int64_t mech_refinements; /* GSPM_MIXED: the refinements of the elastic solves (part of `refinements`) */
 } gspm_step_stats;
 
 /* Create a context on opts->device (NULL opts: device 0, FP64, own stream).
@@ -189,21 +190,31 @@ gspm_status gspm_step(gspm_ctx *ctx, double dt, int32_t n_steps, gspm_step_stats
  * failing step returns its status with the state after the step before. */
 gspm_status gspm_relax(gspm_ctx *ctx, double dt, double dm_tol, int32_t max_steps, gspm_step_stats *stats);
 
+/* Flags of gspm_sweep. */
+#define GSPM_SWEEP_STOP_ON_REVERSAL 1u  /* end after the first point whose mbar has a non-positive component
+                                           along the first point's field (the coercive point) */
+#define GSPM_SWEEP_CONTINUE 2u          /* a point that does not relax within max_steps keeps its state after
+                                           max_steps, records mbar there with converged = 0, and the sweep
+                                           goes on (a fixed number of steps per point, as a field loop run
+                                           for a set length) */
+
 /* A field (and stress) sweep, as the hysteresis runs of Sec. 3.3 (the field
  * lowered in steps of 20 A/m until the magnetisation reverses; a uniaxial
  * stress as a second parameter): for point k = 0 .. n_points-1 the applied
  * field becomes hext[3k .. 3k+2] and, when sigma_ext is not NULL, the applied
  * stress sigma_ext[6k .. 6k+5] (the other parameters stay as set), the state
  * relaxes as in gspm_relax, and mbar[3k .. 3k+2] receives the cell-averaged
- * magnetisation and steps[k] the steps taken.  With stop_on_reversal nonzero
- * the sweep ends after the first point whose mbar has a non-positive
- * component along the first point's field (the coercive point; that field
- * must be nonzero).  points_done (nullable) receives the points completed.
- * The first point that fails to relax ends the sweep with its status (steps
- * filled for it, mbar not).  The parameters keep the last point's field. */
+ * magnetisation, steps[k] the steps taken and converged[k] (nullable) 1 if
+ * dm_avg fell below dm_tol.  flags: GSPM_SWEEP_STOP_ON_REVERSAL (that first
+ * field must be nonzero) and GSPM_SWEEP_CONTINUE, above; any other bit is
+ * GSPM_E_ARG.  points_done (nullable) receives the points completed.  Without
+ * GSPM_SWEEP_CONTINUE the first point that fails to relax ends the sweep with
+ * GSPM_E_NOCONV (steps and converged filled for it, mbar not); a failing step
+ * ends it with its status either way.  The parameters keep the last point's
+ * field. */
 gspm_status gspm_sweep(gspm_ctx *ctx, double dt, double dm_tol, int32_t max_steps, int32_t n_points,
-                       const double *hext, const double *sigma_ext, int32_t stop_on_reversal, double *mbar,
-                       int32_t *steps, int32_t *points_done);
+                       const double *hext, const double *sigma_ext, uint32_t flags, double *mbar,
+                       int32_t *steps, int32_t *converged, int32_t *points_done);
 
 /* Energy densities of Eq. (MicromagneticsEnergy) averaged over the cell
  * [J/m^3] at the current state: out = {exchange, anisotropy, zeeman,

@@ -24,13 +24,21 @@ OP_LAPLACE, OP_MASS, OP_GS, OP_ELASTIC, OP_LAPLACE_ALL, OP_MS = 0, 1, 2, 3, 4, 5
 SOLVE_ELASTIC_JACOBI = 6
 
 
-def build() -> str:
-    """Compile liboracle.so next to its source (plain gcc, no target-specific flags)."""
-    tmp = _LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
+_NATIVE_PATH = os.path.join(_HERE, "liboracle_native.so")
+
+
+def build(native: bool = False) -> str:
+    """Compile the oracle next to its source with plain gcc.  The default
+    library (tests, smoke check) carries no target-specific flags, so it runs
+    on any x86-64 host; native=True builds liboracle_native.so with
+    -O3 -march=native for the CPU-baseline timing on the host that runs it."""
+    path = _NATIVE_PATH if native else _LIB_PATH
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    tmp = path + ".tmp"
+    subprocess.check_call(["gcc"] + opt + ["-std=gnu11", "-fopenmp", "-fPIC", "-shared",
                            "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, path)
+    return path
 
 
 class _Params(ctypes.Structure):
@@ -47,15 +55,27 @@ class _Stats(ctypes.Structure):
 
 
 _lib = None
+_native = False
+
+
+def select_native() -> str:
+    """Use the -O3 -march=native build (compiled here, on this host) for every
+    oracle created from now on in this process; only before the first load."""
+    global _native
+    if _lib is not None and not _native:
+        raise RuntimeError("the portable oracle library is already loaded in this process")
+    _native = True
+    return build(native=True)
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    path = _NATIVE_PATH if _native else _LIB_PATH
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build(native=_native)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     dp = ctypes.POINTER(ctypes.c_double)
     lib.or_create.argtypes = [ctypes.POINTER(P), ctypes.c_int32, dp, ctypes.c_int32, P, P, dp, dp,
@@ -92,6 +112,7 @@ def _load():
     lib.or_energy_density_local.restype = ctypes.c_double
     lib.or_last_error.argtypes = [P]; lib.or_last_error.restype = ctypes.c_char_p
     lib.or_num_threads.argtypes = []; lib.or_num_threads.restype = ctypes.c_int32
+    lib.or_set_num_threads.argtypes = [ctypes.c_int32]
     _lib = lib
     return lib
 
@@ -138,6 +159,10 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    _load().or_set_num_threads(int(k))
 
 
 def demag_factors(a: float, b: float, c: float) -> np.ndarray:
@@ -297,26 +322,30 @@ class Oracle:
         return max_steps, False
 
     def sweep(self, params: dict, dt: float, dm_tol: float, max_steps: int, hext, sigma_ext=None,
-              stop_on_reversal: bool = False, precession: bool = True, local_demag: bool = False):
+              stop_on_reversal: bool = False, precession: bool = True, local_demag: bool = False,
+              keep_going: bool = False):
         """Sec. 3.3 hysteresis protocol: for each applied field (and stress),
         relax and record the cell-averaged m; optionally stop after the first
-        point whose mbar points against the first field.  Returns (mbar list,
-        steps list)."""
+        point whose mbar points against the first field.  A point that does
+        not relax within max_steps ends the sweep, or with keep_going is
+        recorded after max_steps and the sweep goes on.  Returns (mbar list,
+        steps list), and with keep_going also the per-point converged list."""
         hext = np.asarray(hext, dtype=np.float64).reshape(-1, 3)
         first = hext[0]
-        mbars, steps = [], []
+        mbars, steps, conv = [], [], []
         for k in range(hext.shape[0]):
             sig = (0.0,) * 6 if sigma_ext is None else tuple(np.asarray(sigma_ext, dtype=np.float64).reshape(-1, 6)[k])
             self.set_params(params, hext=tuple(hext[k]), sigma_ext=sig, precession=precession, local_demag=local_demag)
             n, ok = self.relax(dt, dm_tol, max_steps)
             steps.append(n)
-            if not ok:
+            conv.append(ok)
+            if not ok and not keep_going:
                 break
             mbar, _ = self.averages()
             mbars.append(mbar)
             if stop_on_reversal and float(np.dot(mbar, first)) <= 0.0:
                 break
-        return mbars, steps
+        return (mbars, steps, conv) if keep_going else (mbars, steps)
 
     def energies(self) -> dict:
         out = np.zeros(7)

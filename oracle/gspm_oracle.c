@@ -608,6 +608,15 @@ int32_t or_num_threads(void) {
 #endif
 }
 
+/* Thread count of the OpenMP loops (the CPU baseline reports a one-thread rate). */
+void or_set_num_threads(int32_t k) {
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 /* Elastic stiffness of Eq. (LHS): block (i,j)_ab = int E(phi_j e_b) : C E(phi_i e_a)
  * = V_e sum_qs C_aqbs d_q phi_i d_s phi_j on each element. */
 static void assemble_elastic(or_sim *s) {

@@ -115,6 +115,7 @@ int or_ms_energy(or_sim *s, const double *U, double *e);
 
 const char *or_last_error(const or_sim *s);
 int32_t or_num_threads(void);   /* OpenMP threads the oracle's loops use */
+void or_set_num_threads(int32_t k);   /* set them (k > 0) */
 
 #ifdef __cplusplus
 }

@@ -96,6 +96,7 @@ struct gspm_ctx {
     int32_t *h_flags = nullptr;   // pinned host mirror: 2 slots x (done[3], iters[3])
     double *h_mixed = nullptr;    // pinned staging of the mixed form's outer loop
     int64_t refinements = 0;      // outer FP64 residual evaluations that launched an inner solve
+    int64_t mech_refinements = 0; // the part of them in elastic solves
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
     std::vector<hipEvent_t> prof_ev;

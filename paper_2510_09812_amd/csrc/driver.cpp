@@ -20,6 +20,7 @@ void add_stats(gspm_step_stats &acc, const gspm_step_stats &s) {
     for (int q = 0; q < 8; ++q) acc.gs_iters_stage[q] += s.gs_iters_stage[q];
     acc.elapsed_ms += s.elapsed_ms;
     acc.refinements += s.refinements;
+    acc.mech_refinements += s.mech_refinements;
     acc.learned_starts += s.learned_starts;
     acc.minres_starts += s.minres_starts;
     acc.ms_iters += s.ms_iters;
@@ -68,12 +69,16 @@ gspm_status gspm_relax(gspm_ctx *c, double dt, double dm_tol, int32_t max_steps,
 }
 
 gspm_status gspm_sweep(gspm_ctx *c, double dt, double dm_tol, int32_t max_steps, int32_t n_points,
-                       const double *hext, const double *sigma_ext, int32_t stop_on_reversal, double *mbar,
-                       int32_t *steps, int32_t *points_done) {
+                       const double *hext, const double *sigma_ext, uint32_t flags, double *mbar,
+                       int32_t *steps, int32_t *converged, int32_t *points_done) {
     if (!c) return GSPM_E_ARG;
     if (points_done) *points_done = 0;
     if (!hext || !mbar || !steps || n_points <= 0) {
         c->err = "sweep: hext, mbar and steps are required and n_points must be positive";
+        return GSPM_E_ARG;
+    }
+    if (flags & ~(GSPM_SWEEP_STOP_ON_REVERSAL | GSPM_SWEEP_CONTINUE)) {
+        c->err = "sweep: unknown flag";
         return GSPM_E_ARG;
     }
     if (!c->have_mesh || !c->have_params || !c->have_m) {
@@ -84,6 +89,7 @@ gspm_status gspm_sweep(gspm_ctx *c, double dt, double dm_tol, int32_t max_steps,
         c->err = "sweep: dt and dm_tol must be positive and finite, max_steps positive";
         return GSPM_E_ARG;
     }
+    const bool stop_on_reversal = flags & GSPM_SWEEP_STOP_ON_REVERSAL, keep_going = flags & GSPM_SWEEP_CONTINUE;
     // the reversal test looks along the first point's field
     double dir[3] = {hext[0], hext[1], hext[2]};
     const double dn = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
@@ -101,10 +107,13 @@ gspm_status gspm_sweep(gspm_ctx *c, double dt, double dm_tol, int32_t max_steps,
         gspm_step_stats st;
         rc = gspm_relax(c, dt, dm_tol, max_steps, &st);
         steps[k] = st.steps_done;
-        if (rc) return rc;
+        if (converged) converged[k] = rc == GSPM_OK;
+        // a point that ran out of steps is recorded and the sweep goes on only
+        // when asked to; a failing step (failed_step set) always ends it
+        if (rc && !(rc == GSPM_E_NOCONV && keep_going && st.failed_step < 0)) return rc;
         double eb[6];
-        rc = gspm_averages(c, mbar + 3 * k, eb);
-        if (rc) return rc;
+        gspm_status ra = gspm_averages(c, mbar + 3 * k, eb);
+        if (ra) return ra;
         if (points_done) *points_done = k + 1;
         const double along = mbar[3 * k] * dir[0] + mbar[3 * k + 1] * dir[1] + mbar[3 * k + 2] * dir[2];
         if (stop_on_reversal && along <= 0.0) break;

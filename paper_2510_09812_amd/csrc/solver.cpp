@@ -1,15 +1,20 @@
 // CG driver and the GSPM step sequence (host side; all arithmetic runs in
 // the kernels).
 //
-// CG runs without a host round trip per iteration.  Each iteration is two
-// launches: the matvec, whose staging forms the new direction
-// p_k = r_k + beta_k p_{k-1} after testing ||r_k|| on the device, with p.Ap
-// fused into its epilogue; and the x/r update with r.r fused.  Directions are
-// double-buffered (a block reads the previous direction at its halo nodes
-// while other blocks write the new one).  Convergence is decided on the device
-// and a converged solve turns the remaining launches into immediate exits.  The host
-// enqueues iterations in batches and reads the convergence flags of the
-// previous batch while the next one runs, so the device never waits for it.
+// CG runs without a host round trip per iteration.  The elastic solve and the
+// step's magnetostatic solve run single-reduction CG: one fused launch per
+// iteration, which completes the previous iteration (its scalars summed in the
+// prologue), forms r, p and x in the staging and writes p and q = A p with the
+// next iteration's dot products in the epilogue.  The GS solves (and
+// multi-component magnetostatic solves) take two launches per iteration: the
+// matvec, whose staging forms the new direction p_k = r_k + beta_k p_{k-1}
+// after testing ||r_k|| on the device, with p.Ap fused into its epilogue; and
+// the x/r update with r.r fused.  Vectors that other workgroups read as halo
+// while a launch writes their successors are double-buffered.  Convergence is
+// decided on the device and a converged solve turns the remaining launches
+// into immediate exits.  The host enqueues iterations in batches and reads the
+// convergence flags of the previous batch while the next one runs, so the
+// device never waits for it.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -228,6 +233,7 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
             if (!conv[q]) total[q] += in.iters[q];
         launch_add_f32(static_cast<int64_t>(nc) * n, x, c->d.x32, s);
         ++c->refinements;
+        if (kind == SK_MECH) ++c->mech_refinements;
     }
     for (int q = 0; q < ns; ++q) res.iters[q] = total[q];
     return res;
@@ -472,7 +478,7 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     const double lex2 = 2.0 * c->p.A / (c->p.mu0 * c->p.Ms * c->p.Ms);
     const double eps1 = lex2 * dtau, eps3 = c->p.alpha * eps1;
     c->prof_used = 0;
-    const int64_t ref0 = c->refinements;
+    const int64_t ref0 = c->refinements, mref0 = c->mech_refinements;
     hipEventRecord(c->t0, c->stream);
     int rc = GSPM_OK;
     for (int step = 0; step < nsteps; ++step) {
@@ -491,6 +497,7 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     st->elapsed_ms = ms;
     for (int q = 0; q < 8; ++q) st->gs_iters += st->gs_iters_stage[q];
     st->refinements = c->refinements - ref0;
+    st->mech_refinements = c->mech_refinements - mref0;
     if (st->minres_starts > 0) hipMemcpy(st->warm_coef, c->d.wcoef, 2 * sizeof(double), hipMemcpyDeviceToHost);
     if (c->profile) {
         double tot = 0.0;

@@ -22,6 +22,7 @@ GSPM_FIELD_M, GSPM_FIELD_U, GSPM_FIELD_UD = 0, 1, 2
 GSPM_OP_LAPLACE, GSPM_OP_MASS, GSPM_OP_GS, GSPM_OP_ELASTIC, GSPM_OP_MS = 0, 1, 2, 3, 4
 GSPM_PERIODIC = 1
 GSPM_WARM_PREVIOUS, GSPM_WARM_LEARNED, GSPM_WARM_EXTRAPOLATE = 0, 1, 2
+GSPM_SWEEP_STOP_ON_REVERSAL, GSPM_SWEEP_CONTINUE = 1, 2
 GSPM_MPNN_PARAMS = 50819
 
 STATUS_NAMES = {0: "GSPM_OK", -1: "GSPM_E_ARG", -2: "GSPM_E_MESH", -3: "GSPM_E_STATE", -4: "GSPM_E_DEVICE",
@@ -60,7 +61,8 @@ class gspm_step_stats(ctypes.Structure):
                 ("elapsed_ms", ctypes.c_double), ("matvec_ms", ctypes.c_double),
                 ("matvec_launches", ctypes.c_int64), ("refinements", ctypes.c_int64),
                 ("learned_starts", ctypes.c_int64), ("minres_starts", ctypes.c_int64),
-                ("warm_coef", ctypes.c_double * 2), ("ms_iters", ctypes.c_int64)]
+                ("warm_coef", ctypes.c_double * 2), ("ms_iters", ctypes.c_int64),
+                ("mech_refinements", ctypes.c_int64)]
 
 
 _lib = None
@@ -88,7 +90,7 @@ def load() -> ctypes.CDLL:
     lib.gspm_relax.restype = S
     i32p = ctypes.POINTER(ctypes.c_int32)
     lib.gspm_sweep.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, dp, dp,
-                               ctypes.c_int32, dp, i32p, i32p]
+                               ctypes.c_uint32, dp, i32p, i32p, i32p]
     lib.gspm_sweep.restype = S
     lib.gspm_energies.argtypes = [P, dp]; lib.gspm_energies.restype = S
     lib.gspm_demag_local_energy.argtypes = [P, dp]; lib.gspm_demag_local_energy.restype = S
@@ -206,7 +208,7 @@ def stats_dict(st: gspm_step_stats) -> dict:
                 gs_iters=st.gs_iters, gs_iters_stage=list(st.gs_iters_stage), dm_avg=st.dm_avg,
                 elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches,
                 refinements=st.refinements, learned_starts=st.learned_starts, minres_starts=st.minres_starts,
-                warm_coef=list(st.warm_coef), ms_iters=st.ms_iters)
+                warm_coef=list(st.warm_coef), ms_iters=st.ms_iters, mech_refinements=st.mech_refinements)
 
 
 def gspm_step(ctx, dt: float, n_steps: int = 1) -> dict:
@@ -235,23 +237,26 @@ def gspm_relax(ctx, dt: float, dm_tol: float, max_steps: int) -> dict:
 
 
 def gspm_sweep(ctx, dt: float, dm_tol: float, max_steps: int, hext, sigma_ext=None,
-               stop_on_reversal: bool = False) -> dict:
+               stop_on_reversal: bool = False, keep_going: bool = False) -> dict:
     """Relaxes at each applied field (n x 3) and stress (n x 6, or None);
-    returns mbar (points done x 3), steps (points done) and points_done.  On
-    failure the GspmError carries them in its `sweep` attribute."""
+    returns mbar (points done x 3), steps and converged (per point) and
+    points_done.  keep_going sets GSPM_SWEEP_CONTINUE.  On failure the
+    GspmError carries them in its `sweep` attribute."""
     h = _f64(hext, (-1, 3))
     n = h.shape[0]
     sg = None if sigma_ext is None else _f64(sigma_ext, (n, 6))
     mbar = np.zeros((n, 3))
     steps = np.zeros(n, dtype=np.int32)
+    conv = np.zeros(n, dtype=np.int32)
     done = ctypes.c_int32(0)
-    status = load().gspm_sweep(ctx, dt, dm_tol, max_steps, n, _dp(h), None if sg is None else _dp(sg),
-                               1 if stop_on_reversal else 0, _dp(mbar), steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                               ctypes.byref(done))
+    flags = (GSPM_SWEEP_STOP_ON_REVERSAL if stop_on_reversal else 0) | (GSPM_SWEEP_CONTINUE if keep_going else 0)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    status = load().gspm_sweep(ctx, dt, dm_tol, max_steps, n, _dp(h), None if sg is None else _dp(sg), flags,
+                               _dp(mbar), steps.ctypes.data_as(i32p), conv.ctypes.data_as(i32p), ctypes.byref(done))
     k = done.value
     # a failing point has its steps filled but no mbar
     ns = k + 1 if status != GSPM_OK and k < n else k
-    out = dict(mbar=mbar[:k].copy(), steps=steps[:ns].copy(), points_done=k)
+    out = dict(mbar=mbar[:k].copy(), steps=steps[:ns].copy(), converged=conv[:ns].astype(bool), points_done=k)
     if status != GSPM_OK:
         err = GspmError(status, gspm_last_error(ctx))
         err.sweep = out
@@ -420,8 +425,9 @@ class Simulation:
     def relax(self, dt: float, dm_tol: float, max_steps: int) -> dict:
         return gspm_relax(self.ctx, dt, dm_tol, max_steps)
 
-    def sweep(self, dt: float, dm_tol: float, max_steps: int, hext, sigma_ext=None, stop_on_reversal=False) -> dict:
-        return gspm_sweep(self.ctx, dt, dm_tol, max_steps, hext, sigma_ext, stop_on_reversal)
+    def sweep(self, dt: float, dm_tol: float, max_steps: int, hext, sigma_ext=None, stop_on_reversal=False,
+              keep_going=False) -> dict:
+        return gspm_sweep(self.ctx, dt, dm_tol, max_steps, hext, sigma_ext, stop_on_reversal, keep_going)
 
     def energies(self) -> dict:
         return gspm_energies(self.ctx)

@@ -15,11 +15,33 @@ N1M, NE1M = 970299, 5821794
 
 
 def test_algorithmic_bytes_at_the_1m_node_cube():
-    # connectivity 16 B per tet, FP64 coordinates 24 B per node, eight 3-vectors
-    assert bench.cg_iteration_bytes(N1M, NE1M, 8) == 16 * NE1M + 24 * N1M + 192 * N1M
-    assert abs(bench.cg_iteration_bytes(N1M, NE1M, 8) / 1e6 - 302.7) < 0.1
-    assert abs(bench.cg_iteration_bytes(N1M, NE1M, 4) / 1e6 - 209.6) < 0.1
+    # the method's count per elastic CG iteration: connectivity 16 B per tet,
+    # FP64 coordinates 24 B per node, nine passes over 3-vectors
+    assert bench.cg_iteration_bytes(N1M, NE1M, 8) == 16 * NE1M + 24 * N1M + 216 * N1M
+    assert abs(bench.cg_iteration_bytes(N1M, NE1M, 8) / 1e6 - 326.0) < 0.1
+    assert abs(bench.cg_iteration_bytes(N1M, NE1M, 4) / 1e6 - 221.2) < 0.1
     assert abs(bench.ms_matvec_bytes(N1M, NE1M, 4) / 1e6 - 124.2) < 0.1
+    # at exactly six tetrahedra per node: 336 and 228 B per node (elastic), 192 and 156 (GS)
+    n = 1000
+    assert bench.cg_iteration_bytes(n, 6 * n, 8) == 336 * n
+    assert bench.cg_iteration_bytes(n, 6 * n, 4) == 228 * n
+    assert bench.gs_iteration_bytes(n, 6 * n, 8) == 192 * n
+    assert bench.gs_iteration_bytes(n, 6 * n, 4) == 156 * n
+
+
+def test_step_bytes_in_both_precisions():
+    n, ne = 1000, 6000
+    base = 3 * (16 * ne + 96 * n) + 200 * n                 # three RHS passes (192 B/node) + node passes
+    assert bench.step_bytes(n, ne, 0, 0) == base
+    # FP64 path: 150 elastic and 40 GS iterations at 336 and 192 B per node
+    assert bench.step_bytes(n, ne, 150, 40, 8) == base + 150 * 336 * n + 40 * 192 * n
+    # mixed path: inner iterations at FP32 bytes, refinements at FP64
+    ref3 = 16 * ne + 24 * n + 3 * 56 * n
+    ref1 = 16 * ne + 24 * n + 56 * n
+    got = bench.step_bytes(n, ne, 150, 40, 4, mech_refinements=2, other_refinements=8)
+    assert got == base + 150 * 228 * n + 40 * 156 * n + 2 * ref3 + 8 * ref1
+    # the FP32 step moves fewer bytes than the FP64 one at equal iteration counts
+    assert bench.step_bytes(n, ne, 150, 40, 4) < bench.step_bytes(n, ne, 150, 40, 8)
 
 
 def test_traffic_is_tied_to_sources_and_workload(tmp_path, monkeypatch):

@@ -108,3 +108,33 @@ def test_argument_errors(setup):
         sim.sweep(DT, TOL, 10, np.zeros((0, 3)))
     assert e.value.status == gspm.GSPM_E_ARG
     sim.close()
+
+
+def test_fixed_length_sweep_continues_past_unrelaxed_points(setup):
+    """GSPM_SWEEP_CONTINUE: a field loop run for a set number of steps per
+    point (the largest workload's protocol: a fixed step count per field),
+    with a threshold no point reaches, records mbar after max_steps at every
+    point and reports it unconverged; the oracle's loop does the same steps."""
+    H = [(2e4, 0.0, 0.0), (-2e4, 0.0, 0.0), (-6e4, 0.0, 0.0), (-1e5, 0.0, 0.0)]
+    sim, orc, params = _pair(setup, H[0])
+    out = sim.sweep(DT, 1e-300, 25, H, keep_going=True)
+    mb, steps, conv = orc.sweep(params, DT, 1e-300, 25, H, keep_going=True)
+    print(f"fixed-length sweep: steps {out['steps'].tolist()}, converged {out['converged'].tolist()}; "
+          f"max |dmbar| {np.abs(out['mbar'] - np.array(mb)).max():.2e}", flush=True)
+    assert out["points_done"] == len(H) and out["steps"].tolist() == [25] * len(H) == steps
+    assert not out["converged"].any() and not any(conv)
+    assert np.abs(out["mbar"] - np.array(mb)).max() < 1e-8
+    # mixing: a threshold the first point reaches, the later ones not
+    sim2, orc2, _ = _pair(setup, H[0])
+    out2 = sim2.sweep(DT, TOL, 150, H[:2], keep_going=True)
+    mb2, steps2, conv2 = orc2.sweep(params, DT, TOL, 150, H[:2], keep_going=True)
+    assert out2["steps"].tolist() == steps2 and out2["converged"].tolist() == conv2
+    assert np.abs(out2["mbar"] - np.array(mb2)).max() < 1e-8
+    # without the flag the first unrelaxed point ends the sweep with NOCONV
+    sim3, _, _ = _pair(setup, H[0])
+    with pytest.raises(gspm.GspmError) as e:
+        sim3.sweep(DT, 1e-300, 5, H)
+    assert e.value.status == gspm.GSPM_E_NOCONV and e.value.sweep["points_done"] == 0
+    assert e.value.sweep["steps"].tolist() == [5] and not e.value.sweep["converged"][0]
+    for s in (sim, sim2, sim3):
+        s.close()
