@@ -233,6 +233,24 @@ gspm_status gspm_demag_local_energy(gspm_ctx *ctx, double *e);
  * strain ebar[6] (order xx yy zz yz xz xy). */
 gspm_status gspm_averages(gspm_ctx *ctx, double mbar[3], double ebar[6]);
 
+/* gspm_averages without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): no hipMalloc, hipFree or allocating library call, no
+ * host synchronisation.  m_dev: device array of n_nodes x 3 doubles in the
+ * caller's node order (row-major), read at the first copy of each periodic
+ * node and used as given (not normalised; copies are not compared);
+ * out_dev: device array of 9 doubles receiving mbar[3] then ebar[6] (order
+ * xx yy zz yz xz xy).  The work is enqueued on the context's stream and the
+ * call returns at once: out_dev is valid once that stream has reached it.
+ * Partial sums go to a fixed scratch array of the library, one per GPU, held
+ * until the process ends (4096 x 9 partial sums plus a few totals, 300 KB):
+ * meshes of more than 4,194,304 unique nodes are GSPM_E_ARG.  The partial
+ * sums are added in a fixed order, so results repeat bitwise; they agree with
+ * gspm_averages to rounding.  Every call on a GPU shares that GPU's scratch
+ * and keeps the last call's contents, so calls that overlap on one GPU (on
+ * different streams or contexts) race.  Needs upload_mesh and set_params. */
+gspm_status gspm_averages_noalloc(gspm_ctx *ctx, const double *m_dev, double *out_dev);
+
 /* Apply one operator of Sec. 2.3 to x (n_nodes x 3, caller's order), writing
  * y = A x (the assembled residual at each node, reported at all its copies).
  * eps is used by GSPM_OP_GS only.  GSPM_OP_ELASTIC needs gspm_set_params. */

@@ -200,7 +200,7 @@ void gspm_ctx::release_mesh() {
     dev_free(this, b.cgi_rr); dev_free(this, b.cgi_pq); dev_free(this, b.cgi_bb); dev_free(this, b.cgi_rq); dev_free(this, b.cgi_qq);
     dev_free(this, b.cgi_flags);
     dev_free(this, b.mprev); dev_free(this, b.uprev); dev_free(this, b.du_prev); dev_free(this, b.kdu); dev_free(this, b.wred); dev_free(this, b.wcoef);
-    dev_free(this, b.ud); dev_free(this, b.udnext);
+    dev_free(this, b.ud); dev_free(this, b.udnext); dev_free(this, b.rep);
     if (arena) hipFree(arena);
     arena = nullptr;
     arena_size = arena_used = 0;
@@ -281,6 +281,13 @@ gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts) {
         g_create_error = "gspm_create: cannot allocate host resources";
         return GSPM_E_DEVICE;
     }
+    // the allocation-free entry point's scratch: its address on this device,
+    // looked up once per device with the device current
+    if (noalloc_scratch_address(o.device, &c->na_scratch) != 0 || !c->na_scratch) {
+        delete c;
+        g_create_error = "gspm_create: cannot look up the device address of the fixed scratch";
+        return GSPM_E_DEVICE;
+    }
     c->err = "no error";
     *out = c;
     return GSPM_OK;
@@ -344,6 +351,7 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
             rc = rc ? rc : dev_alloc(c, p, n3);
         rc = rc ? rc : dev_alloc(c, &d.ud, n);
         rc = rc ? rc : dev_alloc(c, &d.udnext, n);
+        rc = rc ? rc : dev_alloc(c, &d.rep, n);
         rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kMrSums) * kShards);
         rc = rc ? rc : dev_alloc(c, &d.wcoef, 2);
         rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
@@ -396,6 +404,9 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     hipMemcpyAsync(d.blk_ptr, hm.blk_ptr.data(), sizeof(int32_t) * hm.blk_ptr.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.blk_nmag, hm.blk_nmag.data(), sizeof(int32_t) * hm.blk_nmag.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.w, hm.w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
+    std::vector<int32_t> rep(n, -1);
+    for (int64_t i = hm.n0 - 1; i >= 0; --i) rep[static_cast<size_t>(hm.user2int[i])] = static_cast<int32_t>(i);
+    hipMemcpyAsync(d.rep, rep.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
     if (nseg) {
         hipMemcpyAsync(d.seg_ent, hm.seg_ent.data(), sizeof(uint16_t) * hm.seg_ent.size(), hipMemcpyHostToDevice, s);
         hipMemcpyAsync(d.seg_off, hm.seg_off.data(), sizeof(uint32_t) * nseg, hipMemcpyHostToDevice, s);
@@ -697,6 +708,21 @@ gspm_status gspm_averages(gspm_ctx *c, double mbar[3], double ebar[6]) {
     if (rc) return static_cast<gspm_status>(rc);
     for (int k = 0; k < 3; ++k) mbar[k] = der.mbar[k];
     for (int k = 0; k < 6; ++k) ebar[k] = der.ebar[k];
+    return GSPM_OK;
+}
+
+gspm_status gspm_averages_noalloc(gspm_ctx *c, const double *m_dev, double *out_dev) {
+    if (!c) return GSPM_E_ARG;
+    if (!m_dev || !out_dev) return fail(c, GSPM_E_ARG, "averages_noalloc: null device pointer");
+    if (!c->have_mesh || !c->have_params) return fail(c, GSPM_E_STATE, "averages_noalloc needs mesh and params");
+    if (c->n > kNaMaxNodes)
+        return fail(c, GSPM_E_ARG, "averages_noalloc: " + std::to_string(c->n) + " unique nodes, more than the " +
+                                       std::to_string(kNaMaxNodes) + " its fixed scratch serves");
+    hipSetDevice(c->device);
+    const int e = launch_averages_noalloc(c->na_scratch, c->n, c->d.w, c->d.rep, m_dev, c->mat, c->dargs, out_dev,
+                                          c->stream);
+    if (e != 0) return fail(c, GSPM_E_DEVICE, std::string("averages_noalloc: ") +
+                                                  hipGetErrorString(static_cast<hipError_t>(e)));
     return GSPM_OK;
 }
 

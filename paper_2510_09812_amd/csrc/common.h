@@ -158,6 +158,21 @@ struct DeriveArgs {
 };
 void launch_derive(const double *sums, const DeriveArgs &a, Derived *out, hipStream_t s);
 
+// Allocation-free volume averages (gspm_averages_noalloc).  The scratch is a
+// file-scope device array of node_kernels.hip, one per GPU: partial sums of at
+// most kNaMaxGroups workgroups of kNaNodesPerGroup unique nodes each.
+constexpr int kNaNodesPerGroup = 4 * kThreads;
+constexpr int kNaMaxGroups = 4096;
+constexpr int64_t kNaMaxNodes = static_cast<int64_t>(kNaMaxGroups) * kNaNodesPerGroup;
+constexpr int kNaMaxDevices = 64;
+// Device address of the scratch on `device` (which must be current), looked
+// up once per device with hipGetSymbolAddress.  Returns a hipError_t value.
+int noalloc_scratch_address(int device, double **out);
+// mbar and ebar of m_user (caller node order, device) into out[9] (device), on
+// stream s, through the scratch at scr.  Returns a hipError_t value.
+int launch_averages_noalloc(double *scr, int n, const double *w, const int32_t *rep, const double *m_user,
+                            const Material &mat, const DeriveArgs &da, double *out, hipStream_t s);
+
 // Element passes (one workgroup per owner block).
 void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x,
                         double *bb, hipStream_t s);

@@ -48,6 +48,7 @@ struct DeviceBuffers {
     double *wred = nullptr;       // kMrSums x kShards: minimum-residual sums
     double *wcoef = nullptr;      // 2: coefficients of the last minimum-residual start
     double *ud = nullptr, *udnext = nullptr;   // n: local magnetostatic potential (committed, in progress)
+    int32_t *rep = nullptr;       // n: the first caller node of each unique node
 };
 
 // Device state of the learned warm start (allocated on first use).
@@ -114,6 +115,8 @@ struct gspm_ctx {
     bool have_prev = false;               // d.mprev holds the state before the last committed step
     int commits = 0;                      // steps committed since the last set_field (u^{n-2} valid from 2)
     std::vector<int32_t> tets_int;        // 4 x ne internal node ids (graph construction)
+
+    double *na_scratch = nullptr;         // this device's scratch of gspm_averages_noalloc (not owned)
 
     ~gspm_ctx();
     void release_mesh();

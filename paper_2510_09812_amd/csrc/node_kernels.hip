@@ -2,6 +2,8 @@
 // quantities derived from them, the CG vector updates and the GSPM node
 // updates.  Vectors are component-major [c][n]; one thread per node per
 // grid-stride step, so every access is coalesced.
+#include <mutex>
+
 #include "device_common.h"
 
 namespace gspm {
@@ -111,6 +113,130 @@ __global__ void __launch_bounds__(kThreads) k_derive(const double *sums, DeriveA
 
 void launch_derive(const double *sums, const DeriveArgs &a, Derived *out, hipStream_t s) {
     hipLaunchKernelGGL(k_derive, dim3(1), dim3(kThreads), 0, s, sums, a, out);
+}
+
+// ------------------------------------------- averages without allocation
+
+// Device memory of gspm_averages_noalloc: per-workgroup partial sums
+// [group][9], the nine totals in the sharded layout k_derive reads, and the
+// Derived record.  One copy per GPU, held until the process ends; every call
+// on a GPU overwrites it, so calls that overlap on one GPU race.  Host code
+// never passes `scratch` itself (in host code the name is a stand-in, not a
+// device address): it uses the address hipGetSymbolAddress returns for the
+// current device (noalloc_scratch_address).
+constexpr int kNaPartials = kNaMaxGroups * 9;
+constexpr int kNaSums = 9 * kShards;
+constexpr int kNaDerived = 16;
+static_assert(sizeof(Derived) <= kNaDerived * sizeof(double), "Derived record larger than its scratch slot");
+static __device__ __align__(256) double scratch[kNaPartials + kNaSums + kNaDerived];
+
+namespace {
+std::mutex g_na_mutex;
+double *g_na_ptr[kNaMaxDevices] = {};
+}  // namespace
+
+int noalloc_scratch_address(int device, double **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kNaMaxDevices) return static_cast<int>(hipErrorInvalidDevice);
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    if (!g_na_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return static_cast<int>(e);
+        g_na_ptr[device] = static_cast<double *>(p);
+    }
+    *out = g_na_ptr[device];
+    return 0;
+}
+
+// Sum NR per-thread values over the workgroup in a fixed order (wave
+// shuffles, then the waves in order); every thread gets the totals.
+template <int NR>
+__device__ __forceinline__ void block_sum_fixed(double (&v)[NR]) {
+    __shared__ double red[kThreads / 64][NR];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        double s = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) red[wv][k] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < kThreads / 64; ++w2) s += red[w2][k];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+// The sums of k_avg_sums with m in the caller's node order (n_user x 3,
+// row-major, read at one caller node `rep[i]` of each unique node i); group g
+// covers the unique nodes [g kNaNodesPerGroup, (g + 1) kNaNodesPerGroup) and
+// writes its nine sums to partials[9 g ..] (no atomics).
+__global__ void __launch_bounds__(kThreads) k_avg_partials_user(int n, const double *w, const int32_t *rep,
+                                                                const double *m_user, Material mat,
+                                                                double *partials) {
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const double a = 1.5 * mat.l100, b = 1.5 * mat.l111, third = 1.0 / 3.0;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kNaNodesPerGroup;
+    for (int t = threadIdx.x; t < kNaNodesPerGroup; t += kThreads) {
+        const int64_t i = base + t;
+        if (i >= n) break;
+        const double wi = w[i];
+        const double *mu = m_user + 3 * static_cast<int64_t>(rep[i]);
+        double m0 = mu[0], m1 = mu[1], m2 = mu[2];
+        acc[0] += wi * m0;
+        acc[1] += wi * m1;
+        acc[2] += wi * m2;
+        if (mat.rot) {
+            const double ms[3] = {m0, m1, m2};
+            double mc[3];
+            to_crystal3(mat.R, ms, mc);
+            m0 = mc[0]; m1 = mc[1]; m2 = mc[2];
+        }
+        acc[3] += wi * a * (m0 * m0 - third);
+        acc[4] += wi * a * (m1 * m1 - third);
+        acc[5] += wi * a * (m2 * m2 - third);
+        acc[6] += wi * b * m1 * m2;
+        acc[7] += wi * b * m0 * m2;
+        acc[8] += wi * b * m0 * m1;
+    }
+    block_sum_fixed<9>(acc);
+    if (threadIdx.x < 9) partials[9 * static_cast<int64_t>(blockIdx.x) + threadIdx.x] = acc[threadIdx.x];
+}
+
+// One workgroup: the totals of `groups` partial sums in a fixed order, stored
+// as shard 0 of the sharded layout (the other shards zero).
+__global__ void __launch_bounds__(kThreads) k_avg_fold(int groups, const double *partials, double *sums) {
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int g = threadIdx.x; g < groups; g += kThreads)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += partials[9 * static_cast<int64_t>(g) + k];
+    block_sum_fixed<9>(acc);
+    for (int q = threadIdx.x; q < kNaSums; q += kThreads) sums[q] = (q % kShards == 0) ? acc[q / kShards] : 0.0;
+}
+
+__global__ void k_avg_out(const Derived *der, double *out) {
+    const int t = threadIdx.x;
+    if (t < 3) out[t] = der->mbar[t];
+    else if (t < 9) out[t] = der->ebar[t - 3];
+}
+
+int launch_averages_noalloc(double *scr, int n, const double *w, const int32_t *rep, const double *m_user,
+                            const Material &mat, const DeriveArgs &da, double *out, hipStream_t s) {
+    const int groups = static_cast<int>((static_cast<int64_t>(n) + kNaNodesPerGroup - 1) / kNaNodesPerGroup);
+    if (groups < 1 || groups > kNaMaxGroups) return static_cast<int>(hipErrorInvalidValue);
+    double *partials = scr, *sums = scr + kNaPartials;
+    Derived *der = reinterpret_cast<Derived *>(scr + kNaPartials + kNaSums);
+    hipLaunchKernelGGL(k_avg_partials_user, dim3(groups), dim3(kThreads), 0, s, n, w, rep, m_user, mat, partials);
+    hipLaunchKernelGGL(k_avg_fold, dim3(1), dim3(kThreads), 0, s, groups, partials, sums);
+    hipLaunchKernelGGL(k_derive, dim3(1), dim3(kThreads), 0, s, sums, da, der);
+    hipLaunchKernelGGL(k_avg_out, dim3(1), dim3(64), 0, s, der, out);
+    return static_cast<int>(hipGetLastError());
 }
 
 // Anisotropy and Zeeman energies by the vertex rule: sum_j w_j psi(m_j).

@@ -33,7 +33,7 @@ EXPORTS = ("gspm_create", "gspm_destroy", "gspm_upload_mesh", "gspm_set_params",
            "gspm_mesh_info", "gspm_demag_factors", "gspm_time_operator", "gspm_last_error",
            "gspm_set_warm_start", "gspm_mpnn_set_params", "gspm_mpnn_get_params", "gspm_mpnn_forward",
            "gspm_mpnn_train_step", "gspm_mpnn_warm_start", "gspm_set_profile", "gspm_relax", "gspm_sweep",
-           "gspm_demag_local_energy")
+           "gspm_demag_local_energy", "gspm_averages_noalloc")
 
 
 class GspmError(RuntimeError):
@@ -95,6 +95,7 @@ def load() -> ctypes.CDLL:
     lib.gspm_energies.argtypes = [P, dp]; lib.gspm_energies.restype = S
     lib.gspm_demag_local_energy.argtypes = [P, dp]; lib.gspm_demag_local_energy.restype = S
     lib.gspm_averages.argtypes = [P, dp, dp]; lib.gspm_averages.restype = S
+    lib.gspm_averages_noalloc.argtypes = [P, P, P]; lib.gspm_averages_noalloc.restype = S
     lib.gspm_apply.argtypes = [P, ctypes.c_int, ctypes.c_double, dp, dp, i64]; lib.gspm_apply.restype = S
     lib.gspm_solve.argtypes = [P, ctypes.c_int, ctypes.c_double, dp, dp, i64, ctypes.c_double, ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_int32)]
@@ -283,6 +284,14 @@ def gspm_averages(ctx):
     mbar = np.zeros(3); ebar = np.zeros(6)
     _check(ctx, load().gspm_averages(ctx, _dp(mbar), _dp(ebar)))
     return mbar, ebar
+
+
+def gspm_averages_noalloc(ctx, m_dev_ptr: int, out_dev_ptr: int) -> None:
+    """Device pointers in, nothing allocated: m (n_nodes x 3 doubles, caller
+    order) and out (9 doubles: mbar, ebar), both device addresses (for
+    example torch tensors' data_ptr()).  Asynchronous on the context's
+    stream."""
+    _check(ctx, load().gspm_averages_noalloc(ctx, ctypes.c_void_p(m_dev_ptr), ctypes.c_void_p(out_dev_ptr)))
 
 
 def gspm_apply(ctx, op: int, x, eps: float = 0.0) -> np.ndarray:
