@@ -22,6 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OP_LAPLACE, OP_MASS, OP_GS, OP_ELASTIC, OP_LAPLACE_ALL, OP_MS = 0, 1, 2, 3, 4, 5
 SOLVE_ELASTIC_JACOBI = 6
+SOLVE_ELASTIC_GREEN = 7
 
 
 _NATIVE_PATH = os.path.join(_HERE, "liboracle_native.so")
@@ -46,7 +47,7 @@ class _Params(ctypes.Structure):
                 ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0")] + [
         ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
         ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32),
-        ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9)]
+        ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9), ("elastic_precond", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -113,6 +114,9 @@ def _load():
     lib.or_last_error.argtypes = [P]; lib.or_last_error.restype = ctypes.c_char_p
     lib.or_num_threads.argtypes = []; lib.or_num_threads.restype = ctypes.c_int32
     lib.or_set_num_threads.argtypes = [ctypes.c_int32]
+    lib.or_precond_apply.argtypes = [P, dp, dp]
+    lib.or_precond_grid.argtypes = [P, P]
+    lib.or_set_precond_omega.argtypes = [P, ctypes.c_double]
     _lib = lib
     return lib
 
@@ -136,7 +140,9 @@ class OracleError(RuntimeError):
 
 def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession: bool = True,
                 cg_maxit: int = 10000, local_demag: bool = False) -> _Params:
-    """params may carry "crystal_rot" (3 x 3, v_sample = R v_crystal, App. D)."""
+    """params may carry "crystal_rot" (3 x 3, v_sample = R v_crystal, App. D)
+    and "elastic_precond" (1: the Green's-operator preconditioned elastic
+    solve)."""
     p = _Params()
     for k in ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0"):
         setattr(p, k, float(params[k]))
@@ -154,6 +160,7 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
     rot = np.asarray(params.get("crystal_rot", np.eye(3)), dtype=np.float64).reshape(9)
     for i in range(9):
         p.crystal_rot[i] = rot[i]
+    p.elastic_precond = int(params.get("elastic_precond", 0))
     return p
 
 
@@ -370,6 +377,20 @@ class Oracle:
         it = ctypes.c_int32(0)
         self._check(self._lib.or_solve(self._h, which, eps, _dp(b), _dp(x), tol, maxit, ctypes.byref(it)))
         return x, int(it.value)
+
+    def precond_apply(self, r) -> np.ndarray:
+        """z = B r for the elastic preconditioner (unique-node order)."""
+        r = _f64(r, (self.n, 3)); z = np.zeros((self.n, 3))
+        self._check(self._lib.or_precond_apply(self._h, _dp(r), _dp(z)))
+        return z
+
+    def precond_grid(self) -> tuple:
+        g = np.zeros(3, dtype=np.int32)
+        self._check(self._lib.or_precond_grid(self._h, g.ctypes.data))
+        return tuple(int(v) for v in g)
+
+    def set_precond_omega(self, omega: float) -> None:
+        self._lib.or_set_precond_omega(self._h, float(omega))
 
     def elastic_rhs(self) -> np.ndarray:
         b = np.zeros((self.n, 3)); self._check(self._lib.or_elastic_rhs(self._h, _dp(b))); return b

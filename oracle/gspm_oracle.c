@@ -14,6 +14,10 @@
  *     far-field demagnetising field -N_d mbar (Sec. 2.1);
  *   - unpreconditioned CG with d pinned DOFs (Sec. 2.5) and the relative
  *     residual criterion of Sec. 3.1;
+ *   - optionally the elastic solve preconditioned (Sec. 5.2 names the
+ *     elastic CG as the cost to cut) by the Green's operator of the elastic
+ *     stiffness on a periodic auxiliary grid, on the periodic system, pinned
+ *     afterwards by a translation;
  *   - optionally the local magnetostatic potential of Eq. (demag) in the weak
  *     form (weak_demag), with K^ms and F^ms of Eqs. (LHS), (RHS_F) and
  *     (RHS_b), and its field -grad U~ (Sec. 2.1);
@@ -58,8 +62,14 @@ struct or_sim {
     int p0;
     double *m, *u;       /* n x 3 */
     double *ud;          /* n: local magnetostatic potential U~ */
+    struct green_pc *gpc; /* elastic preconditioner (elastic_precond = 1), built by set_params */
+    double gpc_omega;    /* weight of its diagonal term (1/2 unless a test changes it) */
     char err[256];
 };
+
+struct green_pc;
+static void green_free(struct green_pc *g);
+static int green_setup(struct or_sim *s);
 
 /* ------------------------------------------------------------------ utils */
 
@@ -455,6 +465,7 @@ int or_create(or_sim **out, int32_t n0, const double *xyz, int32_t ne, const int
     *out = NULL;
     or_sim *s = (or_sim *)calloc(1, sizeof(or_sim));
     s->n0 = n0; s->ne = ne; s->periodic = periodic ? 1 : 0;
+    s->gpc_omega = 0.5;
     for (int a = 0; a < 3; ++a) { s->lo[a] = lo[a]; s->L[a] = hi[a] - lo[a]; }
     int rc = OR_OK;
     if (n0 < 4 || ne < 1) { seterr(s, "empty mesh"); rc = OR_E_ARG; goto fail; }
@@ -586,6 +597,7 @@ void or_destroy(or_sim *s) {
     free(s->n2e_ptr); free(s->n2e); free(s->adj_ptr); free(s->adj);
     free(s->Kmag); free(s->Mmag); free(s->Kall); free(s->Kmech); free(s->m); free(s->u);
     free(s->ud);
+    green_free(s->gpc);
     free(s);
 }
 
@@ -669,9 +681,20 @@ int or_set_params(or_sim *s, const or_params *p) {
         seterr(s, "the local magnetostatic solve needs a periodic mesh");
         return OR_E_ARG;
     }
+    if (p->elastic_precond != 0 && p->elastic_precond != 1) { seterr(s, "elastic_precond must be 0 or 1"); return OR_E_ARG; }
+    if (p->elastic_precond && !s->periodic) {
+        seterr(s, "the elastic preconditioner needs a periodic mesh");
+        return OR_E_ARG;
+    }
     s->p = *p;
     cubic_tensor(p, s->C);
     assemble_elastic(s);
+    if (p->elastic_precond) {
+        green_setup(s);
+    } else {
+        green_free(s->gpc);
+        s->gpc = NULL;
+    }
     s->have_params = 1;
     if (!s->u) s->u = (double *)calloc((size_t)s->n * 3, sizeof(double));
     if (!s->ud) s->ud = (double *)calloc((size_t)s->n, sizeof(double));
@@ -939,6 +962,329 @@ done:
     return rc;
 }
 
+/* ------------------------------------------ Green's-operator preconditioner
+ *
+ * The paper runs the elastic CG without a preconditioner and names that
+ * solve as the cost to cut (Sec. 5.2).  The elastic stiffness is one
+ * homogeneous C on a periodic cell, so its inverse is nearly the lattice
+ * Green's operator of the same C: this preconditioner is
+ *     B = Q A_g^+ Q^T + omega D^-1
+ * with
+ *   - a periodic auxiliary grid of g_a = round(L_a / l) points per axis,
+ *     l = (V_c / n)^(1/3) the mean node spacing (at least 2 points);
+ *   - Q: grid -> mesh nodes, trilinear interpolation of grid values at the
+ *     node positions (wrapped into the cell), so Q^T spreads nodal values to
+ *     the 8 grid points around each node with the same weights;
+ *   - A_g: the P1 stiffness of C on the grid cells split into six Kuhn
+ *     tetrahedra (each cell around its main diagonal), a block-circulant
+ *     operator whose symbol A(k) = sum_o S(o) exp(2 pi i k.o / g) (S(o) the
+ *     3 x 3 coupling of a node to the node at offset o) is inverted mode by
+ *     mode, the translation mode k = 0 left out (the pseudo-inverse);
+ *   - D: the diagonal of K^mech, omega = 1/2.
+ * B is symmetric and positive semi-definite.  It acts on the periodic system
+ * K u = b (b with its mean removed, the part a periodic u can balance): CG
+ * with B runs on that singular but consistent system, with the stopping rule
+ * of Sec. 3.1 on its residual, and the solution is then pinned at node p0 by
+ * a translation (the pinned system of Sec. 2.5 has the same solution up to
+ * that translation).  Transforms here are plain separable DFTs. */
+
+typedef struct green_pc {
+    int g[3];
+    double h[3];
+    double *Ainv;        /* G x 18: A(k)^-1 / G as a complex 3x3, row-major, (re, im) pairs; zero at k = 0 */
+    double *dinv;        /* n x 3: 1 / diag(K^mech) */
+} green_pc;
+
+static void green_free(green_pc *g) {
+    if (!g) return;
+    free(g->Ainv); free(g->dinv); free(g);
+}
+
+/* Gradients of the barycentric coordinates of a tetrahedron given by its
+ * four vertices; returns the volume. */
+static double tet_grads(const double X[4][3], double g[4][3]) {
+    double A[9], B[9];
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a) A[k * 3 + a] = X[k + 1][a] - X[0][a];
+    for (int r = 0; r < 9; ++r) B[r] = (r % 4 == 0) ? 1.0 : 0.0;
+    double det = gauss_solve(3, A, 3, B);
+    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 3; ++a) g[i + 1][a] = B[a * 3 + i];
+    for (int a = 0; a < 3; ++a) g[0][a] = -(g[1][a] + g[2][a] + g[3][a]);
+    return fabs(det) / 6.0;
+}
+
+/* Inverse of a complex 3x3 matrix (re, im pairs, row-major) by cofactors. */
+static void cinv3(const double M[18], double out[18]) {
+#define RE(i, j) M[((i) * 3 + (j)) * 2]
+#define IM(i, j) M[((i) * 3 + (j)) * 2 + 1]
+    double cof[3][3][2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            int r0 = (i + 1) % 3, r1 = (i + 2) % 3, c0 = (j + 1) % 3, c1 = (j + 2) % 3;
+            double are = RE(r0, c0) * RE(r1, c1) - IM(r0, c0) * IM(r1, c1);
+            double aim = RE(r0, c0) * IM(r1, c1) + IM(r0, c0) * RE(r1, c1);
+            double bre = RE(r0, c1) * RE(r1, c0) - IM(r0, c1) * IM(r1, c0);
+            double bim = RE(r0, c1) * IM(r1, c0) + IM(r0, c1) * RE(r1, c0);
+            cof[i][j][0] = are - bre;
+            cof[i][j][1] = aim - bim;
+        }
+    double dre = 0.0, dim = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        dre += RE(0, j) * cof[0][j][0] - IM(0, j) * cof[0][j][1];
+        dim += RE(0, j) * cof[0][j][1] + IM(0, j) * cof[0][j][0];
+    }
+    double den = dre * dre + dim * dim;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {   /* inverse = adj / det, adj(i,j) = cof(j,i) */
+            double cre = cof[j][i][0], cim = cof[j][i][1];
+            out[(i * 3 + j) * 2] = (cre * dre + cim * dim) / den;
+            out[(i * 3 + j) * 2 + 1] = (cim * dre - cre * dim) / den;
+        }
+#undef RE
+#undef IM
+}
+
+static int green_setup(or_sim *s) {
+    green_free(s->gpc);
+    s->gpc = NULL;
+    green_pc *G = (green_pc *)calloc(1, sizeof(green_pc));
+    double ell = cbrt(s->vc / s->n);
+    for (int a = 0; a < 3; ++a) {
+        int ga = (int)floor(s->L[a] / ell + 0.5);
+        G->g[a] = ga < 2 ? 2 : ga;
+        G->h[a] = s->L[a] / G->g[a];
+    }
+    /* stencil S(o), o in {-1,0,1}^3, of the Kuhn-split grid cell */
+    double S[27][3][3];
+    memset(S, 0, sizeof S);
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int t = 0; t < 6; ++t) {
+        int off[4][3] = {{0, 0, 0}};
+        for (int v = 1; v < 4; ++v) {
+            for (int a = 0; a < 3; ++a) off[v][a] = off[v - 1][a];
+            off[v][perm[t][v - 1]] += 1;
+        }
+        double X[4][3], gr[4][3];
+        for (int v = 0; v < 4; ++v)
+            for (int a = 0; a < 3; ++a) X[v][a] = off[v][a] * G->h[a];
+        double V = tet_grads(X, gr);
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                int o = 0;
+                for (int a = 2; a >= 0; --a) o = o * 3 + (off[j][a] - off[i][a] + 1);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        double v = 0.0;
+                        for (int q = 0; q < 3; ++q)
+                            for (int r = 0; r < 3; ++r) v += s->C[a][q][b][r] * gr[i][q] * gr[j][r];
+                        S[o][a][b] += V * v;
+                    }
+            }
+    }
+    int gx = G->g[0], gy = G->g[1], gz = G->g[2];
+    size_t ng = (size_t)gx * gy * gz;
+    G->Ainv = (double *)calloc(ng * 18, sizeof(double));
+    for (int kz = 0; kz < gz; ++kz)
+        for (int ky = 0; ky < gy; ++ky)
+            for (int kx = 0; kx < gx; ++kx) {
+                size_t id = ((size_t)kz * gy + ky) * gx + kx;
+                if (id == 0) continue;
+                double A[18] = {0};
+                for (int o = 0; o < 27; ++o) {
+                    int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+                    double ph = 2.0 * M_PI * ((double)kx * ox / gx + (double)ky * oy / gy + (double)kz * oz / gz);
+                    double c = cos(ph), sn = sin(ph);
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) {
+                            A[(a * 3 + b) * 2] += S[o][a][b] * c;
+                            A[(a * 3 + b) * 2 + 1] += S[o][a][b] * sn;
+                        }
+                }
+                cinv3(A, &G->Ainv[id * 18]);
+                for (int q = 0; q < 18; ++q) G->Ainv[id * 18 + q] /= (double)ng;
+            }
+    G->dinv = (double *)malloc(sizeof(double) * 3 * (size_t)s->n);
+    for (int i = 0; i < s->n; ++i) {
+        int self = find_col(s, i, i);
+        for (int a = 0; a < 3; ++a) G->dinv[i * 3 + a] = 1.0 / s->Kmech[(size_t)self * 9 + a * 3 + a];
+    }
+    s->gpc = G;
+    return OR_OK;
+}
+
+/* Trilinear weights of node i on the 8 grid points around it: grid index and
+ * weight per corner (corner bits x, y, z). */
+static void green_corners(const or_sim *s, const green_pc *G, int i, size_t idx[8], double wt[8]) {
+    int i0[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double f = (s->x[i * 3 + a] - s->lo[a]) / G->h[a];
+        f -= G->g[a] * floor(f / G->g[a]);
+        int k = (int)floor(f);
+        if (k >= G->g[a]) k = G->g[a] - 1;
+        i0[a] = k;
+        t[a] = f - k;
+    }
+    for (int c = 0; c < 8; ++c) {
+        int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+        int ix = (i0[0] + cx) % G->g[0], iy = (i0[1] + cy) % G->g[1], iz = (i0[2] + cz) % G->g[2];
+        idx[c] = ((size_t)iz * G->g[1] + iy) * G->g[0] + ix;
+        wt[c] = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
+    }
+}
+
+/* In-place DFT of complex data (re, im pairs) along one axis of the grid,
+ * sign -1 (forward) or +1 (inverse, unnormalised). */
+static void dft_axis(const green_pc *G, double *d, int axis, int sign) {
+    int n = G->g[axis];
+    size_t stride = axis == 0 ? 1 : (axis == 1 ? (size_t)G->g[0] : (size_t)G->g[0] * G->g[1]);
+    size_t total = (size_t)G->g[0] * G->g[1] * G->g[2], lines = total / n;
+    double *tmp = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    for (size_t l = 0; l < lines; ++l) {
+        /* first element of line l: index with the axis coordinate zero */
+        size_t base = (l / stride) * stride * n + (l % stride);
+        for (int k = 0; k < n; ++k) {
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j < n; ++j) {
+                double ph = sign * 2.0 * M_PI * (double)((long long)k * j % n) / n;
+                double c = cos(ph), sn = sin(ph);
+                const double *v = &d[(base + j * stride) * 2];
+                re += v[0] * c - v[1] * sn;
+                im += v[0] * sn + v[1] * c;
+            }
+            tmp[2 * k] = re;
+            tmp[2 * k + 1] = im;
+        }
+        for (int k = 0; k < n; ++k) {
+            d[(base + k * stride) * 2] = tmp[2 * k];
+            d[(base + k * stride) * 2 + 1] = tmp[2 * k + 1];
+        }
+    }
+    free(tmp);
+}
+
+/* z = B r on n x 3 vectors (unique-node order). */
+static void green_apply(const or_sim *s, const double *r, double *z) {
+    const green_pc *G = s->gpc;
+    size_t ng = (size_t)G->g[0] * G->g[1] * G->g[2];
+    double *grid = (double *)calloc(ng * 2 * 3, sizeof(double));   /* [comp][point] complex */
+    for (int i = 0; i < s->n; ++i) {
+        size_t idx[8];
+        double wt[8];
+        green_corners(s, G, i, idx, wt);
+        for (int c = 0; c < 8; ++c)
+            for (int a = 0; a < 3; ++a) grid[((size_t)a * ng + idx[c]) * 2] += wt[c] * r[i * 3 + a];
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int ax = 0; ax < 3; ++ax) dft_axis(G, grid + (size_t)a * ng * 2, ax, -1);
+    for (size_t k = 0; k < ng; ++k) {
+        const double *M = &G->Ainv[k * 18];
+        double in[3][2], out[3][2];
+        for (int a = 0; a < 3; ++a) { in[a][0] = grid[((size_t)a * ng + k) * 2]; in[a][1] = grid[((size_t)a * ng + k) * 2 + 1]; }
+        for (int a = 0; a < 3; ++a) {
+            out[a][0] = out[a][1] = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                double mre = M[(a * 3 + b) * 2], mim = M[(a * 3 + b) * 2 + 1];
+                out[a][0] += mre * in[b][0] - mim * in[b][1];
+                out[a][1] += mre * in[b][1] + mim * in[b][0];
+            }
+        }
+        for (int a = 0; a < 3; ++a) { grid[((size_t)a * ng + k) * 2] = out[a][0]; grid[((size_t)a * ng + k) * 2 + 1] = out[a][1]; }
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int ax = 0; ax < 3; ++ax) dft_axis(G, grid + (size_t)a * ng * 2, ax, +1);
+    for (int i = 0; i < s->n; ++i) {
+        size_t idx[8];
+        double wt[8];
+        green_corners(s, G, i, idx, wt);
+        for (int a = 0; a < 3; ++a) {
+            double v = s->gpc_omega * G->dinv[i * 3 + a] * r[i * 3 + a];
+            for (int c = 0; c < 8; ++c) v += wt[c] * grid[((size_t)a * ng + idx[c]) * 2];
+            z[i * 3 + a] = v;
+        }
+    }
+    free(grid);
+}
+
+/* K^mech without the pinned rows: the periodic operator. */
+static void spmv_elastic_periodic(const or_sim *s, const double *x, double *y) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < s->n; ++i) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int t = s->adj_ptr[i]; t < s->adj_ptr[i + 1]; ++t) {
+            const double *B = &s->Kmech[(size_t)t * 9];
+            const double *xj = &x[s->adj[t] * 3];
+            for (int a = 0; a < 3; ++a) v[a] += B[a * 3 + 0] * xj[0] + B[a * 3 + 1] * xj[1] + B[a * 3 + 2] * xj[2];
+        }
+        for (int a = 0; a < 3; ++a) y[i * 3 + a] = v[a];
+    }
+}
+
+/* CG preconditioned by B on the periodic elastic system: b's mean removed,
+ * ||r|| <= tol ||b|| on the periodic residual, then u(p0) = 0 by translation. */
+static int solve_elastic_green(const or_sim *s, const double *b_in, double *u, double tol, int maxit, int *iters) {
+    int len = 3 * s->n, rc = OR_OK, k = 0;
+    double *b = (double *)malloc(sizeof(double) * (size_t)len), *r = (double *)malloc(sizeof(double) * (size_t)len);
+    double *z = (double *)malloc(sizeof(double) * (size_t)len), *p = (double *)malloc(sizeof(double) * (size_t)len);
+    double *q = (double *)malloc(sizeof(double) * (size_t)len);
+    double mean[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < s->n; ++i)
+        for (int a = 0; a < 3; ++a) mean[a] += b_in[i * 3 + a];
+    for (int i = 0; i < s->n; ++i)
+        for (int a = 0; a < 3; ++a) b[i * 3 + a] = b_in[i * 3 + a] - mean[a] / s->n;
+    double bb = dot(b, b, len);
+    if (bb == 0.0) {
+        for (int i = 0; i < len; ++i) u[i] = 0.0;
+        goto done;
+    }
+    spmv_elastic_periodic(s, u, q);
+    for (int i = 0; i < len; ++i) r[i] = b[i] - q[i];
+    double rr = dot(r, r, len), thr = tol * tol * bb;
+    if (rr > thr) {
+        green_apply(s, r, z);
+        for (int i = 0; i < len; ++i) p[i] = z[i];
+    }
+    double rz = dot(r, z, len);
+    while (rr > thr) {
+        if (k >= maxit) { rc = OR_E_NOCONV; break; }
+        spmv_elastic_periodic(s, p, q);
+        double alpha = rz / dot(p, q, len);
+        for (int i = 0; i < len; ++i) { u[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+        ++k;
+        rr = dot(r, r, len);
+        if (!isfinite(rr)) { rc = OR_E_NONFINITE; break; }
+        if (rr <= thr) break;
+        green_apply(s, r, z);
+        double rz_new = dot(r, z, len), beta = rz_new / rz;
+        for (int i = 0; i < len; ++i) p[i] = z[i] + beta * p[i];
+        rz = rz_new;
+    }
+    {
+        double sh[3] = {u[s->p0 * 3], u[s->p0 * 3 + 1], u[s->p0 * 3 + 2]};
+        for (int i = 0; i < s->n; ++i)
+            for (int a = 0; a < 3; ++a) u[i * 3 + a] -= sh[a];
+    }
+done:
+    *iters = k;
+    free(b); free(r); free(z); free(p); free(q);
+    return rc;
+}
+
+int or_precond_apply(or_sim *s, const double *r, double *z) {
+    if (!s->have_params || !s->gpc) return OR_E_STATE;
+    green_apply(s, r, z);
+    return OR_OK;
+}
+
+int or_precond_grid(const or_sim *s, int32_t g[3]) {
+    if (!s->gpc) return OR_E_STATE;
+    for (int a = 0; a < 3; ++a) g[a] = s->gpc->g[a];
+    return OR_OK;
+}
+
+void or_set_precond_omega(or_sim *s, double omega) { s->gpc_omega = omega; }
+
 /* One scalar GS solve (eps K + M) x = b on the magnetic nodes (Eq. weak_GS). */
 static int solve_gs(const or_sim *s, double eps, const double *b, double *x, double tol, int maxit, int *iters) {
     uint8_t *fixed = (uint8_t *)malloc((size_t)s->n);
@@ -950,9 +1296,12 @@ static int solve_gs(const or_sim *s, double eps, const double *b, double *x, dou
 
 int or_solve(const or_sim *s, int32_t which, double eps, const double *b, double *x, double tol, int32_t maxit,
              int32_t *iters) {
-    if (which == 3 || which == 6) {
+    if (which == 3 || which == 6 || which == 7) {
         if (!s->have_params) return OR_E_STATE;
-        int it = 0, rc = which == 3 ? solve_elastic(s, b, x, tol, maxit, &it) : solve_elastic_jacobi(s, b, x, tol, maxit, &it);
+        if (which == 7 && !s->gpc) return OR_E_STATE;
+        int it = 0, rc = which == 3 ? solve_elastic(s, b, x, tol, maxit, &it)
+                                    : (which == 6 ? solve_elastic_jacobi(s, b, x, tol, maxit, &it)
+                                                  : solve_elastic_green(s, b, x, tol, maxit, &it));
         *iters = it;
         return rc;
     }
@@ -1004,7 +1353,15 @@ static void averages_at(const or_sim *s, const double *m, double mbar[3], double
 /* Elastic right-hand side of Eq. (RHS_b): b_(i,a) = int E(phi_i e_a) : C E0_h with
  * E0_h the P1 interpolant of E0(m) on magnetic elements and zero in the
  * inclusions; the pinned node's rows are zero. */
+static void elastic_rhs_full_at(const or_sim *s, const double *m, double *b);
+
 static void elastic_rhs_at(const or_sim *s, const double *m, double *b) {
+    elastic_rhs_full_at(s, m, b);
+    for (int a = 0; a < 3; ++a) b[s->p0 * 3 + a] = 0.0;
+}
+
+/* The same before pinning: the right-hand side of the periodic system. */
+static void elastic_rhs_full_at(const or_sim *s, const double *m, double *b) {
     memset(b, 0, sizeof(double) * 3 * (size_t)s->n);
     for (int e = 0; e < s->ne; ++e) {
         if (!s->tag[e]) continue;
@@ -1024,7 +1381,6 @@ static void elastic_rhs_at(const or_sim *s, const double *m, double *b) {
                 b[node * 3 + a] += s->vol[e] * (S[a][0] * g[0] + S[a][1] * g[1] + S[a][2] * g[2]);
         }
     }
-    for (int a = 0; a < 3; ++a) b[s->p0 * 3 + a] = 0.0;
 }
 
 /* ------------------------------------------------ local magnetostatics */
@@ -1210,9 +1566,14 @@ int or_step(or_sim *s, double dt, int32_t nsteps, or_stats *st) {
         /* averages at m^n feed the far field and the homogeneous strain */
         averages_at(s, m, mbar, ebar);
         /* mechanical equilibrium, Eq. (weak_elasticity), warm start u^{n-1} */
-        elastic_rhs_at(s, m, bm);
         memcpy(u, s->u, sz);
-        rc = solve_elastic(s, bm, u, p->cg_tol, p->cg_maxit, &it);
+        if (p->elastic_precond) {
+            elastic_rhs_full_at(s, m, bm);
+            rc = solve_elastic_green(s, bm, u, p->cg_tol, p->cg_maxit, &it);
+        } else {
+            elastic_rhs_at(s, m, bm);
+            rc = solve_elastic(s, bm, u, p->cg_tol, p->cg_maxit, &it);
+        }
         if (st) st->mech_iters += it;
         if (rc) break;
         /* local magnetostatics, Eq. (weak_demag), at m^n, warm start U~^{n-1};

@@ -31,6 +31,8 @@ typedef struct {
     int32_t precession;    /* 1: full Algorithm B.1; 0: damping stage only (m* = m^n) */
     int32_t local_demag;   /* 1: solve the local magnetostatic potential U~ each step (periodic meshes only) */
     double crystal_rot[9]; /* R of App. D, row-major: v_sample = R v_crystal; all zeros = identity */
+    int32_t elastic_precond; /* 1: elastic solves by CG with the Green's-operator preconditioner (periodic
+                                system, pinned by translation afterwards); 0: plain CG on the pinned system */
 } or_params;
 
 typedef struct {
@@ -77,7 +79,9 @@ int or_apply(const or_sim *s, int32_t which, double eps, const double *x, double
 
 /* CG on operator `which` (2, 3 or 5 above), unique-node order; x holds x0 on
  * entry.  Components of the GS and K^ms operators are solved independently.
- * which = 6: the elastic system (3) by Jacobi-preconditioned CG. */
+ * which = 6: the elastic system (3) by Jacobi-preconditioned CG.
+ * which = 7: the periodic elastic system (b's mean removed) by CG with the Green's-operator preconditioner,
+ *            pinned at p0 by translation afterwards (needs elastic_precond = 1). */
 int or_solve(const or_sim *s, int32_t which, double eps, const double *b, double *x, double tol,
              int32_t maxit, int32_t *iters);
 
@@ -112,6 +116,12 @@ int or_ms_rhs_at(or_sim *s, const double *m, double *b);
 int or_ms_solve_at(or_sim *s, const double *m, double *U, double tol, int32_t maxit, int32_t *iters);
 int or_ms_field(or_sim *s, const double *U, double *hd);
 int or_ms_energy(or_sim *s, const double *U, double *e);
+
+/* The elastic preconditioner B of elastic_precond = 1 (unique-node order, n x 3), the points per axis of its
+ * grid, and the weight of its diagonal term (1/2 by default; tests may change it). */
+int or_precond_apply(or_sim *s, const double *r, double *z);
+int or_precond_grid(const or_sim *s, int32_t g[3]);
+void or_set_precond_omega(or_sim *s, double omega);
 
 const char *or_last_error(const or_sim *s);
 int32_t or_num_threads(void);   /* OpenMP threads the oracle's loops use */
