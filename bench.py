@@ -170,6 +170,8 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start path")
     ap.add_argument("--no-rotated", action="store_true",
                     help="skip the path with the crystal rotated to the <111> frame of App. D")
+    ap.add_argument("--no-precond", action="store_true",
+                    help="skip the paths with the Green's-operator preconditioned elastic solve")
     ap.add_argument("--no-local-demag", action="store_true",
                     help="skip the paths with the local magnetostatic solve (reported beside the headline)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -206,11 +208,14 @@ def main() -> int:
         if weights.size != gspm.GSPM_MPNN_PARAMS:
             weights = None
 
-    def run_path(precision: int, warm: int = 0, local_demag: bool = False, rotated: bool = False) -> dict:
+    def run_path(precision: int, warm: int = 0, local_demag: bool = False, rotated: bool = False,
+                 precond: bool = False) -> dict:
         t_up = time.perf_counter()
         params = dict(case.params)
         if rotated:
             params["crystal_rot"] = R111
+        if precond:
+            params["elastic_precond"] = gspm.GSPM_PRECOND_GREEN
         sim = gspm.Simulation(case.mesh, params, hext=case.hext, device=0, profile=False,
                               block_nodes=args.block_nodes, precision=precision, local_demag=local_demag)
         sim.set_m(case.m0)
@@ -220,7 +225,8 @@ def main() -> int:
         info = sim.mesh_info()
         t_up = time.perf_counter() - t_up
         tag = (f"{'mixed' if precision else 'fp64'}" + {0: "", 1: "+learned", 2: "+extrapolated"}[warm]
-               + ("+local_demag" if local_demag else "") + ("+rotated111" if rotated else ""))
+               + ("+local_demag" if local_demag else "") + ("+rotated111" if rotated else "")
+               + ("+precond" if precond else ""))
         print(f"[bench] {tag}: uploaded {info['n_unique']} nodes, {info['n_tets']} tets in "
               f"{t_up:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
         if args.warmup:
@@ -243,7 +249,7 @@ def main() -> int:
                 out["ms_matvec_ms"] = sim.time_operator(gspm.GSPM_OP_MS, reps=50)
                 print(f"[bench] {tag}: K^ms matvec {out['ms_matvec_ms'] * 1e3:.1f} us per launch (FP32)",
                       file=sys.stderr, flush=True)
-        elif not args.no_profile:
+        elif not args.no_profile and not precond:
             # kernel durations from extra untimed steps: every elastic CG iteration is
             # launched with a start/stop event pair that the runtime records at
             # the kernel's own execution (hipExtLaunchKernelGGL), not in the timed region
@@ -264,6 +270,10 @@ def main() -> int:
             paths["mixed+extrapolated"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_EXTRAPOLATE)
         if weights is not None:
             paths["mixed+learned"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_LEARNED)
+    if not args.no_precond and args.precision in ("fp64", "both"):
+        paths["fp64+precond"] = run_path(gspm.GSPM_FP64, precond=True)
+    if not args.no_precond and args.precision in ("mixed", "both"):
+        paths["mixed+precond"] = run_path(gspm.GSPM_MIXED, precond=True)
     if not args.no_rotated and args.precision == "both":
         paths["fp64+rotated111"] = run_path(gspm.GSPM_FP64, rotated=True)
         paths["mixed+rotated111"] = run_path(gspm.GSPM_MIXED, rotated=True)
@@ -308,6 +318,8 @@ def main() -> int:
         if "prof" in p and p["prof"]["matvec_launches"] > 0:
             row["elastic_cg_launch_us"] = p["prof"]["matvec_ms"] / p["prof"]["matvec_launches"] * 1e3
         ref = "fp64+local_demag" if ld else ("fp64+rotated111" if k.endswith("+rotated111") else "fp64")
+        if k.endswith("+precond"):
+            row["ref_note"] = "errors against the unpreconditioned FP64 path"
         if ref in paths and k != ref:
             f = paths[ref]
             row["speedup_vs_" + ref] = p["value"] / f["value"]

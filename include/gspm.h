@@ -77,9 +77,17 @@ typedef enum {
     GSPM_OP_MASS = 1,       /* M_ij = int phi_i phi_j over magnetic elements (F^GS), per component */
     GSPM_OP_GS = 2,         /* eps K + M: the GSPM operator of Eq. (weak_GS), per component */
     GSPM_OP_ELASTIC = 3,    /* K^mech over all elements; rows of the pinned node are zero */
-    GSPM_OP_MS = 4          /* K^ms: int grad phi_i . grad phi_j over all elements (Eq. weak_demag), rows of
+    GSPM_OP_MS = 4,         /* K^ms: int grad phi_i . grad phi_j over all elements (Eq. weak_demag), rows of
                                the pinned node zero, per component */
+    GSPM_OP_PRECOND = 5     /* gspm_apply only: the elastic preconditioner B of elastic_precond = 1 (FP64
+                               contexts) */
 } gspm_op;
+
+typedef enum {
+    GSPM_PRECOND_NONE = 0,  /* the paper's unpreconditioned CG on the pinned system (Sec. 2.5) */
+    GSPM_PRECOND_GREEN = 1  /* CG on the periodic system preconditioned by the lattice Green's operator of the
+                               stiffness on an auxiliary grid; pinned by a translation afterwards */
+} gspm_precond;
 
 #define GSPM_PERIODIC 1u
 
@@ -122,6 +130,17 @@ typedef struct {
                                sigma_ext and Nd are in the sample frame.  All zeros (or the identity): crystal
                                axes along the sample axes.  Otherwise R must be a proper rotation to 1e-12
                                (GSPM_E_ARG). */
+    int32_t elastic_precond; /* GSPM_PRECOND_NONE or GSPM_PRECOND_GREEN: the elastic solves (the step's and
+                               gspm_solve's) by CG preconditioned with
+                                 B = Q A_g^+ Q^T + (1/2) D^-1,
+                               A_g the stiffness on a periodic grid of round(L_a / l) points per axis
+                               (l = (V_c / n_unique)^(1/3)) with every cell split into six tetrahedra around
+                               its main diagonal, inverted mode by mode by FFT (the translation mode left out),
+                               Q the trilinear interpolation from the grid to the nodes, D the diagonal of
+                               K^mech.  The solve runs on the periodic system (the right-hand side's mean per
+                               component removed, K u = b tested as ||b - K u|| <= cg_tol ||b||) and pins the
+                               caller's node 0 by a translation at the end.  Sec. 5.2 names the elastic CG as
+                               the cost to cut; the paper does not precondition it. */
 } gspm_params;
 
 typedef struct {
@@ -253,14 +272,18 @@ gspm_status gspm_averages_noalloc(gspm_ctx *ctx, const double *m_dev, double *ou
 
 /* Apply one operator of Sec. 2.3 to x (n_nodes x 3, caller's order), writing
  * y = A x (the assembled residual at each node, reported at all its copies).
- * eps is used by GSPM_OP_GS only.  GSPM_OP_ELASTIC needs gspm_set_params. */
+ * eps is used by GSPM_OP_GS only.  GSPM_OP_ELASTIC needs gspm_set_params;
+ * GSPM_OP_PRECOND (y = B x) needs elastic_precond = GSPM_PRECOND_GREEN on an
+ * FP64 context (GSPM_E_STATE otherwise). */
 gspm_status gspm_apply(gspm_ctx *ctx, gspm_op op, double eps, const double *x, double *y, int64_t n_nodes);
 
 /* Solve A x = b by the library's CG (GSPM_OP_GS per component on the magnetic
  * nodes, GSPM_OP_ELASTIC with the pinned node, or GSPM_OP_MS per component
  * with the pinned node).  x holds the initial guess on entry and the solution
  * on return; iters (nullable) receives the iteration count (summed over
- * components for GSPM_OP_GS and GSPM_OP_MS). */
+ * components for GSPM_OP_GS and GSPM_OP_MS).  With elastic_precond =
+ * GSPM_PRECOND_GREEN, GSPM_OP_ELASTIC solves the periodic system for b with
+ * its mean removed (see gspm_params) and pins node 0 afterwards. */
 gspm_status gspm_solve(gspm_ctx *ctx, gspm_op op, double eps, const double *b, double *x, int64_t n_nodes,
                        double tol, int32_t maxit, int32_t *iters);
 

@@ -174,6 +174,7 @@ void scatter_user(const gspm_ctx *c, const std::vector<double> &in, double *out)
 gspm_ctx::~gspm_ctx() {
     release_nn();
     release_mesh();
+    release_pc();
     for (hipEvent_t e : prof_ev) hipEventDestroy(e);
     for (hipEvent_t e : ev)
         if (e) hipEventDestroy(e);
@@ -186,6 +187,7 @@ gspm_ctx::~gspm_ctx() {
 
 void gspm_ctx::release_mesh() {
     if (stream) hipStreamSynchronize(stream);
+    release_pc();
     auto &b = d;
     dev_free(this, b.x); dev_free(this, b.lconn); dev_free(this, b.blk_ptr); dev_free(this, b.blk_nmag); dev_free(this, b.w);
     dev_free(this, b.halo_ptr); dev_free(this, b.halo_ids); dev_free(this, b.halo_lo); dev_free(this, b.img);
@@ -435,6 +437,7 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->nblk = hm.nblk;
     c->p0 = hm.p0;
     c->vc = hm.vc;
+    for (int a = 0; a < 3; ++a) c->box_lo[a] = hm.lo[a];
     c->tets_int.resize(4 * static_cast<size_t>(n_tets));
     for (size_t q = 0; q < c->tets_int.size(); ++q) c->tets_int[q] = hm.user2int[tets[q]];
     c->user2int = std::move(hm.user2int);
@@ -510,6 +513,8 @@ gspm_status gspm_set_params(gspm_ctx *c, const gspm_params *p) {
     if (!(p->c44 > 0 && p->c11 - p->c12 > 0 && p->c11 + 2 * p->c12 > 0))
         return fail(c, GSPM_E_ARG, "set_params: elastic constants are not positive definite");
     if (p->local_demag != 0 && p->local_demag != 1) return fail(c, GSPM_E_ARG, "set_params: local_demag must be 0 or 1");
+    if (p->elastic_precond != GSPM_PRECOND_NONE && p->elastic_precond != GSPM_PRECOND_GREEN)
+        return fail(c, GSPM_E_ARG, "set_params: unknown elastic_precond");
     double R[9];
     bool zero = true, ident = true;
     for (int k = 0; k < 9; ++k) {
@@ -550,6 +555,14 @@ gspm_status gspm_set_params(gspm_ctx *c, const gspm_params *p) {
         rotate_sym(R, true, ec, c->dargs.csig);
     }
     c->have_params = true;
+    if (p->elastic_precond == GSPM_PRECOND_GREEN) {
+        hipSetDevice(c->device);
+        const int rc = green_setup(c);
+        if (rc) {
+            c->p.elastic_precond = GSPM_PRECOND_NONE;
+            return static_cast<gspm_status>(rc);
+        }
+    }
     return GSPM_OK;
 }
 
@@ -731,8 +744,11 @@ gspm_status gspm_apply(gspm_ctx *c, gspm_op op, double eps, const double *x, dou
     if (!x || !y) return fail(c, GSPM_E_ARG, "apply: null array");
     if (!c->have_mesh) return fail(c, GSPM_E_STATE, "apply before upload_mesh");
     if (n_nodes != c->n0) return fail(c, GSPM_E_ARG, "apply: node count differs from the mesh");
-    if (op < GSPM_OP_LAPLACE || op > GSPM_OP_MS) return fail(c, GSPM_E_ARG, "apply: unknown operator");
+    if (op < GSPM_OP_LAPLACE || op > GSPM_OP_PRECOND) return fail(c, GSPM_E_ARG, "apply: unknown operator");
     if (op == GSPM_OP_ELASTIC && !c->have_params) return fail(c, GSPM_E_STATE, "apply(ELASTIC) needs set_params");
+    if (op == GSPM_OP_PRECOND &&
+        !(c->have_params && c->p.elastic_precond == GSPM_PRECOND_GREEN && c->precision == GSPM_FP64))
+        return fail(c, GSPM_E_STATE, "apply(PRECOND) needs elastic_precond = GSPM_PRECOND_GREEN on an FP64 context");
     if (!std::isfinite(eps)) return fail(c, GSPM_E_ARG, "apply: non-finite eps");
     hipSetDevice(c->device);
     std::vector<double> h;
@@ -740,7 +756,10 @@ gspm_status gspm_apply(gspm_ctx *c, gspm_op op, double eps, const double *x, dou
     if (rc) return static_cast<gspm_status>(rc);
     rc = upload(c, c->d.ms, h);
     if (rc) return static_cast<gspm_status>(rc);
-    if (op == GSPM_OP_ELASTIC) {
+    if (op == GSPM_OP_PRECOND) {
+        rc = green_apply64(c, c->d.ms, c->d.q);
+        if (rc) return static_cast<gspm_status>(rc);
+    } else if (op == GSPM_OP_ELASTIC) {
         launch_elastic_matvec<double>(c->mv, c->mat, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0,
                                       0.0, c->stream);
     } else if (op == GSPM_OP_MS) {
@@ -776,7 +795,9 @@ gspm_status gspm_solve(gspm_ctx *c, gspm_op op, double eps, const double *b, dou
     const int n = c->n;
     const bool el = op == GSPM_OP_ELASTIC, msop = op == GSPM_OP_MS;
     const int ns = el ? 1 : 3;
+    const bool green = el && c->p.elastic_precond == GSPM_PRECOND_GREEN;
     for (int k = 0; k < n; ++k) {
+        if (green) break;              // the periodic system: nothing pinned before the solve
         const bool fixed = (el || msop) ? (k == c->p0) : !(c->w_host[k] > 0.0);
         if (!fixed) continue;
         for (int a = 0; a < 3; ++a) hb[static_cast<size_t>(a) * n + k] = hx[static_cast<size_t>(a) * n + k] = 0.0;

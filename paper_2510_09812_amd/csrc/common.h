@@ -140,6 +140,60 @@ struct CGScalars {
 
 enum MatvecMode { MV_APPLY = 0, MV_ITER = 1, MV_RESID = 2 };
 
+// Preconditioned CG on the elastic system keeps r_k . z_k of iteration k in
+// the single-reduction slots of its scalar set: k = 0 in rq[0], k > 0 in
+// qq[k - 1] (the slots the ring zeroing clears before iteration k - 1 runs).
+__host__ __device__ inline double *pcg_rz_at(const CGScalars &cg, int k) {
+    return k == 0 ? cg.rq_at(0) : cg.qq_at(k - 1);
+}
+
+// ------------------------------------------- Green's-operator preconditioner
+
+// Device data of B = Q A_g^+ Q^T + omega D^-1 (elastic_precond), in the
+// working precision of the context's elastic iterations (T = double for FP64
+// contexts, float for the inner solves of the mixed form, where every factor
+// carries 1 / scale with scale the FP32 operator's non-dimensionalisation).
+struct GreenView {
+    int32_t gx, gy, gz, gxh;      // grid points per axis; gxh = gx / 2 + 1 (half spectrum along x)
+    int64_t G, Gh;                // grid points, half-spectrum modes (gz x gy x gxh)
+    double lo[3], h[3];           // grid origin and spacing
+    const int32_t *rptr, *rnode;  // restriction lists: grid point g gathers (rnode, rw)[rptr[g] .. rptr[g + 1])
+    const void *rw;               // their weights (T)
+    const void *dinv;             // [3][n] omega / diag(K^mech) (T)
+    const void *ainv;             // [Gh][9] A(k)^-1 / G, Hermitian: re a00 a11 a22, then a01 a02 a12 (re, im) (T)
+    void *grid;                   // [3][G] real (T)
+    void *spec;                   // [3][Gh] complex (T)
+};
+
+// The preconditioner's node and grid passes (green_kernels.hip).  Every
+// launch returns at once when the scalar set has converged.
+template <class T>
+void launch_pc_restrict(const GreenView &gv, int n, const T *r, const CGScalars &cg, int test_k, double tol,
+                        hipStream_t s);
+template <class T>
+void launch_pc_modes(const GreenView &gv, const CGScalars &cg, hipStream_t s);
+template <class T>
+void launch_pc_prolong(const GreenView &gv, const MeshView &mv, const T *r, T *z, double *rz, const CGScalars &cg,
+                       hipStream_t s);
+// x += alpha p, r -= alpha q with alpha = rz[k] / pq[k]; rr[k + 1] += r.r.
+template <class T>
+void launch_pcg_update(int n, T *x, T *r, const T *p, const T *q, const CGScalars &cg, int k, hipStream_t s);
+// b -= mean(b) per component; bb (zeroed here) += b.b.  aux: 3 x kShards doubles.
+void launch_remove_mean3(int n, double *b, double *aux, double *bb, hipStream_t s);
+// x -= x(p0) on every node.  aux: 3 doubles.
+void launch_pin_shift(int n, double *x, int p0, double *aux, hipStream_t s);
+// The symbol inverse of the grid operator for the half spectrum: stencil27 is
+// the 27 3x3 blocks S(o) (o = (ox, oy, oz) in {-1,0,1}^3, index (oz+1)*9 + (oy+1)*3 + (ox+1)),
+// A(k) = sum_o S(o) exp(2 pi i k.o / g), stored as A(k)^-1 * factor (zero at k = 0).
+template <class T>
+void launch_pc_symbol(const GreenView &gv, const double *stencil27, double factor, hipStream_t s);
+// Preconditioned CG iteration k on the elastic system: p_k = z_k + beta p_{k-1}
+// (beta = rz[k] / rz[k-1], p_0 = z_0) in the staging, q = A p_k (no pinned
+// node), pq[k] += p_k . q.  pin = p_{k-1}, pout = p_k (alternating buffers).
+template <class T>
+void launch_elastic_pcg(const MeshView &mv, const Material &mat, int k, const T *z, const T *pin, T *pout, T *q,
+                        const CGScalars &cg, hipStream_t s);
+
 // ---------------------------------------------------------------- launchers
 
 void launch_fill(double *p, int64_t n, double v, hipStream_t s);

@@ -69,6 +69,20 @@ struct MpnnState {
     mpnn::Grads G{};
 };
 
+// The elastic preconditioner's device data and FFT plans (elastic_precond;
+// built by set_params: the grid and restriction lists once per mesh, the
+// symbol and diagonal whenever the stiffness changes).
+struct GreenState {
+    bool mesh_ready = false, sym_ready = false;
+    double sym_key[37] = {};      // the Voigt stiffness (36) and scale the symbol and diagonal were built for
+    GreenView gv{};
+    int32_t *rptr = nullptr, *rnode = nullptr;
+    void *rw = nullptr, *dinv = nullptr, *ainv = nullptr, *grid = nullptr, *spec = nullptr, *work = nullptr;
+    double *aux = nullptr;        // 3 x kShards: mean sums; then 3: the pinned node's shift
+    size_t work_bytes = 0;
+    void *fwd = nullptr, *inv = nullptr, *info = nullptr;   // rocfft_plan, rocfft_plan, rocfft_execution_info
+};
+
 }  // namespace gspm
 
 struct gspm_ctx {
@@ -84,6 +98,7 @@ struct gspm_ctx {
     int64_t n0 = 0, ne = 0, ncopies = 0;
     int32_t n = 0, nblk = 0, nmag = 0, p0 = -1;
     double vc = 0.0;
+    double box_lo[3] = {0.0, 0.0, 0.0};   // the periodic box's min corner
     std::vector<int32_t> user2int;
     std::vector<double> w_host;   // lumped weights (internal order)
 
@@ -118,9 +133,12 @@ struct gspm_ctx {
 
     double *na_scratch = nullptr;         // this device's scratch of gspm_averages_noalloc (not owned)
 
+    gspm::GreenState pc;                  // elastic preconditioner
+
     ~gspm_ctx();
     void release_mesh();
     void release_nn();
+    void release_pc();
 };
 
 namespace gspm {
@@ -137,6 +155,13 @@ CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, doub
 // K^ms x = b (Eq. weak_demag) on nc components, pinned node p0.
 CgResult cg_ms(gspm_ctx *c, int nc, double *x, const double *b, double tol, int maxit, SolveKind kind);
 int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st);
+// The elastic preconditioner: (re)build what the current mesh and parameters
+// need (green.cpp); y = B x on FP64 device vectors [3][n] (FP64 contexts).
+int green_setup(gspm_ctx *c);
+int green_apply64(gspm_ctx *c, const double *x, double *y);
+// FFTs of the preconditioner on the context's stream: grid -> spec (forward)
+// or spec -> grid (inverse), the three components as one batch.
+int green_fft(gspm_ctx *c, bool forward);
 int hip_check(gspm_ctx *c, hipError_t e, const char *what);
 // Warm start of the elastic solve on the right-hand side b: x (holding u^{n-1})
 // becomes u^{n-1} + a d + c e, d the network's increment at (m, mprev) (when

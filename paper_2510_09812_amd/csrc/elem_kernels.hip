@@ -739,6 +739,66 @@ struct ElasticCgOp {
     }
 };
 
+// The matvec of preconditioned CG iteration k on the periodic elastic system
+// (no pinned node): the direction p_k = z_k + beta p_{k-1}, beta = rz_k /
+// rz_{k-1} (p_0 = z_0), formed in the staging; q = K^mech p_k and p_k . q in
+// the epilogue.  A converged set (decided by the preconditioner's restriction
+// pass, which tests |r|) makes the launch return at once.
+template <class T, class M = Cubic<T>>
+struct ElasticPcgOp {
+    static constexpr bool kMagneticOnly = false;
+    const T *z, *pin;             // z_k, p_{k-1}
+    T *pout, *q;                  // p_k, q_k
+    CGScalars cg;
+    int k, n;
+    M C;
+    double beta;
+    double coord_scale;
+
+    __device__ bool prepare(const MeshView &, int) {
+        if (cg.done[0] != 0) return false;
+        beta = 0.0;
+        if (k > 0) {
+            const double *const src[2] = {pcg_rz_at(cg, k), pcg_rz_at(cg, k - 1)};
+            double t[2];
+            shard_totals<2>(src, t);
+            beta = t[0] / t[1];
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void fetch(int g, T (&v)[3], bool) const {
+        const T bt = static_cast<T>(beta);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t o = static_cast<size_t>(c) * n + g;
+            v[c] = k == 0 ? z[o] : z[o] + bt * pin[o];
+        }
+    }
+
+    __device__ __forceinline__ void element_raw(const T (&v)[4][3], const RawGeo<T> &R, T (&y)[4][3]) const {
+        elastic_element_raw(C, v, R, y);
+    }
+
+    template <int NF>
+    __device__ void finish(const MeshView &mv, const Staged<T, 3, NF> &st, int n0, int cnt) const {
+        double part = 0.0;
+        for (int i = threadIdx.x; i < cnt; i += kThreads) {
+            const int node = n0 + i;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const size_t o = static_cast<size_t>(a) * n + node;
+                const T qv = static_cast<T>(st.acc[a * mv.nb + i]);
+                const T pv = st.fld(a, i);
+                pout[o] = pv;
+                q[o] = qv;
+                part += static_cast<double>(pv) * qv;
+            }
+        }
+        block_atomic_add1(part, cg.pq_at(0, k));
+    }
+};
+
 // One launch of single-reduction CG on K^ms (Eq. weak_demag: the Laplacian
 // over all elements, one scalar component, the pinned node's rows zero), with
 // the control of ElasticCgOp: the direction and the residual formed in the
@@ -1442,6 +1502,31 @@ template void launch_elastic_cg<double>(const MeshView &, const Material &, int,
 template void launch_elastic_cg<float>(const MeshView &, const Material &, int, bool, const float *, const float *,
                                        const float *, float *, float *, float *, float *, const CGScalars &, double,
                                        hipStream_t, const hipEvent_t *);
+
+template <class T>
+void launch_elastic_pcg(const MeshView &mv, const Material &mat, int k, const T *z, const T *pin, T *pout, T *q,
+                        const CGScalars &cg, hipStream_t s) {
+    const bool nd = sizeof(T) == sizeof(float);
+    Material m2 = mat;
+    if (nd) {
+        m2.c12 = mat.c12 / mat.c11;
+        m2.c44 = mat.c44 / mat.c11;
+        m2.c11 = 1.0;
+    }
+    if (mat.rot) {
+        ElasticPcgOp<T, Aniso<T>> op{z, pin, pout, q, cg, k, mv.n, aniso_of<T>(mat, nd), 0.0,
+                                     nd ? 1.0 / mv.len_scale : 1.0};
+        run_strip<T, 3, 3>(mv, op, s);
+        return;
+    }
+    ElasticPcgOp<T> op{z, pin, pout, q, cg, k, mv.n, cubic_of<T>(m2), 0.0, nd ? 1.0 / mv.len_scale : 1.0};
+    run_strip<T, 3, 3>(mv, op, s);
+}
+
+template void launch_elastic_pcg<double>(const MeshView &, const Material &, int, const double *, const double *,
+                                         double *, double *, const CGScalars &, hipStream_t);
+template void launch_elastic_pcg<float>(const MeshView &, const Material &, int, const float *, const float *,
+                                        float *, float *, const CGScalars &, hipStream_t);
 
 void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x, double *bb,
                         hipStream_t s) {

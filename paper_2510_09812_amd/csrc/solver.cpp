@@ -241,9 +241,70 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
 
 }  // namespace
 
+// Iteration k of CG preconditioned by B on the periodic elastic system (no
+// pinned node).  At k = 0 the preconditioner first forms z_0 = B r_0 (and
+// r_0 . z_0).  Then: the matvec forms p_k = z_k + beta p_{k-1} and q = K p_k
+// with p_k . q; the update takes x += alpha p_k, r -= alpha q with |r|^2; the
+// preconditioner tests |r_{k+1}| (recording convergence as iteration k + 1)
+// and forms z_{k+1} = B r_{k+1} with r_{k+1} . z_{k+1}: restriction to the
+// grid, forward FFT, the symbol inverse mode by mode, inverse FFT,
+// prolongation with the diagonal term.  p alternates between two buffers
+// (other workgroups read p_{k-1} as halo while p_k is written).
+template <class T>
+auto pcg_iteration(gspm_ctx *c, const MeshView &mvu, T *x, T *r, T *z, T *pa, T *pb, T *q, const CGScalars &cg,
+                   double tol, int *fft_rc) {
+    return [=](int k, bool last) {
+        if (last) return;                  // |r| of the last iteration was tested by its own preconditioner pass
+        hipStream_t s = c->stream;
+        const GreenView &gv = c->pc.gv;
+        auto precond = [&](int test_k) {
+            launch_pc_restrict<T>(gv, c->n, r, cg, test_k, tol, s);
+            int rc = green_fft(c, true);
+            launch_pc_modes<T>(gv, cg, s);
+            rc = rc ? rc : green_fft(c, false);
+            launch_pc_prolong<T>(gv, c->mv, r, z, pcg_rz_at(cg, test_k), cg, s);
+            if (rc && !*fft_rc) *fft_rc = rc;
+        };
+        if (k == 0) precond(0);
+        T *pin = (k & 1) ? pa : pb, *pout = (k & 1) ? pb : pa;
+        launch_elastic_pcg<T>(mvu, c->mat, k, z, pin, pout, q, cg, s);
+        launch_pcg_update<T>(c->n, x, r, pout, q, cg, k, s);
+        precond(k + 1);
+    };
+}
+
+// The elastic solve with the Green's-operator preconditioner (elastic_precond):
+// b (the periodic right-hand side) loses its mean and |b| is recomputed, CG
+// runs with B on the periodic system (FP64, or FP64 refinement around FP32
+// inner iterations in the mixed form), and x is pinned at p0 by a translation.
+CgResult cg_elastic_green(gspm_ctx *c, double *x, double *b, double tol, int maxit, SolveKind kind) {
+    hipStream_t s = c->stream;
+    MeshView mvu = c->mv;
+    mvu.p0 = -1;
+    launch_remove_mean3(c->n, b, c->pc.aux, c->cg.bb_at(0), s);
+    auto resid = [&]() {
+        launch_elastic_matvec<double>(mvu, c->mat, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
+    };
+    auto &d = c->d;
+    int fft_rc = 0;
+    CgResult r;
+    if (c->precision == GSPM_MIXED) {
+        const double scale = 1.0 / (c->mv.len_scale * c->mat.c11);
+        r = cg_mixed(c, 3, true, x, tol, maxit, kind, scale, resid,
+                     pcg_iteration<float>(c, mvu, d.x32, d.r32, d.r32b, d.p32, d.p32b, d.q32, c->cg_in, 1.0, &fft_rc));
+    } else {
+        r = cg_fp64(c, 3, true, x, tol, maxit, kind, resid,
+                    pcg_iteration<double>(c, mvu, x, d.r, d.r2, d.p, d.p2, d.q, c->cg, tol, &fft_rc));
+    }
+    if (fft_rc && r.status == GSPM_OK) r.status = fft_rc;
+    launch_pin_shift(c->n, x, c->p0, c->pc.aux + 3 * kShards, s);
+    return r;
+}
+
 // The elastic solve runs single-reduction CG: one fused launch per iteration
 // (launch_elastic_cg), r, p and q alternating between two buffers.
 CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int maxit, SolveKind kind) {
+    if (c->p.elastic_precond == GSPM_PRECOND_GREEN) return cg_elastic_green(c, x, const_cast<double *>(b), tol, maxit, kind);
     const size_t first_pair = c->prof_used / 2;
     hipStream_t s = c->stream;
     auto resid = [&]() {
@@ -381,7 +442,14 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     // mechanical equilibrium at m^n, warm start from u^{n-1}
     hipMemcpyAsync(d.unext, d.u, bytes3, hipMemcpyDeviceToDevice, s);
     cg_prepare(c, 1);
-    launch_elastic_rhs(c->mv, c->mat, d.m, d.b, d.unext, c->cg.bb, s);
+    if (c->p.elastic_precond == GSPM_PRECOND_GREEN) {
+        // the periodic system's right-hand side: nothing pinned
+        MeshView mvu = c->mv;
+        mvu.p0 = -1;
+        launch_elastic_rhs(mvu, c->mat, d.m, d.b, d.unext, c->cg.bb, s);
+    } else {
+        launch_elastic_rhs(c->mv, c->mat, d.m, d.b, d.unext, c->cg.bb, s);
+    }
     {
         const bool net = c->warm_mode == GSPM_WARM_LEARNED && c->have_prev;
         const bool extrap = c->warm_mode != GSPM_WARM_PREVIOUS && c->commits >= 2;
