@@ -47,7 +47,8 @@ class _Params(ctypes.Structure):
                 ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0")] + [
         ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
         ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32),
-        ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9), ("elastic_precond", ctypes.c_int32)]
+        ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9), ("elastic_precond", ctypes.c_int32),
+        ("gs_precond", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -141,8 +142,8 @@ class OracleError(RuntimeError):
 def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, precession: bool = True,
                 cg_maxit: int = 10000, local_demag: bool = False) -> _Params:
     """params may carry "crystal_rot" (3 x 3, v_sample = R v_crystal, App. D)
-    and "elastic_precond" (1: the Green's-operator preconditioned elastic
-    solve)."""
+    "elastic_precond" (1: the Green's-operator preconditioned elastic
+    solve) and "gs_precond" (2: Jacobi-preconditioned GS solves)."""
     p = _Params()
     for k in ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0"):
         setattr(p, k, float(params[k]))
@@ -161,6 +162,7 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
     for i in range(9):
         p.crystal_rot[i] = rot[i]
     p.elastic_precond = int(params.get("elastic_precond", 0))
+    p.gs_precond = int(params.get("gs_precond", 0))
     return p
 
 

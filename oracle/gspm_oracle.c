@@ -682,6 +682,7 @@ int or_set_params(or_sim *s, const or_params *p) {
         return OR_E_ARG;
     }
     if (p->elastic_precond != 0 && p->elastic_precond != 1) { seterr(s, "elastic_precond must be 0 or 1"); return OR_E_ARG; }
+    if (p->gs_precond != 0 && p->gs_precond != 2) { seterr(s, "gs_precond must be 0 or 2"); return OR_E_ARG; }
     if (p->elastic_precond && !s->periodic) {
         seterr(s, "the elastic preconditioner needs a periodic mesh");
         return OR_E_ARG;
@@ -1285,11 +1286,72 @@ int or_precond_grid(const or_sim *s, int32_t g[3]) {
 
 void or_set_precond_omega(or_sim *s, double omega) { s->gpc_omega = omega; }
 
-/* One scalar GS solve (eps K + M) x = b on the magnetic nodes (Eq. weak_GS). */
+/* CG preconditioned by the inverse diagonal dinv on the DOFs not marked
+ * fixed (identity rows, zero right-hand side), with the recurrence-residual
+ * stopping rule ||r|| <= tol ||b|| of plain CG. */
+static int pcg_diag(const or_sim *s, apply_fn A, const void *ctx, int len, const uint8_t *fixed, const double *dinv,
+                    const double *b_in, double *x, double tol, int maxit, int *iters) {
+    double *b = (double *)malloc(sizeof(double) * (size_t)len), *r = (double *)malloc(sizeof(double) * (size_t)len);
+    double *z = (double *)malloc(sizeof(double) * (size_t)len), *p = (double *)malloc(sizeof(double) * (size_t)len);
+    double *q = (double *)malloc(sizeof(double) * (size_t)len);
+    for (int i = 0; i < len; ++i) {
+        b[i] = fixed[i] ? 0.0 : b_in[i];
+        if (fixed[i]) x[i] = 0.0;
+    }
+    int rc = OR_OK, k = 0;
+    double bb = dot(b, b, len);
+    if (bb == 0.0) {
+        for (int i = 0; i < len; ++i) x[i] = 0.0;
+        goto done;
+    }
+    A(s, ctx, x, q);
+    for (int i = 0; i < len; ++i) {
+        r[i] = fixed[i] ? 0.0 : b[i] - q[i];
+        z[i] = fixed[i] ? 0.0 : dinv[i] * r[i];
+        p[i] = z[i];
+    }
+    double rr = dot(r, r, len), rz = dot(r, z, len), thr = tol * tol * bb;
+    while (rr > thr) {
+        if (k >= maxit) { rc = OR_E_NOCONV; break; }
+        A(s, ctx, p, q);
+        for (int i = 0; i < len; ++i)
+            if (fixed[i]) q[i] = 0.0;
+        double alpha = rz / dot(p, q, len);
+        for (int i = 0; i < len; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+        ++k;
+        rr = dot(r, r, len);
+        if (!isfinite(rr)) { rc = OR_E_NONFINITE; break; }
+        if (rr <= thr) break;
+        for (int i = 0; i < len; ++i) z[i] = fixed[i] ? 0.0 : dinv[i] * r[i];
+        double rz_new = dot(r, z, len), beta = rz_new / rz;
+        for (int i = 0; i < len; ++i) p[i] = z[i] + beta * p[i];
+        rz = rz_new;
+    }
+done:
+    *iters = k;
+    free(b); free(r); free(z); free(p); free(q);
+    return rc;
+}
+
+/* One scalar GS solve (eps K + M) x = b on the magnetic nodes (Eq. weak_GS);
+ * with gs_precond = 2, CG preconditioned by the inverse of the operator's
+ * diagonal (Jacobi), the same stopping rule. */
 static int solve_gs(const or_sim *s, double eps, const double *b, double *x, double tol, int maxit, int *iters) {
     uint8_t *fixed = (uint8_t *)malloc((size_t)s->n);
     for (int i = 0; i < s->n; ++i) fixed[i] = !s->mag[i];
-    int rc = cg(s, cg_apply_gs, &eps, s->n, fixed, b, x, tol, maxit, iters);
+    int rc;
+    if (s->p.gs_precond == 2) {
+        double *dinv = (double *)malloc(sizeof(double) * (size_t)s->n);
+        for (int i = 0; i < s->n; ++i) {
+            int self = find_col(s, i, i);
+            double d = eps * s->Kmag[self] + s->Mmag[self];
+            dinv[i] = fixed[i] ? 0.0 : 1.0 / d;
+        }
+        rc = pcg_diag(s, cg_apply_gs, &eps, s->n, fixed, dinv, b, x, tol, maxit, iters);
+        free(dinv);
+    } else {
+        rc = cg(s, cg_apply_gs, &eps, s->n, fixed, b, x, tol, maxit, iters);
+    }
     free(fixed);
     return rc;
 }

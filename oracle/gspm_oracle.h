@@ -33,6 +33,7 @@ typedef struct {
     double crystal_rot[9]; /* R of App. D, row-major: v_sample = R v_crystal; all zeros = identity */
     int32_t elastic_precond; /* 1: elastic solves by CG with the Green's-operator preconditioner (periodic
                                 system, pinned by translation afterwards); 0: plain CG on the pinned system */
+    int32_t gs_precond;    /* 2: GS solves by CG preconditioned with the operator's diagonal (Jacobi); 0: plain */
 } or_params;
 
 typedef struct {

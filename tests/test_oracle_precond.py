@@ -182,3 +182,88 @@ def test_green_step_reproduces_the_plain_step():
     assert np.abs(m1 - m0).max() < 1e-10
     assert np.abs(u1 - u0).max() < 1e-9 * np.abs(u0).max()
     assert it1 < it0 / 3
+
+
+# ------------------------------------------- Jacobi-preconditioned GS solves
+
+def _gs_case(n, seed, jitter=0.15, sphere=0.3):
+    case = w.small_cube(n, seed=seed, L=(n - 1) * H_BENCH, jitter=jitter, sphere=sphere)
+    p = dict(case.params)
+    dtau = p["gamma0"] * p["Ms"] * 1e-11
+    eps = 2 * p["A"] / (p["mu0"] * p["Ms"] ** 2) * dtau
+    return case, p, eps
+
+
+def _gs_oracles(case, p):
+    out = []
+    for gp in (0, 2):
+        orc = O.Oracle.from_mesh(case.mesh)
+        q = dict(p); q["gs_precond"] = gp
+        orc.set_params(q)
+        out.append(orc)
+    return out
+
+
+def test_gs_jacobi_matches_dense_solve():
+    case, p, eps = _gs_case(7, 91, sphere=0.35)
+    plain, jac = _gs_oracles(case, p)
+    rng = np.random.default_rng(11)
+    mag = jac.lumped_weights() > 0
+    assert (~mag).any()
+    b = rng.standard_normal((jac.n, 3)) * mag[:, None]
+    xj, _ = jac.solve(O.OP_GS, b, eps=eps, tol=1e-13)
+    n = jac.n
+    A = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros((n, 3)); e[j, 0] = 1.0
+        A[:, j] = jac.apply(O.OP_GS, e, eps)[:, 0]
+    for c in range(3):
+        xd = np.zeros(n)
+        xd[mag] = np.linalg.solve(A[np.ix_(mag, mag)], b[mag, c])
+        assert np.abs(xj[:, c] - xd).max() < 1e-10 * np.abs(xd).max()
+    assert np.abs(xj[~mag]).max() == 0.0
+
+
+def test_gs_jacobi_with_a_constant_diagonal_is_plain_cg():
+    """On the regular lattice without inclusions the GS operator's diagonal is
+    one constant, so Jacobi-preconditioned CG is plain CG rescaled: the same
+    iteration count (within one, where rounding moves the test's crossing)."""
+    case, p, eps = _gs_case(8, 92, jitter=0.0, sphere=0.0)
+    plain, jac = _gs_oracles(case, p)
+    rng = np.random.default_rng(12)
+    b = rng.standard_normal((jac.n, 3))
+    for tol in (1e-6, 1e-10):
+        xp, itp = plain.solve(O.OP_GS, b, eps=eps, tol=tol)
+        xj, itj = jac.solve(O.OP_GS, b, eps=eps, tol=tol)
+        assert abs(itp - itj) <= 3, (tol, itp, itj)       # three components summed
+        assert np.abs(xj - xp).max() < 10 * tol * np.abs(xp).max()
+
+
+def test_gs_jacobi_cuts_iterations_on_jittered_meshes_with_inclusions():
+    case, p, eps = _gs_case(16, 93)
+    plain, jac = _gs_oracles(case, p)
+    rng = np.random.default_rng(13)
+    mag = jac.lumped_weights() > 0
+    b = rng.standard_normal((jac.n, 3)) * mag[:, None]
+    xp, itp = plain.solve(O.OP_GS, b, eps=eps, tol=1e-8)
+    xj, itj = jac.solve(O.OP_GS, b, eps=eps, tol=1e-8)
+    print(f"GS solves (3 components): plain CG {itp} iterations, Jacobi PCG {itj}")
+    assert itj < 0.75 * itp
+    assert np.abs(xj - xp).max() < 1e-6 * np.abs(xp).max()
+
+
+def test_gs_jacobi_step_reproduces_the_plain_step():
+    case, p, eps = _gs_case(7, 94)
+    out = []
+    for gp in (0, 2):
+        orc = O.Oracle.from_mesh(case.mesh)
+        q = dict(p); q["cg_tol"] = 1e-12; q["gs_precond"] = gp
+        orc.set_params(q, hext=(-2e5, 0.0, 0.0))
+        orc.set_m(case.m0)
+        st = orc.step(1e-11, 3)
+        out.append((orc.get_m(), orc.get_u(), sum(st["gs_iters"])))
+    (m0, u0, it0), (m1, u1, it1) = out
+    print(f"GS iterations over 3 steps: plain {it0}, Jacobi {it1}")
+    assert np.abs(m1 - m0).max() < 1e-10
+    assert np.abs(u1 - u0).max() < 1e-9 * np.abs(u0).max()
+    assert it1 < it0
