@@ -170,6 +170,8 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start path")
     ap.add_argument("--no-rotated", action="store_true",
                     help="skip the path with the crystal rotated to the <111> frame of App. D")
+    ap.add_argument("--only", default="",
+                    help="comma-separated path names to run (for profiling one path), e.g. mixed+precond")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the paths with the Green's-operator preconditioned elastic solve")
     ap.add_argument("--no-local-demag", action="store_true",
@@ -216,6 +218,7 @@ def main() -> int:
             params["crystal_rot"] = R111
         if precond:
             params["elastic_precond"] = gspm.GSPM_PRECOND_GREEN
+            params["gs_precond"] = gspm.GSPM_PRECOND_JACOBI
         sim = gspm.Simulation(case.mesh, params, hext=case.hext, device=0, profile=False,
                               block_nodes=args.block_nodes, precision=precision, local_demag=local_demag)
         sim.set_m(case.m0)
@@ -261,26 +264,35 @@ def main() -> int:
         sim.close()
         return out
 
-    paths = {}
-    if args.precision in ("fp64", "both"):
-        paths["fp64"] = run_path(gspm.GSPM_FP64)
-    if args.precision in ("mixed", "both"):
-        paths["mixed"] = run_path(gspm.GSPM_MIXED)
+    specs = [("fp64", dict(precision=gspm.GSPM_FP64)), ("mixed", dict(precision=gspm.GSPM_MIXED))]
+    if not args.no_learned:
+        specs.append(("mixed+extrapolated", dict(precision=gspm.GSPM_MIXED, warm=gspm.GSPM_WARM_EXTRAPOLATE)))
+    if weights is not None:
+        specs.append(("mixed+learned", dict(precision=gspm.GSPM_MIXED, warm=gspm.GSPM_WARM_LEARNED)))
+    if not args.no_precond:
+        specs += [("fp64+precond", dict(precision=gspm.GSPM_FP64, precond=True)),
+                  ("mixed+precond", dict(precision=gspm.GSPM_MIXED, precond=True))]
         if not args.no_learned:
-            paths["mixed+extrapolated"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_EXTRAPOLATE)
+            specs.append(("mixed+extrapolated+precond", dict(precision=gspm.GSPM_MIXED,
+                                                             warm=gspm.GSPM_WARM_EXTRAPOLATE, precond=True)))
         if weights is not None:
-            paths["mixed+learned"] = run_path(gspm.GSPM_MIXED, gspm.GSPM_WARM_LEARNED)
-    if not args.no_precond and args.precision in ("fp64", "both"):
-        paths["fp64+precond"] = run_path(gspm.GSPM_FP64, precond=True)
-    if not args.no_precond and args.precision in ("mixed", "both"):
-        paths["mixed+precond"] = run_path(gspm.GSPM_MIXED, precond=True)
-    if not args.no_rotated and args.precision == "both":
-        paths["fp64+rotated111"] = run_path(gspm.GSPM_FP64, rotated=True)
-        paths["mixed+rotated111"] = run_path(gspm.GSPM_MIXED, rotated=True)
-    if not args.no_local_demag and args.precision == "both":
-        paths["fp64+local_demag"] = run_path(gspm.GSPM_FP64, local_demag=True)
-        paths["mixed+local_demag"] = run_path(gspm.GSPM_MIXED, local_demag=True)
-    head_name = next(k for k in ("mixed+learned", "mixed", "fp64") if k in paths)
+            specs.append(("mixed+learned+precond", dict(precision=gspm.GSPM_MIXED, warm=gspm.GSPM_WARM_LEARNED,
+                                                        precond=True)))
+    if not args.no_rotated:
+        specs += [("fp64+rotated111", dict(precision=gspm.GSPM_FP64, rotated=True)),
+                  ("mixed+rotated111", dict(precision=gspm.GSPM_MIXED, rotated=True))]
+    if not args.no_local_demag:
+        specs += [("fp64+local_demag", dict(precision=gspm.GSPM_FP64, local_demag=True)),
+                  ("mixed+local_demag", dict(precision=gspm.GSPM_MIXED, local_demag=True))]
+    only = set(args.only.split(",")) if args.only else None
+    paths = {}
+    for name, kw in specs:
+        if args.precision != "both" and not name.startswith(args.precision):
+            continue
+        if only is not None and name not in only:
+            continue
+        paths[name] = run_path(**kw)
+    head_name = next((k for k in ("mixed+learned", "mixed", "fp64") if k in paths), next(iter(paths)))
     head = paths[head_name]
     mixed = head_name.startswith("mixed")
     info, st, wall, value = head["info"], head["st"], head["wall"], head["value"]

@@ -85,8 +85,9 @@ typedef enum {
 
 typedef enum {
     GSPM_PRECOND_NONE = 0,  /* the paper's unpreconditioned CG on the pinned system (Sec. 2.5) */
-    GSPM_PRECOND_GREEN = 1  /* CG on the periodic system preconditioned by the lattice Green's operator of the
+    GSPM_PRECOND_GREEN = 1, /* CG on the periodic system preconditioned by the lattice Green's operator of the
                                stiffness on an auxiliary grid; pinned by a translation afterwards */
+    GSPM_PRECOND_JACOBI = 2 /* CG preconditioned by the operator's diagonal */
 } gspm_precond;
 
 #define GSPM_PERIODIC 1u
@@ -141,6 +142,9 @@ typedef struct {
                                component removed, K u = b tested as ||b - K u|| <= cg_tol ||b||) and pins the
                                caller's node 0 by a translation at the end.  Sec. 5.2 names the elastic CG as
                                the cost to cut; the paper does not precondition it. */
+    int32_t gs_precond;     /* GSPM_PRECOND_NONE or GSPM_PRECOND_JACOBI: the GS solves of Eq. (weak_GS) (the
+                               step's and gspm_solve's) by CG preconditioned with D = diag(eps K + M), the
+                               same stopping rule; nodes in the inclusions only keep their identity rows */
 } gspm_params;
 
 typedef struct {

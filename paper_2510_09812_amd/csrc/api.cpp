@@ -203,6 +203,8 @@ void gspm_ctx::release_mesh() {
     dev_free(this, b.cgi_flags);
     dev_free(this, b.mprev); dev_free(this, b.uprev); dev_free(this, b.du_prev); dev_free(this, b.kdu); dev_free(this, b.wred); dev_free(this, b.wcoef);
     dev_free(this, b.ud); dev_free(this, b.udnext); dev_free(this, b.rep);
+    dev_free(this, b.cg_rz); dev_free(this, b.cgi_rz); dev_free(this, b.jkd); dev_free(this, b.jmd);
+    dev_free(this, b.jkd32); dev_free(this, b.jmd32);
     if (arena) hipFree(arena);
     arena = nullptr;
     arena_size = arena_used = 0;
@@ -354,6 +356,9 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
         rc = rc ? rc : dev_alloc(c, &d.ud, n);
         rc = rc ? rc : dev_alloc(c, &d.udnext, n);
         rc = rc ? rc : dev_alloc(c, &d.rep, n);
+        rc = rc ? rc : dev_alloc(c, &d.cg_rz, static_cast<size_t>(kMaxComp) * kRing * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.jkd, n);
+        rc = rc ? rc : dev_alloc(c, &d.jmd, n);
         rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kMrSums) * kShards);
         rc = rc ? rc : dev_alloc(c, &d.wcoef, 2);
         rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
@@ -376,6 +381,9 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
             rc = rc ? rc : dev_alloc(c, &d.cgi_pq, static_cast<size_t>(kMaxComp) * kRing * kShards);
             rc = rc ? rc : dev_alloc(c, &d.cgi_bb, static_cast<size_t>(kMaxComp) * kShards);
             rc = rc ? rc : dev_alloc(c, &d.cgi_flags, 2 * kMaxComp);
+            rc = rc ? rc : dev_alloc(c, &d.cgi_rz, static_cast<size_t>(kMaxComp) * kRing * kShards);
+            rc = rc ? rc : dev_alloc(c, &d.jkd32, n);
+            rc = rc ? rc : dev_alloc(c, &d.jmd32, n);
         }
         return rc;
     };
@@ -406,6 +414,56 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     hipMemcpyAsync(d.blk_ptr, hm.blk_ptr.data(), sizeof(int32_t) * hm.blk_ptr.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.blk_nmag, hm.blk_nmag.data(), sizeof(int32_t) * hm.blk_nmag.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.w, hm.w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
+    {
+        // diagonals of the GS operator's parts (magnetic elements): K_ii = sum V |grad lambda_i|^2,
+        // M_ii = sum V / 10; Jacobi preconditioning takes D = eps K_ii + M_ii
+        std::vector<double> kd(n, 0.0), md(n, 0.0);
+        const double Lb[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+        for (int64_t e = 0; e < n_tets; ++e) {
+            if (!tags[e]) continue;
+            const int32_t *t = tets + 4 * e;
+            double E[3][3];
+            for (int k = 0; k < 3; ++k)
+                for (int a = 0; a < 3; ++a) {
+                    double dv = xyz[3 * static_cast<int64_t>(t[k + 1]) + a] - xyz[3 * static_cast<int64_t>(t[0]) + a];
+                    dv -= Lb[a] * std::nearbyint(dv / Lb[a]);
+                    E[k][a] = dv;
+                }
+            double cf[3][3];
+            for (int k = 0; k < 3; ++k) {
+                const double *a = E[(k + 1) % 3], *bb = E[(k + 2) % 3];
+                cf[k][0] = a[1] * bb[2] - a[2] * bb[1];
+                cf[k][1] = a[2] * bb[0] - a[0] * bb[2];
+                cf[k][2] = a[0] * bb[1] - a[1] * bb[0];
+            }
+            const double det = E[0][0] * cf[0][0] + E[0][1] * cf[0][1] + E[0][2] * cf[0][2];
+            const double V = std::fabs(det) / 6.0;
+            double g[4][3];
+            for (int k = 0; k < 3; ++k)
+                for (int a = 0; a < 3; ++a) g[k + 1][a] = cf[k][a] / det;
+            for (int a = 0; a < 3; ++a) g[0][a] = -(g[1][a] + g[2][a] + g[3][a]);
+            for (int j = 0; j < 4; ++j) {
+                const size_t node = static_cast<size_t>(hm.user2int[t[j]]);
+                kd[node] += V * (g[j][0] * g[j][0] + g[j][1] * g[j][1] + g[j][2] * g[j][2]);
+                md[node] += V / 10.0;
+            }
+        }
+        hipMemcpyAsync(d.jkd, kd.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(d.jmd, md.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
+        if (c->precision == GSPM_MIXED) {
+            const double ls = std::cbrt(hm.vc / static_cast<double>(hm.ne));
+            std::vector<float> k32(n), m32(n);
+            for (size_t i = 0; i < n; ++i) {
+                k32[i] = static_cast<float>(kd[i] / ls);
+                m32[i] = static_cast<float>(md[i] / (ls * ls * ls));
+            }
+            hipMemcpyAsync(d.jkd32, k32.data(), sizeof(float) * n, hipMemcpyHostToDevice, s);
+            hipMemcpyAsync(d.jmd32, m32.data(), sizeof(float) * n, hipMemcpyHostToDevice, s);
+            hipStreamSynchronize(s);
+        } else {
+            hipStreamSynchronize(s);
+        }
+    }
     std::vector<int32_t> rep(n, -1);
     for (int64_t i = hm.n0 - 1; i >= 0; --i) rep[static_cast<size_t>(hm.user2int[i])] = static_cast<int32_t>(i);
     hipMemcpyAsync(d.rep, rep.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
@@ -477,6 +535,7 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->cg.bb = d.cg_bb;
     c->cg.rq = d.cg_rq;
     c->cg.qq = d.cg_qq;
+    c->cg.rz = d.cg_rz;
     c->cg.done = d.cg_flags;
     c->cg.iters = d.cg_flags + kMaxComp;
     c->cg.ring = kRing;
@@ -485,6 +544,7 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->cg_in.bb = d.cgi_bb;
     c->cg_in.rq = d.cgi_rq;
     c->cg_in.qq = d.cgi_qq;
+    c->cg_in.rz = d.cgi_rz;
     c->cg_in.done = d.cgi_flags;
     c->cg_in.iters = d.cgi_flags ? d.cgi_flags + kMaxComp : nullptr;
     c->cg_in.ring = kRing;
@@ -515,6 +575,8 @@ gspm_status gspm_set_params(gspm_ctx *c, const gspm_params *p) {
     if (p->local_demag != 0 && p->local_demag != 1) return fail(c, GSPM_E_ARG, "set_params: local_demag must be 0 or 1");
     if (p->elastic_precond != GSPM_PRECOND_NONE && p->elastic_precond != GSPM_PRECOND_GREEN)
         return fail(c, GSPM_E_ARG, "set_params: unknown elastic_precond");
+    if (p->gs_precond != GSPM_PRECOND_NONE && p->gs_precond != GSPM_PRECOND_JACOBI)
+        return fail(c, GSPM_E_ARG, "set_params: gs_precond must be GSPM_PRECOND_NONE or GSPM_PRECOND_JACOBI");
     double R[9];
     bool zero = true, ident = true;
     for (int k = 0; k < 9; ++k) {

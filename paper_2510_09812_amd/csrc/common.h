@@ -122,12 +122,16 @@ struct CGScalars {
     double *pq;                   // [comp][ring][kShards]: p_k . A p_k
     double *bb;                   // [comp][kShards]: b . b
     double *rq, *qq;              // [ring][kShards]: r_k . A p_k, |A p_k|^2 (single-reduction CG, one scalar set)
+    double *rz;                   // [comp][ring][kShards]: r_k . D^-1 r_k (Jacobi-preconditioned GS solves)
     int32_t *done;                // [comp]: 0 running, 1 converged, 2 broke down (non-finite)
     int32_t *iters;               // [comp]: iterations at convergence
     int32_t ring;
 
     __host__ __device__ double *rr_at(int c, int k) const {
         return rr + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
+    }
+    __host__ __device__ double *rz_at(int c, int k) const {
+        return rz + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
     }
     __host__ __device__ double *pq_at(int c, int k) const {
         return pq + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
@@ -157,7 +161,8 @@ struct GreenView {
     int32_t gx, gy, gz, gxh;      // grid points per axis; gxh = gx / 2 + 1 (half spectrum along x)
     int64_t G, Gh;                // grid points, half-spectrum modes (gz x gy x gxh)
     double lo[3], h[3];           // grid origin and spacing
-    const int32_t *rptr, *rnode;  // restriction lists: grid point g gathers (rnode, rw)[rptr[g] .. rptr[g + 1])
+    const int32_t *rptr, *rnode;  // restriction lists: row t gathers (rnode, rw)[rptr[t] .. rptr[t + 1])
+    const int32_t *rgrid;         // the grid point of row t (rows run in Morton order of the grid points)
     const void *rw;               // their weights (T)
     const void *dinv;             // [3][n] omega / diag(K^mech) (T)
     const void *ainv;             // [Gh][9] A(k)^-1 / G, Hermitian: re a00 a11 a22, then a01 a02 a12 (re, im) (T)
@@ -264,9 +269,18 @@ template <class T>
 void launch_elastic_cg(const MeshView &mv, const Material &mat, int k, bool last, const T *rin, const T *pin,
                        const T *qin, T *rout, T *pout, T *qout, T *x, const CGScalars &cg, double tol, hipStream_t s,
                        const hipEvent_t *ev = nullptr);
+// jkd, jmd (nullable): Jacobi preconditioning with D = eps jkd + mass jmd per
+// node (zero rows stay zero): ITER forms p = D^-1 r + beta p with beta =
+// rz[k] / rz[k-1] (the test still on |r|), and at k = 0 adds r . D^-1 r to rz[0].
 template <class T>
 void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
-                      const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s);
+                      const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s,
+                      const T *jkd = nullptr, const T *jmd = nullptr);
+// The Jacobi-preconditioned GS iteration's update: alpha = rz[k] / pq[k];
+// x += alpha p; r -= alpha q; rr[k+1] += r.r; rz[k+1] += r . D^-1 r.
+template <class T>
+void launch_cg_update_jacobi(int n, int nc, T *x, T *r, const T *p, const T *q, const T *jkd, const T *jmd,
+                             double eps, const CGScalars &cg, int k, hipStream_t s);
 // K^ms (Laplacian over all elements) on nc = 1 or 3 components, rows of the
 // pinned node zero; modes as above.  FP32: A' = K^ms / len_scale^3.
 // One launch of single-reduction CG on K^ms (one component), with the

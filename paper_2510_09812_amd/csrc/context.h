@@ -49,6 +49,9 @@ struct DeviceBuffers {
     double *wcoef = nullptr;      // 2: coefficients of the last minimum-residual start
     double *ud = nullptr, *udnext = nullptr;   // n: local magnetostatic potential (committed, in progress)
     int32_t *rep = nullptr;       // n: the first caller node of each unique node
+    double *cg_rz = nullptr, *cgi_rz = nullptr;   // r . D^-1 r rings of the Jacobi-preconditioned GS solves
+    double *jkd = nullptr, *jmd = nullptr;        // n: diagonals of K and M over magnetic elements
+    float *jkd32 = nullptr, *jmd32 = nullptr;     // n: the same for the FP32 operator (K / len_scale, M / len_scale^3)
 };
 
 // Device state of the learned warm start (allocated on first use).
@@ -76,7 +79,7 @@ struct GreenState {
     bool mesh_ready = false, sym_ready = false;
     double sym_key[37] = {};      // the Voigt stiffness (36) and scale the symbol and diagonal were built for
     GreenView gv{};
-    int32_t *rptr = nullptr, *rnode = nullptr;
+    int32_t *rptr = nullptr, *rgrid = nullptr, *rnode = nullptr;
     void *rw = nullptr, *dinv = nullptr, *ainv = nullptr, *grid = nullptr, *spec = nullptr, *work = nullptr;
     double *aux = nullptr;        // 3 x kShards: mean sums; then 3: the pinned node's shift
     size_t work_bytes = 0;
@@ -122,7 +125,11 @@ struct gspm_ctx {
     gspm_params p{};
     gspm::Material mat{};
     gspm::DeriveArgs dargs{};
-    int predict[gspm::SK_COUNT] = {32, 8, 8, 8, 16, 32};
+    // iteration counts of the last solve of each kind (first inner solve of a
+    // mixed-form solve, or any later one), which size the first batch
+    int predict[gspm::SK_COUNT][2] = {{32, 8}, {8, 4}, {8, 4}, {8, 4}, {16, 8}, {32, 8}};
+    int refine_slot = 0;                  // 1 while a mixed-form solve runs its second or later inner solve
+    bool heavy_iter = false;              // the running solve's iterations are costly (preconditioned): short batches
 
     // learned warm start
     gspm::MpnnState nn;

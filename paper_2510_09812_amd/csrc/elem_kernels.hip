@@ -469,7 +469,7 @@ __device__ __forceinline__ void vertex3(const Staged<T, NC, NF> &st, int k0, con
 // the direction coefficient beta_k = rr[k] / rr[k-1].
 template <int NS>
 __device__ __forceinline__ bool cg_direction_scalars(const CGScalars &cg, int k, double tol2, int (&live)[NS],
-                                                     double (&beta)[NS]) {
+                                                     double (&beta)[NS], bool jacobi = false) {
     __shared__ int32_t flags[NS];
     if (threadIdx.x == 0)
         for (int s = 0; s < NS; ++s) flags[s] = cg.done[s];
@@ -484,14 +484,21 @@ __device__ __forceinline__ bool cg_direction_scalars(const CGScalars &cg, int k,
         for (int s = 0; s < NS; ++s) any |= live[s] != 0;
         return any;
     }
+    // with Jacobi preconditioning beta comes from r . D^-1 r (the test stays on |r|)
     const double *src[3 * NS];
     for (int s = 0; s < NS; ++s) {
         src[s] = cg.rr_at(s, k);
-        src[NS + s] = cg.rr_at(s, k - 1);
+        src[NS + s] = jacobi ? cg.rz_at(s, k - 1) : cg.rr_at(s, k - 1);
         src[2 * NS + s] = cg.bb_at(s);
     }
     double t[3 * NS];
     shard_totals<3 * NS>(src, t);
+    double rzk[NS];
+    if (jacobi) {
+        const double *src2[NS];
+        for (int s = 0; s < NS; ++s) src2[s] = cg.rz_at(s, k);
+        shard_totals<NS>(src2, rzk);
+    }
     bool any = false;
     int stop[NS];
     for (int s = 0; s < NS; ++s) {
@@ -500,7 +507,7 @@ __device__ __forceinline__ bool cg_direction_scalars(const CGScalars &cg, int k,
         const double rrk = t[s];
         if (!isfinite(rrk)) stop[s] = 2;
         else if (rrk <= tol2 * t[2 * NS + s]) stop[s] = 1;
-        else beta[s] = rrk / t[NS + s];
+        else beta[s] = (jacobi ? rzk[s] : rrk) / t[NS + s];
         if (stop[s]) live[s] = 0;
         any |= live[s] != 0;
     }
@@ -965,9 +972,15 @@ struct GsMatvecOp {
     int live[NC];
     double beta[NC];
     double coord_scale;
+    const T *jkd = nullptr, *jmd = nullptr;   // Jacobi: D = eps jkd + mass jmd (null: plain CG)
+
+    __device__ __forceinline__ T jacobi_z(const T rv, int g) const {
+        const T d = eps * jkd[g] + mass * jmd[g];
+        return d > T(0) ? rv / d : T(0);
+    }
 
     __device__ bool prepare(const MeshView &, int) {
-        if (mode == MV_ITER) return cg_direction_scalars<NC>(cg, k, tol2, live, beta);
+        if (mode == MV_ITER) return cg_direction_scalars<NC>(cg, k, tol2, live, beta, jkd != nullptr);
         bool any = false;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -983,9 +996,14 @@ struct GsMatvecOp {
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const size_t o = static_cast<size_t>(q) * n + g;
-            if (!live[q]) v[q] = T(0);
-            else if (mode == MV_ITER) v[q] = (k == 0) ? r[o] : r[o] + static_cast<T>(beta[q]) * in[o];
-            else v[q] = in[o];
+            if (!live[q]) {
+                v[q] = T(0);
+            } else if (mode == MV_ITER) {
+                const T z = jkd ? jacobi_z(r[o], g) : r[o];
+                v[q] = (k == 0) ? z : z + static_cast<T>(beta[q]) * in[o];
+            } else {
+                v[q] = in[o];
+            }
         }
     }
 
@@ -1024,9 +1042,11 @@ struct GsMatvecOp {
 
     template <int NF>
     __device__ void finish(const MeshView &mv, const Staged<T, NC, NF> &st, int n0, int cnt) const {
-        double part[NC];
+        double part[NC], part2[NC];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) part[q] = 0.0;
+        for (int q = 0; q < NC; ++q) part[q] = part2[q] = 0.0;
+        // Jacobi at k = 0: p_0 = D^-1 r_0, so r_0 . D^-1 r_0 = r_0 . p_0
+        const bool rz0 = jkd != nullptr && mode == MV_ITER && k == 0;
         for (int i = threadIdx.x; i < cnt; i += kThreads) {
             const int node = n0 + i;
 #pragma unroll
@@ -1043,13 +1063,18 @@ struct GsMatvecOp {
                     pout[o] = pv;
                     out[o] = av;
                     part[q] += static_cast<double>(pv) * av;
+                    if (rz0) part2[q] += static_cast<double>(r[o]) * pv;
                 } else {
                     out[o] = av;
                 }
             }
         }
-        if (mode == MV_ITER) block_atomic_add<NC>(part, cg.pq_at(0, k), cg.comp_stride());
-        else if (mode == MV_RESID) block_atomic_add<NC>(part, cg.rr_at(0, 0), cg.comp_stride());
+        if (mode == MV_ITER) {
+            block_atomic_add<NC>(part, cg.pq_at(0, k), cg.comp_stride());
+            if (rz0) block_atomic_add<NC>(part2, cg.rz_at(0, 0), cg.comp_stride());
+        } else if (mode == MV_RESID) {
+            block_atomic_add<NC>(part, cg.rr_at(0, 0), cg.comp_stride());
+        }
     }
 };
 
@@ -1539,25 +1564,26 @@ void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m
 // on coordinates divided by len_scale.
 template <class T>
 void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
-                      const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s) {
+                      const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s,
+                      const T *jkd, const T *jmd) {
     const bool nd = sizeof(T) == sizeof(float);
     const double sc = nd ? 1.0 / mv.len_scale : 1.0;
     const int md = static_cast<int>(mode);
     const double t2 = tol * tol;
     const T e = static_cast<T>(eps * sc * sc), ms = static_cast<T>(mass);
     switch (nc) {
-        case 1: run_strip<T, 1, 1>(mv, GsMatvecOp<T, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc}, s); break;
-        case 2: run_strip<T, 2, 2>(mv, GsMatvecOp<T, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0}, {0.0, 0.0}, sc}, s); break;
-        default: run_strip<T, 3, 3>(mv, GsMatvecOp<T, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0}, {0.0, 0.0, 0.0}, sc}, s); break;
+        case 1: run_strip<T, 1, 1>(mv, GsMatvecOp<T, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc, jkd, jmd}, s); break;
+        case 2: run_strip<T, 2, 2>(mv, GsMatvecOp<T, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0}, {0.0, 0.0}, sc, jkd, jmd}, s); break;
+        default: run_strip<T, 3, 3>(mv, GsMatvecOp<T, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0}, {0.0, 0.0, 0.0}, sc, jkd, jmd}, s); break;
     }
 }
 
 template void launch_gs_matvec<double>(const MeshView &, int, double, double, MatvecMode, const double *, double *,
                                        const double *, const double *, double *, const CGScalars &, int, double,
-                                       hipStream_t);
+                                       hipStream_t, const double *, const double *);
 template void launch_gs_matvec<float>(const MeshView &, int, double, double, MatvecMode, const float *, float *,
                                       const float *, const float *, float *, const CGScalars &, int, double,
-                                      hipStream_t);
+                                      hipStream_t, const float *, const float *);
 
 // K^ms on the same strips (all segments), eps = 1 and no mass; FP32 uses the
 // GS operator's scaling, A' = K^ms / len_scale^3.

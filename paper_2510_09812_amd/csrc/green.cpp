@@ -192,20 +192,43 @@ int setup_mesh_part(gspm_ctx *c) {
                                                    ((cc & 4) ? t[2] : 1.0 - t[2]);
         }
     }
+    // rows of the restriction run over the grid points in Morton order (the
+    // nodes are Morton-numbered, so consecutive rows gather nearby nodes)
+    auto spread = [](uint64_t v) {
+        uint64_t x = v & 0x1FFFFFu;
+        x = (x | (x << 32)) & 0x1F00000000FFFFull;
+        x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+        x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+        x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+        x = (x | (x << 2)) & 0x1249249249249249ull;
+        return x;
+    };
+    std::vector<std::pair<uint64_t, int32_t>> order(static_cast<size_t>(gv.G));
+    for (int64_t q = 0; q < gv.G; ++q) {
+        const uint64_t ix = q % g[0], iy = (q / g[0]) % g[1], iz = q / (static_cast<int64_t>(g[0]) * g[1]);
+        order[q] = {spread(ix) | (spread(iy) << 1) | (spread(iz) << 2), static_cast<int32_t>(q)};
+    }
+    std::sort(order.begin(), order.end());
+    std::vector<int32_t> row_of(static_cast<size_t>(gv.G)), rgrid(static_cast<size_t>(gv.G));
+    for (int64_t t = 0; t < gv.G; ++t) {
+        rgrid[t] = order[t].second;
+        row_of[static_cast<size_t>(order[t].second)] = static_cast<int32_t>(t);
+    }
     std::vector<int32_t> ptr(static_cast<size_t>(gv.G) + 1, 0), node(8 * static_cast<size_t>(n));
-    for (int64_t q : gidx) ++ptr[static_cast<size_t>(q) + 1];
+    for (int64_t q : gidx) ++ptr[static_cast<size_t>(row_of[static_cast<size_t>(q)]) + 1];
     for (int64_t q = 0; q < gv.G; ++q) ptr[q + 1] += ptr[q];
     std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
     std::vector<double> w64(8 * static_cast<size_t>(n));
     for (int i = 0; i < n; ++i)      // nodes in order within each list
         for (int cc = 0; cc < 8; ++cc) {
             const size_t e = 8 * static_cast<size_t>(i) + cc;
-            const int32_t slot = fill[static_cast<size_t>(gidx[e])]++;
+            const int32_t slot = fill[static_cast<size_t>(row_of[static_cast<size_t>(gidx[e])])]++;
             node[slot] = i;
             w64[slot] = wts[e];
         }
     const size_t tb = f32 ? sizeof(float) : sizeof(double);
     rc = pc_alloc(c, &pc.rptr, ptr.size());
+    if (!rc) rc = pc_alloc(c, &pc.rgrid, rgrid.size());
     if (!rc) rc = pc_alloc(c, &pc.rnode, node.size());
     if (!rc) rc = pc_alloc(c, reinterpret_cast<char **>(&pc.rw), tb * w64.size());
     if (!rc) rc = pc_alloc(c, reinterpret_cast<char **>(&pc.dinv), tb * 3 * static_cast<size_t>(n));
@@ -216,6 +239,7 @@ int setup_mesh_part(gspm_ctx *c) {
     if (rc) return rc;
     hipMemcpyAsync(pc.rptr, ptr.data(), sizeof(int32_t) * ptr.size(), hipMemcpyHostToDevice, c->stream);
     hipMemcpyAsync(pc.rnode, node.data(), sizeof(int32_t) * node.size(), hipMemcpyHostToDevice, c->stream);
+    hipMemcpyAsync(pc.rgrid, rgrid.data(), sizeof(int32_t) * rgrid.size(), hipMemcpyHostToDevice, c->stream);
     if (f32) {
         std::vector<float> w32(w64.begin(), w64.end());
         hipMemcpyAsync(pc.rw, w32.data(), sizeof(float) * w32.size(), hipMemcpyHostToDevice, c->stream);
@@ -226,6 +250,7 @@ int setup_mesh_part(gspm_ctx *c) {
     }
     if (rc) return rc;
     gv.rptr = pc.rptr;
+    gv.rgrid = pc.rgrid;
     gv.rnode = pc.rnode;
     gv.rw = pc.rw;
     gv.dinv = pc.dinv;
@@ -341,7 +366,8 @@ void gspm_ctx::release_pc() {
     if (q.fwd) rocfft_plan_destroy(static_cast<rocfft_plan>(q.fwd));
     if (q.inv) rocfft_plan_destroy(static_cast<rocfft_plan>(q.inv));
     if (q.info) rocfft_execution_info_destroy(static_cast<rocfft_execution_info>(q.info));
-    for (void *p : {static_cast<void *>(q.rptr), static_cast<void *>(q.rnode), q.rw, q.dinv, q.ainv, q.grid, q.spec,
+    for (void *p : {static_cast<void *>(q.rptr), static_cast<void *>(q.rgrid), static_cast<void *>(q.rnode), q.rw,
+                    q.dinv, q.ainv, q.grid, q.spec,
                     q.work, static_cast<void *>(q.aux)})
         if (p) hipFree(p);
     q = gspm::GreenState{};

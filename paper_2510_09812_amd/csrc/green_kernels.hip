@@ -55,18 +55,20 @@ __device__ __forceinline__ void corners(const GreenView &gv, const double p[3], 
 
 }  // namespace
 
-// Q^T r: grid point g gathers w r over its list, after the test of |r_j|.
+// Q^T r: each row (a grid point, rows in Morton order so that neighbouring
+// threads gather nearby nodes) sums w r over its list, after the test of |r_j|.
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_pc_restrict(GreenView gv, int n, const T *r, CGScalars cg, int test_k,
                                                           double tol2) {
     if (!pc_live(cg, test_k, tol2)) return;
     const T *w = static_cast<const T *>(gv.rw);
     T *grid = static_cast<T *>(gv.grid);
-    for (int64_t g = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; g < gv.G;
-         g += static_cast<int64_t>(gridDim.x) * kThreads) {
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; t < gv.G;
+         t += static_cast<int64_t>(gridDim.x) * kThreads) {
         T s0 = T(0), s1 = T(0), s2 = T(0);
-        const int e1 = gv.rptr[g + 1];
-        for (int e = gv.rptr[g]; e < e1; ++e) {
+        const int e1 = gv.rptr[t + 1];
+        const int64_t g = gv.rgrid[t];
+        for (int e = gv.rptr[t]; e < e1; ++e) {
             const int j = gv.rnode[e];
             const T wj = w[e];
             s0 += wj * r[j];

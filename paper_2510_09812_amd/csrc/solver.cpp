@@ -48,8 +48,11 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
     const int ns = joint ? 1 : nc;
     CgResult res;
     const int cap = cg.ring - 2;
-    const int first = std::min(std::max(c->predict[kind] + 1, 2), cap);
-    const int later = std::min(std::max(c->predict[kind] / 32, 4), std::min(cap, 32));
+    int &pred = c->predict[kind][c->refine_slot];
+    const int first = std::min(std::max(pred + 1, 2), cap);
+    // batches of costly iterations stay short: each queued iteration that
+    // runs past convergence still costs its library FFTs
+    const int later = c->heavy_iter ? 2 : std::min(std::max(pred / 32, 4), std::min(cap, 32));
     int k = 0;
     auto enqueue = [&](int cnt) {
         const int k1 = std::min(k + cnt, maxit);
@@ -93,7 +96,7 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
                 res.status = GSPM_E_NONFINITE;
                 c->err = "non-finite CG residual";
             }
-            c->predict[kind] = mx;
+            pred = mx;
             return res;
         }
         if (!more) {
@@ -223,7 +226,9 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
         launch_fill_f32(c->d.x32, n3, s);
         const int budget = maxit - used;
         const size_t first_pair = c->prof_used / 2;
+        c->refine_slot = outer > 0 ? 1 : 0;
         CgResult in = cg_iterate(c, ci, nc, joint, budget, kind, iter32);
+        c->refine_slot = 0;
         prof_drop_after(c, first_pair, std::max(in.iters[0], std::max(in.iters[1], in.iters[2])));
         if (in.status == GSPM_E_NONFINITE || in.status == GSPM_E_DEVICE || in.status == GSPM_E_OOM) {
             res.status = in.status;
@@ -288,6 +293,7 @@ CgResult cg_elastic_green(gspm_ctx *c, double *x, double *b, double tol, int max
     auto &d = c->d;
     int fft_rc = 0;
     CgResult r;
+    c->heavy_iter = true;
     if (c->precision == GSPM_MIXED) {
         const double scale = 1.0 / (c->mv.len_scale * c->mat.c11);
         r = cg_mixed(c, 3, true, x, tol, maxit, kind, scale, resid,
@@ -296,6 +302,7 @@ CgResult cg_elastic_green(gspm_ctx *c, double *x, double *b, double tol, int max
         r = cg_fp64(c, 3, true, x, tol, maxit, kind, resid,
                     pcg_iteration<double>(c, mvu, x, d.r, d.r2, d.p, d.p2, d.q, c->cg, tol, &fft_rc));
     }
+    c->heavy_iter = false;
     if (fft_rc && r.status == GSPM_OK) r.status = fft_rc;
     launch_pin_shift(c->n, x, c->p0, c->pc.aux + 3 * kShards, s);
     return r;
@@ -336,33 +343,45 @@ CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int max
     return r;
 }
 
+// The GS solves; with gs_precond = GSPM_PRECOND_JACOBI, CG preconditioned by
+// the operator's diagonal D = eps K_ii + M_ii (the same stopping rule on |r|).
 CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit, SolveKind kind) {
     hipStream_t s = c->stream;
+    const bool jac = c->p.gs_precond == GSPM_PRECOND_JACOBI;
     auto resid = [&]() {
         launch_gs_matvec<double>(c->mv, nc, eps, 1.0, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
     };
     if (c->precision == GSPM_MIXED) {
         float *P[2] = {c->d.p32, c->d.p32b};
         const double ls = c->mv.len_scale, scale = 1.0 / (ls * ls * ls);
+        const float *kd = jac ? c->d.jkd32 : nullptr, *md = jac ? c->d.jmd32 : nullptr;
         return cg_mixed(c, nc, false, x, tol, maxit, kind, scale, resid, [&](int k, bool last) {
             if (last) {
                 launch_cg_check(nc, false, c->cg_in, k, 1.0, s);
                 return;
             }
             launch_gs_matvec<float>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q32, nullptr, c->d.r32, P[(k + 1) & 1],
-                                    c->cg_in, k, 1.0, s);
-            launch_cg_update<float>(c->n, nc, false, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, c->cg_in, k, s);
+                                    c->cg_in, k, 1.0, s, kd, md);
+            if (jac)
+                launch_cg_update_jacobi<float>(c->n, nc, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, kd, md,
+                                               eps / (ls * ls), c->cg_in, k, s);
+            else
+                launch_cg_update<float>(c->n, nc, false, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, c->cg_in, k, s);
         });
     }
     double *P[2] = {c->d.p, c->d.p2};
+    const double *kd = jac ? c->d.jkd : nullptr, *md = jac ? c->d.jmd : nullptr;
     return cg_fp64(c, nc, false, x, tol, maxit, kind, resid, [&](int k, bool last) {
         if (last) {
             launch_cg_check(nc, false, c->cg, k, tol, s);
             return;
         }
         launch_gs_matvec<double>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q, nullptr, c->d.r, P[(k + 1) & 1], c->cg,
-                                 k, tol, s);
-        launch_cg_update<double>(c->n, nc, false, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
+                                 k, tol, s, kd, md);
+        if (jac)
+            launch_cg_update_jacobi<double>(c->n, nc, x, c->d.r, P[(k + 1) & 1], c->d.q, kd, md, eps, c->cg, k, s);
+        else
+            launch_cg_update<double>(c->n, nc, false, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
     });
 }
 

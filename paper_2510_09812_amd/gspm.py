@@ -20,7 +20,7 @@ GSPM_OK, GSPM_E_ARG, GSPM_E_MESH, GSPM_E_STATE, GSPM_E_DEVICE, GSPM_E_NOCONV, GS
 GSPM_FP64, GSPM_MIXED = 0, 1
 GSPM_FIELD_M, GSPM_FIELD_U, GSPM_FIELD_UD = 0, 1, 2
 GSPM_OP_LAPLACE, GSPM_OP_MASS, GSPM_OP_GS, GSPM_OP_ELASTIC, GSPM_OP_MS, GSPM_OP_PRECOND = 0, 1, 2, 3, 4, 5
-GSPM_PRECOND_NONE, GSPM_PRECOND_GREEN = 0, 1
+GSPM_PRECOND_NONE, GSPM_PRECOND_GREEN, GSPM_PRECOND_JACOBI = 0, 1, 2
 GSPM_PERIODIC = 1
 GSPM_WARM_PREVIOUS, GSPM_WARM_LEARNED, GSPM_WARM_EXTRAPOLATE = 0, 1, 2
 GSPM_SWEEP_STOP_ON_REVERSAL, GSPM_SWEEP_CONTINUE = 1, 2
@@ -53,7 +53,8 @@ class gspm_params(ctypes.Structure):
                 ("Ms", "A", "K1", "lambda100", "lambda111", "c11", "c12", "c44", "alpha", "mu0", "gamma0")] + [
         ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
         ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32),
-        ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9), ("elastic_precond", ctypes.c_int32)]
+        ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9), ("elastic_precond", ctypes.c_int32),
+        ("gs_precond", ctypes.c_int32)]
 
 
 class gspm_step_stats(ctypes.Structure):
@@ -186,6 +187,7 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
     for i in range(9):
         p.crystal_rot[i] = rot[i]
     p.elastic_precond = int(params.get("elastic_precond", GSPM_PRECOND_NONE))
+    p.gs_precond = int(params.get("gs_precond", GSPM_PRECOND_NONE))
     return p
 
 

@@ -149,3 +149,69 @@ def test_preconditioner_argument_checks():
         mix.apply(gspm.GSPM_OP_PRECOND, np.zeros((case.mesh.n_nodes, 3)))
     assert e.value.status == gspm.GSPM_E_STATE
     mix.close()
+
+
+# ------------------------------------------------- Jacobi-preconditioned GS
+
+def _gs_eps(case, dt=1e-11):
+    p = case.params
+    return 2 * p["A"] / (p["mu0"] * p["Ms"] ** 2) * p["gamma0"] * p["Ms"] * dt
+
+
+def test_jacobi_gs_solve_matches_oracle(case):
+    p = dict(case.params); p["gs_precond"] = gspm.GSPM_PRECOND_JACOBI
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(p)
+    sim = gspm.Simulation(case.mesh, p)
+    eps = _gs_eps(case)
+    rng = np.random.default_rng(14)
+    b = case.mesh.per_site(rng.standard_normal((case.mesh.n_sites, 3)))
+    nmap = orc.node_map()
+    bu = np.zeros((orc.n, 3)); bu[nmap] = b
+    xg, itg = sim.solve(gspm.GSPM_OP_GS, b, eps=eps, tol=1e-12)
+    xo, ito = orc.solve(O.OP_GS, bu, eps=eps, tol=1e-12)
+    err = _rel(xg, xo[nmap])
+    print(f"Jacobi GS solve (3 components): iterations gpu {itg} oracle {ito}, rel err {err:.2e}", flush=True)
+    assert err < 1e-9
+    assert abs(itg - ito) <= 3
+    sim.close()
+
+
+def test_steps_with_both_preconditioners_match_oracle(case):
+    p = _params(case, tol=1e-12); p["gs_precond"] = gspm.GSPM_PRECOND_JACOBI
+    H_ext = (-0.5 * case.material["Ms"], 0.0, 0.0)
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(p, hext=H_ext)
+    orc.set_m(case.m0)
+    sim = gspm.Simulation(case.mesh, p, hext=H_ext)
+    sim.set_m(case.m0)
+    for k in range(3):
+        sg = sim.step(5e-12, 1)
+        so = orc.step(5e-12, 1)
+        em, eu = _rel(sim.get_m(), orc.get_m()), _rel(sim.get_u(), orc.get_u())
+        print(f"step {k}: elastic {sg['mech_iters']}/{so['mech_iters']}, GS {sg['gs_iters']}/{sum(so['gs_iters'])} "
+              f"(gpu/oracle); rel err m {em:.2e} u {eu:.2e}", flush=True)
+        assert abs(sg["mech_iters"] - so["mech_iters"]) <= 1
+        assert abs(sg["gs_iters"] - sum(so["gs_iters"])) <= 8
+        assert em < 1e-9 and eu < 1e-9
+    sim.close()
+
+
+def test_mixed_with_both_preconditioners_against_fp64_plain():
+    case = w.small_cube(21, seed=116, L=20 * H, jitter=0.15, sphere=0.3, m="noisy_x")
+    H_ext = (-0.5 * case.material["Ms"], 0.0, 0.0)
+    ref = gspm.Simulation(case.mesh, case.params, hext=H_ext)
+    ref.set_m(case.m0)
+    p = _params(case); p["gs_precond"] = gspm.GSPM_PRECOND_JACOBI
+    mix = gspm.Simulation(case.mesh, p, hext=H_ext, precision=gspm.GSPM_MIXED)
+    mix.set_m(case.m0)
+    sr = ref.step(1e-11, 10)
+    sm = mix.step(1e-11, 10)
+    um = lambda u: u - u.mean(axis=0)
+    em, eu = _rel(mix.get_m(), ref.get_m()), _rel(um(mix.get_u()), um(ref.get_u()))
+    print(f"10 steps: GS iterations plain FP64 {sr['gs_iters']}, preconditioned mixed {sm['gs_iters']}; "
+          f"rel err m {em:.2e} u {eu:.2e}", flush=True)
+    assert em < 1e-6 and eu < 1e-6
+    assert sm["gs_iters"] < 0.8 * sr["gs_iters"]
+    ref.close()
+    mix.close()
