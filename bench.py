@@ -10,13 +10,15 @@ steps / wall time, with the mesh and state already resident in HBM when the
 timed region starts.
 
 Paths: FP64, mixed (FP64 refinement around FP32 inner CG), mixed with the
-extrapolated elastic start and mixed with the learned elastic start; `value`
-is the learned path when trained weights exist.  Prints one JSON line,
-including the roofline of the dominant kernel (the fused elastic CG
-iteration, its launches timed by start and end events the HIP runtime
-records at each kernel's own execution, in extra untimed steps after the
-timed region) and the CPU oracle's throughput on a bounded sample of the
-same workload.
+extrapolated and with the learned elastic start, the same with the
+preconditioned solves (the elastic CG with the lattice Green's operator, the
+GS solves with Jacobi), and the optional physics (rotated crystal, local
+magnetostatics).  `value` is the fastest mixed-precision path of the
+workload's physics that stays within 1e-6 of the FP64 run on m and u.  Prints
+one JSON line, including the roofline of that path's dominant kernel (its
+launches timed by start and end events the HIP runtime records at each
+kernel's own execution, in extra untimed steps after the timed region) and
+the CPU oracle's throughput on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -82,17 +84,66 @@ def refinement_bytes(n_nodes: int, n_tets: int, components: int) -> int:
     return 16 * n_tets + 24 * n_nodes + c * n_nodes * (3 * 8 + (8 + 4) + (8 + 8 + 4))
 
 
+def gs3_matvec_bytes(n_nodes: int, n_mag_tets: int, real_bytes: int = 4, jacobi: bool = True) -> int:
+    """Algorithmic bytes of one launch of the GS matvec on three components
+    (CG iteration form, magnetic elements): connectivity of the magnetic
+    tetrahedra, FP64 coordinates, and per component r and the old direction
+    read, the new direction and q = A p written; with Jacobi preconditioning
+    the two diagonals of K and M."""
+    return 16 * n_mag_tets + 24 * n_nodes + 3 * 4 * real_bytes * n_nodes + (2 * real_bytes * n_nodes if jacobi else 0)
+
+
+def pcg_matvec_bytes(n_nodes: int, n_tets: int, real_bytes: int = 4) -> int:
+    """One launch of the preconditioned elastic iteration's matvec: connectivity,
+    coordinates, z and the old direction read, the new direction and q written."""
+    return 16 * n_tets + 24 * n_nodes + 4 * 3 * real_bytes * n_nodes
+
+
+def precond_grid(lo, hi, n_nodes: int):
+    """The auxiliary grid of the elastic preconditioner: round(L_a / l) points
+    per axis (at least 2), l = (V_cell / n_unique)^(1/3)."""
+    L = np.asarray(hi, float) - np.asarray(lo, float)
+    ell = (L.prod() / n_nodes) ** (1.0 / 3.0)
+    return [max(2, int(np.floor(La / ell + 0.5))) for La in L]
+
+
+def precond_bytes(n_nodes: int, grid, real_bytes: int = 4) -> int:
+    """One application of the elastic preconditioner, counting each array
+    once: restriction (row pointers, 8 entries of node id and weight per node,
+    r read, three grid arrays written), forward FFT (three grids read, three
+    half spectra written), the symbol multiply (spectra read and written, 9
+    values per mode), inverse FFT (spectra read, grids written), prolongation
+    (coordinates, grids, r and the diagonal read, z written)."""
+    s, n = real_bytes, n_nodes
+    G = int(np.prod(grid))
+    half = (grid[0] // 2 + 1) * grid[1] * grid[2]
+    restrict = 4 * G + 8 * n * (4 + s) + 3 * s * n + 3 * s * G
+    fft = 3 * s * G + 6 * s * half
+    modes = 6 * s * half + 9 * s * half + 6 * s * half
+    prolong = 24 * n + 3 * s * G + 3 * s * n + 3 * s * n + 3 * s * n
+    return restrict + 2 * fft + modes + prolong
+
+
 def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float, real_bytes: int = 8,
-               mech_refinements: float = 0.0, other_refinements: float = 0.0) -> float:
+               mech_refinements: float = 0.0, other_refinements: float = 0.0, precond: bool = False,
+               grid=(1, 1, 1)) -> float:
     """Algorithmic bytes of one step: each elastic CG iteration and each
     scalar GS CG iteration in the precision its vectors use (real_bytes: 8 on
     the FP64 path, 4 for the inner iterations of the mixed path), each FP64
     refinement of the mixed path (elastic ones on three components, the
     others priced as one scalar component, a lower bound), three element
     right-hand-side passes of about 190 B per node and about 200 B per node
-    of node passes (averages, updates, projection)."""
+    of node passes (averages, updates, projection).  With precond the elastic
+    iterations are the preconditioned ones and the GS ones carry the Jacobi
+    diagonals."""
     mech = cg_iteration_bytes(n_nodes, n_tets, real_bytes)
     gs = gs_iteration_bytes(n_nodes, n_tets, real_bytes)
+    if precond:
+        # preconditioned elastic iteration: its matvec, the x/r update (x, r, p, q: five passes), the
+        # preconditioner; Jacobi GS: the two diagonals once more per component iteration
+        mech = (pcg_matvec_bytes(n_nodes, n_tets, real_bytes) + 5 * 3 * real_bytes * n_nodes
+                + precond_bytes(n_nodes, grid, real_bytes))
+        gs += 2 * real_bytes * n_nodes
     rhs = 3 * (16 * n_tets + 24 * n_nodes * 4)
     nodes = 200 * n_nodes
     ref = mech_refinements * refinement_bytes(n_nodes, n_tets, 3) + other_refinements * refinement_bytes(
@@ -252,7 +303,7 @@ def main() -> int:
                 out["ms_matvec_ms"] = sim.time_operator(gspm.GSPM_OP_MS, reps=50)
                 print(f"[bench] {tag}: K^ms matvec {out['ms_matvec_ms'] * 1e3:.1f} us per launch (FP32)",
                       file=sys.stderr, flush=True)
-        elif not args.no_profile and not precond:
+        elif not args.no_profile:
             # kernel durations from extra untimed steps: every elastic CG iteration is
             # launched with a start/stop event pair that the runtime records at
             # the kernel's own execution (hipExtLaunchKernelGGL), not in the timed region
@@ -292,31 +343,67 @@ def main() -> int:
         if only is not None and name not in only:
             continue
         paths[name] = run_path(**kw)
-    head_name = next((k for k in ("mixed+learned", "mixed", "fp64") if k in paths), next(iter(paths)))
+    um = lambda u: u - u.mean(axis=0)
+
+    def within_target(k):
+        """mixed path within 1e-6 of the FP64 run on m and the mean-removed u"""
+        if "fp64" not in paths:
+            return True
+        f, p = paths["fp64"], paths[k]
+        em = np.linalg.norm(p["m"] - f["m"]) / np.linalg.norm(f["m"])
+        eu = np.linalg.norm(um(p["u"]) - um(f["u"])) / np.linalg.norm(um(f["u"]))
+        return em <= 1e-6 and eu <= 1e-6
+
+    # `value`: the fastest mixed-precision path of the workload's physics that stays within the
+    # metric's 1e-6 of the FP64 run (the optional terms are other physics, reported beside it)
+    base = [k for k in paths if k.startswith("mixed") and "+local_demag" not in k and "+rotated111" not in k]
+    good = [k for k in base if within_target(k)]
+    head_name = (max(good, key=lambda k: paths[k]["value"]) if good
+                 else next((k for k in ("mixed", "fp64") if k in paths), next(iter(paths))))
     head = paths[head_name]
     mixed = head_name.startswith("mixed")
+    precond = head_name.endswith("+precond")
     info, st, wall, value = head["info"], head["st"], head["wall"], head["value"]
     n, ne = info["n_unique"], info["n_tets"]
+    ne_mag = int(np.count_nonzero(case.mesh.tags))
+    rb = 4 if mixed else 8
+    tname = "float" if mixed else "double"
 
+    # the roofline of the path's dominant kernel, by summed duration over the profile steps: the
+    # elastic iteration launch, or (preconditioned paths) the GS matvec on three components
     roofline = None
     pst = head.get("prof")
-    if pst and pst["matvec_launches"] > 0:
-        avg_s = pst["matvec_ms"] / pst["matvec_launches"] * 1e-3
-        mb = cg_iteration_bytes(n, ne, 4 if mixed else 8)
+    if pst and (pst["matvec_launches"] > 0 or pst["gs_matvec_launches"] > 0):
+        if pst["gs_matvec_ms"] > pst["matvec_ms"]:
+            launches, tot_ms = pst["gs_matvec_launches"], pst["gs_matvec_ms"]
+            mb = gs3_matvec_bytes(n, ne_mag, rb, jacobi=precond)
+            kname = f"k_strip<{tname},3,3,GsMatvecOp<{tname},3>>" + (" (Jacobi)" if precond else "")
+            what = "GS matvec launch on three components"
+            traffic = None
+        else:
+            launches, tot_ms = pst["matvec_launches"], pst["matvec_ms"]
+            if precond:
+                mb = pcg_matvec_bytes(n, ne, rb)
+                kname = f"k_strip<{tname},3,3,ElasticPcgOp>"
+                traffic = None
+            else:
+                mb = cg_iteration_bytes(n, ne, rb)
+                kname = f"k_strip<{tname},3,3,ElasticCgOp>"
+                traffic = traffic_from_profile("mixed" if mixed else "fp64", case.name)
+            what = "elastic CG iteration launch"
+        avg_s = tot_ms / launches * 1e-3
         achieved = mb / avg_s / 1e9
-        kname = "k_strip<float,3,3,ElasticCgOp>" if mixed else "k_strip<double,3,3,ElasticCgOp>"
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("mixed" if mixed else "fp64", case.name),
-                    "kernel": kname, "bytes_per_launch": mb,
-                    "avg_launch_us": avg_s * 1e6, "launches": pst["matvec_launches"],
-                    "timing": f"kernel start/end events (hipExtLaunchKernelGGL) on every elastic CG iteration of "
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname, "bytes_per_launch": mb,
+                    "avg_launch_us": avg_s * 1e6, "launches": launches,
+                    "share_of_timed_kernels": {"elastic_ms": pst["matvec_ms"], "gs3_matvec_ms": pst["gs_matvec_ms"]},
+                    "timing": f"kernel start/end events (hipExtLaunchKernelGGL) on every working {what} of "
                               f"{args.profile_steps} untimed steps after the timed region"}
     mech_per_step = st["mech_iters"] / args.steps
     gs_per_step = st["gs_iters"] / args.steps
     mref = st["mech_refinements"] / args.steps
-    b_step = step_bytes(n, ne, mech_per_step, gs_per_step, 4 if mixed else 8, mref,
-                        st["refinements"] / args.steps - mref)
-    um = lambda u: u - u.mean(axis=0)
+    b_step = step_bytes(n, ne, mech_per_step, gs_per_step, rb, mref, st["refinements"] / args.steps - mref,
+                        precond=precond, grid=precond_grid(case.mesh.lo, case.mesh.hi, n))
     per_path = {}
     for k, p in paths.items():
         row = {"value": p["value"], "ms_per_step": p["wall"] / args.steps * 1e3,
@@ -329,6 +416,8 @@ def main() -> int:
             row["ms_iters_per_step"] = p["st"]["ms_iters"] / args.steps
         if "prof" in p and p["prof"]["matvec_launches"] > 0:
             row["elastic_cg_launch_us"] = p["prof"]["matvec_ms"] / p["prof"]["matvec_launches"] * 1e3
+        if "prof" in p and p["prof"]["gs_matvec_launches"] > 0:
+            row["gs3_matvec_launch_us"] = p["prof"]["gs_matvec_ms"] / p["prof"]["gs_matvec_launches"] * 1e3
         ref = "fp64+local_demag" if ld else ("fp64+rotated111" if k.endswith("+rotated111") else "fp64")
         if k.endswith("+precond"):
             row["ref_note"] = "errors against the unpreconditioned FP64 path"
@@ -356,13 +445,16 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": case.name, "nodes": n, "tets": ne, "dt_s": case.dt, "cg_tol": case.cg_tol,
                    "path": head_name, "block_nodes": args.block_nodes or 256,
+                   "precond": ("elastic: lattice Green's operator on the auxiliary grid; GS: Jacobi" if precond
+                               else "none (the paper's unpreconditioned CG)"),
                    "mech_iters_per_step": mech_per_step, "gs_iters_per_step": gs_per_step},
         "roofline": roofline,
         "step_roofline": {"bytes_per_node_step": b_step / n, "roofline_node_steps_per_s": HBM_PEAK_GBS * 1e9 / b_step * n,
                           "frac": value / (HBM_PEAK_GBS * 1e9 / b_step * n),
                           "inputs": {"mech_iters_per_step": mech_per_step, "gs_iters_per_step": gs_per_step,
                                      "real_bytes": 4 if mixed else 8, "mech_refinements_per_step": mref,
-                                     "other_refinements_per_step": st["refinements"] / args.steps - mref}},
+                                     "other_refinements_per_step": st["refinements"] / args.steps - mref,
+                                     "preconditioned": precond}},
         "paths": per_path,
         "ms_roofline": ms_roofline,
     }

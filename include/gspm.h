@@ -145,6 +145,11 @@ typedef struct {
     int32_t gs_precond;     /* GSPM_PRECOND_NONE or GSPM_PRECOND_JACOBI: the GS solves of Eq. (weak_GS) (the
                                step's and gspm_solve's) by CG preconditioned with D = diag(eps K + M), the
                                same stopping rule; nodes in the inclusions only keep their identity rows */
+    double ms_tol;          /* local_demag: the magnetostatic CG stops at ||r|| <= ms_tol ||b||; 0 selects
+                               max(1e-3 cg_tol, 1e-12) (the floor: what FP64 residuals of K^ms can reach).  K^ms (the Laplacian of the whole cell, one pinned node) has a
+                               condition number growing as (L/h)^2, so two iterates that both pass a 1e-8
+                               test can differ by ~1e-5; the tighter test keeps the potential (and m, u
+                               through its field) within 1e-6 whatever precision the solve ran in. */
 } gspm_params;
 
 typedef struct {
@@ -156,8 +161,9 @@ typedef struct {
     double dm_avg;          /* mean |m^{n+1} - m^n| over magnetic nodes, last step (Sec. 3.2) */
     double elapsed_ms;      /* wall time of the call on the device stream */
     double matvec_ms;       /* profile mode: summed kernel duration of the working elastic CG
-                               iteration launches (the matvec fused with the CG vector updates; those
-                               issued after convergence, which exit at once, excluded) */
+                               iteration launches (the matvec fused with the CG vector updates, or with
+                               elastic_precond the preconditioned iteration's matvec; those issued after
+                               convergence, which exit at once, excluded) */
     int64_t matvec_launches;/* profile mode: number of elastic CG iteration launches timed */
     int64_t refinements;    /* GSPM_MIXED: outer FP64 residual evaluations that started an FP32 inner solve */
     int64_t learned_starts; /* steps whose elastic start used the network's increment */
@@ -166,6 +172,9 @@ typedef struct {
                                previous displacement increment (0 if unused) */
     int64_t ms_iters;       /* local_demag: magnetostatic CG iterations (GSPM_MIXED: inner FP32), summed */
     int64_t mech_refinements; /* GSPM_MIXED: the refinements of the elastic solves (part of `refinements`) */
+    double gs_matvec_ms;    /* profile mode: summed kernel duration of the working GS matvec launches on three
+                               components (stages 1 and 3; those after convergence excluded) */
+    int64_t gs_matvec_launches; /* profile mode: their number */
 } gspm_step_stats;
 
 /* Create a context on opts->device (NULL opts: device 0, FP64, own stream).

@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
         ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
         ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32),
         ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9), ("elastic_precond", ctypes.c_int32),
-        ("gs_precond", ctypes.c_int32)]
+        ("gs_precond", ctypes.c_int32), ("ms_tol", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -163,6 +163,7 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
         p.crystal_rot[i] = rot[i]
     p.elastic_precond = int(params.get("elastic_precond", 0))
     p.gs_precond = int(params.get("gs_precond", 0))
+    p.ms_tol = float(params.get("ms_tol", 0.0))
     return p
 
 

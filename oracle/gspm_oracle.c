@@ -683,6 +683,7 @@ int or_set_params(or_sim *s, const or_params *p) {
     }
     if (p->elastic_precond != 0 && p->elastic_precond != 1) { seterr(s, "elastic_precond must be 0 or 1"); return OR_E_ARG; }
     if (p->gs_precond != 0 && p->gs_precond != 2) { seterr(s, "gs_precond must be 0 or 2"); return OR_E_ARG; }
+    if (!(p->ms_tol >= 0.0)) { seterr(s, "ms_tol must be >= 0"); return OR_E_ARG; }
     if (p->elastic_precond && !s->periodic) {
         seterr(s, "the elastic preconditioner needs a periodic mesh");
         return OR_E_ARG;
@@ -1643,7 +1644,9 @@ int or_step(or_sim *s, double dt, int32_t nsteps, or_stats *st) {
         if (U) {
             ms_rhs_at(s, m, bm);
             memcpy(U, s->ud, sizeof(double) * (size_t)n);
-            rc = solve_ms(s, bm, U, p->cg_tol, p->cg_maxit, &it);
+            /* reading: the magnetostatic stopping test is tighter than the others (ms_tol,
+             * 1e-3 cg_tol by default, not below 1e-12) since K^ms's conditioning grows as (L/h)^2 */
+            rc = solve_ms(s, bm, U, p->ms_tol > 0.0 ? p->ms_tol : fmax(1e-3 * p->cg_tol, 1e-12), p->cg_maxit, &it);
             if (st) st->ms_iters += it;
             if (rc) break;
         }

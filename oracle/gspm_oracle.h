@@ -34,6 +34,7 @@ typedef struct {
     int32_t elastic_precond; /* 1: elastic solves by CG with the Green's-operator preconditioner (periodic
                                 system, pinned by translation afterwards); 0: plain CG on the pinned system */
     int32_t gs_precond;    /* 2: GS solves by CG preconditioned with the operator's diagonal (Jacobi); 0: plain */
+    double ms_tol;         /* magnetostatic CG tolerance; 0 selects max(1e-3 cg_tol, 1e-12) */
 } or_params;
 
 typedef struct {

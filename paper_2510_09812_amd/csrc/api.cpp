@@ -175,7 +175,8 @@ gspm_ctx::~gspm_ctx() {
     release_nn();
     release_mesh();
     release_pc();
-    for (hipEvent_t e : prof_ev) hipEventDestroy(e);
+    for (auto &pl : prof)
+        for (hipEvent_t e : pl.ev) hipEventDestroy(e);
     for (hipEvent_t e : ev)
         if (e) hipEventDestroy(e);
     if (t0) hipEventDestroy(t0);
@@ -575,6 +576,7 @@ gspm_status gspm_set_params(gspm_ctx *c, const gspm_params *p) {
     if (p->local_demag != 0 && p->local_demag != 1) return fail(c, GSPM_E_ARG, "set_params: local_demag must be 0 or 1");
     if (p->elastic_precond != GSPM_PRECOND_NONE && p->elastic_precond != GSPM_PRECOND_GREEN)
         return fail(c, GSPM_E_ARG, "set_params: unknown elastic_precond");
+    if (!(p->ms_tol >= 0.0) || !std::isfinite(p->ms_tol)) return fail(c, GSPM_E_ARG, "set_params: ms_tol must be >= 0");
     if (p->gs_precond != GSPM_PRECOND_NONE && p->gs_precond != GSPM_PRECOND_JACOBI)
         return fail(c, GSPM_E_ARG, "set_params: gs_precond must be GSPM_PRECOND_NONE or GSPM_PRECOND_JACOBI");
     double R[9];

@@ -197,7 +197,7 @@ void launch_pc_symbol(const GreenView &gv, const double *stencil27, double facto
 // node), pq[k] += p_k . q.  pin = p_{k-1}, pout = p_k (alternating buffers).
 template <class T>
 void launch_elastic_pcg(const MeshView &mv, const Material &mat, int k, const T *z, const T *pin, T *pout, T *q,
-                        const CGScalars &cg, hipStream_t s);
+                        const CGScalars &cg, hipStream_t s, const hipEvent_t *ev = nullptr);
 
 // ---------------------------------------------------------------- launchers
 
@@ -275,7 +275,7 @@ void launch_elastic_cg(const MeshView &mv, const Material &mat, int k, bool last
 template <class T>
 void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
                       const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s,
-                      const T *jkd = nullptr, const T *jmd = nullptr);
+                      const T *jkd = nullptr, const T *jmd = nullptr, const hipEvent_t *ev = nullptr);
 // The Jacobi-preconditioned GS iteration's update: alpha = rz[k] / pq[k];
 // x += alpha p; r -= alpha q; rr[k+1] += r.r; rz[k+1] += r . D^-1 r.
 template <class T>

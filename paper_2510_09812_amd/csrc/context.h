@@ -118,9 +118,15 @@ struct gspm_ctx {
     int64_t mech_refinements = 0; // the part of them in elastic solves
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    std::vector<hipEvent_t> prof_ev;
-    std::vector<int> prof_iter;   // CG iteration of each timed pair, -1 = dropped
-    size_t prof_used = 0;
+    // profile mode: event pairs around the launches of list 0 (the elastic CG
+    // iteration, plain or preconditioned matvec) and list 1 (the GS matvec on
+    // three components); prof_list names the list the running solve records into
+    struct ProfList {
+        std::vector<hipEvent_t> ev;
+        std::vector<int> iter;    // CG iteration of each timed pair, -1 = dropped
+        size_t used = 0;
+    } prof[2];
+    int prof_list = -1;
 
     gspm_params p{};
     gspm::Material mat{};

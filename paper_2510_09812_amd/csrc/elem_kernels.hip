@@ -1530,7 +1530,7 @@ template void launch_elastic_cg<float>(const MeshView &, const Material &, int, 
 
 template <class T>
 void launch_elastic_pcg(const MeshView &mv, const Material &mat, int k, const T *z, const T *pin, T *pout, T *q,
-                        const CGScalars &cg, hipStream_t s) {
+                        const CGScalars &cg, hipStream_t s, const hipEvent_t *ev) {
     const bool nd = sizeof(T) == sizeof(float);
     Material m2 = mat;
     if (nd) {
@@ -1541,17 +1541,17 @@ void launch_elastic_pcg(const MeshView &mv, const Material &mat, int k, const T 
     if (mat.rot) {
         ElasticPcgOp<T, Aniso<T>> op{z, pin, pout, q, cg, k, mv.n, aniso_of<T>(mat, nd), 0.0,
                                      nd ? 1.0 / mv.len_scale : 1.0};
-        run_strip<T, 3, 3>(mv, op, s);
+        run_strip<T, 3, 3>(mv, op, s, ev);
         return;
     }
     ElasticPcgOp<T> op{z, pin, pout, q, cg, k, mv.n, cubic_of<T>(m2), 0.0, nd ? 1.0 / mv.len_scale : 1.0};
-    run_strip<T, 3, 3>(mv, op, s);
+    run_strip<T, 3, 3>(mv, op, s, ev);
 }
 
 template void launch_elastic_pcg<double>(const MeshView &, const Material &, int, const double *, const double *,
-                                         double *, double *, const CGScalars &, hipStream_t);
+                                         double *, double *, const CGScalars &, hipStream_t, const hipEvent_t *);
 template void launch_elastic_pcg<float>(const MeshView &, const Material &, int, const float *, const float *,
-                                        float *, float *, const CGScalars &, hipStream_t);
+                                        float *, float *, const CGScalars &, hipStream_t, const hipEvent_t *);
 
 void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m, double *b, double *x, double *bb,
                         hipStream_t s) {
@@ -1565,25 +1565,25 @@ void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m
 template <class T>
 void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
                       const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s,
-                      const T *jkd, const T *jmd) {
+                      const T *jkd, const T *jmd, const hipEvent_t *ev) {
     const bool nd = sizeof(T) == sizeof(float);
     const double sc = nd ? 1.0 / mv.len_scale : 1.0;
     const int md = static_cast<int>(mode);
     const double t2 = tol * tol;
     const T e = static_cast<T>(eps * sc * sc), ms = static_cast<T>(mass);
     switch (nc) {
-        case 1: run_strip<T, 1, 1>(mv, GsMatvecOp<T, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc, jkd, jmd}, s); break;
-        case 2: run_strip<T, 2, 2>(mv, GsMatvecOp<T, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0}, {0.0, 0.0}, sc, jkd, jmd}, s); break;
-        default: run_strip<T, 3, 3>(mv, GsMatvecOp<T, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0}, {0.0, 0.0, 0.0}, sc, jkd, jmd}, s); break;
+        case 1: run_strip<T, 1, 1>(mv, GsMatvecOp<T, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc, jkd, jmd}, s, ev); break;
+        case 2: run_strip<T, 2, 2>(mv, GsMatvecOp<T, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0}, {0.0, 0.0}, sc, jkd, jmd}, s, ev); break;
+        default: run_strip<T, 3, 3>(mv, GsMatvecOp<T, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0}, {0.0, 0.0, 0.0}, sc, jkd, jmd}, s, ev); break;
     }
 }
 
 template void launch_gs_matvec<double>(const MeshView &, int, double, double, MatvecMode, const double *, double *,
                                        const double *, const double *, double *, const CGScalars &, int, double,
-                                       hipStream_t, const double *, const double *);
+                                       hipStream_t, const double *, const double *, const hipEvent_t *);
 template void launch_gs_matvec<float>(const MeshView &, int, double, double, MatvecMode, const float *, float *,
                                       const float *, const float *, float *, const CGScalars &, int, double,
-                                      hipStream_t, const float *, const float *);
+                                      hipStream_t, const float *, const float *, const hipEvent_t *);
 
 // K^ms on the same strips (all segments), eps = 1 and no mass; FP32 uses the
 // GS operator's scaling, A' = K^ms / len_scale^3.

@@ -115,27 +115,31 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
 // trace times it); pairs of launches issued after convergence (immediate
 // exits) are dropped.  Returns the pair to launch with, or null.
 const hipEvent_t *prof_begin(gspm_ctx *c, int k) {
-    if (!c->profile) return nullptr;
-    if (c->prof_used + 2 > c->prof_ev.size()) {
+    if (!c->profile || c->prof_list < 0) return nullptr;
+    auto &pl = c->prof[c->prof_list];
+    if (pl.used + 2 > pl.ev.size()) {
         for (int i = 0; i < 256; ++i) {
             hipEvent_t e;
             hipEventCreate(&e);
-            c->prof_ev.push_back(e);
+            pl.ev.push_back(e);
         }
     }
-    c->prof_iter.resize(c->prof_ev.size() / 2);
-    c->prof_iter[c->prof_used / 2] = k;
-    return &c->prof_ev[c->prof_used];
+    pl.iter.resize(pl.ev.size() / 2);
+    pl.iter[pl.used / 2] = k;
+    return &pl.ev[pl.used];
 }
 
 void prof_end(gspm_ctx *c) {
-    if (c->profile) c->prof_used += 2;
+    if (c->profile && c->prof_list >= 0) c->prof[c->prof_list].used += 2;
 }
 
+size_t prof_mark(const gspm_ctx *c) { return c->prof_list >= 0 ? c->prof[c->prof_list].used / 2 : 0; }
+
 void prof_drop_after(gspm_ctx *c, size_t first_pair, int iters) {
-    if (!c->profile) return;
-    for (size_t i = first_pair; i < c->prof_used / 2; ++i)
-        if (c->prof_iter[i] >= iters) c->prof_iter[i] = -1;
+    if (!c->profile || c->prof_list < 0) return;
+    auto &pl = c->prof[c->prof_list];
+    for (size_t i = first_pair; i < pl.used / 2; ++i)
+        if (pl.iter[i] >= iters) pl.iter[i] = -1;
 }
 
 // Plain FP64 CG from the initial guess x (Sec. 2.5): residual, start test,
@@ -225,7 +229,7 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
         launch_to_f32_norms(n, nc, joint, c->d.r, scale, c->d.r32, ci, s);
         launch_fill_f32(c->d.x32, n3, s);
         const int budget = maxit - used;
-        const size_t first_pair = c->prof_used / 2;
+        const size_t first_pair = prof_mark(c);
         c->refine_slot = outer > 0 ? 1 : 0;
         CgResult in = cg_iterate(c, ci, nc, joint, budget, kind, iter32);
         c->refine_slot = 0;
@@ -272,7 +276,8 @@ auto pcg_iteration(gspm_ctx *c, const MeshView &mvu, T *x, T *r, T *z, T *pa, T 
         };
         if (k == 0) precond(0);
         T *pin = (k & 1) ? pa : pb, *pout = (k & 1) ? pb : pa;
-        launch_elastic_pcg<T>(mvu, c->mat, k, z, pin, pout, q, cg, s);
+        launch_elastic_pcg<T>(mvu, c->mat, k, z, pin, pout, q, cg, s, prof_begin(c, k));
+        prof_end(c);
         launch_pcg_update<T>(c->n, x, r, pout, q, cg, k, s);
         precond(k + 1);
     };
@@ -299,8 +304,10 @@ CgResult cg_elastic_green(gspm_ctx *c, double *x, double *b, double tol, int max
         r = cg_mixed(c, 3, true, x, tol, maxit, kind, scale, resid,
                      pcg_iteration<float>(c, mvu, d.x32, d.r32, d.r32b, d.p32, d.p32b, d.q32, c->cg_in, 1.0, &fft_rc));
     } else {
+        const size_t first_pair = prof_mark(c);
         r = cg_fp64(c, 3, true, x, tol, maxit, kind, resid,
                     pcg_iteration<double>(c, mvu, x, d.r, d.r2, d.p, d.p2, d.q, c->cg, tol, &fft_rc));
+        prof_drop_after(c, first_pair, r.iters[0]);
     }
     c->heavy_iter = false;
     if (fft_rc && r.status == GSPM_OK) r.status = fft_rc;
@@ -311,8 +318,13 @@ CgResult cg_elastic_green(gspm_ctx *c, double *x, double *b, double tol, int max
 // The elastic solve runs single-reduction CG: one fused launch per iteration
 // (launch_elastic_cg), r, p and q alternating between two buffers.
 CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int maxit, SolveKind kind) {
-    if (c->p.elastic_precond == GSPM_PRECOND_GREEN) return cg_elastic_green(c, x, const_cast<double *>(b), tol, maxit, kind);
-    const size_t first_pair = c->prof_used / 2;
+    c->prof_list = 0;
+    if (c->p.elastic_precond == GSPM_PRECOND_GREEN) {
+        CgResult r = cg_elastic_green(c, x, const_cast<double *>(b), tol, maxit, kind);
+        c->prof_list = -1;
+        return r;
+    }
+    const size_t first_pair = prof_mark(c);
     hipStream_t s = c->stream;
     auto resid = [&]() {
         launch_elastic_matvec<double>(c->mv, c->mat, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
@@ -340,12 +352,24 @@ CgResult cg_elastic(gspm_ctx *c, double *x, const double *b, double tol, int max
         r = cg_fp64(c, 3, true, x, tol, maxit, kind, resid, fused(d.r, d.r2, d.p, d.p2, d.q, d.q2, x, c->cg, tol));
         prof_drop_after(c, first_pair, r.iters[0]);
     }
+    c->prof_list = -1;
     return r;
 }
+
+CgResult cg_gs_run(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit,
+                   SolveKind kind);
 
 // The GS solves; with gs_precond = GSPM_PRECOND_JACOBI, CG preconditioned by
 // the operator's diagonal D = eps K_ii + M_ii (the same stopping rule on |r|).
 CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit, SolveKind kind) {
+    c->prof_list = nc == 3 ? 1 : -1;
+    CgResult r = cg_gs_run(c, nc, eps, x, b, tol, maxit, kind);
+    c->prof_list = -1;
+    return r;
+}
+
+CgResult cg_gs_run(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit,
+                   SolveKind kind) {
     hipStream_t s = c->stream;
     const bool jac = c->p.gs_precond == GSPM_PRECOND_JACOBI;
     auto resid = [&]() {
@@ -361,7 +385,8 @@ CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, doub
                 return;
             }
             launch_gs_matvec<float>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q32, nullptr, c->d.r32, P[(k + 1) & 1],
-                                    c->cg_in, k, 1.0, s, kd, md);
+                                    c->cg_in, k, 1.0, s, kd, md, prof_begin(c, k));
+            prof_end(c);
             if (jac)
                 launch_cg_update_jacobi<float>(c->n, nc, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, kd, md,
                                                eps / (ls * ls), c->cg_in, k, s);
@@ -371,18 +396,22 @@ CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, doub
     }
     double *P[2] = {c->d.p, c->d.p2};
     const double *kd = jac ? c->d.jkd : nullptr, *md = jac ? c->d.jmd : nullptr;
-    return cg_fp64(c, nc, false, x, tol, maxit, kind, resid, [&](int k, bool last) {
+    const size_t first_pair = prof_mark(c);
+    CgResult res = cg_fp64(c, nc, false, x, tol, maxit, kind, resid, [&](int k, bool last) {
         if (last) {
             launch_cg_check(nc, false, c->cg, k, tol, s);
             return;
         }
         launch_gs_matvec<double>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q, nullptr, c->d.r, P[(k + 1) & 1], c->cg,
-                                 k, tol, s, kd, md);
+                                 k, tol, s, kd, md, prof_begin(c, k));
+        prof_end(c);
         if (jac)
             launch_cg_update_jacobi<double>(c->n, nc, x, c->d.r, P[(k + 1) & 1], c->d.q, kd, md, eps, c->cg, k, s);
         else
             launch_cg_update<double>(c->n, nc, false, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
     });
+    prof_drop_after(c, first_pair, std::max(res.iters[0], std::max(res.iters[1], res.iters[2])));
+    return res;
 }
 
 // K^ms x = b (Eq. weak_demag) on the pinned all-element Laplacian.  The
@@ -488,7 +517,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
         hipMemcpyAsync(d.udnext, d.ud, sizeof(double) * static_cast<size_t>(n), hipMemcpyDeviceToDevice, s);
         cg_prepare(c, 1);
         launch_ms_rhs(c->mv, c->p.Ms, d.m, d.b, d.udnext, c->cg.bb, s);
-        r = cg_ms(c, 1, d.udnext, d.b, tol, maxit, SK_MS);
+        r = cg_ms(c, 1, d.udnext, d.b, c->p.ms_tol > 0.0 ? c->p.ms_tol : std::max(1e-3 * tol, 1e-12), maxit, SK_MS);
         st->ms_iters += r.iters[0];
         if (r.status) return r.status;
         ud = d.udnext;
@@ -564,7 +593,7 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     const double dtau = c->p.gamma0 * c->p.Ms * dt;
     const double lex2 = 2.0 * c->p.A / (c->p.mu0 * c->p.Ms * c->p.Ms);
     const double eps1 = lex2 * dtau, eps3 = c->p.alpha * eps1;
-    c->prof_used = 0;
+    for (auto &pl : c->prof) pl.used = 0;
     const int64_t ref0 = c->refinements, mref0 = c->mech_refinements;
     hipEventRecord(c->t0, c->stream);
     int rc = GSPM_OK;
@@ -587,17 +616,25 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     st->mech_refinements = c->mech_refinements - mref0;
     if (st->minres_starts > 0) hipMemcpy(st->warm_coef, c->d.wcoef, 2 * sizeof(double), hipMemcpyDeviceToHost);
     if (c->profile) {
-        double tot = 0.0;
-        int64_t cnt = 0;
-        for (size_t i = 0; i + 1 < c->prof_used; i += 2) {
-            if (c->prof_iter[i / 2] < 0) continue;
-            float e = 0.0f;
-            hipEventElapsedTime(&e, c->prof_ev[i], c->prof_ev[i + 1]);
-            tot += e;
-            ++cnt;
+        for (int li = 0; li < 2; ++li) {
+            double tot = 0.0;
+            int64_t cnt = 0;
+            const auto &pl = c->prof[li];
+            for (size_t i = 0; i + 1 < pl.used; i += 2) {
+                if (pl.iter[i / 2] < 0) continue;
+                float e = 0.0f;
+                hipEventElapsedTime(&e, pl.ev[i], pl.ev[i + 1]);
+                tot += e;
+                ++cnt;
+            }
+            if (li == 0) {
+                st->matvec_ms = tot;
+                st->matvec_launches = cnt;
+            } else {
+                st->gs_matvec_ms = tot;
+                st->gs_matvec_launches = cnt;
+            }
         }
-        st->matvec_ms = tot;
-        st->matvec_launches = cnt;
     }
     return rc;
 }

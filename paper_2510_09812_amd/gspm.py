@@ -54,7 +54,7 @@ class gspm_params(ctypes.Structure):
         ("Nd", ctypes.c_double * 9), ("hext", ctypes.c_double * 3), ("sigma_ext", ctypes.c_double * 6),
         ("cg_tol", ctypes.c_double), ("cg_maxit", ctypes.c_int32), ("precession", ctypes.c_int32),
         ("local_demag", ctypes.c_int32), ("crystal_rot", ctypes.c_double * 9), ("elastic_precond", ctypes.c_int32),
-        ("gs_precond", ctypes.c_int32)]
+        ("gs_precond", ctypes.c_int32), ("ms_tol", ctypes.c_double)]
 
 
 class gspm_step_stats(ctypes.Structure):
@@ -64,7 +64,8 @@ class gspm_step_stats(ctypes.Structure):
                 ("matvec_launches", ctypes.c_int64), ("refinements", ctypes.c_int64),
                 ("learned_starts", ctypes.c_int64), ("minres_starts", ctypes.c_int64),
                 ("warm_coef", ctypes.c_double * 2), ("ms_iters", ctypes.c_int64),
-                ("mech_refinements", ctypes.c_int64)]
+                ("mech_refinements", ctypes.c_int64), ("gs_matvec_ms", ctypes.c_double),
+                ("gs_matvec_launches", ctypes.c_int64)]
 
 
 _lib = None
@@ -188,6 +189,7 @@ def make_params(params: dict, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6, preces
         p.crystal_rot[i] = rot[i]
     p.elastic_precond = int(params.get("elastic_precond", GSPM_PRECOND_NONE))
     p.gs_precond = int(params.get("gs_precond", GSPM_PRECOND_NONE))
+    p.ms_tol = float(params.get("ms_tol", 0.0))
     return p
 
 
@@ -213,7 +215,8 @@ def stats_dict(st: gspm_step_stats) -> dict:
                 gs_iters=st.gs_iters, gs_iters_stage=list(st.gs_iters_stage), dm_avg=st.dm_avg,
                 elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches,
                 refinements=st.refinements, learned_starts=st.learned_starts, minres_starts=st.minres_starts,
-                warm_coef=list(st.warm_coef), ms_iters=st.ms_iters, mech_refinements=st.mech_refinements)
+                warm_coef=list(st.warm_coef), ms_iters=st.ms_iters, mech_refinements=st.mech_refinements,
+                gs_matvec_ms=st.gs_matvec_ms, gs_matvec_launches=st.gs_matvec_launches)
 
 
 def gspm_step(ctx, dt: float, n_steps: int = 1) -> dict:

@@ -2,9 +2,9 @@
 only oracle/ and the seeded workloads).
 
   cube47_sphere_oracle.npz: the 100k-node cube with a sphere (200 steps of
-    5 ps, CG tolerance 1e-8), m and u in the caller's node order after steps
-    100 and 200, and per step the elastic and GS iteration counts, dm_avg,
-    mbar and the energies.
+    5 ps, CG tolerance 1e-8), m and u in the caller's node order after step
+    200, and per step the elastic and GS iteration counts, dm_avg, mbar and
+    the energies.
   cube100_ellipsoids_oracle_sample.npz: the 1M-node cube with three
     ellipsoids (10 steps of 10 ps, tolerance 1e-8); the full state is too
     large to store, so m and u after steps 5 and 10 are kept at 4096 seeded
@@ -66,7 +66,7 @@ def run(case, steps, keep, sample=None):
 def main():
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
     if which in ("c2", "all"):
-        out = run(w.cube47_sphere(), 200, (100, 200))
+        out = run(w.cube47_sphere(), 200, (200,))
         np.savez_compressed(os.path.join(HERE, "cube47_sphere_oracle.npz"), **out)
     if which in ("c3", "all"):
         case = w.cube100_ellipsoids()

@@ -74,3 +74,17 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.returncode != 0
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_preconditioned_step_bytes_and_grid():
+    import workloads as w
+    case = w.cube10_random()
+    g = bench.precond_grid(case.mesh.lo, case.mesh.hi, 729)
+    assert g == [9, 9, 9]
+    n, ne = 1000, 6000
+    plain = bench.step_bytes(n, ne, 100, 40, 4)
+    pc = bench.step_bytes(n, ne, 100, 40, 4, precond=True, grid=(10, 10, 10))
+    # each preconditioned iteration adds the preconditioner and the Jacobi diagonals to the GS ones
+    per_it = bench.pcg_matvec_bytes(n, ne, 4) + 60 * n + bench.precond_bytes(n, (10, 10, 10), 4)
+    assert pc - plain == 100 * (per_it - bench.cg_iteration_bytes(n, ne, 4)) + 40 * 8 * n
+    assert bench.gs3_matvec_bytes(n, ne, 4, jacobi=False) == 16 * ne + 24 * n + 48 * n
