@@ -44,6 +44,7 @@
 #ifndef GSPM_H
 #define GSPM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -102,7 +103,20 @@ typedef struct {
     int32_t block_nodes;    /* nodes per owner block (power of two, 64..1024), 0 = automatic */
     int32_t profile;        /* nonzero: time every elastic CG iteration launch with HIP events */
     void *stream;           /* hipStream_t to run on, or NULL for a stream owned by the context */
+    int32_t reorder;        /* internal node order: GSPM_REORDER_MORTON (default), GSPM_REORDER_NONE (the order
+                               in which the caller's nodes first appear), GSPM_REORDER_RCM (reverse
+                               Cuthill-McKee on the mesh graph).  Owner blocks are ranges of this order, so
+                               it sets the halo sizes; results agree to rounding. */
+    /* Optional device allocator (both or neither): every device buffer the context owns comes from
+     * dev_alloc(bytes, alloc_user) (device memory of opts->device, 256-byte aligned, NULL on failure)
+     * and goes back through dev_free(ptr, alloc_user), for example from PyTorch's caching allocator.
+     * NULL: hipMalloc / hipFree. */
+    void *(*dev_alloc)(size_t bytes, void *alloc_user);
+    void (*dev_free)(void *ptr, void *alloc_user);
+    void *alloc_user;
 } gspm_create_opts;
+
+typedef enum { GSPM_REORDER_MORTON = 0, GSPM_REORDER_NONE = 1, GSPM_REORDER_RCM = 2 } gspm_reorder;
 
 /* Material and run parameters (App. A notation; SI units). */
 typedef struct {

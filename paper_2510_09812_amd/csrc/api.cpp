@@ -29,6 +29,38 @@ gspm_status fail(gspm_ctx *c, gspm_status s, const std::string &msg) {
 // outside the arena (or past its end) it falls back to hipMalloc.
 constexpr size_t kArenaAlign = 256;
 
+}  // namespace
+
+namespace gspm {
+
+int ctx_malloc(gspm_ctx *c, void **p, size_t bytes, const char *what) {
+    *p = nullptr;
+    if (c->alloc_fn) {
+        *p = c->alloc_fn(bytes, c->alloc_user);
+        if (!*p) {
+            c->err = std::string(what) + ": the caller's allocator returned NULL";
+            return GSPM_E_OOM;
+        }
+        return GSPM_OK;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_check(c, e, what);
+    }
+    return GSPM_OK;
+}
+
+void ctx_free(const gspm_ctx *c, void *p) {
+    if (!p) return;
+    if (c->free_fn) c->free_fn(p, c->alloc_user);
+    else hipFree(p);
+}
+
+}  // namespace gspm
+
+namespace {
+
 template <class T>
 int dev_alloc(gspm_ctx *c, T **p, size_t count) {
     *p = nullptr;
@@ -43,18 +75,16 @@ int dev_alloc(gspm_ctx *c, T **p, size_t count) {
         c->arena_used += bytes;
         return GSPM_OK;
     }
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return hip_check(c, e, "hipMalloc");
-    }
-    return GSPM_OK;
+    void *v = nullptr;
+    const int rc = ctx_malloc(c, &v, sizeof(T) * count, "device allocation");
+    *p = static_cast<T *>(v);
+    return rc;
 }
 
 template <class T>
 void dev_free(const gspm_ctx *c, T *&p) {
     const char *q = reinterpret_cast<const char *>(p);
-    if (p && !(c->arena && q >= c->arena && q < c->arena + c->arena_size)) hipFree(p);
+    if (p && !(c->arena && q >= c->arena && q < c->arena + c->arena_size)) ctx_free(c, const_cast<void *>(static_cast<const void *>(p)));
     p = nullptr;
 }
 
@@ -206,7 +236,7 @@ void gspm_ctx::release_mesh() {
     dev_free(this, b.ud); dev_free(this, b.udnext); dev_free(this, b.rep);
     dev_free(this, b.cg_rz); dev_free(this, b.cgi_rz); dev_free(this, b.jkd); dev_free(this, b.jmd);
     dev_free(this, b.jkd32); dev_free(this, b.jmd32);
-    if (arena) hipFree(arena);
+    if (arena) gspm::ctx_free(this, arena);
     arena = nullptr;
     arena_size = arena_used = 0;
     have_mesh = have_m = have_prev = false;
@@ -240,6 +270,14 @@ gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts) {
         g_create_error = "gspm_create: unknown precision";
         return GSPM_E_ARG;
     }
+    if (o.reorder != GSPM_REORDER_MORTON && o.reorder != GSPM_REORDER_NONE && o.reorder != GSPM_REORDER_RCM) {
+        g_create_error = "gspm_create: unknown reorder";
+        return GSPM_E_ARG;
+    }
+    if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr)) {
+        g_create_error = "gspm_create: dev_alloc and dev_free go together";
+        return GSPM_E_ARG;
+    }
     if (o.block_nodes != 0 && (o.block_nodes < 64 || o.block_nodes > 1024 || (o.block_nodes & (o.block_nodes - 1)))) {
         g_create_error = "gspm_create: block_nodes must be 0 or a power of two in [64, 1024]";
         return GSPM_E_ARG;
@@ -266,6 +304,10 @@ gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts) {
     c->device = o.device;
     c->precision = o.precision;
     c->block_nodes = o.block_nodes;
+    c->reorder = o.reorder;
+    c->alloc_fn = o.dev_alloc;
+    c->free_fn = o.dev_free;
+    c->alloc_user = o.alloc_user;
     c->profile = o.profile != 0;
     if (o.stream) {
         c->stream = static_cast<hipStream_t>(o.stream);
@@ -318,7 +360,7 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     int32_t nb = nodes_per_block(c->block_nodes, n_nodes);
     int rc;
     for (;;) {
-        rc = prepare_mesh(n_nodes, xyz, n_tets, tets, tags, lo, hi, nb, hm, err);
+        rc = prepare_mesh(n_nodes, xyz, n_tets, tets, tags, lo, hi, nb, hm, err, c->reorder);
         if (rc) return fail(c, static_cast<gspm_status>(rc), "upload_mesh: " + err);
         const size_t need = elem_lds_bytes(hm.nb, hm.nloc_max);
         if (need <= static_cast<size_t>(lds_max)) break;
@@ -392,7 +434,11 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->arena_size = 0;
     alloc_all();
     c->arena_planning = false;
-    rc = hip_check(c, hipMalloc(reinterpret_cast<void **>(&c->arena), c->arena_size), "hipMalloc (mesh arena)");
+    {
+        void *a = nullptr;
+        rc = ctx_malloc(c, &a, c->arena_size, "device allocation (mesh arena)");
+        c->arena = static_cast<char *>(a);
+    }
     if (rc) {
         c->arena = nullptr;
         c->arena_size = 0;

@@ -62,7 +62,8 @@ constexpr uint32_t kEntElem = 1u << 13;
 constexpr int kMaxLocal = 8191;           // staged nodes per block the entries can address
 
 int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets, const uint8_t *tags,
-                 const double lo[3], const double hi[3], int32_t nb, HostMesh &out, std::string &err);
+                 const double lo[3], const double hi[3], int32_t nb, HostMesh &out, std::string &err,
+                 int reorder = GSPM_REORDER_MORTON);
 
 // ------------------------------------------------------------- device views
 

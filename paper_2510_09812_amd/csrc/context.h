@@ -94,7 +94,11 @@ struct gspm_ctx {
     bool own_stream = false;
     int precision = GSPM_FP64;
     int block_nodes = 0;
+    int reorder = GSPM_REORDER_MORTON;
     bool profile = false;
+    void *(*alloc_fn)(size_t, void *) = nullptr;   // optional device allocator of the caller
+    void (*free_fn)(void *, void *) = nullptr;
+    void *alloc_user = nullptr;
     std::string err;
 
     bool have_mesh = false, have_params = false, have_m = false;
@@ -176,6 +180,9 @@ int green_apply64(gspm_ctx *c, const double *x, double *y);
 // or spec -> grid (inverse), the three components as one batch.
 int green_fft(gspm_ctx *c, bool forward);
 int hip_check(gspm_ctx *c, hipError_t e, const char *what);
+// Device memory of the context: the caller's allocator when given, else hipMalloc / hipFree.
+int ctx_malloc(gspm_ctx *c, void **p, size_t bytes, const char *what);
+void ctx_free(const gspm_ctx *c, void *p);
 // Warm start of the elastic solve on the right-hand side b: x (holding u^{n-1})
 // becomes u^{n-1} + a d + c e, d the network's increment at (m, mprev) (when
 // mprev != nullptr), e = u^{n-1} - uprev (when uprev != nullptr), (a, c) the

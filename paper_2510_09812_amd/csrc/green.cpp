@@ -32,12 +32,10 @@ int fft_fail(gspm_ctx *c, const char *what) {
 
 template <class T>
 int pc_alloc(gspm_ctx *c, T **p, size_t count) {
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * std::max<size_t>(count, 1));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return hip_check(c, e, "hipMalloc (elastic preconditioner)");
-    }
-    return GSPM_OK;
+    void *v = nullptr;
+    const int rc = ctx_malloc(c, &v, sizeof(T) * std::max<size_t>(count, 1), "device allocation (elastic preconditioner)");
+    *p = static_cast<T *>(v);
+    return rc;
 }
 
 // Engineering strain (xx yy zz yz xz xy) of the displacement e_a phi for a
@@ -369,6 +367,6 @@ void gspm_ctx::release_pc() {
     for (void *p : {static_cast<void *>(q.rptr), static_cast<void *>(q.rgrid), static_cast<void *>(q.rnode), q.rw,
                     q.dinv, q.ainv, q.grid, q.spec,
                     q.work, static_cast<void *>(q.aux)})
-        if (p) hipFree(p);
+        gspm::ctx_free(this, p);
     q = gspm::GreenState{};
 }

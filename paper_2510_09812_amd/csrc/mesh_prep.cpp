@@ -176,7 +176,7 @@ static int32_t pack_strips(const uint16_t *lc, const std::vector<int32_t> &order
 }
 
 int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets, const uint8_t *tags,
-                 const double lo[3], const double hi[3], int32_t nb, HostMesh &M, std::string &err) {
+                 const double lo[3], const double hi[3], int32_t nb, HostMesh &M, std::string &err, int reorder) {
     M = HostMesh();
     if (n0 < 4 || ne < 1 || n0 > INT32_MAX || ne > INT32_MAX) { err = "mesh needs 4..2^31-1 nodes and >= 1 tetrahedron"; return GSPM_E_ARG; }
     if (nb < 64 || nb > 1024 || (nb & (nb - 1))) { err = "block_nodes must be a power of two in [64, 1024]"; return GSPM_E_ARG; }
@@ -250,20 +250,69 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
     }
     M.vc = vc;
 
-    // ---- 3. Morton renumbering of the unique nodes
-    std::vector<uint64_t> code(static_cast<size_t>(n));
-    for (int32_t g = 0; g < n; ++g) {
-        uint64_t c = 0;
-        for (int a = 0; a < 3; ++a) {
-            double t = (xyz[rep[g] * 3 + a] - lo[a]) / M.L[a];
-            t = std::min(std::max(t, 0.0), 1.0 - 1e-12);
-            c |= spread3(static_cast<uint64_t>(t * 2097152.0)) << a;
-        }
-        code[g] = c;
-    }
+    // ---- 3. renumbering of the unique nodes: Morton curve (default), the
+    // caller's order, or reverse Cuthill-McKee on the mesh graph
     std::vector<int32_t> order(static_cast<size_t>(n));
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+    if (reorder == GSPM_REORDER_MORTON) {
+        std::vector<uint64_t> code(static_cast<size_t>(n));
+        for (int32_t g = 0; g < n; ++g) {
+            uint64_t c = 0;
+            for (int a = 0; a < 3; ++a) {
+                double t = (xyz[rep[g] * 3 + a] - lo[a]) / M.L[a];
+                t = std::min(std::max(t, 0.0), 1.0 - 1e-12);
+                c |= spread3(static_cast<uint64_t>(t * 2097152.0)) << a;
+            }
+            code[g] = c;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+    } else if (reorder == GSPM_REORDER_RCM) {
+        // node graph (vertices sharing a tetrahedron), breadth-first from a
+        // node of least degree, neighbours by increasing degree, reversed
+        std::vector<int64_t> deg(static_cast<size_t>(n) + 1, 0);
+        for (int64_t e = 0; e < ne; ++e)
+            for (int j = 0; j < 4; ++j) deg[static_cast<size_t>(uid[tets[e * 4 + j]]) + 1] += 3;
+        for (int32_t g = 0; g < n; ++g) deg[g + 1] += deg[g];
+        std::vector<int32_t> adj(static_cast<size_t>(deg[n]));
+        std::vector<int64_t> fill(deg.begin(), deg.end() - 1);
+        for (int64_t e = 0; e < ne; ++e)
+            for (int j = 0; j < 4; ++j)
+                for (int k = 0; k < 4; ++k)
+                    if (k != j) adj[fill[uid[tets[e * 4 + j]]]++] = uid[tets[e * 4 + k]];
+        std::vector<int32_t> nd(static_cast<size_t>(n));
+        for (int32_t g = 0; g < n; ++g) {
+            auto b = adj.begin() + deg[g], en = adj.begin() + deg[g + 1];
+            std::sort(b, en);
+            nd[g] = static_cast<int32_t>(std::unique(b, en) - b);
+        }
+        std::vector<uint8_t> seen(static_cast<size_t>(n), 0);
+        std::vector<int32_t> cm;
+        cm.reserve(static_cast<size_t>(n));
+        std::vector<int32_t> by_deg(order);
+        std::stable_sort(by_deg.begin(), by_deg.end(), [&](int32_t a, int32_t b) { return nd[a] < nd[b]; });
+        for (int32_t start : by_deg) {          // every connected component
+            if (seen[start]) continue;
+            seen[start] = 1;
+            size_t head = cm.size();
+            cm.push_back(start);
+            while (head < cm.size()) {
+                const int32_t g = cm[head++];
+                std::vector<int32_t> next;
+                for (int64_t q = deg[g]; q < deg[g] + nd[g]; ++q)
+                    if (!seen[adj[q]]) {
+                        seen[adj[q]] = 1;
+                        next.push_back(adj[q]);
+                    }
+                std::stable_sort(next.begin(), next.end(), [&](int32_t a, int32_t b) { return nd[a] < nd[b]; });
+                cm.insert(cm.end(), next.begin(), next.end());
+            }
+        }
+        std::reverse(cm.begin(), cm.end());
+        order = cm;
+    } else if (reorder != GSPM_REORDER_NONE) {
+        err = "unknown node order";
+        return GSPM_E_ARG;
+    }
     std::vector<int32_t> newid(static_cast<size_t>(n));
     for (int32_t k = 0; k < n; ++k) newid[order[k]] = k;
 

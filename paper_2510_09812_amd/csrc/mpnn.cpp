@@ -48,13 +48,10 @@ namespace {
 
 template <class T>
 int nn_alloc(gspm_ctx *c, T **p, size_t count) {
-    *p = nullptr;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * std::max<size_t>(count, 1));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return hip_check(c, e, "hipMalloc (network)");
-    }
-    return GSPM_OK;
+    void *v = nullptr;
+    const int rc = ctx_malloc(c, &v, sizeof(T) * std::max<size_t>(count, 1), "device allocation (network)");
+    *p = static_cast<T *>(v);
+    return rc;
 }
 
 gspm_status nfail(gspm_ctx *c, gspm_status s, const char *msg) {

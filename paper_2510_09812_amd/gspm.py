@@ -24,6 +24,7 @@ GSPM_PRECOND_NONE, GSPM_PRECOND_GREEN, GSPM_PRECOND_JACOBI = 0, 1, 2
 GSPM_PERIODIC = 1
 GSPM_WARM_PREVIOUS, GSPM_WARM_LEARNED, GSPM_WARM_EXTRAPOLATE = 0, 1, 2
 GSPM_SWEEP_STOP_ON_REVERSAL, GSPM_SWEEP_CONTINUE = 1, 2
+GSPM_REORDER_MORTON, GSPM_REORDER_NONE, GSPM_REORDER_RCM = 0, 1, 2
 GSPM_MPNN_PARAMS = 50819
 
 STATUS_NAMES = {0: "GSPM_OK", -1: "GSPM_E_ARG", -2: "GSPM_E_MESH", -3: "GSPM_E_STATE", -4: "GSPM_E_DEVICE",
@@ -43,9 +44,14 @@ class GspmError(RuntimeError):
         self.status = status
 
 
+DEV_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+DEV_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class gspm_create_opts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("block_nodes", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p), ("reorder", ctypes.c_int32),
+                ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN), ("alloc_user", ctypes.c_void_p)]
 
 
 class gspm_params(ctypes.Structure):
@@ -141,13 +147,35 @@ def gspm_last_error(ctx) -> str:
     return load().gspm_last_error(ctx).decode()
 
 
+def torch_allocator(device: int = 0):
+    """A (dev_alloc, dev_free) pair of C callbacks that take the context's
+    device memory from PyTorch's caching allocator on `device` (keep the pair
+    alive as long as the context)."""
+    import torch
+
+    def alloc(nbytes, _user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        except Exception:
+            return None
+
+    def free(ptr, _user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return DEV_ALLOC_FN(alloc), DEV_FREE_FN(free)
+
+
 def gspm_create(device: int = 0, precision: int = GSPM_FP64, block_nodes: int = 0, profile: bool = False,
-                stream=None):
+                stream=None, reorder: int = GSPM_REORDER_MORTON, allocator=None):
     """Returns an opaque context handle.  `stream` may be a torch.cuda.Stream
-    (the library then runs on it) or a raw hipStream_t integer."""
-    opts = gspm_create_opts(device, precision, block_nodes, 1 if profile else 0, None)
+    (the library then runs on it) or a raw hipStream_t integer; `allocator` a
+    (dev_alloc, dev_free) pair of C callbacks (see torch_allocator), which the
+    caller keeps alive as long as the context."""
+    opts = gspm_create_opts(device, precision, block_nodes, 1 if profile else 0, None, reorder)
     if stream is not None:
         opts.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    if allocator is not None:
+        opts.dev_alloc, opts.dev_free = allocator
     h = ctypes.c_void_p()
     _check(None, load().gspm_create(ctypes.byref(h), ctypes.byref(opts)))
     return h
@@ -404,6 +432,7 @@ class Simulation:
 
     def __init__(self, mesh, params: dict | None = None, hext=(0.0, 0.0, 0.0), sigma_ext=(0.0,) * 6,
                  precession: bool = True, local_demag: bool = False, **create_kw):
+        self._allocator = create_kw.get("allocator")    # C callbacks must outlive the context
         self.ctx = gspm_create(**create_kw)
         self.n0 = int(np.asarray(mesh.xyz).shape[0])
         gspm_upload_mesh(self.ctx, mesh.xyz, mesh.tets, mesh.tags, mesh.lo, mesh.hi)

@@ -4,7 +4,7 @@
 // non-magnetic groups apart), every local id must index a staged node, every
 // segment must stay inside its entries, and no block may have more segments
 // than a workgroup has threads.
-// Usage: strip_check <mesh.bin> <block_nodes>; prints statistics, exit 0 if valid.
+// Usage: strip_check <mesh.bin> <block_nodes> [reorder]; prints statistics, exit 0 if valid.
 #include <algorithm>
 #include <cstdio>
 #include <map>
@@ -22,8 +22,9 @@ int main(int argc, char **argv) {
     std::vector<double> xyz(3 * n0); std::vector<int32_t> tets(4 * ne); std::vector<uint8_t> tags(ne);
     fread(xyz.data(), 8, 3 * n0, fp); fread(tets.data(), 4, 4 * ne, fp); fread(tags.data(), 1, ne, fp); fclose(fp);
     int nb = argc > 2 ? atoi(argv[2]) : 256;
+    int reorder = argc > 3 ? atoi(argv[3]) : GSPM_REORDER_MORTON;
     HostMesh M; std::string err;
-    int rc = prepare_mesh(n0, xyz.data(), ne, tets.data(), tags.data(), lo, hi, nb, M, err);
+    int rc = prepare_mesh(n0, xyz.data(), ne, tets.data(), tags.data(), lo, hi, nb, M, err, reorder);
     if (rc) { printf("prepare failed %s\n", err.c_str()); return 1; }
     long bad = 0, loads = 0, elems = 0, flush = 0, segs_total = 0;
     for (int b = 0; b < M.nblk; ++b) {

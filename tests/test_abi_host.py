@@ -63,3 +63,15 @@ def test_demag_factors_closed_forms():
     assert abs(N.sum() - 1.0) < 1e-13
     with pytest.raises(gspm.GspmError):
         gspm.gspm_demag_factors(-1.0, 1.0, 1.0)
+
+
+def test_create_option_checks_without_a_device():
+    with pytest.raises(gspm.GspmError) as e:
+        gspm.gspm_create(reorder=9)
+    assert e.value.status == gspm.GSPM_E_ARG
+    only_alloc = (gspm.DEV_ALLOC_FN(lambda n, u: None), None)
+    opts = gspm.gspm_create_opts(0, 0, 0, 0, None, 0)
+    opts.dev_alloc = only_alloc[0]
+    import ctypes
+    h = ctypes.c_void_p()
+    assert gspm.load().gspm_create(ctypes.byref(h), ctypes.byref(opts)) == gspm.GSPM_E_ARG

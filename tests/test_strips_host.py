@@ -52,3 +52,15 @@ def test_strip_segments_decode_to_the_element_lists(checker, name, mesh, nb):
     assert r.returncode == 0, r.stdout
     loads = float(r.stdout.split("loads/elem ")[1].split()[0])
     assert loads < 2.0       # strips share faces: far fewer than 4 loads per element (short segments at nb 64)
+
+
+@pytest.mark.parametrize("reorder", [1, 2])
+def test_strips_under_the_other_node_orders(checker, reorder):
+    """The caller's order (1) and reverse Cuthill-McKee (2) give other owner
+    blocks and halos; the encoding must still decode to the element lists."""
+    exe, d = checker
+    path = str(d / f"order{reorder}.bin")
+    _dump(w.small_cube(15, seed=7, L=1e-7, jitter=0.15, sphere=0.3).mesh, path)
+    r = subprocess.run([exe, path, "256", str(reorder)], capture_output=True, text=True)
+    print(r.stdout.strip())
+    assert r.returncode == 0, r.stdout
