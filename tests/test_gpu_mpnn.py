@@ -37,8 +37,8 @@ def _init_params(seed, scale=1.0):
     return N.pack(p).astype(np.float32)
 
 
-def _setup(n=9, seed=401, shuffle=True):
-    case = w.small_cube(n, seed=seed, L=8e-8, jitter=0.15, sphere=0.3, shuffle=shuffle)
+def _setup(n=9, seed=401, shuffle=True, split="kuhn"):
+    case = w.small_cube(n, seed=seed, L=8e-8, jitter=0.15, sphere=0.3, shuffle=shuffle, split=split)
     orc = O.Oracle.from_mesh(case.mesh)
     orc.set_params(case.params)
     g = N.Graph.from_oracle(orc, case.mesh)
@@ -63,8 +63,9 @@ def _oracle_inputs(orc, m, mp):
     return mu, mpu, wts
 
 
-def test_forward_matches_oracle():
-    case, orc, g, m, mp = _setup()
+@pytest.mark.parametrize("split", ["kuhn", "five"])
+def test_forward_matches_oracle(split):
+    case, orc, g, m, mp = _setup(split=split)
     params = _init_params(11)
     sim = gspm.Simulation(case.mesh, case.params)
     sim.set_m(m)

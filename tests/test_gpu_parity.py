@@ -39,6 +39,9 @@ CASES = {
     "ragged5_sphere_shuffled": lambda: w.small_cube(5, seed=101, L=4e-8, jitter=0.15, sphere=0.3, shuffle=True),
     "cube10": lambda: w.cube10_random(),
     "ragged13_sphere": lambda: w.small_cube(13, seed=102, L=1.2e-7, jitter=0.15, sphere=0.25),
+    # a second tetrahedralization: five tetrahedra per cell, 8 or 32 per node
+    "five11_sphere_shuffled": lambda: w.small_cube(11, seed=103, L=1e-7, jitter=0.15, sphere=0.3, shuffle=True,
+                                                   split="five"),
 }
 
 

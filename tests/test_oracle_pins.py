@@ -752,3 +752,28 @@ def test_dm_avg_is_the_mean_over_magnetic_nodes():
     chord = np.linalg.norm(m1[mag_user][0] - d0)
     assert chord > 1e-3
     assert abs(st["dm_avg"] - chord) < 1e-12 * chord
+
+
+# ------------------------------------ a second tetrahedralization (valence)
+
+def test_five_tet_split_geometry_and_patch_tests():
+    """The five-tetrahedron split (variable valence: 8 or 32 tetrahedra per
+    node) through the same identities: volumes sum to the cell, the Laplacian
+    and the elastic operator vanish on linear fields at interior nodes."""
+    case = w.small_cube(7, seed=14, L=1e-7, jitter=0.15, split="five")
+    cnt = np.bincount(case.mesh.site[case.mesh.tets].ravel(), minlength=case.mesh.n_sites)
+    assert set(np.unique(cnt)) == {8, 32}
+    orc = O.Oracle.from_mesh(case.mesh)
+    vol, _ = orc.geometry()
+    assert np.isclose(vol.sum(), 1e-21, rtol=1e-12)
+    un = O.Oracle.from_mesh(case.mesh, periodic=False)
+    un.set_params(MAT)
+    X = case.mesh.xyz
+    interior = np.all((X > 1e-12) & (X < 1e-7 - 1e-12), axis=1)
+    G = np.array([[0.3, -1.2, 2.0], [1.1, 0.4, -0.5], [-0.2, 0.9, 0.6]])
+    lin = X @ G.T + 0.7e-7
+    for op, x in ((O.OP_LAPLACE, np.repeat(lin[:, :1], 3, axis=1)), (O.OP_ELASTIC, lin)):
+        y = un.apply(op, x)
+        edge = np.abs(y[~interior]).max()
+        assert edge > 0.0
+        assert np.abs(y[interior]).max() < 1e-10 * edge

@@ -42,6 +42,8 @@ def _dump(mesh, path):
     ("ragged9_sphere_shuffled", lambda: w.small_cube(9, seed=5, L=8e-8, jitter=0.15, sphere=0.3, shuffle=True).mesh, 1024),
     ("cube10", lambda: w.cube10_random().mesh, 256),
     ("ragged23_sphere", lambda: w.small_cube(23, seed=6, L=1e-7, jitter=0.15, sphere=0.25).mesh, 256),
+    ("five17_sphere_shuffled", lambda: w.small_cube(17, seed=8, L=1e-7, jitter=0.15, sphere=0.3, shuffle=True,
+                                                    split="five").mesh, 256),
 ])
 def test_strip_segments_decode_to_the_element_lists(checker, name, mesh, nb):
     exe, d = checker

@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .mesh import Inclusion, Mesh, kuhn_cube, random_rotation, tag_inclusions
+from .mesh import Inclusion, Mesh, five_tet_cube, kuhn_cube, random_rotation, tag_inclusions
 
 MU0 = 4e-7 * np.pi
 # Gyromagnetic ratio of the dimensionless time tau = gamma0 * Ms * t, in m/(A s).
@@ -138,11 +138,14 @@ def cube144_ellipsoids(seed: int = 4) -> Case:
 
 def small_cube(n: int, seed: int, L: float = 40e-9, jitter: float = 0.15, sphere: float = 0.0,
                m: str = "random", hext=(0.0, 0.0, 0.0), dt: float = 2e-12, steps: int = 5,
-               shuffle: bool = False) -> Case:
+               shuffle: bool = False, split: str = "kuhn") -> Case:
     """Small test meshes of arbitrary (ragged) size; optional centred sphere of
-    radius `sphere` (fraction of L) and seeded node shuffling."""
+    radius `sphere` (fraction of L), seeded node shuffling, and the cell split
+    ("kuhn": six tetrahedra per cell; "five": five, alternating by parity,
+    n - 1 even)."""
     s_mesh, s_m, s_perm = np.random.SeedSequence(seed).spawn(3)
-    mesh = kuhn_cube(n, L, jitter=jitter, rng=np.random.default_rng(s_mesh) if jitter > 0 else None)
+    gen = five_tet_cube if split == "five" else kuhn_cube
+    mesh = gen(n, L, jitter=jitter, rng=np.random.default_rng(s_mesh) if jitter > 0 else None)
     if sphere > 0.0:
         tag_inclusions(mesh, [Inclusion(center=np.full(3, L / 2), semi=np.full(3, sphere * L))])
     if shuffle:

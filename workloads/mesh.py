@@ -96,6 +96,56 @@ def kuhn_cube(n: int, L: float, jitter: float = 0.0, rng: np.random.Generator | 
                 n_axis=n, site=site.astype(np.int64))
 
 
+# Five-tetrahedron split of a unit cell (corner bits x | y << 1 | z << 2): a
+# central tetrahedron on four alternate corners and one tetrahedron cutting off
+# each of the other four.  Cells alternate between the two mirror images by
+# the parity of i + j + k, so that neighbouring cells split their shared face
+# along the same diagonal.
+_FIVE_EVEN = [(0, 3, 5, 6), (1, 0, 3, 5), (2, 0, 3, 6), (4, 0, 5, 6), (7, 3, 5, 6)]
+_FIVE_ODD = [(1, 2, 4, 7), (0, 1, 2, 4), (3, 1, 2, 7), (5, 1, 4, 7), (6, 2, 4, 7)]
+
+
+def five_tet_cube(n: int, L: float, jitter: float = 0.0, rng: np.random.Generator | None = None,
+                  lo: float = 0.0) -> Mesh:
+    """n nodes per axis on [lo, lo+L]^3 (n - 1 even, so the alternation also
+    matches across the periodic faces), each cell split into five tetrahedra:
+    5 (n-1)^3 tetrahedra; half the nodes carry 8 tetrahedra and 6 edge
+    neighbours, the other half 32 and 18 (the Kuhn split gives every node 24
+    and 14).  Jitter as in kuhn_cube."""
+    if n < 3 or (n - 1) % 2:
+        raise ValueError("the five-tetrahedron split needs an even number of cells per axis")
+    h = L / (n - 1)
+    kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ii = ii.ravel(); jj = jj.ravel(); kk = kk.ravel()
+    xyz = np.stack([ii, jj, kk], axis=1).astype(np.float64) * h + lo
+    if jitter > 0.0:
+        if rng is None:
+            raise ValueError("jitter needs a seeded generator")
+        interior = ((ii > 0) & (ii < n - 1) & (jj > 0) & (jj < n - 1) & (kk > 0) & (kk < n - 1))
+        xyz[interior] += rng.uniform(-jitter * h, jitter * h, size=(int(interior.sum()), 3))
+    m = n - 1
+    site = (ii % m) + m * ((jj % m) + m * (kk % m))
+    cz, cy, cx = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    cx = cx.ravel(); cy = cy.ravel(); cz = cz.ravel()
+    base = (cx + n * (cy + n * cz)).astype(np.int64)
+    corner = np.array([(b & 1) + n * (((b >> 1) & 1) + n * (b >> 2)) for b in range(8)], dtype=np.int64)
+    odd = (cx + cy + cz) % 2 == 1
+    tets = np.empty((base.shape[0], 5, 4), dtype=np.int64)
+    for t in range(5):
+        te = corner[list(_FIVE_EVEN[t])]
+        to = corner[list(_FIVE_ODD[t])]
+        tets[:, t, :] = base[:, None] + np.where(odd[:, None], to[None, :], te[None, :])
+    tets = tets.reshape(-1, 4)
+    # positive orientation on the unjittered lattice
+    X = (np.stack([ii, jj, kk], axis=1).astype(np.float64))[tets]
+    det = np.linalg.det(X[:, 1:] - X[:, :1])
+    flip = det < 0
+    tets[flip, 2], tets[flip, 3] = tets[flip, 3].copy(), tets[flip, 2].copy()
+    tags = np.ones(tets.shape[0], dtype=np.uint8)
+    return Mesh(xyz=xyz, tets=tets.astype(np.int32), tags=tags, lo=np.full(3, lo), hi=np.full(3, lo + L),
+                n_axis=n, site=site.astype(np.int64))
+
+
 def random_rotation(rng: np.random.Generator) -> np.ndarray:
     """Uniformly distributed rotation from a normalised Gaussian quaternion."""
     q = rng.standard_normal(4)
