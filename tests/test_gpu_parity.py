@@ -144,6 +144,17 @@ def test_step_with_inclusion_field_and_stress(precession, cg_tol, tol):
     sim.close()
 
 
+def test_step_on_the_five_tet_split():
+    """Node valence 8 and 32 (two tet orientations alternating per cell): three
+    steps with an inclusion, an applied field and stress."""
+    case = w.small_cube(11, seed=105, L=1e-7, jitter=0.15, sphere=0.3, shuffle=True, split="five")
+    sigma = np.array([3e6, -1e6, 2e6, 0.4e6, -0.2e6, 0.8e6])
+    sim, orc, st, ost = _run_both(case, 3, hext=(0.1 * case.material["Ms"], -0.15 * case.material["Ms"], 0.0),
+                                  sigma=sigma, tol=1e-12)
+    _compare_states(sim, orc, st, ost, 1e-9)
+    sim.close()
+
+
 def test_unit_length_and_inclusion_zero():
     case = w.small_cube(9, seed=104, L=8e-8, jitter=0.15, sphere=0.35)
     sim, orc, st, ost = _run_both(case, 3)

@@ -45,6 +45,8 @@ CASES = {
     "jittered9_sphere_shuffled": lambda: w.small_cube(9, seed=111, L=8 * H, jitter=0.15, sphere=0.3, shuffle=True),
     "regular8": lambda: w.small_cube(8, seed=112, L=7 * H, jitter=0.0),
     "jittered17_sphere": lambda: w.small_cube(17, seed=113, L=16 * H, jitter=0.15, sphere=0.25),
+    "five13_sphere_shuffled": lambda: w.small_cube(13, seed=117, L=12 * H, jitter=0.15, sphere=0.3, shuffle=True,
+                                                   split="five"),
 }
 
 
