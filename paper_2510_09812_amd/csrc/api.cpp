@@ -234,8 +234,15 @@ void gspm_ctx::release_mesh() {
     dev_free(this, b.cgi_flags);
     dev_free(this, b.mprev); dev_free(this, b.uprev); dev_free(this, b.du_prev); dev_free(this, b.kdu); dev_free(this, b.wred); dev_free(this, b.wcoef);
     dev_free(this, b.ud); dev_free(this, b.udnext); dev_free(this, b.rep);
-    dev_free(this, b.cg_rz); dev_free(this, b.cgi_rz); dev_free(this, b.jkd); dev_free(this, b.jmd);
-    dev_free(this, b.jkd32); dev_free(this, b.jmd32);
+    dev_free(this, b.cg_rz); dev_free(this, b.cgi_rz);
+    dev_free(this, b.cg_rzq); dev_free(this, b.cg_qzq); dev_free(this, b.cgi_rzq); dev_free(this, b.cgi_qzq);
+    dev_free(this, b.gs_off); dev_free(this, b.gs_col); dev_free(this, b.gs_kv); dev_free(this, b.gs_mv);
+    dev_free(this, b.gs_kd); dev_free(this, b.gs_md);
+    for (int k = 0; k < 2; ++k) {
+        dev_free(this, b.gs_a64[k]); dev_free(this, b.gs_d64[k]); dev_free(this, b.gs_a32[k]); dev_free(this, b.gs_d32[k]);
+        gs_slot[k] = gspm::GsSlot{};
+    }
+    gs_nent = 0;
     if (arena) gspm::ctx_free(this, arena);
     arena = nullptr;
     arena_size = arena_used = 0;
@@ -370,8 +377,12 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
                                            std::to_string(lds_max) + "; use smaller block_nodes");
         nb /= 2;                   // automatic block size: halve until the element kernels fit
     }
+    GsRowsHost rows;
+    rc = assemble_gs_rows(hm, n_tets, tets, tags, rows, err);
+    if (rc) return fail(c, static_cast<gspm_status>(rc), "upload_mesh: " + err);
     c->release_mesh();
     const size_t n = static_cast<size_t>(hm.n), n3 = 3 * n;
+    const size_t nent = rows.col.size();
     auto &d = c->d;
     const size_t nstc = static_cast<size_t>(hm.nblk) * hm.nb + hm.halo_ids.size();
     const size_t nseg = hm.seg_nel.size();
@@ -400,8 +411,18 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
         rc = rc ? rc : dev_alloc(c, &d.udnext, n);
         rc = rc ? rc : dev_alloc(c, &d.rep, n);
         rc = rc ? rc : dev_alloc(c, &d.cg_rz, static_cast<size_t>(kMaxComp) * kRing * kShards);
-        rc = rc ? rc : dev_alloc(c, &d.jkd, n);
-        rc = rc ? rc : dev_alloc(c, &d.jmd, n);
+        rc = rc ? rc : dev_alloc(c, &d.cg_rzq, static_cast<size_t>(kMaxComp) * kRing * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.cg_qzq, static_cast<size_t>(kMaxComp) * kRing * kShards);
+        rc = rc ? rc : dev_alloc(c, &d.gs_off, rows.off.size());
+        rc = rc ? rc : dev_alloc(c, &d.gs_col, nent);
+        rc = rc ? rc : dev_alloc(c, &d.gs_kv, nent);
+        rc = rc ? rc : dev_alloc(c, &d.gs_mv, nent);
+        rc = rc ? rc : dev_alloc(c, &d.gs_kd, n);
+        rc = rc ? rc : dev_alloc(c, &d.gs_md, n);
+        for (int k = 0; k < 2; ++k) {
+            rc = rc ? rc : dev_alloc(c, &d.gs_a64[k], nent);
+            rc = rc ? rc : dev_alloc(c, &d.gs_d64[k], n);
+        }
         rc = rc ? rc : dev_alloc(c, &d.wred, static_cast<size_t>(mpnn::kMrSums) * kShards);
         rc = rc ? rc : dev_alloc(c, &d.wcoef, 2);
         rc = rc ? rc : dev_alloc(c, &d.ch2, 2 * n);
@@ -425,8 +446,12 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
             rc = rc ? rc : dev_alloc(c, &d.cgi_bb, static_cast<size_t>(kMaxComp) * kShards);
             rc = rc ? rc : dev_alloc(c, &d.cgi_flags, 2 * kMaxComp);
             rc = rc ? rc : dev_alloc(c, &d.cgi_rz, static_cast<size_t>(kMaxComp) * kRing * kShards);
-            rc = rc ? rc : dev_alloc(c, &d.jkd32, n);
-            rc = rc ? rc : dev_alloc(c, &d.jmd32, n);
+            rc = rc ? rc : dev_alloc(c, &d.cgi_rzq, static_cast<size_t>(kMaxComp) * kRing * kShards);
+            rc = rc ? rc : dev_alloc(c, &d.cgi_qzq, static_cast<size_t>(kMaxComp) * kRing * kShards);
+            for (int k = 0; k < 2; ++k) {
+                rc = rc ? rc : dev_alloc(c, &d.gs_a32[k], nent);
+                rc = rc ? rc : dev_alloc(c, &d.gs_d32[k], n);
+            }
         }
         return rc;
     };
@@ -461,56 +486,15 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     hipMemcpyAsync(d.blk_ptr, hm.blk_ptr.data(), sizeof(int32_t) * hm.blk_ptr.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.blk_nmag, hm.blk_nmag.data(), sizeof(int32_t) * hm.blk_nmag.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.w, hm.w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
-    {
-        // diagonals of the GS operator's parts (magnetic elements): K_ii = sum V |grad lambda_i|^2,
-        // M_ii = sum V / 10; Jacobi preconditioning takes D = eps K_ii + M_ii
-        std::vector<double> kd(n, 0.0), md(n, 0.0);
-        const double Lb[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
-        for (int64_t e = 0; e < n_tets; ++e) {
-            if (!tags[e]) continue;
-            const int32_t *t = tets + 4 * e;
-            double E[3][3];
-            for (int k = 0; k < 3; ++k)
-                for (int a = 0; a < 3; ++a) {
-                    double dv = xyz[3 * static_cast<int64_t>(t[k + 1]) + a] - xyz[3 * static_cast<int64_t>(t[0]) + a];
-                    dv -= Lb[a] * std::nearbyint(dv / Lb[a]);
-                    E[k][a] = dv;
-                }
-            double cf[3][3];
-            for (int k = 0; k < 3; ++k) {
-                const double *a = E[(k + 1) % 3], *bb = E[(k + 2) % 3];
-                cf[k][0] = a[1] * bb[2] - a[2] * bb[1];
-                cf[k][1] = a[2] * bb[0] - a[0] * bb[2];
-                cf[k][2] = a[0] * bb[1] - a[1] * bb[0];
-            }
-            const double det = E[0][0] * cf[0][0] + E[0][1] * cf[0][1] + E[0][2] * cf[0][2];
-            const double V = std::fabs(det) / 6.0;
-            double g[4][3];
-            for (int k = 0; k < 3; ++k)
-                for (int a = 0; a < 3; ++a) g[k + 1][a] = cf[k][a] / det;
-            for (int a = 0; a < 3; ++a) g[0][a] = -(g[1][a] + g[2][a] + g[3][a]);
-            for (int j = 0; j < 4; ++j) {
-                const size_t node = static_cast<size_t>(hm.user2int[t[j]]);
-                kd[node] += V * (g[j][0] * g[j][0] + g[j][1] * g[j][1] + g[j][2] * g[j][2]);
-                md[node] += V / 10.0;
-            }
-        }
-        hipMemcpyAsync(d.jkd, kd.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
-        hipMemcpyAsync(d.jmd, md.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
-        if (c->precision == GSPM_MIXED) {
-            const double ls = std::cbrt(hm.vc / static_cast<double>(hm.ne));
-            std::vector<float> k32(n), m32(n);
-            for (size_t i = 0; i < n; ++i) {
-                k32[i] = static_cast<float>(kd[i] / ls);
-                m32[i] = static_cast<float>(md[i] / (ls * ls * ls));
-            }
-            hipMemcpyAsync(d.jkd32, k32.data(), sizeof(float) * n, hipMemcpyHostToDevice, s);
-            hipMemcpyAsync(d.jmd32, m32.data(), sizeof(float) * n, hipMemcpyHostToDevice, s);
-            hipStreamSynchronize(s);
-        } else {
-            hipStreamSynchronize(s);
-        }
+    hipMemcpyAsync(d.gs_off, rows.off.data(), sizeof(int32_t) * rows.off.size(), hipMemcpyHostToDevice, s);
+    if (nent) {
+        hipMemcpyAsync(d.gs_col, rows.col.data(), sizeof(uint16_t) * nent, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(d.gs_kv, rows.kv.data(), sizeof(double) * nent, hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(d.gs_mv, rows.mv.data(), sizeof(double) * nent, hipMemcpyHostToDevice, s);
     }
+    hipMemcpyAsync(d.gs_kd, rows.kd.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.gs_md, rows.md.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
+    c->gs_nent = static_cast<int64_t>(nent);
     std::vector<int32_t> rep(n, -1);
     for (int64_t i = hm.n0 - 1; i >= 0; --i) rep[static_cast<size_t>(hm.user2int[i])] = static_cast<int32_t>(i);
     hipMemcpyAsync(d.rep, rep.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
@@ -583,6 +567,8 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->cg.rq = d.cg_rq;
     c->cg.qq = d.cg_qq;
     c->cg.rz = d.cg_rz;
+    c->cg.rzq = d.cg_rzq;
+    c->cg.qzq = d.cg_qzq;
     c->cg.done = d.cg_flags;
     c->cg.iters = d.cg_flags + kMaxComp;
     c->cg.ring = kRing;
@@ -592,6 +578,8 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     c->cg_in.rq = d.cgi_rq;
     c->cg_in.qq = d.cgi_qq;
     c->cg_in.rz = d.cgi_rz;
+    c->cg_in.rzq = d.cgi_rzq;
+    c->cg_in.qzq = d.cgi_qzq;
     c->cg_in.done = d.cgi_flags;
     c->cg_in.iters = d.cgi_flags ? d.cgi_flags + kMaxComp : nullptr;
     c->cg_in.ring = kRing;
@@ -878,8 +866,8 @@ gspm_status gspm_apply(gspm_ctx *c, gspm_op op, double eps, const double *x, dou
     } else {
         const double e = op == GSPM_OP_LAPLACE ? 1.0 : (op == GSPM_OP_MASS ? 0.0 : eps);
         const double mass = op == GSPM_OP_LAPLACE ? 0.0 : 1.0;
-        launch_gs_matvec<double>(c->mv, 3, e, mass, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr, c->cg, 0,
-                                 0.0, c->stream);
+        launch_gs_rows<double>(c->mv, gs_rows(c, e, mass, false), 3, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr,
+                               c->cg, c->stream);
     }
     rc = download(c, c->d.q, h);
     if (rc) return static_cast<gspm_status>(rc);
@@ -939,8 +927,10 @@ gspm_status gspm_time_operator(gspm_ctx *c, gspm_op op, double eps, int32_t reps
     hipSetDevice(c->device);
     const double e = op == GSPM_OP_LAPLACE ? 1.0 : (op == GSPM_OP_MASS ? 0.0 : eps);
     const double mass = op == GSPM_OP_LAPLACE ? 0.0 : 1.0;
-    hipEventRecord(c->t0, c->stream);
     const bool f32 = c->precision == GSPM_MIXED;   // time the operator the inner solves use
+    const bool gsop = op != GSPM_OP_ELASTIC && op != GSPM_OP_MS;
+    const GsRowsView rv = gsop ? gs_rows(c, e, mass, f32) : GsRowsView{};
+    hipEventRecord(c->t0, c->stream);
     for (int i = 0; i < reps; ++i) {
         if (op == GSPM_OP_ELASTIC) {
             if (f32)
@@ -959,11 +949,9 @@ gspm_status gspm_time_operator(gspm_ctx *c, gspm_op op, double eps, int32_t reps
                                          0.0, c->stream);
         } else {
             if (f32)
-                launch_gs_matvec<float>(c->mv, 3, e, mass, MV_APPLY, c->d.r32, c->d.q32, nullptr, nullptr, nullptr,
-                                        c->cg, 0, 0.0, c->stream);
+                launch_gs_rows<float>(c->mv, rv, 3, MV_APPLY, c->d.r32, c->d.q32, nullptr, nullptr, c->cg, c->stream);
             else
-                launch_gs_matvec<double>(c->mv, 3, e, mass, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, nullptr,
-                                         c->cg, 0, 0.0, c->stream);
+                launch_gs_rows<double>(c->mv, rv, 3, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, c->cg, c->stream);
         }
     }
     hipEventRecord(c->t1, c->stream);

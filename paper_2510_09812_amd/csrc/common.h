@@ -65,6 +65,24 @@ int prepare_mesh(int64_t n0, const double *xyz, int64_t ne, const int32_t *tets,
                  const double lo[3], const double hi[3], int32_t nb, HostMesh &out, std::string &err,
                  int reorder = GSPM_REORDER_MORTON);
 
+// Rows of the GS operator's two parts over magnetic elements, K (Laplacian)
+// and M (consistent mass), assembled on the host at upload (gs_rows.cpp).
+// Rows are in internal node order, in slices of 64 (one per wavefront);
+// slice s holds its rows' off-diagonal entries entry-major, entry k of lane l
+// at off[s] + 64 k + l, padded to the slice's longest row with zero
+// coefficients whose column is the row itself.  Columns index the row's
+// owner-block staging: owned node j -> j - n0, halo node -> nb + its position
+// in the block's halo list.
+struct GsRowsHost {
+    std::vector<int32_t> off;     // slices + 1
+    std::vector<uint16_t> col;    // entries
+    std::vector<double> kv, mv;   // entries: K_ij, M_ij (i != j)
+    std::vector<double> kd, md;   // n: K_ii, M_ii
+};
+
+int assemble_gs_rows(const HostMesh &hm, int64_t ne, const int32_t *tets, const uint8_t *tags, GsRowsHost &out,
+                     std::string &err);
+
 // ------------------------------------------------------------- device views
 
 // Mesh as the element kernels see it: node coordinates (FP64), and per owner
@@ -124,6 +142,7 @@ struct CGScalars {
     double *bb;                   // [comp][kShards]: b . b
     double *rq, *qq;              // [ring][kShards]: r_k . A p_k, |A p_k|^2 (single-reduction CG, one scalar set)
     double *rz;                   // [comp][ring][kShards]: r_k . D^-1 r_k (Jacobi-preconditioned GS solves)
+    double *rzq, *qzq;            // [comp][ring][kShards]: r_k . D^-1 q_k, q_k . D^-1 q_k (single-reduction GS solves)
     int32_t *done;                // [comp]: 0 running, 1 converged, 2 broke down (non-finite)
     int32_t *iters;               // [comp]: iterations at convergence
     int32_t ring;
@@ -133,6 +152,12 @@ struct CGScalars {
     }
     __host__ __device__ double *rz_at(int c, int k) const {
         return rz + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
+    }
+    __host__ __device__ double *rzq_at(int c, int k) const {
+        return rzq + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
+    }
+    __host__ __device__ double *qzq_at(int c, int k) const {
+        return qzq + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
     }
     __host__ __device__ double *pq_at(int c, int k) const {
         return pq + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
@@ -144,6 +169,36 @@ struct CGScalars {
 };
 
 enum MatvecMode { MV_APPLY = 0, MV_ITER = 1, MV_RESID = 2 };
+
+// The GS operator A = eps K + mass M in row form (see GsRowsHost), with the
+// coefficients of one (eps, mass) pair in the working precision T (FP32: A
+// divided by len_scale^3, the scaling of the FP32 operators).
+struct GsRowsView {
+    const int32_t *off;           // per 64-row slice: first entry; width = (off[s + 1] - off[s]) / 64
+    const uint16_t *col;          // entries: staged local column index
+    const void *a;                // entries: off-diagonal coefficients (T)
+    const void *d;                // n: diagonal (T); also the Jacobi preconditioner's D
+};
+
+// The GS operator in row form on nc components: APPLY out = A in; RESID
+// r = b - A in on the components not converged, with r.r into rr[0].
+template <class T>
+void launch_gs_rows(const MeshView &mv, const GsRowsView &rv, int nc, MatvecMode mode, const T *in, T *out,
+                    const T *b, T *r, const CGScalars &cg, hipStream_t s);
+// Single-reduction CG iteration k on the GS operator in row form (nc
+// components, one launch per iteration; Jacobi-preconditioned when jacobi):
+// completes iteration k-1 (x, r) from the sums p.q, r.r, r.D^-1 r, r.D^-1 q
+// and q.D^-1 q of launch k-1, forms p_k, and writes q_k = A p_k with the sums
+// of iteration k.  Buffers and the last launch as for launch_elastic_cg; the
+// start residual's |r_0|^2 must be in slot 0.
+template <class T>
+void launch_gs_rows_cg(const MeshView &mv, const GsRowsView &rv, int nc, int k, bool last, const T *rin, const T *pin,
+                       const T *qin, T *rout, T *pout, T *qout, T *x, const CGScalars &cg, double tol, bool jacobi,
+                       hipStream_t s, const hipEvent_t *ev = nullptr);
+// out[i] = (T) (scale (eps kv[i] + mass mv[i])) for i < count.
+template <class T>
+void launch_gs_combine(int64_t count, const double *kv, const double *mv, double eps, double mass, double scale,
+                       T *out, hipStream_t s);
 
 // Preconditioned CG on the elastic system keeps r_k . z_k of iteration k in
 // the single-reduction slots of its scalar set: k = 0 in rq[0], k > 0 in
@@ -270,18 +325,6 @@ template <class T>
 void launch_elastic_cg(const MeshView &mv, const Material &mat, int k, bool last, const T *rin, const T *pin,
                        const T *qin, T *rout, T *pout, T *qout, T *x, const CGScalars &cg, double tol, hipStream_t s,
                        const hipEvent_t *ev = nullptr);
-// jkd, jmd (nullable): Jacobi preconditioning with D = eps jkd + mass jmd per
-// node (zero rows stay zero): ITER forms p = D^-1 r + beta p with beta =
-// rz[k] / rz[k-1] (the test still on |r|), and at k = 0 adds r . D^-1 r to rz[0].
-template <class T>
-void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
-                      const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s,
-                      const T *jkd = nullptr, const T *jmd = nullptr, const hipEvent_t *ev = nullptr);
-// The Jacobi-preconditioned GS iteration's update: alpha = rz[k] / pq[k];
-// x += alpha p; r -= alpha q; rr[k+1] += r.r; rz[k+1] += r . D^-1 r.
-template <class T>
-void launch_cg_update_jacobi(int n, int nc, T *x, T *r, const T *p, const T *q, const T *jkd, const T *jmd,
-                             double eps, const CGScalars &cg, int k, hipStream_t s);
 // K^ms (Laplacian over all elements) on nc = 1 or 3 components, rows of the
 // pinned node zero; modes as above.  FP32: A' = K^ms / len_scale^3.
 // One launch of single-reduction CG on K^ms (one component), with the

@@ -50,8 +50,22 @@ struct DeviceBuffers {
     double *ud = nullptr, *udnext = nullptr;   // n: local magnetostatic potential (committed, in progress)
     int32_t *rep = nullptr;       // n: the first caller node of each unique node
     double *cg_rz = nullptr, *cgi_rz = nullptr;   // r . D^-1 r rings of the Jacobi-preconditioned GS solves
-    double *jkd = nullptr, *jmd = nullptr;        // n: diagonals of K and M over magnetic elements
-    float *jkd32 = nullptr, *jmd32 = nullptr;     // n: the same for the FP32 operator (K / len_scale, M / len_scale^3)
+    double *cg_rzq = nullptr, *cg_qzq = nullptr, *cgi_rzq = nullptr, *cgi_qzq = nullptr;   // r.D^-1 q, q.D^-1 q rings
+    // the GS operator in row form (GsRowsHost): the pattern, K and M (FP64),
+    // and per slot the combined coefficients of one (eps, mass) pair in FP64
+    // and (mixed contexts) FP32
+    int32_t *gs_off = nullptr;
+    uint16_t *gs_col = nullptr;
+    double *gs_kv = nullptr, *gs_mv = nullptr, *gs_kd = nullptr, *gs_md = nullptr;
+    double *gs_a64[2] = {nullptr, nullptr}, *gs_d64[2] = {nullptr, nullptr};
+    float *gs_a32[2] = {nullptr, nullptr}, *gs_d32[2] = {nullptr, nullptr};
+};
+
+// Which (eps, mass) pair a coefficient slot of the GS rows holds.
+struct GsSlot {
+    bool valid = false;
+    double eps = 0.0, mass = 0.0;
+    int64_t used = 0;             // tick of the last use (the least recent slot is rebuilt)
 };
 
 // Device state of the learned warm start (allocated on first use).
@@ -150,6 +164,10 @@ struct gspm_ctx {
 
     double *na_scratch = nullptr;         // this device's scratch of gspm_averages_noalloc (not owned)
 
+    int64_t gs_nent = 0;                  // entries of the GS rows (padding included)
+    gspm::GsSlot gs_slot[2];
+    int64_t gs_tick = 0;
+
     gspm::GreenState pc;                  // elastic preconditioner
 
     ~gspm_ctx();
@@ -175,6 +193,10 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st);
 // The elastic preconditioner: (re)build what the current mesh and parameters
 // need (green.cpp); y = B x on FP64 device vectors [3][n] (FP64 contexts).
 int green_setup(gspm_ctx *c);
+// The GS operator eps K + mass M in row form, its coefficients in FP32
+// (mixed contexts only) or FP64; builds the slot on the context's stream when
+// the pair is not cached.
+GsRowsView gs_rows(gspm_ctx *c, double eps, double mass, bool fp32);
 int green_apply64(gspm_ctx *c, const double *x, double *y);
 // FFTs of the preconditioner on the context's stream: grid -> spec (forward)
 // or spec -> grid (inverse), the three components as one batch.

@@ -171,14 +171,25 @@ __device__ __forceinline__ void block_atomic_add1(double v, double *dst) {
 // threads of the workgroup call it.
 template <int NR>
 __device__ __forceinline__ void shard_totals(const double *const (&src)[NR], double (&out)[NR]) {
+    static_assert(kShards <= 32, "one shard per lane of the low half-wave");
     __shared__ double tot[NR];
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
+        // every load in flight before the first reduction: the sums sit on the
+        // critical path of each launch that needs them
+        double v[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) v[k] = 0.0;
+        if (lane < kShards) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k)
+                if (src[k] != nullptr) v[k] = src[k][lane];
+        }
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
-            double s = (lane < kShards && src[k] != nullptr) ? src[k][lane] : 0.0;
+            double s = v[k];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+            for (int off = 16; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
             if (lane == 0) tot[k] = s;
         }
     }
@@ -193,6 +204,55 @@ __device__ __forceinline__ double shard_total(const double *src) {
     double o[1];
     shard_totals<1>(a, o);
     return o[0];
+}
+
+// Totals of the CG scalars an iteration's matvec needs: rr[k], rr[k-1], bb
+// per scalar set; decides convergence of rr[k] (recorded by workgroup 0) and
+// the direction coefficient beta_k = rr[k] / rr[k-1].
+template <int NS>
+__device__ __forceinline__ bool cg_direction_scalars(const CGScalars &cg, int k, double tol2, int (&live)[NS],
+                                                     double (&beta)[NS]) {
+    __shared__ int32_t flags[NS];
+    if (threadIdx.x == 0)
+        for (int s = 0; s < NS; ++s) flags[s] = cg.done[s];
+    __syncthreads();
+    for (int s = 0; s < NS; ++s) {
+        live[s] = flags[s] == 0;
+        beta[s] = 0.0;
+    }
+    __syncthreads();
+    if (k == 0) {
+        bool any = false;
+        for (int s = 0; s < NS; ++s) any |= live[s] != 0;
+        return any;
+    }
+    const double *src[3 * NS];
+    for (int s = 0; s < NS; ++s) {
+        src[s] = cg.rr_at(s, k);
+        src[NS + s] = cg.rr_at(s, k - 1);
+        src[2 * NS + s] = cg.bb_at(s);
+    }
+    double t[3 * NS];
+    shard_totals<3 * NS>(src, t);
+    bool any = false;
+    int stop[NS];
+    for (int s = 0; s < NS; ++s) {
+        stop[s] = 0;
+        if (!live[s]) continue;
+        const double rrk = t[s];
+        if (!isfinite(rrk)) stop[s] = 2;
+        else if (rrk <= tol2 * t[2 * NS + s]) stop[s] = 1;
+        else beta[s] = rrk / t[NS + s];
+        if (stop[s]) live[s] = 0;
+        any |= live[s] != 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int s = 0; s < NS; ++s)
+            if (stop[s]) {
+                cg.done[s] = stop[s];
+                cg.iters[s] = k;
+            }
+    return any;
 }
 
 }  // namespace gspm

@@ -464,62 +464,6 @@ __device__ __forceinline__ void vertex3(const Staged<T, NC, NF> &st, int k0, con
         for (int a = 0; a < 3; ++a) v[j][a] = st.fld(k0 + a, id[j]);
 }
 
-// Totals of the CG scalars an iteration's matvec needs: rr[k], rr[k-1], bb
-// per scalar set; decides convergence of rr[k] (recorded by workgroup 0) and
-// the direction coefficient beta_k = rr[k] / rr[k-1].
-template <int NS>
-__device__ __forceinline__ bool cg_direction_scalars(const CGScalars &cg, int k, double tol2, int (&live)[NS],
-                                                     double (&beta)[NS], bool jacobi = false) {
-    __shared__ int32_t flags[NS];
-    if (threadIdx.x == 0)
-        for (int s = 0; s < NS; ++s) flags[s] = cg.done[s];
-    __syncthreads();
-    for (int s = 0; s < NS; ++s) {
-        live[s] = flags[s] == 0;
-        beta[s] = 0.0;
-    }
-    __syncthreads();
-    if (k == 0) {
-        bool any = false;
-        for (int s = 0; s < NS; ++s) any |= live[s] != 0;
-        return any;
-    }
-    // with Jacobi preconditioning beta comes from r . D^-1 r (the test stays on |r|)
-    const double *src[3 * NS];
-    for (int s = 0; s < NS; ++s) {
-        src[s] = cg.rr_at(s, k);
-        src[NS + s] = jacobi ? cg.rz_at(s, k - 1) : cg.rr_at(s, k - 1);
-        src[2 * NS + s] = cg.bb_at(s);
-    }
-    double t[3 * NS];
-    shard_totals<3 * NS>(src, t);
-    double rzk[NS];
-    if (jacobi) {
-        const double *src2[NS];
-        for (int s = 0; s < NS; ++s) src2[s] = cg.rz_at(s, k);
-        shard_totals<NS>(src2, rzk);
-    }
-    bool any = false;
-    int stop[NS];
-    for (int s = 0; s < NS; ++s) {
-        stop[s] = 0;
-        if (!live[s]) continue;
-        const double rrk = t[s];
-        if (!isfinite(rrk)) stop[s] = 2;
-        else if (rrk <= tol2 * t[2 * NS + s]) stop[s] = 1;
-        else beta[s] = (jacobi ? rzk[s] : rrk) / t[NS + s];
-        if (stop[s]) live[s] = 0;
-        any |= live[s] != 0;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        for (int s = 0; s < NS; ++s)
-            if (stop[s]) {
-                cg.done[s] = stop[s];
-                cg.iters[s] = k;
-            }
-    return any;
-}
-
 // ------------------------------------------------------------- elasticity
 
 // K^mech of one element (Eq. LHS) applied to its vertex values (strip form), on
@@ -950,16 +894,15 @@ struct ElasticRhsOp {
     }
 };
 
-// ------------------------------------------------------------ GS operator
+// ----------------------------------------------------- magnetostatic operator
 
-// (eps K + mass M) on NC scalar components stored [c][n], magnetic elements
-// only (Eq. weak_GS), with one CG scalar set per component; a converged
-// component is skipped.
-template <class T, int NC, bool kMs = false>
-struct GsMatvecOp {
-    // kMs: K^ms of Eq. (weak_demag) instead, the Laplacian over all elements
-    // (eps = 1, no mass) with the pinned node's rows zero
-    static constexpr bool kMagneticOnly = !kMs;
+// K^ms of Eq. (weak_demag): the Laplacian over all elements with the pinned
+// node's rows zero, on NC scalar components stored [c][n], one CG scalar set
+// per component; a converged component is skipped.  (The GS operator eps K +
+// M runs in row form, row_kernels.hip.)
+template <class T, int NC>
+struct MsMatvecOp {
+    static constexpr bool kMagneticOnly = false;
     const T *in;
     T *out;
     const T *b;
@@ -968,19 +911,13 @@ struct GsMatvecOp {
     CGScalars cg;
     int k, mode, n;
     double tol2;
-    T eps, mass;
+    T eps;                        // 1 (FP64) or 1 / len_scale^2 (FP32 on scaled coordinates)
     int live[NC];
     double beta[NC];
     double coord_scale;
-    const T *jkd = nullptr, *jmd = nullptr;   // Jacobi: D = eps jkd + mass jmd (null: plain CG)
-
-    __device__ __forceinline__ T jacobi_z(const T rv, int g) const {
-        const T d = eps * jkd[g] + mass * jmd[g];
-        return d > T(0) ? rv / d : T(0);
-    }
 
     __device__ bool prepare(const MeshView &, int) {
-        if (mode == MV_ITER) return cg_direction_scalars<NC>(cg, k, tol2, live, beta, jkd != nullptr);
+        if (mode == MV_ITER) return cg_direction_scalars<NC>(cg, k, tol2, live, beta);
         bool any = false;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -996,21 +933,16 @@ struct GsMatvecOp {
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const size_t o = static_cast<size_t>(q) * n + g;
-            if (!live[q]) {
-                v[q] = T(0);
-            } else if (mode == MV_ITER) {
-                const T z = jkd ? jacobi_z(r[o], g) : r[o];
-                v[q] = (k == 0) ? z : z + static_cast<T>(beta[q]) * in[o];
-            } else {
-                v[q] = in[o];
-            }
+            if (!live[q]) v[q] = T(0);
+            else if (mode == MV_ITER) v[q] = (k == 0) ? r[o] : r[o] + static_cast<T>(beta[q]) * in[o];
+            else v[q] = in[o];
         }
     }
 
     // the element with its vertex values given (strip form), on the unscaled
-    // geometry: eps V g_i . g_j = (eps w) c_i . c_j and V / 20 = |det| / 120
+    // geometry: eps V g_i . g_j = (eps w) c_i . c_j
     __device__ __forceinline__ void element_raw(const T (&f)[4][NC], const RawGeo<T> &R, T (&y)[4][NC]) const {
-        const T ev = eps * R.w, mv20 = mass * R.adet * T(1.0 / 120.0);
+        const T ev = eps * R.w;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             if (!live[q]) {
@@ -1029,31 +961,23 @@ struct GsMatvecOp {
 #pragma unroll
             for (int j = 1; j < 4; ++j) t[j] = R.c[j][0] * gp[0] + R.c[j][1] * gp[1] + R.c[j][2] * gp[2];
             t[0] = -(t[1] + t[2] + t[3]);
-            if constexpr (kMs) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) y[j][q] = ev * t[j];
-            } else {
-                const T sum = v[0] + v[1] + v[2] + v[3];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) y[j][q] = ev * t[j] + mv20 * (v[j] + sum);
-            }
+            for (int j = 0; j < 4; ++j) y[j][q] = ev * t[j];
         }
     }
 
     template <int NF>
     __device__ void finish(const MeshView &mv, const Staged<T, NC, NF> &st, int n0, int cnt) const {
-        double part[NC], part2[NC];
+        double part[NC];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) part[q] = part2[q] = 0.0;
-        // Jacobi at k = 0: p_0 = D^-1 r_0, so r_0 . D^-1 r_0 = r_0 . p_0
-        const bool rz0 = jkd != nullptr && mode == MV_ITER && k == 0;
+        for (int q = 0; q < NC; ++q) part[q] = 0.0;
         for (int i = threadIdx.x; i < cnt; i += kThreads) {
             const int node = n0 + i;
 #pragma unroll
             for (int q = 0; q < NC; ++q) {
                 if (!live[q]) continue;
                 const size_t o = static_cast<size_t>(q) * n + node;
-                const T av = (kMs && node == mv.p0) ? T(0) : static_cast<T>(st.acc[q * mv.nb + i]);
+                const T av = node == mv.p0 ? T(0) : static_cast<T>(st.acc[q * mv.nb + i]);
                 if (mode == MV_RESID) {
                     const T rv = b[o] - av;
                     const_cast<T *>(r)[o] = rv;
@@ -1063,18 +987,13 @@ struct GsMatvecOp {
                     pout[o] = pv;
                     out[o] = av;
                     part[q] += static_cast<double>(pv) * av;
-                    if (rz0) part2[q] += static_cast<double>(r[o]) * pv;
                 } else {
                     out[o] = av;
                 }
             }
         }
-        if (mode == MV_ITER) {
-            block_atomic_add<NC>(part, cg.pq_at(0, k), cg.comp_stride());
-            if (rz0) block_atomic_add<NC>(part2, cg.rz_at(0, 0), cg.comp_stride());
-        } else if (mode == MV_RESID) {
-            block_atomic_add<NC>(part, cg.rr_at(0, 0), cg.comp_stride());
-        }
+        if (mode == MV_ITER) block_atomic_add<NC>(part, cg.pq_at(0, k), cg.comp_stride());
+        else if (mode == MV_RESID) block_atomic_add<NC>(part, cg.rr_at(0, 0), cg.comp_stride());
     }
 };
 
@@ -1560,31 +1479,6 @@ void launch_elastic_rhs(const MeshView &mv, const Material &mat, const double *m
     run_elem<double, 3, 3>(mv, op, s);
 }
 
-// FP32: the non-dimensional operator A' = A / len_scale^3, i.e. eps' = eps / len_scale^2
-// on coordinates divided by len_scale.
-template <class T>
-void launch_gs_matvec(const MeshView &mv, int nc, double eps, double mass, MatvecMode mode, const T *in, T *out,
-                      const T *b, const T *r, T *pout, const CGScalars &cg, int k, double tol, hipStream_t s,
-                      const T *jkd, const T *jmd, const hipEvent_t *ev) {
-    const bool nd = sizeof(T) == sizeof(float);
-    const double sc = nd ? 1.0 / mv.len_scale : 1.0;
-    const int md = static_cast<int>(mode);
-    const double t2 = tol * tol;
-    const T e = static_cast<T>(eps * sc * sc), ms = static_cast<T>(mass);
-    switch (nc) {
-        case 1: run_strip<T, 1, 1>(mv, GsMatvecOp<T, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc, jkd, jmd}, s, ev); break;
-        case 2: run_strip<T, 2, 2>(mv, GsMatvecOp<T, 2>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0}, {0.0, 0.0}, sc, jkd, jmd}, s, ev); break;
-        default: run_strip<T, 3, 3>(mv, GsMatvecOp<T, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0}, {0.0, 0.0, 0.0}, sc, jkd, jmd}, s, ev); break;
-    }
-}
-
-template void launch_gs_matvec<double>(const MeshView &, int, double, double, MatvecMode, const double *, double *,
-                                       const double *, const double *, double *, const CGScalars &, int, double,
-                                       hipStream_t, const double *, const double *, const hipEvent_t *);
-template void launch_gs_matvec<float>(const MeshView &, int, double, double, MatvecMode, const float *, float *,
-                                      const float *, const float *, float *, const CGScalars &, int, double,
-                                      hipStream_t, const float *, const float *, const hipEvent_t *);
-
 // K^ms on the same strips (all segments), eps = 1 and no mass; FP32 uses the
 // GS operator's scaling, A' = K^ms / len_scale^3.
 template <class T>
@@ -1594,12 +1488,12 @@ void launch_ms_matvec(const MeshView &mv, int nc, MatvecMode mode, const T *in, 
     const double sc = nd ? 1.0 / mv.len_scale : 1.0;
     const int md = static_cast<int>(mode);
     const double t2 = tol * tol;
-    const T e = static_cast<T>(sc * sc), ms = T(0);
+    const T e = static_cast<T>(sc * sc);
     if (nc == 1)
-        run_strip<T, 1, 1>(mv, GsMatvecOp<T, 1, true>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0}, {0.0}, sc}, s);
+        run_strip<T, 1, 1>(mv, MsMatvecOp<T, 1>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, {0}, {0.0}, sc}, s);
     else
-        run_strip<T, 3, 3>(mv, GsMatvecOp<T, 3, true>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, ms, {0, 0, 0},
-                                                       {0.0, 0.0, 0.0}, sc}, s);
+        run_strip<T, 3, 3>(mv, MsMatvecOp<T, 3>{in, out, b, r, pout, cg, k, md, mv.n, t2, e, {0, 0, 0}, {0.0, 0.0, 0.0},
+                                                sc}, s);
 }
 
 template <class T>

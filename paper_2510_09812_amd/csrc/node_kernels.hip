@@ -433,52 +433,6 @@ void launch_cg_update(int n, int nc, bool joint, T *x, T *r, const T *p, const T
                        cg, k);
 }
 
-template <class T>
-__global__ void __launch_bounds__(kThreads) k_cg_update_jacobi(int n, int nc, T *x, T *r, const T *p, const T *q,
-                                                               const T *jkd, const T *jmd, T eps, CGScalars cg,
-                                                               int k) {
-    bool live[3];
-    if (!read_live(cg.done, nc, live)) return;
-    const double *const src[6] = {cg.rz_at(0, k), nc > 1 ? cg.rz_at(1, k) : nullptr, nc > 2 ? cg.rz_at(2, k) : nullptr,
-                                  cg.pq_at(0, k), nc > 1 ? cg.pq_at(1, k) : nullptr, nc > 2 ? cg.pq_at(2, k) : nullptr};
-    double t[6];
-    shard_totals<6>(src, t);
-    T alpha[3];
-    for (int c = 0; c < 3; ++c) alpha[c] = live[c] ? static_cast<T>(t[c] / t[3 + c]) : T(0);
-    double prr[3] = {0.0, 0.0, 0.0}, prz[3] = {0.0, 0.0, 0.0};
-    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
-        const T d = eps * jkd[i] + jmd[i];
-        const T dinv = d > T(0) ? T(1) / d : T(0);
-        for (int c = 0; c < nc; ++c) {
-            if (!live[c]) continue;
-            const size_t o = static_cast<size_t>(c) * n + i;
-            x[o] += alpha[c] * p[o];
-            const T rv = r[o] - alpha[c] * q[o];
-            r[o] = rv;
-            prr[c] += static_cast<double>(rv) * rv;
-            prz[c] += static_cast<double>(rv) * (rv * dinv);
-        }
-    }
-    double *const dst[6] = {cg.rr_at(0, k + 1), nc > 1 ? cg.rr_at(1, k + 1) : nullptr,
-                            nc > 2 ? cg.rr_at(2, k + 1) : nullptr, cg.rz_at(0, k + 1),
-                            nc > 1 ? cg.rz_at(1, k + 1) : nullptr, nc > 2 ? cg.rz_at(2, k + 1) : nullptr};
-    const double both[6] = {prr[0], prr[1], prr[2], prz[0], prz[1], prz[2]};
-    block_atomic_add_to<6>(both, dst);
-}
-
-template <class T>
-void launch_cg_update_jacobi(int n, int nc, T *x, T *r, const T *p, const T *q, const T *jkd, const T *jmd,
-                             double eps, const CGScalars &cg, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update_jacobi<T>, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, x, r, p, q, jkd, jmd,
-                       static_cast<T>(eps), cg, k);
-}
-
-template void launch_cg_update_jacobi<double>(int, int, double *, double *, const double *, const double *,
-                                              const double *, const double *, double, const CGScalars &, int,
-                                              hipStream_t);
-template void launch_cg_update_jacobi<float>(int, int, float *, float *, const float *, const float *, const float *,
-                                             const float *, double, const CGScalars &, int, hipStream_t);
-
 template void launch_cg_start<double>(int, int, bool, double *, const CGScalars &, double, hipStream_t);
 template void launch_cg_start<float>(int, int, bool, float *, const CGScalars &, double, hipStream_t);
 template void launch_cg_update<double>(int, int, bool, double *, double *, const double *, const double *,
@@ -611,6 +565,11 @@ __global__ void __launch_bounds__(kThreads) k_zero_ring(CGScalars cg, int ns, in
         base[sh] = 0.0;
         // r . D^-1 r of the Jacobi-preconditioned solves shares the r.r slots
         if (slot < nrr && cg.rz) cg.rz_at(c, rr_from + slot)[sh] = 0.0;
+        // the single-reduction GS sums share the p.q slots of their component
+        if (slot >= nrr && cg.rzq) {
+            cg.rzq_at(c, pq_from + slot - nrr)[sh] = 0.0;
+            cg.qzq_at(c, pq_from + slot - nrr)[sh] = 0.0;
+        }
         // the single-reduction sums of one scalar set share the p.q slots
         if (slot >= nrr && c == 0 && cg.rq) {
             cg.rq_at(pq_from + slot - nrr)[sh] = 0.0;

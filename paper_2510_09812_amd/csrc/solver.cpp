@@ -1,15 +1,15 @@
 // CG driver and the GSPM step sequence (host side; all arithmetic runs in
 // the kernels).
 //
-// CG runs without a host round trip per iteration.  The elastic solve and the
-// step's magnetostatic solve run single-reduction CG: one fused launch per
-// iteration, which completes the previous iteration (its scalars summed in the
-// prologue), forms r, p and x in the staging and writes p and q = A p with the
-// next iteration's dot products in the epilogue.  The GS solves (and
-// multi-component magnetostatic solves) take two launches per iteration: the
-// matvec, whose staging forms the new direction p_k = r_k + beta_k p_{k-1}
-// after testing ||r_k|| on the device, with p.Ap fused into its epilogue; and
-// the x/r update with r.r fused.  Vectors that other workgroups read as halo
+// CG runs without a host round trip per iteration.  The elastic solve, the GS
+// solves and the step's magnetostatic solve run single-reduction CG: one
+// fused launch per iteration, which completes the previous iteration (its
+// scalars summed in the prologue), forms r, p and x in the staging and writes
+// p and q = A p with the next iteration's dot products in the epilogue.
+// Multi-component magnetostatic solves (and the preconditioned elastic solve)
+// take separate launches: the matvec, whose staging forms the new direction
+// p_k = z_k + beta_k p_{k-1} after testing ||r_k|| on the device, with p.Ap
+// fused into its epilogue; and the x/r update with r.r fused.  Vectors that other workgroups read as halo
 // while a launch writes their successors are double-buffered.  Convergence is
 // decided on the device and a converged solve turns the remaining launches
 // into immediate exits.  The host enqueues iterations in batches and reads the
@@ -368,48 +368,70 @@ CgResult cg_gs(gspm_ctx *c, int nc, double eps, double *x, const double *b, doub
     return r;
 }
 
+GsRowsView gs_rows(gspm_ctx *c, double eps, double mass, bool fp32) {
+    auto &d = c->d;
+    int k = -1;
+    for (int j = 0; j < 2; ++j)
+        if (c->gs_slot[j].valid && c->gs_slot[j].eps == eps && c->gs_slot[j].mass == mass) k = j;
+    if (k < 0) {
+        k = !c->gs_slot[0].valid ? 0 : !c->gs_slot[1].valid ? 1 : (c->gs_slot[0].used <= c->gs_slot[1].used ? 0 : 1);
+        const int n = c->n;
+        launch_gs_combine<double>(c->gs_nent, d.gs_kv, d.gs_mv, eps, mass, 1.0, d.gs_a64[k], c->stream);
+        launch_gs_combine<double>(n, d.gs_kd, d.gs_md, eps, mass, 1.0, d.gs_d64[k], c->stream);
+        if (c->precision == GSPM_MIXED) {
+            // the FP32 operators' scaling: A' = A / len_scale^3
+            const double ls = c->mv.len_scale, sc = 1.0 / (ls * ls * ls);
+            launch_gs_combine<float>(c->gs_nent, d.gs_kv, d.gs_mv, eps, mass, sc, d.gs_a32[k], c->stream);
+            launch_gs_combine<float>(n, d.gs_kd, d.gs_md, eps, mass, sc, d.gs_d32[k], c->stream);
+        }
+        c->gs_slot[k].valid = true;
+        c->gs_slot[k].eps = eps;
+        c->gs_slot[k].mass = mass;
+    }
+    c->gs_slot[k].used = ++c->gs_tick;
+    GsRowsView v{d.gs_off, d.gs_col, nullptr, nullptr};
+    if (fp32) {
+        v.a = d.gs_a32[k];
+        v.d = d.gs_d32[k];
+    } else {
+        v.a = d.gs_a64[k];
+        v.d = d.gs_d64[k];
+    }
+    return v;
+}
+
+// The GS solves run single-reduction CG in row form (launch_gs_rows_cg): one
+// launch per iteration, r, p and q alternating between two buffers.
 CgResult cg_gs_run(gspm_ctx *c, int nc, double eps, double *x, const double *b, double tol, int maxit,
                    SolveKind kind) {
     hipStream_t s = c->stream;
     const bool jac = c->p.gs_precond == GSPM_PRECOND_JACOBI;
+    const GsRowsView r64 = gs_rows(c, eps, 1.0, false);
     auto resid = [&]() {
-        launch_gs_matvec<double>(c->mv, nc, eps, 1.0, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
+        launch_gs_rows<double>(c->mv, r64, nc, MV_RESID, x, nullptr, b, c->d.r, c->cg, s);
     };
+    // iteration k reads the buffers of iteration k-1 and writes those of k
+    auto fused = [&](const GsRowsView &rv, auto *R0, auto *R1, auto *P0, auto *P1, auto *Q0, auto *Q1, auto *xv,
+                     const CGScalars &cg, double t) {
+        return [=](int k, bool last) {
+            auto *R = k & 1 ? R1 : R0, *P = k & 1 ? P1 : P0, *Q = k & 1 ? Q1 : Q0;
+            auto *Rp = k & 1 ? R0 : R1, *Pp = k & 1 ? P0 : P1, *Qp = k & 1 ? Q0 : Q1;
+            if (k == 0) Rp = R0;
+            const hipEvent_t *ev = last ? nullptr : prof_begin(c, k);
+            launch_gs_rows_cg(c->mv, rv, nc, k, last, Rp, Pp, Qp, R, P, Q, xv, cg, t, jac, s, ev);
+            if (!last) prof_end(c);
+        };
+    };
+    auto &d = c->d;
     if (c->precision == GSPM_MIXED) {
-        float *P[2] = {c->d.p32, c->d.p32b};
         const double ls = c->mv.len_scale, scale = 1.0 / (ls * ls * ls);
-        const float *kd = jac ? c->d.jkd32 : nullptr, *md = jac ? c->d.jmd32 : nullptr;
-        return cg_mixed(c, nc, false, x, tol, maxit, kind, scale, resid, [&](int k, bool last) {
-            if (last) {
-                launch_cg_check(nc, false, c->cg_in, k, 1.0, s);
-                return;
-            }
-            launch_gs_matvec<float>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q32, nullptr, c->d.r32, P[(k + 1) & 1],
-                                    c->cg_in, k, 1.0, s, kd, md, prof_begin(c, k));
-            prof_end(c);
-            if (jac)
-                launch_cg_update_jacobi<float>(c->n, nc, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, kd, md,
-                                               eps / (ls * ls), c->cg_in, k, s);
-            else
-                launch_cg_update<float>(c->n, nc, false, c->d.x32, c->d.r32, P[(k + 1) & 1], c->d.q32, c->cg_in, k, s);
-        });
+        const GsRowsView r32 = gs_rows(c, eps, 1.0, true);
+        return cg_mixed(c, nc, false, x, tol, maxit, kind, scale, resid,
+                        fused(r32, d.r32, d.r32b, d.p32, d.p32b, d.q32, d.q32b, d.x32, c->cg_in, 1.0));
     }
-    double *P[2] = {c->d.p, c->d.p2};
-    const double *kd = jac ? c->d.jkd : nullptr, *md = jac ? c->d.jmd : nullptr;
     const size_t first_pair = prof_mark(c);
-    CgResult res = cg_fp64(c, nc, false, x, tol, maxit, kind, resid, [&](int k, bool last) {
-        if (last) {
-            launch_cg_check(nc, false, c->cg, k, tol, s);
-            return;
-        }
-        launch_gs_matvec<double>(c->mv, nc, eps, 1.0, MV_ITER, P[k & 1], c->d.q, nullptr, c->d.r, P[(k + 1) & 1], c->cg,
-                                 k, tol, s, kd, md, prof_begin(c, k));
-        prof_end(c);
-        if (jac)
-            launch_cg_update_jacobi<double>(c->n, nc, x, c->d.r, P[(k + 1) & 1], c->d.q, kd, md, eps, c->cg, k, s);
-        else
-            launch_cg_update<double>(c->n, nc, false, x, c->d.r, P[(k + 1) & 1], c->d.q, c->cg, k, s);
-    });
+    CgResult res = cg_fp64(c, nc, false, x, tol, maxit, kind, resid,
+                           fused(r64, d.r, d.r2, d.p, d.p2, d.q, d.q2, x, c->cg, tol));
     prof_drop_after(c, first_pair, std::max(res.iters[0], std::max(res.iters[1], res.iters[2])));
     return res;
 }
