@@ -84,13 +84,12 @@ def refinement_bytes(n_nodes: int, n_tets: int, components: int) -> int:
     return 16 * n_tets + 24 * n_nodes + c * n_nodes * (3 * 8 + (8 + 4) + (8 + 8 + 4))
 
 
-def gs3_matvec_bytes(n_nodes: int, n_mag_tets: int, real_bytes: int = 4, jacobi: bool = True) -> int:
-    """Algorithmic bytes of one launch of the GS matvec on three components
-    (CG iteration form, magnetic elements): connectivity of the magnetic
-    tetrahedra, FP64 coordinates, and per component r and the old direction
-    read, the new direction and q = A p written; with Jacobi preconditioning
-    the two diagonals of K and M."""
-    return 16 * n_mag_tets + 24 * n_nodes + 3 * 4 * real_bytes * n_nodes + (2 * real_bytes * n_nodes if jacobi else 0)
+def gs3_iteration_bytes(n_nodes: int, n_mag_tets: int, real_bytes: int = 4, jacobi: bool = True) -> int:
+    """Algorithmic bytes of one GS CG iteration on three components (one
+    fused launch), the method's count: connectivity of the magnetic
+    tetrahedra, FP64 coordinates, nine vector passes per component (as
+    gs_iteration_bytes) and, with Jacobi preconditioning, the diagonal once."""
+    return 16 * n_mag_tets + 24 * n_nodes + 3 * 9 * real_bytes * n_nodes + (real_bytes * n_nodes if jacobi else 0)
 
 
 def pcg_matvec_bytes(n_nodes: int, n_tets: int, real_bytes: int = 4) -> int:
@@ -140,10 +139,10 @@ def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float, re
     gs = gs_iteration_bytes(n_nodes, n_tets, real_bytes)
     if precond:
         # preconditioned elastic iteration: its matvec, the x/r update (x, r, p, q: five passes), the
-        # preconditioner; Jacobi GS: the two diagonals once more per component iteration
+        # preconditioner; Jacobi GS: the diagonal once more per component iteration
         mech = (pcg_matvec_bytes(n_nodes, n_tets, real_bytes) + 5 * 3 * real_bytes * n_nodes
                 + precond_bytes(n_nodes, grid, real_bytes))
-        gs += 2 * real_bytes * n_nodes
+        gs += real_bytes * n_nodes
     rhs = 3 * (16 * n_tets + 24 * n_nodes * 4)
     nodes = 200 * n_nodes
     ref = mech_refinements * refinement_bytes(n_nodes, n_tets, 3) + other_refinements * refinement_bytes(
@@ -370,15 +369,15 @@ def main() -> int:
     tname = "float" if mixed else "double"
 
     # the roofline of the path's dominant kernel, by summed duration over the profile steps: the
-    # elastic iteration launch, or (preconditioned paths) the GS matvec on three components
+    # elastic iteration launch, or the GS CG iteration launch on three components
     roofline = None
     pst = head.get("prof")
     if pst and (pst["matvec_launches"] > 0 or pst["gs_matvec_launches"] > 0):
         if pst["gs_matvec_ms"] > pst["matvec_ms"]:
             launches, tot_ms = pst["gs_matvec_launches"], pst["gs_matvec_ms"]
-            mb = gs3_matvec_bytes(n, ne_mag, rb, jacobi=precond)
-            kname = f"k_strip<{tname},3,3,GsMatvecOp<{tname},3>>" + (" (Jacobi)" if precond else "")
-            what = "GS matvec launch on three components"
+            mb = gs3_iteration_bytes(n, ne_mag, rb, jacobi=precond)
+            kname = f"k_gs_rows_cg<{tname},3>" + (" (Jacobi)" if precond else "")
+            what = "GS CG iteration launch on three components"
             traffic = None
         else:
             launches, tot_ms = pst["matvec_launches"], pst["matvec_ms"]
@@ -396,7 +395,7 @@ def main() -> int:
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname, "bytes_per_launch": mb,
                     "avg_launch_us": avg_s * 1e6, "launches": launches,
-                    "share_of_timed_kernels": {"elastic_ms": pst["matvec_ms"], "gs3_matvec_ms": pst["gs_matvec_ms"]},
+                    "share_of_timed_kernels": {"elastic_ms": pst["matvec_ms"], "gs3_iteration_ms": pst["gs_matvec_ms"]},
                     "timing": f"kernel start/end events (hipExtLaunchKernelGGL) on every working {what} of "
                               f"{args.profile_steps} untimed steps after the timed region"}
     mech_per_step = st["mech_iters"] / args.steps
@@ -417,7 +416,7 @@ def main() -> int:
         if "prof" in p and p["prof"]["matvec_launches"] > 0:
             row["elastic_cg_launch_us"] = p["prof"]["matvec_ms"] / p["prof"]["matvec_launches"] * 1e3
         if "prof" in p and p["prof"]["gs_matvec_launches"] > 0:
-            row["gs3_matvec_launch_us"] = p["prof"]["gs_matvec_ms"] / p["prof"]["gs_matvec_launches"] * 1e3
+            row["gs3_iteration_launch_us"] = p["prof"]["gs_matvec_ms"] / p["prof"]["gs_matvec_launches"] * 1e3
         ref = "fp64+local_demag" if ld else ("fp64+rotated111" if k.endswith("+rotated111") else "fp64")
         if k.endswith("+precond"):
             row["ref_note"] = "errors against the unpreconditioned FP64 path"
@@ -435,7 +434,7 @@ def main() -> int:
         mb = ms_matvec_bytes(n, ne, 4)
         ms_roofline = {"bound": "hbm", "achieved": mb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": mb / t / 1e9 / HBM_PEAK_GBS, "traffic": traffic_from_profile("ms_mixed", case.name),
-                       "kernel": "k_strip<float,1,1,GsMatvecOp<float,1,true>>", "bytes_per_launch": mb,
+                       "kernel": "k_strip<float,1,1,MsMatvecOp<float,1>>", "bytes_per_launch": mb,
                        "avg_launch_us": t * 1e6,
                        "timing": "50 device-resident launches of y = K^ms x between HIP events on the library's stream"}
     out = {

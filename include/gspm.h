@@ -186,8 +186,9 @@ typedef struct {
                                previous displacement increment (0 if unused) */
     int64_t ms_iters;       /* local_demag: magnetostatic CG iterations (GSPM_MIXED: inner FP32), summed */
     int64_t mech_refinements; /* GSPM_MIXED: the refinements of the elastic solves (part of `refinements`) */
-    double gs_matvec_ms;    /* profile mode: summed kernel duration of the working GS matvec launches on three
-                               components (stages 1 and 3; those after convergence excluded) */
+    double gs_matvec_ms;    /* profile mode: summed kernel duration of the working GS CG iteration launches on
+                               three components (one fused launch per iteration: the matvec with the CG vector
+                               updates; stages 1 and 3; those after convergence excluded) */
     int64_t gs_matvec_launches; /* profile mode: their number */
 } gspm_step_stats;
 

@@ -84,7 +84,8 @@ def test_preconditioned_step_bytes_and_grid():
     n, ne = 1000, 6000
     plain = bench.step_bytes(n, ne, 100, 40, 4)
     pc = bench.step_bytes(n, ne, 100, 40, 4, precond=True, grid=(10, 10, 10))
-    # each preconditioned iteration adds the preconditioner and the Jacobi diagonals to the GS ones
+    # each preconditioned iteration adds the preconditioner, and the Jacobi diagonal to the GS ones
     per_it = bench.pcg_matvec_bytes(n, ne, 4) + 60 * n + bench.precond_bytes(n, (10, 10, 10), 4)
-    assert pc - plain == 100 * (per_it - bench.cg_iteration_bytes(n, ne, 4)) + 40 * 8 * n
-    assert bench.gs3_matvec_bytes(n, ne, 4, jacobi=False) == 16 * ne + 24 * n + 48 * n
+    assert pc - plain == 100 * (per_it - bench.cg_iteration_bytes(n, ne, 4)) + 40 * 4 * n
+    assert bench.gs3_iteration_bytes(n, ne, 4, jacobi=False) == 16 * ne + 24 * n + 108 * n
+    assert bench.gs3_iteration_bytes(n, ne, 4) == 16 * ne + 24 * n + 112 * n
