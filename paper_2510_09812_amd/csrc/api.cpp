@@ -326,8 +326,11 @@ gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts) {
         }
         c->own_stream = true;
     }
-    bool ok = hipHostMalloc(reinterpret_cast<void **>(&c->h_flags), sizeof(int32_t) * 4 * kMaxComp) == hipSuccess;
-    ok = ok && hipHostMalloc(reinterpret_cast<void **>(&c->h_mixed), sizeof(double) * 16 * kShards) == hipSuccess;
+    // coherent: kernels write the convergence flags and residual totals here directly
+    bool ok = hipHostMalloc(reinterpret_cast<void **>(&c->h_flags), sizeof(int32_t) * 4 * kMaxComp,
+                            hipHostMallocCoherent) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void **>(&c->h_mixed), sizeof(double) * 16 * kShards,
+                             hipHostMallocCoherent) == hipSuccess;
     for (auto &e : c->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreate(&c->t0) == hipSuccess && hipEventCreate(&c->t1) == hipSuccess;
     if (!ok) {

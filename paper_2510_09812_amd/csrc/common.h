@@ -350,6 +350,21 @@ template <class T>
 void launch_cg_update(int n, int nc, bool joint, T *x, T *r, const T *p, const T *q, const CGScalars &cg, int k,
                       hipStream_t s);
 void launch_cg_check(int nc, bool joint, const CGScalars &cg, int k, double tol, hipStream_t s);
+// Small values for the host: count (<= 64) int32 copied into pinned host
+// memory; the totals of up to six sharded sums into pinned host memory.
+struct ShardSources {
+    static constexpr int kMax = 6;
+    const double *p[kMax];
+};
+void launch_i32_to_host(const int32_t *src, int count, int32_t *host_dst, hipStream_t s);
+void launch_totals_to_host(const ShardSources &src, int count, double *host_dst, hipStream_t s);
+// The start of an inner FP32 solve: bb[q] (shard 0; the other shards zero)
+// and done[q] per component, iters zero.
+struct InnerStart {
+    double bb[kMaxComp];
+    int32_t done[kMaxComp];
+};
+void launch_set_inner(const CGScalars &cg, const InnerStart &st, hipStream_t s);
 
 // Precision conversions of the mixed form: dst = (float) src; x += (double) d.
 void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s);

@@ -11,9 +11,11 @@ namespace gspm {
 
 namespace {
 
+// one thread per item: these passes are bound by the latency of their
+// gathers, so every item's loads should be in flight at once
 inline int grid_of(int64_t n) {
     const int64_t g = (n + kThreads - 1) / kThreads;
-    return static_cast<int>(g < 2048 ? (g > 0 ? g : 1) : 2048);
+    return static_cast<int>(g < (1 << 30) ? (g > 0 ? g : 1) : (1 << 30));
 }
 
 // The test of |r_j|^2 <= tol2 |b|^2 (recorded by workgroup 0 as iteration
@@ -63,17 +65,34 @@ __global__ void __launch_bounds__(kThreads) k_pc_restrict(GreenView gv, int n, c
     if (!pc_live(cg, test_k, tol2)) return;
     const T *w = static_cast<const T *>(gv.rw);
     T *grid = static_cast<T *>(gv.grid);
+    constexpr int kB = 8;   // entries gathered per batch: their index loads, then their data loads
     for (int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; t < gv.G;
          t += static_cast<int64_t>(gridDim.x) * kThreads) {
         T s0 = T(0), s1 = T(0), s2 = T(0);
-        const int e1 = gv.rptr[t + 1];
+        const int e0 = gv.rptr[t], e1 = gv.rptr[t + 1];
         const int64_t g = gv.rgrid[t];
-        for (int e = gv.rptr[t]; e < e1; ++e) {
-            const int j = gv.rnode[e];
-            const T wj = w[e];
-            s0 += wj * r[j];
-            s1 += wj * r[static_cast<size_t>(n) + j];
-            s2 += wj * r[2 * static_cast<size_t>(n) + j];
+        for (int eb = e0; eb < e1; eb += kB) {
+            int j[kB];
+            T wj[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const bool in = eb + u < e1;
+                j[u] = in ? gv.rnode[eb + u] : 0;
+                wj[u] = in ? w[eb + u] : T(0);
+            }
+            T v0[kB], v1[kB], v2[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                v0[u] = r[j[u]];
+                v1[u] = r[static_cast<size_t>(n) + j[u]];
+                v2[u] = r[2 * static_cast<size_t>(n) + j[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                s0 += wj[u] * v0[u];
+                s1 += wj[u] * v1[u];
+                s2 += wj[u] * v2[u];
+            }
         }
         grid[g] = s0;
         grid[gv.G + g] = s1;

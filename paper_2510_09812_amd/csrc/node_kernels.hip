@@ -50,6 +50,53 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(node_grid(n)), dim3(kThreads), 0, s, p, n, v);
 }
 
+// ------------------------------------------------ host-visible small values
+
+// Small results the host polls are written straight into its pinned memory
+// (device-accessible), and small inputs arrive as kernel arguments: a copy
+// engine transfer of a few bytes costs more device time than these launches.
+__global__ void __launch_bounds__(64) k_i32_to_host(const int32_t *src, int count, int32_t *dst) {
+    if (static_cast<int>(threadIdx.x) < count) dst[threadIdx.x] = src[threadIdx.x];
+    __threadfence_system();
+}
+
+void launch_i32_to_host(const int32_t *src, int count, int32_t *host_dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_i32_to_host, dim3(1), dim3(64), 0, s, src, count, host_dst);
+}
+
+__global__ void __launch_bounds__(64) k_totals_to_host(ShardSources src, int count, double *dst) {
+    const int lane = threadIdx.x;
+    double v[ShardSources::kMax];
+#pragma unroll
+    for (int k = 0; k < ShardSources::kMax; ++k) v[k] = (k < count && lane < kShards) ? src.p[k][lane] : 0.0;
+#pragma unroll
+    for (int k = 0; k < ShardSources::kMax; ++k) {
+        double t = v[k];
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if (lane == 0 && k < count) dst[k] = t;
+    }
+    __threadfence_system();
+}
+
+void launch_totals_to_host(const ShardSources &src, int count, double *host_dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_totals_to_host, dim3(1), dim3(64), 0, s, src, count, host_dst);
+}
+
+__global__ void __launch_bounds__(kThreads) k_set_inner(CGScalars cg, InnerStart st) {
+    const int t = threadIdx.x;
+    if (t < kMaxComp * kShards) cg.bb[t] = (t % kShards == 0) ? st.bb[t / kShards] : 0.0;
+    if (t < kMaxComp) {
+        cg.done[t] = st.done[t];
+        cg.iters[t] = 0;
+    }
+}
+
+void launch_set_inner(const CGScalars &cg, const InnerStart &st, hipStream_t s) {
+    static_assert(kMaxComp * kShards <= kThreads, "one workgroup sets every shard");
+    hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(kThreads), 0, s, cg, st);
+}
+
 // ---------------------------------------------------------------- averages
 
 // Volume averages of Sec. 2.4 for P1 fields: int_Omega g = sum_j w_j g_j with

@@ -62,8 +62,7 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
         k = k1;
     };
     auto post = [&](int slot) {
-        hipMemcpyAsync(c->h_flags + 2 * kMaxComp * slot, cg.done, sizeof(int32_t) * 2 * kMaxComp,
-                       hipMemcpyDeviceToHost, s);
+        launch_i32_to_host(cg.done, 2 * kMaxComp, c->h_flags + 2 * kMaxComp * slot, s);
         hipEventRecord(c->ev[slot], s);
     };
     enqueue(first);
@@ -169,14 +168,16 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
     const size_t n3 = 3 * static_cast<size_t>(n);
     CgResult res;
     int total[kMaxComp] = {0, 0, 0};
-    double *hs = c->h_mixed;   // pinned: rr[3][kShards] | bb[3][kShards] staging
+    double *hs = c->h_mixed;   // pinned: the totals rr[ns] | bb[ns] of the outer residual
     for (int outer = 0;; ++outer) {
         launch_zero_ring(c->cg, ns, 0, 1, 0, 0, s);
         resid();
+        ShardSources src{};
         for (int q = 0; q < ns; ++q) {
-            hipMemcpyAsync(hs + q * kShards, c->cg.rr_at(q, 0), sizeof(double) * kShards, hipMemcpyDeviceToHost, s);
-            hipMemcpyAsync(hs + (3 + q) * kShards, c->cg.bb_at(q), sizeof(double) * kShards, hipMemcpyDeviceToHost, s);
+            src.p[q] = c->cg.rr_at(q, 0);
+            src.p[ns + q] = c->cg.bb_at(q);
         }
+        launch_totals_to_host(src, 2 * ns, hs, s);
         int rc = hip_check(c, hipStreamSynchronize(s), "CG");
         if (rc) {
             res.status = rc;
@@ -185,10 +186,8 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
         double rr[kMaxComp] = {0, 0, 0}, bb[kMaxComp] = {0, 0, 0};
         bool conv[kMaxComp] = {true, true, true}, all = true;
         for (int q = 0; q < ns; ++q) {
-            for (int k = 0; k < kShards; ++k) {
-                rr[q] += hs[q * kShards + k];
-                bb[q] += hs[(3 + q) * kShards + k];
-            }
+            rr[q] = hs[q];
+            bb[q] = hs[ns + q];
             if (!std::isfinite(rr[q])) {
                 res.status = GSPM_E_NONFINITE;
                 c->err = "non-finite residual";
@@ -210,21 +209,15 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
             break;
         }
         // inner FP32 solve: per-component stopping folded into bb_in = eta^2 rr
-        double *h_in = hs + 6 * kShards;   // bb_in[3][kShards] | rr0[3][kShards]
-        int32_t *h_fl = reinterpret_cast<int32_t *>(hs + 12 * kShards);
-        std::memset(h_in, 0, sizeof(double) * 6 * kShards);
-        for (int q = 0; q < kMaxComp; ++q) {
-            h_fl[q] = (q < ns && !conv[q]) ? 0 : 1;
-            h_fl[kMaxComp + q] = 0;
-        }
+        InnerStart ist{};
+        for (int q = 0; q < kMaxComp; ++q) ist.done[q] = (q < ns && !conv[q]) ? 0 : 1;
         for (int q = 0; q < ns; ++q) {
             if (conv[q]) continue;
             const double eta = std::max(0.5 * tol * std::sqrt(bb[q] / rr[q]), kInnerFloor);
-            h_in[q * kShards] = eta * eta * rr[q] * scale * scale;
+            ist.bb[q] = eta * eta * rr[q] * scale * scale;
         }
         const CGScalars &ci = c->cg_in;
-        hipMemcpyAsync(ci.bb, h_in, sizeof(double) * kMaxComp * kShards, hipMemcpyHostToDevice, s);
-        hipMemcpyAsync(ci.done, h_fl, sizeof(int32_t) * 2 * kMaxComp, hipMemcpyHostToDevice, s);
+        launch_set_inner(ci, ist, s);
         launch_zero_ring(ci, ns, 0, 1, 0, 0, s);
         launch_to_f32_norms(n, nc, joint, c->d.r, scale, c->d.r32, ci, s);
         launch_fill_f32(c->d.x32, n3, s);
