@@ -18,6 +18,13 @@ inline int grid_of(int64_t n) {
     return static_cast<int>(g < (1 << 30) ? (g > 0 ? g : 1) : (1 << 30));
 }
 
+// streaming passes with a per-workgroup reduction: a bounded grid keeps the
+// number of atomic adds on the sharded sums small
+inline int reduce_grid_of(int64_t n) {
+    const int64_t g = (n + kThreads - 1) / kThreads;
+    return static_cast<int>(g < 2048 ? (g > 0 ? g : 1) : 2048);
+}
+
 // The test of |r_j|^2 <= tol2 |b|^2 (recorded by workgroup 0 as iteration
 // j) and the converged state of the set; true when the launch has work.
 __device__ __forceinline__ bool pc_live(const CGScalars &cg, int test_k, double tol2) {
@@ -94,27 +101,44 @@ __global__ void __launch_bounds__(kThreads) k_pc_restrict(GreenView gv, int n, c
                 s2 += wj[u] * v2[u];
             }
         }
-        grid[g] = s0;
-        grid[gv.G + g] = s1;
-        grid[2 * gv.G + g] = s2;
+        // packed for the complex transforms: w0 = x0 + i x1, w1 = x2
+        grid[2 * g] = s0;
+        grid[2 * g + 1] = s1;
+        grid[2 * (gv.G + g)] = s2;
+        grid[2 * (gv.G + g) + 1] = T(0);
     }
 }
 
-// y(k) = A(k)^-1 x(k) / G on the half spectrum (Hermitian 3x3 per mode).
+// Y(k) = A(k)^-1 X(k) / G on the packed spectra.  The two complex grids hold
+// the transforms of w0 = x0 + i x1 and w1 = x2 (x real), so
+//   X0(k) = (W0(k) + conj W0(-k)) / 2,  X1(k) = (W0(k) - conj W0(-k)) / 2i,
+//   X2(k) = (W1(k) + conj W1(-k)) / 2,
+// and the results go back packed the same way with Y(-k) = conj Y(k) (A(-k)
+// = conj A(k) for the real stencil), so the inverse transform returns
+// y0 + i y1 and y2.  One thread takes a mode k of the half spectrum (kx <=
+// gx / 2, the table's index) together with its mirror -k; a pair whose mirror
+// is in the half spectrum too is taken once.
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_pc_modes(GreenView gv, CGScalars cg) {
     if (cg.done[0] != 0) return;
     const T *M = static_cast<const T *>(gv.ainv);
-    T *sp = static_cast<T *>(gv.spec);      // (re, im) pairs
+    T *w0 = static_cast<T *>(gv.grid);      // (re, im) pairs, [2][G]
+    T *w1 = w0 + 2 * gv.G;
     for (int64_t m = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; m < gv.Gh;
          m += static_cast<int64_t>(gridDim.x) * kThreads) {
+        const int kx = static_cast<int>(m % gv.gxh);
+        const int ky = static_cast<int>((m / gv.gxh) % gv.gy);
+        const int kz = static_cast<int>(m / (static_cast<int64_t>(gv.gxh) * gv.gy));
+        const int mx = (gv.gx - kx) % gv.gx, my = (gv.gy - ky) % gv.gy, mz = (gv.gz - kz) % gv.gz;
+        const int64_t f = (static_cast<int64_t>(kz) * gv.gy + ky) * gv.gx + kx;
+        const int64_t fm = (static_cast<int64_t>(mz) * gv.gy + my) * gv.gx + mx;
+        if (mx < gv.gxh && fm < f) continue;
+        const T ar = w0[2 * f], ai = w0[2 * f + 1], br = w0[2 * fm], bi = w0[2 * fm + 1];
+        const T cr = w1[2 * f], ci = w1[2 * f + 1], dr = w1[2 * fm], di = w1[2 * fm + 1];
+        const T h = T(0.5);
+        const T xr[3] = {h * (ar + br), h * (ai + bi), h * (cr + dr)};
+        const T xi[3] = {h * (ai - bi), h * (br - ar), h * (ci - di)};
         const T *a = M + 9 * m;
-        T xr[3], xi[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            xr[c] = sp[2 * (c * gv.Gh + m)];
-            xi[c] = sp[2 * (c * gv.Gh + m) + 1];
-        }
         // off-diagonal (a01, a02, a12) and their conjugates below the diagonal
         const T r01 = a[3], i01 = a[4], r02 = a[5], i02 = a[6], r12 = a[7], i12 = a[8];
         const T yr0 = a[0] * xr[0] + (r01 * xr[1] - i01 * xi[1]) + (r02 * xr[2] - i02 * xi[2]);
@@ -123,12 +147,23 @@ __global__ void __launch_bounds__(kThreads) k_pc_modes(GreenView gv, CGScalars c
         const T yi1 = (r01 * xi[0] - i01 * xr[0]) + a[1] * xi[1] + (r12 * xi[2] + i12 * xr[2]);
         const T yr2 = (r02 * xr[0] + i02 * xi[0]) + (r12 * xr[1] + i12 * xi[1]) + a[2] * xr[2];
         const T yi2 = (r02 * xi[0] - i02 * xr[0]) + (r12 * xi[1] - i12 * xr[1]) + a[2] * xi[2];
-        sp[2 * m] = yr0;
-        sp[2 * m + 1] = yi0;
-        sp[2 * (gv.Gh + m)] = yr1;
-        sp[2 * (gv.Gh + m) + 1] = yi1;
-        sp[2 * (2 * gv.Gh + m)] = yr2;
-        sp[2 * (2 * gv.Gh + m) + 1] = yi2;
+        if (fm == f) {
+            // a self-conjugate mode: X and A^-1 are real there (up to rounding)
+            w0[2 * f] = yr0;
+            w0[2 * f + 1] = yr1;
+            w1[2 * f] = yr2;
+            w1[2 * f + 1] = T(0);
+            continue;
+        }
+        // W0(k) = Y0 + i Y1, W0(-k) = conj Y0 + i conj Y1, W1(+-k) = Y2, conj Y2
+        w0[2 * f] = yr0 - yi1;
+        w0[2 * f + 1] = yi0 + yr1;
+        w0[2 * fm] = yr0 + yi1;
+        w0[2 * fm + 1] = yr1 - yi0;
+        w1[2 * f] = yr2;
+        w1[2 * f + 1] = yi2;
+        w1[2 * fm] = yr2;
+        w1[2 * fm + 1] = -yi2;
     }
 }
 
@@ -154,8 +189,10 @@ __global__ void __launch_bounds__(kThreads) k_pc_prolong(GreenView gv, MeshView 
                               ((c & 4) ? t[2] : 1.0 - t[2]);
             const T wc = static_cast<T>(wd);
             const int64_t g = (static_cast<int64_t>(iz) * gv.gy + iy) * gv.gx + ix;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) acc[a] += wc * y[a * gv.G + g];
+            // packed: y0 + i y1 in the first complex grid, y2 in the second
+            acc[0] += wc * y[2 * g];
+            acc[1] += wc * y[2 * g + 1];
+            acc[2] += wc * y[2 * (gv.G + g)];
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -317,15 +354,15 @@ void launch_pc_prolong(const GreenView &gv, const MeshView &mv, const T *r, T *z
 
 template <class T>
 void launch_pcg_update(int n, T *x, T *r, const T *p, const T *q, const CGScalars &cg, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_update<T>, dim3(grid_of(3 * static_cast<int64_t>(n))), dim3(kThreads), 0, s, n, x, r, p, q,
+    hipLaunchKernelGGL(k_pcg_update<T>, dim3(reduce_grid_of(3 * static_cast<int64_t>(n))), dim3(kThreads), 0, s, n, x, r, p, q,
                        cg, k);
 }
 
 void launch_remove_mean3(int n, double *b, double *aux, double *bb, hipStream_t s) {
     launch_fill(aux, 3 * kShards, 0.0, s);
     launch_fill(bb, kShards, 0.0, s);
-    hipLaunchKernelGGL(k_sum3, dim3(grid_of(n)), dim3(kThreads), 0, s, n, b, aux);
-    hipLaunchKernelGGL(k_sub_mean3, dim3(grid_of(n)), dim3(kThreads), 0, s, n, b, aux, bb);
+    hipLaunchKernelGGL(k_sum3, dim3(reduce_grid_of(n)), dim3(kThreads), 0, s, n, b, aux);
+    hipLaunchKernelGGL(k_sub_mean3, dim3(reduce_grid_of(n)), dim3(kThreads), 0, s, n, b, aux, bb);
 }
 
 void launch_pin_shift(int n, double *x, int p0, double *aux, hipStream_t s) {
