@@ -112,13 +112,13 @@ int make_plans(gspm_ctx *c, bool f32) {
     const size_t len[3] = {static_cast<size_t>(pc.gv.gx), static_cast<size_t>(pc.gv.gy),
                            static_cast<size_t>(pc.gv.gz)};
     const rocfft_precision prec = f32 ? rocfft_precision_single : rocfft_precision_double;
-    // the three real fields packed into two complex ones, transformed in place as one batch
+    // the three real fields packed into two complex ones, transformed as one batch (grid -> spec, spec -> grid)
     rocfft_plan fwd = nullptr, inv = nullptr;
-    if (rocfft_plan_create(&fwd, rocfft_placement_inplace, rocfft_transform_type_complex_forward, prec, 3, len, 2,
+    if (rocfft_plan_create(&fwd, rocfft_placement_notinplace, rocfft_transform_type_complex_forward, prec, 3, len, 2,
                            nullptr) != rocfft_status_success)
         return fft_fail(c, "rocfft_plan_create (forward) failed");
     pc.fwd = fwd;
-    if (rocfft_plan_create(&inv, rocfft_placement_inplace, rocfft_transform_type_complex_inverse, prec, 3, len, 2,
+    if (rocfft_plan_create(&inv, rocfft_placement_notinplace, rocfft_transform_type_complex_inverse, prec, 3, len, 2,
                            nullptr) != rocfft_status_success)
         return fft_fail(c, "rocfft_plan_create (inverse) failed");
     pc.inv = inv;
@@ -233,7 +233,7 @@ int setup_mesh_part(gspm_ctx *c) {
     if (!rc) rc = pc_alloc(c, reinterpret_cast<char **>(&pc.dinv), tb * 3 * static_cast<size_t>(n));
     if (!rc) rc = pc_alloc(c, reinterpret_cast<char **>(&pc.ainv), tb * 9 * static_cast<size_t>(gv.Gh));
     if (!rc) rc = pc_alloc(c, reinterpret_cast<char **>(&pc.grid), tb * 4 * static_cast<size_t>(gv.G));
-    if (!rc) pc.spec = pc.grid;
+    if (!rc) rc = pc_alloc(c, reinterpret_cast<char **>(&pc.spec), tb * 4 * static_cast<size_t>(gv.G));
     if (!rc) rc = pc_alloc(c, &pc.aux, 3 * kShards + 3);
     if (rc) return rc;
     hipMemcpyAsync(pc.rptr, ptr.data(), sizeof(int32_t) * ptr.size(), hipMemcpyHostToDevice, c->stream);
@@ -336,8 +336,9 @@ int green_setup(gspm_ctx *c) {
 
 int green_fft(gspm_ctx *c, bool forward) {
     auto &pc = c->pc;
-    void *io[1] = {pc.grid};
-    const rocfft_status st = rocfft_execute(static_cast<rocfft_plan>(forward ? pc.fwd : pc.inv), io, nullptr,
+    void *in[1] = {forward ? pc.grid : pc.spec};
+    void *out[1] = {forward ? pc.spec : pc.grid};
+    const rocfft_status st = rocfft_execute(static_cast<rocfft_plan>(forward ? pc.fwd : pc.inv), in, out,
                                             static_cast<rocfft_execution_info>(pc.info));
     return st == rocfft_status_success ? GSPM_OK : fft_fail(c, "rocfft_execute failed");
 }
@@ -364,9 +365,8 @@ void gspm_ctx::release_pc() {
     if (q.fwd) rocfft_plan_destroy(static_cast<rocfft_plan>(q.fwd));
     if (q.inv) rocfft_plan_destroy(static_cast<rocfft_plan>(q.inv));
     if (q.info) rocfft_execution_info_destroy(static_cast<rocfft_execution_info>(q.info));
-    // (spec aliases grid: the transforms run in place)
     for (void *p : {static_cast<void *>(q.rptr), static_cast<void *>(q.rgrid), static_cast<void *>(q.rnode), q.rw,
-                    q.dinv, q.ainv, q.grid, q.work, static_cast<void *>(q.aux)})
+                    q.dinv, q.ainv, q.grid, q.spec, q.work, static_cast<void *>(q.aux)})
         gspm::ctx_free(this, p);
     q = gspm::GreenState{};
 }

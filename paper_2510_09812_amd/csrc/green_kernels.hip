@@ -122,7 +122,7 @@ template <class T>
 __global__ void __launch_bounds__(kThreads) k_pc_modes(GreenView gv, CGScalars cg) {
     if (cg.done[0] != 0) return;
     const T *M = static_cast<const T *>(gv.ainv);
-    T *w0 = static_cast<T *>(gv.grid);      // (re, im) pairs, [2][G]
+    T *w0 = static_cast<T *>(gv.spec);      // (re, im) pairs, [2][G]
     T *w1 = w0 + 2 * gv.G;
     for (int64_t m = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; m < gv.Gh;
          m += static_cast<int64_t>(gridDim.x) * kThreads) {
