@@ -222,8 +222,8 @@ struct GreenView {
     const void *rw;               // their weights (T)
     const void *dinv;             // [3][n] omega / diag(K^mech) (T)
     const void *ainv;             // [Gh][9] A(k)^-1 / G, Hermitian: re a00 a11 a22, then a01 a02 a12 (re, im) (T)
-    void *grid;                   // [2][G] complex (T): x0 + i x1, x2 on the grid; their spectra in place
-    void *spec;                   // the same array (the transforms run in place)
+    void *grid;                   // [2][G] complex (T): x0 + i x1, x2 on the grid (restriction in, prolongation out)
+    void *spec;                   // [2][G] complex (T): their spectra (forward FFT out, inverse FFT in)
 };
 
 // The preconditioner's node and grid passes (green_kernels.hip).  Every

@@ -198,8 +198,8 @@ int green_setup(gspm_ctx *c);
 // the pair is not cached.
 GsRowsView gs_rows(gspm_ctx *c, double eps, double mass, bool fp32);
 int green_apply64(gspm_ctx *c, const double *x, double *y);
-// FFTs of the preconditioner on the context's stream, in place on the two
-// packed complex grids (one batch): forward or inverse.
+// FFTs of the preconditioner on the context's stream, the two packed complex
+// grids as one batch: grid -> spec (forward) or spec -> grid (inverse).
 int green_fft(gspm_ctx *c, bool forward);
 int hip_check(gspm_ctx *c, hipError_t e, const char *what);
 // Device memory of the context: the caller's allocator when given, else hipMalloc / hipFree.
