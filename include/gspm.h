@@ -190,6 +190,14 @@ typedef struct {
                                three components (one fused launch per iteration: the matvec with the CG vector
                                updates; stages 1 and 3; those after convergence excluded) */
     int64_t gs_matvec_launches; /* profile mode: their number */
+    double phase_ms[8];     /* profile mode: device time of each phase of Alg. B.1, summed over the steps:
+                               [0] averages at m^n, [1] elastic solve (right-hand side, start, CG), [2] local
+                               magnetostatic solve, [3] GS stage 1 (field right-hand side, 3 solves), [4] stage 2
+                               (m updates, right-hand side, 2 solves), [5] averages at m*, [6] stage 3, [7]
+                               projection and commit check */
+    double final_residual[5]; /* the last step of the call: the relative residual ||b - A x|| / ||b|| at which
+                               each solve stopped (largest over its components; FP64 in both precisions):
+                               elastic, GS stage 1, stage 2, stage 3, magnetostatic; 0 for a solve not run */
 } gspm_step_stats;
 
 /* Create a context on opts->device (NULL opts: device 0, FP64, own stream).

@@ -211,8 +211,11 @@ gspm_ctx::~gspm_ctx() {
         if (e) hipEventDestroy(e);
     if (t0) hipEventDestroy(t0);
     if (t1) hipEventDestroy(t1);
+    for (hipEvent_t e : phase_ev)
+        if (e) hipEventDestroy(e);
     if (h_flags) hipHostFree(h_flags);
     if (h_mixed) hipHostFree(h_mixed);
+    if (h_step) hipHostFree(h_step);
     if (own_stream && stream) hipStreamDestroy(stream);
 }
 
@@ -331,8 +334,11 @@ gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts) {
                             hipHostMallocCoherent) == hipSuccess;
     ok = ok && hipHostMalloc(reinterpret_cast<void **>(&c->h_mixed), sizeof(double) * 16 * kShards,
                              hipHostMallocCoherent) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void **>(&c->h_step), sizeof(double) * 16, hipHostMallocCoherent) ==
+                   hipSuccess;
     for (auto &e : c->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreate(&c->t0) == hipSuccess && hipEventCreate(&c->t1) == hipSuccess;
+    for (auto &e : c->phase_ev) ok = ok && hipEventCreate(&e) == hipSuccess;
     if (!ok) {
         delete c;
         g_create_error = "gspm_create: cannot allocate host resources";

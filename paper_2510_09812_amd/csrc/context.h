@@ -136,6 +136,10 @@ struct gspm_ctx {
     int64_t mech_refinements = 0; // the part of them in elastic solves
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipEvent_t phase_ev[9] = {};          // profile mode: boundaries of a step's phases
+    double *h_step = nullptr;             // pinned: the step's results the host reads (sums, flags, residual totals)
+    bool want_res = false;                // record the final residual of each solve (the call's last step)
+    double last_res[gspm::SK_COUNT] = {}; // relative residual at which the last solve of each kind stopped
     // profile mode: event pairs around the launches of list 0 (the elastic CG
     // iteration, plain or preconditioned matvec) and list 1 (the GS matvec on
     // three components); prof_list names the list the running solve records into

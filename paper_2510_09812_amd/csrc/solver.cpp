@@ -143,12 +143,33 @@ void prof_drop_after(gspm_ctx *c, size_t first_pair, int iters) {
 
 // Plain FP64 CG from the initial guess x (Sec. 2.5): residual, start test,
 // iterations.  resid() writes r = b - A x and rr[0]; iter(k) one iteration.
+// The relative residual at which a solve stopped (the largest over its scalar
+// sets): |r|^2 of the recorded iteration (the slot every form leaves it in)
+// over |b|^2; kept for the statistics of the call's last step.
+void record_residual(gspm_ctx *c, const CGScalars &cg, int ns, const CgResult &r, SolveKind kind) {
+    if (!c->want_res || r.status) return;
+    ShardSources src{};
+    for (int q = 0; q < ns; ++q) {
+        src.p[q] = cg.rr_at(q, r.iters[q]);
+        src.p[ns + q] = cg.bb_at(q);
+    }
+    double *h = c->h_step + 8;
+    launch_totals_to_host(src, 2 * ns, h, c->stream);
+    if (hip_check(c, hipStreamSynchronize(c->stream), "CG residual")) return;
+    double worst = 0.0;
+    for (int q = 0; q < ns; ++q)
+        if (h[ns + q] > 0.0) worst = std::max(worst, std::sqrt(std::max(h[q], 0.0) / h[ns + q]));
+    c->last_res[kind] = worst;
+}
+
 template <class Resid, class Iter>
 CgResult cg_fp64(gspm_ctx *c, int nc, bool joint, double *x, double tol, int maxit, SolveKind kind, Resid resid,
                  Iter iter) {
     resid();
     launch_cg_start<double>(c->n, nc, joint, x, c->cg, tol, c->stream);
-    return cg_iterate(c, c->cg, nc, joint, maxit, kind, iter);
+    CgResult r = cg_iterate(c, c->cg, nc, joint, maxit, kind, iter);
+    record_residual(c, c->cg, joint ? 1 : nc, r, kind);
+    return r;
 }
 
 // Mixed form: FP64 iterative refinement around FP32 CG.  Each outer step
@@ -200,7 +221,13 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
             conv[q] = bb[q] == 0.0 || rr[q] <= tol * tol * bb[q];
             all &= conv[q];
         }
-        if (all) break;
+        if (all) {
+            double worst = 0.0;
+            for (int q = 0; q < ns; ++q)
+                if (bb[q] > 0.0) worst = std::max(worst, std::sqrt(std::max(rr[q], 0.0) / bb[q]));
+            c->last_res[kind] = worst;
+            break;
+        }
         int used = 0;
         for (int q = 0; q < ns; ++q) used = std::max(used, total[q]);
         if (used >= maxit) {
@@ -497,10 +524,16 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     const size_t bytes3 = sizeof(double) * 3 * static_cast<size_t>(n);
     const double tol = c->p.cg_tol;
     const int maxit = c->p.cg_maxit;
+    // profile mode: event at each phase boundary (phase_ms of the statistics)
+    auto mark = [&](int b) {
+        if (c->profile) hipEventRecord(c->phase_ev[b], s);
+    };
+    mark(0);
 
     // volume averages at m^n: far field and homogeneous strain
     launch_avg_sums(n, d.w, d.m, c->mat, d.sums, s);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
+    mark(1);
 
     // mechanical equilibrium at m^n, warm start from u^{n-1}
     hipMemcpyAsync(d.unext, d.u, bytes3, hipMemcpyDeviceToDevice, s);
@@ -525,6 +558,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     CgResult r = cg_elastic(c, d.unext, d.b, tol, maxit, SK_MECH);
     st->mech_iters += r.iters[0];
     if (r.status) return r.status;
+    mark(2);
 
     // local magnetostatics at m^n, warm start from the previous potential
     const double *ud = nullptr;
@@ -537,6 +571,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
         if (r.status) return r.status;
         ud = d.udnext;
     }
+    mark(3);
     const double inv_ms = 1.0 / c->p.Ms;
 
     if (c->p.precession) {
@@ -547,6 +582,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
         r = cg_gs(c, 3, eps1, d.g, d.b, tol, maxit, SK_GS1);
         for (int q = 0; q < 3; ++q) st->gs_iters_stage[q] += r.iters[q];
         if (r.status) return r.status;
+        mark(4);
         // Step 2, rows 1 and 2
         launch_update_m12(n, d.m, d.g, d.ms, s);
         // Step 1: g* for components 1 and 2 with h[m^n]
@@ -558,36 +594,46 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
         // Step 2, row 3
         launch_update_m3(n, d.m, d.gs, d.ms, s);
     } else {
+        mark(4);
         hipMemcpyAsync(d.ms, d.m, bytes3, hipMemcpyDeviceToDevice, s);
     }
+    mark(5);
 
     // Step 3: damped solve with h[m*], averages re-evaluated at m*
     launch_avg_sums(n, d.w, d.ms, c->mat, d.sums, s);
     launch_derive(d.sums, c->dargs, &d.der[1], s);
+    mark(6);
     cg_prepare(c, 3);
     launch_field_rhs(c->mv, c->mat, d.ms, d.unext, &d.der[1], c->p.alpha * dtau, d.b, d.g, nullptr, c->cg.bb,
                      kShards, ud, inv_ms, s);
     r = cg_gs(c, 3, eps3, d.g, d.b, tol, maxit, SK_GS3);
     for (int q = 0; q < 3; ++q) st->gs_iters_stage[5 + q] += r.iters[q];
     if (r.status) return r.status;
+    mark(7);
 
-    // Step 4: unit length
+    // Step 4: unit length; the host reads the sum of |dm| and the failure flag
     launch_fill(d.dm, kShards, 0.0, s);
     launch_fill_i32(d.bad, 1, 0, s);
     launch_normalize(n, d.w, d.g, d.m, d.mnext, d.dm, d.bad, s);
-    double dmh[kShards];
-    int32_t badh = 0;
-    hipMemcpyAsync(dmh, d.dm, sizeof dmh, hipMemcpyDeviceToHost, s);
-    hipMemcpyAsync(&badh, d.bad, sizeof badh, hipMemcpyDeviceToHost, s);
+    ShardSources dms{};
+    dms.p[0] = d.dm;
+    launch_totals_to_host(dms, 1, c->h_step, s);
+    launch_i32_to_host(d.bad, 1, reinterpret_cast<int32_t *>(c->h_step + 1), s);
+    mark(8);
     int rc = hip_check(c, hipStreamSynchronize(s), "step");
     if (rc) return rc;
-    if (badh) {
+    if (c->profile) {
+        for (int b = 0; b < 8; ++b) {
+            float e = 0.0f;
+            hipEventElapsedTime(&e, c->phase_ev[b], c->phase_ev[b + 1]);
+            st->phase_ms[b] += e;
+        }
+    }
+    if (*reinterpret_cast<const int32_t *>(c->h_step + 1)) {
         c->err = "zero or non-finite magnetisation after the damped solve";
         return GSPM_E_NONFINITE;
     }
-    double dsum = 0.0;
-    for (int k = 0; k < kShards; ++k) dsum += dmh[k];
-    st->dm_avg = c->nmag > 0 ? dsum / c->nmag : 0.0;
+    st->dm_avg = c->nmag > 0 ? c->h_step[0] / c->nmag : 0.0;
     // m^{n-1} <- m^n <- m^{n+1} and u^{n-2} <- u^{n-1} <- u^n: the old
     // buffers keep the previous states
     std::swap(d.mprev, d.m);
@@ -612,7 +658,9 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     const int64_t ref0 = c->refinements, mref0 = c->mech_refinements;
     hipEventRecord(c->t0, c->stream);
     int rc = GSPM_OK;
+    for (auto &v : c->last_res) v = 0.0;
     for (int step = 0; step < nsteps; ++step) {
+        c->want_res = step == nsteps - 1;
         rc = one_step(c, dtau, eps1, eps3, st);
         if (rc) {
             st->failed_step = step;
@@ -626,6 +674,9 @@ int run_steps(gspm_ctx *c, double dt, int nsteps, gspm_step_stats *st) {
     float ms = 0.0f;
     hipEventElapsedTime(&ms, c->t0, c->t1);
     st->elapsed_ms = ms;
+    c->want_res = false;
+    const SolveKind res_kind[5] = {SK_MECH, SK_GS1, SK_GS2, SK_GS3, SK_MS};
+    for (int q = 0; q < 5; ++q) st->final_residual[q] = c->last_res[res_kind[q]];
     for (int q = 0; q < 8; ++q) st->gs_iters += st->gs_iters_stage[q];
     st->refinements = c->refinements - ref0;
     st->mech_refinements = c->mech_refinements - mref0;

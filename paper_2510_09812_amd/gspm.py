@@ -71,7 +71,12 @@ class gspm_step_stats(ctypes.Structure):
                 ("learned_starts", ctypes.c_int64), ("minres_starts", ctypes.c_int64),
                 ("warm_coef", ctypes.c_double * 2), ("ms_iters", ctypes.c_int64),
                 ("mech_refinements", ctypes.c_int64), ("gs_matvec_ms", ctypes.c_double),
-                ("gs_matvec_launches", ctypes.c_int64)]
+                ("gs_matvec_launches", ctypes.c_int64), ("phase_ms", ctypes.c_double * 8),
+                ("final_residual", ctypes.c_double * 5)]
+
+PHASES = ("averages", "elastic", "magnetostatic", "gs_stage1", "gs_stage2", "averages_mstar", "gs_stage3",
+          "projection")
+RESIDUAL_SOLVES = ("elastic", "gs_stage1", "gs_stage2", "gs_stage3", "magnetostatic")
 
 
 _lib = None
@@ -244,7 +249,8 @@ def stats_dict(st: gspm_step_stats) -> dict:
                 elapsed_ms=st.elapsed_ms, matvec_ms=st.matvec_ms, matvec_launches=st.matvec_launches,
                 refinements=st.refinements, learned_starts=st.learned_starts, minres_starts=st.minres_starts,
                 warm_coef=list(st.warm_coef), ms_iters=st.ms_iters, mech_refinements=st.mech_refinements,
-                gs_matvec_ms=st.gs_matvec_ms, gs_matvec_launches=st.gs_matvec_launches)
+                gs_matvec_ms=st.gs_matvec_ms, gs_matvec_launches=st.gs_matvec_launches,
+                phase_ms=dict(zip(PHASES, st.phase_ms)), final_residual=dict(zip(RESIDUAL_SOLVES, st.final_residual)))
 
 
 def gspm_step(ctx, dt: float, n_steps: int = 1) -> dict:
