@@ -456,6 +456,9 @@ def main() -> int:
                                      "preconditioned": precond}},
         "paths": per_path,
         "ms_roofline": ms_roofline,
+        # device time per phase of the step on the value path (profile steps after the timed region)
+        "phase_ms_per_step": ({k: v / args.profile_steps for k, v in pst["phase_ms"].items()} if pst else None),
+        "final_residual": st["final_residual"],
     }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
