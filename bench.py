@@ -224,6 +224,8 @@ def main() -> int:
                     help="comma-separated path names to run (for profiling one path), e.g. mixed+precond")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the paths with the Green's-operator preconditioned elastic solve")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="also run the preconditioned paths in the bitwise-reproducible mode")
     ap.add_argument("--no-local-demag", action="store_true",
                     help="skip the paths with the local magnetostatic solve (reported beside the headline)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -261,7 +263,7 @@ def main() -> int:
             weights = None
 
     def run_path(precision: int, warm: int = 0, local_demag: bool = False, rotated: bool = False,
-                 precond: bool = False) -> dict:
+                 precond: bool = False, deterministic: bool = False) -> dict:
         t_up = time.perf_counter()
         params = dict(case.params)
         if rotated:
@@ -270,7 +272,8 @@ def main() -> int:
             params["elastic_precond"] = gspm.GSPM_PRECOND_GREEN
             params["gs_precond"] = gspm.GSPM_PRECOND_JACOBI
         sim = gspm.Simulation(case.mesh, params, hext=case.hext, device=0, profile=False,
-                              block_nodes=args.block_nodes, precision=precision, local_demag=local_demag)
+                              block_nodes=args.block_nodes, precision=precision, local_demag=local_demag,
+                              deterministic=deterministic)
         sim.set_m(case.m0)
         if warm == gspm.GSPM_WARM_LEARNED:
             sim.mpnn_set_params(weights)
@@ -328,6 +331,11 @@ def main() -> int:
         if weights is not None:
             specs.append(("mixed+learned+precond", dict(precision=gspm.GSPM_MIXED, warm=gspm.GSPM_WARM_LEARNED,
                                                         precond=True)))
+        if args.deterministic:
+            # the bitwise-reproducible mode (fixed-order sums), reported beside the others
+            specs += [("fp64+precond+deterministic", dict(precision=gspm.GSPM_FP64, precond=True, deterministic=True)),
+                      ("mixed+precond+deterministic", dict(precision=gspm.GSPM_MIXED, precond=True,
+                                                           deterministic=True))]
     if not args.no_rotated:
         specs += [("fp64+rotated111", dict(precision=gspm.GSPM_FP64, rotated=True)),
                   ("mixed+rotated111", dict(precision=gspm.GSPM_MIXED, rotated=True))]
@@ -355,7 +363,8 @@ def main() -> int:
 
     # `value`: the fastest mixed-precision path of the workload's physics that stays within the
     # metric's 1e-6 of the FP64 run (the optional terms are other physics, reported beside it)
-    base = [k for k in paths if k.startswith("mixed") and "+local_demag" not in k and "+rotated111" not in k]
+    base = [k for k in paths if k.startswith("mixed") and "+local_demag" not in k and "+rotated111" not in k
+            and "+deterministic" not in k]
     good = [k for k in base if within_target(k)]
     head_name = (max(good, key=lambda k: paths[k]["value"]) if good
                  else next((k for k in ("mixed", "fp64") if k in paths), next(iter(paths))))

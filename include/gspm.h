@@ -114,6 +114,13 @@ typedef struct {
     void *(*dev_alloc)(size_t bytes, void *alloc_user);
     void (*dev_free)(void *ptr, void *alloc_user);
     void *alloc_user;
+    int32_t deterministic;  /* nonzero: bitwise reproducible steps (same device, mesh, block size and inputs
+                               give the same bits, whether run at once or split by a save and restore of M
+                               and U).  Every sum is added in a fixed order: workgroup totals go to slots
+                               that a follow-up launch adds in workgroup order (no atomic adds), and the
+                               element passes gather each owned node's elements in a fixed order (no LDS
+                               atomics; each element is evaluated once per owned vertex).  Slower; the
+                               learned and extrapolated warm starts are not available (GSPM_E_STATE). */
 } gspm_create_opts;
 
 typedef enum { GSPM_REORDER_MORTON = 0, GSPM_REORDER_NONE = 1, GSPM_REORDER_RCM = 2 } gspm_reorder;
@@ -222,9 +229,11 @@ gspm_status gspm_upload_mesh(gspm_ctx *ctx, int64_t n_nodes, const double *xyz, 
 gspm_status gspm_set_params(gspm_ctx *ctx, const gspm_params *params);
 
 /* Set or read a nodal field (n_nodes x 3, caller's order; GSPM_FIELD_UD:
- * n_nodes values).  Setting M normalises m on magnetic nodes and zeroes it on
- * nodes that lie in inclusions only; a zero or non-finite vector on a
- * magnetic node is GSPM_E_ARG.  U is the periodic displacement [m]; UD the
+ * n_nodes values).  Setting M normalises m on magnetic nodes (a vector whose
+ * length is 1 to within 1e-14 is kept as given, so a state read with
+ * get_field restores bit for bit) and zeroes it on nodes that lie in
+ * inclusions only; a zero or non-finite vector on a magnetic node is
+ * GSPM_E_ARG.  U is the periodic displacement [m]; UD the
  * local magnetostatic potential [A] (the warm start of the next solve and
  * the potential the energies use). */
 gspm_status gspm_set_field(gspm_ctx *ctx, gspm_field which, const double *values, int64_t n_nodes);

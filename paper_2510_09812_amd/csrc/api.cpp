@@ -1,6 +1,7 @@
 // C ABI of the GSPM library: argument checking, state machine, host<->device
 // marshalling in the caller's node order.  Every numerical step runs in the
 // HIP kernels; this file only moves data and sequences calls.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -239,6 +240,8 @@ void gspm_ctx::release_mesh() {
     dev_free(this, b.ud); dev_free(this, b.udnext); dev_free(this, b.rep);
     dev_free(this, b.cg_rz); dev_free(this, b.cgi_rz);
     dev_free(this, b.cg_rzq); dev_free(this, b.cg_qzq); dev_free(this, b.cgi_rzq); dev_free(this, b.cgi_qzq);
+    dev_free(this, b.det_part); dev_free(this, b.det_dst); dev_free(this, b.det_count); dev_free(this, b.inc_ptr);
+    dev_free(this, b.inc_ent);
     dev_free(this, b.gs_off); dev_free(this, b.gs_col); dev_free(this, b.gs_kv); dev_free(this, b.gs_mv);
     dev_free(this, b.gs_kd); dev_free(this, b.gs_md);
     for (int k = 0; k < 2; ++k) {
@@ -315,6 +318,7 @@ gspm_status gspm_create(gspm_ctx **out, const gspm_create_opts *opts) {
     c->precision = o.precision;
     c->block_nodes = o.block_nodes;
     c->reorder = o.reorder;
+    c->deterministic = o.deterministic != 0;
     c->alloc_fn = o.dev_alloc;
     c->free_fn = o.dev_free;
     c->alloc_user = o.alloc_user;
@@ -389,6 +393,38 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     GsRowsHost rows;
     rc = assemble_gs_rows(hm, n_tets, tets, tags, rows, err);
     if (rc) return fail(c, static_cast<gspm_status>(rc), "upload_mesh: " + err);
+    // deterministic mode: per owned node its element copies, (copy index within the block's list) << 2 | slot
+    std::vector<int32_t> inc_ptr;
+    std::vector<uint16_t> inc_ent;
+    int32_t det_blocks = 0;
+    if (c->deterministic) {
+        const size_t nslot = static_cast<size_t>(hm.nblk) * hm.nb;
+        inc_ptr.assign(nslot + 1, 0);
+        for (int32_t b = 0; b < hm.nblk; ++b) {
+            if (hm.blk_ptr[b + 1] - hm.blk_ptr[b] > 16384)
+                return fail(c, GSPM_E_ARG, "upload_mesh: deterministic mode needs at most 16384 element copies per "
+                                           "block; use smaller block_nodes");
+            for (int32_t e = hm.blk_ptr[b]; e < hm.blk_ptr[b + 1]; ++e)
+                for (int j = 0; j < 4; ++j) {
+                    const int v = hm.lconn[4 * static_cast<size_t>(e) + j];
+                    if (v < hm.nb) ++inc_ptr[static_cast<size_t>(b) * hm.nb + v + 1];
+                }
+        }
+        for (size_t i = 0; i < nslot; ++i) inc_ptr[i + 1] += inc_ptr[i];
+        inc_ent.resize(static_cast<size_t>(inc_ptr[nslot]));
+        std::vector<int32_t> cur(inc_ptr.begin(), inc_ptr.end() - 1);
+        for (int32_t b = 0; b < hm.nblk; ++b)
+            for (int32_t e = hm.blk_ptr[b]; e < hm.blk_ptr[b + 1]; ++e)
+                for (int j = 0; j < 4; ++j) {
+                    const int v = hm.lconn[4 * static_cast<size_t>(e) + j];
+                    if (v < hm.nb)
+                        inc_ent[static_cast<size_t>(cur[static_cast<size_t>(b) * hm.nb + v]++)] =
+                            static_cast<uint16_t>(((e - hm.blk_ptr[b]) << 2) | j);
+                }
+        // the largest grid of a launch that adds sums: the element passes (one workgroup per block) and the
+        // node passes (at most 2048, or one thread per node)
+        det_blocks = std::max({2048, hm.nblk, (hm.n + kThreads - 1) / kThreads});
+    }
     c->release_mesh();
     const size_t n = static_cast<size_t>(hm.n), n3 = 3 * n;
     const size_t nent = rows.col.size();
@@ -428,6 +464,13 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
         rc = rc ? rc : dev_alloc(c, &d.gs_mv, nent);
         rc = rc ? rc : dev_alloc(c, &d.gs_kd, n);
         rc = rc ? rc : dev_alloc(c, &d.gs_md, n);
+        if (c->deterministic) {
+            rc = rc ? rc : dev_alloc(c, &d.inc_ptr, inc_ptr.size());
+            rc = rc ? rc : dev_alloc(c, &d.inc_ent, inc_ent.size());
+            rc = rc ? rc : dev_alloc(c, &d.det_part, static_cast<size_t>(kDetSlots) * det_blocks);
+            rc = rc ? rc : dev_alloc(c, &d.det_dst, static_cast<size_t>(kDetSlots));
+            rc = rc ? rc : dev_alloc(c, &d.det_count, 1);
+        }
         for (int k = 0; k < 2; ++k) {
             rc = rc ? rc : dev_alloc(c, &d.gs_a64[k], nent);
             rc = rc ? rc : dev_alloc(c, &d.gs_d64[k], n);
@@ -504,6 +547,15 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     hipMemcpyAsync(d.gs_kd, rows.kd.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.gs_md, rows.md.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
     c->gs_nent = static_cast<int64_t>(nent);
+    if (c->deterministic) {
+        hipMemcpyAsync(d.inc_ptr, inc_ptr.data(), sizeof(int32_t) * inc_ptr.size(), hipMemcpyHostToDevice, s);
+        if (!inc_ent.empty())
+            hipMemcpyAsync(d.inc_ent, inc_ent.data(), sizeof(uint16_t) * inc_ent.size(), hipMemcpyHostToDevice, s);
+        const std::vector<double *> no_dst(kDetSlots, nullptr);
+        hipMemcpyAsync(d.det_dst, no_dst.data(), sizeof(double *) * kDetSlots, hipMemcpyHostToDevice, s);
+        launch_fill(d.det_part, static_cast<int64_t>(kDetSlots) * det_blocks, 0.0, s);
+        launch_fill_i32(d.det_count, 1, 0, s);
+    }
     std::vector<int32_t> rep(n, -1);
     for (int64_t i = hm.n0 - 1; i >= 0; --i) rep[static_cast<size_t>(hm.user2int[i])] = static_cast<int32_t>(i);
     hipMemcpyAsync(d.rep, rep.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
@@ -570,6 +622,16 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     mv.Lx = hm.L[0]; mv.Ly = hm.L[1]; mv.Lz = hm.L[2];
     mv.iLx = 1.0 / hm.L[0]; mv.iLy = 1.0 / hm.L[1]; mv.iLz = 1.0 / hm.L[2];
     mv.len_scale = std::cbrt(hm.vc / static_cast<double>(hm.ne));
+    mv.det = DetSums{};
+    mv.inc_ptr = nullptr;
+    mv.inc_ent = nullptr;
+    if (c->deterministic) {
+        mv.det = DetSums{d.det_part, d.det_dst, d.det_count, det_blocks};
+        mv.inc_ptr = d.inc_ptr;
+        mv.inc_ent = d.inc_ent;
+    }
+    c->cg.det = mv.det;
+    c->cg_in.det = mv.det;
     c->cg.rr = d.cg_rr;
     c->cg.pq = d.cg_pq;
     c->cg.bb = d.cg_bb;
@@ -703,7 +765,11 @@ gspm_status gspm_set_field(gspm_ctx *c, gspm_field which, const double *v, int64
             }
             const double r = std::sqrt(*a * *a + *b * *b + *cc * *cc);
             if (!(r > 0.0)) return fail(c, GSPM_E_ARG, "set_field: zero magnetisation on a magnetic node");
-            *a /= r; *b /= r; *cc /= r;
+            // a vector of unit length to rounding (a state read back with get_field) is kept bit for bit,
+            // so a saved state restores exactly
+            if (std::fabs(r - 1.0) > 1e-14) {
+                *a /= r; *b /= r; *cc /= r;
+            }
         }
         rc = upload(c, c->d.m, h);
         if (rc) return static_cast<gspm_status>(rc);
@@ -758,11 +824,11 @@ gspm_status gspm_energies(gspm_ctx *c, double out[7]) {
     hipSetDevice(c->device);
     auto &d = c->d;
     hipStream_t s = c->stream;
-    launch_avg_sums(c->n, d.w, d.m, c->mat, d.sums, s);
+    launch_avg_sums(c->n, d.w, d.m, c->mat, d.sums, s, c->mv.det);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
     launch_fill(d.esums, 5 * kShards, 0.0, s);
     launch_energy_elem(c->mv, c->mat, d.m, d.u, c->p.local_demag ? d.ud : nullptr, &d.der[0], d.esums, s);
-    launch_energy_nodes(c->n, d.w, d.m, c->mat, c->p.hext, d.esums + 2 * kShards, s);
+    launch_energy_nodes(c->n, d.w, d.m, c->mat, c->p.hext, d.esums + 2 * kShards, s, c->mv.det);
     double es[5 * kShards];
     Derived der;
     hipMemcpyAsync(es, d.esums, sizeof es, hipMemcpyDeviceToHost, s);
@@ -801,7 +867,7 @@ gspm_status gspm_demag_local_energy(gspm_ctx *c, double *e) {
     auto &d = c->d;
     hipStream_t s = c->stream;
     // the element pass also needs m, u and the averages; only its potential sum is used here
-    launch_avg_sums(c->n, d.w, d.m, c->mat, d.sums, s);
+    launch_avg_sums(c->n, d.w, d.m, c->mat, d.sums, s, c->mv.det);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
     launch_fill(d.esums, 5 * kShards, 0.0, s);
     launch_energy_elem(c->mv, c->mat, d.m, d.u, d.ud, &d.der[0], d.esums, s);
@@ -820,7 +886,7 @@ gspm_status gspm_averages(gspm_ctx *c, double mbar[3], double ebar[6]) {
     if (!mbar || !ebar) return fail(c, GSPM_E_ARG, "averages: null output");
     if (!c->have_mesh || !c->have_params || !c->have_m) return fail(c, GSPM_E_STATE, "averages need mesh, params and m");
     hipSetDevice(c->device);
-    launch_avg_sums(c->n, c->d.w, c->d.m, c->mat, c->d.sums, c->stream);
+    launch_avg_sums(c->n, c->d.w, c->d.m, c->mat, c->d.sums, c->stream, c->mv.det);
     launch_derive(c->d.sums, c->dargs, &c->d.der[0], c->stream);
     Derived der;
     hipMemcpyAsync(&der, &c->d.der[0], sizeof der, hipMemcpyDeviceToHost, c->stream);

@@ -85,6 +85,19 @@ int assemble_gs_rows(const HostMesh &hm, int64_t ne, const int32_t *tets, const 
 
 // ------------------------------------------------------------- device views
 
+// Fixed-order sums of the deterministic mode.  A producer launch stores the
+// workgroup totals of its sums in slots (sum, workgroup) and workgroup 0
+// records each sum's destination; the finishing launch that follows
+// (launch_det_finish) adds every recorded sum's slots in workgroup order to
+// shard 0 of its destination and clears them.  part == nullptr: atomic adds.
+constexpr int kDetSlots = 16;
+struct DetSums {
+    double *part = nullptr;       // [kDetSlots][max_blocks]
+    double **dst = nullptr;       // [kDetSlots]: destination of each recorded sum (null: skipped)
+    int32_t *count = nullptr;     // sums recorded by the last producer launch
+    int32_t max_blocks = 0;       // workgroups a producer launch may have
+};
+
 // Mesh as the element kernels see it: node coordinates (FP64), and per owner
 // block its element copies as local vertex indices into the block's staged
 // node set [owned range | halo list].
@@ -104,6 +117,11 @@ struct MeshView {
     int32_t n, nb, nblk, p0, nloc_max;
     double Lx, Ly, Lz, iLx, iLy, iLz;   // box edges and their inverses (nearest periodic image)
     double len_scale;                   // cube root of the mean element volume (FP32 non-dimensionalisation)
+    // deterministic mode: fixed-order sums, and per owned node (block-major, nb per block) its element
+    // copies as (copy index within the block's list) << 2 | vertex slot, in copy order
+    DetSums det;
+    const int32_t *inc_ptr;
+    const uint16_t *inc_ent;
 };
 
 // Material constants in the form the kernels use.
@@ -146,6 +164,7 @@ struct CGScalars {
     int32_t *done;                // [comp]: 0 running, 1 converged, 2 broke down (non-finite)
     int32_t *iters;               // [comp]: iterations at convergence
     int32_t ring;
+    DetSums det;                  // deterministic mode: the fixed-order sums (part == nullptr: atomic adds)
 
     __host__ __device__ double *rr_at(int c, int k) const {
         return rr + (static_cast<size_t>(c) * ring + static_cast<size_t>(k % ring)) * kShards;
@@ -240,7 +259,7 @@ void launch_pc_prolong(const GreenView &gv, const MeshView &mv, const T *r, T *z
 template <class T>
 void launch_pcg_update(int n, T *x, T *r, const T *p, const T *q, const CGScalars &cg, int k, hipStream_t s);
 // b -= mean(b) per component; bb (zeroed here) += b.b.  aux: 3 x kShards doubles.
-void launch_remove_mean3(int n, double *b, double *aux, double *bb, hipStream_t s);
+void launch_remove_mean3(int n, double *b, double *aux, double *bb, hipStream_t s, const DetSums &det = DetSums{});
 // x -= x(p0) on every node.  aux: 3 doubles.
 void launch_pin_shift(int n, double *x, int p0, double *aux, hipStream_t s);
 // The symbol inverse of the grid operator for the half spectrum: stencil27 is
@@ -262,7 +281,8 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 
 // Volume-average sums (sharded, 9 x kShards): sum w m (3), sum w E0(m) (6).
 // <E0> is summed in the crystal frame when mat.rot (k_derive rotates it).
-void launch_avg_sums(int n, const double *w, const double *m, const Material &mat, double *sums, hipStream_t s);
+void launch_avg_sums(int n, const double *w, const double *m, const Material &mat, double *sums, hipStream_t s,
+                     const DetSums &det = DetSums{});
 struct DeriveArgs {
     double vc;
     double Nd[9];
@@ -340,7 +360,7 @@ void launch_ms_matvec(const MeshView &mv, int nc, MatvecMode mode, const T *in, 
 void launch_energy_elem(const MeshView &mv, const Material &mat, const double *m, const double *u,
                         const double *ud, const Derived *d, double *out2, hipStream_t s);
 void launch_energy_nodes(int n, const double *w, const double *m, const Material &mat, const double hext[3],
-                         double *out2, hipStream_t s);
+                         double *out2, hipStream_t s, const DetSums &det = DetSums{});
 
 // CG vector kernels on [nc][n] component-major vectors; joint: one set of
 // scalars for all components (the elastic solve), else one per component.
@@ -377,7 +397,9 @@ void launch_fill_f32(float *p, int64_t n, hipStream_t s);
 void launch_update_m12(int n, const double *m, const double *g, double *ms, hipStream_t s);
 void launch_update_m3(int n, const double *m, const double *gs, double *ms, hipStream_t s);
 void launch_normalize(int n, const double *w, const double *mss, const double *mold, double *mnew, double *dm_sum,
-                      int32_t *bad, hipStream_t s);
+                      int32_t *bad, hipStream_t s, const DetSums &det = DetSums{});
+// Deterministic mode: adds the sums the last producer launch recorded (no-op when det.part is null).
+void launch_det_finish(const DetSums &det, hipStream_t s);
 void launch_zero_ring(const CGScalars &cg, int ns, int rr_from, int rr_to, int pq_from, int pq_to, hipStream_t s);
 
 // --------------------------------------------------------------- utilities

@@ -51,6 +51,12 @@ struct DeviceBuffers {
     int32_t *rep = nullptr;       // n: the first caller node of each unique node
     double *cg_rz = nullptr, *cgi_rz = nullptr;   // r . D^-1 r rings of the Jacobi-preconditioned GS solves
     double *cg_rzq = nullptr, *cg_qzq = nullptr, *cgi_rzq = nullptr, *cgi_qzq = nullptr;   // r.D^-1 q, q.D^-1 q rings
+    // deterministic mode: the fixed-order sums' slots and per owned node its element copies (MeshView)
+    double *det_part = nullptr;
+    double **det_dst = nullptr;
+    int32_t *det_count = nullptr;
+    int32_t *inc_ptr = nullptr;
+    uint16_t *inc_ent = nullptr;
     // the GS operator in row form (GsRowsHost): the pattern, K and M (FP64),
     // and per slot the combined coefficients of one (eps, mass) pair in FP64
     // and (mixed contexts) FP32
@@ -109,6 +115,7 @@ struct gspm_ctx {
     int precision = GSPM_FP64;
     int block_nodes = 0;
     int reorder = GSPM_REORDER_MORTON;
+    bool deterministic = false;           // fixed-order sums (gspm_create_opts.deterministic)
     bool profile = false;
     void *(*alloc_fn)(size_t, void *) = nullptr;   // optional device allocator of the caller
     void (*free_fn)(void *, void *) = nullptr;

@@ -114,14 +114,10 @@ __device__ __forceinline__ void tet_geometry_from_edges(const T (&e)[3][3], Geo<
     G.vol = fabs(det) * T(1.0 / 6.0);
 }
 
-// Sum NR per-thread values over the workgroup (wave shuffles, then LDS) and add
-// the totals with one FP64 atomic each to shard (blockIdx.x % kShards) of the
-// sharded scalars dst + k * stride.  Spreading the atomics of thousands of
-// workgroups over kShards addresses keeps them from serialising on one.  All
-// threads of the workgroup call it.
+// Workgroup sums of NR per-thread values: wave shuffles, then per-wave totals
+// in LDS (fixed order).
 template <int NR>
-__device__ __forceinline__ void block_atomic_add(const double (&v)[NR], double *dst, int stride) {
-    __shared__ double red[kThreads / 64][NR];
+__device__ __forceinline__ void block_partials(const double (&v)[NR], double (&red)[kThreads / 64][NR]) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
@@ -131,39 +127,64 @@ __device__ __forceinline__ void block_atomic_add(const double (&v)[NR], double *
         if (lane == 0) red[wv][k] = s;
     }
     __syncthreads();
+}
+
+// The workgroup total s of sum k (thread k) to its destination: an atomic add
+// to shard (blockIdx.x % kShards), or in the deterministic mode a store to
+// the workgroup's slot of sum base + k (workgroup 0 records the destination
+// and how many sums the launch produced).
+__device__ __forceinline__ void sum_out(int k, int nr, double s, double *dst, const DetSums &det, int base) {
+    if (det.part == nullptr) {
+        if (dst != nullptr) unsafeAtomicAdd(dst + (blockIdx.x % kShards), s);
+        return;
+    }
+    // (every launch that adds sums is sized within max_blocks at upload; the test only keeps a
+    // mis-sized launch inside the slot array)
+    if (static_cast<int>(blockIdx.x) < det.max_blocks)
+        det.part[static_cast<size_t>(base + k) * det.max_blocks + blockIdx.x] = s;
+    if (blockIdx.x == 0) {
+        det.dst[base + k] = dst;
+        if (k == 0) *det.count = base + nr;
+    }
+}
+
+// Sum NR per-thread values over the workgroup and add the totals with one FP64
+// atomic each to shard (blockIdx.x % kShards) of the sharded scalars
+// dst + k * stride (deterministic mode: to the workgroup's slots, see sum_out).
+// Spreading the atomics of thousands of workgroups over kShards addresses keeps
+// them from serialising on one.  All threads of the workgroup call it.
+template <int NR>
+__device__ __forceinline__ void block_atomic_add(const double (&v)[NR], double *dst, int stride,
+                                                 const DetSums &det = DetSums{}, int base = 0) {
+    __shared__ double red[kThreads / 64][NR];
+    block_partials<NR>(v, red);
     if (threadIdx.x < NR && dst != nullptr) {
         double s = 0.0;
 #pragma unroll
         for (int w2 = 0; w2 < kThreads / 64; ++w2) s += red[w2][threadIdx.x];
-        unsafeAtomicAdd(dst + threadIdx.x * stride + (blockIdx.x % kShards), s);
+        sum_out(threadIdx.x, NR, s, dst + threadIdx.x * stride, det, base);
     }
 }
 
 // The same with the NR totals going to NR separate sharded scalars (a null
 // destination drops its total).
 template <int NR>
-__device__ __forceinline__ void block_atomic_add_to(const double (&v)[NR], double *const (&dst)[NR]) {
+__device__ __forceinline__ void block_atomic_add_to(const double (&v)[NR], double *const (&dst)[NR],
+                                                    const DetSums &det = DetSums{}, int base = 0) {
     __shared__ double red[kThreads / 64][NR];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        double s = v[k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) red[wv][k] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < NR && dst[threadIdx.x] != nullptr) {
+    block_partials<NR>(v, red);
+    if (threadIdx.x < NR) {
         double s = 0.0;
 #pragma unroll
         for (int w2 = 0; w2 < kThreads / 64; ++w2) s += red[w2][threadIdx.x];
-        unsafeAtomicAdd(dst[threadIdx.x] + (blockIdx.x % kShards), s);
+        sum_out(threadIdx.x, NR, s, dst[threadIdx.x], det, base);
     }
 }
 
-__device__ __forceinline__ void block_atomic_add1(double v, double *dst) {
+__device__ __forceinline__ void block_atomic_add1(double v, double *dst, const DetSums &det = DetSums{},
+                                                  int base = 0) {
     const double a[1] = {v};
-    block_atomic_add<1>(a, dst, 0);
+    block_atomic_add<1>(a, dst, 0, det, base);
 }
 
 // Totals of NR sharded scalars (each kShards consecutive doubles at src[k]),

@@ -113,13 +113,41 @@ __global__ void __launch_bounds__(kThreads) k_elem(const MeshView mv, const Op o
     const int e_beg = mv.blk_ptr[b];
     const int e_mag = e_beg + mv.blk_nmag[b];
     const int e_end = Op::kMagneticOnly ? e_mag : mv.blk_ptr[b + 1];
-    for (int e = e_beg + static_cast<int>(threadIdx.x); e < e_end; e += kThreads) {
-        const ushort4 c = mv.lconn[e];
-        Geo<T> G;
-        stage_geometry(st.sx, st.sy, st.sz, c, img, mv, sc, G);
-        T y[4][NC];
-        op.element(st, c, G, e < e_mag, y);
-        scatter_owned<T, NC>(st.acc, nb, c, y);
+    if (mv.det.part != nullptr) {
+        // deterministic mode: each owned node gathers its element copies in
+        // copy order (each element evaluated once per owned vertex)
+        for (int i = threadIdx.x; i < cnt; i += kThreads) {
+            double acc[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) acc[k] = 0.0;
+            const int t1 = mv.inc_ptr[b * nb + i + 1];
+            for (int t = mv.inc_ptr[b * nb + i]; t < t1; ++t) {
+                const int en = mv.inc_ent[t], e = e_beg + (en >> 2), j = en & 3;
+                if (e >= e_end) break;              // magnetic copies come first
+                const ushort4 c = mv.lconn[e];
+                Geo<T> G;
+                stage_geometry(st.sx, st.sy, st.sz, c, img, mv, sc, G);
+                T y[4][NC];
+                op.element(st, c, G, e < e_mag, y);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (v == j) {
+#pragma unroll
+                        for (int k = 0; k < NC; ++k) acc[k] += static_cast<double>(y[v][k]);
+                    }
+            }
+#pragma unroll
+            for (int k = 0; k < NC; ++k) st.acc[k * nb + i] = acc[k];
+        }
+    } else {
+        for (int e = e_beg + static_cast<int>(threadIdx.x); e < e_end; e += kThreads) {
+            const ushort4 c = mv.lconn[e];
+            Geo<T> G;
+            stage_geometry(st.sx, st.sy, st.sz, c, img, mv, sc, G);
+            T y[4][NC];
+            op.element(st, c, G, e < e_mag, y);
+            scatter_owned<T, NC>(st.acc, nb, c, y);
+        }
     }
     __syncthreads();
     op.finish(mv, st, n0, cnt);
@@ -129,6 +157,7 @@ template <class T, int NC, int NF, class Op>
 static void run_elem(const MeshView &mv, const Op &op, hipStream_t s) {
     const size_t lds = sizeof(double) * NC * static_cast<size_t>(mv.nb) + sizeof(T) * (3 + NF) * static_cast<size_t>(mv.nloc_max);
     hipLaunchKernelGGL((k_elem<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
+    launch_det_finish(mv.det, s);
 }
 
 __global__ void __launch_bounds__(kThreads) k_stage_coords(const MeshView mv, double *stc64, float *stc32) {
@@ -178,14 +207,13 @@ __device__ __forceinline__ const float *staged_coords<float>(const MeshView &mv)
 // window, and only for owned vertices.  Along a strip each element loads one
 // vertex instead of four, which cuts the LDS reads and atomics that bound the
 // element-list form.  Staging and the per-node epilogue are the same.
+// Staging of the matrix-free operators (strip and gather forms): LDS layout,
+// accumulators cleared, the block's precomputed staged coordinates and the
+// operand the op fetches (owned range, then halo list).
 template <class T, int NC, int NF, class Op>
-__global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op op_in) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    Op op = op_in;
-    const int b = xcd_block(blockIdx.x, gridDim.x);
-    if (!op.prepare(mv, b)) return;            // uniform: e.g. every CG component converged
-    const int nb = mv.nb, n0 = b * nb, cnt = min(nb, mv.n - n0);
-    const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg);
+__device__ __forceinline__ Staged<T, NC, NF> stage_operator(const MeshView &mv, const Op &op, unsigned char *smem_raw,
+                                                           int b, int n0, int cnt, int hbeg, int nloc) {
+    const int nb = mv.nb;
     Staged<T, NC, NF> st;
     st.nloc_max = mv.nloc_max;
     st.acc = reinterpret_cast<double *>(smem_raw);
@@ -194,7 +222,6 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
     st.sz = st.sy + mv.nloc_max;
     st.f = st.sz + mv.nloc_max;
     for (int i = threadIdx.x; i < NC * nb; i += kThreads) st.acc[i] = 0.0;
-    const double xr = mv.x[n0], yr = mv.y[n0], zr = mv.z[n0], sc = op.coord_scale;
     // staging, four nodes per thread at a time: all their index loads, then
     // all their data loads, then the LDS stores (the halo gather is a chain of
     // two dependent loads; batching keeps many of them in flight).  The
@@ -202,7 +229,6 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
     // precision and units), only the operand is gathered.
     const T *stc = staged_coords<T>(mv);
     const size_t sbase = static_cast<size_t>(b) * nb + hbeg;
-    (void)xr; (void)yr; (void)zr;
     constexpr int kU = 4;
     for (int l0 = threadIdx.x; l0 < nloc; l0 += kU * kThreads) {
         int ls[kU], gs[kU];
@@ -234,6 +260,19 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
             for (int q = 0; q < NF; ++q) st.fld(q, l) = v[u][q];
         }
     }
+    return st;
+}
+
+template <class T, int NC, int NF, class Op>
+__global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op op_in) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Op op = op_in;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (!op.prepare(mv, b)) return;            // uniform: e.g. every CG component converged
+    const int nb = mv.nb, n0 = b * nb, cnt = min(nb, mv.n - n0);
+    const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg);
+    Staged<T, NC, NF> st = stage_operator<T, NC, NF, Op>(mv, op, smem_raw, b, n0, cnt, hbeg, nloc);
+    const double sc = op.coord_scale;
     __syncthreads();
     const bool img = mv.img[b] != 0;
     const T Lx = static_cast<T>(mv.Lx * sc), Ly = static_cast<T>(mv.Ly * sc), Lz = static_cast<T>(mv.Lz * sc);
@@ -362,9 +401,87 @@ __global__ void __launch_bounds__(kThreads) k_strip(const MeshView mv, const Op 
     op.finish(mv, st, n0, cnt);
 }
 
+// Deterministic mode: the same operator with every owned node gathering the
+// contributions of its element copies (the block's list, in copy order) in
+// registers, so no LDS atomics decide the order of the sums.  Each element is
+// evaluated once per owned vertex.
+template <class T, int NC, int NF, class Op>
+__global__ void __launch_bounds__(kThreads) k_strip_det(const MeshView mv, const Op op_in) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Op op = op_in;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (!op.prepare(mv, b)) return;
+    const int nb = mv.nb, n0 = b * nb, cnt = min(nb, mv.n - n0);
+    const int hbeg = mv.halo_ptr[b], nloc = nb + (mv.halo_ptr[b + 1] - hbeg);
+    Staged<T, NC, NF> st = stage_operator<T, NC, NF, Op>(mv, op, smem_raw, b, n0, cnt, hbeg, nloc);
+    const double sc = op.coord_scale;
+    __syncthreads();
+    const bool img = mv.img[b] != 0;
+    const T Lx = static_cast<T>(mv.Lx * sc), Ly = static_cast<T>(mv.Ly * sc), Lz = static_cast<T>(mv.Lz * sc);
+    const T iLx = static_cast<T>(mv.iLx / sc), iLy = static_cast<T>(mv.iLy / sc), iLz = static_cast<T>(mv.iLz / sc);
+    const int e_beg = mv.blk_ptr[b], e_mag = e_beg + mv.blk_nmag[b];
+    for (int i = threadIdx.x; i < cnt; i += kThreads) {
+        double acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+        const int t1 = mv.inc_ptr[b * nb + i + 1];
+        for (int t = mv.inc_ptr[b * nb + i]; t < t1; ++t) {
+            const int en = mv.inc_ent[t], e = e_beg + (en >> 2), j = en & 3;
+            if (Op::kMagneticOnly && e >= e_mag) break;   // magnetic copies come first
+            const ushort4 cv = mv.lconn[e];
+            const int id[4] = {cv.x, cv.y, cv.z, cv.w};
+            T x[4][3], f[4][NF];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                x[v][0] = st.sx[id[v]];
+                x[v][1] = st.sy[id[v]];
+                x[v][2] = st.sz[id[v]];
+#pragma unroll
+                for (int q = 0; q < NF; ++q) f[v][q] = st.fld(q, id[v]);
+            }
+            T ed[3][3];
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ed[kk][a] = x[kk + 1][a] - x[0][a];
+            if (img) {
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) {
+                    ed[kk][0] = near_image(ed[kk][0], Lx, iLx);
+                    ed[kk][1] = near_image(ed[kk][1], Ly, iLy);
+                    ed[kk][2] = near_image(ed[kk][2], Lz, iLz);
+                }
+            }
+            RawGeo<T> R;
+            tet_raw_geometry(ed, R);
+            T y[4][NC];
+            op.element_raw(f, R, y);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (v == j) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[c] += static_cast<double>(y[v][c]);
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) st.acc[c * nb + i] = acc[c];
+    }
+    __syncthreads();
+    op.finish(mv, st, n0, cnt);
+}
+
 template <class T, int NC, int NF, class Op>
 static void run_strip(const MeshView &mv, const Op &op, hipStream_t s, const hipEvent_t *ev = nullptr) {
     const size_t lds = sizeof(double) * NC * static_cast<size_t>(mv.nb) + sizeof(T) * (3 + NF) * static_cast<size_t>(mv.nloc_max);
+    if (mv.det.part != nullptr) {
+        if (ev)
+            hipExtLaunchKernelGGL((k_strip_det<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, ev[0], ev[1], 0,
+                                  mv, op);
+        else
+            hipLaunchKernelGGL((k_strip_det<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, op);
+        launch_det_finish(mv.det, s);
+        return;
+    }
     if (ev)
         hipExtLaunchKernelGGL((k_strip<T, NC, NF, Op>), dim3(mv.nblk), dim3(kThreads), lds, s, ev[0], ev[1], 0, mv, op);
     else
@@ -557,8 +674,8 @@ struct ElasticMatvecOp {
                 }
             }
         }
-        if (mode == MV_ITER) block_atomic_add1(part, cg.pq_at(0, k));
-        else if (mode == MV_RESID) block_atomic_add1(part, cg.rr_at(0, 0));
+        if (mode == MV_ITER) block_atomic_add1(part, cg.pq_at(0, k), cg.det);
+        else if (mode == MV_RESID) block_atomic_add1(part, cg.rr_at(0, 0), cg.det);
     }
 };
 
@@ -686,7 +803,7 @@ struct ElasticCgOp {
         }
         // r_0.r_0 is already in slot 0 (the residual launch wrote it)
         double *const dst[4] = {cg.pq_at(0, k), cg.rq_at(k), cg.qq_at(k), k == 0 ? nullptr : cg.rr_at(0, k)};
-        block_atomic_add_to<4>(part, dst);
+        block_atomic_add_to<4>(part, dst, cg.det);
     }
 };
 
@@ -746,7 +863,7 @@ struct ElasticPcgOp {
                 part += static_cast<double>(pv) * qv;
             }
         }
-        block_atomic_add1(part, cg.pq_at(0, k));
+        block_atomic_add1(part, cg.pq_at(0, k), cg.det);
     }
 };
 
@@ -818,7 +935,7 @@ struct MsCgOp {
             part[3] += rv * rv;
         }
         double *const dst[4] = {cg.pq_at(0, k), cg.rq_at(k), cg.qq_at(k), k == 0 ? nullptr : cg.rr_at(0, k)};
-        block_atomic_add_to<4>(part, dst);
+        block_atomic_add_to<4>(part, dst, cg.det);
     }
 };
 
@@ -890,7 +1007,7 @@ struct ElasticRhsOp {
                 part += static_cast<double>(v) * v;
             }
         }
-        block_atomic_add1(part, bb);
+        block_atomic_add1(part, bb, mv.det);
     }
 };
 
@@ -992,8 +1109,8 @@ struct MsMatvecOp {
                 }
             }
         }
-        if (mode == MV_ITER) block_atomic_add<NC>(part, cg.pq_at(0, k), cg.comp_stride());
-        else if (mode == MV_RESID) block_atomic_add<NC>(part, cg.rr_at(0, 0), cg.comp_stride());
+        if (mode == MV_ITER) block_atomic_add<NC>(part, cg.pq_at(0, k), cg.comp_stride(), cg.det);
+        else if (mode == MV_RESID) block_atomic_add<NC>(part, cg.rr_at(0, 0), cg.comp_stride(), cg.det);
     }
 };
 
@@ -1046,7 +1163,7 @@ struct MsRhsOp {
             if (pinned) x[node] = T(0);
             part += static_cast<double>(v) * v;
         }
-        block_atomic_add1(part, bb);
+        block_atomic_add1(part, bb, mv.det);
     }
 };
 
@@ -1181,7 +1298,7 @@ struct FieldRhsOp {
                 part[a] += static_cast<double>(bv) * bv;
             }
         }
-        block_atomic_add<3>(part, bb, bbstride);
+        block_atomic_add<3>(part, bb, bbstride, mv.det);
     }
 };
 
@@ -1236,7 +1353,7 @@ struct MassRhsOp {
                 part[q] += static_cast<double>(bv) * bv;
             }
         }
-        block_atomic_add<2>(part, bb, bbstride);
+        block_atomic_add<2>(part, bb, bbstride, mv.det);
     }
 };
 
@@ -1357,8 +1474,8 @@ __global__ void __launch_bounds__(kThreads) k_energy_elem(const MeshView mv, Mat
         }
     }
     const double v2[2] = {ex, me};
-    block_atomic_add<2>(v2, out, kShards);
-    if (ud) block_atomic_add1(dl, out + 4 * kShards);
+    block_atomic_add<2>(v2, out, kShards, mv.det);
+    if (ud) block_atomic_add1(dl, out + 4 * kShards, mv.det, 2);
 }
 
 // --------------------------------------------------------------- launchers
@@ -1548,6 +1665,7 @@ void launch_energy_elem(const MeshView &mv, const Material &mat, const double *m
                         const Derived *d, double *out2, hipStream_t s) {
     const size_t lds = sizeof(double) * (static_cast<size_t>(mv.nb) + 10 * static_cast<size_t>(mv.nloc_max));
     hipLaunchKernelGGL(k_energy_elem<double>, dim3(mv.nblk), dim3(kThreads), lds, s, mv, mat, m, u, ud, d, out2);
+    launch_det_finish(mv.det, s);
 }
 
 }  // namespace gspm

@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(kThreads) k_pc_prolong(GreenView gv, MeshView 
             part += static_cast<double>(rv) * zv;
         }
     }
-    block_atomic_add1(part, rz);
+    block_atomic_add1(part, rz, cg.det);
 }
 
 template <class T>
@@ -223,18 +223,19 @@ __global__ void __launch_bounds__(kThreads) k_pcg_update(int n, T *x, T *r, cons
         r[i] = rv;
         part += static_cast<double>(rv) * rv;
     }
-    block_atomic_add1(part, cg.rr_at(0, k + 1));
+    block_atomic_add1(part, cg.rr_at(0, k + 1), cg.det);
 }
 
-__global__ void __launch_bounds__(kThreads) k_sum3(int n, const double *b, double *aux) {
+__global__ void __launch_bounds__(kThreads) k_sum3(int n, const double *b, double *aux, DetSums det) {
     double acc[3] = {0.0, 0.0, 0.0};
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
 #pragma unroll
         for (int a = 0; a < 3; ++a) acc[a] += b[static_cast<size_t>(a) * n + i];
-    block_atomic_add<3>(acc, aux, kShards);
+    block_atomic_add<3>(acc, aux, kShards, det);
 }
 
-__global__ void __launch_bounds__(kThreads) k_sub_mean3(int n, double *b, const double *aux, double *bb) {
+__global__ void __launch_bounds__(kThreads) k_sub_mean3(int n, double *b, const double *aux, double *bb,
+                                                        DetSums det) {
     const double *const src[3] = {aux, aux + kShards, aux + 2 * kShards};
     double t[3];
     shard_totals<3>(src, t);
@@ -247,7 +248,7 @@ __global__ void __launch_bounds__(kThreads) k_sub_mean3(int n, double *b, const 
             b[o] = v;
             part += v * v;
         }
-    block_atomic_add1(part, bb);
+    block_atomic_add1(part, bb, det);
 }
 
 __global__ void k_pin_copy(int n, const double *x, int p0, double *aux) {
@@ -350,19 +351,23 @@ template <class T>
 void launch_pc_prolong(const GreenView &gv, const MeshView &mv, const T *r, T *z, double *rz, const CGScalars &cg,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_pc_prolong<T>, dim3(grid_of(mv.n)), dim3(kThreads), 0, s, gv, mv, r, z, rz, cg);
+    launch_det_finish(cg.det, s);
 }
 
 template <class T>
 void launch_pcg_update(int n, T *x, T *r, const T *p, const T *q, const CGScalars &cg, int k, hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_update<T>, dim3(reduce_grid_of(3 * static_cast<int64_t>(n))), dim3(kThreads), 0, s, n, x, r, p, q,
                        cg, k);
+    launch_det_finish(cg.det, s);
 }
 
-void launch_remove_mean3(int n, double *b, double *aux, double *bb, hipStream_t s) {
+void launch_remove_mean3(int n, double *b, double *aux, double *bb, hipStream_t s, const DetSums &det) {
     launch_fill(aux, 3 * kShards, 0.0, s);
     launch_fill(bb, kShards, 0.0, s);
-    hipLaunchKernelGGL(k_sum3, dim3(reduce_grid_of(n)), dim3(kThreads), 0, s, n, b, aux);
-    hipLaunchKernelGGL(k_sub_mean3, dim3(reduce_grid_of(n)), dim3(kThreads), 0, s, n, b, aux, bb);
+    hipLaunchKernelGGL(k_sum3, dim3(reduce_grid_of(n)), dim3(kThreads), 0, s, n, b, aux, det);
+    launch_det_finish(det, s);
+    hipLaunchKernelGGL(k_sub_mean3, dim3(reduce_grid_of(n)), dim3(kThreads), 0, s, n, b, aux, bb, det);
+    launch_det_finish(det, s);
 }
 
 void launch_pin_shift(int n, double *x, int p0, double *aux, hipStream_t s) {

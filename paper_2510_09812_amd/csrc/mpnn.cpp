@@ -173,6 +173,8 @@ gspm_status gspm_set_warm_start(gspm_ctx *c, int32_t mode) {
         return nfail(c, GSPM_E_ARG, "unknown warm start");
     if (mode == GSPM_WARM_LEARNED && !c->nn.have_params)
         return nfail(c, GSPM_E_STATE, "learned warm start needs gspm_mpnn_set_params");
+    if (mode != GSPM_WARM_PREVIOUS && c->deterministic)
+        return nfail(c, GSPM_E_STATE, "the learned and extrapolated warm starts are not available in deterministic mode");
     c->warm_mode = mode;
     return GSPM_OK;
 }
@@ -298,7 +300,7 @@ gspm_status gspm_mpnn_warm_start(gspm_ctx *c, const double *m_prev, const double
     hipStream_t s = c->stream;
     const size_t bytes3 = sizeof(double) * 3 * static_cast<size_t>(c->n);
     // the elastic right-hand side at the current m, as the step forms it
-    launch_avg_sums(c->n, d.w, d.m, c->mat, d.sums, s);
+    launch_avg_sums(c->n, d.w, d.m, c->mat, d.sums, s, c->mv.det);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
     hipMemcpyAsync(d.unext, d.u, bytes3, hipMemcpyDeviceToDevice, s);
     cg_prepare(c, 1);

@@ -104,7 +104,7 @@ void launch_set_inner(const CGScalars &cg, const InnerStart &st, hipStream_t s) 
 // With a rotated crystal (App. D) the E0 sums are taken at the crystal-frame
 // m_c = R^T m and k_derive carries their mean back to the sample frame.
 __global__ void __launch_bounds__(kThreads) k_avg_sums(int n, const double *w, const double *m, Material mat,
-                                                       double *sums) {
+                                                       double *sums, DetSums det) {
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const double a = 1.5 * mat.l100, b = 1.5 * mat.l111, third = 1.0 / 3.0;
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
@@ -126,12 +126,14 @@ __global__ void __launch_bounds__(kThreads) k_avg_sums(int n, const double *w, c
         acc[7] += wi * b * m0 * m2;
         acc[8] += wi * b * m0 * m1;
     }
-    block_atomic_add<9>(acc, sums, kShards);
+    block_atomic_add<9>(acc, sums, kShards, det);
 }
 
-void launch_avg_sums(int n, const double *w, const double *m, const Material &mat, double *sums, hipStream_t s) {
+void launch_avg_sums(int n, const double *w, const double *m, const Material &mat, double *sums, hipStream_t s,
+                     const DetSums &det) {
     launch_fill(sums, 9 * kShards, 0.0, s);
-    hipLaunchKernelGGL(k_avg_sums, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, m, mat, sums);
+    hipLaunchKernelGGL(k_avg_sums, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, m, mat, sums, det);
+    launch_det_finish(det, s);
 }
 
 // mbar = sum w m / V_c; Ebar = <E0(m)> + C^-1 sigma_ext (the homogeneous strain
@@ -288,7 +290,8 @@ int launch_averages_noalloc(double *scr, int n, const double *w, const int32_t *
 
 // Anisotropy and Zeeman energies by the vertex rule: sum_j w_j psi(m_j).
 __global__ void __launch_bounds__(kThreads) k_energy_nodes(int n, const double *w, const double *m, Material mat,
-                                                           double h0, double h1, double h2, double *out) {
+                                                           double h0, double h1, double h2, double *out,
+                                                           DetSums det) {
     double acc[2] = {0.0, 0.0};
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
         const double m0 = m[i], m1 = m[n + i], m2 = m[2 * static_cast<size_t>(n) + i];
@@ -300,13 +303,14 @@ __global__ void __launch_bounds__(kThreads) k_energy_nodes(int n, const double *
         acc[0] += w[i] * mat.K1 * (c[0] * c[0] * c[1] * c[1] + c[1] * c[1] * c[2] * c[2] + c[2] * c[2] * c[0] * c[0]);
         acc[1] -= w[i] * mat.mu0Ms * (h0 * m0 + h1 * m1 + h2 * m2);
     }
-    block_atomic_add<2>(acc, out, kShards);
+    block_atomic_add<2>(acc, out, kShards, det);
 }
 
 void launch_energy_nodes(int n, const double *w, const double *m, const Material &mat, const double hext[3],
-                         double *out2, hipStream_t s) {
+                         double *out2, hipStream_t s, const DetSums &det) {
     hipLaunchKernelGGL(k_energy_nodes, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, m, mat, hext[0], hext[1],
-                       hext[2], out2);
+                       hext[2], out2, det);
+    launch_det_finish(det, s);
 }
 
 // ---------------------------------------------------------------------- CG
@@ -416,7 +420,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint
             r[i] = rv;
             part[0] += static_cast<double>(rv) * rv;
         }
-        block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride());
+        block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride(), cg.det);
         return;
     }
     // per component: a scalar head up to the first 16-byte boundary, a body of
@@ -439,7 +443,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int n, int nc, int joint
         for (int v = tid; v < nv; v += nthr) vec(c0 + head + static_cast<size_t>(v) * W, a, part[s]);
         for (int i = head + nv * W + tid; i < n; i += nthr) scalar(i);
     }
-    block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride());
+    block_atomic_add<3>(part, cg.rr_at(0, k + 1), cg.comp_stride(), cg.det);
 }
 
 // Convergence test of rr[k] alone (after the last permitted iteration, when no
@@ -478,6 +482,7 @@ void launch_cg_update(int n, int nc, bool joint, T *x, T *r, const T *p, const T
     const int flat = joint && a16(x) && a16(r) && a16(p) && a16(q) ? 1 : 0;
     hipLaunchKernelGGL(k_cg_update<T>, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, flat, x, r, p, q,
                        cg, k);
+    launch_det_finish(cg.det, s);
 }
 
 template void launch_cg_start<double>(int, int, bool, double *, const CGScalars &, double, hipStream_t);
@@ -520,13 +525,14 @@ __global__ void __launch_bounds__(kThreads) k_to_f32_norms(int n, int nc, int jo
             dst[o] = v;
             part[joint ? 0 : c] += static_cast<double>(v) * v;
         }
-    block_atomic_add<3>(part, cg.rr_at(0, 0), cg.comp_stride());
+    block_atomic_add<3>(part, cg.rr_at(0, 0), cg.comp_stride(), cg.det);
 }
 
 void launch_to_f32_norms(int n, int nc, bool joint, const double *src, double scale, float *dst, const CGScalars &cg,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_to_f32_norms, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, src, scale, dst,
                        cg);
+    launch_det_finish(cg.det, s);
 }
 
 void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s) {
@@ -572,7 +578,7 @@ __global__ void __launch_bounds__(kThreads) k_update_m3(int n, const double *m, 
 // mnew; sums |m^{n+1} - m^n| for the convergence measure of Sec. 3.2; flags a
 // zero or non-finite m**.
 __global__ void __launch_bounds__(kThreads) k_normalize(int n, const double *w, const double *mss, const double *mold,
-                                                        double *mnew, double *dm_sum, int32_t *bad) {
+                                                        double *mnew, double *dm_sum, int32_t *bad, DetSums det) {
     double dsum = 0.0;
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
         const size_t n1 = n, n2 = 2 * static_cast<size_t>(n);
@@ -596,7 +602,7 @@ __global__ void __launch_bounds__(kThreads) k_normalize(int n, const double *w, 
         mnew[n1 + i] = nb;
         mnew[n2 + i] = nc;
     }
-    block_atomic_add1(dsum, dm_sum);
+    block_atomic_add1(dsum, dm_sum, det);
 }
 
 // Zero the ring slots that iterations [rr_from, rr_to) of r.r and
@@ -641,8 +647,41 @@ void launch_update_m3(int n, const double *m, const double *gs, double *ms, hipS
 }
 
 void launch_normalize(int n, const double *w, const double *mss, const double *mold, double *mnew, double *dm_sum,
-                      int32_t *bad, hipStream_t s) {
-    hipLaunchKernelGGL(k_normalize, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, mss, mold, mnew, dm_sum, bad);
+                      int32_t *bad, hipStream_t s, const DetSums &det) {
+    hipLaunchKernelGGL(k_normalize, dim3(node_grid(n)), dim3(kThreads), 0, s, n, w, mss, mold, mnew, dm_sum, bad, det);
+    launch_det_finish(det, s);
+}
+
+// ------------------------------------------------------- deterministic sums
+
+// The recorded sums of the last producer launch: each sum's workgroup slots
+// added in workgroup order (every thread a strided run, then a fixed
+// reduction tree) to shard 0 of its destination, and the slots cleared.
+__global__ void __launch_bounds__(kThreads) k_det_finish(DetSums det) {
+    const int k = blockIdx.x;
+    if (k >= *det.count) return;
+    double *slots = det.part + static_cast<size_t>(k) * det.max_blocks;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < det.max_blocks; b += kThreads) {
+        acc += slots[b];
+        slots[b] = 0.0;
+    }
+    __shared__ double red[kThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w2 = 0; w2 < kThreads / 64; ++w2) t += red[w2];
+        double *d = det.dst[k];
+        if (d != nullptr) d[0] += t;
+    }
+}
+
+void launch_det_finish(const DetSums &det, hipStream_t s) {
+    if (det.part != nullptr) hipLaunchKernelGGL(k_det_finish, dim3(kDetSlots), dim3(kThreads), 0, s, det);
 }
 
 }  // namespace gspm

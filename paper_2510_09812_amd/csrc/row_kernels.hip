@@ -120,13 +120,14 @@ __global__ void __launch_bounds__(kThreads) k_gs_rows(const MeshView mv, const G
             }
         }
     }
-    if (a.mode == MV_RESID) block_atomic_add<NC>(part, a.cg.rr_at(0, 0), a.cg.comp_stride());
+    if (a.mode == MV_RESID) block_atomic_add<NC>(part, a.cg.rr_at(0, 0), a.cg.comp_stride(), a.cg.det);
 }
 
 template <class T, int NC>
 static void run_rows(const MeshView &mv, const GsRowsView &rv, const GsRowArgs<T, NC> &a, hipStream_t s) {
     const size_t lds = sizeof(RowVec<T, NC>) * static_cast<size_t>(mv.nloc_max);
     hipLaunchKernelGGL((k_gs_rows<T, NC>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, rv, a);
+    launch_det_finish(a.cg.det, s);
 }
 
 template <class T>
@@ -465,7 +466,7 @@ __global__ void __launch_bounds__(kThreads) k_gs_rows_cg(const MeshView mv, cons
         dst[3 * NC + q] = on ? a.cg.rzq_at(q, k) : nullptr;
         dst[4 * NC + q] = on ? a.cg.qzq_at(q, k) : nullptr;
     }
-    block_atomic_add_to<5 * NC>(part, dst);
+    block_atomic_add_to<5 * NC>(part, dst, a.cg.det);
 }
 
 template <class T, int NC>
@@ -477,6 +478,7 @@ static void run_rows_cg(const MeshView &mv, const GsRowsView &rv, const GsCgArgs
         hipExtLaunchKernelGGL((k_gs_rows_cg<T, NC>), dim3(mv.nblk), dim3(kThreads), lds, s, ev[0], ev[1], 0, mv, rv, a);
     else
         hipLaunchKernelGGL((k_gs_rows_cg<T, NC>), dim3(mv.nblk), dim3(kThreads), lds, s, mv, rv, a);
+    launch_det_finish(a.cg.det, s);
 }
 
 template <class T>

@@ -311,7 +311,7 @@ CgResult cg_elastic_green(gspm_ctx *c, double *x, double *b, double tol, int max
     hipStream_t s = c->stream;
     MeshView mvu = c->mv;
     mvu.p0 = -1;
-    launch_remove_mean3(c->n, b, c->pc.aux, c->cg.bb_at(0), s);
+    launch_remove_mean3(c->n, b, c->pc.aux, c->cg.bb_at(0), s, c->mv.det);
     auto resid = [&]() {
         launch_elastic_matvec<double>(mvu, c->mat, MV_RESID, x, nullptr, b, c->d.r, nullptr, c->cg, 0, tol, s);
     };
@@ -531,7 +531,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     mark(0);
 
     // volume averages at m^n: far field and homogeneous strain
-    launch_avg_sums(n, d.w, d.m, c->mat, d.sums, s);
+    launch_avg_sums(n, d.w, d.m, c->mat, d.sums, s, c->mv.det);
     launch_derive(d.sums, c->dargs, &d.der[0], s);
     mark(1);
 
@@ -600,7 +600,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     mark(5);
 
     // Step 3: damped solve with h[m*], averages re-evaluated at m*
-    launch_avg_sums(n, d.w, d.ms, c->mat, d.sums, s);
+    launch_avg_sums(n, d.w, d.ms, c->mat, d.sums, s, c->mv.det);
     launch_derive(d.sums, c->dargs, &d.der[1], s);
     mark(6);
     cg_prepare(c, 3);
@@ -614,7 +614,7 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     // Step 4: unit length; the host reads the sum of |dm| and the failure flag
     launch_fill(d.dm, kShards, 0.0, s);
     launch_fill_i32(d.bad, 1, 0, s);
-    launch_normalize(n, d.w, d.g, d.m, d.mnext, d.dm, d.bad, s);
+    launch_normalize(n, d.w, d.g, d.m, d.mnext, d.dm, d.bad, s, c->mv.det);
     ShardSources dms{};
     dms.p[0] = d.dm;
     launch_totals_to_host(dms, 1, c->h_step, s);

@@ -51,7 +51,8 @@ DEV_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class gspm_create_opts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("block_nodes", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("stream", ctypes.c_void_p), ("reorder", ctypes.c_int32),
-                ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN), ("alloc_user", ctypes.c_void_p)]
+                ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN), ("alloc_user", ctypes.c_void_p),
+                ("deterministic", ctypes.c_int32)]
 
 
 class gspm_params(ctypes.Structure):
@@ -171,12 +172,13 @@ def torch_allocator(device: int = 0):
 
 
 def gspm_create(device: int = 0, precision: int = GSPM_FP64, block_nodes: int = 0, profile: bool = False,
-                stream=None, reorder: int = GSPM_REORDER_MORTON, allocator=None):
+                stream=None, reorder: int = GSPM_REORDER_MORTON, allocator=None, deterministic: bool = False):
     """Returns an opaque context handle.  `stream` may be a torch.cuda.Stream
     (the library then runs on it) or a raw hipStream_t integer; `allocator` a
     (dev_alloc, dev_free) pair of C callbacks (see torch_allocator), which the
     caller keeps alive as long as the context."""
     opts = gspm_create_opts(device, precision, block_nodes, 1 if profile else 0, None, reorder)
+    opts.deterministic = 1 if deterministic else 0
     if stream is not None:
         opts.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
     if allocator is not None:
