@@ -53,8 +53,11 @@ def init_params(seed: int) -> np.ndarray:
     return p
 
 
-def trajectory(sim, case, steps: int):
-    """Samples (m^{n-1}, m^n, u^n - u^{n-1}) of `steps` FP64 steps from m0."""
+def trajectory(sim, case, steps: int, target: str = "du"):
+    """Samples (m^{n-1}, m^n, t) of `steps` FP64 steps from m0, t = u^n - u^{n-1}
+    (target "du"), or that minus the previous increment u^{n-1} - u^{n-2}
+    (target "du-e": what the extrapolated start leaves, the part the learned
+    start's second direction cannot supply)."""
     sim.set_m(case.m0)
     sim.set_u(np.zeros_like(case.m0))
     ms, us = [sim.get_m()], []
@@ -62,7 +65,23 @@ def trajectory(sim, case, steps: int):
         sim.step(case.dt, 1)
         us.append(sim.get_u())       # solution at ms[-1]
         ms.append(sim.get_m())
-    return [(ms[k - 1], ms[k], us[k] - us[k - 1]) for k in range(1, steps)]
+    if target == "du":
+        return [(ms[k - 1], ms[k], us[k] - us[k - 1]) for k in range(1, steps)]
+    return [(ms[k - 1], ms[k], (us[k] - us[k - 1]) - (us[k - 1] - us[k - 2])) for k in range(2, steps)]
+
+
+def training_case(seed: int, n: int, vary: bool):
+    """The training family; with vary, 1 to 3 inclusions by seed."""
+    return w.warm_start_training(seed, n=n, inclusions=1 + seed % 3 if vary else 3)
+
+
+def solver_params(case, precond: bool) -> dict:
+    """The case's parameters; with precond both preconditioners (same solutions to the CG tolerance)."""
+    p = dict(case.params)
+    if precond:
+        p["elastic_precond"] = gspm.GSPM_PRECOND_GREEN
+        p["gs_precond"] = gspm.GSPM_PRECOND_JACOBI
+    return p
 
 
 def start_ratios(sim, ms, us):
@@ -89,7 +108,8 @@ def start_ratios(sim, ms, us):
         u_both, _ = sim.mpnn_warm_start(m_prev, u_prev2)
         e = u_prev - u_prev2
         ke = K(e)
-        c = float(np.sum(ke * r0)) / float(np.sum(ke * ke))
+        kk = float(np.sum(ke * ke))
+        c = float(np.sum(ke * r0)) / kk if kk > 0 else 0.0   # (a settled trajectory: no previous increment)
         for key, u0 in (("network", u_net), ("learned", u_both), ("extrapolated", u_prev + c * e)):
             err = u_sol - u0
             kerr = K(err)
@@ -108,7 +128,13 @@ def main() -> int:
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--eval-only", default="", help="evaluate these weights on the held-out mesh, no training")
+    ap.add_argument("--passes", type=int, default=1, help="passes over all training meshes (trajectories regenerated)")
+    ap.add_argument("--target", choices=("du", "du-e"), default="du",
+                    help="training target: the displacement increment, or its change from the previous one")
+    ap.add_argument("--vary-inclusions", action="store_true", help="1 to 3 inclusions per mesh")
+    ap.add_argument("--no-precond", action="store_true", help="generate trajectories with the unpreconditioned solves")
     args = ap.parse_args()
+    precond = not args.no_precond
 
     params = init_params(args.seed)
     if args.eval_only:
@@ -116,25 +142,28 @@ def main() -> int:
     rng = np.random.default_rng(args.seed)
     t0 = time.perf_counter()
     log = {"train_loss": [], "heldout": None}
-    for mi in range(0 if args.eval_only else args.meshes):
-        case = w.warm_start_training(100 + mi, n=args.n)
-        sim = gspm.Simulation(case.mesh, case.params, hext=case.hext)
-        samples = trajectory(sim, case, args.steps)
-        print(f"[train] mesh {mi}: {len(samples)} samples in {time.perf_counter() - t0:.1f} s", flush=True)
-        sim.mpnn_set_params(params)
-        for ep in range(args.epochs):
-            losses = []
-            for k in rng.permutation(len(samples)):
-                mp, m, du = samples[k]
-                losses.append(sim.mpnn_train_step(mp, m, du, lr=args.lr)[0])
-            log["train_loss"].append(float(np.mean(losses)))
-            if ep % 5 == 0 or ep == args.epochs - 1:
-                print(f"[train] mesh {mi} epoch {ep}: mean loss {np.mean(losses):.4e}", flush=True)
-        params = sim.mpnn_get_params()
-        sim.close()
+    n_samples = 0
+    for ps in range(0 if args.eval_only else args.passes):
+        for mi in range(args.meshes):
+            case = training_case(100 + mi, args.n, args.vary_inclusions)
+            sim = gspm.Simulation(case.mesh, solver_params(case, precond), hext=case.hext)
+            samples = trajectory(sim, case, args.steps, args.target)
+            n_samples += len(samples)
+            sim.mpnn_set_params(params)
+            for ep in range(args.epochs):
+                losses = []
+                for k in rng.permutation(len(samples)):
+                    mp, m, du = samples[k]
+                    losses.append(sim.mpnn_train_step(mp, m, du, lr=args.lr)[0])
+                log["train_loss"].append(float(np.mean(losses)))
+            print(f"[train] pass {ps} mesh {mi}: {len(samples)} samples ({n_samples} so far), mean loss "
+                  f"{log['train_loss'][-1]:.4e}, {time.perf_counter() - t0:.1f} s", flush=True)
+            params = sim.mpnn_get_params()
+            sim.close()
+    log["samples"] = n_samples
     # held-out mesh
-    case = w.warm_start_training(100 + args.meshes, n=args.n)
-    sim = gspm.Simulation(case.mesh, case.params, hext=case.hext)
+    case = training_case(100 + args.meshes, args.n, args.vary_inclusions)
+    sim = gspm.Simulation(case.mesh, solver_params(case, precond), hext=case.hext)
     sim.set_m(case.m0)
     sim.set_u(np.zeros_like(case.m0))
     ms, us = [sim.get_m()], []
