@@ -201,6 +201,45 @@ def cpu_baseline(case, single_core_case=None) -> dict:
     return out
 
 
+def run_sweep(case, args) -> int:
+    """The hysteresis protocol of a workload with a field sweep (the 3M-node
+    cube: 41 fields, 200 steps of 10 ps each): the library's sweep driver with
+    no early stop (dm_tol 0, every point runs its full length), one field
+    point per call so that progress is printed.  Prints one JSON line: wall
+    time, node-steps/s over the whole sweep and the mbar loop."""
+    from paper_2510_09812_amd import gspm
+    if case.field_sweep is None:
+        print(json.dumps({"error": f"workload {case.name} has no field sweep"}))
+        return 2
+    params = dict(case.params)
+    params["elastic_precond"] = gspm.GSPM_PRECOND_GREEN
+    params["gs_precond"] = gspm.GSPM_PRECOND_JACOBI
+    t_up = time.perf_counter()
+    sim = gspm.Simulation(case.mesh, params, hext=case.field_sweep[0], precision=gspm.GSPM_MIXED)
+    sim.set_m(case.m0)
+    n = sim.mesh_info()["n_unique"]
+    print(f"[sweep] {case.name}: {n} nodes uploaded in {time.perf_counter() - t_up:.1f} s; "
+          f"{len(case.field_sweep)} fields x {case.steps} steps", file=sys.stderr, flush=True)
+    loop, steps_total = [], 0
+    t0 = time.perf_counter()
+    for k, h in enumerate(case.field_sweep):
+        r = sim.sweep(case.dt, 0.0, case.steps, hext=np.asarray(h)[None, :], keep_going=True)
+        steps_total += int(r["steps"][0])
+        mbar = [float(x) for x in r["mbar"][0]]
+        loop.append({"h_over_ms": float(h[0] / case.material["Ms"]), "mbar": mbar})
+        print(f"[sweep] field {k}: H = {h[0] / case.material['Ms']:+.2f} Ms, mbar_x {mbar[0]:+.4f}, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    sim.close()
+    print(json.dumps({"metric": "hysteresis sweep node-steps/s", "value": n * steps_total / wall,
+                      "unit": "node-steps/s", "wall_s": wall, "steps": steps_total, "n_gpus": 1,
+                      "config": {"workload": case.name, "nodes": n, "fields": len(case.field_sweep),
+                                 "steps_per_field": case.steps, "dt_s": case.dt,
+                                 "path": "mixed+precond", "cg_tol": case.params["cg_tol"]},
+                      "data": "synthetic", "mbar_loop": loop}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +263,9 @@ def main() -> int:
                     help="comma-separated path names to run (for profiling one path), e.g. mixed+precond")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the paths with the Green's-operator preconditioned elastic solve")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the step benchmark, run the workload's hysteresis sweep protocol (every field "
+                         "point for its configured number of steps) on the mixed path with both preconditioners")
     ap.add_argument("--deterministic", action="store_true",
                     help="also run the preconditioned paths in the bitwise-reproducible mode")
     ap.add_argument("--no-local-demag", action="store_true",
@@ -255,6 +297,8 @@ def main() -> int:
         del src
     print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
     case = w.CASES[args.workload]()
+    if args.sweep:
+        return run_sweep(case, args)
 
     weights = None
     if not args.no_learned and os.path.exists(WEIGHTS_FILE):
