@@ -36,16 +36,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GSPM node-steps/s at 1M nodes, mixed vs FP64 at 1e-6 rel err; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_elastic_cg_cube100.json")
 WEIGHTS_FILE = os.path.join(ROOT, "paper_2510_09812_amd", "weights", "warm_start.f32")
 # App. D's rotated frame: the sample axes along the crystal's <111>, <-110>, <11-2>
 R111 = np.array([[1, 1, 1], [-1, 1, 0], [-1, -1, 2]], dtype=np.float64) / np.sqrt([[3.0], [2.0], [6.0]])
-KERNEL_SOURCES = ["paper_2510_09812_amd/csrc/elem_kernels.hip", "paper_2510_09812_amd/csrc/device_common.h"]
+# committed rocprofv3 counter summaries (HBM bytes per launch) and the kernel sources each was taken on
+TRAFFIC = {
+    "elastic": ("profiles/traffic_elastic_cg_cube100.json",
+                ["paper_2510_09812_amd/csrc/elem_kernels.hip", "paper_2510_09812_amd/csrc/device_common.h"]),
+    "gs": ("profiles/traffic_gs_rows_cg_cube100.json",
+           ["paper_2510_09812_amd/csrc/row_kernels.hip", "paper_2510_09812_amd/csrc/device_common.h"]),
+}
 
 
-def kernel_hash() -> str:
+def kernel_hash(family: str) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in TRAFFIC[family][1]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -150,15 +155,16 @@ def step_bytes(n_nodes: int, n_tets: int, mech_iters: float, gs_iters: float, re
     return mech_iters * mech + gs_iters * gs + rhs + nodes + ref
 
 
-def traffic_from_profile(path: str, workload: str = "cube100_ellipsoids"):
-    """HBM bytes per launch of the path's kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources and on this workload."""
+def traffic_from_profile(family: str, path: str, workload: str = "cube100_ellipsoids"):
+    """HBM bytes per launch of a kernel of the family ("elastic", "gs") on the
+    path from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel sources and on this workload."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, TRAFFIC[family][0])) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash() or not t.get("workload", "").startswith(workload + " "):
+    if t.get("kernel_hash") != kernel_hash(family) or not t.get("workload", "").startswith(workload + " "):
         return None
     return t.get(path, {}).get("bytes_per_launch")
 
@@ -307,7 +313,7 @@ def main() -> int:
             weights = None
 
     def run_path(precision: int, warm: int = 0, local_demag: bool = False, rotated: bool = False,
-                 precond: bool = False, deterministic: bool = False) -> dict:
+                 precond: bool = False, deterministic: bool = False, gs_corrected: bool = False) -> dict:
         t_up = time.perf_counter()
         params = dict(case.params)
         if rotated:
@@ -322,11 +328,13 @@ def main() -> int:
         if warm == gspm.GSPM_WARM_LEARNED:
             sim.mpnn_set_params(weights)
         sim.set_warm_start(warm)
+        if gs_corrected:
+            sim.set_gs_start(gspm.GSPM_GS_START_CORRECTED)
         info = sim.mesh_info()
         t_up = time.perf_counter() - t_up
         tag = (f"{'mixed' if precision else 'fp64'}" + {0: "", 1: "+learned", 2: "+extrapolated"}[warm]
                + ("+local_demag" if local_demag else "") + ("+rotated111" if rotated else "")
-               + ("+precond" if precond else ""))
+               + ("+precond" if precond else "") + ("+gscorr" if gs_corrected else ""))
         print(f"[bench] {tag}: uploaded {info['n_unique']} nodes, {info['n_tets']} tets in "
               f"{t_up:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
         if args.warmup:
@@ -368,7 +376,10 @@ def main() -> int:
         specs.append(("mixed+learned", dict(precision=gspm.GSPM_MIXED, warm=gspm.GSPM_WARM_LEARNED)))
     if not args.no_precond:
         specs += [("fp64+precond", dict(precision=gspm.GSPM_FP64, precond=True)),
-                  ("mixed+precond", dict(precision=gspm.GSPM_MIXED, precond=True))]
+                  ("mixed+precond", dict(precision=gspm.GSPM_MIXED, precond=True)),
+                  # GS solves started from the lumped solution plus the last step's correction
+                  ("fp64+precond+gscorr", dict(precision=gspm.GSPM_FP64, precond=True, gs_corrected=True)),
+                  ("mixed+precond+gscorr", dict(precision=gspm.GSPM_MIXED, precond=True, gs_corrected=True))]
         if not args.no_learned:
             specs.append(("mixed+extrapolated+precond", dict(precision=gspm.GSPM_MIXED,
                                                              warm=gspm.GSPM_WARM_EXTRAPOLATE, precond=True)))
@@ -414,7 +425,7 @@ def main() -> int:
                  else next((k for k in ("mixed", "fp64") if k in paths), next(iter(paths))))
     head = paths[head_name]
     mixed = head_name.startswith("mixed")
-    precond = head_name.endswith("+precond")
+    precond = "+precond" in head_name
     info, st, wall, value = head["info"], head["st"], head["wall"], head["value"]
     n, ne = info["n_unique"], info["n_tets"]
     ne_mag = int(np.count_nonzero(case.mesh.tags))
@@ -431,17 +442,18 @@ def main() -> int:
             mb = gs3_iteration_bytes(n, ne_mag, rb, jacobi=precond)
             kname = f"k_gs_rows_cg<{tname},3>" + (" (Jacobi)" if precond else "")
             what = "GS CG iteration launch on three components"
-            traffic = None
+            traffic = traffic_from_profile("gs", ("mixed" if mixed else "fp64") + ("+precond" if precond else ""),
+                                           case.name)
         else:
             launches, tot_ms = pst["matvec_launches"], pst["matvec_ms"]
             if precond:
                 mb = pcg_matvec_bytes(n, ne, rb)
                 kname = f"k_strip<{tname},3,3,ElasticPcgOp>"
-                traffic = None
+                traffic = traffic_from_profile("elastic", ("mixed" if mixed else "fp64") + "+precond", case.name)
             else:
                 mb = cg_iteration_bytes(n, ne, rb)
                 kname = f"k_strip<{tname},3,3,ElasticCgOp>"
-                traffic = traffic_from_profile("mixed" if mixed else "fp64", case.name)
+                traffic = traffic_from_profile("elastic", "mixed" if mixed else "fp64", case.name)
             what = "elastic CG iteration launch"
         avg_s = tot_ms / launches * 1e-3
         achieved = mb / avg_s / 1e9
@@ -471,7 +483,7 @@ def main() -> int:
         if "prof" in p and p["prof"]["gs_matvec_launches"] > 0:
             row["gs3_iteration_launch_us"] = p["prof"]["gs_matvec_ms"] / p["prof"]["gs_matvec_launches"] * 1e3
         ref = "fp64+local_demag" if ld else ("fp64+rotated111" if k.endswith("+rotated111") else "fp64")
-        if k.endswith("+precond"):
+        if "+precond" in k:
             row["ref_note"] = "errors against the unpreconditioned FP64 path"
         if ref in paths and k != ref:
             f = paths[ref]
@@ -486,7 +498,7 @@ def main() -> int:
         t = paths["mixed+local_demag"]["ms_matvec_ms"] * 1e-3
         mb = ms_matvec_bytes(n, ne, 4)
         ms_roofline = {"bound": "hbm", "achieved": mb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": mb / t / 1e9 / HBM_PEAK_GBS, "traffic": traffic_from_profile("ms_mixed", case.name),
+                       "frac": mb / t / 1e9 / HBM_PEAK_GBS, "traffic": traffic_from_profile("elastic", "ms_mixed", case.name),
                        "kernel": "k_strip<float,1,1,MsMatvecOp<float,1>>", "bytes_per_launch": mb,
                        "avg_launch_us": t * 1e6,
                        "timing": "50 device-resident launches of y = K^ms x between HIP events on the library's stream"}
@@ -499,6 +511,8 @@ def main() -> int:
                    "path": head_name, "block_nodes": args.block_nodes or 256,
                    "precond": ("elastic: lattice Green's operator on the auxiliary grid; GS: Jacobi" if precond
                                else "none (the paper's unpreconditioned CG)"),
+                   "gs_start": ("lumped solution + the stage's correction at the last step" if "+gscorr" in head_name
+                                else "lumped solution"),
                    "mech_iters_per_step": mech_per_step, "gs_iters_per_step": gs_per_step},
         "roofline": roofline,
         "step_roofline": {"bytes_per_node_step": b_step / n, "roofline_node_steps_per_s": HBM_PEAK_GBS * 1e9 / b_step * n,

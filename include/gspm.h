@@ -228,6 +228,23 @@ gspm_status gspm_upload_mesh(gspm_ctx *ctx, int64_t n_nodes, const double *xyz, 
  * example to change hext along a hysteresis sweep). */
 gspm_status gspm_set_params(gspm_ctx *ctx, const gspm_params *params);
 
+typedef enum {
+    GSPM_GS_START_LUMPED = 0,    /* the lumped-mass solution of each GS system (the default) */
+    GSPM_GS_START_CORRECTED = 1  /* that start plus the same stage's correction of the previous step */
+} gspm_gs_start;
+
+/* Choose the start vector of the Gauss-Seidel solves of Alg. B.1 (steps 1
+ * and 3).  Each GS system (eps K + M) g = b starts from the lumped solution
+ * g0 = M_L^-1 b' that the right-hand side defines (m + dtau h-terms / w per
+ * node); the corrected start adds d = g - g0 of the same stage at the last
+ * step, so that a solve whose answer moves little from step to step starts
+ * closer to it.  Only the start changes: every solve still stops at cg_tol.
+ * The correction is kept per stage from the second step on and dropped by
+ * gspm_set_field(M), by a failed solve and by a new mesh.  Not available in
+ * deterministic mode (GSPM_E_STATE): a restored state would lack it.  Uses
+ * 11 doubles per node of device memory (allocated with the mesh). */
+gspm_status gspm_set_gs_start(gspm_ctx *ctx, int32_t mode);
+
 /* Set or read a nodal field (n_nodes x 3, caller's order; GSPM_FIELD_UD:
  * n_nodes values).  Setting M normalises m on magnetic nodes (a vector whose
  * length is 1 to within 1e-14 is kept as given, so a state read with

@@ -236,6 +236,7 @@ void gspm_ctx::release_mesh() {
     dev_free(this, b.q32b);
     dev_free(this, b.cgi_rr); dev_free(this, b.cgi_pq); dev_free(this, b.cgi_bb); dev_free(this, b.cgi_rq); dev_free(this, b.cgi_qq);
     dev_free(this, b.cgi_flags);
+    dev_free(this, b.gcorr); dev_free(this, b.gstart);
     dev_free(this, b.mprev); dev_free(this, b.uprev); dev_free(this, b.du_prev); dev_free(this, b.kdu); dev_free(this, b.wred); dev_free(this, b.wcoef);
     dev_free(this, b.ud); dev_free(this, b.udnext); dev_free(this, b.rep);
     dev_free(this, b.cg_rz); dev_free(this, b.cgi_rz);
@@ -253,6 +254,7 @@ void gspm_ctx::release_mesh() {
     arena = nullptr;
     arena_size = arena_used = 0;
     have_mesh = have_m = have_prev = false;
+    gcorr_ok = 0;
     commits = 0;
     tets_int.clear();
     release_nn();
@@ -450,8 +452,9 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
         rc = rc ? rc : dev_alloc(c, &d.seg_ptr, hm.seg_ptr.size());
         rc = rc ? rc : dev_alloc(c, &d.seg_nmag, hm.seg_nmag.size());
         for (double **p : {&d.m, &d.mnext, &d.u, &d.unext, &d.ms, &d.g, &d.gs, &d.b, &d.r, &d.p, &d.p2, &d.q, &d.r2, &d.q2,
-                            &d.mprev, &d.uprev, &d.du_prev, &d.kdu})
+                            &d.mprev, &d.uprev, &d.du_prev, &d.kdu, &d.gstart})
             rc = rc ? rc : dev_alloc(c, p, n3);
+        rc = rc ? rc : dev_alloc(c, &d.gcorr, 8 * static_cast<size_t>(n));
         rc = rc ? rc : dev_alloc(c, &d.ud, n);
         rc = rc ? rc : dev_alloc(c, &d.udnext, n);
         rc = rc ? rc : dev_alloc(c, &d.rep, n);
@@ -666,6 +669,17 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     return GSPM_OK;
 }
 
+gspm_status gspm_set_gs_start(gspm_ctx *c, int32_t mode) {
+    if (!c) return GSPM_E_ARG;
+    if (mode != GSPM_GS_START_LUMPED && mode != GSPM_GS_START_CORRECTED)
+        return fail(c, GSPM_E_ARG, "set_gs_start: unknown mode");
+    if (mode == GSPM_GS_START_CORRECTED && c->deterministic)
+        return fail(c, GSPM_E_STATE, "the corrected GS start is not available in deterministic mode");
+    if (mode != c->gs_start) c->gcorr_ok = 0;
+    c->gs_start = mode;
+    return GSPM_OK;
+}
+
 gspm_status gspm_set_params(gspm_ctx *c, const gspm_params *p) {
     if (!c) return GSPM_E_ARG;
     if (!p) return fail(c, GSPM_E_ARG, "set_params: null params");
@@ -775,6 +789,7 @@ gspm_status gspm_set_field(gspm_ctx *c, gspm_field which, const double *v, int64
         if (rc) return static_cast<gspm_status>(rc);
         c->have_m = true;
         c->have_prev = false;     // a new state has no history for the warm starts
+        c->gcorr_ok = 0;
         c->commits = 0;
     } else {
         rc = upload(c, c->d.u, h);

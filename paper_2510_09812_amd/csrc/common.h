@@ -279,6 +279,12 @@ void launch_elastic_pcg(const MeshView &mv, const Material &mat, int k, const T 
 void launch_fill(double *p, int64_t n, double v, hipStream_t s);
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 
+// The corrected start of a GS solve: x0 += corr (when use) and start = x0;
+// after the solve corr = (use ? corr : 0) + x - start, the solution minus the
+// lumped start, for the next step's solve of the same stage.
+void launch_gs_start(int64_t n, double *x, const double *corr, double *start, bool use, hipStream_t s);
+void launch_gs_correction(int64_t n, const double *x, const double *start, double *corr, bool use, hipStream_t s);
+
 // Volume-average sums (sharded, 9 x kShards): sum w m (3), sum w E0(m) (6).
 // <E0> is summed in the crystal frame when mat.rot (k_derive rotates it).
 void launch_avg_sums(int n, const double *w, const double *m, const Material &mat, double *sums, hipStream_t s,

@@ -13,6 +13,10 @@ namespace gspm {
 // sizes the first batch of iterations launched before polling.
 enum SolveKind { SK_MECH = 0, SK_GS1 = 1, SK_GS2 = 2, SK_GS3 = 3, SK_OTHER = 4, SK_MS = 5, SK_COUNT = 6 };
 
+// offsets (in n) of the GS stages' corrections in DeviceBuffers::gcorr: three,
+// two and three components
+constexpr int kGcorrOff[3] = {0, 3, 5};
+
 struct DeviceBuffers {
     double *x = nullptr;          // 3n coordinates
     ushort4 *lconn = nullptr;
@@ -43,6 +47,9 @@ struct DeviceBuffers {
     int32_t *cgi_flags = nullptr;
     double *mprev = nullptr;      // 3n: m^{n-1} (previous committed state), for the learned warm start
     double *uprev = nullptr;      // 3n: u^{n-2}, for the previous displacement increment
+    double *gcorr = nullptr;      // 8n: the last step's GS corrections (solution - lumped start): stages 1, 2, 3
+                                  // at kGcorrOff[stage] * n
+    double *gstart = nullptr;     // 3n: the start of the running GS solve
     double *du_prev = nullptr;    // 3n: u^{n-1} - u^{n-2} (warm start scratch)
     double *kdu = nullptr;        // 3n: K (u^{n-1} - u^{n-2}) (warm start scratch)
     double *wred = nullptr;       // kMrSums x kShards: minimum-residual sums
@@ -169,6 +176,8 @@ struct gspm_ctx {
     // learned warm start
     gspm::MpnnState nn;
     int warm_mode = GSPM_WARM_PREVIOUS;
+    int gs_start = GSPM_GS_START_LUMPED;
+    unsigned gcorr_ok = 0;                // bit s: d.gcorr holds GS stage s's last correction
     bool have_prev = false;               // d.mprev holds the state before the last committed step
     int commits = 0;                      // steps committed since the last set_field (u^{n-2} valid from 2)
     std::vector<int32_t> tets_int;        // 4 x ne internal node ids (graph construction)

@@ -50,6 +50,36 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(node_grid(n)), dim3(kThreads), 0, s, p, n, v);
 }
 
+// ------------------------------------------------- corrected GS start vector
+
+// x0 <- x0 + corr (the last step's correction, when `use`), start <- x0
+__global__ void __launch_bounds__(kThreads) k_gs_start(int64_t n, double *x, const double *corr, double *start,
+                                                       int use) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads) {
+        const double v = use ? x[i] + corr[i] : x[i];
+        x[i] = v;
+        start[i] = v;
+    }
+}
+
+// corr <- corr + x - start: the solution minus the lumped start
+__global__ void __launch_bounds__(kThreads) k_gs_correction(int64_t n, const double *x, const double *start,
+                                                            double *corr, int use) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        corr[i] = (use ? corr[i] : 0.0) + (x[i] - start[i]);
+}
+
+void launch_gs_start(int64_t n, double *x, const double *corr, double *start, bool use, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_gs_start, dim3(node_grid(n)), dim3(kThreads), 0, s, n, x, corr, start, use ? 1 : 0);
+}
+
+void launch_gs_correction(int64_t n, const double *x, const double *start, double *corr, bool use, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_gs_correction, dim3(node_grid(n)), dim3(kThreads), 0, s, n, x, start, corr, use ? 1 : 0);
+}
+
 // ------------------------------------------------ host-visible small values
 
 // Small results the host polls are written straight into its pinned memory

@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(kThreads) k_gs_rows_cg(const MeshView mv, cons
     constexpr int kNS = 6 * NC;                 // sums read per launch: rr pq rz rzq qzq bb per component
     constexpr int kSh = (kNS * kShards + kThreads - 1) / kThreads;
     constexpr int kU = 2;                       // halo nodes per thread per batch
-    constexpr int kE = 8;                       // row entries per batch
+    constexpr int kE = (sizeof(T) == 4 && NC == 3) ? 16 : 8;   // row entries per batch (prefetch fits the VGPR budget of 4 waves/SIMD)
     __shared__ int32_t sflags[NC];
     __shared__ double sred[kNS * kShards];
     __shared__ double stot[kNS];
@@ -237,15 +237,17 @@ __global__ void __launch_bounds__(kThreads) k_gs_rows_cg(const MeshView mv, cons
         }
     }
     // owned node tid (the first of the thread's owned nodes); the loads are
-    // unconditional so they stay in flight together (unused values: converged
-    // components, and q, p, x at k = 0)
+    // unconditional so they stay in flight together (unused values: q, p, x
+    // at k = 0).  A component that converged in an earlier launch reads
+    // element 0 on every lane (one cached line) instead of its vectors.
     const bool has_own = tid < cnt;
     const int go = n0 + (has_own ? tid : 0);
+    auto at = [&](int q, int node) -> size_t { return live[q] ? static_cast<size_t>(q) * n + node : 0; };
     T orr[NC], oq[NC], op[NC], ox[NC];
     const T od = D[go];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-        const size_t o = static_cast<size_t>(q) * n + go;
+        const size_t o = at(q, go);
         orr[q] = a.rin[o];
         oq[q] = a.qin[o];
         op[q] = a.pin[o];
@@ -274,7 +276,7 @@ __global__ void __launch_bounds__(kThreads) k_gs_rows_cg(const MeshView mv, cons
         hd[u] = D[gs[u]];
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-            const size_t o = static_cast<size_t>(q) * n + gs[u];
+            const size_t o = at(q, gs[u]);
             hr[u][q] = a.rin[o];
             hq[u][q] = a.qin[o];
             hp[u][q] = a.pin[o];
@@ -374,7 +376,7 @@ __global__ void __launch_bounds__(kThreads) k_gs_rows_cg(const MeshView mv, cons
         const T d = D[n0 + i];
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-            const size_t o = static_cast<size_t>(q) * n + n0 + i;
+            const size_t o = at(q, n0 + i);
             r[q] = a.rin[o];
             qv[q] = a.qin[o];
             pv[q] = a.pin[o];
@@ -395,7 +397,7 @@ __global__ void __launch_bounds__(kThreads) k_gs_rows_cg(const MeshView mv, cons
         const T d = D[g];
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
-            const size_t o = static_cast<size_t>(q) * n + g;
+            const size_t o = at(q, g);
             r[q] = a.rin[o];
             qv[q] = a.qin[o];
             pv[q] = a.pin[o];

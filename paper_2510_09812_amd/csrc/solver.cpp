@@ -50,9 +50,13 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
     const int cap = cg.ring - 2;
     int &pred = c->predict[kind][c->refine_slot];
     const int first = std::min(std::max(pred + 1, 2), cap);
-    // batches of costly iterations stay short: each queued iteration that
-    // runs past convergence still costs its library FFTs
-    const int later = c->heavy_iter ? 2 : std::min(std::max(pred / 32, 4), std::min(cap, 32));
+    // Costly iterations are not queued ahead: each launch group that runs
+    // past convergence still costs its library FFTs (about 80 us, a third of
+    // a working iteration), more than the device idles while the host reads
+    // the flags.  Their solves enqueue the predicted count plus the testing
+    // launch, wait, and go on one iteration at a time.
+    const bool ahead = !c->heavy_iter;
+    const int later = c->heavy_iter ? 1 : std::min(std::max(pred / 32, 4), std::min(cap, 32));
     int k = 0;
     auto enqueue = [&](int cnt) {
         const int k1 = std::min(k + cnt, maxit);
@@ -70,7 +74,7 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
     int pending = 0, next = 1;
     for (;;) {
         const bool more = k < maxit;
-        if (more) {
+        if (more && ahead) {
             enqueue(later);
             post(next);
         }
@@ -103,6 +107,12 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
             c->err = "CG did not converge within cg_maxit iterations";
             for (int q = 0; q < ns; ++q) res.iters[q] = f[q] ? f[kMaxComp + q] : maxit;
             return res;
+        }
+        if (!ahead) {
+            // the flags just read are consumed: their slot takes the next batch
+            enqueue(later);
+            post(pending);
+            continue;
         }
         pending = next;
         next ^= 1;
@@ -574,12 +584,33 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     mark(3);
     const double inv_ms = 1.0 / c->p.Ms;
 
+    // GS starts: the lumped solution the right-hand side kernels write, plus,
+    // with the corrected start, the same stage's correction of the last step
+    const bool corrected = c->gs_start == GSPM_GS_START_CORRECTED;
+    auto gs_begin = [&](double *x, int nc, int stage) {
+        if (!corrected) return;
+        launch_gs_start(static_cast<int64_t>(nc) * n, x, d.gcorr + kGcorrOff[stage] * static_cast<int64_t>(n),
+                        d.gstart, (c->gcorr_ok >> stage) & 1u, s);
+    };
+    auto gs_end = [&](const double *x, int nc, int stage, const CgResult &res) {
+        if (!corrected) return;
+        if (res.status) {
+            c->gcorr_ok &= ~(1u << stage);
+            return;
+        }
+        launch_gs_correction(static_cast<int64_t>(nc) * n, x, d.gstart,
+                             d.gcorr + kGcorrOff[stage] * static_cast<int64_t>(n), (c->gcorr_ok >> stage) & 1u, s);
+        c->gcorr_ok |= 1u << stage;
+    };
+
     if (c->p.precession) {
         // Step 1: g^n, three components
         cg_prepare(c, 3);
         launch_field_rhs(c->mv, c->mat, d.m, d.unext, &d.der[0], dtau, d.b, d.g, d.ch2, c->cg.bb, kShards, ud,
                          inv_ms, s);
+        gs_begin(d.g, 3, 0);
         r = cg_gs(c, 3, eps1, d.g, d.b, tol, maxit, SK_GS1);
+        gs_end(d.g, 3, 0, r);
         for (int q = 0; q < 3; ++q) st->gs_iters_stage[q] += r.iters[q];
         if (r.status) return r.status;
         mark(4);
@@ -588,7 +619,9 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
         // Step 1: g* for components 1 and 2 with h[m^n]
         cg_prepare(c, 2);
         launch_mass_rhs(c->mv, d.ms, d.ch2, d.b, d.gs, c->cg.bb, kShards, s);
+        gs_begin(d.gs, 2, 1);
         r = cg_gs(c, 2, eps1, d.gs, d.b, tol, maxit, SK_GS2);
+        gs_end(d.gs, 2, 1, r);
         for (int q = 0; q < 2; ++q) st->gs_iters_stage[3 + q] += r.iters[q];
         if (r.status) return r.status;
         // Step 2, row 3
@@ -606,7 +639,9 @@ int one_step(gspm_ctx *c, double dtau, double eps1, double eps3, gspm_step_stats
     cg_prepare(c, 3);
     launch_field_rhs(c->mv, c->mat, d.ms, d.unext, &d.der[1], c->p.alpha * dtau, d.b, d.g, nullptr, c->cg.bb,
                      kShards, ud, inv_ms, s);
+    gs_begin(d.g, 3, 2);
     r = cg_gs(c, 3, eps3, d.g, d.b, tol, maxit, SK_GS3);
+    gs_end(d.g, 3, 2, r);
     for (int q = 0; q < 3; ++q) st->gs_iters_stage[5 + q] += r.iters[q];
     if (r.status) return r.status;
     mark(7);

@@ -23,6 +23,7 @@ GSPM_OP_LAPLACE, GSPM_OP_MASS, GSPM_OP_GS, GSPM_OP_ELASTIC, GSPM_OP_MS, GSPM_OP_
 GSPM_PRECOND_NONE, GSPM_PRECOND_GREEN, GSPM_PRECOND_JACOBI = 0, 1, 2
 GSPM_PERIODIC = 1
 GSPM_WARM_PREVIOUS, GSPM_WARM_LEARNED, GSPM_WARM_EXTRAPOLATE = 0, 1, 2
+GSPM_GS_START_LUMPED, GSPM_GS_START_CORRECTED = 0, 1
 GSPM_SWEEP_STOP_ON_REVERSAL, GSPM_SWEEP_CONTINUE = 1, 2
 GSPM_REORDER_MORTON, GSPM_REORDER_NONE, GSPM_REORDER_RCM = 0, 1, 2
 GSPM_MPNN_PARAMS = 50819
@@ -35,7 +36,7 @@ EXPORTS = ("gspm_create", "gspm_destroy", "gspm_upload_mesh", "gspm_set_params",
            "gspm_mesh_info", "gspm_demag_factors", "gspm_time_operator", "gspm_last_error",
            "gspm_set_warm_start", "gspm_mpnn_set_params", "gspm_mpnn_get_params", "gspm_mpnn_forward",
            "gspm_mpnn_train_step", "gspm_mpnn_warm_start", "gspm_set_profile", "gspm_relax", "gspm_sweep",
-           "gspm_demag_local_energy", "gspm_averages_noalloc")
+           "gspm_demag_local_energy", "gspm_averages_noalloc", "gspm_set_gs_start")
 
 
 class GspmError(RuntimeError):
@@ -124,6 +125,7 @@ def load() -> ctypes.CDLL:
     lib.gspm_last_error.argtypes = [P]; lib.gspm_last_error.restype = ctypes.c_char_p
     fp = ctypes.POINTER(ctypes.c_float)
     lib.gspm_set_warm_start.argtypes = [P, ctypes.c_int32]; lib.gspm_set_warm_start.restype = S
+    lib.gspm_set_gs_start.argtypes = [P, ctypes.c_int32]; lib.gspm_set_gs_start.restype = S
     lib.gspm_set_profile.argtypes = [P, ctypes.c_int32]; lib.gspm_set_profile.restype = S
     lib.gspm_mpnn_set_params.argtypes = [P, fp, i64]; lib.gspm_mpnn_set_params.restype = S
     lib.gspm_mpnn_get_params.argtypes = [P, fp, i64]; lib.gspm_mpnn_get_params.restype = S
@@ -391,6 +393,10 @@ def gspm_set_warm_start(ctx, mode: int) -> None:
     _check(ctx, load().gspm_set_warm_start(ctx, mode))
 
 
+def gspm_set_gs_start(ctx, mode: int) -> None:
+    _check(ctx, load().gspm_set_gs_start(ctx, mode))
+
+
 def gspm_mpnn_set_params(ctx, params) -> None:
     p = _f32(params, GSPM_MPNN_PARAMS)
     _check(ctx, load().gspm_mpnn_set_params(ctx, _fp(p), p.size))
@@ -505,6 +511,9 @@ class Simulation:
 
     def set_warm_start(self, mode: int):
         gspm_set_warm_start(self.ctx, mode)
+
+    def set_gs_start(self, mode: int):
+        gspm_set_gs_start(self.ctx, mode)
 
     def mpnn_set_params(self, params):
         gspm_mpnn_set_params(self.ctx, params)

@@ -6,6 +6,7 @@ import os
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -44,21 +45,23 @@ def test_step_bytes_in_both_precisions():
     assert bench.step_bytes(n, ne, 150, 40, 4) < bench.step_bytes(n, ne, 150, 40, 8)
 
 
-def test_traffic_is_tied_to_sources_and_workload(tmp_path, monkeypatch):
-    with open(bench.TRAFFIC_FILE) as f:
+@pytest.mark.parametrize("family,path", [("elastic", "mixed"), ("gs", "mixed+precond")])
+def test_traffic_is_tied_to_sources_and_workload(tmp_path, monkeypatch, family, path):
+    rel, sources = bench.TRAFFIC[family]
+    with open(os.path.join(bench.ROOT, rel)) as f:
         t = json.load(f)
     assert t["workload"].startswith("cube100_ellipsoids ")
+    current = t["kernel_hash"] == bench.kernel_hash(family)
     fake = dict(t)
-    path = tmp_path / "traffic.json"
-    path.write_text(json.dumps(fake))
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
-    current = fake["kernel_hash"] == bench.kernel_hash()
-    got = bench.traffic_from_profile("mixed")
-    assert (got == fake["mixed"]["bytes_per_launch"]) if current else got is None
-    assert bench.traffic_from_profile("mixed", "cube144_ellipsoids") is None
+    tmp = tmp_path / "traffic.json"
+    tmp.write_text(json.dumps(fake))
+    monkeypatch.setitem(bench.TRAFFIC, family, (str(tmp), sources))
+    got = bench.traffic_from_profile(family, path)
+    assert (got == fake[path]["bytes_per_launch"]) if current else got is None
+    assert bench.traffic_from_profile(family, path, "cube144_ellipsoids") is None
     fake["kernel_hash"] = "0" * 16
-    path.write_text(json.dumps(fake))
-    assert bench.traffic_from_profile("mixed") is None
+    tmp.write_text(json.dumps(fake))
+    assert bench.traffic_from_profile(family, path) is None
 
 
 def test_rotation_of_the_bench_path_is_app_d_frame():
