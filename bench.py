@@ -223,6 +223,9 @@ def run_sweep(case, args) -> int:
     t_up = time.perf_counter()
     sim = gspm.Simulation(case.mesh, params, hext=case.field_sweep[0], precision=gspm.GSPM_MIXED)
     sim.set_m(case.m0)
+    if args.gs_corrected:
+        sim.set_gs_start(gspm.GSPM_GS_START_CORRECTED)
+    path = "mixed+precond" + ("+gscorr" if args.gs_corrected else "")
     n = sim.mesh_info()["n_unique"]
     print(f"[sweep] {case.name}: {n} nodes uploaded in {time.perf_counter() - t_up:.1f} s; "
           f"{len(case.field_sweep)} fields x {case.steps} steps", file=sys.stderr, flush=True)
@@ -241,8 +244,63 @@ def run_sweep(case, args) -> int:
                       "unit": "node-steps/s", "wall_s": wall, "steps": steps_total, "n_gpus": 1,
                       "config": {"workload": case.name, "nodes": n, "fields": len(case.field_sweep),
                                  "steps_per_field": case.steps, "dt_s": case.dt,
-                                 "path": "mixed+precond", "cg_tol": case.params["cg_tol"]},
+                                 "path": path, "cg_tol": case.params["cg_tol"]},
                       "data": "synthetic", "mbar_loop": loop}))
+    return 0
+
+
+def trajectory(case, gs_corrected: bool, log: str = "trajectory") -> dict:
+    """The workload's configured trajectory (the 1M-node cube: 500 steps of
+    10 ps from the noisy start) on the mixed path with both preconditioners,
+    in windows of 50 steps: node-steps/s over the whole run, and per window
+    the time and the elastic and GS iterations per step."""
+    import torch
+
+    from paper_2510_09812_amd import gspm
+    params = dict(case.params)
+    params["elastic_precond"] = gspm.GSPM_PRECOND_GREEN
+    params["gs_precond"] = gspm.GSPM_PRECOND_JACOBI
+    t_up = time.perf_counter()
+    sim = gspm.Simulation(case.mesh, params, hext=case.hext, precision=gspm.GSPM_MIXED)
+    sim.set_m(case.m0)
+    if gs_corrected:
+        sim.set_gs_start(gspm.GSPM_GS_START_CORRECTED)
+    n = sim.mesh_info()["n_unique"]
+    path = "mixed+precond" + ("+gscorr" if gs_corrected else "")
+    print(f"[{log}] {case.name}: {n} nodes uploaded in {time.perf_counter() - t_up:.1f} s; "
+          f"{case.steps} steps on {path}", file=sys.stderr, flush=True)
+    win = 50
+    windows, done = [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while done < case.steps:
+        k = min(win, case.steps - done)
+        t1 = time.perf_counter()
+        st = sim.step(case.dt, k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        done += k
+        mbar = [float(x) for x in sim.averages()[0]]
+        windows.append({"steps": [done - k, done], "ms_per_step": dt / k * 1e3,
+                        "mech_iters_per_step": st["mech_iters"] / k, "gs_iters_per_step": st["gs_iters"] / k,
+                        "dm_avg_last": st["dm_avg"], "mbar": mbar})
+        print(f"[{log}] {path} steps {done - k}-{done}: {dt / k * 1e3:.2f} ms/step, elastic "
+              f"{st['mech_iters'] / k:.1f}, GS {st['gs_iters'] / k:.1f} iterations per step, dm_avg {st['dm_avg']:.2e}",
+              file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    sim.close()
+    return {"path": path, "value": n * done / wall, "unit": "node-steps/s", "wall_s": wall, "steps": done,
+            "windows": windows}
+
+
+def run_trajectory(case, args) -> int:
+    """Trajectory mode: one JSON line for the configured trajectory."""
+    t = trajectory(case, args.gs_corrected)
+    print(json.dumps({"metric": "GSPM node-steps/s over the configured trajectory", "value": t["value"],
+                      "unit": "node-steps/s", "wall_s": t["wall_s"], "steps": t["steps"], "n_gpus": 1,
+                      "config": {"workload": case.name, "dt_s": case.dt, "path": t["path"],
+                                 "cg_tol": case.params["cg_tol"]},
+                      "data": "synthetic", "windows": t["windows"]}))
     return 0
 
 
@@ -269,6 +327,13 @@ def main() -> int:
                     help="comma-separated path names to run (for profiling one path), e.g. mixed+precond")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the paths with the Green's-operator preconditioned elastic solve")
+    ap.add_argument("--trajectory", action="store_true",
+                    help="instead of the step benchmark, run the workload's configured number of steps in windows")
+    ap.add_argument("--no-trajectory", action="store_true",
+                    help="skip the run of the whole configured trajectory that the default output carries")
+    ap.add_argument("--gs-corrected", action="store_true",
+                    help="trajectory and sweep modes: start the GS solves from the lumped solution plus the last "
+                         "correction")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the step benchmark, run the workload's hysteresis sweep protocol (every field "
                          "point for its configured number of steps) on the mixed path with both preconditioners")
@@ -305,6 +370,8 @@ def main() -> int:
     case = w.CASES[args.workload]()
     if args.sweep:
         return run_sweep(case, args)
+    if args.trajectory:
+        return run_trajectory(case, args)
 
     weights = None
     if not args.no_learned and os.path.exists(WEIGHTS_FILE):
@@ -527,6 +594,10 @@ def main() -> int:
         "phase_ms_per_step": ({k: v / args.profile_steps for k, v in pst["phase_ms"].items()} if pst else None),
         "final_residual": st["final_residual"],
     }
+    if not args.no_trajectory and not args.no_precond and case.steps > args.warmup + args.steps:
+        # the whole configured trajectory beside the timed window (which lies in its transient)
+        out["trajectory"] = {t["path"]: {k: v for k, v in t.items() if k != "path"}
+                             for t in (trajectory(case, False, "bench"), trajectory(case, True, "bench"))}
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, None if args.no_single_core else w.cube47_sphere())
