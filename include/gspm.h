@@ -117,10 +117,11 @@ typedef struct {
     int32_t deterministic;  /* nonzero: bitwise reproducible steps (same device, mesh, block size and inputs
                                give the same bits, whether run at once or split by a save and restore of M
                                and U).  Every sum is added in a fixed order: workgroup totals go to slots
-                               that a follow-up launch adds in workgroup order (no atomic adds), and the
+                               that a follow-up launch adds in a fixed order (no atomic adds), and the
                                element passes gather each owned node's elements in a fixed order (no LDS
                                atomics; each element is evaluated once per owned vertex).  Slower; the
-                               learned and extrapolated warm starts are not available (GSPM_E_STATE). */
+                               learned and extrapolated warm starts and the corrected GS start are not
+                               available (GSPM_E_STATE). */
 } gspm_create_opts;
 
 typedef enum { GSPM_REORDER_MORTON = 0, GSPM_REORDER_NONE = 1, GSPM_REORDER_RCM = 2 } gspm_reorder;

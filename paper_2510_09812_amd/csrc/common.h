@@ -88,7 +88,7 @@ int assemble_gs_rows(const HostMesh &hm, int64_t ne, const int32_t *tets, const 
 // Fixed-order sums of the deterministic mode.  A producer launch stores the
 // workgroup totals of its sums in slots (sum, workgroup) and workgroup 0
 // records each sum's destination; the finishing launch that follows
-// (launch_det_finish) adds every recorded sum's slots in workgroup order to
+// (launch_det_finish) adds every recorded sum's slots in a fixed order to
 // shard 0 of its destination and clears them.  part == nullptr: atomic adds.
 constexpr int kDetSlots = 16;
 struct DetSums {

@@ -1,5 +1,5 @@
 """The deterministic create option: fixed-order sums (per-workgroup slots
-added in workgroup order, element passes gathered per owned node) make steps
+added in a fixed order, element passes gathered per owned node) make steps
 bitwise reproducible: repeated runs agree bit for bit, and 2n steps equal n
 steps, a save and restore of the state into a fresh context, and n more.
 Also checked against the oracle (the gather form computes the same
