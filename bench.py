@@ -401,7 +401,8 @@ def main() -> int:
         t_up = time.perf_counter() - t_up
         tag = (f"{'mixed' if precision else 'fp64'}" + {0: "", 1: "+learned", 2: "+extrapolated"}[warm]
                + ("+local_demag" if local_demag else "") + ("+rotated111" if rotated else "")
-               + ("+precond" if precond else "") + ("+gscorr" if gs_corrected else ""))
+               + ("+precond" if precond else "") + ("+gscorr" if gs_corrected else "")
+               + ("+deterministic" if deterministic else ""))
         print(f"[bench] {tag}: uploaded {info['n_unique']} nodes, {info['n_tets']} tets in "
               f"{t_up:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
         if args.warmup:

@@ -172,6 +172,8 @@ struct gspm_ctx {
     int predict[gspm::SK_COUNT][2] = {{32, 8}, {8, 4}, {8, 4}, {8, 4}, {16, 8}, {32, 8}};
     int refine_slot = 0;                  // 1 while a mixed-form solve runs its second or later inner solve
     bool heavy_iter = false;              // the running solve's iterations are costly (preconditioned): short batches
+    int batch_last = -1;                  // the last iteration of the batch being enqueued
+    bool pc_owed = false;                 // the preconditioned solve's next batch starts by forming z = B r
 
     // learned warm start
     gspm::MpnnState nn;

@@ -49,17 +49,23 @@ CgResult cg_iterate(gspm_ctx *c, const CGScalars &cg, int nc, bool joint, int ma
     CgResult res;
     const int cap = cg.ring - 2;
     int &pred = c->predict[kind][c->refine_slot];
-    const int first = std::min(std::max(pred + 1, 2), cap);
+    // fused launches test an iteration's residual in the next launch (hence
+    // pred + 1); the preconditioned iteration tests it at the end of its own
+    // launch group when it closes a batch
+    const int first = c->heavy_iter ? std::min(std::max(pred, 1), cap) : std::min(std::max(pred + 1, 2), cap);
     // Costly iterations are not queued ahead: each launch group that runs
     // past convergence still costs its library FFTs (about 80 us, a third of
     // a working iteration), more than the device idles while the host reads
-    // the flags.  Their solves enqueue the predicted count plus the testing
-    // launch, wait, and go on one iteration at a time.
+    // the flags.  Their solves enqueue the predicted count (the batch's last
+    // iteration tests its residual and leaves the next preconditioner
+    // application to the next batch), wait, and go on one iteration at a
+    // time.
     const bool ahead = !c->heavy_iter;
     const int later = c->heavy_iter ? 1 : std::min(std::max(pred / 32, 4), std::min(cap, 32));
     int k = 0;
     auto enqueue = [&](int cnt) {
         const int k1 = std::min(k + cnt, maxit);
+        c->batch_last = k1 - 1;
         launch_zero_ring(cg, ns, k + 1, k1 + 1, k, k1, s);
         for (int it = k; it < k1; ++it) iter(it, false);
         if (k1 == maxit) iter(maxit, true);
@@ -289,6 +295,9 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
 // grid, forward FFT, the symbol inverse mode by mode, inverse FFT,
 // prolongation with the diagonal term.  p alternates between two buffers
 // (other workgroups read p_{k-1} as halo while p_k is written).
+// The last iteration of a batch only tests |r_{k+1}| and leaves z_{k+1} to
+// the next batch, which the host enqueues after reading the flags: a solve
+// that converged there skips the preconditioner's FFTs.
 template <class T>
 auto pcg_iteration(gspm_ctx *c, const MeshView &mvu, T *x, T *r, T *z, T *pa, T *pb, T *q, const CGScalars &cg,
                    double tol, int *fft_rc) {
@@ -304,12 +313,20 @@ auto pcg_iteration(gspm_ctx *c, const MeshView &mvu, T *x, T *r, T *z, T *pa, T 
             launch_pc_prolong<T>(gv, c->mv, r, z, pcg_rz_at(cg, test_k), cg, s);
             if (rc && !*fft_rc) *fft_rc = rc;
         };
-        if (k == 0) precond(0);
+        if (k == 0 || c->pc_owed) {
+            precond(k);
+            c->pc_owed = false;
+        }
         T *pin = (k & 1) ? pa : pb, *pout = (k & 1) ? pb : pa;
         launch_elastic_pcg<T>(mvu, c->mat, k, z, pin, pout, q, cg, s, prof_begin(c, k));
         prof_end(c);
         launch_pcg_update<T>(c->n, x, r, pout, q, cg, k, s);
-        precond(k + 1);
+        if (k == c->batch_last) {
+            launch_cg_check(3, true, cg, k + 1, tol, s);
+            c->pc_owed = true;
+        } else {
+            precond(k + 1);
+        }
     };
 }
 
