@@ -243,6 +243,7 @@ void gspm_ctx::release_mesh() {
     dev_free(this, b.cg_rzq); dev_free(this, b.cg_qzq); dev_free(this, b.cgi_rzq); dev_free(this, b.cgi_qzq);
     dev_free(this, b.det_part); dev_free(this, b.det_dst); dev_free(this, b.det_count); dev_free(this, b.inc_ptr);
     dev_free(this, b.inc_ent);
+    dev_free(this, b.gs_halo_ptr); dev_free(this, b.gs_halo_ids);
     dev_free(this, b.gs_off); dev_free(this, b.gs_col); dev_free(this, b.gs_kv); dev_free(this, b.gs_mv);
     dev_free(this, b.gs_kd); dev_free(this, b.gs_md);
     for (int k = 0; k < 2; ++k) {
@@ -392,9 +393,19 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
                                            std::to_string(lds_max) + "; use smaller block_nodes");
         nb /= 2;                   // automatic block size: halve until the element kernels fit
     }
+    // GS row blocks: twice the element blocks (at most 512 nodes) in the mixed
+    // form, whose FP32 row kernels stage 16 bytes per node; the element
+    // blocks' size in FP64 contexts (FP64 staging would halve occupancy)
     GsRowsHost rows;
-    rc = assemble_gs_rows(hm, n_tets, tets, tags, rows, err);
+    const bool fp64_cg = c->precision != GSPM_MIXED;
+    const int32_t nb_rows = fp64_cg ? hm.nb : std::max(hm.nb, std::min(2 * hm.nb, 512));
+    rc = assemble_gs_rows(hm, n_tets, tets, tags, nb_rows, rows, err);
+    if (!rc && rows.nb != hm.nb && rows_lds_bytes(rows.nb, rows.nloc_max, fp64_cg) > static_cast<size_t>(lds_max))
+        rc = assemble_gs_rows(hm, n_tets, tets, tags, hm.nb, rows, err);
     if (rc) return fail(c, static_cast<gspm_status>(rc), "upload_mesh: " + err);
+    if (rows_lds_bytes(rows.nb, rows.nloc_max, fp64_cg) > static_cast<size_t>(lds_max))
+        return fail(c, GSPM_E_ARG, "upload_mesh: the GS row blocks need more LDS than the device has; use smaller "
+                                   "block_nodes");
     // deterministic mode: per owned node its element copies, (copy index within the block's list) << 2 | slot
     std::vector<int32_t> inc_ptr;
     std::vector<uint16_t> inc_ent;
@@ -462,6 +473,8 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
         rc = rc ? rc : dev_alloc(c, &d.cg_rzq, static_cast<size_t>(kMaxComp) * kRing * kShards);
         rc = rc ? rc : dev_alloc(c, &d.cg_qzq, static_cast<size_t>(kMaxComp) * kRing * kShards);
         rc = rc ? rc : dev_alloc(c, &d.gs_off, rows.off.size());
+        rc = rc ? rc : dev_alloc(c, &d.gs_halo_ptr, rows.halo_ptr.size());
+        if (!rows.halo_ids.empty()) rc = rc ? rc : dev_alloc(c, &d.gs_halo_ids, rows.halo_ids.size());
         rc = rc ? rc : dev_alloc(c, &d.gs_col, nent);
         rc = rc ? rc : dev_alloc(c, &d.gs_kv, nent);
         rc = rc ? rc : dev_alloc(c, &d.gs_mv, nent);
@@ -542,6 +555,11 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     hipMemcpyAsync(d.blk_nmag, hm.blk_nmag.data(), sizeof(int32_t) * hm.blk_nmag.size(), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.w, hm.w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d.gs_off, rows.off.data(), sizeof(int32_t) * rows.off.size(), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d.gs_halo_ptr, rows.halo_ptr.data(), sizeof(int32_t) * rows.halo_ptr.size(), hipMemcpyHostToDevice,
+                   s);
+    if (!rows.halo_ids.empty())
+        hipMemcpyAsync(d.gs_halo_ids, rows.halo_ids.data(), sizeof(int32_t) * rows.halo_ids.size(),
+                       hipMemcpyHostToDevice, s);
     if (nent) {
         hipMemcpyAsync(d.gs_col, rows.col.data(), sizeof(uint16_t) * nent, hipMemcpyHostToDevice, s);
         hipMemcpyAsync(d.gs_kv, rows.kv.data(), sizeof(double) * nent, hipMemcpyHostToDevice, s);
@@ -635,6 +653,12 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
     }
     c->cg.det = mv.det;
     c->cg_in.det = mv.det;
+    c->mv_rows = mv;
+    c->mv_rows.nb = rows.nb;
+    c->mv_rows.nblk = rows.nblk;
+    c->mv_rows.halo_ptr = d.gs_halo_ptr;
+    c->mv_rows.halo_ids = d.gs_halo_ids;
+    c->mv_rows.nloc_max = rows.nloc_max;
     c->cg.rr = d.cg_rr;
     c->cg.pq = d.cg_pq;
     c->cg.bb = d.cg_bb;
@@ -956,7 +980,7 @@ gspm_status gspm_apply(gspm_ctx *c, gspm_op op, double eps, const double *x, dou
     } else {
         const double e = op == GSPM_OP_LAPLACE ? 1.0 : (op == GSPM_OP_MASS ? 0.0 : eps);
         const double mass = op == GSPM_OP_LAPLACE ? 0.0 : 1.0;
-        launch_gs_rows<double>(c->mv, gs_rows(c, e, mass, false), 3, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr,
+        launch_gs_rows<double>(c->mv_rows, gs_rows(c, e, mass, false), 3, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr,
                                c->cg, c->stream);
     }
     rc = download(c, c->d.q, h);
@@ -1039,9 +1063,9 @@ gspm_status gspm_time_operator(gspm_ctx *c, gspm_op op, double eps, int32_t reps
                                          0.0, c->stream);
         } else {
             if (f32)
-                launch_gs_rows<float>(c->mv, rv, 3, MV_APPLY, c->d.r32, c->d.q32, nullptr, nullptr, c->cg, c->stream);
+                launch_gs_rows<float>(c->mv_rows, rv, 3, MV_APPLY, c->d.r32, c->d.q32, nullptr, nullptr, c->cg, c->stream);
             else
-                launch_gs_rows<double>(c->mv, rv, 3, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, c->cg, c->stream);
+                launch_gs_rows<double>(c->mv_rows, rv, 3, MV_APPLY, c->d.ms, c->d.q, nullptr, nullptr, c->cg, c->stream);
         }
     }
     hipEventRecord(c->t1, c->stream);

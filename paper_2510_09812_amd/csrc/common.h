@@ -78,10 +78,16 @@ struct GsRowsHost {
     std::vector<uint16_t> col;    // entries
     std::vector<double> kv, mv;   // entries: K_ij, M_ij (i != j)
     std::vector<double> kd, md;   // n: K_ii, M_ii
+    // row blocks (ranges of nb rows in the node order; independent of the element blocks): the staged
+    // nodes of block b are its owned range, then halo_ids[halo_ptr[b] .. halo_ptr[b + 1]), the sorted
+    // columns of its rows outside that range
+    int32_t nb = 0, nblk = 0, nloc_max = 0;
+    std::vector<int32_t> halo_ptr, halo_ids;
 };
 
-int assemble_gs_rows(const HostMesh &hm, int64_t ne, const int32_t *tets, const uint8_t *tags, GsRowsHost &out,
-                     std::string &err);
+// nb_rows: nodes per row block, a multiple of 64 (0: the element blocks' size)
+int assemble_gs_rows(const HostMesh &hm, int64_t ne, const int32_t *tets, const uint8_t *tags, int32_t nb_rows,
+                     GsRowsHost &out, std::string &err);
 
 // ------------------------------------------------------------- device views
 
@@ -418,6 +424,10 @@ void launch_stage_coords(const MeshView &mv, double *stc64, float *stc32, hipStr
 // Largest dynamic LDS request of the element kernels for blocks of nb owned
 // nodes and at most nloc_max staged nodes (elem_kernels.hip).
 size_t elem_lds_bytes(int32_t nb, int32_t nloc_max);
+// Largest LDS request of the GS row kernels for row blocks of nb nodes and
+// at most nloc_max staged nodes (row_kernels.hip); fp64_cg: FP64 CG
+// iterations run too (FP64 contexts).
+size_t rows_lds_bytes(int32_t nb, int32_t nloc_max, bool fp64_cg);
 double carlson_rd(double x, double y, double z);
 void demag_factors(double a, double b, double c, double N[3]);
 

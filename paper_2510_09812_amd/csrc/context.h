@@ -69,6 +69,7 @@ struct DeviceBuffers {
     // and (mixed contexts) FP32
     int32_t *gs_off = nullptr;
     uint16_t *gs_col = nullptr;
+    int32_t *gs_halo_ptr = nullptr, *gs_halo_ids = nullptr;   // the row blocks' halo lists
     double *gs_kv = nullptr, *gs_mv = nullptr, *gs_kd = nullptr, *gs_md = nullptr;
     double *gs_a64[2] = {nullptr, nullptr}, *gs_d64[2] = {nullptr, nullptr};
     float *gs_a32[2] = {nullptr, nullptr}, *gs_d32[2] = {nullptr, nullptr};
@@ -142,6 +143,7 @@ struct gspm_ctx {
     size_t arena_size = 0, arena_used = 0;
     bool arena_planning = false;
     gspm::MeshView mv{};
+    gspm::MeshView mv_rows{};     // mv with the GS row blocks (size, count, halo lists, largest staging)
     gspm::CGScalars cg{};
     gspm::CGScalars cg_in{};      // inner FP32 solves of the mixed form
     int32_t *h_flags = nullptr;   // pinned host mirror: 2 slots x (done[3], iters[3])

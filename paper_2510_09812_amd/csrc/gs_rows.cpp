@@ -12,9 +12,12 @@
 // wavefront, one lane per row).  A slice stores its rows' off-diagonal
 // entries entry-major: entry k of lane l at off[s] + 64 k + l, padded to the
 // slice's longest row with zero coefficients that point at the row itself.
-// Columns are 16-bit indices into the row's owner-block staging (the block's
-// owned range, then its sorted halo list), the node set the element kernels
-// stage; the diagonal is kept apart.
+// Columns are 16-bit indices into the row's block staging: the block's owned
+// range, then its sorted halo list, which holds exactly the columns outside
+// the range.  Row blocks are ranges of the node order like the element
+// blocks, of a size of their own: the row kernels carry less per node than
+// the element kernels, so larger blocks amortise their per-block work and
+// stage fewer halo nodes per owned node.  The diagonal is kept apart.
 #include <algorithm>
 #include <atomic>
 #include <climits>
@@ -52,11 +55,10 @@ void element_gradients(const HostMesh &hm, const int32_t (&v)[4], double (&g)[4]
     for (int a = 0; a < 3; ++a) g[0][a] = -(g[1][a] + g[2][a] + g[3][a]);
 }
 
-// Runs body(i) for every row i on the host's threads, in chunks.
+// Runs body(i) for every i in [0, n) on the host's threads, in chunks.
 template <class Body>
-void for_rows(int32_t n, Body body) {
+void for_rows(int32_t n, Body body, int32_t kChunk = 2048) {
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    constexpr int32_t kChunk = 2048;
     std::atomic<int32_t> next{0};
     auto worker = [&]() {
         for (;;) {
@@ -74,9 +76,9 @@ void for_rows(int32_t n, Body body) {
 
 }  // namespace
 
-int assemble_gs_rows(const HostMesh &hm, int64_t ne, const int32_t *tets, const uint8_t *tags, GsRowsHost &out,
-                     std::string &err) {
-    const int32_t n = hm.n, nb = hm.nb;
+int assemble_gs_rows(const HostMesh &hm, int64_t ne, const int32_t *tets, const uint8_t *tags, int32_t nb_rows,
+                     GsRowsHost &out, std::string &err) {
+    const int32_t n = hm.n, nb = nb_rows > 0 ? nb_rows : hm.nb;
     if (nb % 64 != 0) {
         err = "GS rows: blocks must hold a multiple of 64 nodes";
         return GSPM_E_ARG;
@@ -167,6 +169,32 @@ int assemble_gs_rows(const HostMesh &hm, int64_t ne, const int32_t *tets, const 
             cm[r0 + q] = m2[q];
         }
     });
+    // row blocks: the halo of a block is the set of its rows' columns outside its owned range
+    out.nb = nb;
+    out.nblk = (n + nb - 1) / nb;
+    std::vector<std::vector<int32_t>> halos(static_cast<size_t>(out.nblk));
+    for_rows(out.nblk, [&](int32_t b) {
+        const int32_t n0 = b * nb, n1 = std::min(n, n0 + nb);
+        auto &h = halos[b];
+        for (int64_t t = rptr[n0]; t < rptr[n1]; ++t)
+            if (ccol[t] < n0 || ccol[t] >= n1) h.push_back(ccol[t]);
+        std::sort(h.begin(), h.end());
+        h.erase(std::unique(h.begin(), h.end()), h.end());
+    }, 8);
+    out.halo_ptr.assign(static_cast<size_t>(out.nblk) + 1, 0);
+    out.nloc_max = 0;
+    for (int32_t b = 0; b < out.nblk; ++b) {
+        const int64_t nloc = static_cast<int64_t>(nb) + static_cast<int64_t>(halos[b].size());
+        if (nloc > 65535) {
+            err = "GS rows: a row block stages more than 65535 nodes";
+            return GSPM_E_MESH;
+        }
+        out.nloc_max = std::max(out.nloc_max, static_cast<int32_t>(nloc));
+        out.halo_ptr[b + 1] = out.halo_ptr[b] + static_cast<int32_t>(halos[b].size());
+    }
+    out.halo_ids.resize(static_cast<size_t>(out.halo_ptr[out.nblk]));
+    for (int32_t b = 0; b < out.nblk; ++b)
+        std::copy(halos[b].begin(), halos[b].end(), out.halo_ids.begin() + out.halo_ptr[b]);
     // sliced rows with block-local columns
     const int32_t nsl = (n + 63) / 64;
     out.off.assign(static_cast<size_t>(nsl) + 1, 0);
@@ -187,7 +215,7 @@ int assemble_gs_rows(const HostMesh &hm, int64_t ne, const int32_t *tets, const 
     std::atomic<int> bad{0};
     for_rows(n, [&](int32_t i) {
         const int32_t b = i / nb, n0 = b * nb, s = i / 64, lane = i % 64;
-        const int32_t *h0 = hm.halo_ids.data() + hm.halo_ptr[b], *h1 = hm.halo_ids.data() + hm.halo_ptr[b + 1];
+        const int32_t *h0 = out.halo_ids.data() + out.halo_ptr[b], *h1 = out.halo_ids.data() + out.halo_ptr[b + 1];
         const int64_t w = (out.off[s + 1] - out.off[s]) / 64, cnt = rptr[i + 1] - rptr[i];
         for (int64_t q = 0; q < w; ++q) {
             const size_t e = static_cast<size_t>(out.off[s]) + 64 * static_cast<size_t>(q) + lane;

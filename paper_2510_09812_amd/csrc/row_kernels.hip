@@ -483,6 +483,14 @@ static void run_rows_cg(const MeshView &mv, const GsRowsView &rv, const GsCgArgs
     launch_det_finish(a.cg.det, s);
 }
 
+size_t rows_lds_bytes(int32_t nb, int32_t nloc_max, bool fp64_cg) {
+    const size_t nl = static_cast<size_t>(nloc_max), b = static_cast<size_t>(nb);
+    size_t need = sizeof(RowVec<double, 3>) * nl;                                           // FP64 residuals
+    need = std::max(need, sizeof(RowVec<float, 3>) * nl + sizeof(RowOwn<float, 3>) * b);  // FP32 CG
+    if (fp64_cg) need = std::max(need, sizeof(RowVec<double, 3>) * nl + sizeof(RowOwn<double, 3>) * b);
+    return need + 8192;   // the CG kernel's static arrays
+}
+
 template <class T>
 void launch_gs_rows_cg(const MeshView &mv, const GsRowsView &rv, int nc, int k, bool last, const T *rin, const T *pin,
                        const T *qin, T *rout, T *pout, T *qout, T *x, const CGScalars &cg, double tol, bool jacobi,

@@ -455,7 +455,7 @@ CgResult cg_gs_run(gspm_ctx *c, int nc, double eps, double *x, const double *b, 
     const bool jac = c->p.gs_precond == GSPM_PRECOND_JACOBI;
     const GsRowsView r64 = gs_rows(c, eps, 1.0, false);
     auto resid = [&]() {
-        launch_gs_rows<double>(c->mv, r64, nc, MV_RESID, x, nullptr, b, c->d.r, c->cg, s);
+        launch_gs_rows<double>(c->mv_rows, r64, nc, MV_RESID, x, nullptr, b, c->d.r, c->cg, s);
     };
     // iteration k reads the buffers of iteration k-1 and writes those of k
     auto fused = [&](const GsRowsView &rv, auto *R0, auto *R1, auto *P0, auto *P1, auto *Q0, auto *Q1, auto *xv,
@@ -465,7 +465,7 @@ CgResult cg_gs_run(gspm_ctx *c, int nc, double eps, double *x, const double *b, 
             auto *Rp = k & 1 ? R0 : R1, *Pp = k & 1 ? P0 : P1, *Qp = k & 1 ? Q0 : Q1;
             if (k == 0) Rp = R0;
             const hipEvent_t *ev = last ? nullptr : prof_begin(c, k);
-            launch_gs_rows_cg(c->mv, rv, nc, k, last, Rp, Pp, Qp, R, P, Q, xv, cg, t, jac, s, ev);
+            launch_gs_rows_cg(c->mv_rows, rv, nc, k, last, Rp, Pp, Qp, R, P, Q, xv, cg, t, jac, s, ev);
             if (!last) prof_end(c);
         };
     };

@@ -8,7 +8,9 @@
 //     the caller's coordinates), for random x;
 //   - K and M are symmetric, K's rows sum to zero, and M's entries sum to the
 //     magnetic volume.
-// Usage: rows_check <mesh.bin> <block_nodes> [reorder]; prints statistics, exit 0 if valid.
+//   - each row block's halo list is sorted, lies outside the block's owned
+//     range and holds only nodes that some row of the block uses.
+// Usage: rows_check <mesh.bin> <block_nodes> [reorder] [row_block_nodes]; prints statistics, exit 0 if valid.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -45,6 +47,7 @@ int main(int argc, char **argv) {
     }
     const int nb = argc > 2 ? atoi(argv[2]) : 256;
     const int reorder = argc > 3 ? atoi(argv[3]) : GSPM_REORDER_MORTON;
+    const int nb_rows = argc > 4 ? atoi(argv[4]) : 0;
     HostMesh M;
     std::string err;
     if (prepare_mesh(n0, xyz.data(), ne, tets.data(), tags.data(), lo, hi, nb, M, err, reorder)) {
@@ -52,12 +55,20 @@ int main(int argc, char **argv) {
         return 1;
     }
     GsRowsHost R;
-    if (assemble_gs_rows(M, ne, tets.data(), tags.data(), R, err)) {
+    if (assemble_gs_rows(M, ne, tets.data(), tags.data(), nb_rows, R, err)) {
         printf("assembly failed %s\n", err.c_str());
         return 1;
     }
     const int n = M.n;
     long bad = 0;
+    const int rb = R.nb;
+    if (rb != (nb_rows > 0 ? nb_rows : M.nb) || R.nblk != (n + rb - 1) / rb ||
+        static_cast<int>(R.halo_ptr.size()) != R.nblk + 1 ||
+        static_cast<size_t>(R.halo_ptr[R.nblk]) != R.halo_ids.size()) {
+        printf("row blocks inconsistent\n");
+        return 1;
+    }
+    std::vector<char> used(R.halo_ids.size(), 0);
     const int nsl = (n + 63) / 64;
     if (static_cast<int>(R.off.size()) != nsl + 1 || R.off[0] != 0 ||
         static_cast<size_t>(R.off[nsl]) != R.col.size()) {
@@ -68,18 +79,19 @@ int main(int argc, char **argv) {
     std::vector<std::map<int, std::pair<double, double>>> rows(n);
     long entries = 0, padding = 0;
     for (int i = 0; i < n; ++i) {
-        const int b = i / M.nb, nloc = M.nb + (M.halo_ptr[b + 1] - M.halo_ptr[b]);
+        const int b = i / rb, nloc = rb + (R.halo_ptr[b + 1] - R.halo_ptr[b]);
         const int s = i / 64, lane = i % 64, w = (R.off[s + 1] - R.off[s]) / 64;
         if ((R.off[s + 1] - R.off[s]) % 64) bad++;
         for (int k = 0; k < w; ++k) {
             const size_t e = static_cast<size_t>(R.off[s]) + 64 * static_cast<size_t>(k) + lane;
             const int loc = R.col[e];
-            if (loc >= nloc || (loc >= n - b * M.nb && loc < M.nb)) {
+            if (loc >= nloc || (loc >= n - b * rb && loc < rb)) {
                 bad++;
                 printf("row %d: column %d outside the staged set\n", i, loc);
                 continue;
             }
-            const int j = loc < M.nb ? b * M.nb + loc : M.halo_ids[M.halo_ptr[b] + loc - M.nb];
+            if (loc >= rb) used[R.halo_ptr[b] + loc - rb] = 1;
+            const int j = loc < rb ? b * rb + loc : R.halo_ids[R.halo_ptr[b] + loc - rb];
             if (j == i) {
                 if (R.kv[e] != 0.0 || R.mv[e] != 0.0) {
                     bad++;
@@ -170,11 +182,23 @@ int main(int argc, char **argv) {
         ynorm += y1[i] * y1[i];
         dnorm += (y1[i] - y2[i]) * (y1[i] - y2[i]);
     }
+    // halo lists: sorted, outside the owned range, every entry used
+    long halo_bad = 0;
+    for (int b = 0; b < R.nblk; ++b)
+        for (int t = R.halo_ptr[b]; t < R.halo_ptr[b + 1]; ++t) {
+            const int j = R.halo_ids[t];
+            if ((t > R.halo_ptr[b] && R.halo_ids[t - 1] >= j) || (j >= b * rb && j < (b + 1) * rb) || !used[t])
+                halo_bad++;
+        }
+    if (halo_bad) {
+        bad++;
+        printf("%ld halo entries unsorted, owned or unused\n", halo_bad);
+    }
     const double rel = std::sqrt(dnorm / ynorm), mrel = std::fabs(msum - vmag) / vmag;
-    printf("rows %d entries %ld padding %ld (%.1f%%) per row %.2f | product rel err %.2e | symmetry %.1e "
-           "row sums %.1e mass %.1e\n",
-           n, entries, padding, 100.0 * padding / std::max(1L, entries + padding), double(entries) / n, rel, worst_sym,
-           worst_rowsum, mrel);
+    printf("rows %d entries %ld padding %ld (%.1f%%) per row %.2f | row blocks of %d: %.2f halo nodes per row | "
+           "product rel err %.2e | symmetry %.1e row sums %.1e mass %.1e\n",
+           n, entries, padding, 100.0 * padding / std::max(1L, entries + padding), double(entries) / n, rb,
+           double(R.halo_ids.size()) / n, rel, worst_sym, worst_rowsum, mrel);
     if (rel > 1e-13 || worst_sym > 1e-13 || worst_rowsum > 1e-12 || mrel > 1e-13) bad++;
     return bad ? 1 : 0;
 }

@@ -38,20 +38,24 @@ def _dump(mesh, path):
         mesh.tags.astype(np.uint8).tofile(f)
 
 
-@pytest.mark.parametrize("name,mesh,nb,reorder", [
+@pytest.mark.parametrize("name,mesh,nb,reorder,nb_rows", [
     ("ragged9_sphere_shuffled", lambda: w.small_cube(9, seed=5, L=8e-8, jitter=0.15, sphere=0.3, shuffle=True).mesh,
-     64, 0),
-    ("ragged23_sphere", lambda: w.small_cube(23, seed=6, L=1e-7, jitter=0.15, sphere=0.25).mesh, 256, 0),
-    ("ragged23_sphere_blocks1024", lambda: w.small_cube(23, seed=6, L=1e-7, jitter=0.15, sphere=0.25).mesh, 1024, 0),
-    ("five17_sphere_shuffled", lambda: w.small_cube(17, seed=8, L=1e-7, jitter=0.15, sphere=0.3, shuffle=True,
-                                                    split="five").mesh, 256, 0),
-    ("callers_order", lambda: w.small_cube(15, seed=7, L=1e-7, jitter=0.15, sphere=0.3).mesh, 256, 1),
-    ("rcm_order", lambda: w.small_cube(15, seed=7, L=1e-7, jitter=0.15, sphere=0.3).mesh, 256, 2),
+     64, 0, 0),
+    ("ragged9_sphere_shuffled_rows128", lambda: w.small_cube(9, seed=5, L=8e-8, jitter=0.15, sphere=0.3,
+                                                             shuffle=True).mesh, 64, 0, 128),
+    ("ragged23_sphere", lambda: w.small_cube(23, seed=6, L=1e-7, jitter=0.15, sphere=0.25).mesh, 256, 0, 0),
+    ("ragged23_sphere_rows512", lambda: w.small_cube(23, seed=6, L=1e-7, jitter=0.15, sphere=0.25).mesh, 256, 0, 512),
+    ("ragged23_sphere_blocks1024", lambda: w.small_cube(23, seed=6, L=1e-7, jitter=0.15, sphere=0.25).mesh, 1024, 0,
+     0),
+    ("five17_sphere_shuffled_rows512", lambda: w.small_cube(17, seed=8, L=1e-7, jitter=0.15, sphere=0.3, shuffle=True,
+                                                            split="five").mesh, 256, 0, 512),
+    ("callers_order", lambda: w.small_cube(15, seed=7, L=1e-7, jitter=0.15, sphere=0.3).mesh, 256, 1, 0),
+    ("rcm_order_rows512", lambda: w.small_cube(15, seed=7, L=1e-7, jitter=0.15, sphere=0.3).mesh, 256, 2, 512),
 ])
-def test_gs_rows_decode_to_the_assembled_operator(checker, name, mesh, nb, reorder):
+def test_gs_rows_decode_to_the_assembled_operator(checker, name, mesh, nb, reorder, nb_rows):
     exe, d = checker
     path = str(d / f"{name}.bin")
     _dump(mesh(), path)
-    r = subprocess.run([exe, path, str(nb), str(reorder)], capture_output=True, text=True)
+    r = subprocess.run([exe, path, str(nb), str(reorder), str(nb_rows)], capture_output=True, text=True)
     print(r.stdout.strip())
     assert r.returncode == 0, r.stdout

@@ -67,7 +67,7 @@ def test_mesh_preparation_under_sanitizers(tools, name):
     exes, d = tools
     path = str(d / f"{name}.bin")
     _dump(MESHES[name](), path)
-    for exe, args in (("strip_check", ["64"]), ("strip_check", ["256", "2"]), ("rows_check", ["64"]),
+    for exe, args in (("strip_check", ["64"]), ("strip_check", ["256", "2"]), ("rows_check", ["64", "0", "128"]),
                       ("rows_check", ["256", "1"])):
         r = subprocess.run([exes[exe], path] + args, capture_output=True, text=True, env=ENV)
         print(exe, args, r.stdout.strip()[-300:])
