@@ -393,12 +393,14 @@ gspm_status gspm_upload_mesh(gspm_ctx *c, int64_t n_nodes, const double *xyz, in
                                            std::to_string(lds_max) + "; use smaller block_nodes");
         nb /= 2;                   // automatic block size: halve until the element kernels fit
     }
-    // GS row blocks: twice the element blocks (at most 512 nodes) in the mixed
-    // form, whose FP32 row kernels stage 16 bytes per node; the element
-    // blocks' size in FP64 contexts (FP64 staging would halve occupancy)
+    // GS row blocks: four times the element blocks (at most 1024 nodes) in
+    // the mixed form, whose FP32 row kernels stage 16 bytes per node (two
+    // workgroups per CU; the per-workgroup work of a CG iteration is spread
+    // over more rows); the element blocks' size in FP64 contexts (FP64
+    // staging would cut occupancy further)
     GsRowsHost rows;
     const bool fp64_cg = c->precision != GSPM_MIXED;
-    const int32_t nb_rows = fp64_cg ? hm.nb : std::max(hm.nb, std::min(2 * hm.nb, 512));
+    const int32_t nb_rows = fp64_cg ? hm.nb : std::max(hm.nb, std::min(4 * hm.nb, 1024));
     rc = assemble_gs_rows(hm, n_tets, tets, tags, nb_rows, rows, err);
     if (!rc && rows.nb != hm.nb && rows_lds_bytes(rows.nb, rows.nloc_max, fp64_cg) > static_cast<size_t>(lds_max))
         rc = assemble_gs_rows(hm, n_tets, tets, tags, hm.nb, rows, err);
