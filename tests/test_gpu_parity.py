@@ -92,6 +92,34 @@ def test_solves_match_oracle(case):
     sim.close()
 
 
+@pytest.mark.parametrize("block_nodes", [64, 256])
+def test_gs_row_blocks_of_the_mixed_form_match_oracle(case, block_nodes):
+    """Mixed contexts give the GS rows blocks of four element blocks (256 and
+    1024 nodes here, the last one ragged): the FP64 GS operator they apply and
+    the solve they run match the oracle."""
+    mesh = case.mesh
+    orc = O.Oracle.from_mesh(mesh)
+    orc.set_params(case.params)
+    sim = gspm.Simulation(mesh, case.params, block_nodes=block_nodes, precision=gspm.GSPM_MIXED)
+    rng = np.random.default_rng(9)
+    nmap = orc.node_map()
+    x = _site_vector(mesh, rng)
+    xu = np.zeros((orc.n, 3)); xu[nmap] = x
+    y = sim.apply(gspm.GSPM_OP_GS, x, 7e-18)
+    ref = orc.apply(O.OP_GS, xu, 7e-18)[nmap]
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    b = _site_vector(mesh, rng)
+    bu = np.zeros((orc.n, 3)); bu[nmap] = b
+    xs, it = sim.solve(gspm.GSPM_OP_GS, b, None, 3e-17, tol=1e-10)
+    xr, itr = orc.solve(O.OP_GS, bu, None, 3e-17, tol=1e-12)
+    serr = _rel(xs, xr[nmap])
+    print(f"mixed, {block_nodes}-node element blocks: GS apply max rel err {err:.2e}, solve rel err {serr:.2e} "
+          f"(iterations {it}, oracle {itr})", flush=True)
+    assert err < 1e-12
+    assert serr < 1e-8
+    sim.close()
+
+
 def _run_both(case, steps, hext=None, sigma=(0.0,) * 6, precession=True, tol=None):
     params = case.params
     if tol is not None:
