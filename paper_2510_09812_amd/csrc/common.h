@@ -390,18 +390,20 @@ struct ShardSources {
 };
 void launch_i32_to_host(const int32_t *src, int count, int32_t *host_dst, hipStream_t s);
 void launch_totals_to_host(const ShardSources &src, int count, double *host_dst, hipStream_t s);
-// The start of an inner FP32 solve: bb[q] (shard 0; the other shards zero)
-// and done[q] per component, iters zero.
+// The start of an inner FP32 solve of the mixed form, in one launch: the
+// inner threshold bb[q] (shard 0; the other shards zero) and done[q] per
+// component with iters zero; r32 = (float) (scale * r64) on nc components
+// with ||r32||^2 per scalar set into slot 0 of the ring (zeroed by an
+// earlier launch); x32 = 0 on nx values.
 struct InnerStart {
     double bb[kMaxComp];
     int32_t done[kMaxComp];
 };
-void launch_set_inner(const CGScalars &cg, const InnerStart &st, hipStream_t s);
+void launch_inner_start(int n, int nc, bool joint, const double *src, double scale, float *dst, float *x32,
+                        int64_t nx, const CGScalars &cg, const InnerStart &st, hipStream_t s);
 
 // Precision conversions of the mixed form: dst = (float) src; x += (double) d.
 void launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s);
-void launch_to_f32_norms(int n, int nc, bool joint, const double *src, double scale, float *dst, const CGScalars &cg,
-                         hipStream_t s);
 void launch_add_f32(int64_t n, double *x, const float *d, hipStream_t s);
 void launch_fill_f32(float *p, int64_t n, hipStream_t s);
 

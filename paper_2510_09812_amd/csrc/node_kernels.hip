@@ -113,20 +113,6 @@ void launch_totals_to_host(const ShardSources &src, int count, double *host_dst,
     hipLaunchKernelGGL(k_totals_to_host, dim3(1), dim3(64), 0, s, src, count, host_dst);
 }
 
-__global__ void __launch_bounds__(kThreads) k_set_inner(CGScalars cg, InnerStart st) {
-    const int t = threadIdx.x;
-    if (t < kMaxComp * kShards) cg.bb[t] = (t % kShards == 0) ? st.bb[t / kShards] : 0.0;
-    if (t < kMaxComp) {
-        cg.done[t] = st.done[t];
-        cg.iters[t] = 0;
-    }
-}
-
-void launch_set_inner(const CGScalars &cg, const InnerStart &st, hipStream_t s) {
-    static_assert(kMaxComp * kShards <= kThreads, "one workgroup sets every shard");
-    hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(kThreads), 0, s, cg, st);
-}
-
 // ---------------------------------------------------------------- averages
 
 // Volume averages of Sec. 2.4 for P1 fields: int_Omega g = sum_j w_j g_j with
@@ -542,11 +528,25 @@ __global__ void __launch_bounds__(kThreads) k_fill_f32(float *p, int64_t n) {
         p[i] = 0.0f;
 }
 
-// r32 = (float) (scale * r64) on nc components, and ||r32||^2 per scalar set
-// into slot 0 of the inner solve's r.r ring (the starting residual of the
-// inner CG).
-__global__ void __launch_bounds__(kThreads) k_to_f32_norms(int n, int nc, int joint, const double *src, double scale,
-                                                           float *dst, CGScalars cg) {
+// The start of an inner FP32 solve of the mixed form in one launch: the
+// inner scalars (threshold and per-component done flags, written by
+// workgroup 0), r32 = (float) (scale * r64) on nc components with ||r32||^2
+// per scalar set into slot 0 of the r.r ring (zeroed by an earlier launch),
+// and x32 = 0 on nx values.
+__global__ void __launch_bounds__(kThreads) k_inner_start(int n, int nc, int joint, const double *src, double scale,
+                                                          float *dst, float *x32, int64_t nx, CGScalars cg,
+                                                          InnerStart st) {
+    if (blockIdx.x == 0) {
+        const int t = threadIdx.x;
+        if (t < kMaxComp * kShards) cg.bb[t] = (t % kShards == 0) ? st.bb[t / kShards] : 0.0;
+        if (t < kMaxComp) {
+            cg.done[t] = st.done[t];
+            cg.iters[t] = 0;
+        }
+    }
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < nx;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        x32[i] = 0.0f;
     double part[3] = {0.0, 0.0, 0.0};
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
         for (int c = 0; c < nc; ++c) {
@@ -558,10 +558,11 @@ __global__ void __launch_bounds__(kThreads) k_to_f32_norms(int n, int nc, int jo
     block_atomic_add<3>(part, cg.rr_at(0, 0), cg.comp_stride(), cg.det);
 }
 
-void launch_to_f32_norms(int n, int nc, bool joint, const double *src, double scale, float *dst, const CGScalars &cg,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_to_f32_norms, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, src, scale, dst,
-                       cg);
+void launch_inner_start(int n, int nc, bool joint, const double *src, double scale, float *dst, float *x32,
+                        int64_t nx, const CGScalars &cg, const InnerStart &st, hipStream_t s) {
+    static_assert(kMaxComp * kShards <= kThreads, "one workgroup sets every shard");
+    hipLaunchKernelGGL(k_inner_start, dim3(node_grid(n)), dim3(kThreads), 0, s, n, nc, joint ? 1 : 0, src, scale, dst,
+                       x32, nx, cg, st);
     launch_det_finish(cg.det, s);
 }
 

@@ -208,6 +208,7 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
     double *hs = c->h_mixed;   // pinned: the totals rr[ns] | bb[ns] of the outer residual
     for (int outer = 0;; ++outer) {
         launch_zero_ring(c->cg, ns, 0, 1, 0, 0, s);
+        launch_zero_ring(c->cg_in, ns, 0, 1, 0, 0, s);   // slot 0 of an inner solve that may follow
         resid();
         ShardSources src{};
         for (int q = 0; q < ns; ++q) {
@@ -260,10 +261,7 @@ CgResult cg_mixed(gspm_ctx *c, int nc, bool joint, double *x, double tol, int ma
             ist.bb[q] = eta * eta * rr[q] * scale * scale;
         }
         const CGScalars &ci = c->cg_in;
-        launch_set_inner(ci, ist, s);
-        launch_zero_ring(ci, ns, 0, 1, 0, 0, s);
-        launch_to_f32_norms(n, nc, joint, c->d.r, scale, c->d.r32, ci, s);
-        launch_fill_f32(c->d.x32, n3, s);
+        launch_inner_start(n, nc, joint, c->d.r, scale, c->d.r32, c->d.x32, static_cast<int64_t>(n3), ci, ist, s);
         const int budget = maxit - used;
         const size_t first_pair = prof_mark(c);
         c->refine_slot = outer > 0 ? 1 : 0;
