@@ -9,12 +9,14 @@
 // Multi-component magnetostatic solves (and the preconditioned elastic solve)
 // take separate launches: the matvec, whose staging forms the new direction
 // p_k = z_k + beta_k p_{k-1} after testing ||r_k|| on the device, with p.Ap
-// fused into its epilogue; and the x/r update with r.r fused.  Vectors that other workgroups read as halo
-// while a launch writes their successors are double-buffered.  Convergence is
-// decided on the device and a converged solve turns the remaining launches
-// into immediate exits.  The host enqueues iterations in batches and reads the
-// convergence flags of the previous batch while the next one runs, so the
-// device never waits for it.
+// fused into its epilogue; and the x/r update with r.r fused.  Vectors that
+// other workgroups read as halo while a launch writes their successors are
+// double-buffered.  Convergence is decided on the device and a converged
+// solve turns the remaining launches into immediate exits.  The host
+// enqueues iterations in batches sized by the last solve of the same kind and
+// reads the convergence flags of the previous batch while the next one runs;
+// solves whose iterations carry library FFTs (the preconditioned elastic
+// solve) wait for the flags instead of queueing ahead (cg_iterate).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
