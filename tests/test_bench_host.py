@@ -28,6 +28,12 @@ def test_algorithmic_bytes_at_the_1m_node_cube():
     assert bench.cg_iteration_bytes(n, 6 * n, 4) == 228 * n
     assert bench.gs_iteration_bytes(n, 6 * n, 8) == 192 * n
     assert bench.gs_iteration_bytes(n, 6 * n, 4) == 156 * n
+    # the fused GS iteration on three components: the magnetic tets' connectivity and the coordinates once,
+    # nine passes per component, the Jacobi diagonal once (5,811,637 magnetic tets at the 1M-node cube)
+    nem = 5811637
+    assert bench.gs3_iteration_bytes(N1M, nem, 4, jacobi=True) == 16 * nem + 24 * N1M + 27 * 4 * N1M + 4 * N1M
+    assert bench.gs3_iteration_bytes(N1M, nem, 4, jacobi=True) == 224946856
+    assert bench.gs3_iteration_bytes(N1M, nem, 8, jacobi=False) == 16 * nem + 24 * N1M + 27 * 8 * N1M
 
 
 def test_step_bytes_in_both_precisions():
