@@ -22,6 +22,36 @@ def test_header_and_binding_agree():
     assert sorted(gspm.EXPORTS) == _declared()
 
 
+def test_header_enum_values_match_the_binding():
+    """Every GSPM_* enumerator and #define of the header has the value the
+    binding's constant of the same name carries."""
+    text = open(os.path.join(ROOT, "include", "gspm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)      # comments may hold braces
+    values = {}
+    for body in re.findall(r"typedef enum\s*\{(.*?)\}", text, re.S):
+        nxt = 0
+        for item in body.split(","):
+            item = item.strip()
+            if not item:
+                continue
+            m = re.match(r"(GSPM_\w+)\s*(?:=\s*(-?\d+))?$", item)
+            assert m, item
+            nxt = int(m.group(2)) if m.group(2) is not None else nxt
+            values[m.group(1)] = nxt
+            nxt += 1
+    for name, val in re.findall(r"#define\s+(GSPM_\w+)\s+(\d+)\b", text):
+        values[name] = int(val)
+    checked = 0
+    for name, val in values.items():
+        if hasattr(gspm, name):
+            assert getattr(gspm, name) == val, name
+            checked += 1
+    for name in ("GSPM_GS_START_LUMPED", "GSPM_GS_START_CORRECTED", "GSPM_MIXED", "GSPM_PRECOND_JACOBI",
+                 "GSPM_REORDER_RCM", "GSPM_WARM_EXTRAPOLATE", "GSPM_MPNN_PARAMS"):
+        assert name in values and hasattr(gspm, name), name
+    assert checked >= 20
+
+
 def test_library_exports_every_declared_symbol():
     lib = gspm.load()
     for name in _declared():
