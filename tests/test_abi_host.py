@@ -52,6 +52,32 @@ def test_header_enum_values_match_the_binding():
     assert checked >= 20
 
 
+def test_struct_layouts_match_the_binding(tmp_path):
+    """The ctypes structures of the binding have the size and field offsets
+    the C compiler gives the header's structs (tests/host/abi_layout.c)."""
+    import ctypes
+    import shutil
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    exe = str(tmp_path / "abi_layout")
+    subprocess.check_call([gcc, "-std=c11", "-I" + os.path.join(ROOT, "include"),
+                           os.path.join(ROOT, "tests", "host", "abi_layout.c"), "-o", exe])
+    lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, lines):
+        struct, field, value = line.split()
+        cls = getattr(gspm, struct)
+        got = ctypes.sizeof(cls) if field == "sizeof" else getattr(cls, field).offset
+        assert got == int(value), (struct, field, got, value)
+        seen += 1
+    # every ctypes field is covered by the C listing
+    for cls in (gspm.gspm_create_opts, gspm.gspm_params, gspm.gspm_step_stats):
+        names = {line.split()[1] for line in filter(None, lines) if line.split()[0] == cls.__name__}
+        assert {f[0] for f in cls._fields_} <= names, cls.__name__
+    assert seen >= 50
+
+
 def test_library_exports_every_declared_symbol():
     lib = gspm.load()
     for name in _declared():
