@@ -629,6 +629,37 @@ def test_field_rhs_sees_only_symmetric_strain():
     assert np.abs(res["lin"] - res["zero"]).max() > 1e-6 * scale
 
 
+@pytest.mark.parametrize("direction", ["100", "1-23"])
+def test_lumped_gs_start_is_exact_for_uniform_m(direction):
+    """Reading R14: the GS start y + (sum_e M^e c h^e) / w is the exact
+    solution of (eps K + M) g = b when m is uniform: h is then the same at
+    every magnetic vertex, the mass rows over magnetic elements sum to the
+    lumped weights w, and K annihilates a field that is constant on every
+    magnetic element (inclusion-only nodes carry zero and touch no magnetic
+    element).  So the start has a rounding-level residual and CG takes no
+    iteration, while the start without the field term does not."""
+    case = w.small_cube(9, seed=57, L=8e-8, jitter=0.15, sphere=0.3)
+    d = {"100": [1.0, 0.0, 0.0], "1-23": [1.0, -2.0, 3.0]}[direction]
+    d = np.asarray(d) / np.linalg.norm(d)
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(MAT, hext=(2e5, -1e5, 5e4), sigma_ext=(1e7, 0, -2e7, 0, 3e6, 0))
+    orc.set_m(case.mesh.per_site(np.tile(d, (case.mesh.n_sites, 1))))
+    c, eps = 0.37, 2.5e-17
+    b, ch = orc.field_rhs(c)
+    wts = orc.lumped_weights()
+    mag = wts > 0
+    m = np.zeros((orc.n, 3)); m[mag] = d
+    h = ch[mag] / (c * wts[mag, None])
+    assert np.abs(h - h.mean(axis=0)).max() <= 1e-12 * np.abs(h).max()   # one field at every magnetic node
+    g0 = np.where(mag[:, None], m + ch / np.where(mag, wts, 1.0)[:, None], 0.0)
+    res = np.linalg.norm(b - orc.apply(O.OP_GS, g0, eps)) / np.linalg.norm(b)
+    res_plain = np.linalg.norm(b - orc.apply(O.OP_GS, m, eps)) / np.linalg.norm(b)
+    g, its = orc.solve(O.OP_GS, b, g0, eps, tol=1e-12)
+    assert res < 1e-14 and its == 0
+    assert res_plain > 1e-6
+    assert np.abs(g - g0).max() == 0.0
+
+
 # ------------------------------------------------- energy terms, dm_avg
 
 def _e0_closed(p, m):
