@@ -10,7 +10,9 @@ changes, so
     iterations once a correction exists, and the answer moves by no more
     than the tolerance allows;
   - the option is refused in deterministic mode, and set_field(M) drops the
-    correction (the next step takes the lumped start's iterations).
+    correction (the next step takes the lumped start's iterations);
+  - on a homogeneous cell with m uniform the lumped start is exact and no
+    GS solve iterates.
 """
 import numpy as np
 import pytest
@@ -123,3 +125,32 @@ def test_set_field_drops_the_correction():
     assert _rel(a.get_m(), b.get_m()) < 1e-10 and _rel(a.get_u(), b.get_u()) < 1e-10
     for sim in (a, b, c):
         sim.close()
+
+
+@pytest.mark.parametrize("precision", [gspm.GSPM_FP64, gspm.GSPM_MIXED])
+def test_lumped_start_solves_a_uniform_state_without_iterations(precision):
+    """On a homogeneous periodic cell with m uniform the eigenstrain is
+    uniform, the elastic right-hand side vanishes, h is one vector at every
+    node and the lumped GS start is the exact solution of every GS system
+    (the oracle's pin of reading R14): every GS solve of the step stops
+    before its first iteration and m stays uniform, as in the oracle."""
+    case = w.small_cube(13, seed=135, L=12 * H, jitter=0.15)
+    d = np.array([1.0, -2.0, 3.0]) / np.sqrt(14.0)
+    m0 = case.mesh.per_site(np.tile(d, (case.mesh.n_sites, 1)))
+    p = _params(case, tol=1e-10)
+    H_ext = (2e5, -1e5, 5e4)
+    sim = gspm.Simulation(case.mesh, p, hext=H_ext, precision=precision)
+    sim.set_m(m0)
+    orc = O.Oracle.from_mesh(case.mesh)
+    orc.set_params(p, hext=H_ext)
+    orc.set_m(m0)
+    for k in range(2):
+        st = sim.step(5e-12, 1)
+        so = orc.step(5e-12, 1)
+        m, mo = sim.get_m(), orc.get_m()
+        em, spread = _rel(m, mo), np.abs(m - m.mean(axis=0)).max()
+        print(f"step {k}: GS iterations per solve {st['gs_iters_stage']} (oracle {so['gs_iters']}), "
+              f"rel err m {em:.1e}, spread of m {spread:.1e}", flush=True)
+        assert all(v == 0 for v in st["gs_iters_stage"]) and all(v == 0 for v in so["gs_iters"])
+        assert em < 1e-9 and spread < 1e-12
+    sim.close()
