@@ -415,6 +415,10 @@ void launch_normalize(int n, const double *w, const double *mss, const double *m
 // Deterministic mode: adds the sums the last producer launch recorded (no-op when det.part is null).
 void launch_det_finish(const DetSums &det, hipStream_t s);
 void launch_zero_ring(const CGScalars &cg, int ns, int rr_from, int rr_to, int pq_from, int pq_to, hipStream_t s);
+// A new solve on `cg`: slot 0 of the r.r ring of ns components, the b.b
+// shards and the done and iteration flags of every component cleared in one
+// launch.
+void launch_cg_reset(const CGScalars &cg, int ns, hipStream_t s);
 
 // --------------------------------------------------------------- utilities
 

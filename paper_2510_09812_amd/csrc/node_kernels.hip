@@ -637,9 +637,18 @@ __global__ void __launch_bounds__(kThreads) k_normalize(int n, const double *w, 
 }
 
 // Zero the ring slots that iterations [rr_from, rr_to) of r.r and
-// [pq_from, pq_to) of p.Ap will accumulate into.
+// [pq_from, pq_to) of p.Ap will accumulate into; with `reset` also the b.b
+// shards and the done and iteration flags of every component (a new solve).
 __global__ void __launch_bounds__(kThreads) k_zero_ring(CGScalars cg, int ns, int rr_from, int rr_to, int pq_from,
-                                                        int pq_to) {
+                                                        int pq_to, int reset) {
+    if (reset && blockIdx.x == 0) {
+        const int t = threadIdx.x;
+        if (t < kMaxComp * kShards) cg.bb[t] = 0.0;
+        if (t < kMaxComp) {
+            cg.done[t] = 0;
+            cg.iters[t] = 0;
+        }
+    }
     const int nrr = rr_to - rr_from, npq = pq_to - pq_from;
     const int total = ns * (nrr + npq) * kShards;
     for (int t = blockIdx.x * kThreads + threadIdx.x; t < total; t += gridDim.x * kThreads) {
@@ -666,7 +675,12 @@ void launch_zero_ring(const CGScalars &cg, int ns, int rr_from, int rr_to, int p
     const int total = ns * ((rr_to - rr_from) + (pq_to - pq_from)) * kShards;
     if (total <= 0) return;
     hipLaunchKernelGGL(k_zero_ring, dim3(node_grid(total)), dim3(kThreads), 0, s, cg, ns, rr_from, rr_to, pq_from,
-                       pq_to);
+                       pq_to, 0);
+}
+
+void launch_cg_reset(const CGScalars &cg, int ns, hipStream_t s) {
+    static_assert(kMaxComp * kShards <= kThreads, "one workgroup clears every shard");
+    hipLaunchKernelGGL(k_zero_ring, dim3(node_grid(ns * kShards)), dim3(kThreads), 0, s, cg, ns, 0, 1, 0, 0, 1);
 }
 
 void launch_update_m12(int n, const double *m, const double *g, double *ms, hipStream_t s) {

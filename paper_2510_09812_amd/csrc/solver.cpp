@@ -31,11 +31,7 @@ int hip_check(gspm_ctx *c, hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? GSPM_E_OOM : GSPM_E_DEVICE;
 }
 
-void cg_prepare(gspm_ctx *c, int ns) {
-    launch_fill(c->d.cg_bb, kMaxComp * kShards, 0.0, c->stream);
-    launch_fill_i32(c->d.cg_flags, 2 * kMaxComp, 0, c->stream);
-    launch_zero_ring(c->cg, ns, 0, 1, 0, 0, c->stream);
-}
+void cg_prepare(gspm_ctx *c, int ns) { launch_cg_reset(c->cg, ns, c->stream); }
 
 namespace {
 
