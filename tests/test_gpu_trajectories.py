@@ -10,9 +10,9 @@ counts), against the oracle and between the precisions.
   - The 1M-node cube (10 steps of 10 ps): the FP64 path against the oracle's
     state at 4096 sampled nodes (the full state is too large to store) and its
     cell averages and energies, which the oracle computed over the whole mesh.
-  - The 1M-node cube over 500 steps: mixed (and mixed with both
-    preconditioners) against FP64 at steps 20, 100 and 500, within 1e-6 on m
-    and u.
+  - The 1M-node cube over 500 steps: mixed, mixed with both preconditioners,
+    and the same with the corrected GS start (the bench's fastest path)
+    against FP64 at steps 20, 100 and 500, within 1e-6 on m and u.
   - The 1M-node cube with the local magnetostatic potential over 25 steps:
     mixed against FP64 within 1e-6 on m, u and U~.
 """
@@ -108,14 +108,16 @@ def test_cube100_ten_steps_against_oracle_sample():
 def test_cube100_500_steps_mixed_against_fp64():
     case = w.cube100_ellipsoids()
     sims = {"fp64": _sim(case, gspm.GSPM_FP64), "mixed": _sim(case, gspm.GSPM_MIXED),
-            "mixed+precond": _sim(case, gspm.GSPM_MIXED, precond=True)}
+            "mixed+precond": _sim(case, gspm.GSPM_MIXED, precond=True),
+            "mixed+precond+gscorr": _sim(case, gspm.GSPM_MIXED, precond=True)}
+    sims["mixed+precond+gscorr"].set_gs_start(gspm.GSPM_GS_START_CORRECTED)
     done = 0
     for mark in (20, 100, 500):
         for s in sims.values():
             s.step(case.dt, mark - done)
         done = mark
         ref_m, ref_u = sims["fp64"].get_m(), _demean(sims["fp64"].get_u())
-        for name in ("mixed", "mixed+precond"):
+        for name in ("mixed", "mixed+precond", "mixed+precond+gscorr"):
             em = _rel(sims[name].get_m(), ref_m)
             eu = _rel(_demean(sims[name].get_u()), ref_u)
             print(f"[traj] cube100 step {mark}: {name} vs fp64 m {em:.2e} u {eu:.2e}", flush=True)
